@@ -1,0 +1,141 @@
+/*
+ * tg.h - C ABI of the MI355X typed-graphlet counting library (libtg.so).
+ *
+ * Computes, for every edge of a simple undirected graph whose nodes carry one
+ * of L types, the counts of all typed 2-, 3- and 4-node graphlets that
+ * contain the edge (local typed graphlet counting, Problem 1 of Rossi et al.,
+ * "Heterogeneous Graphlets"), and the global count of every typed graphlet
+ * (Problem 2).  Algorithm 1 of the paper requires a graph and ensures the
+ * counts for each edge; this library produces them as a dense table.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Graph: CSR over n nodes with int64 row offsets row_ptr[n+1] and int32
+ *   neighbour ids col[nnz], nnz = 2M.  Every row is strictly ascending
+ *   (no duplicates), contains no self-loop, and the adjacency is symmetric.
+ *   types[n] (uint8) holds each node's type in [0, L), 1 <= L <= TG_MAX_L.
+ * Memory: graph, types, outputs and workspace are DEVICE pointers on the
+ *   current HIP device.  The caller allocates and owns all of them; the
+ *   library allocates no device memory and frees nothing.
+ * Stream: every kernel runs on the given hipStream_t (passed as void*, NULL
+ *   means the null stream).  A call returns after the counts are enqueued;
+ *   validation results are read back once with a stream synchronisation,
+ *   so the call blocks until the input checks (not the counting) finish.
+ * Errors: every call returns tg_status.  Input checks run before any output
+ *   is written; on error the outputs are left untouched except where noted.
+ *   Device faults reported by HIP map to TG_E_DEVICE.
+ * Determinism: all counts are exact unsigned 64-bit integers; identical
+ *   inputs give identical outputs regardless of scheduling.
+ *
+ * Per-edge row layout (row_width(L) = 2L + 10 P columns, P = L(L+1)/2):
+ *   [ tri[t], t = 0..L-1 ]        |T_ij^t|: type-t nodes adjacent to both
+ *                                  i and j (typed triangles, Cor. 1)
+ *   [ path3[t], t = 0..L-1 ]      |S_i^t| + |S_j^t|, S_i^t the type-t
+ *                                  neighbours of i that are neither j nor
+ *                                  adjacent to j (typed 3-paths, Cor. 2-3)
+ *   [ g3 | g4 | ... | g12 ]       ten blocks of P columns, one per 4-node
+ *                                  orbit of Table 3; inside a block the
+ *                                  unordered type pair {t, t'} (t <= t') of
+ *                                  the two nodes outside the edge, in
+ *                                  lexicographic order: index
+ *                                  t*L - t(t-1)/2 + (t'-t).
+ *   Orbits: g3 4-path end edge, g4 4-path centre edge, g5 4-star, g6 4-cycle,
+ *   g7 tailed-triangle tail, g8 tailed-triangle edge opposite the tail's
+ *   node, g9 tailed-triangle edge at the tail's node, g10 chordal-cycle outer
+ *   edge, g11 chordal-cycle chord, g12 4-clique.
+ * Edge order: row e belongs to the e-th undirected edge (u, v), u < v, in
+ *   lexicographic order of (u, v) (the unique edge id of the parallel
+ *   scheme, Sec. 4.7).
+ * Global layout (global_width(L) = C(L+1,2) + 2 C(L+2,3) + 6 C(L+3,4)):
+ *   blocks h0 (edges), h1 (3-paths), h2 (triangles), h3 (4-paths),
+ *   h4 (4-stars), h5 (4-cycles), h6 (tailed triangles), h7 (chordal cycles),
+ *   h8 (4-cliques); inside a block, the sorted type multiset of the
+ *   graphlet's nodes at its co-lexicographic rank
+ *   sum_k C(s_k + k, k + 1) over the sorted types s_0 <= s_1 <= ....
+ *   Each entry is the number of instances (per-edge sums divided by the
+ *   graphlet's edge count, Problem 2 / Sec. 6).
+ */
+#ifndef TG_H
+#define TG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TG_MAX_L 16
+
+typedef enum tg_status {
+    TG_OK = 0,
+    TG_E_INVALID_ARG = 1, /* null pointer, negative size, odd nnz, ... */
+    TG_E_NOT_SIMPLE = 2,  /* unsorted row, duplicate, self-loop, asymmetric, id out of range */
+    TG_E_TYPE_RANGE = 3,  /* some types[v] >= L */
+    TG_E_L_RANGE = 4,     /* L < 1 or L > TG_MAX_L */
+    TG_E_WORKSPACE = 5,   /* workspace smaller than tg_workspace_bytes() */
+    TG_E_DEVICE = 6,      /* a HIP call failed */
+    TG_E_INTERNAL = 7,    /* an internal consistency check failed */
+    TG_E_TOO_LARGE = 8    /* n or nnz beyond the supported range (see below) */
+} tg_status;
+
+/* Human-readable name of a status code (static string). */
+const char *tg_status_str(tg_status s);
+
+/* Number of uint64 columns of a per-edge row, 2L + 10 L(L+1)/2; 0 if L is
+ * out of range. */
+int32_t tg_row_width(int32_t L);
+
+/* Number of uint64 entries of the global table; 0 if L is out of range. */
+int32_t tg_global_width(int32_t L);
+
+/* Bytes of device workspace tg_count_typed_graphlets needs for a graph of n
+ * nodes, nnz adjacency entries and L types.  Returns 0 for invalid sizes.
+ * Supported range: n < 2^31, nnz < 2^32. */
+size_t tg_workspace_bytes(int64_t n, int64_t nnz, int32_t L);
+
+/* Count typed 2-, 3- and 4-node graphlets for every edge (Problem 1,
+ * Algorithm 1) and globally (Problem 2).
+ *   row_ptr, col, types   device CSR and node types as described above.
+ *   per_edge              device uint64 [nnz/2][tg_row_width(L)] or NULL to
+ *                         skip the per-edge table (global counts only).
+ *   global_counts         device uint64 [tg_global_width(L)], or NULL.
+ *   workspace             device buffer of ws_bytes >= tg_workspace_bytes().
+ *   stream                hipStream_t as void*.
+ * Blocks until the input checks have run; the counting itself is enqueued
+ * on the stream and complete once the stream is synchronised. */
+tg_status tg_count_typed_graphlets(const int64_t *row_ptr, const int32_t *col,
+                                   const uint8_t *types, int64_t n, int64_t nnz, int32_t L,
+                                   uint64_t *per_edge, uint64_t *global_counts,
+                                   void *workspace, size_t ws_bytes, void *stream);
+
+/* Meaning of per-edge column `col` for L types: orbit 1 = tri, 2 = path3
+ * (with *t the third node's type and *t2 = -1), else the orbit number 3..12
+ * of Table 3 with the unordered type pair (*t <= *t2). */
+tg_status tg_key_describe(int32_t L, int32_t col, int32_t *orbit, int32_t *t, int32_t *t2);
+
+/* Meaning of global entry `idx`: *graphlet in 0..8 (h0..h8), *k its node
+ * count (2, 3 or 4) and types_sorted[0..k-1] the sorted type multiset. */
+tg_status tg_global_key_describe(int32_t L, int32_t idx, int32_t *graphlet,
+                                 int32_t types_sorted[4], int32_t *k);
+
+/* Timing of the phases of the most recent tg_count_typed_graphlets call on
+ * this host thread, measured with HIP events on the caller's stream when
+ * timing is enabled.  tg_set_timing(1) turns it on (off by default).
+ * tg_phase_times writes up to max_phases durations in milliseconds into ms
+ * and their names into names (static strings); returns the phase count.
+ * It synchronises on the recorded events. */
+void tg_set_timing(int32_t enable);
+int32_t tg_phase_times(float *ms, const char **names, int32_t max_phases);
+
+/* Work statistics of the most recent call (for bandwidth accounting):
+ * stats[0] = wedges of the 4-cycle passes (each pass), stats[1] = vertices
+ * in the light cycle path, stats[2] = vertices in the heavy cycle path,
+ * stats[3] = edges in the heavy clique path.  Synchronises the stream. */
+int32_t tg_last_stats(int64_t *stats, int32_t max_stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TG_H */

@@ -1,0 +1,121 @@
+"""ctypes binding of ``libtg.so`` (argument marshalling only).
+
+Every count is computed by the HIP kernels behind the C ABI in
+``include/tg.h``; this module only passes device pointers, sizes and the
+stream.  It raises if the library has not been built: there is no CPU
+fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libtg.so")
+
+# Every function the header declares, with its ctypes signature.
+_c = ctypes
+SIGNATURES = {
+    "tg_status_str": (_c.c_char_p, [_c.c_int]),
+    "tg_row_width": (_c.c_int32, [_c.c_int32]),
+    "tg_global_width": (_c.c_int32, [_c.c_int32]),
+    "tg_workspace_bytes": (_c.c_size_t, [_c.c_int64, _c.c_int64, _c.c_int32]),
+    "tg_count_typed_graphlets": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int64,
+                                            _c.c_int64, _c.c_int32, _c.c_void_p, _c.c_void_p,
+                                            _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "tg_key_describe": (_c.c_int, [_c.c_int32, _c.c_int32, _c.POINTER(_c.c_int32),
+                                   _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
+    "tg_global_key_describe": (_c.c_int, [_c.c_int32, _c.c_int32, _c.POINTER(_c.c_int32),
+                                          _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
+    "tg_set_timing": (None, [_c.c_int32]),
+    "tg_phase_times": (_c.c_int32, [_c.POINTER(_c.c_float), _c.POINTER(_c.c_char_p), _c.c_int32]),
+    "tg_last_stats": (_c.c_int32, [_c.POINTER(_c.c_int64), _c.c_int32]),
+}
+
+_lib = None
+
+
+class TGError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: tg_status {code} ({status_str(code)})")
+
+
+def load(path: str | None = None):
+    """Load the library (once).  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(
+            f"{p} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+            "(the typed-graphlet counts only run on the HIP library)")
+    lib = ctypes.CDLL(p)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_str(code: int) -> str:
+    s = load().tg_status_str(code)
+    return s.decode() if s else "?"
+
+
+def row_width(L: int) -> int:
+    return load().tg_row_width(L)
+
+
+def global_width(L: int) -> int:
+    return load().tg_global_width(L)
+
+
+def workspace_bytes(n: int, nnz: int, L: int) -> int:
+    return load().tg_workspace_bytes(n, nnz, L)
+
+
+def key_describe(L: int, col: int):
+    o, t, u = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    rc = load().tg_key_describe(L, col, ctypes.byref(o), ctypes.byref(t), ctypes.byref(u))
+    if rc:
+        raise TGError(rc, "tg_key_describe")
+    return o.value, t.value, u.value
+
+
+def global_key_describe(L: int, idx: int):
+    h, k = ctypes.c_int32(), ctypes.c_int32()
+    ts = (ctypes.c_int32 * 4)()
+    rc = load().tg_global_key_describe(L, idx, ctypes.byref(h), ts, ctypes.byref(k))
+    if rc:
+        raise TGError(rc, "tg_global_key_describe")
+    return h.value, tuple(ts[: k.value])
+
+
+def set_timing(enable: bool) -> None:
+    load().tg_set_timing(1 if enable else 0)
+
+
+def phase_times() -> list[tuple[str, float]]:
+    ms = (ctypes.c_float * 32)()
+    names = (ctypes.c_char_p * 32)()
+    cnt = load().tg_phase_times(ms, names, 32)
+    return [(names[q].decode(), float(ms[q])) for q in range(max(cnt, 0))]
+
+
+def last_stats() -> dict:
+    st = (ctypes.c_int64 * 8)()
+    load().tg_last_stats(st, 8)
+    return {"wedges_pass_a": st[0], "light_groups": st[1], "heavy_groups": st[2],
+            "heavy_edges": st[3], "wedges_pass_b": st[4]}
+
+
+def count_raw(row_ptr_ptr: int, col_ptr: int, types_ptr: int, n: int, nnz: int, L: int,
+              per_edge_ptr: int, global_ptr: int, ws_ptr: int, ws_bytes: int, stream: int) -> None:
+    rc = load().tg_count_typed_graphlets(row_ptr_ptr, col_ptr, types_ptr, n, nnz, L, per_edge_ptr,
+                                         global_ptr, ws_ptr, ws_bytes, stream)
+    if rc:
+        raise TGError(rc, "tg_count_typed_graphlets")

@@ -1,0 +1,442 @@
+// Host side of the typed-graphlet library: workspace planning, the input
+// checks, the launch sequence and the C ABI declared in include/tg.h.
+#include <hip/hip_runtime.h>
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include <cstring>
+#include <vector>
+
+#include "tg_internal.hpp"
+
+
+namespace tg {
+
+static int64_t binom_host(int64_t a, int64_t b) {
+    if (b < 0 || a < b) return 0;
+    int64_t r = 1;
+    for (int64_t k = 1; k <= b; ++k) r = r * (a - b + k) / k;
+    return r;
+}
+
+static int bits_for(int64_t n) {
+    int b = 1;
+    while ((int64_t(1) << b) < n) ++b;
+    return b;
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Bytes of dense cycle maps allowed; the number of heavy workgroups follows.
+static const size_t MAP_BUDGET = size_t(8) << 30;
+static const size_t TBUF_BUDGET = size_t(2) << 30;
+static const int MAX_HEAVY_SLOTS = 512;
+
+static size_t sort_tmp_bytes(int64_t n, int64_t nnz) {
+    size_t a = 0, b = 0, c = 0;
+    uint64_t *k = nullptr;
+    uint32_t *v = nullptr;
+    int64_t *s = nullptr;
+    if (rocprim::radix_sort_keys(nullptr, a, k, k, (size_t)(n > 0 ? n : 1), 0, 64) != hipSuccess ||
+        rocprim::radix_sort_pairs(nullptr, b, k, k, v, v, (size_t)(nnz > 0 ? nnz : 1), 0, 64) !=
+            hipSuccess ||
+        rocprim::exclusive_scan(nullptr, c, s, s, int64_t(0), (size_t)(n + 1),
+                                rocprim::plus<int64_t>()) != hipSuccess) {
+        // no device to ask (e.g. a build host): a bound well above what the
+        // radix sorts and scans request; the run re-checks the real need
+        return (size_t)(64 << 20) + (size_t)(n + nnz + 2) * 16;
+    }
+    size_t mx = a;
+    if (b > mx) mx = b;
+    if (c > mx) mx = c;
+    return mx + 256;
+}
+
+tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay) {
+    if (L < 1 || L > TG_MAX_L) return TG_E_L_RANGE;
+    if (n < 0 || nnz < 0 || (nnz & 1)) return TG_E_INVALID_ARG;
+    if (n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 32)) return TG_E_TOO_LARGE;
+    Layout &y = *lay;
+    memset(&y, 0, sizeof(y));
+    y.n = n;
+    y.nnz = nnz;
+    y.m = nnz / 2;
+    y.L = L;
+    int64_t LL = (int64_t)L * L;
+    size_t per_map = (size_t)(n > 0 ? n : 1) * L * sizeof(uint32_t);
+    int64_t slots = (int64_t)(MAP_BUDGET / per_map);
+    if (slots > MAX_HEAVY_SLOTS) slots = MAX_HEAVY_SLOTS;
+    if (slots < 1) slots = 1;
+    y.heavy_slots = (int)slots;
+    size_t per_t = (size_t)(n > 0 ? n : 1) * sizeof(uint32_t);
+    int64_t eslots = (int64_t)(TBUF_BUDGET / per_t);
+    if (eslots > MAX_HEAVY_SLOTS) eslots = MAX_HEAVY_SLOTS;
+    if (eslots < 1) eslots = 1;
+    y.heavy_edge_slots = (int)eslots;
+    y.sort_tmp_bytes = sort_tmp_bytes(n, nnz);
+    if (y.sort_tmp_bytes == 0) return TG_E_INTERNAL;
+    int gw = (int)(binom_host(L + 1, 2) + 2 * binom_host(L + 2, 3) + 6 * binom_host(L + 3, 4));
+
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    y.off_status = take(64);
+    y.off_counters = take(sizeof(uint64_t) * C_NUM);
+    y.off_deg = take(sizeof(uint32_t) * (n + 1));
+    y.off_ucount = take(sizeof(int64_t) * (n + 1));
+    y.off_eoff = take(sizeof(int64_t) * (n + 1));
+    y.off_order = take(sizeof(int32_t) * (n + 1));
+    y.off_newid = take(sizeof(int32_t) * (n + 1));
+    y.off_ntype = take(n + 1);
+    y.off_nrp = take(sizeof(int64_t) * (n + 1));
+    y.off_ndeg = take(sizeof(int64_t) * (n + 1));
+    int64_t nk = nnz > n ? nnz : n;
+    y.off_key_a = take(sizeof(uint64_t) * (nk + 1));
+    y.off_key_b = take(sizeof(uint64_t) * (nk + 1));
+    y.off_val_a = take(sizeof(uint32_t) * (nnz + 1));
+    y.off_val_b = take(sizeof(uint32_t) * (nnz + 1));
+    y.off_ncol = take(sizeof(int32_t) * (nnz + 1));
+    y.off_neid = take(sizeof(uint32_t) * (nnz + 1));
+    y.off_ei = take(sizeof(int32_t) * (y.m + 1));
+    y.off_ej = take(sizeof(int32_t) * (y.m + 1));
+    y.off_tdeg = take(sizeof(uint32_t) * (n + 1) * L);
+    y.off_tri = take(sizeof(uint32_t) * (y.m + 1) * L);
+    y.off_A = take(sizeof(uint64_t) * (n + 1) * LL);
+    y.off_D = take(sizeof(uint64_t) * (n + 1) * LL);
+    y.off_NC = take(sizeof(uint64_t) * (y.m + 1) * LL);
+    y.off_listA_light = take(sizeof(uint32_t) * (n + 1));
+    y.off_listA_heavy = take(sizeof(uint32_t) * (n + 1));
+    y.off_listB_light = take(sizeof(uint32_t) * (n + 1));
+    y.off_listB_heavy = take(sizeof(uint32_t) * (n + 1));
+    y.off_list_edge = take(sizeof(uint32_t) * (y.m + 1));
+    y.off_maps = take(per_map * (size_t)y.heavy_slots);
+    y.off_tbuf = take(per_t * (size_t)y.heavy_edge_slots);
+    y.off_gacc = take(sizeof(uint64_t) * gw);
+    y.off_sort_tmp = take(y.sort_tmp_bytes);
+    y.total = off;
+    return TG_OK;
+}
+
+// --------------------------------------------------------------- timing
+
+namespace {
+struct Timing {
+    bool enabled = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<const char *> names;
+    int used = 0;
+    hipStream_t stream = nullptr;
+    int64_t stats[8] = {0};
+};
+thread_local Timing g_timing;
+
+void timing_reset(hipStream_t st) {
+    g_timing.used = 0;
+    g_timing.names.clear();
+    g_timing.stream = st;
+}
+
+void timing_mark(const char *name) {
+    if (!g_timing.enabled) return;
+    Timing &T = g_timing;
+    if ((int)T.ev.size() <= T.used) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        T.ev.push_back(e);
+    }
+    if (hipEventRecord(T.ev[T.used], T.stream) != hipSuccess) return;
+    T.names.push_back(name);
+    ++T.used;
+}
+}  // namespace
+
+static tg_status status_from_bits(uint32_t bits) {
+    if (bits & ST_TYPE_RANGE) return TG_E_TYPE_RANGE;
+    if (bits & (ST_COL_RANGE | ST_UNSORTED | ST_SELF_LOOP | ST_ASYMMETRIC)) return TG_E_NOT_SIMPLE;
+    if (bits) return TG_E_INTERNAL;
+    return TG_OK;
+}
+
+#define HIPCHK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return TG_E_DEVICE; } while (0)
+
+template <class T>
+static T *at(void *base, size_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(base) + off);
+}
+
+static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *types, int64_t n,
+                     int64_t nnz, int L, uint64_t *per_edge, uint64_t *global_counts, void *ws,
+                     const Layout &y, hipStream_t st) {
+    const int64_t m = y.m;
+    const int LL = L * L;
+    const int gw = tg_global_width(L);
+    uint32_t *status = at<uint32_t>(ws, y.off_status);
+    uint64_t *counters = at<uint64_t>(ws, y.off_counters);
+    uint32_t *deg = at<uint32_t>(ws, y.off_deg);
+    int64_t *ucount = at<int64_t>(ws, y.off_ucount);
+    int64_t *eoff = at<int64_t>(ws, y.off_eoff);
+    int32_t *order = at<int32_t>(ws, y.off_order);
+    int32_t *newid = at<int32_t>(ws, y.off_newid);
+    uint8_t *ntype = at<uint8_t>(ws, y.off_ntype);
+    int64_t *nrp = at<int64_t>(ws, y.off_nrp);
+    int64_t *ndeg = at<int64_t>(ws, y.off_ndeg);
+    uint64_t *key_a = at<uint64_t>(ws, y.off_key_a);
+    uint64_t *key_b = at<uint64_t>(ws, y.off_key_b);
+    uint32_t *val_a = at<uint32_t>(ws, y.off_val_a);
+    uint32_t *val_b = at<uint32_t>(ws, y.off_val_b);
+    int32_t *ncol = at<int32_t>(ws, y.off_ncol);
+    uint32_t *neid = at<uint32_t>(ws, y.off_neid);
+    int32_t *ei = at<int32_t>(ws, y.off_ei);
+    int32_t *ej = at<int32_t>(ws, y.off_ej);
+    uint32_t *tdeg = at<uint32_t>(ws, y.off_tdeg);
+    uint32_t *tri = at<uint32_t>(ws, y.off_tri);
+    uint64_t *A = at<uint64_t>(ws, y.off_A);
+    uint64_t *D = at<uint64_t>(ws, y.off_D);
+    uint64_t *NC = at<uint64_t>(ws, y.off_NC);
+    uint32_t *la_l = at<uint32_t>(ws, y.off_listA_light);
+    uint32_t *la_h = at<uint32_t>(ws, y.off_listA_heavy);
+    uint32_t *lb_l = at<uint32_t>(ws, y.off_listB_light);
+    uint32_t *lb_h = at<uint32_t>(ws, y.off_listB_heavy);
+    uint32_t *le = at<uint32_t>(ws, y.off_list_edge);
+    uint32_t *maps = at<uint32_t>(ws, y.off_maps);
+    uint32_t *tbuf = at<uint32_t>(ws, y.off_tbuf);
+    uint64_t *gacc = at<uint64_t>(ws, y.off_gacc);
+    void *stmp = at<void>(ws, y.off_sort_tmp);
+    size_t stmp_bytes = y.sort_tmp_bytes;
+    if (sort_tmp_bytes(n, nnz) > stmp_bytes) return TG_E_INTERNAL;
+
+    timing_reset(st);
+    timing_mark("start");
+    // status, counters and global accumulators start at zero
+    HIPCHK(launch_fill_u64(reinterpret_cast<uint64_t *>(status), 0, 8, st));
+    HIPCHK(launch_fill_u64(counters, 0, C_NUM, st));
+    HIPCHK(launch_fill_u64(gacc, 0, gw, st));
+
+    // ---- input checks: rows, degrees, the canonical edge numbering
+    HIPCHK(launch_check_rows(row_ptr, col, types, n, nnz, L, deg, ucount, status, st));
+    HIPCHK(rocprim::exclusive_scan(stmp, stmp_bytes, ucount, eoff, int64_t(0), (size_t)(n + 1),
+                                   rocprim::plus<int64_t>(), st));
+    struct {
+        uint32_t status;
+        uint32_t pad;
+        int64_t upper;
+    } probe;
+    HIPCHK(hipMemcpyAsync(&probe.status, status, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&probe.upper, eoff + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (probe.status) return status_from_bits(probe.status);
+    if (probe.upper != m) return TG_E_NOT_SIMPLE;
+
+    // ---- relabel by (degree, id): rank order = internal id order
+    HIPCHK(launch_node_keys(deg, n, key_a, st));
+    HIPCHK(rocprim::radix_sort_keys(stmp, stmp_bytes, key_a, key_b, (size_t)n, 0, 64, st));
+    HIPCHK(launch_relabel(key_b, types, deg, n, order, newid, ntype, ndeg, st));
+    HIPCHK(rocprim::exclusive_scan(stmp, stmp_bytes, ndeg, nrp, int64_t(0), (size_t)(n + 1),
+                                   rocprim::plus<int64_t>(), st));
+    const int bits = bits_for(n);
+    HIPCHK(launch_slot_keys(row_ptr, col, ucount, eoff, newid, n, bits, key_a, val_a, ei, ej, status,
+                            st));
+    HIPCHK(hipMemcpyAsync(&probe.status, status, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (probe.status) return status_from_bits(probe.status);
+    HIPCHK(rocprim::radix_sort_pairs(stmp, stmp_bytes, key_a, key_b, val_a, val_b, (size_t)nnz, 0,
+                                     2 * bits, st));
+    HIPCHK(launch_finish_csr(key_b, val_b, nnz, bits, ncol, neid, st));
+    HIPCHK(launch_tdeg(nrp, ncol, ntype, n, L, tdeg, st));
+    timing_mark("prep");
+
+    // ---- typed triangles and node aggregates
+    HIPCHK(launch_tri(nrp, ncol, ntype, ei, ej, m, L, tri, st));
+    timing_mark("tri");
+    HIPCHK(launch_node_aggr(nrp, ncol, ntype, neid, tri, tdeg, n, L, A, D, st));
+    timing_mark("aggr");
+
+    // ---- 4-cycles from degree-ordered wedges
+    HIPCHK(launch_fill_u64(NC, 0, m * LL, st));
+    HIPCHK(launch_cyc_work(nrp, ncol, n, la_l, la_h, lb_l, lb_h, counters, st));
+    timing_mark("cyc_work");
+    CycleArgs ca;
+    ca.nrp = nrp; ca.ncol = ncol; ca.ntype = ntype; ca.neid = neid; ca.ei = ei;
+    ca.counters = counters; ca.L = L; ca.n = n; ca.NC = NC; ca.maps = maps;
+    ca.chunk = heavy_chunk_for(L);
+    ca.status = status;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    int cus = 0;
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    unsigned light_grid = (unsigned)(cus > 0 ? cus * 16 : 1024);
+    for (int pass = 0; pass < 2; ++pass) {
+        ca.list = pass == 0 ? la_l : lb_l;
+        ca.count_idx = pass == 0 ? C_A_LIGHT : C_B_LIGHT;
+        ca.next_idx = 0;
+        HIPCHK(launch_cycles(pass, false, ca, light_grid, st));
+        timing_mark(pass == 0 ? "cycA_light" : "cycB_light");
+        ca.list = pass == 0 ? la_h : lb_h;
+        ca.count_idx = pass == 0 ? C_A_HEAVY : C_B_HEAVY;
+        ca.next_idx = pass == 0 ? C_A_NEXT : C_B_NEXT;
+        HIPCHK(launch_cycles(pass, true, ca, (unsigned)y.heavy_slots, st));
+        timing_mark(pass == 0 ? "cycA_heavy" : "cycB_heavy");
+    }
+
+    // ---- cliques, derivation, rows and global counts
+    EdgeArgs ea;
+    ea.nrp = nrp; ea.ncol = ncol; ea.ntype = ntype; ea.neid = neid; ea.ei = ei; ea.ej = ej;
+    ea.tri = tri; ea.tdeg = tdeg; ea.A = A; ea.D = D; ea.NC = NC; ea.m = m; ea.L = L;
+    ea.rows = per_edge; ea.gacc = gacc; ea.gw = gw;
+    ea.hist_in_lds = (size_t)gw * sizeof(uint64_t) <= 32768 ? 1 : 0;
+    ea.heavy_list = le; ea.counters = counters; ea.tbuf = tbuf; ea.n = n; ea.status = status;
+    unsigned edge_grid = (unsigned)(cus > 0 ? cus * 24 : 2048);
+    if ((int64_t)edge_grid > m) edge_grid = (unsigned)(m > 0 ? m : 1);
+    HIPCHK(launch_edges(false, ea, edge_grid, st));
+    timing_mark("edges_light");
+    HIPCHK(launch_edges(true, ea, (unsigned)y.heavy_edge_slots, st));
+    timing_mark("edges_heavy");
+    if (global_counts)
+        HIPCHK(launch_global_finalize(gacc, L, gw, global_counts, status, st));
+    timing_mark("global");
+
+    HIPCHK(hipMemcpyAsync(&probe.status, status, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    uint64_t cnt_host[C_NUM];
+    HIPCHK(hipMemcpyAsync(cnt_host, counters, sizeof(cnt_host), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    g_timing.stats[0] = (int64_t)cnt_host[C_WEDGES_A];
+    g_timing.stats[1] = (int64_t)(cnt_host[C_A_LIGHT] + cnt_host[C_B_LIGHT]);
+    g_timing.stats[2] = (int64_t)(cnt_host[C_A_HEAVY] + cnt_host[C_B_HEAVY]);
+    g_timing.stats[3] = (int64_t)cnt_host[C_EDGE_HEAVY];
+    g_timing.stats[4] = (int64_t)cnt_host[C_WEDGES_B];
+    if (probe.status) return TG_E_INTERNAL;
+    return TG_OK;
+}
+
+}  // namespace tg
+
+// ================================================================ C ABI
+
+extern "C" {
+
+const char *tg_status_str(tg_status s) {
+    switch (s) {
+        case TG_OK: return "ok";
+        case TG_E_INVALID_ARG: return "invalid argument";
+        case TG_E_NOT_SIMPLE: return "graph is not a simple symmetric sorted CSR";
+        case TG_E_TYPE_RANGE: return "node type out of range";
+        case TG_E_L_RANGE: return "number of types out of range";
+        case TG_E_WORKSPACE: return "workspace too small";
+        case TG_E_DEVICE: return "HIP error";
+        case TG_E_INTERNAL: return "internal consistency check failed";
+        case TG_E_TOO_LARGE: return "graph too large";
+    }
+    return "unknown status";
+}
+
+int32_t tg_row_width(int32_t L) {
+    if (L < 1 || L > TG_MAX_L) return 0;
+    return 2 * L + 10 * (L * (L + 1) / 2);
+}
+
+int32_t tg_global_width(int32_t L) {
+    if (L < 1 || L > TG_MAX_L) return 0;
+    return (int32_t)(tg::binom_host(L + 1, 2) + 2 * tg::binom_host(L + 2, 3) +
+                     6 * tg::binom_host(L + 3, 4));
+}
+
+size_t tg_workspace_bytes(int64_t n, int64_t nnz, int32_t L) {
+    tg::Layout y;
+    if (tg::plan_layout(n, nnz, L, &y) != TG_OK) return 0;
+    return y.total;
+}
+
+tg_status tg_count_typed_graphlets(const int64_t *row_ptr, const int32_t *col,
+                                   const uint8_t *types, int64_t n, int64_t nnz, int32_t L,
+                                   uint64_t *per_edge, uint64_t *global_counts, void *workspace,
+                                   size_t ws_bytes, void *stream) {
+    tg::Layout y;
+    tg_status s = tg::plan_layout(n, nnz, L, &y);
+    if (s != TG_OK) return s;
+    if (n > 0 && (!row_ptr || !types)) return TG_E_INVALID_ARG;
+    if (nnz > 0 && !col) return TG_E_INVALID_ARG;
+    if (!workspace) return TG_E_INVALID_ARG;
+    if (ws_bytes < y.total) return TG_E_WORKSPACE;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (n == 0) {
+        if (global_counts && tg::launch_fill_u64(global_counts, 0, tg_global_width(L), st) !=
+                                 hipSuccess)
+            return TG_E_DEVICE;
+        return hipStreamSynchronize(st) == hipSuccess ? TG_OK : TG_E_DEVICE;
+    }
+    return tg::run(row_ptr, col, types, n, nnz, L, per_edge, global_counts, workspace, y, st);
+}
+
+tg_status tg_key_describe(int32_t L, int32_t c, int32_t *orbit, int32_t *t, int32_t *t2) {
+    if (L < 1 || L > TG_MAX_L) return TG_E_L_RANGE;
+    if (!orbit || !t || !t2 || c < 0 || c >= tg_row_width(L)) return TG_E_INVALID_ARG;
+    if (c < 2 * L) {
+        *orbit = c < L ? 1 : 2;
+        *t = c % L;
+        *t2 = -1;
+        return TG_OK;
+    }
+    int P = L * (L + 1) / 2;
+    int q = c - 2 * L;
+    *orbit = 3 + q / P;
+    int p = q % P, a = 0;
+    while (p >= L - a) { p -= L - a; ++a; }
+    *t = a;
+    *t2 = a + p;
+    return TG_OK;
+}
+
+tg_status tg_global_key_describe(int32_t L, int32_t idx, int32_t *graphlet, int32_t types_sorted[4],
+                                 int32_t *k) {
+    if (L < 1 || L > TG_MAX_L) return TG_E_L_RANGE;
+    if (!graphlet || !types_sorted || !k || idx < 0 || idx >= tg_global_width(L))
+        return TG_E_INVALID_ARG;
+    int64_t n2 = tg::binom_host(L + 1, 2), n3 = tg::binom_host(L + 2, 3),
+            n4 = tg::binom_host(L + 3, 4);
+    int64_t r;
+    int h, kk;
+    if (idx < n2) { h = 0; kk = 2; r = idx; }
+    else if (idx < n2 + n3) { h = 1; kk = 3; r = idx - n2; }
+    else if (idx < n2 + 2 * n3) { h = 2; kk = 3; r = idx - n2 - n3; }
+    else { int64_t q = idx - n2 - 2 * n3; h = 3 + (int)(q / n4); kk = 4; r = q % n4; }
+    // invert the co-lexicographic rank: largest element first
+    int32_t out[4] = {0, 0, 0, 0};
+    for (int pos = kk - 1; pos >= 0; --pos) {
+        int64_t c = pos;  // s_pos + pos is the largest c with C(c, pos+1) <= r
+        while (tg::binom_host(c + 1, pos + 1) <= r) ++c;
+        r -= tg::binom_host(c, pos + 1);
+        out[pos] = (int32_t)(c - pos);
+    }
+    *graphlet = h;
+    *k = kk;
+    for (int q = 0; q < 4; ++q) types_sorted[q] = q < kk ? out[q] : -1;
+    return TG_OK;
+}
+
+void tg_set_timing(int32_t enable) { tg::g_timing.enabled = enable != 0; }
+
+int32_t tg_phase_times(float *ms, const char **names, int32_t max_phases) {
+    tg::Timing &T = tg::g_timing;
+    if (T.used < 2) return 0;
+    if (hipEventSynchronize(T.ev[T.used - 1]) != hipSuccess) return -1;
+    int cnt = 0;
+    for (int q = 1; q < T.used && cnt < max_phases; ++q, ++cnt) {
+        float v = 0.f;
+        if (hipEventElapsedTime(&v, T.ev[q - 1], T.ev[q]) != hipSuccess) v = -1.f;
+        if (ms) ms[cnt] = v;
+        if (names) names[cnt] = T.names[q];
+    }
+    return cnt;
+}
+
+int32_t tg_last_stats(int64_t *stats, int32_t max_stats) {
+    int cnt = max_stats < 8 ? max_stats : 8;
+    for (int q = 0; q < cnt; ++q) stats[q] = tg::g_timing.stats[q];
+    return cnt;
+}
+
+}  // extern "C"

@@ -1,0 +1,133 @@
+// Internal declarations shared by the library's HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tg.h"
+
+namespace tg {
+
+constexpr int WAVE = 64;
+
+// Status bits raised on the device by the input checks and the counters.
+enum : uint32_t {
+    ST_COL_RANGE = 1u << 0,
+    ST_UNSORTED = 1u << 1,
+    ST_SELF_LOOP = 1u << 2,
+    ST_TYPE_RANGE = 1u << 3,
+    ST_ASYMMETRIC = 1u << 4,
+    ST_INTERNAL = 1u << 5,
+    ST_NOT_DIVISIBLE = 1u << 6,
+};
+
+// Tunables of the cycle and clique passes.
+constexpr int LIGHT_HCAP = 1024;      // LDS hash slots per light group
+constexpr int64_t LIGHT_MAXW = 512;   // a group is light if it has at most this many wedges
+constexpr int HEAVY_THREADS = 256;    // threads of a heavy-group workgroup
+constexpr int HEAVY_CHUNK = 128;      // items staged per round in the heavy path
+constexpr int TCAP = 1024;            // triangle set kept in LDS by the light edge kernel
+constexpr int EDGE_THREADS_HEAVY = 256;
+
+// Device-side layout of everything the library keeps in the caller's
+// workspace.  All offsets are byte offsets from the workspace base.
+struct Layout {
+    int64_t n, nnz, m;
+    int L;
+    int heavy_slots;          // dense cycle maps (one per heavy workgroup)
+    int heavy_edge_slots;     // global triangle buffers of the heavy edge kernel
+    size_t sort_tmp_bytes;
+    size_t off_status, off_counters;
+    size_t off_deg, off_ucount, off_eoff, off_order, off_newid, off_ntype, off_nrp, off_ndeg;
+    size_t off_key_a, off_key_b, off_val_a, off_val_b;
+    size_t off_ncol, off_neid, off_ei, off_ej;
+    size_t off_tdeg, off_tri, off_A, off_D, off_NC;
+    size_t off_listA_light, off_listA_heavy, off_listB_light, off_listB_heavy, off_list_edge;
+    size_t off_maps, off_tbuf, off_gacc, off_sort_tmp;
+    size_t total;
+};
+
+// Counters block (uint64 each) at off_counters.
+enum Counter {
+    C_A_LIGHT = 0, C_A_HEAVY, C_B_LIGHT, C_B_HEAVY, C_EDGE_HEAVY,
+    C_A_NEXT, C_B_NEXT, C_EDGE_NEXT, C_WEDGES_A, C_WEDGES_B,
+    C_NUM
+};
+
+tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay);
+
+// Arguments of the 4-cycle passes.
+struct CycleArgs {
+    const int64_t *nrp;
+    const int32_t *ncol;
+    const uint8_t *ntype;
+    const uint32_t *neid;
+    const int32_t *ei;
+    const uint32_t *list;
+    uint64_t *counters;
+    int count_idx;
+    int next_idx;
+    int L;
+    int64_t n;
+    uint64_t *NC;
+    uint32_t *maps;
+    int chunk;
+    uint32_t *status;
+};
+
+// Arguments of the per-edge clique / derivation kernels.
+struct EdgeArgs {
+    const int64_t *nrp;
+    const int32_t *ncol;
+    const uint8_t *ntype;
+    const uint32_t *neid;
+    const int32_t *ei, *ej;
+    const uint32_t *tri, *tdeg;
+    const uint64_t *A, *D, *NC;
+    int64_t m;
+    int L;
+    uint64_t *rows;      // may be null
+    uint64_t *gacc;      // global accumulators
+    int gw;
+    int hist_in_lds;
+    uint32_t *heavy_list;
+    uint64_t *counters;
+    uint32_t *tbuf;      // heavy: per-workgroup triangle buffers of n entries
+    int64_t n;
+    uint32_t *status;
+};
+
+// Launch wrappers (tg_kernels.hip).
+hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t st);
+hipError_t launch_check_rows(const int64_t *rp, const int32_t *col, const uint8_t *types, int64_t n,
+                             int64_t nnz, int L, uint32_t *deg, int64_t *ucount, uint32_t *status,
+                             hipStream_t st);
+hipError_t launch_node_keys(const uint32_t *deg, int64_t n, uint64_t *keys, hipStream_t st);
+hipError_t launch_relabel(const uint64_t *sorted, const uint8_t *types, const uint32_t *deg, int64_t n,
+                          int32_t *order, int32_t *newid, uint8_t *ntype, int64_t *ndeg,
+                          hipStream_t st);
+hipError_t launch_slot_keys(const int64_t *rp, const int32_t *col, const int64_t *ucount,
+                            const int64_t *eoff, const int32_t *newid, int64_t n, int bits,
+                            uint64_t *keys, uint32_t *vals, int32_t *ei, int32_t *ej,
+                            uint32_t *status, hipStream_t st);
+hipError_t launch_finish_csr(const uint64_t *keys, const uint32_t *vals, int64_t nnz, int bits,
+                             int32_t *ncol, uint32_t *neid, hipStream_t st);
+hipError_t launch_tdeg(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype, int64_t n,
+                       int L, uint32_t *tdeg, hipStream_t st);
+hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype,
+                      const int32_t *ei, const int32_t *ej, int64_t m, int L, uint32_t *tri,
+                      hipStream_t st);
+hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype,
+                            const uint32_t *neid, const uint32_t *tri, const uint32_t *tdeg,
+                            int64_t n, int L, uint64_t *A, uint64_t *D, hipStream_t st);
+hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, int64_t n, uint32_t *la_l,
+                           uint32_t *la_h, uint32_t *lb_l, uint32_t *lb_h, uint64_t *counters,
+                           hipStream_t st);
+int heavy_chunk_for(int L);
+hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned grid, hipStream_t st);
+hipError_t launch_edges(bool heavy, const EdgeArgs &args, unsigned grid, hipStream_t st);
+hipError_t launch_global_finalize(const uint64_t *gacc, int L, int gw, uint64_t *out,
+                                  uint32_t *status, hipStream_t st);
+
+
+}  // namespace tg

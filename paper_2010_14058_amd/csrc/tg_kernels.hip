@@ -1,0 +1,1070 @@
+// Device kernels of the typed-graphlet library (gfx950, wave64).
+//
+// Pipeline for one graph (all integer arithmetic):
+//   prep      validate the CSR, relabel nodes by (degree, id) so that a
+//             larger internal id means a higher rank, build the relabelled
+//             CSR with each slot's canonical edge id, typed degrees.
+//   tri       typed triangle counts |T_ij^t| per edge (Cor. 1; intersection
+//             of the two neighbour lists).
+//   aggr      per node u: A_u(t,t') = sum over type-t neighbours k of
+//             |T_uk^t'| and D_u(t,t') = sum over type-t neighbours k of
+//             d_k^t'.
+//   cycles    non-induced typed 4-cycle counts NC per edge from
+//             degree-ordered wedges: every 4-cycle is found once from its
+//             highest-ranked vertex (pass A credits the two cycle edges at
+//             that vertex, pass B the two far edges).
+//   edges     per edge: the triangle set T, ordered typed clique pairs K
+//             (Alg. 3's 4-clique branch), gathers X_i, X_j, Y over T; then
+//             every orbit of Table 3 by inclusion-exclusion in the spirit of
+//             Theorem 1 and Lemmas 1-4, the row write, and the per-workgroup
+//             histogram of global counts (Problem 2).
+#include <hip/hip_runtime.h>
+
+#include "tg_internal.hpp"
+
+namespace tg {
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
+
+__device__ __forceinline__ int64_t lower_bound(const int32_t *a, int64_t lo, int64_t hi,
+                                               int32_t key) {
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int64_t upper_bound(const int32_t *a, int64_t lo, int64_t hi,
+                                               int32_t key) {
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] <= key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// First index in s[0..len) whose value exceeds f (s inclusive scan, LDS).
+__device__ __forceinline__ int owner_of(const uint32_t *s, int len, uint32_t f) {
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (s[mid] <= f) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        uint32_t o = __shfl_up(v, d, WAVE);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) v += (uint64_t)__shfl_xor((unsigned long long)v, d, WAVE);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) v |= __shfl_xor(v, d, WAVE);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t load_agent(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// C(n, r) for r <= 4 (co-lexicographic ranks of type multisets).
+__device__ __forceinline__ int64_t binom_small(int64_t n, int r) {
+    if (n < r) return 0;
+    switch (r) {
+        case 1: return n;
+        case 2: return n * (n - 1) / 2;
+        case 3: return n * (n - 1) * (n - 2) / 6;
+        default: return n * (n - 1) * (n - 2) * (n - 3) / 24;
+    }
+}
+
+__device__ __forceinline__ void sort2(int &a, int &b) { if (a > b) { int c = a; a = b; b = c; } }
+
+__device__ __forceinline__ int rank2(int a, int b) {
+    sort2(a, b);
+    return (int)(binom_small(a, 1) + binom_small(b + 1, 2));
+}
+
+__device__ __forceinline__ int rank3(int a, int b, int c) {
+    sort2(a, b); sort2(b, c); sort2(a, b);
+    return (int)(binom_small(a, 1) + binom_small(b + 1, 2) + binom_small(c + 2, 3));
+}
+
+__device__ __forceinline__ int rank4(int a, int b, int c, int d) {
+    sort2(a, b); sort2(c, d); sort2(a, c); sort2(b, d); sort2(b, c);
+    return (int)(binom_small(a, 1) + binom_small(b + 1, 2) + binom_small(c + 2, 3) +
+                 binom_small(d + 3, 4));
+}
+
+// ------------------------------------------------------------------ prep
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t count) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += stride) p[q] = v;
+}
+
+// One wave per input row: row checks, degree, number of larger neighbours.
+__global__ void k_check_rows(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                             const uint8_t *__restrict__ types, int64_t n, int64_t nnz, int L,
+                             uint32_t *__restrict__ deg, int64_t *__restrict__ ucount,
+                             uint32_t *__restrict__ status) {
+    int64_t u = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
+    int lane = lane_id();
+    if (u > n) return;
+    if (u == n) {  // sentinel of the exclusive scan
+        if (lane == 0) ucount[n] = 0;
+        return;
+    }
+    int64_t b = rp[u], e = rp[u + 1];
+    uint32_t bad = 0;
+    if (b < 0 || e > nnz || e < b || (u == 0 && b != 0) || (u == n - 1 && e != nnz)) {
+        if (lane == 0) {
+            atomicOr(status, ST_UNSORTED);
+            deg[u] = 0;
+            ucount[u] = 0;
+        }
+        return;
+    }
+    uint64_t up = 0;
+    for (int64_t s = b + lane; s < e; s += WAVE) {
+        int32_t x = col[s];
+        if (x < 0 || x >= n) bad |= ST_COL_RANGE;
+        if (x == u) bad |= ST_SELF_LOOP;
+        if (s > b && col[s - 1] >= x) bad |= ST_UNSORTED;
+        if (x > u) ++up;
+    }
+    up = wave_sum_u64(up);
+    bad = wave_or(bad);
+    if (lane == 0) {
+        if (types[u] >= L) bad |= ST_TYPE_RANGE;
+        deg[u] = (uint32_t)(e - b);
+        ucount[u] = (int64_t)up;
+        if (bad) atomicOr(status, bad);
+    }
+}
+
+// keys[v] = degree << 32 | v (rank order = sorted order)
+__global__ void k_node_keys(const uint32_t *__restrict__ deg, int64_t n, uint64_t *__restrict__ keys) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) keys[v] = ((uint64_t)deg[v] << 32) | (uint64_t)v;
+}
+
+__global__ void k_relabel(const uint64_t *__restrict__ sorted, const uint8_t *__restrict__ types,
+                          const uint32_t *__restrict__ deg, int64_t n,
+                          int32_t *__restrict__ order, int32_t *__restrict__ newid,
+                          uint8_t *__restrict__ ntype, int64_t *__restrict__ ndeg) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) {
+        int32_t v = (int32_t)(sorted[r] & 0xffffffffu);
+        order[r] = v;
+        newid[v] = (int32_t)r;
+        ntype[r] = types[v];
+        ndeg[r] = deg[v];
+    }
+    if (r == 0) ndeg[n] = 0;
+}
+
+// One wave per input row: canonical edge id of every slot, the relabelled
+// slot key (row << bits | col), and the canonical endpoints of each edge.
+__global__ void k_slot_keys(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                            const int64_t *__restrict__ ucount, const int64_t *__restrict__ eoff,
+                            const int32_t *__restrict__ newid, int64_t n, int bits,
+                            uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                            int32_t *__restrict__ ei, int32_t *__restrict__ ej,
+                            uint32_t *__restrict__ status) {
+    int64_t u = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
+    int lane = lane_id();
+    if (u >= n) return;
+    int64_t b = rp[u], e = rp[u + 1];
+    int64_t ustart = e - ucount[u];
+    uint32_t bad = 0;
+    uint64_t nu = (uint64_t)newid[u];
+    for (int64_t s = b + lane; s < e; s += WAVE) {
+        int32_t x = col[s];
+        int64_t eid;
+        if (x > u) {
+            eid = eoff[u] + (s - ustart);
+            ei[eid] = (int32_t)nu;
+            ej[eid] = newid[x];
+        } else {
+            int64_t xb = rp[x], xe = rp[x + 1];
+            int64_t p = lower_bound(col, xb, xe, (int32_t)u);
+            if (p >= xe || col[p] != (int32_t)u) {
+                bad |= ST_ASYMMETRIC;
+                eid = 0;
+            } else {
+                eid = eoff[x] + (p - (xe - ucount[x]));
+            }
+        }
+        keys[s] = (nu << bits) | (uint64_t)newid[x];
+        vals[s] = (uint32_t)eid;
+    }
+    bad = wave_or(bad);
+    if (lane == 0 && bad) atomicOr(status, bad);
+}
+
+__global__ void k_finish_csr(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
+                             int64_t nnz, int bits, int32_t *__restrict__ ncol,
+                             uint32_t *__restrict__ neid) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < nnz) {
+        ncol[s] = (int32_t)(keys[s] & ((1ull << bits) - 1));
+        neid[s] = vals[s];
+    }
+}
+
+// One wave per internal node: typed degrees d_v^t.
+__global__ void k_tdeg(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
+                       const uint8_t *__restrict__ ntype, int64_t n, int L,
+                       uint32_t *__restrict__ tdeg) {
+    int64_t v = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
+    int lane = lane_id();
+    if (v >= n) return;
+    uint32_t c = 0;
+    for (int64_t base = nrp[v]; base < nrp[v + 1]; base += WAVE) {
+        int64_t s = base + lane;
+        int t = s < nrp[v + 1] ? (int)ntype[ncol[s]] : -1;
+        for (int tt = 0; tt < L; ++tt) {
+            uint64_t bal = __ballot(t == tt);
+            if (lane == tt) c += (uint32_t)__popcll(bal);
+        }
+    }
+    if (lane < L) tdeg[v * L + lane] = c;
+}
+
+// ------------------------------------------------------- typed triangles
+
+// One wave per edge: |T^t| by probing the shorter list in the longer one.
+__global__ void k_tri(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
+                      const uint8_t *__restrict__ ntype, const int32_t *__restrict__ ei,
+                      const int32_t *__restrict__ ej, int64_t m, int L,
+                      uint32_t *__restrict__ tri) {
+    int64_t e = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
+    int lane = lane_id();
+    if (e >= m) return;
+    int32_t i = ei[e], j = ej[e];
+    int64_t sb = nrp[i], se = nrp[i + 1], bb = nrp[j], be = nrp[j + 1];
+    if (se - sb > be - bb) {
+        int64_t t0 = sb, t1 = se;
+        sb = bb; se = be; bb = t0; be = t1;
+    }
+    uint32_t c = 0;
+    for (int64_t base = sb; base < se; base += WAVE) {
+        int64_t s = base + lane;
+        int t = -1;
+        if (s < se) {
+            int32_t x = ncol[s];
+            int64_t q = lower_bound(ncol, bb, be, x);
+            if (q < be && ncol[q] == x) t = ntype[x];
+        }
+        uint64_t any = __ballot(t >= 0);
+        if (!any) continue;
+        for (int tt = 0; tt < L; ++tt) {
+            uint64_t bal = __ballot(t == tt);
+            if (lane == tt) c += (uint32_t)__popcll(bal);
+        }
+    }
+    if (lane < L) tri[e * L + lane] = c;
+}
+
+// ------------------------------------------------------ node aggregates
+
+// One wave per internal node u; LDS holds A_u and D_u (L x L uint64 each).
+__global__ void k_node_aggr(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
+                            const uint8_t *__restrict__ ntype, const uint32_t *__restrict__ neid,
+                            const uint32_t *__restrict__ tri, const uint32_t *__restrict__ tdeg,
+                            int64_t n, int L, uint64_t *__restrict__ A, uint64_t *__restrict__ D) {
+    extern __shared__ uint64_t sm_aggr[];
+    int w = threadIdx.x / WAVE;
+    int lane = lane_id();
+    int LL = L * L;
+    uint64_t *sA = sm_aggr + (size_t)w * 2 * LL;
+    uint64_t *sD = sA + LL;
+    int64_t u = (int64_t)blockIdx.x * (blockDim.x / WAVE) + w;
+    if (u >= n) return;
+    for (int q = lane; q < LL; q += WAVE) { sA[q] = 0; sD[q] = 0; }
+    wave_sync();
+    for (int64_t s = nrp[u] + lane; s < nrp[u + 1]; s += WAVE) {
+        int32_t k = ncol[s];
+        int t = ntype[k];
+        uint32_t e = neid[s];
+        for (int t2 = 0; t2 < L; ++t2) {
+            uint32_t a = tri[(size_t)e * L + t2];
+            uint32_t d = tdeg[(size_t)k * L + t2];
+            if (a) atomicAdd((unsigned long long *)&sA[t * L + t2], (unsigned long long)a);
+            if (d) atomicAdd((unsigned long long *)&sD[t * L + t2], (unsigned long long)d);
+        }
+    }
+    wave_sync();
+    for (int q = lane; q < LL; q += WAVE) {
+        A[(size_t)u * LL + q] = sA[q];
+        D[(size_t)u * LL + q] = sD[q];
+    }
+}
+
+// ------------------------------------------------------------ 4-cycles
+//
+// A wedge is a path x - g - ... seen from a "group" vertex.  Pass A groups by
+// the cycle's top vertex v (largest internal id): items are v's lower
+// neighbours u, targets are u's neighbours w < v, the map counts, per w, the
+// centres u by type.  Every pair of centres sharing (v, w) closes the 4-cycle
+// v-u1-w-u2; its two edges at v, oriented (v, u), get +1 at (type u2, type w).
+// Pass B groups by the vertex a opposite the top: items are all neighbours c
+// of a, targets are c's neighbours v above both a and c, the map counts, per
+// v, the centres c by type; the far edge oriented (c, a) gets +1 at
+// (type v, type of the other centre).  NC is kept in canonical orientation.
+
+
+
+template <int PASS>
+__device__ __forceinline__ void item_range(const CycleArgs &a, int32_t g, int64_t &ib, int64_t &ie) {
+    ib = a.nrp[g];
+    if (PASS == 0) ie = lower_bound(a.ncol, a.nrp[g], a.nrp[g + 1], g);
+    else ie = a.nrp[g + 1];
+}
+
+template <int PASS>
+__device__ __forceinline__ void target_range(const CycleArgs &a, int32_t g, int32_t x, int64_t &tb,
+                                             int64_t &te) {
+    if (PASS == 0) {
+        tb = a.nrp[x];
+        te = lower_bound(a.ncol, a.nrp[x], a.nrp[x + 1], g);
+    } else {
+        int32_t lim = g > x ? g : x;
+        tb = upper_bound(a.ncol, a.nrp[x], a.nrp[x + 1], lim);
+        te = a.nrp[x + 1];
+    }
+}
+
+// flip = 1 when the pass orientation is the reverse of the canonical one.
+template <int PASS>
+__device__ __forceinline__ int orient_flip(const CycleArgs &a, int32_t g, int32_t x, uint32_t e) {
+    int32_t ci = a.ei[e];
+    return PASS == 0 ? (ci != g) : (ci != x);
+}
+
+// Matrix index (pass orientation) of the count for centre type t, target type ty.
+template <int PASS>
+__device__ __forceinline__ int pass_entry(int t, int ty, int L) {
+    return PASS == 0 ? t * L + ty : ty * L + t;
+}
+
+constexpr uint32_t EMPTY_KEY = 0xffffffffu;
+
+__device__ __forceinline__ int hash_slot(uint32_t y) {
+    return (int)((y * 0x9E3779B1u) >> (32 - 10));  // LIGHT_HCAP = 1024
+}
+
+// Light groups: one 64-thread workgroup per group, LDS open-addressing map
+// keyed by target with 16-bit counters per type (group wedges <= LIGHT_MAXW).
+template <int PASS>
+__global__ void __launch_bounds__(64) k_cyc_light(CycleArgs a) {
+    extern __shared__ uint32_t sm_light[];
+    const int L = a.L;
+    const int LW = (L + 1) / 2;
+    uint32_t *keys = sm_light;
+    uint32_t *cnt = keys + LIGHT_HCAP;
+    __shared__ int32_t it_x[WAVE];
+    __shared__ int64_t it_tb[WAVE];
+    __shared__ uint32_t it_scan[WAVE];
+    __shared__ uint32_t it_eid[WAVE];
+    __shared__ int it_flip[WAVE];
+    int lane = threadIdx.x;
+    uint64_t count = a.counters[a.count_idx];
+    for (int q = lane; q < LIGHT_HCAP; q += WAVE) keys[q] = EMPTY_KEY;
+    for (int q = lane; q < LIGHT_HCAP * LW; q += WAVE) cnt[q] = 0;
+    __syncthreads();
+    for (uint64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+        int32_t g = (int32_t)a.list[idx];
+        int64_t ib, ie;
+        item_range<PASS>(a, g, ib, ie);
+        for (int phase = 0; phase < 2; ++phase) {
+            for (int64_t cb = ib; cb < ie; cb += WAVE) {
+                int64_t s = cb + lane;
+                uint32_t len = 0;
+                if (s < ie) {
+                    int32_t x = a.ncol[s];
+                    int64_t tb, te;
+                    target_range<PASS>(a, g, x, tb, te);
+                    len = (uint32_t)(te - tb);
+                    it_x[lane] = x;
+                    it_tb[lane] = tb;
+                    uint32_t e = a.neid[s];
+                    it_eid[lane] = e;
+                    it_flip[lane] = phase ? orient_flip<PASS>(a, g, x, e) : 0;
+                }
+                uint32_t incl = wave_incl_scan(len);
+                it_scan[lane] = incl;
+                uint32_t total = __shfl(incl, WAVE - 1, WAVE);
+                int nitems = (int)((ie - cb) < WAVE ? (ie - cb) : WAVE);
+                __syncthreads();
+                for (uint32_t f = lane; f < total; f += WAVE) {
+                    int o = owner_of(it_scan, nitems, f);
+                    uint32_t excl = o ? it_scan[o - 1] : 0;
+                    int32_t x = it_x[o];
+                    uint32_t y = (uint32_t)a.ncol[it_tb[o] + (f - excl)];
+                    int tx = a.ntype[x];
+                    int h = hash_slot(y);
+                    if (phase == 0) {
+                        // the group has at most LIGHT_MAXW < LIGHT_HCAP distinct keys,
+                        // so the probe ends; the bound only guards corrupted input
+                        bool ok = false;
+                        for (int probe = 0; probe < LIGHT_HCAP; ++probe) {
+                            uint32_t old = atomicCAS(&keys[h], EMPTY_KEY, y);
+                            if (old == EMPTY_KEY || old == y) { ok = true; break; }
+                            h = (h + 1) & (LIGHT_HCAP - 1);
+                        }
+                        if (ok) atomicAdd(&cnt[h * LW + (tx >> 1)], 1u << ((tx & 1) * 16));
+                        else atomicOr(a.status, ST_INTERNAL);
+                    } else {
+                        int probe = 0;
+                        while (keys[h] != y && probe < LIGHT_HCAP) {
+                            h = (h + 1) & (LIGHT_HCAP - 1);
+                            ++probe;
+                        }
+                        if (probe == LIGHT_HCAP) {
+                            atomicOr(a.status, ST_INTERNAL);
+                            continue;
+                        }
+                        int ty = a.ntype[y];
+                        uint32_t e = it_eid[o];
+                        int flip = it_flip[o];
+                        uint64_t *nc = a.NC + (size_t)e * L * L;
+                        for (int t = 0; t < L; ++t) {
+                            uint32_t c = (cnt[h * LW + (t >> 1)] >> ((t & 1) * 16)) & 0xffffu;
+                            uint32_t val = c - (t == tx ? 1u : 0u);
+                            if (val) {
+                                int pq = pass_entry<PASS>(t, ty, L);
+                                int p = pq / L, q = pq - p * L;
+                                int canon = flip ? q * L + p : pq;
+                                atomicAdd((unsigned long long *)&nc[canon], (unsigned long long)val);
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int q = lane; q < LIGHT_HCAP; q += WAVE) keys[q] = EMPTY_KEY;
+        for (int q = lane; q < LIGHT_HCAP * LW; q += WAVE) cnt[q] = 0;
+        __syncthreads();
+    }
+}
+
+// Block-wide inclusive scan of up to HEAVY_CHUNK values held by threads
+// [0, HEAVY_CHUNK); result in s[0..HEAVY_CHUNK).
+__device__ __forceinline__ void block_scan_chunk(uint32_t v, uint32_t *s, uint32_t *wave_tot) {
+    int tid = threadIdx.x;
+    int w = tid / WAVE;
+    uint32_t incl = wave_incl_scan(v);
+    if ((tid & (WAVE - 1)) == WAVE - 1) wave_tot[w] = incl;
+    __syncthreads();
+    uint32_t add = 0;
+    for (int q = 0; q < w; ++q) add += wave_tot[q];
+    if (tid < HEAVY_CHUNK) s[tid] = incl + add;
+    __syncthreads();
+}
+
+// Heavy groups: one 256-thread workgroup per group, pulled from a queue; the
+// map is a dense n x L uint32 array private to the workgroup.  Three walks
+// over the group's wedges: clear the entries the group touches, count,
+// emit.  Entries no wedge touches are never read, so the map needs no
+// initialisation.
+template <int PASS>
+__global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
+    extern __shared__ uint64_t sm_heavy[];
+    const int L = a.L;
+    const int LL = L * L;
+    const int CH = a.chunk;
+    uint64_t *acc = sm_heavy;  // CH * L * L
+    __shared__ int32_t it_x[HEAVY_CHUNK];
+    __shared__ int64_t it_tb[HEAVY_CHUNK];
+    __shared__ uint32_t it_scan[HEAVY_CHUNK];
+    __shared__ uint32_t it_eid[HEAVY_CHUNK];
+    __shared__ int it_flip[HEAVY_CHUNK];
+    __shared__ uint32_t wave_tot[HEAVY_THREADS / WAVE];
+    __shared__ uint64_t s_idx;
+    int tid = threadIdx.x;
+    uint32_t *map = a.maps + (size_t)blockIdx.x * (size_t)a.n * L;
+    uint64_t count = a.counters[a.count_idx];
+    while (true) {
+        if (tid == 0) s_idx = atomicAdd((unsigned long long *)&a.counters[a.next_idx], 1ull);
+        __syncthreads();
+        uint64_t idx = s_idx;
+        __syncthreads();
+        if (idx >= count) break;
+        int32_t g = (int32_t)a.list[idx];
+        int64_t ib, ie;
+        item_range<PASS>(a, g, ib, ie);
+        for (int phase = 0; phase < 3; ++phase) {
+            for (int64_t cb = ib; cb < ie; cb += CH) {
+                int nitems = (int)((ie - cb) < CH ? (ie - cb) : CH);
+                uint32_t len = 0;
+                if (tid < nitems) {
+                    int64_t s = cb + tid;
+                    int32_t x = a.ncol[s];
+                    int64_t tb, te;
+                    target_range<PASS>(a, g, x, tb, te);
+                    len = (uint32_t)(te - tb);
+                    it_x[tid] = x;
+                    it_tb[tid] = tb;
+                    uint32_t e = a.neid[s];
+                    it_eid[tid] = e;
+                    it_flip[tid] = orient_flip<PASS>(a, g, x, e);
+                }
+                block_scan_chunk(len, it_scan, wave_tot);
+                uint32_t total = it_scan[nitems - 1];
+                if (phase == 2) {
+                    for (int q = tid; q < nitems * LL; q += HEAVY_THREADS) acc[q] = 0;
+                    __syncthreads();
+                }
+                for (uint32_t f = tid; f < total; f += HEAVY_THREADS) {
+                    int o = owner_of(it_scan, nitems, f);
+                    uint32_t excl = o ? it_scan[o - 1] : 0;
+                    int32_t x = it_x[o];
+                    uint32_t y = (uint32_t)a.ncol[it_tb[o] + (f - excl)];
+                    uint32_t *my = map + (size_t)y * L;
+                    if (phase == 0) {
+                        for (int t = 0; t < L; ++t) my[t] = 0u;
+                    } else if (phase == 1) {
+                        atomicAdd(&my[a.ntype[x]], 1u);
+                    } else {
+                        int tx = a.ntype[x];
+                        int ty = a.ntype[y];
+                        uint64_t *ac = acc + (size_t)o * LL;
+                        for (int t = 0; t < L; ++t) {
+                            uint32_t c = load_agent(&my[t]);
+                            uint32_t val = c - (t == tx ? 1u : 0u);
+                            if (val)
+                                atomicAdd((unsigned long long *)&ac[pass_entry<PASS>(t, ty, L)],
+                                          (unsigned long long)val);
+                        }
+                    }
+                }
+                __syncthreads();
+                if (phase == 2) {
+                    for (int q = tid; q < nitems * LL; q += HEAVY_THREADS) {
+                        uint64_t v = acc[q];
+                        if (!v) continue;
+                        int o = q / LL;
+                        int pq = q - o * LL;
+                        int p = pq / L, r = pq - p * L;
+                        int canon = it_flip[o] ? r * L + p : pq;
+                        atomicAdd((unsigned long long *)&a.NC[(size_t)it_eid[o] * LL + canon],
+                                  (unsigned long long)v);
+                    }
+                    __syncthreads();
+                }
+            }
+            __threadfence();
+            __syncthreads();
+        }
+    }
+}
+
+// One wave per internal node: wedge counts of both passes, bucketed into
+// light and heavy lists.
+__global__ void k_cyc_work(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
+                           int64_t n, uint32_t *__restrict__ listA_light,
+                           uint32_t *__restrict__ listA_heavy, uint32_t *__restrict__ listB_light,
+                           uint32_t *__restrict__ listB_heavy, uint64_t *__restrict__ counters) {
+    int64_t v = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
+    int lane = lane_id();
+    if (v >= n) return;
+    int32_t vv = (int32_t)v;
+    int64_t b = nrp[v], e = nrp[v + 1];
+    uint64_t wa = 0, wb = 0;
+    for (int64_t s = b + lane; s < e; s += WAVE) {
+        int32_t x = ncol[s];
+        int64_t xb = nrp[x], xe = nrp[x + 1];
+        if (x < vv) wa += (uint64_t)(lower_bound(ncol, xb, xe, vv) - xb);
+        int32_t lim = vv > x ? vv : x;
+        wb += (uint64_t)(xe - upper_bound(ncol, xb, xe, lim));
+    }
+    wa = wave_sum_u64(wa);
+    wb = wave_sum_u64(wb);
+    if (lane == 0) {
+        if (wa) {
+            if (wa <= (uint64_t)LIGHT_MAXW)
+                listA_light[atomicAdd((unsigned long long *)&counters[C_A_LIGHT], 1ull)] = vv;
+            else
+                listA_heavy[atomicAdd((unsigned long long *)&counters[C_A_HEAVY], 1ull)] = vv;
+            atomicAdd((unsigned long long *)&counters[C_WEDGES_A], (unsigned long long)wa);
+        }
+        if (wb) {
+            if (wb <= (uint64_t)LIGHT_MAXW)
+                listB_light[atomicAdd((unsigned long long *)&counters[C_B_LIGHT], 1ull)] = vv;
+            else
+                listB_heavy[atomicAdd((unsigned long long *)&counters[C_B_HEAVY], 1ull)] = vv;
+            atomicAdd((unsigned long long *)&counters[C_WEDGES_B], (unsigned long long)wb);
+        }
+    }
+}
+
+// ----------------------------------------------- per-edge derive + write
+
+
+
+__device__ __forceinline__ void hist_add(const EdgeArgs &a, uint64_t *hist, int idx, uint64_t v) {
+    if (!v) return;
+    if (a.hist_in_lds) atomicAdd((unsigned long long *)&hist[idx], (unsigned long long)v);
+    else atomicAdd((unsigned long long *)&a.gacc[idx], (unsigned long long)v);
+}
+
+// Edge (canonical i, j) with its triangle set already in T[0..nT) and the
+// LDS matrices Xi, Xj, Y (filled), K (zeroed): counts cliques, derives all
+// orbits and writes the row.  NT threads cooperate.
+template <int NT>
+__device__ void edge_finish(const EdgeArgs &a, int64_t e, int32_t i, int32_t j, const uint32_t *T,
+                            int nT, uint64_t *Xi, uint64_t *Xj, uint64_t *Y, uint64_t *K,
+                            uint64_t *hist, int tid, uint32_t &bad) {
+    const int L = a.L;
+    // ordered typed clique pairs: k, r in T adjacent (Alg. 3, 4-clique test)
+    for (int kk = 0; kk < nT; ++kk) {
+        int32_t k = (int32_t)T[kk];
+        int64_t kb = a.nrp[k], ke = a.nrp[k + 1];
+        int tk = a.ntype[k];
+        for (int rr = kk + 1 + tid; rr < nT; rr += NT) {
+            int32_t r = (int32_t)T[rr];
+            int64_t rb = a.nrp[r], re = a.nrp[r + 1];
+            bool adj;
+            if (ke - kb <= re - rb) {
+                int64_t p = lower_bound(a.ncol, kb, ke, r);
+                adj = p < ke && a.ncol[p] == r;
+            } else {
+                int64_t p = lower_bound(a.ncol, rb, re, k);
+                adj = p < re && a.ncol[p] == k;
+            }
+            if (adj) {
+                int tr = a.ntype[r];
+                atomicAdd((unsigned long long *)&K[tk * L + tr], 1ull);
+                atomicAdd((unsigned long long *)&K[tr * L + tk], 1ull);
+            }
+        }
+    }
+    if (NT == WAVE) wave_sync(); else __syncthreads();
+
+    const int ta = a.ntype[i], tb = a.ntype[j];
+    const int LL = L * L;
+    const int P = L * (L + 1) / 2;
+    const int W = 2 * L + 10 * P;
+    const uint32_t *tri_e = a.tri + (size_t)e * L;
+    const uint32_t *di = a.tdeg + (size_t)i * L;
+    const uint32_t *dj = a.tdeg + (size_t)j * L;
+    const uint64_t *Ai = a.A + (size_t)i * LL, *Aj = a.A + (size_t)j * LL;
+    const uint64_t *Di = a.D + (size_t)i * LL, *Dj = a.D + (size_t)j * LL;
+    const uint64_t *NC = a.NC + (size_t)e * LL;
+    uint64_t *row = a.rows ? a.rows + (size_t)e * W : nullptr;
+    const int n2 = (int)binom_small(L + 1, 2);
+    const int n3 = (int)binom_small(L + 2, 3);
+    const int n4 = (int)binom_small(L + 3, 4);
+
+    if (tid == 0) hist_add(a, hist, rank2(ta, tb), 1);
+    for (int t = tid; t < L; t += NT) {
+        int64_t nTt = tri_e[t];
+        int64_t si = (int64_t)di[t] - nTt - (tb == t);
+        int64_t sj = (int64_t)dj[t] - nTt - (ta == t);
+        if (si < 0 || sj < 0) bad |= ST_INTERNAL;
+        if (row) {
+            row[t] = (uint64_t)nTt;
+            row[L + t] = (uint64_t)(si + sj);
+        }
+        int r3 = rank3(ta, tb, t);
+        hist_add(a, hist, n2 + r3, (uint64_t)(si + sj));
+        hist_add(a, hist, n2 + n3 + r3, (uint64_t)nTt);
+    }
+    for (int p = tid; p < P; p += NT) {
+        // pair (t, u), t <= u, from its lexicographic index
+        int t = 0, rem = p;
+        while (rem >= L - t) { rem -= L - t; ++t; }
+        int u = t + rem;
+        int64_t nT_[2] = {(int64_t)tri_e[t], (int64_t)tri_e[u]};
+        int64_t Si[2], Sj[2];
+        int xs[2] = {t, u};
+        for (int z = 0; z < 2; ++z) {
+            int x = xs[z];
+            Si[z] = (int64_t)di[x] - nT_[z] - (tb == x);
+            Sj[z] = (int64_t)dj[x] - nT_[z] - (ta == x);
+        }
+        // ordered quantities for (x, y) = (t, u) [z=0] and (u, t) [z=1]
+        int64_t Ci[2], Cj[2], sgi[2], sgj[2], dli[2], dlj[2], Kx[2], Yx[2], Xix[2], NCx[2];
+        for (int z = 0; z < 2; ++z) {
+            int x = z ? u : t, y = z ? t : u;
+            int zx = z, zy = 1 - z;  // index of x / y inside nT_, Si, Sj
+            int q = x * L + y;
+            int64_t xi = (int64_t)Xi[q], xj = (int64_t)Xj[q], kk = (int64_t)K[q], yy = (int64_t)Y[q];
+            Ci[z] = xi - nT_[zx] * (tb == y) - kk;
+            Cj[z] = xj - nT_[zx] * (ta == y) - kk;
+            sgi[z] = (int64_t)Ai[q] - xi - (tb == x) * nT_[zy];
+            sgj[z] = (int64_t)Aj[q] - xj - (ta == x) * nT_[zy];
+            dli[z] = (int64_t)Di[q] - yy - (tb == x) * (int64_t)dj[y];
+            dlj[z] = (int64_t)Dj[q] - yy - (ta == x) * (int64_t)di[y];
+            Kx[z] = kk;
+            Yx[z] = yy;
+            Xix[z] = xi;
+            NCx[z] = (int64_t)NC[q];
+        }
+        int64_t Cyc[2], Ei[2], Ej[2], Pi[2], Pj[2], Q[2];
+        for (int z = 0; z < 2; ++z) Cyc[z] = NCx[z] - Ci[1 - z] - Cj[z] - Kx[z];
+        for (int z = 0; z < 2; ++z) {
+            int zb = 1 - z;
+            int y = z ? t : u;
+            int zx = z;
+            Ei[z] = sgi[z] - Ci[zb];
+            Ej[z] = sgj[z] - Cj[zb];
+            Pi[z] = dli[z] - Si[zx] * (ta == y) - sgi[z] - Cyc[z];
+            Pj[z] = dlj[z] - Sj[zx] * (tb == y) - sgj[z] - Cyc[zb];
+            Q[z] = Yx[z] - Xix[z] - Cj[z] - nT_[zx] * (ta == y);
+        }
+        int64_t g[13];
+        if (t == u) {
+            if (Kx[0] & 1) bad |= ST_INTERNAL;
+            if ((Ei[0] + Ej[0]) & 1) bad |= ST_INTERNAL;
+            g[12] = Kx[0] / 2;
+            g[6] = Cyc[0];
+            g[10] = Ci[0] + Cj[0];
+            g[7] = (Ei[0] + Ej[0]) / 2;
+            g[3] = Pi[0] + Pj[0];
+            g[8] = Q[0];
+            g[4] = Si[0] * Sj[0] - g[6];
+            g[5] = Si[0] * (Si[0] - 1) / 2 + Sj[0] * (Sj[0] - 1) / 2 - g[7];
+            g[9] = nT_[0] * (Si[0] + Sj[0]) - g[10];
+            g[11] = nT_[0] * (nT_[0] - 1) / 2 - g[12];
+        } else {
+            if (Ei[0] != Ei[1] || Ej[0] != Ej[1] || Kx[0] != Kx[1]) bad |= ST_INTERNAL;
+            g[12] = Kx[0];
+            g[6] = Cyc[0] + Cyc[1];
+            g[10] = Ci[0] + Cj[0] + Ci[1] + Cj[1];
+            g[7] = Ei[0] + Ej[0];
+            g[3] = Pi[0] + Pi[1] + Pj[0] + Pj[1];
+            g[8] = Q[0] + Q[1];
+            g[4] = Si[0] * Sj[1] + Si[1] * Sj[0] - g[6];
+            g[5] = Si[0] * Si[1] + Sj[0] * Sj[1] - g[7];
+            g[9] = nT_[0] * (Si[1] + Sj[1]) + nT_[1] * (Si[0] + Sj[0]) - g[10];
+            g[11] = nT_[0] * nT_[1] - g[12];
+        }
+        int r4 = rank4(ta, tb, t, u);
+        // graphlet of each orbit (Sec. 4.4): h3 = g3+g4, h4 = g5, h5 = g6,
+        // h6 = g7+g8+g9, h7 = g10+g11, h8 = g12
+        const int hof[13] = {0, 0, 0, 3, 3, 4, 5, 6, 6, 6, 7, 7, 8};
+        for (int o = 3; o <= 12; ++o) {
+            if (g[o] < 0) bad |= ST_INTERNAL;
+            uint64_t v = (uint64_t)g[o];
+            if (row) row[2 * L + (o - 3) * P + p] = v;
+            hist_add(a, hist, n2 + 2 * n3 + (hof[o] - 3) * n4 + r4, v);
+        }
+    }
+}
+
+// Light edges: one wave per edge with the triangle set in LDS (|T| <= TCAP);
+// edges with both degrees above TCAP go to the heavy list.
+__global__ void __launch_bounds__(64) k_edges_light(EdgeArgs a) {
+    extern __shared__ uint64_t sm_edge[];
+    const int L = a.L;
+    const int LL = L * L;
+    uint64_t *Xi = sm_edge, *Xj = Xi + LL, *Y = Xj + LL, *K = Y + LL;
+    uint64_t *hist = K + LL;
+    uint32_t *T = (uint32_t *)(hist + (a.hist_in_lds ? a.gw : 0));
+    int lane = threadIdx.x;
+    uint32_t bad = 0;
+    if (a.hist_in_lds)
+        for (int q = lane; q < a.gw; q += WAVE) hist[q] = 0;
+    __syncthreads();
+    for (int64_t e = blockIdx.x; e < a.m; e += gridDim.x) {
+        int32_t i = a.ei[e], j = a.ej[e];
+        int64_t ib = a.nrp[i], ie = a.nrp[i + 1], jb = a.nrp[j], je = a.nrp[j + 1];
+        int64_t dmin = (ie - ib) < (je - jb) ? (ie - ib) : (je - jb);
+        if (dmin > TCAP) {
+            if (lane == 0)
+                a.heavy_list[atomicAdd((unsigned long long *)&a.counters[C_EDGE_HEAVY], 1ull)] =
+                    (uint32_t)e;
+            continue;
+        }
+        for (int q = lane; q < 4 * LL; q += WAVE) Xi[q] = 0;
+        __syncthreads();
+        bool i_small = (ie - ib) <= (je - jb);
+        int64_t sb = i_small ? ib : jb, se = i_small ? ie : je;
+        int64_t bb = i_small ? jb : ib, be = i_small ? je : ie;
+        uint32_t nT = 0;
+        for (int64_t base = sb; base < se; base += WAVE) {
+            int64_t s = base + lane;
+            bool found = false;
+            int64_t q = 0;
+            int32_t x = 0;
+            if (s < se) {
+                x = a.ncol[s];
+                q = lower_bound(a.ncol, bb, be, x);
+                found = q < be && a.ncol[q] == x;
+            }
+            uint64_t bal = __ballot(found);
+            if (found) {
+                uint32_t pos = nT + (uint32_t)__popcll(bal & ((1ull << lane) - 1));
+                T[pos] = (uint32_t)x;
+                int64_t s_i = i_small ? s : q, s_j = i_small ? q : s;
+                uint32_t eik = a.neid[s_i], ejk = a.neid[s_j];
+                int t = a.ntype[x];
+                for (int t2 = 0; t2 < L; ++t2) {
+                    uint32_t vi = a.tri[(size_t)eik * L + t2];
+                    uint32_t vj = a.tri[(size_t)ejk * L + t2];
+                    uint32_t vy = a.tdeg[(size_t)x * L + t2];
+                    if (vi) atomicAdd((unsigned long long *)&Xi[t * L + t2], (unsigned long long)vi);
+                    if (vj) atomicAdd((unsigned long long *)&Xj[t * L + t2], (unsigned long long)vj);
+                    if (vy) atomicAdd((unsigned long long *)&Y[t * L + t2], (unsigned long long)vy);
+                }
+            }
+            nT += (uint32_t)__popcll(bal);
+        }
+        __syncthreads();
+        edge_finish<WAVE>(a, e, i, j, T, (int)nT, Xi, Xj, Y, K, hist, lane, bad);
+        __syncthreads();
+    }
+    if (a.hist_in_lds)
+        for (int q = lane; q < a.gw; q += WAVE)
+            if (hist[q]) atomicAdd((unsigned long long *)&a.gacc[q], (unsigned long long)hist[q]);
+    bad = wave_or(bad);
+    if (lane == 0 && bad) atomicOr(a.status, bad);
+}
+
+// Heavy edges: one 256-thread workgroup per edge, triangle set in a global
+// buffer private to the workgroup.
+__global__ void __launch_bounds__(EDGE_THREADS_HEAVY) k_edges_heavy(EdgeArgs a) {
+    extern __shared__ uint64_t sm_edgeh[];
+    const int L = a.L;
+    const int LL = L * L;
+    const int NT = EDGE_THREADS_HEAVY;
+    uint64_t *Xi = sm_edgeh, *Xj = Xi + LL, *Y = Xj + LL, *K = Y + LL;
+    uint64_t *hist = K + LL;
+    __shared__ uint32_t s_nT;
+    __shared__ uint64_t s_idx;
+    uint32_t *T = a.tbuf + (size_t)blockIdx.x * (size_t)a.n;
+    int tid = threadIdx.x;
+    uint32_t bad = 0;
+    if (a.hist_in_lds)
+        for (int q = tid; q < a.gw; q += NT) hist[q] = 0;
+    uint64_t count = a.counters[C_EDGE_HEAVY];
+    __syncthreads();
+    while (true) {
+        if (tid == 0) s_idx = atomicAdd((unsigned long long *)&a.counters[C_EDGE_NEXT], 1ull);
+        __syncthreads();
+        uint64_t idx = s_idx;
+        __syncthreads();
+        if (idx >= count) break;
+        int64_t e = a.heavy_list[idx];
+        int32_t i = a.ei[e], j = a.ej[e];
+        int64_t ib = a.nrp[i], ie = a.nrp[i + 1], jb = a.nrp[j], je = a.nrp[j + 1];
+        for (int q = tid; q < 4 * LL; q += NT) Xi[q] = 0;
+        if (tid == 0) s_nT = 0;
+        __syncthreads();
+        bool i_small = (ie - ib) <= (je - jb);
+        int64_t sb = i_small ? ib : jb, se = i_small ? ie : je;
+        int64_t bb = i_small ? jb : ib, be = i_small ? je : ie;
+        for (int64_t base = sb; base < se; base += NT) {
+            int64_t s = base + tid;
+            if (s < se) {
+                int32_t x = a.ncol[s];
+                int64_t q = lower_bound(a.ncol, bb, be, x);
+                if (q < be && a.ncol[q] == x) {
+                    uint32_t pos = atomicAdd(&s_nT, 1u);
+                    T[pos] = (uint32_t)x;
+                    int64_t s_i = i_small ? s : q, s_j = i_small ? q : s;
+                    uint32_t eik = a.neid[s_i], ejk = a.neid[s_j];
+                    int t = a.ntype[x];
+                    for (int t2 = 0; t2 < L; ++t2) {
+                        uint32_t vi = a.tri[(size_t)eik * L + t2];
+                        uint32_t vj = a.tri[(size_t)ejk * L + t2];
+                        uint32_t vy = a.tdeg[(size_t)x * L + t2];
+                        if (vi) atomicAdd((unsigned long long *)&Xi[t * L + t2], (unsigned long long)vi);
+                        if (vj) atomicAdd((unsigned long long *)&Xj[t * L + t2], (unsigned long long)vj);
+                        if (vy) atomicAdd((unsigned long long *)&Y[t * L + t2], (unsigned long long)vy);
+                    }
+                }
+            }
+        }
+        __threadfence_block();
+        __syncthreads();
+        int nT = (int)s_nT;
+        edge_finish<NT>(a, e, i, j, T, nT, Xi, Xj, Y, K, hist, tid, bad);
+        __threadfence_block();
+        __syncthreads();
+    }
+    if (a.hist_in_lds)
+        for (int q = tid; q < a.gw; q += NT)
+            if (hist[q]) atomicAdd((unsigned long long *)&a.gacc[q], (unsigned long long)hist[q]);
+    if (bad) atomicOr(a.status, bad);
+}
+
+// Global counts: divide each graphlet block by its edge count.
+__global__ void k_global_finalize(const uint64_t *__restrict__ gacc, int L,
+                                  uint64_t *__restrict__ out, uint32_t *__restrict__ status) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    int n2 = (int)binom_small(L + 1, 2), n3 = (int)binom_small(L + 2, 3),
+        n4 = (int)binom_small(L + 3, 4);
+    int gw = n2 + 2 * n3 + 6 * n4;
+    if (q >= gw) return;
+    int h;
+    if (q < n2) h = 0;
+    else if (q < n2 + n3) h = 1;
+    else if (q < n2 + 2 * n3) h = 2;
+    else h = 3 + (q - n2 - 2 * n3) / n4;
+    const uint64_t E[9] = {1, 2, 3, 3, 3, 4, 4, 5, 6};
+    uint64_t v = gacc[q];
+    if (v % E[h]) atomicOr(status, ST_NOT_DIVISIBLE);
+    out[q] = v / E[h];
+}
+
+// ------------------------------------------------------ launch wrappers
+
+#define LAUNCH_CHECK() do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
+
+static inline unsigned blocks_for(int64_t items, int per_block) {
+    return (unsigned)((items + per_block - 1) / per_block);
+}
+
+hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    int64_t b = (count + 255) / 256;
+    if (b > 4096) b = 4096;
+    k_fill_u64<<<(unsigned)b, 256, 0, st>>>(p, v, count);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_check_rows(const int64_t *rp, const int32_t *col, const uint8_t *types, int64_t n,
+                             int64_t nnz, int L, uint32_t *deg, int64_t *ucount, uint32_t *status,
+                             hipStream_t st) {
+    k_check_rows<<<blocks_for(n + 1, 4), 256, 0, st>>>(rp, col, types, n, nnz, L, deg, ucount, status);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_node_keys(const uint32_t *deg, int64_t n, uint64_t *keys, hipStream_t st) {
+    k_node_keys<<<blocks_for(n, 256), 256, 0, st>>>(deg, n, keys);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_relabel(const uint64_t *sorted, const uint8_t *types, const uint32_t *deg, int64_t n,
+                          int32_t *order, int32_t *newid, uint8_t *ntype, int64_t *ndeg,
+                          hipStream_t st) {
+    k_relabel<<<blocks_for(n > 0 ? n : 1, 256), 256, 0, st>>>(sorted, types, deg, n, order, newid,
+                                                              ntype, ndeg);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_slot_keys(const int64_t *rp, const int32_t *col, const int64_t *ucount,
+                            const int64_t *eoff, const int32_t *newid, int64_t n, int bits,
+                            uint64_t *keys, uint32_t *vals, int32_t *ei, int32_t *ej,
+                            uint32_t *status, hipStream_t st) {
+    k_slot_keys<<<blocks_for(n, 4), 256, 0, st>>>(rp, col, ucount, eoff, newid, n, bits, keys, vals,
+                                                  ei, ej, status);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_finish_csr(const uint64_t *keys, const uint32_t *vals, int64_t nnz, int bits,
+                             int32_t *ncol, uint32_t *neid, hipStream_t st) {
+    if (nnz == 0) return hipSuccess;
+    k_finish_csr<<<blocks_for(nnz, 256), 256, 0, st>>>(keys, vals, nnz, bits, ncol, neid);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_tdeg(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype, int64_t n,
+                       int L, uint32_t *tdeg, hipStream_t st) {
+    k_tdeg<<<blocks_for(n, 4), 256, 0, st>>>(nrp, ncol, ntype, n, L, tdeg);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype,
+                      const int32_t *ei, const int32_t *ej, int64_t m, int L, uint32_t *tri,
+                      hipStream_t st) {
+    if (m == 0) return hipSuccess;
+    k_tri<<<blocks_for(m, 4), 256, 0, st>>>(nrp, ncol, ntype, ei, ej, m, L, tri);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype,
+                            const uint32_t *neid, const uint32_t *tri, const uint32_t *tdeg,
+                            int64_t n, int L, uint64_t *A, uint64_t *D, hipStream_t st) {
+    size_t sh = (size_t)4 * 2 * L * L * sizeof(uint64_t);
+    k_node_aggr<<<blocks_for(n, 4), 256, sh, st>>>(nrp, ncol, ntype, neid, tri, tdeg, n, L, A, D);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, int64_t n, uint32_t *la_l,
+                           uint32_t *la_h, uint32_t *lb_l, uint32_t *lb_h, uint64_t *counters,
+                           hipStream_t st) {
+    k_cyc_work<<<blocks_for(n, 4), 256, 0, st>>>(nrp, ncol, n, la_l, la_h, lb_l, lb_h, counters);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+int heavy_chunk_for(int L) {
+    int ch = 32768 / (L * L * 8);
+    if (ch > HEAVY_CHUNK) ch = HEAVY_CHUNK;
+    if (ch < 1) ch = 1;
+    return ch;
+}
+
+hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned grid, hipStream_t st) {
+    if (grid == 0) return hipSuccess;
+    if (!heavy) {
+        size_t sh = (size_t)LIGHT_HCAP * (1 + (args.L + 1) / 2) * sizeof(uint32_t);
+        if (pass == 0) k_cyc_light<0><<<grid, 64, sh, st>>>(args);
+        else k_cyc_light<1><<<grid, 64, sh, st>>>(args);
+    } else {
+        size_t sh = (size_t)args.chunk * args.L * args.L * sizeof(uint64_t);
+        if (pass == 0) k_cyc_heavy<0><<<grid, HEAVY_THREADS, sh, st>>>(args);
+        else k_cyc_heavy<1><<<grid, HEAVY_THREADS, sh, st>>>(args);
+    }
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_edges(bool heavy, const EdgeArgs &args, unsigned grid, hipStream_t st) {
+    if (grid == 0) return hipSuccess;
+    int LL = args.L * args.L;
+    size_t sh = (size_t)(4 * LL + (args.hist_in_lds ? args.gw : 0)) * sizeof(uint64_t);
+    if (!heavy) {
+        sh += (size_t)TCAP * sizeof(uint32_t);
+        k_edges_light<<<grid, 64, sh, st>>>(args);
+    } else {
+        k_edges_heavy<<<grid, EDGE_THREADS_HEAVY, sh, st>>>(args);
+    }
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_global_finalize(const uint64_t *gacc, int L, int gw, uint64_t *out, uint32_t *status,
+                                  hipStream_t st) {
+    k_global_finalize<<<blocks_for(gw, 256), 256, 0, st>>>(gacc, L, out, status);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+}  // namespace tg

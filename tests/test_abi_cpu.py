@@ -1,0 +1,77 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+the header declares, and its layout helpers agree with the documented
+layout (checked against the brute-force module's own enumeration)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import brute_force as BF
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tg.h")
+
+
+def _lib():
+    from paper_2010_14058_amd import _lib as L
+
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libtg.so not built")
+    return L
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(tg_[a-z_0-9]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_symbols_exported():
+    L = _lib()
+    lib = ctypes.CDLL(L.LIB_PATH)
+    names = header_functions()
+    assert len(names) >= 9
+    for name in names:
+        assert hasattr(lib, name), name
+    # the binding declares exactly the header's functions
+    assert sorted(L.SIGNATURES) == names
+
+
+def test_widths_and_workspace():
+    L = _lib()
+    for nt in range(1, 17):
+        assert L.row_width(nt) == 2 * nt + 10 * (nt * (nt + 1) // 2)
+        assert L.global_width(nt) == len(BF.multisets(nt, 2)) + 2 * len(BF.multisets(nt, 3)) + 6 * len(
+            BF.multisets(nt, 4))
+    assert L.row_width(0) == 0 and L.row_width(17) == 0
+    assert L.workspace_bytes(1000, 8000, 3) > 0
+    assert L.workspace_bytes(1000, 8001, 3) == 0      # odd nnz
+    assert L.workspace_bytes(10, 20, 0) == 0          # L out of range
+
+
+@pytest.mark.parametrize("nt", [1, 3, 5, 8])
+def test_key_describe(nt):
+    L = _lib()
+    idx = BF.column_index(nt)
+    for name, c in idx.items():
+        o, t, u = L.key_describe(nt, c)
+        if name.startswith("tri"):
+            assert (o, u) == (1, -1) and name == f"tri[{t}]"
+        elif name.startswith("path3"):
+            assert (o, u) == (2, -1) and name == f"path3[{t}]"
+        else:
+            assert name == f"g{o}[{t},{u}]"
+
+
+@pytest.mark.parametrize("nt", [1, 2, 4, 6])
+def test_global_key_describe(nt):
+    L = _lib()
+    q = 0
+    for h, k in [(0, 2), (1, 3), (2, 3)] + [(h, 4) for h in range(3, 9)]:
+        for ms in BF.multisets(nt, k):
+            assert L.global_key_describe(nt, q) == (h, ms)
+            q += 1
+    assert q == L.global_width(nt)
