@@ -18,12 +18,13 @@
  *   current HIP device.  The caller allocates and owns all of them; the
  *   library allocates no device memory and frees nothing.
  * Stream: every kernel runs on the given hipStream_t (passed as void*, NULL
- *   means the null stream).  A call returns after the counts are enqueued;
- *   validation results are read back once with a stream synchronisation,
- *   so the call blocks until the input checks (not the counting) finish.
+ *   means the null stream).  The call synchronises that stream twice during
+ *   the input checks and once at the end, to read back the device-side
+ *   consistency checks, so the counts are complete when it returns.
  * Errors: every call returns tg_status.  Input checks run before any output
- *   is written; on error the outputs are left untouched except where noted.
- *   Device faults reported by HIP map to TG_E_DEVICE.
+ *   is written; on an input error the outputs are left untouched.  Device
+ *   faults reported by HIP map to TG_E_DEVICE; a failed internal check
+ *   (TG_E_INTERNAL) leaves the outputs unspecified.
  * Determinism: all counts are exact unsigned 64-bit integers; identical
  *   inputs give identical outputs regardless of scheduling.
  *
@@ -102,8 +103,7 @@ size_t tg_workspace_bytes(int64_t n, int64_t nnz, int32_t L);
  *   global_counts         device uint64 [tg_global_width(L)], or NULL.
  *   workspace             device buffer of ws_bytes >= tg_workspace_bytes().
  *   stream                hipStream_t as void*.
- * Blocks until the input checks have run; the counting itself is enqueued
- * on the stream and complete once the stream is synchronised. */
+ * Returns when the counts are complete (see Stream above). */
 tg_status tg_count_typed_graphlets(const int64_t *row_ptr, const int32_t *col,
                                    const uint8_t *types, int64_t n, int64_t nnz, int32_t L,
                                    uint64_t *per_edge, uint64_t *global_counts,
@@ -128,10 +128,13 @@ tg_status tg_global_key_describe(int32_t L, int32_t idx, int32_t *graphlet,
 void tg_set_timing(int32_t enable);
 int32_t tg_phase_times(float *ms, const char **names, int32_t max_phases);
 
-/* Work statistics of the most recent call (for bandwidth accounting):
- * stats[0] = wedges of the 4-cycle passes (each pass), stats[1] = vertices
- * in the light cycle path, stats[2] = vertices in the heavy cycle path,
- * stats[3] = edges in the heavy clique path.  Synchronises the stream. */
+/* Work statistics of the most recent call on this host thread (for
+ * bandwidth accounting), up to max_stats of: [0] wedges of 4-cycle pass A,
+ * [1] groups on the light cycle path (both passes), [2] groups on the heavy
+ * cycle path, [3] edges on the heavy clique path, [4] wedges of pass B,
+ * [5] pass-A wedges in heavy groups, [6] pass-B wedges in heavy groups,
+ * [7] sum over edges of |T_ij| (three times the triangle count).
+ * Returns the number written. */
 int32_t tg_last_stats(int64_t *stats, int32_t max_stats);
 
 #ifdef __cplusplus

@@ -110,7 +110,8 @@ def last_stats() -> dict:
     st = (ctypes.c_int64 * 8)()
     load().tg_last_stats(st, 8)
     return {"wedges_pass_a": st[0], "light_groups": st[1], "heavy_groups": st[2],
-            "heavy_edges": st[3], "wedges_pass_b": st[4]}
+            "heavy_edges": st[3], "wedges_pass_b": st[4], "heavy_wedges_pass_a": st[5],
+            "heavy_wedges_pass_b": st[6], "triangle_slots": st[7]}
 
 
 def count_raw(row_ptr_ptr: int, col_ptr: int, types_ptr: int, n: int, nnz: int, L: int,

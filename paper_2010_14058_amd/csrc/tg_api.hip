@@ -250,7 +250,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     timing_mark("prep");
 
     // ---- typed triangles and node aggregates
-    HIPCHK(launch_tri(nrp, ncol, ntype, ei, ej, m, L, tri, st));
+    HIPCHK(launch_tri(nrp, ncol, ntype, ei, ej, m, L, tri, counters + C_TRI_SUM, st));
     timing_mark("tri");
     HIPCHK(launch_node_aggr(nrp, ncol, ntype, neid, tri, tdeg, n, L, A, D, st));
     timing_mark("aggr");
@@ -308,6 +308,9 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     g_timing.stats[2] = (int64_t)(cnt_host[C_A_HEAVY] + cnt_host[C_B_HEAVY]);
     g_timing.stats[3] = (int64_t)cnt_host[C_EDGE_HEAVY];
     g_timing.stats[4] = (int64_t)cnt_host[C_WEDGES_B];
+    g_timing.stats[5] = (int64_t)cnt_host[C_WEDGES_A_HEAVY];
+    g_timing.stats[6] = (int64_t)cnt_host[C_WEDGES_B_HEAVY];
+    g_timing.stats[7] = (int64_t)cnt_host[C_TRI_SUM];
     if (probe.status) return TG_E_INTERNAL;
     return TG_OK;
 }

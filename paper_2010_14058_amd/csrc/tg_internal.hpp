@@ -51,6 +51,7 @@ struct Layout {
 enum Counter {
     C_A_LIGHT = 0, C_A_HEAVY, C_B_LIGHT, C_B_HEAVY, C_EDGE_HEAVY,
     C_A_NEXT, C_B_NEXT, C_EDGE_NEXT, C_WEDGES_A, C_WEDGES_B,
+    C_WEDGES_A_HEAVY, C_WEDGES_B_HEAVY, C_TRI_SUM,
     C_NUM
 };
 
@@ -116,7 +117,7 @@ hipError_t launch_tdeg(const int64_t *nrp, const int32_t *ncol, const uint8_t *n
                        int L, uint32_t *tdeg, hipStream_t st);
 hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype,
                       const int32_t *ei, const int32_t *ej, int64_t m, int L, uint32_t *tri,
-                      hipStream_t st);
+                      uint64_t *tri_sum, hipStream_t st);
 hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype,
                             const uint32_t *neid, const uint32_t *tri, const uint32_t *tdeg,
                             int64_t n, int L, uint64_t *A, uint64_t *D, hipStream_t st);

@@ -259,7 +259,7 @@ __global__ void k_tdeg(const int64_t *__restrict__ nrp, const int32_t *__restric
 __global__ void k_tri(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
                       const uint8_t *__restrict__ ntype, const int32_t *__restrict__ ei,
                       const int32_t *__restrict__ ej, int64_t m, int L,
-                      uint32_t *__restrict__ tri) {
+                      uint32_t *__restrict__ tri, uint64_t *__restrict__ tri_sum) {
     int64_t e = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
     int lane = lane_id();
     if (e >= m) return;
@@ -286,6 +286,8 @@ __global__ void k_tri(const int64_t *__restrict__ nrp, const int32_t *__restrict
         }
     }
     if (lane < L) tri[e * L + lane] = c;
+    uint64_t tot = wave_sum_u64(lane < L ? (uint64_t)c : 0ull);
+    if (lane == 0 && tot) atomicAdd((unsigned long long *)tri_sum, (unsigned long long)tot);
 }
 
 // ------------------------------------------------------ node aggregates
@@ -606,17 +608,21 @@ __global__ void k_cyc_work(const int64_t *__restrict__ nrp, const int32_t *__res
     wb = wave_sum_u64(wb);
     if (lane == 0) {
         if (wa) {
-            if (wa <= (uint64_t)LIGHT_MAXW)
+            if (wa <= (uint64_t)LIGHT_MAXW) {
                 listA_light[atomicAdd((unsigned long long *)&counters[C_A_LIGHT], 1ull)] = vv;
-            else
+            } else {
                 listA_heavy[atomicAdd((unsigned long long *)&counters[C_A_HEAVY], 1ull)] = vv;
+                atomicAdd((unsigned long long *)&counters[C_WEDGES_A_HEAVY], (unsigned long long)wa);
+            }
             atomicAdd((unsigned long long *)&counters[C_WEDGES_A], (unsigned long long)wa);
         }
         if (wb) {
-            if (wb <= (uint64_t)LIGHT_MAXW)
+            if (wb <= (uint64_t)LIGHT_MAXW) {
                 listB_light[atomicAdd((unsigned long long *)&counters[C_B_LIGHT], 1ull)] = vv;
-            else
+            } else {
                 listB_heavy[atomicAdd((unsigned long long *)&counters[C_B_HEAVY], 1ull)] = vv;
+                atomicAdd((unsigned long long *)&counters[C_WEDGES_B_HEAVY], (unsigned long long)wb);
+            }
             atomicAdd((unsigned long long *)&counters[C_WEDGES_B], (unsigned long long)wb);
         }
     }
@@ -1000,9 +1006,9 @@ hipError_t launch_tdeg(const int64_t *nrp, const int32_t *ncol, const uint8_t *n
 
 hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype,
                       const int32_t *ei, const int32_t *ej, int64_t m, int L, uint32_t *tri,
-                      hipStream_t st) {
+                      uint64_t *tri_sum, hipStream_t st) {
     if (m == 0) return hipSuccess;
-    k_tri<<<blocks_for(m, 4), 256, 0, st>>>(nrp, ncol, ntype, ei, ej, m, L, tri);
+    k_tri<<<blocks_for(m, 4), 256, 0, st>>>(nrp, ncol, ntype, ei, ej, m, L, tri, tri_sum);
     LAUNCH_CHECK();
     return hipSuccess;
 }
