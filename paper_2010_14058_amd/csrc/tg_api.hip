@@ -117,6 +117,11 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay) {
     y.off_tbuf = take(per_t * (size_t)y.heavy_edge_slots);
     y.off_gacc = take(sizeof(uint64_t) * gw);
     y.off_sort_tmp = take(y.sort_tmp_bytes);
+    y.off_hstart = take(sizeof(int64_t) * (n + 1));
+    const size_t hw = HUB_MAX / 64;
+    y.off_HB = take(sizeof(uint64_t) * HUB_MAX * hw);
+    y.off_hpre = take(sizeof(uint32_t) * HUB_MAX * hw);
+    y.off_TM = take(sizeof(uint64_t) * TG_MAX_L * hw);
     y.total = off;
     return TG_OK;
 }
@@ -234,19 +239,32 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     // ---- relabel by (degree, id): rank order = internal id order
     HIPCHK(launch_node_keys(deg, n, key_a, st));
     HIPCHK(rocprim::radix_sort_keys(stmp, stmp_bytes, key_a, key_b, (size_t)n, 0, 64, st));
-    HIPCHK(launch_relabel(key_b, types, deg, n, order, newid, ntype, ndeg, st));
+    HIPCHK(launch_relabel(key_b, types, deg, n, order, newid, ntype, ndeg, counters + C_HUB_CAND,
+                          st));
     HIPCHK(rocprim::exclusive_scan(stmp, stmp_bytes, ndeg, nrp, int64_t(0), (size_t)(n + 1),
                                    rocprim::plus<int64_t>(), st));
     const int bits = bits_for(n);
     HIPCHK(launch_slot_keys(row_ptr, col, ucount, eoff, newid, n, bits, key_a, val_a, ei, ej, status,
                             st));
     HIPCHK(hipMemcpyAsync(&probe.status, status, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    uint64_t hub_cand = 0;
+    HIPCHK(hipMemcpyAsync(&hub_cand, counters + C_HUB_CAND, sizeof(uint64_t), hipMemcpyDeviceToHost,
+                          st));
     HIPCHK(hipStreamSynchronize(st));
     if (probe.status) return status_from_bits(probe.status);
+    // hub core: the highest-ranked nodes of degree >= HUB_DMIN, at most HUB_MAX
+    const int H = (int)(hub_cand < (uint64_t)HUB_MAX ? hub_cand : (uint64_t)HUB_MAX);
+    const int Hw = (H + 63) / 64;
+    const int32_t hub_base = (int32_t)(n - H);
     HIPCHK(rocprim::radix_sort_pairs(stmp, stmp_bytes, key_a, key_b, val_a, val_b, (size_t)nnz, 0,
                                      2 * bits, st));
     HIPCHK(launch_finish_csr(key_b, val_b, nnz, bits, ncol, neid, st));
-    HIPCHK(launch_tdeg(nrp, ncol, ntype, n, L, tdeg, st));
+    int64_t *hstart = at<int64_t>(ws, y.off_hstart);
+    uint64_t *HB = at<uint64_t>(ws, y.off_HB);
+    uint32_t *hpre = at<uint32_t>(ws, y.off_hpre);
+    uint64_t *TM = at<uint64_t>(ws, y.off_TM);
+    HIPCHK(launch_tdeg(nrp, ncol, ntype, n, L, hub_base, tdeg, hstart, st));
+    HIPCHK(launch_hub_build(nrp, ncol, hstart, ntype, n, H, Hw, L, HB, hpre, TM, st));
     timing_mark("prep");
 
     // ---- typed triangles and node aggregates
@@ -289,6 +307,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     ea.rows = per_edge; ea.gacc = gacc; ea.gw = gw;
     ea.hist_in_lds = (size_t)gw * sizeof(uint64_t) <= 32768 ? 1 : 0;
     ea.heavy_list = le; ea.counters = counters; ea.tbuf = tbuf; ea.n = n; ea.status = status;
+    ea.hub_base = hub_base; ea.Hw = Hw; ea.hstart = hstart; ea.HB = HB; ea.hpre = hpre; ea.TM = TM;
     unsigned edge_grid = (unsigned)(cus > 0 ? cus * 24 : 2048);
     if ((int64_t)edge_grid > m) edge_grid = (unsigned)(m > 0 ? m : 1);
     HIPCHK(launch_edges(false, ea, edge_grid, st));

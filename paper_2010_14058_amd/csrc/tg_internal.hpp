@@ -28,6 +28,8 @@ constexpr int HEAVY_THREADS = 256;    // threads of a heavy-group workgroup
 constexpr int HEAVY_CHUNK = 128;      // items staged per round in the heavy path
 constexpr int TCAP = 1024;            // triangle set kept in LDS by the light edge kernel
 constexpr int EDGE_THREADS_HEAVY = 256;
+constexpr int HUB_DMIN = 32;          // smallest degree of a hub-core node
+constexpr int HUB_MAX = 8192;         // largest hub core (bit-matrix HUB_MAX^2 bits)
 
 // Device-side layout of everything the library keeps in the caller's
 // workspace.  All offsets are byte offsets from the workspace base.
@@ -44,6 +46,7 @@ struct Layout {
     size_t off_tdeg, off_tri, off_A, off_D, off_NC;
     size_t off_listA_light, off_listA_heavy, off_listB_light, off_listB_heavy, off_list_edge;
     size_t off_maps, off_tbuf, off_gacc, off_sort_tmp;
+    size_t off_hstart, off_HB, off_hpre, off_TM;
     size_t total;
 };
 
@@ -51,7 +54,7 @@ struct Layout {
 enum Counter {
     C_A_LIGHT = 0, C_A_HEAVY, C_B_LIGHT, C_B_HEAVY, C_EDGE_HEAVY,
     C_A_NEXT, C_B_NEXT, C_EDGE_NEXT, C_WEDGES_A, C_WEDGES_B,
-    C_WEDGES_A_HEAVY, C_WEDGES_B_HEAVY, C_TRI_SUM,
+    C_WEDGES_A_HEAVY, C_WEDGES_B_HEAVY, C_TRI_SUM, C_HUB_CAND,
     C_NUM
 };
 
@@ -93,9 +96,16 @@ struct EdgeArgs {
     int hist_in_lds;
     uint32_t *heavy_list;
     uint64_t *counters;
-    uint32_t *tbuf;      // heavy: per-workgroup triangle buffers of n entries
+    uint32_t *tbuf;      // heavy: per-workgroup low-member buffers of n entries
     int64_t n;
     uint32_t *status;
+    // hub core: internal ids hub_base..n-1
+    int32_t hub_base;
+    int Hw;                      // 64-bit words per bit row
+    const int64_t *hstart;       // first slot of each row's hub suffix
+    const uint64_t *HB;          // [H][Hw] hub adjacency bits
+    const uint32_t *hpre;        // [H][Hw] exclusive prefix popcounts
+    const uint64_t *TM;          // [L][Hw] hubs of each type
 };
 
 // Launch wrappers (tg_kernels.hip).
@@ -106,7 +116,7 @@ hipError_t launch_check_rows(const int64_t *rp, const int32_t *col, const uint8_
 hipError_t launch_node_keys(const uint32_t *deg, int64_t n, uint64_t *keys, hipStream_t st);
 hipError_t launch_relabel(const uint64_t *sorted, const uint8_t *types, const uint32_t *deg, int64_t n,
                           int32_t *order, int32_t *newid, uint8_t *ntype, int64_t *ndeg,
-                          hipStream_t st);
+                          uint64_t *hub_cand, hipStream_t st);
 hipError_t launch_slot_keys(const int64_t *rp, const int32_t *col, const int64_t *ucount,
                             const int64_t *eoff, const int32_t *newid, int64_t n, int bits,
                             uint64_t *keys, uint32_t *vals, int32_t *ei, int32_t *ej,
@@ -114,7 +124,10 @@ hipError_t launch_slot_keys(const int64_t *rp, const int32_t *col, const int64_t
 hipError_t launch_finish_csr(const uint64_t *keys, const uint32_t *vals, int64_t nnz, int bits,
                              int32_t *ncol, uint32_t *neid, hipStream_t st);
 hipError_t launch_tdeg(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype, int64_t n,
-                       int L, uint32_t *tdeg, hipStream_t st);
+                       int L, int32_t hub_base, uint32_t *tdeg, int64_t *hstart, hipStream_t st);
+hipError_t launch_hub_build(const int64_t *nrp, const int32_t *ncol, const int64_t *hstart,
+                            const uint8_t *ntype, int64_t n, int H, int Hw, int L, uint64_t *HB,
+                            uint32_t *pre, uint64_t *TM, hipStream_t st);
 hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype,
                       const int32_t *ei, const int32_t *ej, int64_t m, int L, uint32_t *tri,
                       uint64_t *tri_sum, hipStream_t st);

@@ -20,102 +20,9 @@
 //             histogram of global counts (Problem 2).
 #include <hip/hip_runtime.h>
 
-#include "tg_internal.hpp"
+#include "tg_device.hpp"
 
 namespace tg {
-
-// ---------------------------------------------------------------- helpers
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
-
-__device__ __forceinline__ int64_t lower_bound(const int32_t *a, int64_t lo, int64_t hi,
-                                               int32_t key) {
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (a[mid] < key) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ int64_t upper_bound(const int32_t *a, int64_t lo, int64_t hi,
-                                               int32_t key) {
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (a[mid] <= key) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
-// First index in s[0..len) whose value exceeds f (s inclusive scan, LDS).
-__device__ __forceinline__ int owner_of(const uint32_t *s, int len, uint32_t f) {
-    int lo = 0, hi = len;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (s[mid] <= f) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        uint32_t o = __shfl_up(v, d, WAVE);
-        if (lane >= d) v += o;
-    }
-    return v;
-}
-
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-#pragma unroll
-    for (int d = WAVE / 2; d > 0; d >>= 1) v += (uint64_t)__shfl_xor((unsigned long long)v, d, WAVE);
-    return v;
-}
-
-__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
-#pragma unroll
-    for (int d = WAVE / 2; d > 0; d >>= 1) v |= __shfl_xor(v, d, WAVE);
-    return v;
-}
-
-__device__ __forceinline__ uint32_t load_agent(const uint32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// C(n, r) for r <= 4 (co-lexicographic ranks of type multisets).
-__device__ __forceinline__ int64_t binom_small(int64_t n, int r) {
-    if (n < r) return 0;
-    switch (r) {
-        case 1: return n;
-        case 2: return n * (n - 1) / 2;
-        case 3: return n * (n - 1) * (n - 2) / 6;
-        default: return n * (n - 1) * (n - 2) * (n - 3) / 24;
-    }
-}
-
-__device__ __forceinline__ void sort2(int &a, int &b) { if (a > b) { int c = a; a = b; b = c; } }
-
-__device__ __forceinline__ int rank2(int a, int b) {
-    sort2(a, b);
-    return (int)(binom_small(a, 1) + binom_small(b + 1, 2));
-}
-
-__device__ __forceinline__ int rank3(int a, int b, int c) {
-    sort2(a, b); sort2(b, c); sort2(a, b);
-    return (int)(binom_small(a, 1) + binom_small(b + 1, 2) + binom_small(c + 2, 3));
-}
-
-__device__ __forceinline__ int rank4(int a, int b, int c, int d) {
-    sort2(a, b); sort2(c, d); sort2(a, c); sort2(b, d); sort2(b, c);
-    return (int)(binom_small(a, 1) + binom_small(b + 1, 2) + binom_small(c + 2, 3) +
-                 binom_small(d + 3, 4));
-}
 
 // ------------------------------------------------------------------ prep
 
@@ -173,16 +80,22 @@ __global__ void k_node_keys(const uint32_t *__restrict__ deg, int64_t n, uint64_
 __global__ void k_relabel(const uint64_t *__restrict__ sorted, const uint8_t *__restrict__ types,
                           const uint32_t *__restrict__ deg, int64_t n,
                           int32_t *__restrict__ order, int32_t *__restrict__ newid,
-                          uint8_t *__restrict__ ntype, int64_t *__restrict__ ndeg) {
+                          uint8_t *__restrict__ ntype, int64_t *__restrict__ ndeg,
+                          uint64_t *__restrict__ hub_cand) {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool cand = false;
     if (r < n) {
         int32_t v = (int32_t)(sorted[r] & 0xffffffffu);
         order[r] = v;
         newid[v] = (int32_t)r;
         ntype[r] = types[v];
         ndeg[r] = deg[v];
+        cand = deg[v] >= (uint32_t)HUB_DMIN;
     }
     if (r == 0) ndeg[n] = 0;
+    uint64_t bal = __ballot(cand);
+    if (lane_id() == 0 && bal)
+        atomicAdd((unsigned long long *)hub_cand, (unsigned long long)__popcll(bal));
 }
 
 // One wave per input row: canonical edge id of every slot, the relabelled
@@ -234,13 +147,15 @@ __global__ void k_finish_csr(const uint64_t *__restrict__ keys, const uint32_t *
     }
 }
 
-// One wave per internal node: typed degrees d_v^t.
+// One wave per internal node: typed degrees d_v^t and the first slot of the
+// row's hub suffix (neighbours with internal id >= hub_base).
 __global__ void k_tdeg(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
-                       const uint8_t *__restrict__ ntype, int64_t n, int L,
-                       uint32_t *__restrict__ tdeg) {
+                       const uint8_t *__restrict__ ntype, int64_t n, int L, int32_t hub_base,
+                       uint32_t *__restrict__ tdeg, int64_t *__restrict__ hstart) {
     int64_t v = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
     int lane = lane_id();
     if (v >= n) return;
+    if (lane == 0) hstart[v] = lower_bound(ncol, nrp[v], nrp[v + 1], hub_base);
     uint32_t c = 0;
     for (int64_t base = nrp[v]; base < nrp[v + 1]; base += WAVE) {
         int64_t s = base + lane;
@@ -628,298 +543,6 @@ __global__ void k_cyc_work(const int64_t *__restrict__ nrp, const int32_t *__res
     }
 }
 
-// ----------------------------------------------- per-edge derive + write
-
-
-
-__device__ __forceinline__ void hist_add(const EdgeArgs &a, uint64_t *hist, int idx, uint64_t v) {
-    if (!v) return;
-    if (a.hist_in_lds) atomicAdd((unsigned long long *)&hist[idx], (unsigned long long)v);
-    else atomicAdd((unsigned long long *)&a.gacc[idx], (unsigned long long)v);
-}
-
-// Edge (canonical i, j) with its triangle set already in T[0..nT) and the
-// LDS matrices Xi, Xj, Y (filled), K (zeroed): counts cliques, derives all
-// orbits and writes the row.  NT threads cooperate.
-template <int NT>
-__device__ void edge_finish(const EdgeArgs &a, int64_t e, int32_t i, int32_t j, const uint32_t *T,
-                            int nT, uint64_t *Xi, uint64_t *Xj, uint64_t *Y, uint64_t *K,
-                            uint64_t *hist, int tid, uint32_t &bad) {
-    const int L = a.L;
-    // ordered typed clique pairs: k, r in T adjacent (Alg. 3, 4-clique test)
-    for (int kk = 0; kk < nT; ++kk) {
-        int32_t k = (int32_t)T[kk];
-        int64_t kb = a.nrp[k], ke = a.nrp[k + 1];
-        int tk = a.ntype[k];
-        for (int rr = kk + 1 + tid; rr < nT; rr += NT) {
-            int32_t r = (int32_t)T[rr];
-            int64_t rb = a.nrp[r], re = a.nrp[r + 1];
-            bool adj;
-            if (ke - kb <= re - rb) {
-                int64_t p = lower_bound(a.ncol, kb, ke, r);
-                adj = p < ke && a.ncol[p] == r;
-            } else {
-                int64_t p = lower_bound(a.ncol, rb, re, k);
-                adj = p < re && a.ncol[p] == k;
-            }
-            if (adj) {
-                int tr = a.ntype[r];
-                atomicAdd((unsigned long long *)&K[tk * L + tr], 1ull);
-                atomicAdd((unsigned long long *)&K[tr * L + tk], 1ull);
-            }
-        }
-    }
-    if (NT == WAVE) wave_sync(); else __syncthreads();
-
-    const int ta = a.ntype[i], tb = a.ntype[j];
-    const int LL = L * L;
-    const int P = L * (L + 1) / 2;
-    const int W = 2 * L + 10 * P;
-    const uint32_t *tri_e = a.tri + (size_t)e * L;
-    const uint32_t *di = a.tdeg + (size_t)i * L;
-    const uint32_t *dj = a.tdeg + (size_t)j * L;
-    const uint64_t *Ai = a.A + (size_t)i * LL, *Aj = a.A + (size_t)j * LL;
-    const uint64_t *Di = a.D + (size_t)i * LL, *Dj = a.D + (size_t)j * LL;
-    const uint64_t *NC = a.NC + (size_t)e * LL;
-    uint64_t *row = a.rows ? a.rows + (size_t)e * W : nullptr;
-    const int n2 = (int)binom_small(L + 1, 2);
-    const int n3 = (int)binom_small(L + 2, 3);
-    const int n4 = (int)binom_small(L + 3, 4);
-
-    if (tid == 0) hist_add(a, hist, rank2(ta, tb), 1);
-    for (int t = tid; t < L; t += NT) {
-        int64_t nTt = tri_e[t];
-        int64_t si = (int64_t)di[t] - nTt - (tb == t);
-        int64_t sj = (int64_t)dj[t] - nTt - (ta == t);
-        if (si < 0 || sj < 0) bad |= ST_INTERNAL;
-        if (row) {
-            row[t] = (uint64_t)nTt;
-            row[L + t] = (uint64_t)(si + sj);
-        }
-        int r3 = rank3(ta, tb, t);
-        hist_add(a, hist, n2 + r3, (uint64_t)(si + sj));
-        hist_add(a, hist, n2 + n3 + r3, (uint64_t)nTt);
-    }
-    for (int p = tid; p < P; p += NT) {
-        // pair (t, u), t <= u, from its lexicographic index
-        int t = 0, rem = p;
-        while (rem >= L - t) { rem -= L - t; ++t; }
-        int u = t + rem;
-        int64_t nT_[2] = {(int64_t)tri_e[t], (int64_t)tri_e[u]};
-        int64_t Si[2], Sj[2];
-        int xs[2] = {t, u};
-        for (int z = 0; z < 2; ++z) {
-            int x = xs[z];
-            Si[z] = (int64_t)di[x] - nT_[z] - (tb == x);
-            Sj[z] = (int64_t)dj[x] - nT_[z] - (ta == x);
-        }
-        // ordered quantities for (x, y) = (t, u) [z=0] and (u, t) [z=1]
-        int64_t Ci[2], Cj[2], sgi[2], sgj[2], dli[2], dlj[2], Kx[2], Yx[2], Xix[2], NCx[2];
-        for (int z = 0; z < 2; ++z) {
-            int x = z ? u : t, y = z ? t : u;
-            int zx = z, zy = 1 - z;  // index of x / y inside nT_, Si, Sj
-            int q = x * L + y;
-            int64_t xi = (int64_t)Xi[q], xj = (int64_t)Xj[q], kk = (int64_t)K[q], yy = (int64_t)Y[q];
-            Ci[z] = xi - nT_[zx] * (tb == y) - kk;
-            Cj[z] = xj - nT_[zx] * (ta == y) - kk;
-            sgi[z] = (int64_t)Ai[q] - xi - (tb == x) * nT_[zy];
-            sgj[z] = (int64_t)Aj[q] - xj - (ta == x) * nT_[zy];
-            dli[z] = (int64_t)Di[q] - yy - (tb == x) * (int64_t)dj[y];
-            dlj[z] = (int64_t)Dj[q] - yy - (ta == x) * (int64_t)di[y];
-            Kx[z] = kk;
-            Yx[z] = yy;
-            Xix[z] = xi;
-            NCx[z] = (int64_t)NC[q];
-        }
-        int64_t Cyc[2], Ei[2], Ej[2], Pi[2], Pj[2], Q[2];
-        for (int z = 0; z < 2; ++z) Cyc[z] = NCx[z] - Ci[1 - z] - Cj[z] - Kx[z];
-        for (int z = 0; z < 2; ++z) {
-            int zb = 1 - z;
-            int y = z ? t : u;
-            int zx = z;
-            Ei[z] = sgi[z] - Ci[zb];
-            Ej[z] = sgj[z] - Cj[zb];
-            Pi[z] = dli[z] - Si[zx] * (ta == y) - sgi[z] - Cyc[z];
-            Pj[z] = dlj[z] - Sj[zx] * (tb == y) - sgj[z] - Cyc[zb];
-            Q[z] = Yx[z] - Xix[z] - Cj[z] - nT_[zx] * (ta == y);
-        }
-        int64_t g[13];
-        if (t == u) {
-            if (Kx[0] & 1) bad |= ST_INTERNAL;
-            if ((Ei[0] + Ej[0]) & 1) bad |= ST_INTERNAL;
-            g[12] = Kx[0] / 2;
-            g[6] = Cyc[0];
-            g[10] = Ci[0] + Cj[0];
-            g[7] = (Ei[0] + Ej[0]) / 2;
-            g[3] = Pi[0] + Pj[0];
-            g[8] = Q[0];
-            g[4] = Si[0] * Sj[0] - g[6];
-            g[5] = Si[0] * (Si[0] - 1) / 2 + Sj[0] * (Sj[0] - 1) / 2 - g[7];
-            g[9] = nT_[0] * (Si[0] + Sj[0]) - g[10];
-            g[11] = nT_[0] * (nT_[0] - 1) / 2 - g[12];
-        } else {
-            if (Ei[0] != Ei[1] || Ej[0] != Ej[1] || Kx[0] != Kx[1]) bad |= ST_INTERNAL;
-            g[12] = Kx[0];
-            g[6] = Cyc[0] + Cyc[1];
-            g[10] = Ci[0] + Cj[0] + Ci[1] + Cj[1];
-            g[7] = Ei[0] + Ej[0];
-            g[3] = Pi[0] + Pi[1] + Pj[0] + Pj[1];
-            g[8] = Q[0] + Q[1];
-            g[4] = Si[0] * Sj[1] + Si[1] * Sj[0] - g[6];
-            g[5] = Si[0] * Si[1] + Sj[0] * Sj[1] - g[7];
-            g[9] = nT_[0] * (Si[1] + Sj[1]) + nT_[1] * (Si[0] + Sj[0]) - g[10];
-            g[11] = nT_[0] * nT_[1] - g[12];
-        }
-        int r4 = rank4(ta, tb, t, u);
-        // graphlet of each orbit (Sec. 4.4): h3 = g3+g4, h4 = g5, h5 = g6,
-        // h6 = g7+g8+g9, h7 = g10+g11, h8 = g12
-        const int hof[13] = {0, 0, 0, 3, 3, 4, 5, 6, 6, 6, 7, 7, 8};
-        for (int o = 3; o <= 12; ++o) {
-            if (g[o] < 0) bad |= ST_INTERNAL;
-            uint64_t v = (uint64_t)g[o];
-            if (row) row[2 * L + (o - 3) * P + p] = v;
-            hist_add(a, hist, n2 + 2 * n3 + (hof[o] - 3) * n4 + r4, v);
-        }
-    }
-}
-
-// Light edges: one wave per edge with the triangle set in LDS (|T| <= TCAP);
-// edges with both degrees above TCAP go to the heavy list.
-__global__ void __launch_bounds__(64) k_edges_light(EdgeArgs a) {
-    extern __shared__ uint64_t sm_edge[];
-    const int L = a.L;
-    const int LL = L * L;
-    uint64_t *Xi = sm_edge, *Xj = Xi + LL, *Y = Xj + LL, *K = Y + LL;
-    uint64_t *hist = K + LL;
-    uint32_t *T = (uint32_t *)(hist + (a.hist_in_lds ? a.gw : 0));
-    int lane = threadIdx.x;
-    uint32_t bad = 0;
-    if (a.hist_in_lds)
-        for (int q = lane; q < a.gw; q += WAVE) hist[q] = 0;
-    __syncthreads();
-    for (int64_t e = blockIdx.x; e < a.m; e += gridDim.x) {
-        int32_t i = a.ei[e], j = a.ej[e];
-        int64_t ib = a.nrp[i], ie = a.nrp[i + 1], jb = a.nrp[j], je = a.nrp[j + 1];
-        int64_t dmin = (ie - ib) < (je - jb) ? (ie - ib) : (je - jb);
-        if (dmin > TCAP) {
-            if (lane == 0)
-                a.heavy_list[atomicAdd((unsigned long long *)&a.counters[C_EDGE_HEAVY], 1ull)] =
-                    (uint32_t)e;
-            continue;
-        }
-        for (int q = lane; q < 4 * LL; q += WAVE) Xi[q] = 0;
-        __syncthreads();
-        bool i_small = (ie - ib) <= (je - jb);
-        int64_t sb = i_small ? ib : jb, se = i_small ? ie : je;
-        int64_t bb = i_small ? jb : ib, be = i_small ? je : ie;
-        uint32_t nT = 0;
-        for (int64_t base = sb; base < se; base += WAVE) {
-            int64_t s = base + lane;
-            bool found = false;
-            int64_t q = 0;
-            int32_t x = 0;
-            if (s < se) {
-                x = a.ncol[s];
-                q = lower_bound(a.ncol, bb, be, x);
-                found = q < be && a.ncol[q] == x;
-            }
-            uint64_t bal = __ballot(found);
-            if (found) {
-                uint32_t pos = nT + (uint32_t)__popcll(bal & ((1ull << lane) - 1));
-                T[pos] = (uint32_t)x;
-                int64_t s_i = i_small ? s : q, s_j = i_small ? q : s;
-                uint32_t eik = a.neid[s_i], ejk = a.neid[s_j];
-                int t = a.ntype[x];
-                for (int t2 = 0; t2 < L; ++t2) {
-                    uint32_t vi = a.tri[(size_t)eik * L + t2];
-                    uint32_t vj = a.tri[(size_t)ejk * L + t2];
-                    uint32_t vy = a.tdeg[(size_t)x * L + t2];
-                    if (vi) atomicAdd((unsigned long long *)&Xi[t * L + t2], (unsigned long long)vi);
-                    if (vj) atomicAdd((unsigned long long *)&Xj[t * L + t2], (unsigned long long)vj);
-                    if (vy) atomicAdd((unsigned long long *)&Y[t * L + t2], (unsigned long long)vy);
-                }
-            }
-            nT += (uint32_t)__popcll(bal);
-        }
-        __syncthreads();
-        edge_finish<WAVE>(a, e, i, j, T, (int)nT, Xi, Xj, Y, K, hist, lane, bad);
-        __syncthreads();
-    }
-    if (a.hist_in_lds)
-        for (int q = lane; q < a.gw; q += WAVE)
-            if (hist[q]) atomicAdd((unsigned long long *)&a.gacc[q], (unsigned long long)hist[q]);
-    bad = wave_or(bad);
-    if (lane == 0 && bad) atomicOr(a.status, bad);
-}
-
-// Heavy edges: one 256-thread workgroup per edge, triangle set in a global
-// buffer private to the workgroup.
-__global__ void __launch_bounds__(EDGE_THREADS_HEAVY) k_edges_heavy(EdgeArgs a) {
-    extern __shared__ uint64_t sm_edgeh[];
-    const int L = a.L;
-    const int LL = L * L;
-    const int NT = EDGE_THREADS_HEAVY;
-    uint64_t *Xi = sm_edgeh, *Xj = Xi + LL, *Y = Xj + LL, *K = Y + LL;
-    uint64_t *hist = K + LL;
-    __shared__ uint32_t s_nT;
-    __shared__ uint64_t s_idx;
-    uint32_t *T = a.tbuf + (size_t)blockIdx.x * (size_t)a.n;
-    int tid = threadIdx.x;
-    uint32_t bad = 0;
-    if (a.hist_in_lds)
-        for (int q = tid; q < a.gw; q += NT) hist[q] = 0;
-    uint64_t count = a.counters[C_EDGE_HEAVY];
-    __syncthreads();
-    while (true) {
-        if (tid == 0) s_idx = atomicAdd((unsigned long long *)&a.counters[C_EDGE_NEXT], 1ull);
-        __syncthreads();
-        uint64_t idx = s_idx;
-        __syncthreads();
-        if (idx >= count) break;
-        int64_t e = a.heavy_list[idx];
-        int32_t i = a.ei[e], j = a.ej[e];
-        int64_t ib = a.nrp[i], ie = a.nrp[i + 1], jb = a.nrp[j], je = a.nrp[j + 1];
-        for (int q = tid; q < 4 * LL; q += NT) Xi[q] = 0;
-        if (tid == 0) s_nT = 0;
-        __syncthreads();
-        bool i_small = (ie - ib) <= (je - jb);
-        int64_t sb = i_small ? ib : jb, se = i_small ? ie : je;
-        int64_t bb = i_small ? jb : ib, be = i_small ? je : ie;
-        for (int64_t base = sb; base < se; base += NT) {
-            int64_t s = base + tid;
-            if (s < se) {
-                int32_t x = a.ncol[s];
-                int64_t q = lower_bound(a.ncol, bb, be, x);
-                if (q < be && a.ncol[q] == x) {
-                    uint32_t pos = atomicAdd(&s_nT, 1u);
-                    T[pos] = (uint32_t)x;
-                    int64_t s_i = i_small ? s : q, s_j = i_small ? q : s;
-                    uint32_t eik = a.neid[s_i], ejk = a.neid[s_j];
-                    int t = a.ntype[x];
-                    for (int t2 = 0; t2 < L; ++t2) {
-                        uint32_t vi = a.tri[(size_t)eik * L + t2];
-                        uint32_t vj = a.tri[(size_t)ejk * L + t2];
-                        uint32_t vy = a.tdeg[(size_t)x * L + t2];
-                        if (vi) atomicAdd((unsigned long long *)&Xi[t * L + t2], (unsigned long long)vi);
-                        if (vj) atomicAdd((unsigned long long *)&Xj[t * L + t2], (unsigned long long)vj);
-                        if (vy) atomicAdd((unsigned long long *)&Y[t * L + t2], (unsigned long long)vy);
-                    }
-                }
-            }
-        }
-        __threadfence_block();
-        __syncthreads();
-        int nT = (int)s_nT;
-        edge_finish<NT>(a, e, i, j, T, nT, Xi, Xj, Y, K, hist, tid, bad);
-        __threadfence_block();
-        __syncthreads();
-    }
-    if (a.hist_in_lds)
-        for (int q = tid; q < a.gw; q += NT)
-            if (hist[q]) atomicAdd((unsigned long long *)&a.gacc[q], (unsigned long long)hist[q]);
-    if (bad) atomicOr(a.status, bad);
-}
-
 // Global counts: divide each graphlet block by its edge count.
 __global__ void k_global_finalize(const uint64_t *__restrict__ gacc, int L,
                                   uint64_t *__restrict__ out, uint32_t *__restrict__ status) {
@@ -972,9 +595,9 @@ hipError_t launch_node_keys(const uint32_t *deg, int64_t n, uint64_t *keys, hipS
 
 hipError_t launch_relabel(const uint64_t *sorted, const uint8_t *types, const uint32_t *deg, int64_t n,
                           int32_t *order, int32_t *newid, uint8_t *ntype, int64_t *ndeg,
-                          hipStream_t st) {
+                          uint64_t *hub_cand, hipStream_t st) {
     k_relabel<<<blocks_for(n > 0 ? n : 1, 256), 256, 0, st>>>(sorted, types, deg, n, order, newid,
-                                                              ntype, ndeg);
+                                                              ntype, ndeg, hub_cand);
     LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -998,8 +621,8 @@ hipError_t launch_finish_csr(const uint64_t *keys, const uint32_t *vals, int64_t
 }
 
 hipError_t launch_tdeg(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype, int64_t n,
-                       int L, uint32_t *tdeg, hipStream_t st) {
-    k_tdeg<<<blocks_for(n, 4), 256, 0, st>>>(nrp, ncol, ntype, n, L, tdeg);
+                       int L, int32_t hub_base, uint32_t *tdeg, int64_t *hstart, hipStream_t st) {
+    k_tdeg<<<blocks_for(n, 4), 256, 0, st>>>(nrp, ncol, ntype, n, L, hub_base, tdeg, hstart);
     LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1047,20 +670,6 @@ hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned g
         size_t sh = (size_t)args.chunk * args.L * args.L * sizeof(uint64_t);
         if (pass == 0) k_cyc_heavy<0><<<grid, HEAVY_THREADS, sh, st>>>(args);
         else k_cyc_heavy<1><<<grid, HEAVY_THREADS, sh, st>>>(args);
-    }
-    LAUNCH_CHECK();
-    return hipSuccess;
-}
-
-hipError_t launch_edges(bool heavy, const EdgeArgs &args, unsigned grid, hipStream_t st) {
-    if (grid == 0) return hipSuccess;
-    int LL = args.L * args.L;
-    size_t sh = (size_t)(4 * LL + (args.hist_in_lds ? args.gw : 0)) * sizeof(uint64_t);
-    if (!heavy) {
-        sh += (size_t)TCAP * sizeof(uint32_t);
-        k_edges_light<<<grid, 64, sh, st>>>(args);
-    } else {
-        k_edges_heavy<<<grid, EDGE_THREADS_HEAVY, sh, st>>>(args);
     }
     LAUNCH_CHECK();
     return hipSuccess;
