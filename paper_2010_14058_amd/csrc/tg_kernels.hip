@@ -465,13 +465,17 @@ __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
                     if (phase == 0) {
                         for (int t = 0; t < L; ++t) my[t] = 0u;
                     } else if (phase == 1) {
-                        atomicAdd(&my[a.ntype[x]], 1u);
+                        // the map is private to this workgroup: workgroup scope
+                        // keeps the update in the XCD's L2
+                        __hip_atomic_fetch_add(&my[a.ntype[x]], 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
                     } else {
                         int tx = a.ntype[x];
                         int ty = a.ntype[y];
                         uint64_t *ac = acc + (size_t)o * LL;
                         for (int t = 0; t < L; ++t) {
-                            uint32_t c = load_agent(&my[t]);
+                            uint32_t c = __hip_atomic_load(&my[t], __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_WORKGROUP);
                             uint32_t val = c - (t == tx ? 1u : 0u);
                             if (val)
                                 atomicAdd((unsigned long long *)&ac[pass_entry<PASS>(t, ty, L)],
@@ -494,7 +498,8 @@ __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
                     __syncthreads();
                 }
             }
-            __threadfence();
+            // all map traffic of a group stays inside this workgroup, so a
+            // workgroup barrier orders the clear, count and emit walks
             __syncthreads();
         }
     }
