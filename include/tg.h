@@ -77,7 +77,8 @@ typedef enum tg_status {
     TG_E_WORKSPACE = 5,   /* workspace smaller than tg_workspace_bytes() */
     TG_E_DEVICE = 6,      /* a HIP call failed */
     TG_E_INTERNAL = 7,    /* an internal consistency check failed */
-    TG_E_TOO_LARGE = 8    /* n or nnz beyond the supported range (see below) */
+    TG_E_TOO_LARGE = 8,   /* n or nnz beyond the supported range (see below) */
+    TG_E_BATCH = 9        /* batch descriptor inconsistent, or an edge joins two graphs */
 } tg_status;
 
 /* Human-readable name of a status code (static string). */
@@ -108,6 +109,33 @@ tg_status tg_count_typed_graphlets(const int64_t *row_ptr, const int32_t *col,
                                    const uint8_t *types, int64_t n, int64_t nnz, int32_t L,
                                    uint64_t *per_edge, uint64_t *global_counts,
                                    void *workspace, size_t ws_bytes, void *stream);
+
+/* Batched counting of many graphs in one call.  The graphs are given as one
+ * CSR over all their nodes (a disjoint union): graph g owns the nodes
+ * [graph_node_ptr[g], graph_node_ptr[g+1]) and no edge joins two graphs;
+ * its node types lie in [0, graph_L[g]), 1 <= graph_L[g] <= L_max.  Graphlets
+ * are connected, so every edge's counts are those of its own graph.
+ *   graph_node_ptr    device int64 [G+1], graph_node_ptr[0] = 0,
+ *                     graph_node_ptr[G] = n, non-decreasing.
+ *   graph_L           device int32 [G].
+ *   graph_global_off  device int64 [G+1]: graph g's global vector occupies
+ *                     graph_globals[off[g] .. off[g+1]), which must be
+ *                     tg_global_width(graph_L[g]) entries (its own layout);
+ *                     off[0] = 0, off[G] = globals_len.
+ *   graph_globals     device uint64 [globals_len]: per-graph global counts.
+ *   per_edge          NULL, or device uint64 [nnz/2][tg_row_width(L_max)]
+ *                     rows of the union's edges in canonical order (the
+ *                     edges of graph g are contiguous), laid out for L_max.
+ *   workspace         at least tg_batch_workspace_bytes(n, nnz, G, L_max).
+ * Validation, streams and errors as for tg_count_typed_graphlets; an
+ * inconsistent descriptor or a cross-graph edge gives TG_E_BATCH. */
+size_t tg_batch_workspace_bytes(int64_t n, int64_t nnz, int64_t G, int32_t L_max);
+tg_status tg_count_batch(const int64_t *row_ptr, const int32_t *col, const uint8_t *types,
+                         int64_t n, int64_t nnz, const int64_t *graph_node_ptr,
+                         const int32_t *graph_L, int64_t G, int32_t L_max,
+                         const int64_t *graph_global_off, int64_t globals_len,
+                         uint64_t *per_edge, uint64_t *graph_globals, void *workspace,
+                         size_t ws_bytes, void *stream);
 
 /* Meaning of per-edge column `col` for L types: orbit 1 = tri, 2 = path3
  * (with *t the third node's type and *t2 = -1), else the orbit number 3..12

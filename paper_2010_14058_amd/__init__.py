@@ -10,6 +10,7 @@ from __future__ import annotations
 from . import _lib
 from ._lib import (  # noqa: F401
     TGError,
+    batch_workspace_bytes,
     global_key_describe,
     global_width,
     key_describe,
@@ -79,3 +80,68 @@ def count_typed_graphlets(row_ptr, col, types, L: int, *, per_edge: bool = True,
                    rows.data_ptr() if rows is not None and rows.numel() else 0,
                    glob.data_ptr(), ws.data_ptr(), ws.numel(), stream.cuda_stream)
     return rows, glob
+
+
+def global_offsets(graph_L) -> "np.ndarray":
+    """Offsets of the per-graph global vectors (each in its graph's own layout)."""
+    import numpy as np
+
+    widths = np.array([global_width(int(x)) for x in range(0, 17)], dtype=np.int64)
+    gl = np.asarray(graph_L, dtype=np.int64)
+    return np.concatenate([[0], np.cumsum(widths[gl])]).astype(np.int64)
+
+
+class BatchPlan:
+    """Device-resident descriptor of a batch of graphs (disjoint-union CSR)."""
+
+    def __init__(self, row_ptr, col, types, node_ptr, graph_L, L_max: int | None = None):
+        import numpy as np
+        import torch
+
+        self.row_ptr = row_ptr.contiguous()
+        self.col = col.contiguous()
+        self.types = types.contiguous()
+        dev = self.row_ptr.device
+        gl_host = graph_L.cpu().numpy() if hasattr(graph_L, "cpu") else np.asarray(graph_L)
+        self.node_ptr = torch.as_tensor(np.asarray(node_ptr.cpu() if hasattr(node_ptr, "cpu")
+                                                   else node_ptr, dtype=np.int64)).to(dev)
+        self.graph_L = torch.as_tensor(gl_host.astype(np.int32)).to(dev)
+        self.goff_host = global_offsets(gl_host)
+        self.goff = torch.as_tensor(self.goff_host).to(dev)
+        self.G = int(gl_host.shape[0])
+        self.L_max = int(L_max if L_max is not None else gl_host.max())
+        self.n = self.row_ptr.numel() - 1
+        self.nnz = self.col.numel()
+
+
+def count_batch(plan: BatchPlan, *, per_edge: bool = False, out_globals=None, out_rows=None,
+                workspace: Workspace | None = None, stream=None):
+    """Typed graphlet counts of every graph of a batch in one library call.
+
+    Returns ``(globals, rows)``: globals is an int64 tensor holding the
+    per-graph uint64 global vectors back to back (graph g at
+    ``plan.goff_host[g]``, in its own L layout); rows (optional) holds the
+    union's per-edge table in the layout of ``plan.L_max``.
+    """
+    import torch
+
+    dev = plan.row_ptr.device
+    glen = int(plan.goff_host[-1])
+    glob = out_globals if out_globals is not None else torch.empty(glen, dtype=torch.int64,
+                                                                   device=dev)
+    rows = None
+    if per_edge:
+        rows = out_rows if out_rows is not None else torch.empty(
+            (plan.nnz // 2, row_width(plan.L_max)), dtype=torch.int64, device=dev)
+    wsb = batch_workspace_bytes(plan.n, plan.nnz, plan.G, plan.L_max)
+    if wsb == 0:
+        raise _lib.TGError(1, "tg_batch_workspace_bytes")
+    ws = (workspace or Workspace(dev)).get(wsb)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    _lib.count_batch_raw(plan.row_ptr.data_ptr(), plan.col.data_ptr() if plan.nnz else 0,
+                         plan.types.data_ptr(), plan.n, plan.nnz, plan.node_ptr.data_ptr(),
+                         plan.graph_L.data_ptr(), plan.G, plan.L_max, plan.goff.data_ptr(), glen,
+                         rows.data_ptr() if rows is not None and rows.numel() else 0,
+                         glob.data_ptr(), ws.data_ptr(), ws.numel(), stream.cuda_stream)
+    return glob, rows

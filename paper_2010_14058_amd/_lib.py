@@ -24,6 +24,11 @@ SIGNATURES = {
     "tg_count_typed_graphlets": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int64,
                                             _c.c_int64, _c.c_int32, _c.c_void_p, _c.c_void_p,
                                             _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "tg_batch_workspace_bytes": (_c.c_size_t, [_c.c_int64, _c.c_int64, _c.c_int64, _c.c_int32]),
+    "tg_count_batch": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int64,
+                                  _c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int32, _c.c_void_p,
+                                  _c.c_int64, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_size_t,
+                                  _c.c_void_p]),
     "tg_key_describe": (_c.c_int, [_c.c_int32, _c.c_int32, _c.POINTER(_c.c_int32),
                                    _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
     "tg_global_key_describe": (_c.c_int, [_c.c_int32, _c.c_int32, _c.POINTER(_c.c_int32),
@@ -120,3 +125,16 @@ def count_raw(row_ptr_ptr: int, col_ptr: int, types_ptr: int, n: int, nnz: int, 
                                          global_ptr, ws_ptr, ws_bytes, stream)
     if rc:
         raise TGError(rc, "tg_count_typed_graphlets")
+
+
+def batch_workspace_bytes(n: int, nnz: int, G: int, L_max: int) -> int:
+    return load().tg_batch_workspace_bytes(n, nnz, G, L_max)
+
+
+def count_batch_raw(row_ptr: int, col: int, types: int, n: int, nnz: int, node_ptr: int,
+                    graph_L: int, G: int, L_max: int, goff: int, globals_len: int, per_edge: int,
+                    globals_ptr: int, ws: int, ws_bytes: int, stream: int) -> None:
+    rc = load().tg_count_batch(row_ptr, col, types, n, nnz, node_ptr, graph_L, G, L_max, goff,
+                               globals_len, per_edge, globals_ptr, ws, ws_bytes, stream)
+    if rc:
+        raise TGError(rc, "tg_count_batch")

@@ -53,7 +53,7 @@ static size_t sort_tmp_bytes(int64_t n, int64_t nnz) {
     return mx + 256;
 }
 
-tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay) {
+tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G) {
     if (L < 1 || L > TG_MAX_L) return TG_E_L_RANGE;
     if (n < 0 || nnz < 0 || (nnz & 1)) return TG_E_INVALID_ARG;
     if (n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 32)) return TG_E_TOO_LARGE;
@@ -122,6 +122,10 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay) {
     y.off_HB = take(sizeof(uint64_t) * HUB_MAX * hw);
     y.off_hpre = take(sizeof(uint32_t) * HUB_MAX * hw);
     y.off_TM = take(sizeof(uint64_t) * TG_MAX_L * hw);
+    y.G = G;
+    y.off_node_graph = take(sizeof(int32_t) * (G > 0 ? n + 1 : 1));
+    y.off_ngraph = take(sizeof(int32_t) * (G > 0 ? n + 1 : 1));
+    y.off_gedge = take(sizeof(int64_t) * (G + 1));
     y.total = off;
     return TG_OK;
 }
@@ -160,6 +164,7 @@ void timing_mark(const char *name) {
 }  // namespace
 
 static tg_status status_from_bits(uint32_t bits) {
+    if (bits & (ST_BATCH | ST_CROSS_GRAPH)) return TG_E_BATCH;
     if (bits & ST_TYPE_RANGE) return TG_E_TYPE_RANGE;
     if (bits & (ST_COL_RANGE | ST_UNSORTED | ST_SELF_LOOP | ST_ASYMMETRIC)) return TG_E_NOT_SIMPLE;
     if (bits) return TG_E_INTERNAL;
@@ -175,7 +180,7 @@ static T *at(void *base, size_t off) {
 
 static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *types, int64_t n,
                      int64_t nnz, int L, uint64_t *per_edge, uint64_t *global_counts, void *ws,
-                     const Layout &y, hipStream_t st) {
+                     const Layout &y, hipStream_t st, const BatchIn *batch) {
     const int64_t m = y.m;
     const int LL = L * L;
     const int gw = tg_global_width(L);
@@ -214,15 +219,29 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     size_t stmp_bytes = y.sort_tmp_bytes;
     if (sort_tmp_bytes(n, nnz) > stmp_bytes) return TG_E_INTERNAL;
 
+    int32_t *node_graph = batch ? at<int32_t>(ws, y.off_node_graph) : nullptr;
+    int32_t *ngraph = batch ? at<int32_t>(ws, y.off_ngraph) : nullptr;
+    int64_t *gedge = at<int64_t>(ws, y.off_gedge);
+
     timing_reset(st);
     timing_mark("start");
     // status, counters and global accumulators start at zero
     HIPCHK(launch_fill_u64(reinterpret_cast<uint64_t *>(status), 0, 8, st));
     HIPCHK(launch_fill_u64(counters, 0, C_NUM, st));
-    HIPCHK(launch_fill_u64(gacc, 0, gw, st));
+    if (batch) HIPCHK(launch_fill_u64(global_counts, 0, batch->globals_len, st));
+    else HIPCHK(launch_fill_u64(gacc, 0, gw, st));
 
-    // ---- input checks: rows, degrees, the canonical edge numbering
-    HIPCHK(launch_check_rows(row_ptr, col, types, n, nnz, L, deg, ucount, status, st));
+    // ---- input checks: batch descriptor, rows, degrees, edge numbering
+    if (batch) {
+        HIPCHK(launch_batch_graphs(batch->node_ptr, batch->gL, batch->goff, batch->G, n, L,
+                                   batch->globals_len, node_graph, status, st));
+        uint32_t bst = 0;
+        HIPCHK(hipMemcpyAsync(&bst, status, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (bst) return status_from_bits(bst);
+    }
+    HIPCHK(launch_check_rows(row_ptr, col, types, n, nnz, L, deg, ucount, status, node_graph,
+                             batch ? batch->gL : nullptr, st));
     HIPCHK(rocprim::exclusive_scan(stmp, stmp_bytes, ucount, eoff, int64_t(0), (size_t)(n + 1),
                                    rocprim::plus<int64_t>(), st));
     struct {
@@ -235,12 +254,13 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     HIPCHK(hipStreamSynchronize(st));
     if (probe.status) return status_from_bits(probe.status);
     if (probe.upper != m) return TG_E_NOT_SIMPLE;
+    if (batch) HIPCHK(launch_batch_edges(batch->node_ptr, eoff, batch->G, gedge, st));
 
     // ---- relabel by (degree, id): rank order = internal id order
     HIPCHK(launch_node_keys(deg, n, key_a, st));
     HIPCHK(rocprim::radix_sort_keys(stmp, stmp_bytes, key_a, key_b, (size_t)n, 0, 64, st));
     HIPCHK(launch_relabel(key_b, types, deg, n, order, newid, ntype, ndeg, counters + C_HUB_CAND,
-                          st));
+                          node_graph, ngraph, st));
     HIPCHK(rocprim::exclusive_scan(stmp, stmp_bytes, ndeg, nrp, int64_t(0), (size_t)(n + 1),
                                    rocprim::plus<int64_t>(), st));
     const int bits = bits_for(n);
@@ -308,13 +328,25 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     ea.hist_in_lds = (size_t)gw * sizeof(uint64_t) <= 32768 ? 1 : 0;
     ea.heavy_list = le; ea.counters = counters; ea.tbuf = tbuf; ea.n = n; ea.status = status;
     ea.hub_base = hub_base; ea.Hw = Hw; ea.hstart = hstart; ea.HB = HB; ea.hpre = hpre; ea.TM = TM;
+    ea.batch = batch ? 1 : 0;
+    ea.ngraph = ngraph;
+    ea.gedge_ptr = gedge;
+    ea.gL = batch ? batch->gL : nullptr;
+    ea.goff = batch ? batch->goff : nullptr;
+    ea.G = batch ? batch->G : 1;
+    if (batch) ea.gacc = global_counts;
     unsigned edge_grid = (unsigned)(cus > 0 ? cus * 24 : 2048);
-    if ((int64_t)edge_grid > m) edge_grid = (unsigned)(m > 0 ? m : 1);
+    int64_t units = batch ? batch->G : m;
+    if ((int64_t)edge_grid > units) edge_grid = (unsigned)(units > 0 ? units : 1);
     HIPCHK(launch_edges(false, ea, edge_grid, st));
     timing_mark("edges_light");
-    HIPCHK(launch_edges(true, ea, (unsigned)y.heavy_edge_slots, st));
+    EdgeArgs eh = ea;
+    if (batch) eh.hist_in_lds = 0;  // heavy edges of many graphs: direct per-graph atomics
+    HIPCHK(launch_edges(true, eh, (unsigned)y.heavy_edge_slots, st));
     timing_mark("edges_heavy");
-    if (global_counts)
+    if (batch)
+        HIPCHK(launch_batch_finalize(global_counts, batch->gL, batch->goff, batch->G, status, st));
+    else if (global_counts)
         HIPCHK(launch_global_finalize(gacc, L, gw, global_counts, status, st));
     timing_mark("global");
 
@@ -330,7 +362,8 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     g_timing.stats[5] = (int64_t)cnt_host[C_WEDGES_A_HEAVY];
     g_timing.stats[6] = (int64_t)cnt_host[C_WEDGES_B_HEAVY];
     g_timing.stats[7] = (int64_t)cnt_host[C_TRI_SUM];
-    if (probe.status) return TG_E_INTERNAL;
+    if (probe.status) return status_from_bits(probe.status) == TG_OK ? TG_E_INTERNAL
+                                                                    : status_from_bits(probe.status);
     return TG_OK;
 }
 
@@ -351,6 +384,7 @@ const char *tg_status_str(tg_status s) {
         case TG_E_DEVICE: return "HIP error";
         case TG_E_INTERNAL: return "internal consistency check failed";
         case TG_E_TOO_LARGE: return "graph too large";
+        case TG_E_BATCH: return "inconsistent batch descriptor or an edge between two graphs";
     }
     return "unknown status";
 }
@@ -390,7 +424,32 @@ tg_status tg_count_typed_graphlets(const int64_t *row_ptr, const int32_t *col,
             return TG_E_DEVICE;
         return hipStreamSynchronize(st) == hipSuccess ? TG_OK : TG_E_DEVICE;
     }
-    return tg::run(row_ptr, col, types, n, nnz, L, per_edge, global_counts, workspace, y, st);
+    return tg::run(row_ptr, col, types, n, nnz, L, per_edge, global_counts, workspace, y, st,
+                   nullptr);
+}
+
+size_t tg_batch_workspace_bytes(int64_t n, int64_t nnz, int64_t G, int32_t L_max) {
+    tg::Layout y;
+    if (G < 1 || tg::plan_layout(n, nnz, L_max, &y, G) != TG_OK) return 0;
+    return y.total;
+}
+
+tg_status tg_count_batch(const int64_t *row_ptr, const int32_t *col, const uint8_t *types, int64_t n,
+                         int64_t nnz, const int64_t *graph_node_ptr, const int32_t *graph_L,
+                         int64_t G, int32_t L_max, const int64_t *graph_global_off,
+                         int64_t globals_len, uint64_t *per_edge, uint64_t *graph_globals,
+                         void *workspace, size_t ws_bytes, void *stream) {
+    if (G < 1) return TG_E_INVALID_ARG;
+    tg::Layout y;
+    tg_status s = tg::plan_layout(n, nnz, L_max, &y, G);
+    if (s != TG_OK) return s;
+    if (!row_ptr || !types || !graph_node_ptr || !graph_L || !graph_global_off || !graph_globals ||
+        !workspace || (nnz > 0 && !col) || n < 1 || globals_len < 1)
+        return TG_E_INVALID_ARG;
+    if (ws_bytes < y.total) return TG_E_WORKSPACE;
+    tg::BatchIn b{graph_node_ptr, graph_L, graph_global_off, G, globals_len};
+    return tg::run(row_ptr, col, types, n, nnz, L_max, per_edge, graph_globals, workspace, y,
+                   reinterpret_cast<hipStream_t>(stream), &b);
 }
 
 tg_status tg_key_describe(int32_t L, int32_t c, int32_t *orbit, int32_t *t, int32_t *t2) {

@@ -63,10 +63,37 @@ __global__ void k_hub_types(const uint8_t *__restrict__ ntype, int64_t n, int H,
     TM[idx] = m;
 }
 
-__device__ __forceinline__ void hist_add(const EdgeArgs &a, uint64_t *hist, int idx, uint64_t v) {
+// Index of global entry idx (layout of L types) in the layout of Lg <= L
+// types, or -1 if the entry involves a type >= Lg.  Co-lexicographic ranks
+// of multisets over {0..Lg-1} are the same in both layouts.
+__device__ __forceinline__ int remap_global(int idx, int L, int Lg) {
+    int n2 = (int)binom_small(L + 1, 2), n3 = (int)binom_small(L + 2, 3),
+        n4 = (int)binom_small(L + 3, 4);
+    int m2 = (int)binom_small(Lg + 1, 2), m3 = (int)binom_small(Lg + 2, 3),
+        m4 = (int)binom_small(Lg + 3, 4);
+    if (idx < n2) return idx < m2 ? idx : -1;
+    idx -= n2;
+    if (idx < n3) return idx < m3 ? m2 + idx : -1;
+    idx -= n3;
+    if (idx < n3) return idx < m3 ? m2 + m3 + idx : -1;
+    idx -= n3;
+    int h = idx / n4, r = idx - h * n4;
+    return r < m4 ? m2 + 2 * m3 + h * m4 + r : -1;
+}
+
+// Add v to global entry idx of the edge's graph g (always 0 for one graph).
+__device__ __forceinline__ void hist_add(const EdgeArgs &a, uint64_t *hist, int idx, uint64_t v,
+                                         int64_t g) {
     if (!v) return;
-    if (a.hist_in_lds) atomicAdd((unsigned long long *)&hist[idx], (unsigned long long)v);
-    else atomicAdd((unsigned long long *)&a.gacc[idx], (unsigned long long)v);
+    if (a.hist_in_lds) {
+        atomicAdd((unsigned long long *)&hist[idx], (unsigned long long)v);
+    } else if (a.batch) {
+        int j = remap_global(idx, a.L, a.gL[g]);
+        if (j < 0) atomicOr(a.status, ST_INTERNAL);
+        else atomicAdd((unsigned long long *)&a.gacc[a.goff[g] + j], (unsigned long long)v);
+    } else {
+        atomicAdd((unsigned long long *)&a.gacc[idx], (unsigned long long)v);
+    }
 }
 
 template <int NT>
@@ -321,6 +348,7 @@ __device__ void edge_cliques(const EdgeArgs &a, const EdgeShared &S, int tid) {
 template <int NT>
 __device__ void edge_derive(const EdgeArgs &a, int64_t e, int32_t i, int32_t j, const EdgeShared &S,
                             uint64_t *hist, int tid, uint32_t &bad) {
+    const int64_t gid = a.batch ? (int64_t)a.ngraph[i] : 0;
     const int L = a.L;
     const uint64_t *Xi = S.Xi, *Xj = S.Xj, *Y = S.Y, *K = S.K;
     const int ta = a.ntype[i], tb = a.ntype[j];
@@ -338,7 +366,7 @@ __device__ void edge_derive(const EdgeArgs &a, int64_t e, int32_t i, int32_t j, 
     const int n3 = (int)binom_small(L + 2, 3);
     const int n4 = (int)binom_small(L + 3, 4);
 
-    if (tid == 0) hist_add(a, hist, rank2(ta, tb), 1);
+    if (tid == 0) hist_add(a, hist, rank2(ta, tb), 1, gid);
     for (int t = tid; t < L; t += NT) {
         int64_t nTt = tri_e[t];
         int64_t si = (int64_t)di[t] - nTt - (tb == t);
@@ -349,8 +377,8 @@ __device__ void edge_derive(const EdgeArgs &a, int64_t e, int32_t i, int32_t j, 
             row[L + t] = (uint64_t)(si + sj);
         }
         int r3 = rank3(ta, tb, t);
-        hist_add(a, hist, n2 + r3, (uint64_t)(si + sj));
-        hist_add(a, hist, n2 + n3 + r3, (uint64_t)nTt);
+        hist_add(a, hist, n2 + r3, (uint64_t)(si + sj), gid);
+        hist_add(a, hist, n2 + n3 + r3, (uint64_t)nTt, gid);
     }
     for (int p = tid; p < P; p += NT) {
         // pair (t, u), t <= u, from its lexicographic index
@@ -430,7 +458,7 @@ __device__ void edge_derive(const EdgeArgs &a, int64_t e, int32_t i, int32_t j, 
             if (g[o] < 0) bad |= ST_INTERNAL;
             uint64_t v = (uint64_t)g[o];
             if (row) row[2 * L + (o - 3) * P + p] = v;
-            hist_add(a, hist, n2 + 2 * n3 + (hof[o] - 3) * n4 + r4, v);
+            hist_add(a, hist, n2 + 2 * n3 + (hof[o] - 3) * n4 + r4, v, gid);
         }
     }
 }
@@ -471,23 +499,45 @@ __global__ void __launch_bounds__(64) k_edges_light(EdgeArgs a) {
     if (a.hist_in_lds)
         for (int q = lane; q < a.gw; q += WAVE) hist[q] = 0;
     __syncthreads();
-    for (int64_t e = blockIdx.x; e < a.m; e += gridDim.x) {
+    auto one_edge = [&](int64_t e) {
         int32_t i = a.ei[e], j = a.ej[e];
         int64_t di = a.nrp[i + 1] - a.nrp[i], dj = a.nrp[j + 1] - a.nrp[j];
         if ((di < dj ? di : dj) > TCAP) {
             if (lane == 0)
                 a.heavy_list[atomicAdd((unsigned long long *)&a.counters[C_EDGE_HEAVY], 1ull)] =
                     (uint32_t)e;
-            continue;
+            return;
         }
         edge_build<WAVE>(a, i, j, S, lane);
         edge_cliques<WAVE>(a, S, lane);
         edge_derive<WAVE>(a, e, i, j, S, hist, lane, bad);
         __syncthreads();
+    };
+    if (!a.batch) {
+        for (int64_t e = blockIdx.x; e < a.m; e += gridDim.x) one_edge(e);
+        if (a.hist_in_lds)
+            for (int q = lane; q < a.gw; q += WAVE)
+                if (hist[q]) atomicAdd((unsigned long long *)&a.gacc[q], (unsigned long long)hist[q]);
+    } else {
+        // whole graphs per workgroup; the histogram is flushed into the
+        // graph's own vector after its last edge
+        for (int64_t g = blockIdx.x; g < a.G; g += gridDim.x) {
+            for (int64_t e = a.gedge_ptr[g]; e < a.gedge_ptr[g + 1]; ++e) one_edge(e);
+            if (a.hist_in_lds) {
+                const int Lg = a.gL[g];
+                uint64_t *dst = a.gacc + a.goff[g];
+                for (int q = lane; q < a.gw; q += WAVE) {
+                    uint64_t v = hist[q];
+                    if (!v) continue;
+                    int jq = remap_global(q, a.L, Lg);
+                    if (jq < 0) bad |= ST_INTERNAL;
+                    else atomicAdd((unsigned long long *)&dst[jq], (unsigned long long)v);
+                    hist[q] = 0;
+                }
+                __syncthreads();
+            }
+        }
     }
-    if (a.hist_in_lds)
-        for (int q = lane; q < a.gw; q += WAVE)
-            if (hist[q]) atomicAdd((unsigned long long *)&a.gacc[q], (unsigned long long)hist[q]);
     bad = wave_or(bad);
     if (lane == 0 && bad) atomicOr(a.status, bad);
 }

@@ -19,6 +19,8 @@ enum : uint32_t {
     ST_ASYMMETRIC = 1u << 4,
     ST_INTERNAL = 1u << 5,
     ST_NOT_DIVISIBLE = 1u << 6,
+    ST_BATCH = 1u << 7,       // inconsistent batch descriptor
+    ST_CROSS_GRAPH = 1u << 8, // an edge joins two graphs of a batch
 };
 
 // Tunables of the cycle and clique passes.
@@ -47,6 +49,8 @@ struct Layout {
     size_t off_listA_light, off_listA_heavy, off_listB_light, off_listB_heavy, off_list_edge;
     size_t off_maps, off_tbuf, off_gacc, off_sort_tmp;
     size_t off_hstart, off_HB, off_hpre, off_TM;
+    size_t off_node_graph, off_ngraph, off_gedge;   // batched graphs only
+    int64_t G;
     size_t total;
 };
 
@@ -58,7 +62,16 @@ enum Counter {
     C_NUM
 };
 
-tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay);
+tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G = 0);
+
+// Batch descriptor (device pointers) of tg_count_batch.
+struct BatchIn {
+    const int64_t *node_ptr;   // [G+1]
+    const int32_t *gL;         // [G]
+    const int64_t *goff;       // [G+1]
+    int64_t G;
+    int64_t globals_len;
+};
 
 // Arguments of the 4-cycle passes.
 struct CycleArgs {
@@ -106,17 +119,33 @@ struct EdgeArgs {
     const uint64_t *HB;          // [H][Hw] hub adjacency bits
     const uint32_t *hpre;        // [H][Hw] exclusive prefix popcounts
     const uint64_t *TM;          // [L][Hw] hubs of each type
+    // batched graphs: per-graph global vectors at goff[g], in graph g's own
+    // L layout; the kernels compute in the layout of L (= max over graphs)
+    int batch;
+    const int32_t *ngraph;       // internal node -> graph
+    const int64_t *gedge_ptr;    // [G+1] canonical edge range of each graph
+    const int32_t *gL;           // [G]
+    const int64_t *goff;         // [G+1]
+    int64_t G;
 };
 
 // Launch wrappers (tg_kernels.hip).
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t st);
 hipError_t launch_check_rows(const int64_t *rp, const int32_t *col, const uint8_t *types, int64_t n,
                              int64_t nnz, int L, uint32_t *deg, int64_t *ucount, uint32_t *status,
-                             hipStream_t st);
+                             const int32_t *node_graph, const int32_t *gL, hipStream_t st);
+hipError_t launch_batch_graphs(const int64_t *node_ptr, const int32_t *gL, const int64_t *goff,
+                               int64_t G, int64_t n, int L_max, int64_t globals_len,
+                               int32_t *node_graph, uint32_t *status, hipStream_t st);
+hipError_t launch_batch_edges(const int64_t *node_ptr, const int64_t *eoff, int64_t G,
+                              int64_t *gedge_ptr, hipStream_t st);
+hipError_t launch_batch_finalize(uint64_t *globals, const int32_t *gL, const int64_t *goff, int64_t G,
+                                 uint32_t *status, hipStream_t st);
 hipError_t launch_node_keys(const uint32_t *deg, int64_t n, uint64_t *keys, hipStream_t st);
 hipError_t launch_relabel(const uint64_t *sorted, const uint8_t *types, const uint32_t *deg, int64_t n,
                           int32_t *order, int32_t *newid, uint8_t *ntype, int64_t *ndeg,
-                          uint64_t *hub_cand, hipStream_t st);
+                          uint64_t *hub_cand, const int32_t *node_graph, int32_t *ngraph,
+                          hipStream_t st);
 hipError_t launch_slot_keys(const int64_t *rp, const int32_t *col, const int64_t *ucount,
                             const int64_t *eoff, const int32_t *newid, int64_t n, int bits,
                             uint64_t *keys, uint32_t *vals, int32_t *ei, int32_t *ej,

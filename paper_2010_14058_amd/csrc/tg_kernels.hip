@@ -35,7 +35,8 @@ __global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t count) {
 __global__ void k_check_rows(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
                              const uint8_t *__restrict__ types, int64_t n, int64_t nnz, int L,
                              uint32_t *__restrict__ deg, int64_t *__restrict__ ucount,
-                             uint32_t *__restrict__ status) {
+                             uint32_t *__restrict__ status, const int32_t *__restrict__ node_graph,
+                             const int32_t *__restrict__ gL) {
     int64_t u = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
     int lane = lane_id();
     if (u > n) return;
@@ -54,9 +55,11 @@ __global__ void k_check_rows(const int64_t *__restrict__ rp, const int32_t *__re
         return;
     }
     uint64_t up = 0;
+    const int32_t gu = node_graph ? node_graph[u] : 0;
     for (int64_t s = b + lane; s < e; s += WAVE) {
         int32_t x = col[s];
         if (x < 0 || x >= n) bad |= ST_COL_RANGE;
+        else if (node_graph && node_graph[x] != gu) bad |= ST_CROSS_GRAPH;
         if (x == u) bad |= ST_SELF_LOOP;
         if (s > b && col[s - 1] >= x) bad |= ST_UNSORTED;
         if (x > u) ++up;
@@ -64,10 +67,64 @@ __global__ void k_check_rows(const int64_t *__restrict__ rp, const int32_t *__re
     up = wave_sum_u64(up);
     bad = wave_or(bad);
     if (lane == 0) {
-        if (types[u] >= L) bad |= ST_TYPE_RANGE;
+        if (types[u] >= (node_graph ? gL[gu] : L)) bad |= ST_TYPE_RANGE;
         deg[u] = (uint32_t)(e - b);
         ucount[u] = (int64_t)up;
         if (bad) atomicOr(status, bad);
+    }
+}
+
+// Batch descriptor checks (one thread per graph) and the node -> graph map
+// (one wave per graph, written only for a consistent descriptor).
+__global__ void k_batch_graphs(const int64_t *__restrict__ node_ptr, const int32_t *__restrict__ gL,
+                               const int64_t *__restrict__ goff, int64_t G, int64_t n, int L_max,
+                               int64_t globals_len, int32_t *__restrict__ node_graph,
+                               uint32_t *__restrict__ status) {
+    int64_t g = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
+    int lane = lane_id();
+    if (g >= G) return;
+    int64_t a = node_ptr[g], b = node_ptr[g + 1];
+    int Lg = gL[g];
+    bool ok = a >= 0 && b >= a && b <= n && Lg >= 1 && Lg <= L_max;
+    if (g == 0 && (a != 0 || goff[0] != 0)) ok = false;
+    if (g == G - 1 && (b != n || goff[G] != globals_len)) ok = false;
+    if (ok) {
+        int64_t w = binom_small(Lg + 1, 2) + 2 * binom_small(Lg + 2, 3) + 6 * binom_small(Lg + 3, 4);
+        if (goff[g + 1] - goff[g] != w) ok = false;
+    }
+    if (!ok) {
+        if (lane == 0) atomicOr(status, ST_BATCH);
+        return;
+    }
+    for (int64_t v = a + lane; v < b; v += WAVE) node_graph[v] = (int32_t)g;
+}
+
+__global__ void k_batch_edges(const int64_t *__restrict__ node_ptr, const int64_t *__restrict__ eoff,
+                              int64_t G, int64_t *__restrict__ gedge_ptr) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g <= G) gedge_ptr[g] = eoff[node_ptr[g]];
+}
+
+// Per-graph global vectors: divide each graphlet block by its edge count.
+__global__ void k_batch_finalize(uint64_t *__restrict__ glob, const int32_t *__restrict__ gL,
+                                 const int64_t *__restrict__ goff, int64_t G,
+                                 uint32_t *__restrict__ status) {
+    const uint64_t E[9] = {1, 2, 3, 3, 3, 4, 4, 5, 6};
+    for (int64_t g = blockIdx.x; g < G; g += gridDim.x) {
+        int Lg = gL[g];
+        int n2 = (int)binom_small(Lg + 1, 2), n3 = (int)binom_small(Lg + 2, 3),
+            n4 = (int)binom_small(Lg + 3, 4);
+        int gw = n2 + 2 * n3 + 6 * n4;
+        uint64_t *v = glob + goff[g];
+        for (int q = threadIdx.x; q < gw; q += blockDim.x) {
+            int h;
+            if (q < n2) h = 0;
+            else if (q < n2 + n3) h = 1;
+            else if (q < n2 + 2 * n3) h = 2;
+            else h = 3 + (q - n2 - 2 * n3) / n4;
+            if (v[q] % E[h]) atomicOr(status, ST_NOT_DIVISIBLE);
+            v[q] /= E[h];
+        }
     }
 }
 
@@ -81,12 +138,14 @@ __global__ void k_relabel(const uint64_t *__restrict__ sorted, const uint8_t *__
                           const uint32_t *__restrict__ deg, int64_t n,
                           int32_t *__restrict__ order, int32_t *__restrict__ newid,
                           uint8_t *__restrict__ ntype, int64_t *__restrict__ ndeg,
-                          uint64_t *__restrict__ hub_cand) {
+                          uint64_t *__restrict__ hub_cand, const int32_t *__restrict__ node_graph,
+                          int32_t *__restrict__ ngraph) {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool cand = false;
     if (r < n) {
         int32_t v = (int32_t)(sorted[r] & 0xffffffffu);
         order[r] = v;
+        if (node_graph) ngraph[r] = node_graph[v];
         newid[v] = (int32_t)r;
         ntype[r] = types[v];
         ndeg[r] = deg[v];
@@ -586,8 +645,9 @@ hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s
 
 hipError_t launch_check_rows(const int64_t *rp, const int32_t *col, const uint8_t *types, int64_t n,
                              int64_t nnz, int L, uint32_t *deg, int64_t *ucount, uint32_t *status,
-                             hipStream_t st) {
-    k_check_rows<<<blocks_for(n + 1, 4), 256, 0, st>>>(rp, col, types, n, nnz, L, deg, ucount, status);
+                             const int32_t *node_graph, const int32_t *gL, hipStream_t st) {
+    k_check_rows<<<blocks_for(n + 1, 4), 256, 0, st>>>(rp, col, types, n, nnz, L, deg, ucount, status,
+                                                       node_graph, gL);
     LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -600,9 +660,11 @@ hipError_t launch_node_keys(const uint32_t *deg, int64_t n, uint64_t *keys, hipS
 
 hipError_t launch_relabel(const uint64_t *sorted, const uint8_t *types, const uint32_t *deg, int64_t n,
                           int32_t *order, int32_t *newid, uint8_t *ntype, int64_t *ndeg,
-                          uint64_t *hub_cand, hipStream_t st) {
+                          uint64_t *hub_cand, const int32_t *node_graph, int32_t *ngraph,
+                          hipStream_t st) {
     k_relabel<<<blocks_for(n > 0 ? n : 1, 256), 256, 0, st>>>(sorted, types, deg, n, order, newid,
-                                                              ntype, ndeg, hub_cand);
+                                                              ntype, ndeg, hub_cand, node_graph,
+                                                              ngraph);
     LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -683,6 +745,32 @@ hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned g
 hipError_t launch_global_finalize(const uint64_t *gacc, int L, int gw, uint64_t *out, uint32_t *status,
                                   hipStream_t st) {
     k_global_finalize<<<blocks_for(gw, 256), 256, 0, st>>>(gacc, L, out, status);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_batch_graphs(const int64_t *node_ptr, const int32_t *gL, const int64_t *goff,
+                               int64_t G, int64_t n, int L_max, int64_t globals_len,
+                               int32_t *node_graph, uint32_t *status, hipStream_t st) {
+    if (G <= 0) return hipSuccess;
+    k_batch_graphs<<<blocks_for(G, 4), 256, 0, st>>>(node_ptr, gL, goff, G, n, L_max, globals_len,
+                                                     node_graph, status);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_batch_edges(const int64_t *node_ptr, const int64_t *eoff, int64_t G,
+                              int64_t *gedge_ptr, hipStream_t st) {
+    k_batch_edges<<<blocks_for(G + 1, 256), 256, 0, st>>>(node_ptr, eoff, G, gedge_ptr);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_batch_finalize(uint64_t *globals, const int32_t *gL, const int64_t *goff, int64_t G,
+                                 uint32_t *status, hipStream_t st) {
+    if (G <= 0) return hipSuccess;
+    unsigned grid = (unsigned)(G < 8192 ? G : 8192);
+    k_batch_finalize<<<grid, 256, 0, st>>>(globals, gL, goff, G, status);
     LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -7,6 +7,7 @@ it without sharing any of the method's code.
 
 from .graphs import (  # noqa: F401
     Graph,
+    GraphBatch,
     csr_from_edges,
     er_graph,
     chung_lu_typed,

@@ -294,31 +294,78 @@ def config_graph(k: int, seed: int = 0, scale: float = 1.0) -> Graph:
     raise ValueError(f"config {k} is not a single graph")
 
 
-def batch_graphs(num_graphs: int = 100_000, seed: int = 0, beta: float = 2.5):
-    """Many small typed Chung-Lu graphs (the batched configuration).
+@dataclasses.dataclass
+class GraphBatch:
+    """Many typed graphs as one disjoint-union CSR.
 
-    n_g = clip(round(exp(N(4, 1))), 10, 500); average degree ~ U(4, 12);
-    Chung-Lu within each graph with exponent ``beta`` and largest weight
-    2 * sqrt(n_g * dbar_g); L_g ~ U{4..8}; types uniform in [0, L_g).
-    Graph g draws from child g of the seed sequence.
+    Graph g owns nodes [node_ptr[g], node_ptr[g+1]) and types in [0, L[g]);
+    no edge joins two graphs.  ``union.L`` is max(L).
     """
-    children = np.random.SeedSequence(seed).spawn(num_graphs)
-    out = []
-    for g in range(num_graphs):
-        rng = np.random.default_rng(children[g])
-        n = int(np.clip(round(math.exp(rng.normal(4.0, 1.0))), 10, 500))
-        dbar = float(rng.uniform(4.0, 12.0))
-        L = int(rng.integers(4, 9))
-        wmax = min(2.0 * math.sqrt(n * dbar), n - 1.0)
-        w = _power_weights(n, beta, dbar, max(wmax, dbar * 1.01))
-        m_draw = int(round(n * dbar / 2))
-        cdf = np.cumsum(w)
-        u = _draw(rng, cdf, m_draw)
-        v = _draw(rng, cdf, m_draw)
-        row_ptr, col = csr_from_edges(n, u, v)
-        types = rng.integers(0, L, size=n).astype(np.uint8)
-        out.append(Graph(row_ptr, col, types, L, f"batch_g{g}"))
-    return out
+    union: Graph
+    node_ptr: np.ndarray  # int64 [G+1]
+    L: np.ndarray         # int32 [G]
+
+    @property
+    def G(self) -> int:
+        return int(self.L.shape[0])
+
+    def edge_ptr(self) -> np.ndarray:
+        """Edge id range of each graph in the union's canonical edge order."""
+        d = self.union.degrees()
+        src = np.repeat(np.arange(self.union.n, dtype=np.int64), d)
+        upper = np.bincount(src[self.union.col > src], minlength=self.union.n)
+        eoff = np.concatenate([[0], np.cumsum(upper)])
+        return eoff[self.node_ptr]
+
+    def graph(self, g: int) -> Graph:
+        """Graph g on its own (node ids shifted to start at 0)."""
+        a, b = int(self.node_ptr[g]), int(self.node_ptr[g + 1])
+        rp = self.union.row_ptr[a:b + 1] - self.union.row_ptr[a]
+        col = self.union.col[self.union.row_ptr[a]:self.union.row_ptr[b]] - a
+        return Graph(rp.astype(np.int64), col.astype(np.int32), self.union.types[a:b].copy(),
+                     int(self.L[g]), f"batch_g{g}")
+
+
+def batch_graphs(num_graphs: int = 100_000, seed: int = 0, beta: float = 2.5) -> GraphBatch:
+    """The batched configuration: many small typed Chung-Lu graphs.
+
+    n_g = clip(round(exp(N(4, 1))), 10, 500); average degree dbar_g ~ U(4, 12);
+    L_g ~ U{4..8}; types uniform in [0, L_g).  Inside each graph, Chung-Lu
+    with weights proportional to (v+1)^(-1/(beta-1)) scaled to mean dbar_g
+    and capped at 2 sqrt(n_g dbar_g); round(n_g dbar_g / 2) endpoint pairs
+    drawn proportional to weight, self-loops and repeats dropped.  All graphs
+    draw from one seeded stream, vectorised over graphs.
+    """
+    r_par, r_w, r_e, r_t = _rngs(seed, 4)
+    del r_w
+    n = np.clip(np.round(np.exp(r_par.normal(4.0, 1.0, size=num_graphs))), 10, 500).astype(np.int64)
+    dbar = r_par.uniform(4.0, 12.0, size=num_graphs)
+    L = r_par.integers(4, 9, size=num_graphs).astype(np.int32)
+    node_ptr = np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+    N = int(node_ptr[-1])
+    gid = np.repeat(np.arange(num_graphs), n)
+    local = np.arange(N, dtype=np.int64) - node_ptr[gid]
+    a = 1.0 / (beta - 1.0)
+    w = (local + 1.0) ** (-a)
+    mean_w = np.add.reduceat(w, node_ptr[:-1]) / n
+    w = w * (dbar / mean_w)[gid]
+    wmax = 2.0 * np.sqrt(n * dbar)
+    w = np.minimum(w, wmax[gid])
+    cdf = np.cumsum(w)
+    start = np.concatenate([[0.0], cdf[node_ptr[1:-1] - 1]])
+    mass = cdf[node_ptr[1:] - 1] - start
+    m_draw = np.round(n * dbar / 2).astype(np.int64)
+    eg = np.repeat(np.arange(num_graphs), m_draw)
+    def pick():
+        x = start[eg] + r_e.random(eg.shape[0]) * mass[eg]
+        v = np.searchsorted(cdf, x, side="right")
+        return np.clip(v, node_ptr[eg], node_ptr[eg + 1] - 1)
+    u = pick()
+    v = pick()
+    row_ptr, col = csr_from_edges(N, u, v)
+    types = np.floor(r_t.random(N) * L[gid]).astype(np.uint8)
+    union = Graph(row_ptr, col, types, int(L.max()), f"batch_{num_graphs}")
+    return GraphBatch(union, node_ptr, L)
 
 
 def serving_requests(num_requests: int, rate: float = 2000.0, seed: int = 0,
