@@ -336,7 +336,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     ea.G = batch ? batch->G : 1;
     if (batch) ea.gacc = global_counts;
     unsigned edge_grid = (unsigned)(cus > 0 ? cus * 24 : 2048);
-    int64_t units = batch ? batch->G : m;
+    int64_t units = batch ? (m + BATCH_EDGE_CHUNK - 1) / BATCH_EDGE_CHUNK : m;
     if ((int64_t)edge_grid > units) edge_grid = (unsigned)(units > 0 ? units : 1);
     HIPCHK(launch_edges(false, ea, edge_grid, st));
     timing_mark("edges_light");

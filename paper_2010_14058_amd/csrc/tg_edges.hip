@@ -519,23 +519,37 @@ __global__ void __launch_bounds__(64) k_edges_light(EdgeArgs a) {
             for (int q = lane; q < a.gw; q += WAVE)
                 if (hist[q]) atomicAdd((unsigned long long *)&a.gacc[q], (unsigned long long)hist[q]);
     } else {
-        // whole graphs per workgroup; the histogram is flushed into the
-        // graph's own vector after its last edge
-        for (int64_t g = blockIdx.x; g < a.G; g += gridDim.x) {
-            for (int64_t e = a.gedge_ptr[g]; e < a.gedge_ptr[g + 1]; ++e) one_edge(e);
-            if (a.hist_in_lds) {
-                const int Lg = a.gL[g];
-                uint64_t *dst = a.gacc + a.goff[g];
-                for (int q = lane; q < a.gw; q += WAVE) {
-                    uint64_t v = hist[q];
-                    if (!v) continue;
-                    int jq = remap_global(q, a.L, Lg);
-                    if (jq < 0) bad |= ST_INTERNAL;
-                    else atomicAdd((unsigned long long *)&dst[jq], (unsigned long long)v);
-                    hist[q] = 0;
-                }
-                __syncthreads();
+        // chunks of consecutive edges (the edges of one graph are
+        // contiguous); the histogram is flushed into a graph's own vector
+        // whenever the graph changes and at the end of each chunk
+        auto flush = [&](int64_t g) {
+            if (!a.hist_in_lds) return;
+            const int Lg = a.gL[g];
+            uint64_t *dst = a.gacc + a.goff[g];
+            for (int q = lane; q < a.gw; q += WAVE) {
+                uint64_t v = hist[q];
+                if (!v) continue;
+                int jq = remap_global(q, a.L, Lg);
+                if (jq < 0) bad |= ST_INTERNAL;
+                else atomicAdd((unsigned long long *)&dst[jq], (unsigned long long)v);
+                hist[q] = 0;
             }
+            __syncthreads();
+        };
+        const int64_t nchunks = (a.m + BATCH_EDGE_CHUNK - 1) / BATCH_EDGE_CHUNK;
+        for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+            int64_t e0 = c * BATCH_EDGE_CHUNK;
+            int64_t e1 = e0 + BATCH_EDGE_CHUNK < a.m ? e0 + BATCH_EDGE_CHUNK : a.m;
+            int64_t cur = a.ngraph[a.ei[e0]];
+            for (int64_t e = e0; e < e1; ++e) {
+                int64_t g = a.ngraph[a.ei[e]];
+                if (g != cur) {
+                    flush(cur);
+                    cur = g;
+                }
+                one_edge(e);
+            }
+            flush(cur);
         }
     }
     bad = wave_or(bad);

@@ -30,6 +30,7 @@ constexpr int HEAVY_THREADS = 256;    // threads of a heavy-group workgroup
 constexpr int HEAVY_CHUNK = 128;      // items staged per round in the heavy path
 constexpr int TCAP = 1024;            // triangle set kept in LDS by the light edge kernel
 constexpr int EDGE_THREADS_HEAVY = 256;
+constexpr int64_t BATCH_EDGE_CHUNK = 256;  // consecutive edges per work item in batches
 constexpr int HUB_DMIN = 32;          // smallest degree of a hub-core node
 constexpr int HUB_MAX = 8192;         // largest hub core (bit-matrix HUB_MAX^2 bits)
 
