@@ -123,6 +123,15 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G) {
     y.off_hpre = take(sizeof(uint32_t) * HUB_MAX * hw);
     y.off_TM = take(sizeof(uint64_t) * TG_MAX_L * hw);
     y.G = G;
+    {
+        const int64_t nw = (n + 63) / 64;
+        const size_t per_sh = (size_t)nw * (sizeof(uint64_t) + sizeof(uint32_t));
+        int64_t shm = (int64_t)(SH_BUDGET / (per_sh > 0 ? per_sh : 1));
+        if (shm > SH_MAX) shm = SH_MAX;
+        y.sh_max = (int)shm;
+        y.off_SB = take(sizeof(uint64_t) * (size_t)nw * (size_t)(shm > 0 ? shm : 1));
+        y.off_SP = take(sizeof(uint32_t) * (size_t)nw * (size_t)(shm > 0 ? shm : 1));
+    }
     y.off_node_graph = take(sizeof(int32_t) * (G > 0 ? n + 1 : 1));
     y.off_ngraph = take(sizeof(int32_t) * (G > 0 ? n + 1 : 1));
     y.off_gedge = take(sizeof(int64_t) * (G + 1));
@@ -267,14 +276,22 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     HIPCHK(launch_slot_keys(row_ptr, col, ucount, eoff, newid, n, bits, key_a, val_a, ei, ej, status,
                             st));
     HIPCHK(hipMemcpyAsync(&probe.status, status, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    uint64_t hub_cand = 0;
-    HIPCHK(hipMemcpyAsync(&hub_cand, counters + C_HUB_CAND, sizeof(uint64_t), hipMemcpyDeviceToHost,
+    uint64_t cand[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(cand, counters + C_HUB_CAND, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost,
                           st));
     HIPCHK(hipStreamSynchronize(st));
     if (probe.status) return status_from_bits(probe.status);
     // hub core: the highest-ranked nodes of degree >= HUB_DMIN, at most HUB_MAX
+    const uint64_t hub_cand = cand[0], sh_cand = cand[1];
     const int H = (int)(hub_cand < (uint64_t)HUB_MAX ? hub_cand : (uint64_t)HUB_MAX);
-    const int Hw = (H + 63) / 64;
+    // super-hubs: the highest-ranked nodes of degree >= SH_DMIN that fit
+    const int S = (int)(sh_cand < (uint64_t)y.sh_max ? sh_cand : (uint64_t)y.sh_max);
+    const int32_t sh_base = (int32_t)(n - S);
+    const int64_t nw = (n + 63) / 64;
+    uint64_t *SB = at<uint64_t>(ws, y.off_SB);
+    uint32_t *SP = at<uint32_t>(ws, y.off_SP);
+    // bit rows padded to whole 64-byte blocks (8 words) for vector loads
+    const int Hw = H > 0 ? (((H + 63) / 64 + 7) / 8) * 8 : 0;
     const int32_t hub_base = (int32_t)(n - H);
     HIPCHK(rocprim::radix_sort_pairs(stmp, stmp_bytes, key_a, key_b, val_a, val_b, (size_t)nnz, 0,
                                      2 * bits, st));
@@ -285,10 +302,12 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     uint64_t *TM = at<uint64_t>(ws, y.off_TM);
     HIPCHK(launch_tdeg(nrp, ncol, ntype, n, L, hub_base, tdeg, hstart, st));
     HIPCHK(launch_hub_build(nrp, ncol, hstart, ntype, n, H, Hw, L, HB, hpre, TM, st));
+    HIPCHK(launch_superhubs(nrp, ncol, n, S, nw, SB, SP, st));
     timing_mark("prep");
 
     // ---- typed triangles and node aggregates
-    HIPCHK(launch_tri(nrp, ncol, ntype, ei, ej, m, L, tri, counters + C_TRI_SUM, st));
+    HIPCHK(launch_tri(nrp, ncol, ntype, ei, ej, m, L, tri, counters + C_TRI_SUM, sh_base, nw, SB,
+                      st));
     timing_mark("tri");
     HIPCHK(launch_node_aggr(nrp, ncol, ntype, neid, tri, tdeg, n, L, A, D, st));
     timing_mark("aggr");
@@ -328,6 +347,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     ea.hist_in_lds = (size_t)gw * sizeof(uint64_t) <= 32768 ? 1 : 0;
     ea.heavy_list = le; ea.counters = counters; ea.tbuf = tbuf; ea.n = n; ea.status = status;
     ea.hub_base = hub_base; ea.Hw = Hw; ea.hstart = hstart; ea.HB = HB; ea.hpre = hpre; ea.TM = TM;
+    ea.sh_base = sh_base; ea.nw = nw; ea.SB = SB; ea.SP = SP;
     ea.batch = batch ? 1 : 0;
     ea.ngraph = ngraph;
     ea.gedge_ptr = gedge;

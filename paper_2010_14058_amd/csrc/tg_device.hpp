@@ -101,4 +101,17 @@ static __device__ __forceinline__ int rank4(int a, int b, int c, int d) {
                  binom_small(d + 3, 4));
 }
 
+// Super-hub bitmap probes: bit of node x in the bitmap of super-hub index s,
+// and the slot of x inside the super-hub's (sorted) row.
+static __device__ __forceinline__ bool sh_bit(const uint64_t *SB, int64_t nw, int s, int32_t x) {
+    return (SB[(size_t)s * nw + (x >> 6)] >> (x & 63)) & 1ull;
+}
+
+static __device__ __forceinline__ int64_t sh_slot(const uint64_t *SB, const uint32_t *SP, int64_t nw,
+                                                  int64_t row_begin, int s, int32_t x) {
+    size_t o = (size_t)s * nw + (x >> 6);
+    uint64_t below = (x & 63) ? (SB[o] & ((1ull << (x & 63)) - 1)) : 0ull;
+    return row_begin + SP[o] + (uint32_t)__popcll(below);
+}
+
 }  // namespace tg

@@ -183,11 +183,15 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
     const int64_t ib = a.nrp[i], ie = a.nrp[i + 1], jb = a.nrp[j], je = a.nrp[j + 1];
     const int64_t ih = a.hstart[i], jh = a.hstart[j];
 
-    // low members: probe the shorter low prefix in the longer one
+    // low members: walk the shorter low prefix, test each node against the
+    // other endpoint (its super-hub bitmap, else a binary search)
     {
         bool i_small = (ih - ib) <= (jh - jb);
         int64_t sb = i_small ? ib : jb, se = i_small ? ih : jh;
         int64_t lb = i_small ? jb : ib, le = i_small ? jh : ih;
+        const int32_t other = i_small ? j : i;
+        const bool probe = other >= a.sh_base;
+        const int so = other - a.sh_base;
         uint32_t count = 0;
         for (int64_t p0 = sb; p0 < se; p0 += NT) {
             int64_t p = p0 + tid;
@@ -196,8 +200,13 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
             int32_t x = 0;
             if (p < se) {
                 x = a.ncol[p];
-                q = lower_bound(a.ncol, lb, le, x);
-                found = q < le && a.ncol[q] == x;
+                if (probe) {
+                    found = sh_bit(a.SB, a.nw, so, x);
+                    if (found) q = sh_slot(a.SB, a.SP, a.nw, a.nrp[other], so, x);
+                } else {
+                    q = lower_bound(a.ncol, lb, le, x);
+                    found = q < le && a.ncol[q] == x;
+                }
             }
             uint32_t pos = ordered_append<NT>(found, count, S.wave_cnt);
             if (found) {
@@ -260,13 +269,43 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
     group_sync<NT>();
 }
 
-// Ordered typed clique pairs K over the triangle set built by edge_build.
+// Inclusive scan of one value per thread over the NT threads.
 template <int NT>
-__device__ void edge_cliques(const EdgeArgs &a, const EdgeShared &S, int tid) {
+__device__ __forceinline__ uint32_t group_incl_scan(uint32_t v, uint32_t *wave_cnt) {
+    uint32_t incl = wave_incl_scan(v);
+    if (NT == WAVE) return incl;
+    int w = threadIdx.x / WAVE;
+    if (lane_id() == WAVE - 1) wave_cnt[w] = incl;
+    __syncthreads();
+    uint32_t add = 0;
+    for (int q = 0; q < w; ++q) add += wave_cnt[q];
+    __syncthreads();
+    return incl + add;
+}
+
+// Scratch of the flattened low-member scans (NT entries each).
+struct ScanScratch {
+    uint32_t *r;       // member
+    int64_t *start;    // first slot scanned in its row
+    uint32_t *scan;    // inclusive scan of the scanned lengths
+};
+
+// Ordered typed clique pairs K over the triangle set built by edge_build.
+// Hub-hub pairs: per hub member, its bit row AND the hub mask of T, counted
+// by type (popcounts against the type masks TMs), or bit tests when T has
+// few hub members.  Pairs with a low member r: the neighbours x > r of r are
+// walked (flattened over all threads) and each x in T adds both orders, so
+// every such pair is seen once.
+template <int NT>
+__device__ void edge_cliques(const EdgeArgs &a, int32_t i, int32_t j, const EdgeShared &S,
+                             const uint64_t *TMs, const ScanScratch &F, int tid) {
     const int L = a.L;
     const int Hw = a.Hw;
     const int32_t base = a.hub_base;
     const uint32_t nTl = S.meta[0], nTh = S.meta[1];
+    // both endpoints super-hubs: low membership of T by two bitmap probes
+    const bool both_sh = i >= a.sh_base && j >= a.sh_base;
+    const int si = i - a.sh_base, sj = j - a.sh_base;
     if (nTh) {
         const uint32_t wlo = S.meta[2], whi = S.meta[3];
         const uint32_t range = whi - wlo + 1;
@@ -289,12 +328,21 @@ __device__ void edge_cliques(const EdgeArgs &a, const EdgeShared &S, int tid) {
                     }
                 }
             } else {
-                for (uint32_t q = wlo; q <= whi; ++q) {
-                    uint64_t v = rowk[q] & S.Tm[q];
-                    if (!v) continue;
+                // whole 64-byte blocks of the bit row (rows are padded to
+                // multiples of 8 words): four 16-byte loads per block
+                const uint32_t q0 = wlo & ~7u, q1 = (whi | 7u) + 1;
+                for (uint32_t q = q0; q < q1; q += 8) {
+                    const ulonglong2 *rp = reinterpret_cast<const ulonglong2 *>(rowk + q);
+                    ulonglong2 r0 = rp[0], r1 = rp[1], r2 = rp[2], r3 = rp[3];
+                    uint64_t w[8] = {r0.x, r0.y, r1.x, r1.y, r2.x, r2.y, r3.x, r3.y};
 #pragma unroll
-                    for (int t = 0; t < TG_MAX_L; ++t)
-                        if (t < L) cnt[t] += (uint32_t)__popcll(v & a.TM[(size_t)t * Hw + q]);
+                    for (int b = 0; b < 8; ++b) {
+                        uint64_t v = w[b] & S.Tm[q + b];
+                        if (!v) continue;
+#pragma unroll
+                        for (int t = 0; t < TG_MAX_L; ++t)
+                            if (t < L) cnt[t] += (uint32_t)__popcll(v & TMs[t * Hw + q + b]);
+                    }
                 }
             }
 #pragma unroll
@@ -303,19 +351,31 @@ __device__ void edge_cliques(const EdgeArgs &a, const EdgeShared &S, int tid) {
                     atomicAdd((unsigned long long *)&S.K[tk * L + t], (unsigned long long)cnt[t]);
         }
     }
-    for (uint32_t idx = tid; idx < nTl; idx += NT) {
-        int32_t r = (int32_t)S.Tl[idx];
-        int tr = a.ntype[r];
-        uint32_t cnt[TG_MAX_L], rev[TG_MAX_L];
-#pragma unroll
-        for (int t = 0; t < TG_MAX_L; ++t) { cnt[t] = 0; rev[t] = 0; }
-        for (int64_t s = a.nrp[r]; s < a.nrp[r + 1]; ++s) {
-            int32_t x = a.ncol[s];
+    for (uint32_t c0 = 0; c0 < nTl; c0 += NT) {
+        const uint32_t items = nTl - c0 < (uint32_t)NT ? nTl - c0 : (uint32_t)NT;
+        uint32_t len = 0;
+        if ((uint32_t)tid < items) {
+            int32_t r = (int32_t)S.Tl[c0 + tid];
+            int64_t b = upper_bound(a.ncol, a.nrp[r], a.nrp[r + 1], r);
+            len = (uint32_t)(a.nrp[r + 1] - b);
+            F.r[tid] = (uint32_t)r;
+            F.start[tid] = b;
+        }
+        uint32_t incl = group_incl_scan<NT>(len, S.wave_cnt);
+        F.scan[tid] = incl;
+        group_sync<NT>();
+        const uint32_t total = F.scan[items - 1];
+        for (uint32_t f = tid; f < total; f += NT) {
+            int o = owner_of(F.scan, (int)items, f);
+            uint32_t excl = o ? F.scan[o - 1] : 0;
+            int32_t r = (int32_t)F.r[o];
+            int32_t x = a.ncol[F.start[o] + (f - excl)];
             bool in;
-            bool hubx = x >= base;
-            if (hubx) {
+            if (x >= base) {
                 int hx = x - base;
                 in = (S.Tm[hx >> 6] >> (hx & 63)) & 1ull;
+            } else if (both_sh) {
+                in = sh_bit(a.SB, a.nw, si, x) && sh_bit(a.SB, a.nw, sj, x);
             } else {
                 uint32_t lo = 0, hi2 = nTl;
                 while (lo < hi2) {
@@ -325,21 +385,12 @@ __device__ void edge_cliques(const EdgeArgs &a, const EdgeShared &S, int tid) {
                 in = lo < nTl && (int32_t)S.Tl[lo] == x;
             }
             if (!in) continue;
-            int tx = a.ntype[x];
-#pragma unroll
-            for (int t = 0; t < TG_MAX_L; ++t) {
-                cnt[t] += (t == tx);
-                rev[t] += (hubx && t == tx);
-            }
+            int tr = a.ntype[r], tx = a.ntype[x];
+            atomicAdd((unsigned long long *)&S.K[tr * L + tx], 1ull);
+            atomicAdd((unsigned long long *)&S.K[tx * L + tr], 1ull);
         }
-#pragma unroll
-        for (int t = 0; t < TG_MAX_L; ++t) {
-            if (t >= L) continue;
-            if (cnt[t]) atomicAdd((unsigned long long *)&S.K[tr * L + t], (unsigned long long)cnt[t]);
-            if (rev[t]) atomicAdd((unsigned long long *)&S.K[t * L + tr], (unsigned long long)rev[t]);
-        }
+        group_sync<NT>();
     }
-    group_sync<NT>();
 }
 
 // Every orbit of Table 3 for edge e from the triangle, clique, cycle and
@@ -380,86 +431,74 @@ __device__ void edge_derive(const EdgeArgs &a, int64_t e, int32_t i, int32_t j, 
         hist_add(a, hist, n2 + r3, (uint64_t)(si + sj), gid);
         hist_add(a, hist, n2 + n3 + r3, (uint64_t)nTt, gid);
     }
+    const int hbase = n2 + 2 * n3;
     for (int p = tid; p < P; p += NT) {
         // pair (t, u), t <= u, from its lexicographic index
         int t = 0, rem = p;
         while (rem >= L - t) { rem -= L - t; ++t; }
-        int u = t + rem;
-        int64_t nT_[2] = {(int64_t)tri_e[t], (int64_t)tri_e[u]};
-        int64_t Si[2], Sj[2];
-        int xs[2] = {t, u};
-        for (int z = 0; z < 2; ++z) {
-            int x = xs[z];
-            Si[z] = (int64_t)di[x] - nT_[z] - (tb == x);
-            Sj[z] = (int64_t)dj[x] - nT_[z] - (ta == x);
-        }
-        // ordered quantities for (x, y) = (t, u) [z=0] and (u, t) [z=1]
-        int64_t Ci[2], Cj[2], sgi[2], sgj[2], dli[2], dlj[2], Kx[2], Yx[2], Xix[2], NCx[2];
-        for (int z = 0; z < 2; ++z) {
-            int x = z ? u : t, y = z ? t : u;
-            int zx = z, zy = 1 - z;  // index of x / y inside nT_, Si, Sj
-            int q = x * L + y;
-            int64_t xi = (int64_t)Xi[q], xj = (int64_t)Xj[q], kk = (int64_t)K[q], yy = (int64_t)Y[q];
-            Ci[z] = xi - nT_[zx] * (tb == y) - kk;
-            Cj[z] = xj - nT_[zx] * (ta == y) - kk;
-            sgi[z] = (int64_t)Ai[q] - xi - (tb == x) * nT_[zy];
-            sgj[z] = (int64_t)Aj[q] - xj - (ta == x) * nT_[zy];
-            dli[z] = (int64_t)Di[q] - yy - (tb == x) * (int64_t)dj[y];
-            dlj[z] = (int64_t)Dj[q] - yy - (ta == x) * (int64_t)di[y];
-            Kx[z] = kk;
-            Yx[z] = yy;
-            Xix[z] = xi;
-            NCx[z] = (int64_t)NC[q];
-        }
-        int64_t Cyc[2], Ei[2], Ej[2], Pi[2], Pj[2], Q[2];
-        for (int z = 0; z < 2; ++z) Cyc[z] = NCx[z] - Ci[1 - z] - Cj[z] - Kx[z];
-        for (int z = 0; z < 2; ++z) {
-            int zb = 1 - z;
-            int y = z ? t : u;
-            int zx = z;
-            Ei[z] = sgi[z] - Ci[zb];
-            Ej[z] = sgj[z] - Cj[zb];
-            Pi[z] = dli[z] - Si[zx] * (ta == y) - sgi[z] - Cyc[z];
-            Pj[z] = dlj[z] - Sj[zx] * (tb == y) - sgj[z] - Cyc[zb];
-            Q[z] = Yx[z] - Xix[z] - Cj[z] - nT_[zx] * (ta == y);
-        }
-        int64_t g[13];
-        if (t == u) {
-            if (Kx[0] & 1) bad |= ST_INTERNAL;
-            if ((Ei[0] + Ej[0]) & 1) bad |= ST_INTERNAL;
-            g[12] = Kx[0] / 2;
-            g[6] = Cyc[0];
-            g[10] = Ci[0] + Cj[0];
-            g[7] = (Ei[0] + Ej[0]) / 2;
-            g[3] = Pi[0] + Pj[0];
-            g[8] = Q[0];
-            g[4] = Si[0] * Sj[0] - g[6];
-            g[5] = Si[0] * (Si[0] - 1) / 2 + Sj[0] * (Sj[0] - 1) / 2 - g[7];
-            g[9] = nT_[0] * (Si[0] + Sj[0]) - g[10];
-            g[11] = nT_[0] * (nT_[0] - 1) / 2 - g[12];
-        } else {
-            if (Ei[0] != Ei[1] || Ej[0] != Ej[1] || Kx[0] != Kx[1]) bad |= ST_INTERNAL;
-            g[12] = Kx[0];
-            g[6] = Cyc[0] + Cyc[1];
-            g[10] = Ci[0] + Cj[0] + Ci[1] + Cj[1];
-            g[7] = Ei[0] + Ej[0];
-            g[3] = Pi[0] + Pi[1] + Pj[0] + Pj[1];
-            g[8] = Q[0] + Q[1];
-            g[4] = Si[0] * Sj[1] + Si[1] * Sj[0] - g[6];
-            g[5] = Si[0] * Si[1] + Sj[0] * Sj[1] - g[7];
-            g[9] = nT_[0] * (Si[1] + Sj[1]) + nT_[1] * (Si[0] + Sj[0]) - g[10];
-            g[11] = nT_[0] * nT_[1] - g[12];
-        }
-        int r4 = rank4(ta, tb, t, u);
-        // graphlet of each orbit (Sec. 4.4): h3 = g3+g4, h4 = g5, h5 = g6,
-        // h6 = g7+g8+g9, h7 = g10+g11, h8 = g12
-        const int hof[13] = {0, 0, 0, 3, 3, 4, 5, 6, 6, 6, 7, 7, 8};
-        for (int o = 3; o <= 12; ++o) {
-            if (g[o] < 0) bad |= ST_INTERNAL;
-            uint64_t v = (uint64_t)g[o];
-            if (row) row[2 * L + (o - 3) * P + p] = v;
-            hist_add(a, hist, n2 + 2 * n3 + (hof[o] - 3) * n4 + r4, v, gid);
-        }
+        const int u = t + rem;
+        const bool same = t == u;
+        const int r4 = rank4(ta, tb, t, u);
+        const int qa = t * L + u, qb = u * L + t;   // ordered (t,u) and (u,t)
+        const int64_t nTt = tri_e[t], nTu = tri_e[u];
+        const int64_t Sit = (int64_t)di[t] - nTt - (tb == t), Siu = (int64_t)di[u] - nTu - (tb == u);
+        const int64_t Sjt = (int64_t)dj[t] - nTt - (ta == t), Sju = (int64_t)dj[u] - nTu - (ta == u);
+        auto emit = [&](int o, int64_t v) {
+            if (v < 0) bad |= ST_INTERNAL;
+            if (row) row[2 * L + (o - 3) * P + p] = (uint64_t)v;
+            // graphlet of each orbit (Sec. 4.4): h3 = g3+g4, h4 = g5,
+            // h5 = g6, h6 = g7+g8+g9, h7 = g10+g11, h8 = g12
+            const int h = o <= 4 ? 3 : o == 5 ? 4 : o == 6 ? 5 : o <= 9 ? 6 : o <= 11 ? 7 : 8;
+            hist_add(a, hist, hbase + (h - 3) * n4 + r4, (uint64_t)v, gid);
+        };
+        // cliques and chordal cycles
+        const int64_t K0 = (int64_t)K[qa], K1 = (int64_t)K[qb];
+        if (same && (K0 & 1)) bad |= ST_INTERNAL;
+        if (!same && K0 != K1) bad |= ST_INTERNAL;
+        const int64_t g12 = same ? K0 / 2 : K0;
+        emit(12, g12);
+        emit(11, (same ? nTt * (nTt - 1) / 2 : nTt * nTu) - g12);                 // Lemma 4
+        const int64_t Xi0 = (int64_t)Xi[qa], Xi1 = (int64_t)Xi[qb];
+        const int64_t Xj0 = (int64_t)Xj[qa], Xj1 = (int64_t)Xj[qb];
+        // C_i(x,y): pairs k in T^x, r in S_i^y adjacent; likewise C_j
+        const int64_t Ci0 = Xi0 - nTt * (tb == u) - K0, Ci1 = Xi1 - nTu * (tb == t) - K1;
+        const int64_t Cj0 = Xj0 - nTt * (ta == u) - K0, Cj1 = Xj1 - nTu * (ta == t) - K1;
+        const int64_t g10 = same ? Ci0 + Cj0 : Ci0 + Cj0 + Ci1 + Cj1;
+        emit(10, g10);
+        emit(9, (same ? nTt * (Sit + Sjt) : nTt * (Siu + Sju) + nTu * (Sit + Sjt)) - g10);  // Lemma 3
+        // 4-cycles: non-induced cycles minus chordal and clique instances
+        const int64_t Cyc0 = (int64_t)NC[qa] - Ci1 - Cj0 - K0;
+        const int64_t Cyc1 = (int64_t)NC[qb] - Ci0 - Cj1 - K1;
+        const int64_t g6 = same ? Cyc0 : Cyc0 + Cyc1;
+        emit(6, g6);
+        emit(4, (same ? Sit * Sjt : Sit * Sju + Siu * Sjt) - g6);                 // Lemma 1
+        // tailed-triangle tails: adjacent pairs inside S_i (resp. S_j)
+        const int64_t sgi0 = (int64_t)Ai[qa] - Xi0 - (tb == t) * nTu;
+        const int64_t sgi1 = (int64_t)Ai[qb] - Xi1 - (tb == u) * nTt;
+        const int64_t sgj0 = (int64_t)Aj[qa] - Xj0 - (ta == t) * nTu;
+        const int64_t sgj1 = (int64_t)Aj[qb] - Xj1 - (ta == u) * nTt;
+        const int64_t Ei0 = sgi0 - Ci1, Ei1 = sgi1 - Ci0;
+        const int64_t Ej0 = sgj0 - Cj1, Ej1 = sgj1 - Cj0;
+        if (same && ((Ei0 + Ej0) & 1)) bad |= ST_INTERNAL;
+        if (!same && (Ei0 != Ei1 || Ej0 != Ej1)) bad |= ST_INTERNAL;
+        const int64_t g7 = same ? (Ei0 + Ej0) / 2 : Ei0 + Ej0;
+        emit(7, g7);
+        emit(5, (same ? Sit * (Sit - 1) / 2 + Sjt * (Sjt - 1) / 2 : Sit * Siu + Sjt * Sju) - g7);  // Lemma 2
+        // 4-path end edges: neighbours of S_i / S_j outside the edge's sets
+        const int64_t Y0 = (int64_t)Y[qa], Y1 = (int64_t)Y[qb];
+        const int64_t dli0 = (int64_t)Di[qa] - Y0 - (tb == t) * (int64_t)dj[u];
+        const int64_t dli1 = (int64_t)Di[qb] - Y1 - (tb == u) * (int64_t)dj[t];
+        const int64_t dlj0 = (int64_t)Dj[qa] - Y0 - (ta == t) * (int64_t)di[u];
+        const int64_t dlj1 = (int64_t)Dj[qb] - Y1 - (ta == u) * (int64_t)di[t];
+        const int64_t Pi0 = dli0 - Sit * (ta == u) - sgi0 - Cyc0;
+        const int64_t Pi1 = dli1 - Siu * (ta == t) - sgi1 - Cyc1;
+        const int64_t Pj0 = dlj0 - Sjt * (tb == u) - sgj0 - Cyc1;
+        const int64_t Pj1 = dlj1 - Sju * (tb == t) - sgj1 - Cyc0;
+        emit(3, same ? Pi0 + Pj0 : Pi0 + Pi1 + Pj0 + Pj1);
+        // tailed-triangle edges opposite the tail's node
+        const int64_t Q0 = Y0 - Xi0 - Cj0 - nTt * (ta == u);
+        const int64_t Q1 = Y1 - Xi1 - Cj1 - nTu * (ta == t);
+        emit(8, same ? Q0 : Q0 + Q1);
     }
 }
 
@@ -488,6 +527,9 @@ __global__ void __launch_bounds__(64) k_edges_light(EdgeArgs a) {
     extern __shared__ uint64_t sm_edge[];
     __shared__ uint32_t meta[4];
     __shared__ uint32_t wave_cnt[1];
+    __shared__ uint32_t fl_r[WAVE], fl_scan[WAVE];
+    __shared__ int64_t fl_start[WAVE];
+    const ScanScratch F{fl_r, fl_start, fl_scan};
     const int LL = a.L * a.L;
     uint64_t *hist;
     uint64_t *after = sm_edge + 4 * LL + (a.hist_in_lds ? a.gw : 0) + a.Hw;
@@ -509,7 +551,7 @@ __global__ void __launch_bounds__(64) k_edges_light(EdgeArgs a) {
             return;
         }
         edge_build<WAVE>(a, i, j, S, lane);
-        edge_cliques<WAVE>(a, S, lane);
+        edge_cliques<WAVE>(a, i, j, S, a.TM, F, lane);
         edge_derive<WAVE>(a, e, i, j, S, hist, lane, bad);
         __syncthreads();
     };
@@ -564,14 +606,19 @@ __global__ void __launch_bounds__(EDGE_THREADS_HEAVY) k_edges_heavy(EdgeArgs a) 
     __shared__ uint32_t meta[4];
     __shared__ uint32_t wave_cnt[EDGE_THREADS_HEAVY / WAVE];
     __shared__ uint64_t s_idx;
+    __shared__ uint32_t fl_r[EDGE_THREADS_HEAVY], fl_scan[EDGE_THREADS_HEAVY];
+    __shared__ int64_t fl_start[EDGE_THREADS_HEAVY];
+    const ScanScratch F{fl_r, fl_start, fl_scan};
     const int NT = EDGE_THREADS_HEAVY;
     const int LL = a.L * a.L;
     uint64_t *hist;
     uint64_t *after = sm_edgeh + 4 * LL + (a.hist_in_lds ? a.gw : 0) + a.Hw;
-    uint32_t *Th = (uint32_t *)after;
+    uint64_t *TMs = after;                        // type masks of the hub core
+    uint32_t *Th = (uint32_t *)(TMs + (size_t)a.L * a.Hw);
     uint32_t *Tl = a.tbuf + (size_t)blockIdx.x * (size_t)a.n;
     EdgeShared S = carve(a, sm_edgeh, meta, wave_cnt, &hist, Th, Tl);
     int tid = threadIdx.x;
+    for (int q = tid; q < a.L * a.Hw; q += NT) TMs[q] = a.TM[q];
     uint32_t bad = 0;
     if (a.hist_in_lds)
         for (int q = tid; q < a.gw; q += NT) hist[q] = 0;
@@ -588,7 +635,7 @@ __global__ void __launch_bounds__(EDGE_THREADS_HEAVY) k_edges_heavy(EdgeArgs a) 
         edge_build<NT>(a, i, j, S, tid);
         __threadfence_block();
         __syncthreads();
-        edge_cliques<NT>(a, S, tid);
+        edge_cliques<NT>(a, i, j, S, TMs, F, tid);
         edge_derive<NT>(a, e, i, j, S, hist, tid, bad);
         __threadfence_block();
         __syncthreads();
@@ -617,7 +664,8 @@ size_t edge_lds_bytes(const EdgeArgs &args, bool heavy) {
     int LL = args.L * args.L;
     size_t sh = (size_t)(4 * LL + (args.hist_in_lds ? args.gw : 0) + args.Hw) * sizeof(uint64_t);
     if (!heavy) sh += (size_t)2 * TCAP * sizeof(uint32_t);
-    else sh += (size_t)(args.hub_base < args.n ? (args.n - args.hub_base) : 0) * sizeof(uint32_t);
+    else sh += (size_t)args.L * args.Hw * sizeof(uint64_t) +
+               (size_t)(args.hub_base < args.n ? (args.n - args.hub_base) : 0) * sizeof(uint32_t);
     return sh;
 }
 

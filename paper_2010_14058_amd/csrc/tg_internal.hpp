@@ -33,6 +33,9 @@ constexpr int EDGE_THREADS_HEAVY = 256;
 constexpr int64_t BATCH_EDGE_CHUNK = 256;  // consecutive edges per work item in batches
 constexpr int HUB_DMIN = 32;          // smallest degree of a hub-core node
 constexpr int HUB_MAX = 8192;         // largest hub core (bit-matrix HUB_MAX^2 bits)
+constexpr int SH_DMIN = 1024;         // smallest degree of a super-hub (full-row bitmap)
+constexpr int SH_MAX = 2048;          // most super-hubs
+constexpr size_t SH_BUDGET = size_t(512) << 20;  // bytes of super-hub bitmaps and prefixes
 
 // Device-side layout of everything the library keeps in the caller's
 // workspace.  All offsets are byte offsets from the workspace base.
@@ -51,6 +54,8 @@ struct Layout {
     size_t off_maps, off_tbuf, off_gacc, off_sort_tmp;
     size_t off_hstart, off_HB, off_hpre, off_TM;
     size_t off_node_graph, off_ngraph, off_gedge;   // batched graphs only
+    size_t off_SB, off_SP;                          // super-hub bitmaps
+    int sh_max;
     int64_t G;
     size_t total;
 };
@@ -59,7 +64,7 @@ struct Layout {
 enum Counter {
     C_A_LIGHT = 0, C_A_HEAVY, C_B_LIGHT, C_B_HEAVY, C_EDGE_HEAVY,
     C_A_NEXT, C_B_NEXT, C_EDGE_NEXT, C_WEDGES_A, C_WEDGES_B,
-    C_WEDGES_A_HEAVY, C_WEDGES_B_HEAVY, C_TRI_SUM, C_HUB_CAND,
+    C_WEDGES_A_HEAVY, C_WEDGES_B_HEAVY, C_TRI_SUM, C_HUB_CAND, C_SH_CAND,
     C_NUM
 };
 
@@ -120,6 +125,11 @@ struct EdgeArgs {
     const uint64_t *HB;          // [H][Hw] hub adjacency bits
     const uint32_t *hpre;        // [H][Hw] exclusive prefix popcounts
     const uint64_t *TM;          // [L][Hw] hubs of each type
+    // super-hubs: internal ids sh_base..n-1 with a bitmap over all nodes
+    int32_t sh_base;
+    int64_t nw;                  // 64-bit words per super-hub bitmap
+    const uint64_t *SB;          // [S][nw]
+    const uint32_t *SP;          // [S][nw] exclusive prefix popcounts
     // batched graphs: per-graph global vectors at goff[g], in graph g's own
     // L layout; the kernels compute in the layout of L (= max over graphs)
     int batch;
@@ -160,7 +170,10 @@ hipError_t launch_hub_build(const int64_t *nrp, const int32_t *ncol, const int64
                             uint32_t *pre, uint64_t *TM, hipStream_t st);
 hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype,
                       const int32_t *ei, const int32_t *ej, int64_t m, int L, uint32_t *tri,
-                      uint64_t *tri_sum, hipStream_t st);
+                      uint64_t *tri_sum, int32_t sh_base, int64_t nw, const uint64_t *SB,
+                      hipStream_t st);
+hipError_t launch_superhubs(const int64_t *nrp, const int32_t *ncol, int64_t n, int S, int64_t nw,
+                            uint64_t *SB, uint32_t *SP, hipStream_t st);
 hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype,
                             const uint32_t *neid, const uint32_t *tri, const uint32_t *tdeg,
                             int64_t n, int L, uint64_t *A, uint64_t *D, hipStream_t st);

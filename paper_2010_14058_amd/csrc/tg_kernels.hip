@@ -155,6 +155,9 @@ __global__ void k_relabel(const uint64_t *__restrict__ sorted, const uint8_t *__
     uint64_t bal = __ballot(cand);
     if (lane_id() == 0 && bal)
         atomicAdd((unsigned long long *)hub_cand, (unsigned long long)__popcll(bal));
+    uint64_t sbal = __ballot(r < n && ndeg[r] >= SH_DMIN);
+    if (lane_id() == 0 && sbal)
+        atomicAdd((unsigned long long *)(hub_cand + 1), (unsigned long long)__popcll(sbal));
 }
 
 // One wave per input row: canonical edge id of every slot, the relabelled
@@ -229,39 +232,114 @@ __global__ void k_tdeg(const int64_t *__restrict__ nrp, const int32_t *__restric
 
 // ------------------------------------------------------- typed triangles
 
-// One wave per edge: |T^t| by probing the shorter list in the longer one.
+// Typed triangles: a wave takes TRI_GROUPS consecutive edges, one group of
+// WAVE/TRI_GROUPS lanes per edge; a group walks the shorter row and tests each
+// node against the longer one (its super-hub bitmap when it has one, else a
+// binary search), counting hits by type.
+constexpr int TRI_GROUPS = 8;
+constexpr int TRI_LANES = WAVE / TRI_GROUPS;
+
 __global__ void k_tri(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
                       const uint8_t *__restrict__ ntype, const int32_t *__restrict__ ei,
                       const int32_t *__restrict__ ej, int64_t m, int L,
-                      uint32_t *__restrict__ tri, uint64_t *__restrict__ tri_sum) {
-    int64_t e = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
+                      uint32_t *__restrict__ tri, uint64_t *__restrict__ tri_sum, int32_t sh_base,
+                      int64_t nw, const uint64_t *__restrict__ SB) {
+    int64_t wave = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
     int lane = lane_id();
-    if (e >= m) return;
-    int32_t i = ei[e], j = ej[e];
-    int64_t sb = nrp[i], se = nrp[i + 1], bb = nrp[j], be = nrp[j + 1];
-    if (se - sb > be - bb) {
-        int64_t t0 = sb, t1 = se;
-        sb = bb; se = be; bb = t0; be = t1;
-    }
-    uint32_t c = 0;
-    for (int64_t base = sb; base < se; base += WAVE) {
-        int64_t s = base + lane;
-        int t = -1;
-        if (s < se) {
+    int grp = lane / TRI_LANES, gl = lane % TRI_LANES;
+    int64_t e = wave * TRI_GROUPS + grp;
+    uint32_t cnt[TG_MAX_L];
+#pragma unroll
+    for (int t = 0; t < TG_MAX_L; ++t) cnt[t] = 0;
+    if (e < m) {
+        int32_t i = ei[e], j = ej[e];
+        int64_t sb = nrp[i], se = nrp[i + 1], bb = nrp[j], be = nrp[j + 1];
+        int32_t big = j;
+        if (se - sb > be - bb) {
+            int64_t t0 = sb, t1 = se;
+            sb = bb; se = be; bb = t0; be = t1;
+            big = i;
+        }
+        const bool probe = big >= sh_base;
+        const int sidx = big - sh_base;
+        for (int64_t s = sb + gl; s < se; s += TRI_LANES) {
             int32_t x = ncol[s];
-            int64_t q = lower_bound(ncol, bb, be, x);
-            if (q < be && ncol[q] == x) t = ntype[x];
-        }
-        uint64_t any = __ballot(t >= 0);
-        if (!any) continue;
-        for (int tt = 0; tt < L; ++tt) {
-            uint64_t bal = __ballot(t == tt);
-            if (lane == tt) c += (uint32_t)__popcll(bal);
+            bool found;
+            if (probe) {
+                found = sh_bit(SB, nw, sidx, x);
+            } else {
+                int64_t q = lower_bound(ncol, bb, be, x);
+                found = q < be && ncol[q] == x;
+            }
+            if (found) {
+                int tx = ntype[x];
+#pragma unroll
+                for (int t = 0; t < TG_MAX_L; ++t) cnt[t] += (t == tx);
+            }
         }
     }
-    if (lane < L) tri[e * L + lane] = c;
-    uint64_t tot = wave_sum_u64(lane < L ? (uint64_t)c : 0ull);
+    uint64_t tot = 0;
+#pragma unroll
+    for (int t = 0; t < TG_MAX_L; ++t) {
+        if (t < L) {
+            uint32_t v = cnt[t];
+#pragma unroll
+            for (int d = 1; d < TRI_LANES; d <<= 1) v += __shfl_xor(v, d, WAVE);
+            if (gl == 0 && e < m) tri[e * L + t] = v;
+            tot += v;
+        }
+    }
+    // one count per group (lanes of a group hold the same totals)
+    tot = gl == 0 ? tot : 0ull;
+    tot = wave_sum_u64(tot);
     if (lane == 0 && tot) atomicAdd((unsigned long long *)tri_sum, (unsigned long long)tot);
+}
+
+// One workgroup per super-hub: bitmap of its neighbours over all nodes and
+// the per-word exclusive prefix popcounts (slot of a neighbour in the row).
+__global__ void __launch_bounds__(256) k_superhubs(const int64_t *__restrict__ nrp,
+                                                   const int32_t *__restrict__ ncol, int64_t n,
+                                                   int S, int64_t nw, uint64_t *__restrict__ SB,
+                                                   uint32_t *__restrict__ SP) {
+    __shared__ uint32_t part[256];
+    const int s = blockIdx.x;
+    if (s >= S) return;
+    const int tid = threadIdx.x;
+    const int64_t v = n - S + s;
+    uint64_t *bits = SB + (size_t)s * nw;
+    uint32_t *pre = SP + (size_t)s * nw;
+    for (int64_t q = tid; q < nw; q += 256) bits[q] = 0ull;
+    __syncthreads();
+    for (int64_t p = nrp[v] + tid; p < nrp[v + 1]; p += 256) {
+        int32_t x = ncol[p];
+        __hip_atomic_fetch_or((unsigned long long *)&bits[x >> 6], 1ull << (x & 63),
+                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __syncthreads();
+    // contiguous word segments per thread, then a block scan of their sums
+    const int64_t seg = (nw + 255) / 256;
+    const int64_t q0 = tid * seg, q1 = q0 + seg < nw ? q0 + seg : nw;
+    uint32_t sum = 0;
+    for (int64_t q = q0; q < q1; ++q)
+        sum += (uint32_t)__popcll(__hip_atomic_load((unsigned long long *)&bits[q], __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_WORKGROUP));
+    part[tid] = sum;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int q = 0; q < 256; ++q) {
+            uint32_t c = part[q];
+            part[q] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    uint32_t run = part[tid];
+    for (int64_t q = q0; q < q1; ++q) {
+        pre[q] = run;
+        run += (uint32_t)__popcll(__hip_atomic_load((unsigned long long *)&bits[q], __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_WORKGROUP));
+    }
 }
 
 // ------------------------------------------------------ node aggregates
@@ -696,9 +774,11 @@ hipError_t launch_tdeg(const int64_t *nrp, const int32_t *ncol, const uint8_t *n
 
 hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype,
                       const int32_t *ei, const int32_t *ej, int64_t m, int L, uint32_t *tri,
-                      uint64_t *tri_sum, hipStream_t st) {
+                      uint64_t *tri_sum, int32_t sh_base, int64_t nw, const uint64_t *SB,
+                      hipStream_t st) {
     if (m == 0) return hipSuccess;
-    k_tri<<<blocks_for(m, 4), 256, 0, st>>>(nrp, ncol, ntype, ei, ej, m, L, tri, tri_sum);
+    k_tri<<<blocks_for(m, 4 * TRI_GROUPS), 256, 0, st>>>(nrp, ncol, ntype, ei, ej, m, L, tri,
+                                                         tri_sum, sh_base, nw, SB);
     LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -771,6 +851,14 @@ hipError_t launch_batch_finalize(uint64_t *globals, const int32_t *gL, const int
     if (G <= 0) return hipSuccess;
     unsigned grid = (unsigned)(G < 8192 ? G : 8192);
     k_batch_finalize<<<grid, 256, 0, st>>>(globals, gL, goff, G, status);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_superhubs(const int64_t *nrp, const int32_t *ncol, int64_t n, int S, int64_t nw,
+                            uint64_t *SB, uint32_t *SP, hipStream_t st) {
+    if (S <= 0) return hipSuccess;
+    k_superhubs<<<(unsigned)S, 256, 0, st>>>(nrp, ncol, n, S, nw, SB, SP);
     LAUNCH_CHECK();
     return hipSuccess;
 }
