@@ -147,6 +147,29 @@ tg_status tg_key_describe(int32_t L, int32_t col, int32_t *orbit, int32_t *t, in
 tg_status tg_global_key_describe(int32_t L, int32_t idx, int32_t *graphlet,
                                  int32_t types_sorted[4], int32_t *k);
 
+/* Text naming the HIP call and error behind the most recent TG_E_DEVICE
+ * returned by a counting call on this host thread ("" if that call had no
+ * HIP failure).  The string is owned by the library and valid until the
+ * next counting call on the thread. */
+const char *tg_last_error(void);
+
+/* Tuning knobs of the heavy 4-cycle path, kept per host thread and applied
+ * to later calls on that thread.  They change how work is scheduled, never
+ * the counts.
+ *   TG_TUNE_TASK_WEDGES  (default 262144, >= 1): a heavy wedge group is split
+ *       into target-id ranges of about this many wedges each (at most 64).
+ *   TG_TUNE_CLEAR_BYTES  (default 16, >= 0): a task clears its map range by
+ *       streaming zeros when the range costs at most this many bytes per
+ *       wedge of the task, else by a walk over its wedges; 0 never streams.
+ * tg_set_tuning returns TG_E_INVALID_ARG for an unknown knob or a value out
+ * of range; tg_get_tuning returns the current value (-1 if unknown). */
+typedef enum {
+    TG_TUNE_TASK_WEDGES = 0,
+    TG_TUNE_CLEAR_BYTES = 1
+} tg_tune;
+tg_status tg_set_tuning(int32_t knob, int64_t value);
+int64_t tg_get_tuning(int32_t knob);
+
 /* Timing of the phases of the most recent tg_count_typed_graphlets call on
  * this host thread, measured with HIP events on the caller's stream when
  * timing is enabled.  tg_set_timing(1) turns it on (off by default).

@@ -11,6 +11,7 @@ from . import _lib
 from ._lib import (  # noqa: F401
     TGError,
     batch_workspace_bytes,
+    get_tuning,
     global_key_describe,
     global_width,
     key_describe,
@@ -18,6 +19,7 @@ from ._lib import (  # noqa: F401
     phase_times,
     row_width,
     set_timing,
+    set_tuning,
     workspace_bytes,
 )
 

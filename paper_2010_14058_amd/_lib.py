@@ -36,6 +36,9 @@ SIGNATURES = {
     "tg_set_timing": (None, [_c.c_int32]),
     "tg_phase_times": (_c.c_int32, [_c.POINTER(_c.c_float), _c.POINTER(_c.c_char_p), _c.c_int32]),
     "tg_last_stats": (_c.c_int32, [_c.POINTER(_c.c_int64), _c.c_int32]),
+    "tg_set_tuning": (_c.c_int, [_c.c_int32, _c.c_int64]),
+    "tg_last_error": (_c.c_char_p, []),
+    "tg_get_tuning": (_c.c_int64, [_c.c_int32]),
 }
 
 _lib = None
@@ -44,7 +47,12 @@ _lib = None
 class TGError(RuntimeError):
     def __init__(self, code: int, what: str):
         self.code = code
-        super().__init__(f"{what}: tg_status {code} ({status_str(code)})")
+        msg = f"{what}: tg_status {code} ({status_str(code)})"
+        if code == 6:
+            detail = load().tg_last_error()
+            if detail:
+                msg += f": {detail.decode()}"
+        super().__init__(msg)
 
 
 def load(path: str | None = None):
@@ -109,6 +117,25 @@ def phase_times() -> list[tuple[str, float]]:
     names = (ctypes.c_char_p * 32)()
     cnt = load().tg_phase_times(ms, names, 32)
     return [(names[q].decode(), float(ms[q])) for q in range(max(cnt, 0))]
+
+
+TUNE_KNOBS = {"task_wedges": 0, "clear_bytes": 1}
+
+
+def set_tuning(**knobs) -> dict:
+    """Set heavy-path scheduling knobs for this thread; returns the old values."""
+    old = {}
+    for name, value in knobs.items():
+        k = TUNE_KNOBS[name]
+        old[name] = load().tg_get_tuning(k)
+        rc = load().tg_set_tuning(k, int(value))
+        if rc:
+            raise TGError(rc, f"tg_set_tuning({name}={value})")
+    return old
+
+
+def get_tuning() -> dict:
+    return {name: load().tg_get_tuning(k) for name, k in TUNE_KNOBS.items()}
 
 
 def last_stats() -> dict:

@@ -5,6 +5,7 @@
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
 
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -109,9 +110,9 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G) {
     y.off_D = take(sizeof(uint64_t) * (n + 1) * LL);
     y.off_NC = take(sizeof(uint64_t) * (y.m + 1) * LL);
     y.off_listA_light = take(sizeof(uint32_t) * (n + 1));
-    y.off_listA_heavy = take(sizeof(uint32_t) * (n + 1));
+    y.off_listA_heavy = take(sizeof(uint4) * (n + 1 + TASK_EXTRA));
     y.off_listB_light = take(sizeof(uint32_t) * (n + 1));
-    y.off_listB_heavy = take(sizeof(uint32_t) * (n + 1));
+    y.off_listB_heavy = take(sizeof(uint4) * (n + 1 + TASK_EXTRA));
     y.off_list_edge = take(sizeof(uint32_t) * (y.m + 1));
     y.off_maps = take(per_map * (size_t)y.heavy_slots);
     y.off_tbuf = take(per_t * (size_t)y.heavy_edge_slots);
@@ -151,6 +152,7 @@ struct Timing {
     int64_t stats[8] = {0};
 };
 thread_local Timing g_timing;
+thread_local int64_t g_tune[2] = {TASK_WEDGES, SEQ_CLEAR_BYTES};
 
 void timing_reset(hipStream_t st) {
     g_timing.used = 0;
@@ -180,7 +182,14 @@ static tg_status status_from_bits(uint32_t bits) {
     return TG_OK;
 }
 
-#define HIPCHK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return TG_E_DEVICE; } while (0)
+thread_local char g_last_error[256];
+
+static tg_status hip_failed(hipError_t e, const char *what) {
+    snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+    return TG_E_DEVICE;
+}
+
+#define HIPCHK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return hip_failed(e_, #x); } while (0)
 
 template <class T>
 static T *at(void *base, size_t off) {
@@ -193,6 +202,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     const int64_t m = y.m;
     const int LL = L * L;
     const int gw = tg_global_width(L);
+    g_last_error[0] = 0;
     uint32_t *status = at<uint32_t>(ws, y.off_status);
     uint64_t *counters = at<uint64_t>(ws, y.off_counters);
     uint32_t *deg = at<uint32_t>(ws, y.off_deg);
@@ -217,9 +227,9 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     uint64_t *D = at<uint64_t>(ws, y.off_D);
     uint64_t *NC = at<uint64_t>(ws, y.off_NC);
     uint32_t *la_l = at<uint32_t>(ws, y.off_listA_light);
-    uint32_t *la_h = at<uint32_t>(ws, y.off_listA_heavy);
+    uint4 *la_h = at<uint4>(ws, y.off_listA_heavy);
     uint32_t *lb_l = at<uint32_t>(ws, y.off_listB_light);
-    uint32_t *lb_h = at<uint32_t>(ws, y.off_listB_heavy);
+    uint4 *lb_h = at<uint4>(ws, y.off_listB_heavy);
     uint32_t *le = at<uint32_t>(ws, y.off_list_edge);
     uint32_t *maps = at<uint32_t>(ws, y.off_maps);
     uint32_t *tbuf = at<uint32_t>(ws, y.off_tbuf);
@@ -314,9 +324,12 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
 
     // ---- 4-cycles from degree-ordered wedges
     HIPCHK(launch_fill_u64(NC, 0, m * LL, st));
-    HIPCHK(launch_cyc_work(nrp, ncol, n, la_l, la_h, lb_l, lb_h, counters, st));
+    HIPCHK(launch_cyc_work(nrp, ncol, n, la_l, la_h, lb_l, lb_h, counters,
+                           (uint64_t)g_tune[TG_TUNE_TASK_WEDGES], st));
     timing_mark("cyc_work");
     CycleArgs ca;
+    ca.tasks = nullptr;
+    ca.clear_bytes = (uint64_t)g_tune[TG_TUNE_CLEAR_BYTES];
     ca.nrp = nrp; ca.ncol = ncol; ca.ntype = ntype; ca.neid = neid; ca.ei = ei;
     ca.counters = counters; ca.L = L; ca.n = n; ca.NC = NC; ca.maps = maps;
     ca.chunk = heavy_chunk_for(L);
@@ -332,7 +345,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
         ca.next_idx = 0;
         HIPCHK(launch_cycles(pass, false, ca, light_grid, st));
         timing_mark(pass == 0 ? "cycA_light" : "cycB_light");
-        ca.list = pass == 0 ? la_h : lb_h;
+        ca.tasks = pass == 0 ? la_h : lb_h;
         ca.count_idx = pass == 0 ? C_A_HEAVY : C_B_HEAVY;
         ca.next_idx = pass == 0 ? C_A_NEXT : C_B_NEXT;
         HIPCHK(launch_cycles(pass, true, ca, (unsigned)y.heavy_slots, st));
@@ -376,7 +389,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     HIPCHK(hipStreamSynchronize(st));
     g_timing.stats[0] = (int64_t)cnt_host[C_WEDGES_A];
     g_timing.stats[1] = (int64_t)(cnt_host[C_A_LIGHT] + cnt_host[C_B_LIGHT]);
-    g_timing.stats[2] = (int64_t)(cnt_host[C_A_HEAVY] + cnt_host[C_B_HEAVY]);
+    g_timing.stats[2] = (int64_t)cnt_host[C_HEAVY_GROUPS];
     g_timing.stats[3] = (int64_t)cnt_host[C_EDGE_HEAVY];
     g_timing.stats[4] = (int64_t)cnt_host[C_WEDGES_B];
     g_timing.stats[5] = (int64_t)cnt_host[C_WEDGES_A_HEAVY];
@@ -533,6 +546,28 @@ int32_t tg_phase_times(float *ms, const char **names, int32_t max_phases) {
     }
     return cnt;
 }
+
+tg_status tg_set_tuning(int32_t knob, int64_t value) {
+    switch (knob) {
+    case TG_TUNE_TASK_WEDGES:
+        if (value < 1) return TG_E_INVALID_ARG;
+        break;
+    case TG_TUNE_CLEAR_BYTES:
+        if (value < 0 || value > (int64_t(1) << 30)) return TG_E_INVALID_ARG;
+        break;
+    default:
+        return TG_E_INVALID_ARG;
+    }
+    tg::g_tune[knob] = value;
+    return TG_OK;
+}
+
+int64_t tg_get_tuning(int32_t knob) {
+    if (knob < 0 || knob > TG_TUNE_CLEAR_BYTES) return -1;
+    return tg::g_tune[knob];
+}
+
+const char *tg_last_error(void) { return tg::g_last_error; }
 
 int32_t tg_last_stats(int64_t *stats, int32_t max_stats) {
     int cnt = max_stats < 8 ? max_stats : 8;

@@ -391,6 +391,8 @@ __device__ void edge_cliques(const EdgeArgs &a, int32_t i, int32_t j, const Edge
         }
         group_sync<NT>();
     }
+    // K is read by every thread next, also when T has no low member
+    group_sync<NT>();
 }
 
 // Every orbit of Table 3 for edge e from the triangle, clique, cycle and

@@ -28,6 +28,10 @@ constexpr int LIGHT_HCAP = 1024;      // LDS hash slots per light group
 constexpr int64_t LIGHT_MAXW = 512;   // a group is light if it has at most this many wedges
 constexpr int HEAVY_THREADS = 256;    // threads of a heavy-group workgroup
 constexpr int HEAVY_CHUNK = 128;      // items staged per round in the heavy path
+constexpr int64_t TASK_WEDGES = 1 << 18;  // default wedges per heavy task (target range)
+constexpr int TASK_MAX_PARTS = 64;        // most target ranges per heavy group
+constexpr int64_t TASK_EXTRA = 1 << 16;   // task slots beyond one per node, shared by both passes
+constexpr int SEQ_CLEAR_BYTES = 16;       // default bytes per wedge below which a range is cleared by streaming
 constexpr int TCAP = 1024;            // triangle set kept in LDS by the light edge kernel
 constexpr int EDGE_THREADS_HEAVY = 256;
 constexpr int64_t BATCH_EDGE_CHUNK = 256;  // consecutive edges per work item in batches
@@ -65,6 +69,7 @@ enum Counter {
     C_A_LIGHT = 0, C_A_HEAVY, C_B_LIGHT, C_B_HEAVY, C_EDGE_HEAVY,
     C_A_NEXT, C_B_NEXT, C_EDGE_NEXT, C_WEDGES_A, C_WEDGES_B,
     C_WEDGES_A_HEAVY, C_WEDGES_B_HEAVY, C_TRI_SUM, C_HUB_CAND, C_SH_CAND,
+    C_TASK_EXTRA, C_HEAVY_GROUPS,
     C_NUM
 };
 
@@ -86,7 +91,9 @@ struct CycleArgs {
     const uint8_t *ntype;
     const uint32_t *neid;
     const int32_t *ei;
-    const uint32_t *list;
+    const uint32_t *list;      // light groups
+    const uint4 *tasks;        // heavy tasks: group, part, parts, wedges of the group
+    uint64_t clear_bytes;      // streamed-clear threshold (bytes per wedge)
     uint64_t *counters;
     int count_idx;
     int next_idx;
@@ -178,8 +185,8 @@ hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8
                             const uint32_t *neid, const uint32_t *tri, const uint32_t *tdeg,
                             int64_t n, int L, uint64_t *A, uint64_t *D, hipStream_t st);
 hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, int64_t n, uint32_t *la_l,
-                           uint32_t *la_h, uint32_t *lb_l, uint32_t *lb_h, uint64_t *counters,
-                           hipStream_t st);
+                           uint4 *la_h, uint32_t *lb_l, uint4 *lb_h, uint64_t *counters,
+                           uint64_t task_wedges, hipStream_t st);
 int heavy_chunk_for(int L);
 hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned grid, hipStream_t st);
 hipError_t launch_edges(bool heavy, const EdgeArgs &args, unsigned grid, hipStream_t st);

@@ -540,11 +540,26 @@ __device__ __forceinline__ void block_scan_chunk(uint32_t v, uint32_t *s, uint32
     __syncthreads();
 }
 
-// Heavy groups: one 256-thread workgroup per group, pulled from a queue; the
-// map is a dense n x L uint32 array private to the workgroup.  Three walks
-// over the group's wedges: clear the entries the group touches, count,
-// emit.  Entries no wedge touches are never read, so the map needs no
-// initialisation.
+// First id c in [lo, hi] whose row starts at or after offset off (row
+// starts are nondecreasing).
+__device__ __forceinline__ int32_t row_at(const int64_t *nrp, int32_t lo, int32_t hi, int64_t off) {
+    while (lo < hi) {
+        int32_t mid = lo + ((hi - lo) >> 1);
+        if (nrp[mid] < off) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Heavy tasks: one 256-thread workgroup per task, pulled from a queue.  A
+// task is a heavy group restricted to one range of target ids; a group with
+// many wedges is split into ranges of about equal adjacency mass (targets are
+// met in proportion to their degree), so its work spreads over workgroups and
+// each range has every wedge that reaches its targets.  The map is a dense
+// uint32 array private to the workgroup, indexed by target: L 32-bit counts
+// per target, or L 16-bit counts when the group has fewer than 2^16 items
+// (a count never exceeds the item count).  The entries of the range are
+// cleared by streaming zeros over the range when that is cheaper than a walk
+// over the wedges; then a count walk and an emit walk.
 template <int PASS>
 __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
     extern __shared__ uint64_t sm_heavy[];
@@ -558,29 +573,79 @@ __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
     __shared__ uint32_t it_eid[HEAVY_CHUNK];
     __shared__ int it_flip[HEAVY_CHUNK];
     __shared__ uint32_t wave_tot[HEAVY_THREADS / WAVE];
-    __shared__ uint64_t s_idx;
+    __shared__ int32_t s_task[4];  // group, first target, end target, streamed clear
     int tid = threadIdx.x;
     uint32_t *map = a.maps + (size_t)blockIdx.x * (size_t)a.n * L;
     uint64_t count = a.counters[a.count_idx];
     while (true) {
-        if (tid == 0) s_idx = atomicAdd((unsigned long long *)&a.counters[a.next_idx], 1ull);
+        if (tid == 0) {
+            uint64_t idx = atomicAdd((unsigned long long *)&a.counters[a.next_idx], 1ull);
+            s_task[0] = -1;
+            if (idx < count) {
+                uint4 tk = a.tasks[idx];
+                int32_t g = (int32_t)tk.x;
+                int32_t rb = PASS == 0 ? 0 : g + 1;
+                int32_t re = PASS == 0 ? g : (int32_t)a.n;
+                int32_t lo = rb, hi = re;
+                if (tk.z > 1) {
+                    int64_t base = a.nrp[rb], mass = a.nrp[re] - base;
+                    lo = tk.y ? row_at(a.nrp, rb, re, base + mass * tk.y / tk.z) : rb;
+                    hi = tk.y + 1 < tk.z ? row_at(a.nrp, rb, re, base + mass * (tk.y + 1) / tk.z)
+                                         : re;
+                }
+                int64_t nitem = PASS == 0 ? lower_bound(a.ncol, a.nrp[g], a.nrp[g + 1], g) - a.nrp[g]
+                                          : a.nrp[g + 1] - a.nrp[g];
+                int ew = nitem < 65536 ? (L + 1) / 2 : L;
+                uint64_t wt = tk.w / tk.z;
+                s_task[0] = g;
+                s_task[1] = lo;
+                s_task[2] = hi;
+                s_task[3] = (uint64_t)(hi - lo) * ew * 4 <= wt * a.clear_bytes ? 1 : 0;
+            }
+        }
         __syncthreads();
-        uint64_t idx = s_idx;
+        const int32_t g = s_task[0];
+        const int32_t lo = s_task[1], hi = s_task[2];
+        const bool streamed = s_task[3] != 0;
         __syncthreads();
-        if (idx >= count) break;
-        int32_t g = (int32_t)a.list[idx];
+        if (g < 0) break;
         int64_t ib, ie;
         item_range<PASS>(a, g, ib, ie);
-        for (int phase = 0; phase < 3; ++phase) {
+        const bool narrow = ie - ib < 65536;
+        const int EW = narrow ? (L + 1) / 2 : L;
+        if (hi <= lo) continue;
+        if (streamed) {
+            uint32_t *p0 = map + (size_t)lo * EW;
+            size_t cnt = (size_t)(hi - lo) * EW;
+            size_t head = ((16 - ((uintptr_t)p0 & 15)) & 15) / 4;
+            if (head > cnt) head = cnt;
+            if ((size_t)tid < head) p0[tid] = 0u;
+            uint4 *pv = reinterpret_cast<uint4 *>(p0 + head);
+            size_t nv = (cnt - head) / 4;
+            for (size_t q = tid; q < nv; q += HEAVY_THREADS) pv[q] = make_uint4(0u, 0u, 0u, 0u);
+            size_t done = head + nv * 4;
+            if ((size_t)tid < cnt - done) p0[done + tid] = 0u;
+            __syncthreads();
+        }
+        for (int phase = streamed ? 1 : 0; phase < 3; ++phase) {
             for (int64_t cb = ib; cb < ie; cb += CH) {
                 int nitems = (int)((ie - cb) < CH ? (ie - cb) : CH);
                 uint32_t len = 0;
                 if (tid < nitems) {
                     int64_t s = cb + tid;
                     int32_t x = a.ncol[s];
+                    int64_t xb = a.nrp[x], xe = a.nrp[x + 1];
                     int64_t tb, te;
-                    target_range<PASS>(a, g, x, tb, te);
-                    len = (uint32_t)(te - tb);
+                    if (PASS == 0) {
+                        tb = lo > 0 ? lower_bound(a.ncol, xb, xe, lo) : xb;
+                        te = lower_bound(a.ncol, xb, xe, hi);
+                    } else {
+                        int32_t first = (g > x ? g : x) + 1;
+                        if (lo > first) first = lo;
+                        tb = lower_bound(a.ncol, xb, xe, first);
+                        te = hi < a.n ? lower_bound(a.ncol, tb, xe, hi) : xe;
+                    }
+                    len = (uint32_t)(te > tb ? te - tb : 0);
                     it_x[tid] = x;
                     it_tb[tid] = tb;
                     uint32_t e = a.neid[s];
@@ -598,21 +663,33 @@ __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
                     uint32_t excl = o ? it_scan[o - 1] : 0;
                     int32_t x = it_x[o];
                     uint32_t y = (uint32_t)a.ncol[it_tb[o] + (f - excl)];
-                    uint32_t *my = map + (size_t)y * L;
+                    uint32_t *my = map + (size_t)y * EW;
                     if (phase == 0) {
-                        for (int t = 0; t < L; ++t) my[t] = 0u;
+                        for (int t = 0; t < EW; ++t) my[t] = 0u;
                     } else if (phase == 1) {
                         // the map is private to this workgroup: workgroup scope
                         // keeps the update in the XCD's L2
-                        __hip_atomic_fetch_add(&my[a.ntype[x]], 1u, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                        int tx = a.ntype[x];
+                        if (narrow)
+                            __hip_atomic_fetch_add(&my[tx >> 1], 1u << ((tx & 1) * 16),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        else
+                            __hip_atomic_fetch_add(&my[tx], 1u, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
                     } else {
                         int tx = a.ntype[x];
                         int ty = a.ntype[y];
                         uint64_t *ac = acc + (size_t)o * LL;
                         for (int t = 0; t < L; ++t) {
-                            uint32_t c = __hip_atomic_load(&my[t], __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                            uint32_t c;
+                            if (narrow) {
+                                c = __hip_atomic_load(&my[t >> 1], __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+                                c = (c >> ((t & 1) * 16)) & 0xffffu;
+                            } else {
+                                c = __hip_atomic_load(&my[t], __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+                            }
                             uint32_t val = c - (t == tx ? 1u : 0u);
                             if (val)
                                 atomicAdd((unsigned long long *)&ac[pass_entry<PASS>(t, ty, L)],
@@ -635,19 +712,39 @@ __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
                     __syncthreads();
                 }
             }
-            // all map traffic of a group stays inside this workgroup, so a
+            // all map traffic of a task stays inside this workgroup, so a
             // workgroup barrier orders the clear, count and emit walks
             __syncthreads();
         }
     }
 }
 
+// Queue entries of a heavy group: one per target range.  Splits beyond one
+// entry per group draw on a shared budget of extra slots; when it is spent the
+// group stays whole.
+__device__ void push_heavy(uint4 *tasks, uint64_t *counters, int idx, int32_t g, uint64_t w,
+                           uint64_t task_wedges) {
+    uint64_t p = (w + task_wedges - 1) / task_wedges;
+    if (p > (uint64_t)TASK_MAX_PARTS) p = TASK_MAX_PARTS;
+    if (p > 1) {
+        uint64_t old = atomicAdd((unsigned long long *)&counters[C_TASK_EXTRA],
+                                 (unsigned long long)(p - 1));
+        if (old + (p - 1) > (uint64_t)TASK_EXTRA) p = 1;
+    }
+    uint64_t base = atomicAdd((unsigned long long *)&counters[idx], (unsigned long long)p);
+    uint32_t wc = w > 0xffffffffull ? 0xffffffffu : (uint32_t)w;
+    for (uint32_t k = 0; k < (uint32_t)p; ++k)
+        tasks[base + k] = make_uint4((uint32_t)g, k, (uint32_t)p, wc);
+    atomicAdd((unsigned long long *)&counters[C_HEAVY_GROUPS], 1ull);
+}
+
 // One wave per internal node: wedge counts of both passes, bucketed into
 // light and heavy lists.
 __global__ void k_cyc_work(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
                            int64_t n, uint32_t *__restrict__ listA_light,
-                           uint32_t *__restrict__ listA_heavy, uint32_t *__restrict__ listB_light,
-                           uint32_t *__restrict__ listB_heavy, uint64_t *__restrict__ counters) {
+                           uint4 *__restrict__ listA_heavy, uint32_t *__restrict__ listB_light,
+                           uint4 *__restrict__ listB_heavy, uint64_t *__restrict__ counters,
+                           uint64_t task_wedges) {
     int64_t v = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
     int lane = lane_id();
     if (v >= n) return;
@@ -668,7 +765,7 @@ __global__ void k_cyc_work(const int64_t *__restrict__ nrp, const int32_t *__res
             if (wa <= (uint64_t)LIGHT_MAXW) {
                 listA_light[atomicAdd((unsigned long long *)&counters[C_A_LIGHT], 1ull)] = vv;
             } else {
-                listA_heavy[atomicAdd((unsigned long long *)&counters[C_A_HEAVY], 1ull)] = vv;
+                push_heavy(listA_heavy, counters, C_A_HEAVY, vv, wa, task_wedges);
                 atomicAdd((unsigned long long *)&counters[C_WEDGES_A_HEAVY], (unsigned long long)wa);
             }
             atomicAdd((unsigned long long *)&counters[C_WEDGES_A], (unsigned long long)wa);
@@ -677,7 +774,7 @@ __global__ void k_cyc_work(const int64_t *__restrict__ nrp, const int32_t *__res
             if (wb <= (uint64_t)LIGHT_MAXW) {
                 listB_light[atomicAdd((unsigned long long *)&counters[C_B_LIGHT], 1ull)] = vv;
             } else {
-                listB_heavy[atomicAdd((unsigned long long *)&counters[C_B_HEAVY], 1ull)] = vv;
+                push_heavy(listB_heavy, counters, C_B_HEAVY, vv, wb, task_wedges);
                 atomicAdd((unsigned long long *)&counters[C_WEDGES_B_HEAVY], (unsigned long long)wb);
             }
             atomicAdd((unsigned long long *)&counters[C_WEDGES_B], (unsigned long long)wb);
@@ -793,9 +890,10 @@ hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8
 }
 
 hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, int64_t n, uint32_t *la_l,
-                           uint32_t *la_h, uint32_t *lb_l, uint32_t *lb_h, uint64_t *counters,
-                           hipStream_t st) {
-    k_cyc_work<<<blocks_for(n, 4), 256, 0, st>>>(nrp, ncol, n, la_l, la_h, lb_l, lb_h, counters);
+                           uint4 *la_h, uint32_t *lb_l, uint4 *lb_h, uint64_t *counters,
+                           uint64_t task_wedges, hipStream_t st) {
+    k_cyc_work<<<blocks_for(n, 4), 256, 0, st>>>(nrp, ncol, n, la_l, la_h, lb_l, lb_h, counters,
+                                                 task_wedges);
     LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -75,3 +75,18 @@ def test_global_key_describe(nt):
             assert L.global_key_describe(nt, q) == (h, ms)
             q += 1
     assert q == L.global_width(nt)
+
+
+def test_tuning_knobs():
+    import paper_2010_14058_amd as P
+
+    base = P.get_tuning()
+    assert base == {"task_wedges": 1 << 18, "clear_bytes": 16}
+    old = P.set_tuning(task_wedges=100, clear_bytes=0)
+    assert old == base and P.get_tuning() == {"task_wedges": 100, "clear_bytes": 0}
+    with pytest.raises(P.TGError):
+        P.set_tuning(task_wedges=0)
+    with pytest.raises(P.TGError):
+        P.set_tuning(clear_bytes=-1)
+    P.set_tuning(**base)
+    assert P.get_tuning() == base

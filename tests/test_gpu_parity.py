@@ -194,3 +194,21 @@ def test_invalid_inputs():
     rp = np.array([0, 1, 2, 3, 4], np.int64)
     col = np.array([1, 0, 9, 2], np.int32)
     assert _status(G.Graph(rp, col, base.types, 2, "range")) == 2
+
+
+@pytest.mark.parametrize("clear_bytes", [0, 1 << 20])
+def test_split_heavy_tasks(oracle_mod, clear_bytes):
+    """Heavy 4-cycle groups split into many target ranges (64 wedges per
+    task), with map ranges cleared by wedge walks (0) or by streaming (large
+    threshold): the counts must not change."""
+    import paper_2010_14058_amd as P
+
+    old = P.set_tuning(task_wedges=64, clear_bytes=clear_bytes)
+    try:
+        g = G.chung_lu_typed(20000, 16.0, 2.1, 3000.0, 5, type_probs=G.zipf_probs(5, 1.2),
+                             homophily=0.6, seed=5, name="cl_20k_split")
+        check(oracle_mod, g)
+        assert P.last_stats()["heavy_groups"] >= 1
+        check(oracle_mod, G.config_graph(2, scale=0.01))
+    finally:
+        P.set_tuning(**old)
