@@ -119,6 +119,8 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G) {
     y.off_gacc = take(sizeof(uint64_t) * gw);
     y.off_sort_tmp = take(y.sort_tmp_bytes);
     y.off_hstart = take(sizeof(int64_t) * (n + 1));
+    y.off_eslot = take(sizeof(uint32_t) * (2 * y.m + 1));
+    y.off_nlow = take(sizeof(uint32_t) * (n + 1));
     const size_t hw = HUB_MAX / 64;
     y.off_HB = take(sizeof(uint64_t) * HUB_MAX * hw);
     y.off_hpre = take(sizeof(uint32_t) * HUB_MAX * hw);
@@ -305,12 +307,14 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     const int32_t hub_base = (int32_t)(n - H);
     HIPCHK(rocprim::radix_sort_pairs(stmp, stmp_bytes, key_a, key_b, val_a, val_b, (size_t)nnz, 0,
                                      2 * bits, st));
-    HIPCHK(launch_finish_csr(key_b, val_b, nnz, bits, ncol, neid, st));
+    uint32_t *eslot = at<uint32_t>(ws, y.off_eslot);
+    uint32_t *nlow = at<uint32_t>(ws, y.off_nlow);
+    HIPCHK(launch_finish_csr(key_b, val_b, nnz, bits, eslot, ncol, neid, st));
     int64_t *hstart = at<int64_t>(ws, y.off_hstart);
     uint64_t *HB = at<uint64_t>(ws, y.off_HB);
     uint32_t *hpre = at<uint32_t>(ws, y.off_hpre);
     uint64_t *TM = at<uint64_t>(ws, y.off_TM);
-    HIPCHK(launch_tdeg(nrp, ncol, ntype, n, L, hub_base, tdeg, hstart, st));
+    HIPCHK(launch_tdeg(nrp, ncol, ntype, n, L, hub_base, tdeg, hstart, nlow, st));
     HIPCHK(launch_hub_build(nrp, ncol, hstart, ntype, n, H, Hw, L, HB, hpre, TM, st));
     HIPCHK(launch_superhubs(nrp, ncol, n, S, nw, SB, SP, st));
     timing_mark("prep");
@@ -324,11 +328,13 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
 
     // ---- 4-cycles from degree-ordered wedges
     HIPCHK(launch_fill_u64(NC, 0, m * LL, st));
-    HIPCHK(launch_cyc_work(nrp, ncol, n, la_l, la_h, lb_l, lb_h, counters,
+    HIPCHK(launch_cyc_work(nrp, ncol, neid, eslot, nlow, n, la_l, la_h, lb_l, lb_h, counters,
                            (uint64_t)g_tune[TG_TUNE_TASK_WEDGES], st));
     timing_mark("cyc_work");
     CycleArgs ca;
     ca.tasks = nullptr;
+    ca.eslot = eslot;
+    ca.nlow = nlow;
     ca.clear_bytes = (uint64_t)g_tune[TG_TUNE_CLEAR_BYTES];
     ca.nrp = nrp; ca.ncol = ncol; ca.ntype = ntype; ca.neid = neid; ca.ei = ei;
     ca.counters = counters; ca.L = L; ca.n = n; ca.NC = NC; ca.maps = maps;
@@ -359,7 +365,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     ea.rows = per_edge; ea.gacc = gacc; ea.gw = gw;
     ea.hist_in_lds = (size_t)gw * sizeof(uint64_t) <= 32768 ? 1 : 0;
     ea.heavy_list = le; ea.counters = counters; ea.tbuf = tbuf; ea.n = n; ea.status = status;
-    ea.hub_base = hub_base; ea.Hw = Hw; ea.hstart = hstart; ea.HB = HB; ea.hpre = hpre; ea.TM = TM;
+    ea.hub_base = hub_base; ea.Hw = Hw; ea.hstart = hstart; ea.nlow = nlow; ea.HB = HB; ea.hpre = hpre; ea.TM = TM;
     ea.sh_base = sh_base; ea.nw = nw; ea.SB = SB; ea.SP = SP;
     ea.batch = batch ? 1 : 0;
     ea.ngraph = ngraph;

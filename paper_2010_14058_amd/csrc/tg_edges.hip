@@ -356,7 +356,7 @@ __device__ void edge_cliques(const EdgeArgs &a, int32_t i, int32_t j, const Edge
         uint32_t len = 0;
         if ((uint32_t)tid < items) {
             int32_t r = (int32_t)S.Tl[c0 + tid];
-            int64_t b = upper_bound(a.ncol, a.nrp[r], a.nrp[r + 1], r);
+            int64_t b = a.nrp[r] + a.nlow[r];
             len = (uint32_t)(a.nrp[r + 1] - b);
             F.r[tid] = (uint32_t)r;
             F.start[tid] = b;

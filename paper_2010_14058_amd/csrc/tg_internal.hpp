@@ -56,7 +56,7 @@ struct Layout {
     size_t off_tdeg, off_tri, off_A, off_D, off_NC;
     size_t off_listA_light, off_listA_heavy, off_listB_light, off_listB_heavy, off_list_edge;
     size_t off_maps, off_tbuf, off_gacc, off_sort_tmp;
-    size_t off_hstart, off_HB, off_hpre, off_TM;
+    size_t off_hstart, off_HB, off_hpre, off_TM, off_eslot, off_nlow;
     size_t off_node_graph, off_ngraph, off_gedge;   // batched graphs only
     size_t off_SB, off_SP;                          // super-hub bitmaps
     int sh_max;
@@ -93,6 +93,8 @@ struct CycleArgs {
     const int32_t *ei;
     const uint32_t *list;      // light groups
     const uint4 *tasks;        // heavy tasks: group, part, parts, wedges of the group
+    const uint32_t *eslot;     // [2e] slot of edge e in the row of its smaller end, [2e+1] larger end
+    const uint32_t *nlow;      // neighbours below the node itself, per node
     uint64_t clear_bytes;      // streamed-clear threshold (bytes per wedge)
     uint64_t *counters;
     int count_idx;
@@ -129,6 +131,7 @@ struct EdgeArgs {
     int32_t hub_base;
     int Hw;                      // 64-bit words per bit row
     const int64_t *hstart;       // first slot of each row's hub suffix
+    const uint32_t *nlow;        // neighbours below the node itself, per node
     const uint64_t *HB;          // [H][Hw] hub adjacency bits
     const uint32_t *hpre;        // [H][Hw] exclusive prefix popcounts
     const uint64_t *TM;          // [L][Hw] hubs of each type
@@ -169,9 +172,11 @@ hipError_t launch_slot_keys(const int64_t *rp, const int32_t *col, const int64_t
                             uint64_t *keys, uint32_t *vals, int32_t *ei, int32_t *ej,
                             uint32_t *status, hipStream_t st);
 hipError_t launch_finish_csr(const uint64_t *keys, const uint32_t *vals, int64_t nnz, int bits,
+                             uint32_t *eslot,
                              int32_t *ncol, uint32_t *neid, hipStream_t st);
 hipError_t launch_tdeg(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype, int64_t n,
-                       int L, int32_t hub_base, uint32_t *tdeg, int64_t *hstart, hipStream_t st);
+                       int L, int32_t hub_base, uint32_t *tdeg, int64_t *hstart, uint32_t *nlow,
+                       hipStream_t st);
 hipError_t launch_hub_build(const int64_t *nrp, const int32_t *ncol, const int64_t *hstart,
                             const uint8_t *ntype, int64_t n, int H, int Hw, int L, uint64_t *HB,
                             uint32_t *pre, uint64_t *TM, hipStream_t st);
@@ -184,7 +189,8 @@ hipError_t launch_superhubs(const int64_t *nrp, const int32_t *ncol, int64_t n, 
 hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype,
                             const uint32_t *neid, const uint32_t *tri, const uint32_t *tdeg,
                             int64_t n, int L, uint64_t *A, uint64_t *D, hipStream_t st);
-hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, int64_t n, uint32_t *la_l,
+hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32_t *neid,
+                           const uint32_t *eslot, const uint32_t *nlow, int64_t n, uint32_t *la_l,
                            uint4 *la_h, uint32_t *lb_l, uint4 *lb_h, uint64_t *counters,
                            uint64_t task_wedges, hipStream_t st);
 int heavy_chunk_for(int L);

@@ -199,13 +199,21 @@ __global__ void k_slot_keys(const int64_t *__restrict__ rp, const int32_t *__res
     if (lane == 0 && bad) atomicOr(status, bad);
 }
 
+// Sorted keys (row << bits | column) to the relabelled CSR, plus the slot of
+// every edge in both of its rows: eslot[2e] in the row of its smaller end,
+// eslot[2e + 1] in the row of its larger end.
 __global__ void k_finish_csr(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
-                             int64_t nnz, int bits, int32_t *__restrict__ ncol,
-                             uint32_t *__restrict__ neid) {
+                             int64_t nnz, int bits, uint32_t *__restrict__ eslot,
+                             int32_t *__restrict__ ncol, uint32_t *__restrict__ neid) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s < nnz) {
-        ncol[s] = (int32_t)(keys[s] & ((1ull << bits) - 1));
-        neid[s] = vals[s];
+        uint64_t k = keys[s];
+        int32_t c = (int32_t)(k & ((1ull << bits) - 1));
+        int32_t r = (int32_t)(k >> bits);
+        uint32_t e = vals[s];
+        ncol[s] = c;
+        neid[s] = e;
+        eslot[2 * (size_t)e + (r < c ? 0 : 1)] = (uint32_t)s;
     }
 }
 
@@ -213,11 +221,15 @@ __global__ void k_finish_csr(const uint64_t *__restrict__ keys, const uint32_t *
 // row's hub suffix (neighbours with internal id >= hub_base).
 __global__ void k_tdeg(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
                        const uint8_t *__restrict__ ntype, int64_t n, int L, int32_t hub_base,
-                       uint32_t *__restrict__ tdeg, int64_t *__restrict__ hstart) {
+                       uint32_t *__restrict__ tdeg, int64_t *__restrict__ hstart,
+                       uint32_t *__restrict__ nlow) {
     int64_t v = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
     int lane = lane_id();
     if (v >= n) return;
-    if (lane == 0) hstart[v] = lower_bound(ncol, nrp[v], nrp[v + 1], hub_base);
+    if (lane == 0) {
+        hstart[v] = lower_bound(ncol, nrp[v], nrp[v + 1], hub_base);
+        nlow[v] = (uint32_t)(lower_bound(ncol, nrp[v], nrp[v + 1], (int32_t)v) - nrp[v]);
+    }
     uint32_t c = 0;
     for (int64_t base = nrp[v]; base < nrp[v + 1]; base += WAVE) {
         int64_t s = base + lane;
@@ -394,19 +406,29 @@ __global__ void k_node_aggr(const int64_t *__restrict__ nrp, const int32_t *__re
 template <int PASS>
 __device__ __forceinline__ void item_range(const CycleArgs &a, int32_t g, int64_t &ib, int64_t &ie) {
     ib = a.nrp[g];
-    if (PASS == 0) ie = lower_bound(a.ncol, a.nrp[g], a.nrp[g + 1], g);
+    if (PASS == 0) ie = ib + a.nlow[g];
     else ie = a.nrp[g + 1];
 }
 
+// Slot of g in the row of its neighbour x, for the item at a slot of g's row
+// holding edge e.
+__device__ __forceinline__ int64_t slot_in_row_of(const CycleArgs &a, int32_t g, int32_t x,
+                                                  uint32_t e) {
+    return (int64_t)a.eslot[2 * (size_t)e + (x < g ? 0 : 1)];
+}
+
+// Targets of item x (edge e) in group g: pass A, x's neighbours below g;
+// pass B, x's neighbours above both g and x.  The row is sorted, so both
+// are contiguous, bounded by g's own slot in x's row or x's split point.
 template <int PASS>
-__device__ __forceinline__ void target_range(const CycleArgs &a, int32_t g, int32_t x, int64_t &tb,
-                                             int64_t &te) {
+__device__ __forceinline__ void target_range(const CycleArgs &a, int32_t g, int32_t x, uint32_t e,
+                                             int64_t &tb, int64_t &te) {
+    const int64_t xb = a.nrp[x];
     if (PASS == 0) {
-        tb = a.nrp[x];
-        te = lower_bound(a.ncol, a.nrp[x], a.nrp[x + 1], g);
+        tb = xb;
+        te = slot_in_row_of(a, g, x, e);
     } else {
-        int32_t lim = g > x ? g : x;
-        tb = upper_bound(a.ncol, a.nrp[x], a.nrp[x + 1], lim);
+        tb = g > x ? slot_in_row_of(a, g, x, e) + 1 : xb + a.nlow[x];
         te = a.nrp[x + 1];
     }
 }
@@ -459,12 +481,12 @@ __global__ void __launch_bounds__(64) k_cyc_light(CycleArgs a) {
                 uint32_t len = 0;
                 if (s < ie) {
                     int32_t x = a.ncol[s];
+                    uint32_t e = a.neid[s];
                     int64_t tb, te;
-                    target_range<PASS>(a, g, x, tb, te);
+                    target_range<PASS>(a, g, x, e, tb, te);
                     len = (uint32_t)(te - tb);
                     it_x[lane] = x;
                     it_tb[lane] = tb;
-                    uint32_t e = a.neid[s];
                     it_eid[lane] = e;
                     it_flip[lane] = phase ? orient_flip<PASS>(a, g, x, e) : 0;
                 }
@@ -593,8 +615,7 @@ __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
                     hi = tk.y + 1 < tk.z ? row_at(a.nrp, rb, re, base + mass * (tk.y + 1) / tk.z)
                                          : re;
                 }
-                int64_t nitem = PASS == 0 ? lower_bound(a.ncol, a.nrp[g], a.nrp[g + 1], g) - a.nrp[g]
-                                          : a.nrp[g + 1] - a.nrp[g];
+                int64_t nitem = PASS == 0 ? (int64_t)a.nlow[g] : a.nrp[g + 1] - a.nrp[g];
                 int ew = nitem < 65536 ? (L + 1) / 2 : L;
                 uint64_t wt = tk.w / tk.z;
                 s_task[0] = g;
@@ -607,6 +628,7 @@ __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
         const int32_t g = s_task[0];
         const int32_t lo = s_task[1], hi = s_task[2];
         const bool streamed = s_task[3] != 0;
+        const bool whole = PASS == 0 ? (lo == 0 && hi == g) : (lo == g + 1 && hi == a.n);
         __syncthreads();
         if (g < 0) break;
         int64_t ib, ie;
@@ -634,21 +656,17 @@ __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
                 if (tid < nitems) {
                     int64_t s = cb + tid;
                     int32_t x = a.ncol[s];
-                    int64_t xb = a.nrp[x], xe = a.nrp[x + 1];
+                    uint32_t e = a.neid[s];
                     int64_t tb, te;
-                    if (PASS == 0) {
-                        tb = lo > 0 ? lower_bound(a.ncol, xb, xe, lo) : xb;
-                        te = lower_bound(a.ncol, xb, xe, hi);
-                    } else {
-                        int32_t first = (g > x ? g : x) + 1;
-                        if (lo > first) first = lo;
-                        tb = lower_bound(a.ncol, xb, xe, first);
-                        te = hi < a.n ? lower_bound(a.ncol, tb, xe, hi) : xe;
+                    target_range<PASS>(a, g, x, e, tb, te);
+                    if (!whole) {
+                        // clip to the task's target range [lo, hi)
+                        if (tb < te && a.ncol[tb] < lo) tb = lower_bound(a.ncol, tb, te, lo);
+                        if (tb < te && a.ncol[te - 1] >= hi) te = lower_bound(a.ncol, tb, te, hi);
                     }
                     len = (uint32_t)(te > tb ? te - tb : 0);
                     it_x[tid] = x;
                     it_tb[tid] = tb;
-                    uint32_t e = a.neid[s];
                     it_eid[tid] = e;
                     it_flip[tid] = orient_flip<PASS>(a, g, x, e);
                 }
@@ -719,66 +737,128 @@ __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
     }
 }
 
-// Queue entries of a heavy group: one per target range.  Splits beyond one
-// entry per group draw on a shared budget of extra slots; when it is spent the
-// group stays whole.
-__device__ void push_heavy(uint4 *tasks, uint64_t *counters, int idx, int32_t g, uint64_t w,
-                           uint64_t task_wedges) {
-    uint64_t p = (w + task_wedges - 1) / task_wedges;
-    if (p > (uint64_t)TASK_MAX_PARTS) p = TASK_MAX_PARTS;
-    if (p > 1) {
-        uint64_t old = atomicAdd((unsigned long long *)&counters[C_TASK_EXTRA],
-                                 (unsigned long long)(p - 1));
-        if (old + (p - 1) > (uint64_t)TASK_EXTRA) p = 1;
+// Wave-wide list appends of the groups found by the lanes of a wave (one
+// counter update per wave and list).  Every lane of the wave calls this with
+// its own node v and wedge count w (0: no group).  Light groups go to
+// `light`; a heavy group gets one queue entry per target range, the splits
+// beyond one entry per group drawing on a shared budget of extra slots (a
+// wave whose splits do not fit keeps its groups whole).
+__device__ void push_groups(int32_t v, uint64_t w, uint32_t *light, uint4 *heavy,
+                            uint64_t *counters, int c_light, int c_heavy, int c_wedges,
+                            int c_wedges_heavy, uint64_t task_wedges) {
+    const int lane = lane_id();
+    const uint64_t below = (1ull << lane) - 1ull;
+    const bool is_light = w && w <= (uint64_t)LIGHT_MAXW;
+    const bool is_heavy = w > (uint64_t)LIGHT_MAXW;
+    uint64_t bl = __ballot(is_light);
+    if (bl) {
+        uint64_t base = 0;
+        if (lane == 0)
+            base = atomicAdd((unsigned long long *)&counters[c_light], (unsigned long long)__popcll(bl));
+        base = __shfl(base, 0, WAVE);
+        if (is_light) light[base + __popcll(bl & below)] = (uint32_t)v;
     }
-    uint64_t base = atomicAdd((unsigned long long *)&counters[idx], (unsigned long long)p);
+    uint64_t tot = wave_sum_u64(w);
+    uint64_t tot_heavy = wave_sum_u64(is_heavy ? w : 0ull);
+    if (lane == 0 && tot) atomicAdd((unsigned long long *)&counters[c_wedges], (unsigned long long)tot);
+    uint64_t bh = __ballot(is_heavy);
+    if (!bh) return;
+    if (lane == 0) {
+        atomicAdd((unsigned long long *)&counters[c_wedges_heavy], (unsigned long long)tot_heavy);
+        atomicAdd((unsigned long long *)&counters[C_HEAVY_GROUPS], (unsigned long long)__popcll(bh));
+    }
+    uint32_t parts = 0;
+    if (is_heavy) {
+        uint64_t q = (w + task_wedges - 1) / task_wedges;
+        parts = (uint32_t)(q > (uint64_t)TASK_MAX_PARTS ? TASK_MAX_PARTS : q);
+    }
+    uint32_t extra = wave_incl_scan(parts ? parts - 1 : 0u);
+    uint32_t extra_tot = __shfl(extra, WAVE - 1, WAVE);
+    if (extra_tot) {
+        int ok = 1;
+        if (lane == 0) {
+            uint64_t old = atomicAdd((unsigned long long *)&counters[C_TASK_EXTRA],
+                                     (unsigned long long)extra_tot);
+            ok = old + extra_tot <= (uint64_t)TASK_EXTRA;
+        }
+        if (!__shfl(ok, 0, WAVE) && parts) parts = 1;
+    }
+    uint32_t incl = wave_incl_scan(parts);
+    uint32_t all = __shfl(incl, WAVE - 1, WAVE);
+    uint64_t base = 0;
+    if (lane == 0) base = atomicAdd((unsigned long long *)&counters[c_heavy], (unsigned long long)all);
+    base = __shfl(base, 0, WAVE) + (incl - parts);
     uint32_t wc = w > 0xffffffffull ? 0xffffffffu : (uint32_t)w;
-    for (uint32_t k = 0; k < (uint32_t)p; ++k)
-        tasks[base + k] = make_uint4((uint32_t)g, k, (uint32_t)p, wc);
-    atomicAdd((unsigned long long *)&counters[C_HEAVY_GROUPS], 1ull);
+    for (uint32_t k = 0; k < parts; ++k) heavy[base + k] = make_uint4((uint32_t)v, k, parts, wc);
 }
 
-// One wave per internal node: wedge counts of both passes, bucketed into
-// light and heavy lists.
-__global__ void k_cyc_work(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
-                           int64_t n, uint32_t *__restrict__ listA_light,
-                           uint4 *__restrict__ listA_heavy, uint32_t *__restrict__ listB_light,
-                           uint4 *__restrict__ listB_heavy, uint64_t *__restrict__ counters,
-                           uint64_t task_wedges) {
-    int64_t v = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
-    int lane = lane_id();
-    if (v >= n) return;
-    int32_t vv = (int32_t)v;
-    int64_t b = nrp[v], e = nrp[v + 1];
-    uint64_t wa = 0, wb = 0;
-    for (int64_t s = b + lane; s < e; s += WAVE) {
-        int32_t x = ncol[s];
-        int64_t xb = nrp[x], xe = nrp[x + 1];
-        if (x < vv) wa += (uint64_t)(lower_bound(ncol, xb, xe, vv) - xb);
-        int32_t lim = vv > x ? vv : x;
-        wb += (uint64_t)(xe - upper_bound(ncol, xb, xe, lim));
+// Wedges of node v in both passes from its own row: for a neighbour x below
+// v, v's slot in x's row splits x's row into pass-A targets (below v) and
+// pass-B targets (above v); for x above v, pass B takes x's neighbours above
+// x (x's split point).
+__device__ __forceinline__ void node_wedges(const int64_t *__restrict__ nrp,
+                                            const int32_t *__restrict__ ncol,
+                                            const uint32_t *__restrict__ neid,
+                                            const uint32_t *__restrict__ eslot,
+                                            const uint32_t *__restrict__ nlow, int32_t v, int64_t s,
+                                            uint64_t &wa, uint64_t &wb) {
+    int32_t x = ncol[s];
+    int64_t xb = nrp[x], xe = nrp[x + 1];
+    if (x < v) {
+        int64_t r = (int64_t)eslot[2 * (size_t)neid[s] + 0];
+        wa += (uint64_t)(r - xb);
+        wb += (uint64_t)(xe - r - 1);
+    } else {
+        wb += (uint64_t)(xe - xb - nlow[x]);
     }
-    wa = wave_sum_u64(wa);
-    wb = wave_sum_u64(wb);
-    if (lane == 0) {
-        if (wa) {
-            if (wa <= (uint64_t)LIGHT_MAXW) {
-                listA_light[atomicAdd((unsigned long long *)&counters[C_A_LIGHT], 1ull)] = vv;
-            } else {
-                push_heavy(listA_heavy, counters, C_A_HEAVY, vv, wa, task_wedges);
-                atomicAdd((unsigned long long *)&counters[C_WEDGES_A_HEAVY], (unsigned long long)wa);
-            }
-            atomicAdd((unsigned long long *)&counters[C_WEDGES_A], (unsigned long long)wa);
+}
+
+// Wedge counts of both passes per node, bucketed into light and heavy lists.
+// Node ids are ranked by degree, so nodes below the first one of degree >=
+// 64 are taken one per lane (64 nodes of similar degree per wave) and the
+// rest one per wave.
+__global__ void __launch_bounds__(256) k_cyc_work(
+    const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
+    const uint32_t *__restrict__ neid, const uint32_t *__restrict__ eslot,
+    const uint32_t *__restrict__ nlow, int64_t n, uint32_t *__restrict__ listA_light,
+    uint4 *__restrict__ listA_heavy, uint32_t *__restrict__ listB_light,
+    uint4 *__restrict__ listB_heavy, uint64_t *__restrict__ counters, uint64_t task_wedges) {
+    __shared__ int64_t s_thr;
+    if (threadIdx.x == 0) {
+        int64_t lo = 0, hi = n;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (nrp[mid + 1] - nrp[mid] < WAVE) lo = mid + 1; else hi = mid;
         }
-        if (wb) {
-            if (wb <= (uint64_t)LIGHT_MAXW) {
-                listB_light[atomicAdd((unsigned long long *)&counters[C_B_LIGHT], 1ull)] = vv;
-            } else {
-                push_heavy(listB_heavy, counters, C_B_HEAVY, vv, wb, task_wedges);
-                atomicAdd((unsigned long long *)&counters[C_WEDGES_B_HEAVY], (unsigned long long)wb);
-            }
-            atomicAdd((unsigned long long *)&counters[C_WEDGES_B], (unsigned long long)wb);
-        }
+        s_thr = lo;
+    }
+    __syncthreads();
+    const int64_t thr = s_thr;
+    const int lane = lane_id();
+    const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    const int64_t chunks = (thr + WAVE - 1) / WAVE;
+    for (int64_t c = wid; c < chunks; c += nwaves) {
+        const int64_t v = c * WAVE + lane;
+        uint64_t wa = 0, wb = 0;
+        if (v < thr)
+            for (int64_t s = nrp[v]; s < nrp[v + 1]; ++s)
+                node_wedges(nrp, ncol, neid, eslot, nlow, (int32_t)v, s, wa, wb);
+        push_groups((int32_t)v, wa, listA_light, listA_heavy, counters, C_A_LIGHT, C_A_HEAVY,
+                    C_WEDGES_A, C_WEDGES_A_HEAVY, task_wedges);
+        push_groups((int32_t)v, wb, listB_light, listB_heavy, counters, C_B_LIGHT, C_B_HEAVY,
+                    C_WEDGES_B, C_WEDGES_B_HEAVY, task_wedges);
+    }
+    for (int64_t v = thr + wid; v < n; v += nwaves) {
+        uint64_t wa = 0, wb = 0;
+        for (int64_t s = nrp[v] + lane; s < nrp[v + 1]; s += WAVE)
+            node_wedges(nrp, ncol, neid, eslot, nlow, (int32_t)v, s, wa, wb);
+        wa = wave_sum_u64(wa);
+        wb = wave_sum_u64(wb);
+        push_groups((int32_t)v, lane == 0 ? wa : 0ull, listA_light, listA_heavy, counters,
+                    C_A_LIGHT, C_A_HEAVY, C_WEDGES_A, C_WEDGES_A_HEAVY, task_wedges);
+        push_groups((int32_t)v, lane == 0 ? wb : 0ull, listB_light, listB_heavy, counters,
+                    C_B_LIGHT, C_B_HEAVY, C_WEDGES_B, C_WEDGES_B_HEAVY, task_wedges);
     }
 }
 
@@ -855,16 +935,17 @@ hipError_t launch_slot_keys(const int64_t *rp, const int32_t *col, const int64_t
 }
 
 hipError_t launch_finish_csr(const uint64_t *keys, const uint32_t *vals, int64_t nnz, int bits,
-                             int32_t *ncol, uint32_t *neid, hipStream_t st) {
+                             uint32_t *eslot, int32_t *ncol, uint32_t *neid, hipStream_t st) {
     if (nnz == 0) return hipSuccess;
-    k_finish_csr<<<blocks_for(nnz, 256), 256, 0, st>>>(keys, vals, nnz, bits, ncol, neid);
+    k_finish_csr<<<blocks_for(nnz, 256), 256, 0, st>>>(keys, vals, nnz, bits, eslot, ncol, neid);
     LAUNCH_CHECK();
     return hipSuccess;
 }
 
 hipError_t launch_tdeg(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype, int64_t n,
-                       int L, int32_t hub_base, uint32_t *tdeg, int64_t *hstart, hipStream_t st) {
-    k_tdeg<<<blocks_for(n, 4), 256, 0, st>>>(nrp, ncol, ntype, n, L, hub_base, tdeg, hstart);
+                       int L, int32_t hub_base, uint32_t *tdeg, int64_t *hstart, uint32_t *nlow,
+                       hipStream_t st) {
+    k_tdeg<<<blocks_for(n, 4), 256, 0, st>>>(nrp, ncol, ntype, n, L, hub_base, tdeg, hstart, nlow);
     LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -889,10 +970,21 @@ hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8
     return hipSuccess;
 }
 
-hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, int64_t n, uint32_t *la_l,
+hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32_t *neid,
+                           const uint32_t *eslot, const uint32_t *nlow, int64_t n, uint32_t *la_l,
                            uint4 *la_h, uint32_t *lb_l, uint4 *lb_h, uint64_t *counters,
                            uint64_t task_wedges, hipStream_t st) {
-    k_cyc_work<<<blocks_for(n, 4), 256, 0, st>>>(nrp, ncol, n, la_l, la_h, lb_l, lb_h, counters,
+    if (n <= 0) return hipSuccess;
+    int dev = 0, cus = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return err;
+    err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (err != hipSuccess) return err;
+    int64_t want = (n + 4 * WAVE - 1) / (4 * WAVE) + 1;
+    int64_t cap = (int64_t)(cus > 0 ? cus : 256) * 16;
+    unsigned grid = (unsigned)(want < cap ? want : cap);
+    k_cyc_work<<<grid, 256, 0, st>>>(nrp, ncol, neid, eslot, nlow, n, la_l, la_h, lb_l,
+                                                 lb_h, counters,
                                                  task_wedges);
     LAUNCH_CHECK();
     return hipSuccess;
