@@ -106,6 +106,7 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G) {
     y.off_ej = take(sizeof(int32_t) * (y.m + 1));
     y.off_tdeg = take(sizeof(uint32_t) * (n + 1) * L);
     y.off_tri = take(sizeof(uint32_t) * (y.m + 1) * L);
+    y.off_tri_slot = take(sizeof(uint32_t) * (size_t)(nnz + 1) * tri_pitch(L));
     y.off_A = take(sizeof(uint64_t) * (n + 1) * LL);
     y.off_D = take(sizeof(uint64_t) * (n + 1) * LL);
     y.off_NC = take(sizeof(uint64_t) * (y.m + 1) * LL);
@@ -225,6 +226,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     int32_t *ej = at<int32_t>(ws, y.off_ej);
     uint32_t *tdeg = at<uint32_t>(ws, y.off_tdeg);
     uint32_t *tri = at<uint32_t>(ws, y.off_tri);
+    uint32_t *tri_slot = at<uint32_t>(ws, y.off_tri_slot);
     uint64_t *A = at<uint64_t>(ws, y.off_A);
     uint64_t *D = at<uint64_t>(ws, y.off_D);
     uint64_t *NC = at<uint64_t>(ws, y.off_NC);
@@ -320,10 +322,10 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     timing_mark("prep");
 
     // ---- typed triangles and node aggregates
-    HIPCHK(launch_tri(nrp, ncol, ntype, ei, ej, m, L, tri, counters + C_TRI_SUM, sh_base, nw, SB,
+    HIPCHK(launch_tri(nrp, ncol, ntype, ei, ej, eslot, tri_slot, m, L, tri, counters + C_TRI_SUM, sh_base, nw, SB,
                       st));
     timing_mark("tri");
-    HIPCHK(launch_node_aggr(nrp, ncol, ntype, neid, tri, tdeg, n, L, A, D, st));
+    HIPCHK(launch_node_aggr(nrp, ncol, ntype, tri_slot, tdeg, n, L, A, D, st));
     timing_mark("aggr");
 
     // ---- 4-cycles from degree-ordered wedges
@@ -361,7 +363,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     // ---- cliques, derivation, rows and global counts
     EdgeArgs ea;
     ea.nrp = nrp; ea.ncol = ncol; ea.ntype = ntype; ea.neid = neid; ea.ei = ei; ea.ej = ej;
-    ea.tri = tri; ea.tdeg = tdeg; ea.A = A; ea.D = D; ea.NC = NC; ea.m = m; ea.L = L;
+    ea.tri = tri; ea.tdeg = tdeg; ea.tri_slot = tri_slot; ea.A = A; ea.D = D; ea.NC = NC; ea.m = m; ea.L = L;
     ea.rows = per_edge; ea.gacc = gacc; ea.gw = gw;
     ea.hist_in_lds = (size_t)gw * sizeof(uint64_t) <= 32768 ? 1 : 0;
     ea.heavy_list = le; ea.counters = counters; ea.tbuf = tbuf; ea.n = n; ea.status = status;

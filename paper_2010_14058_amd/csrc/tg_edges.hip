@@ -117,11 +117,13 @@ __device__ __forceinline__ bool hub_adj(const EdgeArgs &a, int hy, int hx) {
 __device__ __forceinline__ void gather_member(const EdgeArgs &a, int32_t k, int64_t s_i, int64_t s_j,
                                               uint64_t *Xi, uint64_t *Xj, uint64_t *Y) {
     const int L = a.L;
-    uint32_t eik = a.neid[s_i], ejk = a.neid[s_j];
+    const int LP = tri_pitch(L);
+    const uint32_t *ri = a.tri_slot + (size_t)s_i * LP;
+    const uint32_t *rj = a.tri_slot + (size_t)s_j * LP;
     int t = a.ntype[k];
     for (int t2 = 0; t2 < L; ++t2) {
-        uint32_t vi = a.tri[(size_t)eik * L + t2];
-        uint32_t vj = a.tri[(size_t)ejk * L + t2];
+        uint32_t vi = ri[t2];
+        uint32_t vj = rj[t2];
         uint32_t vy = a.tdeg[(size_t)k * L + t2];
         if (vi) atomicAdd((unsigned long long *)&Xi[t * L + t2], (unsigned long long)vi);
         if (vj) atomicAdd((unsigned long long *)&Xj[t * L + t2], (unsigned long long)vj);
@@ -306,49 +308,91 @@ __device__ void edge_cliques(const EdgeArgs &a, int32_t i, int32_t j, const Edge
     // both endpoints super-hubs: low membership of T by two bitmap probes
     const bool both_sh = i >= a.sh_base && j >= a.sh_base;
     const int si = i - a.sh_base, sj = j - a.sh_base;
-    if (nTh) {
-        const uint32_t wlo = S.meta[2], whi = S.meta[3];
-        const uint32_t range = whi - wlo + 1;
-        const bool pair_mode = nTh <= range;
-        for (uint32_t idx = tid; idx < nTh; idx += NT) {
-            int32_t k = (int32_t)S.Th[idx];
-            int hk = k - base;
-            int tk = a.ntype[k];
-            uint32_t cnt[TG_MAX_L];
-#pragma unroll
-            for (int t = 0; t < TG_MAX_L; ++t) cnt[t] = 0;
-            const uint64_t *rowk = a.HB + (size_t)hk * Hw;
-            if (pair_mode) {
-                for (uint32_t jdx = 0; jdx < nTh; ++jdx) {
-                    int hx = (int)S.Th[jdx] - base;
-                    if ((rowk[hx >> 6] >> (hx & 63)) & 1ull) {
-                        int tx = a.ntype[base + hx];
-#pragma unroll
-                        for (int t = 0; t < TG_MAX_L; ++t) cnt[t] += (t == tx);
-                    }
-                }
-            } else {
-                // whole 64-byte blocks of the bit row (rows are padded to
-                // multiples of 8 words): four 16-byte loads per block
-                const uint32_t q0 = wlo & ~7u, q1 = (whi | 7u) + 1;
-                for (uint32_t q = q0; q < q1; q += 8) {
-                    const ulonglong2 *rp = reinterpret_cast<const ulonglong2 *>(rowk + q);
-                    ulonglong2 r0 = rp[0], r1 = rp[1], r2 = rp[2], r3 = rp[3];
-                    uint64_t w[8] = {r0.x, r0.y, r1.x, r1.y, r2.x, r2.y, r3.x, r3.y};
-#pragma unroll
-                    for (int b = 0; b < 8; ++b) {
-                        uint64_t v = w[b] & S.Tm[q + b];
-                        if (!v) continue;
-#pragma unroll
-                        for (int t = 0; t < TG_MAX_L; ++t)
-                            if (t < L) cnt[t] += (uint32_t)__popcll(v & TMs[t * Hw + q + b]);
-                    }
+    if (nTh >= 2) {
+        // each unordered hub pair {k, x} once, from its lower member, adding
+        // both orders; the work is spread over all threads
+        const uint32_t b0 = S.meta[2] >> 3, b1 = (S.meta[3] >> 3) + 1;  // 64-byte blocks
+        const uint32_t nb = b1 - b0;
+        if (nTh <= 8 * nb + 1) {
+            // few members: test every pair's bit
+            const uint32_t P = nTh * (nTh - 1) / 2;
+            for (uint32_t f = tid; f < P; f += NT) {
+                // f = bb (bb - 1) / 2 + aa with aa < bb
+                uint32_t bb = (uint32_t)((1.0 + sqrt(1.0 + 8.0 * (double)f)) * 0.5);
+                while (bb * (bb - 1) / 2 > f) --bb;
+                while ((bb + 1) * bb / 2 <= f) ++bb;
+                const uint32_t aa = f - bb * (bb - 1) / 2;
+                const int32_t k = (int32_t)S.Th[aa], x = (int32_t)S.Th[bb];
+                const int hk = k - base, hx = x - base;
+                if ((a.HB[(size_t)hk * Hw + (hx >> 6)] >> (hx & 63)) & 1ull) {
+                    const int tk = a.ntype[k], tx = a.ntype[x];
+                    atomicAdd((unsigned long long *)&S.K[tk * L + tx], 1ull);
+                    atomicAdd((unsigned long long *)&S.K[tx * L + tk], 1ull);
                 }
             }
+        } else {
+            // member k's bit row from its own block on (bits above k), AND
+            // the hub mask of T, counted by type; items (member, block) are
+            // laid out member by member and each thread takes a contiguous
+            // run of them, so counts of one member add up in registers
+            for (uint32_t c0 = 0; c0 < nTh; c0 += NT) {
+                const uint32_t members = nTh - c0 < (uint32_t)NT ? nTh - c0 : (uint32_t)NT;
+                uint32_t len = 0;
+                if ((uint32_t)tid < members) {
+                    const int32_t k = (int32_t)S.Th[c0 + tid];
+                    const uint32_t kb = (uint32_t)(k - base) >> 9;
+                    const uint32_t sb = kb > b0 ? kb : b0;
+                    len = sb < b1 ? b1 - sb : 0;
+                    F.r[tid] = (uint32_t)k;
+                    F.start[tid] = sb;
+                }
+                uint32_t incl = group_incl_scan<NT>(len, S.wave_cnt);
+                F.scan[tid] = incl;
+                group_sync<NT>();
+                const uint32_t total = F.scan[members - 1];
+                const uint32_t per = (total + NT - 1) / NT;
+                uint32_t f = (uint32_t)tid * per;
+                const uint32_t fe = f + per < total ? f + per : total;
+                int o = f < fe ? owner_of(F.scan, (int)members, f) : 0;
+                while (f < fe) {
+                    const int32_t k = (int32_t)F.r[o];
+                    const int hk = k - base;
+                    const int tk = a.ntype[k];
+                    const uint32_t oend = F.scan[o] < fe ? F.scan[o] : fe;
+                    const uint32_t excl = o ? F.scan[o - 1] : 0;
+                    const uint64_t *rowk = a.HB + (size_t)hk * Hw;
+                    uint32_t cnt[TG_MAX_L];
 #pragma unroll
-            for (int t = 0; t < TG_MAX_L; ++t)
-                if (t < L && cnt[t])
-                    atomicAdd((unsigned long long *)&S.K[tk * L + t], (unsigned long long)cnt[t]);
+                    for (int t = 0; t < TG_MAX_L; ++t) cnt[t] = 0;
+                    for (; f < oend; ++f) {
+                        const uint32_t q = ((uint32_t)F.start[o] + (f - excl)) * 8;
+                        const ulonglong2 *rp = reinterpret_cast<const ulonglong2 *>(rowk + q);
+                        ulonglong2 r0 = rp[0], r1 = rp[1], r2 = rp[2], r3 = rp[3];
+                        uint64_t w[8] = {r0.x, r0.y, r1.x, r1.y, r2.x, r2.y, r3.x, r3.y};
+#pragma unroll
+                        for (int bq = 0; bq < 8; ++bq) {
+                            const int word = (int)q + bq;
+                            uint64_t v = w[bq] & S.Tm[word];
+                            // keep members above k only
+                            if (word < (hk >> 6)) v = 0;
+                            else if (word == (hk >> 6))
+                                v &= (hk & 63) == 63 ? 0ull : (~0ull << ((hk & 63) + 1));
+                            if (!v) continue;
+#pragma unroll
+                            for (int t = 0; t < TG_MAX_L; ++t)
+                                if (t < L) cnt[t] += (uint32_t)__popcll(v & TMs[t * Hw + word]);
+                        }
+                    }
+#pragma unroll
+                    for (int t = 0; t < TG_MAX_L; ++t)
+                        if (t < L && cnt[t]) {
+                            atomicAdd((unsigned long long *)&S.K[tk * L + t], (unsigned long long)cnt[t]);
+                            atomicAdd((unsigned long long *)&S.K[t * L + tk], (unsigned long long)cnt[t]);
+                        }
+                    ++o;
+                }
+                group_sync<NT>();
+            }
         }
     }
     for (uint32_t c0 = 0; c0 < nTl; c0 += NT) {

@@ -53,7 +53,7 @@ struct Layout {
     size_t off_deg, off_ucount, off_eoff, off_order, off_newid, off_ntype, off_nrp, off_ndeg;
     size_t off_key_a, off_key_b, off_val_a, off_val_b;
     size_t off_ncol, off_neid, off_ei, off_ej;
-    size_t off_tdeg, off_tri, off_A, off_D, off_NC;
+    size_t off_tdeg, off_tri, off_tri_slot, off_A, off_D, off_NC;
     size_t off_listA_light, off_listA_heavy, off_listB_light, off_listB_heavy, off_list_edge;
     size_t off_maps, off_tbuf, off_gacc, off_sort_tmp;
     size_t off_hstart, off_HB, off_hpre, off_TM, off_eslot, off_nlow;
@@ -115,6 +115,7 @@ struct EdgeArgs {
     const uint32_t *neid;
     const int32_t *ei, *ej;
     const uint32_t *tri, *tdeg;
+    const uint32_t *tri_slot;    // typed triangle counts per slot, rows of tri_pitch(L)
     const uint64_t *A, *D, *NC;
     int64_t m;
     int L;
@@ -180,14 +181,19 @@ hipError_t launch_tdeg(const int64_t *nrp, const int32_t *ncol, const uint8_t *n
 hipError_t launch_hub_build(const int64_t *nrp, const int32_t *ncol, const int64_t *hstart,
                             const uint8_t *ntype, int64_t n, int H, int Hw, int L, uint64_t *HB,
                             uint32_t *pre, uint64_t *TM, hipStream_t st);
+// Row pitch (uint32 words) of per-slot typed triangle counts: L rounded up
+// to a multiple of 4, for 16-byte loads.
+__host__ __device__ inline int tri_pitch(int L) { return (L + 3) & ~3; }
+
 hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype,
-                      const int32_t *ei, const int32_t *ej, int64_t m, int L, uint32_t *tri,
+                      const int32_t *ei, const int32_t *ej, const uint32_t *eslot,
+                      uint32_t *tri_slot, int64_t m, int L, uint32_t *tri,
                       uint64_t *tri_sum, int32_t sh_base, int64_t nw, const uint64_t *SB,
                       hipStream_t st);
 hipError_t launch_superhubs(const int64_t *nrp, const int32_t *ncol, int64_t n, int S, int64_t nw,
                             uint64_t *SB, uint32_t *SP, hipStream_t st);
 hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype,
-                            const uint32_t *neid, const uint32_t *tri, const uint32_t *tdeg,
+                            const uint32_t *tri_slot, const uint32_t *tdeg,
                             int64_t n, int L, uint64_t *A, uint64_t *D, hipStream_t st);
 hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32_t *neid,
                            const uint32_t *eslot, const uint32_t *nlow, int64_t n, uint32_t *la_l,

@@ -253,7 +253,8 @@ constexpr int TRI_LANES = WAVE / TRI_GROUPS;
 
 __global__ void k_tri(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
                       const uint8_t *__restrict__ ntype, const int32_t *__restrict__ ei,
-                      const int32_t *__restrict__ ej, int64_t m, int L,
+                      const int32_t *__restrict__ ej, const uint32_t *__restrict__ eslot,
+                      uint32_t *__restrict__ tri_slot, int64_t m, int L,
                       uint32_t *__restrict__ tri, uint64_t *__restrict__ tri_sum, int32_t sh_base,
                       int64_t nw, const uint64_t *__restrict__ SB) {
     int64_t wave = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
@@ -297,7 +298,12 @@ __global__ void k_tri(const int64_t *__restrict__ nrp, const int32_t *__restrict
             uint32_t v = cnt[t];
 #pragma unroll
             for (int d = 1; d < TRI_LANES; d <<= 1) v += __shfl_xor(v, d, WAVE);
-            if (gl == 0 && e < m) tri[e * L + t] = v;
+            if (gl == 0 && e < m) {
+                tri[e * L + t] = v;
+                const int LP = tri_pitch(L);
+                tri_slot[(size_t)eslot[2 * e] * LP + t] = v;
+                tri_slot[(size_t)eslot[2 * e + 1] * LP + t] = v;
+            }
             tot += v;
         }
     }
@@ -358,8 +364,8 @@ __global__ void __launch_bounds__(256) k_superhubs(const int64_t *__restrict__ n
 
 // One wave per internal node u; LDS holds A_u and D_u (L x L uint64 each).
 __global__ void k_node_aggr(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
-                            const uint8_t *__restrict__ ntype, const uint32_t *__restrict__ neid,
-                            const uint32_t *__restrict__ tri, const uint32_t *__restrict__ tdeg,
+                            const uint8_t *__restrict__ ntype, const uint32_t *__restrict__ tri_slot,
+                            const uint32_t *__restrict__ tdeg,
                             int64_t n, int L, uint64_t *__restrict__ A, uint64_t *__restrict__ D) {
     extern __shared__ uint64_t sm_aggr[];
     int w = threadIdx.x / WAVE;
@@ -374,9 +380,9 @@ __global__ void k_node_aggr(const int64_t *__restrict__ nrp, const int32_t *__re
     for (int64_t s = nrp[u] + lane; s < nrp[u + 1]; s += WAVE) {
         int32_t k = ncol[s];
         int t = ntype[k];
-        uint32_t e = neid[s];
+        const uint32_t *ts = tri_slot + (size_t)s * tri_pitch(L);
         for (int t2 = 0; t2 < L; ++t2) {
-            uint32_t a = tri[(size_t)e * L + t2];
+            uint32_t a = ts[t2];
             uint32_t d = tdeg[(size_t)k * L + t2];
             if (a) atomicAdd((unsigned long long *)&sA[t * L + t2], (unsigned long long)a);
             if (d) atomicAdd((unsigned long long *)&sD[t * L + t2], (unsigned long long)d);
@@ -951,21 +957,22 @@ hipError_t launch_tdeg(const int64_t *nrp, const int32_t *ncol, const uint8_t *n
 }
 
 hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype,
-                      const int32_t *ei, const int32_t *ej, int64_t m, int L, uint32_t *tri,
+                      const int32_t *ei, const int32_t *ej, const uint32_t *eslot,
+                      uint32_t *tri_slot, int64_t m, int L, uint32_t *tri,
                       uint64_t *tri_sum, int32_t sh_base, int64_t nw, const uint64_t *SB,
                       hipStream_t st) {
     if (m == 0) return hipSuccess;
-    k_tri<<<blocks_for(m, 4 * TRI_GROUPS), 256, 0, st>>>(nrp, ncol, ntype, ei, ej, m, L, tri,
+    k_tri<<<blocks_for(m, 4 * TRI_GROUPS), 256, 0, st>>>(nrp, ncol, ntype, ei, ej, eslot, tri_slot, m, L, tri,
                                                          tri_sum, sh_base, nw, SB);
     LAUNCH_CHECK();
     return hipSuccess;
 }
 
 hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype,
-                            const uint32_t *neid, const uint32_t *tri, const uint32_t *tdeg,
+                            const uint32_t *tri_slot, const uint32_t *tdeg,
                             int64_t n, int L, uint64_t *A, uint64_t *D, hipStream_t st) {
     size_t sh = (size_t)4 * 2 * L * L * sizeof(uint64_t);
-    k_node_aggr<<<blocks_for(n, 4), 256, sh, st>>>(nrp, ncol, ntype, neid, tri, tdeg, n, L, A, D);
+    k_node_aggr<<<blocks_for(n, 4), 256, sh, st>>>(nrp, ncol, ntype, tri_slot, tdeg, n, L, A, D);
     LAUNCH_CHECK();
     return hipSuccess;
 }
