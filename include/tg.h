@@ -161,11 +161,25 @@ const char *tg_last_error(void);
  *   TG_TUNE_CLEAR_BYTES  (default 16, >= 0): a task clears its map range by
  *       streaming zeros when the range costs at most this many bytes per
  *       wedge of the task, else by a walk over its wedges; 0 never streams.
+ *   TG_TUNE_CYCLE_SLOTS  (default 1024, 1..65536): most workgroups of the heavy
+ *       4-cycle kernels; each owns a dense map of n*L*4 bytes of workspace.
+ *   TG_TUNE_MAP_BYTES    (default 32 GiB, >= 1): workspace bytes for those
+ *       maps; the slot count is cut to fit (at least one slot).
+ *   TG_TUNE_EDGE_SLOTS   (default 1024, 1..65536): most workgroups of the
+ *       heavy-edge kernel; each owns a list of n*4 bytes of workspace.
+ *   TG_TUNE_TBUF_BYTES   (default 8 GiB, >= 1): workspace bytes for those
+ *       lists; the slot count is cut to fit (at least one slot).
+ * The last four change tg_workspace_bytes and tg_batch_workspace_bytes, so
+ * they must be set before the workspace is sized.
  * tg_set_tuning returns TG_E_INVALID_ARG for an unknown knob or a value out
  * of range; tg_get_tuning returns the current value (-1 if unknown). */
 typedef enum {
     TG_TUNE_TASK_WEDGES = 0,
-    TG_TUNE_CLEAR_BYTES = 1
+    TG_TUNE_CLEAR_BYTES = 1,
+    TG_TUNE_CYCLE_SLOTS = 2,
+    TG_TUNE_MAP_BYTES = 3,
+    TG_TUNE_EDGE_SLOTS = 4,
+    TG_TUNE_TBUF_BYTES = 5
 } tg_tune;
 tg_status tg_set_tuning(int32_t knob, int64_t value);
 int64_t tg_get_tuning(int32_t knob);

@@ -119,7 +119,8 @@ def phase_times() -> list[tuple[str, float]]:
     return [(names[q].decode(), float(ms[q])) for q in range(max(cnt, 0))]
 
 
-TUNE_KNOBS = {"task_wedges": 0, "clear_bytes": 1}
+TUNE_KNOBS = {"task_wedges": 0, "clear_bytes": 1, "cycle_slots": 2, "map_bytes": 3,
+              "edge_slots": 4, "tbuf_bytes": 5}
 
 
 def set_tuning(**knobs) -> dict:

@@ -30,9 +30,13 @@ static int bits_for(int64_t n) {
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Bytes of dense cycle maps allowed; the number of heavy workgroups follows.
-static const size_t MAP_BUDGET = size_t(8) << 30;
-static const size_t TBUF_BUDGET = size_t(2) << 30;
-static const int MAX_HEAVY_SLOTS = 512;
+static const size_t MAP_BUDGET = size_t(32) << 30;
+static const size_t TBUF_BUDGET = size_t(8) << 30;
+static const int MAX_HEAVY_SLOTS = 1024;
+
+// Scheduling knobs (tg_set_tuning), per host thread.
+thread_local int64_t g_tune[6] = {TASK_WEDGES, SEQ_CLEAR_BYTES, MAX_HEAVY_SLOTS,
+                                   (int64_t)MAP_BUDGET, MAX_HEAVY_SLOTS, (int64_t)TBUF_BUDGET};
 
 static size_t sort_tmp_bytes(int64_t n, int64_t nnz) {
     size_t a = 0, b = 0, c = 0;
@@ -66,13 +70,13 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G) {
     y.L = L;
     int64_t LL = (int64_t)L * L;
     size_t per_map = (size_t)(n > 0 ? n : 1) * L * sizeof(uint32_t);
-    int64_t slots = (int64_t)(MAP_BUDGET / per_map);
-    if (slots > MAX_HEAVY_SLOTS) slots = MAX_HEAVY_SLOTS;
+    int64_t slots = (int64_t)((size_t)g_tune[TG_TUNE_MAP_BYTES] / per_map);
+    if (slots > g_tune[TG_TUNE_CYCLE_SLOTS]) slots = g_tune[TG_TUNE_CYCLE_SLOTS];
     if (slots < 1) slots = 1;
     y.heavy_slots = (int)slots;
     size_t per_t = (size_t)(n > 0 ? n : 1) * sizeof(uint32_t);
-    int64_t eslots = (int64_t)(TBUF_BUDGET / per_t);
-    if (eslots > MAX_HEAVY_SLOTS) eslots = MAX_HEAVY_SLOTS;
+    int64_t eslots = (int64_t)((size_t)g_tune[TG_TUNE_TBUF_BYTES] / per_t);
+    if (eslots > g_tune[TG_TUNE_EDGE_SLOTS]) eslots = g_tune[TG_TUNE_EDGE_SLOTS];
     if (eslots < 1) eslots = 1;
     y.heavy_edge_slots = (int)eslots;
     y.sort_tmp_bytes = sort_tmp_bytes(n, nnz);
@@ -155,7 +159,6 @@ struct Timing {
     int64_t stats[8] = {0};
 };
 thread_local Timing g_timing;
-thread_local int64_t g_tune[2] = {TASK_WEDGES, SEQ_CLEAR_BYTES};
 
 void timing_reset(hipStream_t st) {
     g_timing.used = 0;
@@ -563,6 +566,14 @@ tg_status tg_set_tuning(int32_t knob, int64_t value) {
     case TG_TUNE_CLEAR_BYTES:
         if (value < 0 || value > (int64_t(1) << 30)) return TG_E_INVALID_ARG;
         break;
+    case TG_TUNE_CYCLE_SLOTS:
+    case TG_TUNE_EDGE_SLOTS:
+        if (value < 1 || value > 65536) return TG_E_INVALID_ARG;
+        break;
+    case TG_TUNE_MAP_BYTES:
+    case TG_TUNE_TBUF_BYTES:
+        if (value < 1) return TG_E_INVALID_ARG;
+        break;
     default:
         return TG_E_INVALID_ARG;
     }
@@ -571,7 +582,7 @@ tg_status tg_set_tuning(int32_t knob, int64_t value) {
 }
 
 int64_t tg_get_tuning(int32_t knob) {
-    if (knob < 0 || knob > TG_TUNE_CLEAR_BYTES) return -1;
+    if (knob < 0 || knob > TG_TUNE_TBUF_BYTES) return -1;
     return tg::g_tune[knob];
 }
 

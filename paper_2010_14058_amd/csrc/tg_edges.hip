@@ -194,6 +194,10 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
         const int32_t other = i_small ? j : i;
         const bool probe = other >= a.sh_base;
         const int so = other - a.sh_base;
+        // the low list must be sorted only for the binary searches of the
+        // clique walk, which both endpoints being super-hubs avoid; then
+        // waves append on their own, with no barrier per chunk
+        const bool unordered = NT > WAVE && i >= a.sh_base && j >= a.sh_base;
         uint32_t count = 0;
         for (int64_t p0 = sb; p0 < se; p0 += NT) {
             int64_t p = p0 + tid;
@@ -210,13 +214,24 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
                     found = q < le && a.ncol[q] == x;
                 }
             }
-            uint32_t pos = ordered_append<NT>(found, count, S.wave_cnt);
+            uint32_t pos;
+            if (unordered) {
+                const uint64_t bal = __ballot(found);
+                uint32_t at = 0;
+                if (bal) {
+                    if (lane_id() == 0) at = atomicAdd(&S.meta[0], (uint32_t)__popcll(bal));
+                    at = __shfl(at, 0, WAVE);
+                }
+                pos = at + (uint32_t)__popcll(bal & ((1ull << lane_id()) - 1ull));
+            } else {
+                pos = ordered_append<NT>(found, count, S.wave_cnt);
+            }
             if (found) {
                 S.Tl[pos] = (uint32_t)x;
                 gather_member(a, x, i_small ? p : q, i_small ? q : p, S.Xi, S.Xj, S.Y);
             }
         }
-        if (tid == 0) S.meta[0] = count;
+        if (tid == 0 && !unordered) S.meta[0] = count;
     }
 
     // hub members
