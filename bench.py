@@ -32,7 +32,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 TCAP = 1024             # light clique path capacity (both degrees above: heavy path)
-KERNEL_SRC = os.path.join(ROOT, "paper_2010_14058_amd", "csrc", "tg_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2010_14058_amd", "csrc")
 
 
 def log(*a):
@@ -40,8 +40,13 @@ def log(*a):
 
 
 def kernel_source_sha() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Digest of every HIP source and header of the library."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
 
 
 def host_threads() -> int:
