@@ -296,6 +296,9 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     uint64_t cand[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(cand, counters + C_HUB_CAND, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost,
                           st));
+    int64_t max_deg = 0;  // the top-ranked node has the largest degree
+    if (n > 0)
+        HIPCHK(hipMemcpyAsync(&max_deg, ndeg + (n - 1), sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (probe.status) return status_from_bits(probe.status);
     // hub core: the highest-ranked nodes of degree >= HUB_DMIN, at most HUB_MAX
@@ -369,6 +372,12 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     ea.tri = tri; ea.tdeg = tdeg; ea.tri_slot = tri_slot; ea.A = A; ea.D = D; ea.NC = NC; ea.m = m; ea.L = L;
     ea.rows = per_edge; ea.gacc = gacc; ea.gw = gw;
     ea.hist_in_lds = (size_t)gw * sizeof(uint64_t) <= 32768 ? 1 : 0;
+    // a batch chunk flushes after at most BATCH_EDGE_CHUNK (256) edges, each
+    // adding at most 6 * max_deg^2 to one entry (three orbits of a graphlet,
+    // each at most 2 * max_deg^2): 32-bit entries hold that sum when
+    // max_deg <= 1024
+    if (batch && max_deg <= 1024 && (size_t)gw * sizeof(uint32_t) <= 32768) ea.hist_in_lds = 2;
+    ea.tcap = (int)(max_deg < TCAP ? (max_deg > 0 ? max_deg : 1) : TCAP);
     ea.heavy_list = le; ea.counters = counters; ea.tbuf = tbuf; ea.n = n; ea.status = status;
     ea.hub_base = hub_base; ea.Hw = Hw; ea.hstart = hstart; ea.nlow = nlow; ea.HB = HB; ea.hpre = hpre; ea.TM = TM;
     ea.sh_base = sh_base; ea.nw = nw; ea.SB = SB; ea.SP = SP;
@@ -386,6 +395,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     timing_mark("edges_light");
     EdgeArgs eh = ea;
     if (batch) eh.hist_in_lds = 0;  // heavy edges of many graphs: direct per-graph atomics
+    else eh.hist_in_lds = ea.hist_in_lds ? 1 : 0;
     HIPCHK(launch_edges(true, eh, (unsigned)y.heavy_edge_slots, st));
     timing_mark("edges_heavy");
     if (batch)

@@ -82,10 +82,32 @@ __device__ __forceinline__ int remap_global(int idx, int L, int Lg) {
 }
 
 // Add v to global entry idx of the edge's graph g (always 0 for one graph).
+// uint64 words of the LDS histogram (0 when it lives in global memory).
+__device__ __forceinline__ int hist_words(const EdgeArgs &a) {
+    return a.hist_in_lds == 2 ? (a.gw + 1) / 2 : a.hist_in_lds ? a.gw : 0;
+}
+
+// Entry q of the LDS histogram, read and cleared.
+__device__ __forceinline__ uint64_t hist_take(const EdgeArgs &a, uint64_t *hist, int q) {
+    if (a.hist_in_lds == 2) {
+        uint32_t *h = reinterpret_cast<uint32_t *>(hist);
+        uint32_t v = h[q];
+        if (v) h[q] = 0u;
+        return v;
+    }
+    uint64_t v = hist[q];
+    if (v) hist[q] = 0ull;
+    return v;
+}
+
 __device__ __forceinline__ void hist_add(const EdgeArgs &a, uint64_t *hist, int idx, uint64_t v,
                                          int64_t g) {
     if (!v) return;
-    if (a.hist_in_lds) {
+    if (a.hist_in_lds == 2) {
+        // 32-bit entries: the host allows them only when a flush interval's
+        // sum fits (batch chunks of small-degree graphs)
+        atomicAdd(reinterpret_cast<uint32_t *>(hist) + idx, (uint32_t)v);
+    } else if (a.hist_in_lds) {
         atomicAdd((unsigned long long *)&hist[idx], (unsigned long long)v);
     } else if (a.batch) {
         int j = remap_global(idx, a.L, a.gL[g]);
@@ -161,7 +183,8 @@ __device__ __forceinline__ uint32_t ordered_append(bool flag, uint32_t &count, u
 struct EdgeShared {
     uint64_t *Xi, *Xj, *Y, *K;
     uint64_t *Tm;           // hub members as bits over hub indices
-    uint32_t *Th;           // hub members, unordered
+    uint32_t *Th;           // hub members, unordered; member q at Th[q * th_step]
+    int th_step;            // +1, or -1 when Th grows down from the end of Tl's buffer
     uint32_t *Tl;           // low members, ascending
     uint32_t *meta;         // [0] |Tl| [1] |Th| [2] first word of Tm [3] last word
     uint32_t *wave_cnt;     // ordered_append scratch
@@ -250,7 +273,7 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
                 int hk = q * 64 + b;
                 int32_t k = base + hk;
                 uint32_t pos = atomicAdd(&S.meta[1], 1u);
-                S.Th[pos] = (uint32_t)k;
+                S.Th[(ptrdiff_t)pos * S.th_step] = (uint32_t)k;
                 gather_member(a, k, hub_slot(a, i, hx_i, hk), hub_slot(a, j, hx_j, hk), S.Xi, S.Xj, S.Y);
             }
         }
@@ -279,7 +302,7 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
             atomicMin(&S.meta[2], (uint32_t)(hk >> 6));
             atomicMax(&S.meta[3], (uint32_t)(hk >> 6));
             uint32_t pos = atomicAdd(&S.meta[1], 1u);
-            S.Th[pos] = (uint32_t)x;
+            S.Th[(ptrdiff_t)pos * S.th_step] = (uint32_t)x;
             gather_member(a, x, i_small ? p : q, i_small ? q : p, S.Xi, S.Xj, S.Y);
         }
     }
@@ -337,7 +360,8 @@ __device__ void edge_cliques(const EdgeArgs &a, int32_t i, int32_t j, const Edge
                 while (bb * (bb - 1) / 2 > f) --bb;
                 while ((bb + 1) * bb / 2 <= f) ++bb;
                 const uint32_t aa = f - bb * (bb - 1) / 2;
-                const int32_t k = (int32_t)S.Th[aa], x = (int32_t)S.Th[bb];
+                const int32_t k = (int32_t)S.Th[(ptrdiff_t)aa * S.th_step];
+                const int32_t x = (int32_t)S.Th[(ptrdiff_t)bb * S.th_step];
                 const int hk = k - base, hx = x - base;
                 if ((a.HB[(size_t)hk * Hw + (hx >> 6)] >> (hx & 63)) & 1ull) {
                     const int tk = a.ntype[k], tx = a.ntype[x];
@@ -354,7 +378,7 @@ __device__ void edge_cliques(const EdgeArgs &a, int32_t i, int32_t j, const Edge
                 const uint32_t members = nTh - c0 < (uint32_t)NT ? nTh - c0 : (uint32_t)NT;
                 uint32_t len = 0;
                 if ((uint32_t)tid < members) {
-                    const int32_t k = (int32_t)S.Th[c0 + tid];
+                    const int32_t k = (int32_t)S.Th[(ptrdiff_t)(c0 + tid) * S.th_step];
                     const uint32_t kb = (uint32_t)(k - base) >> 9;
                     const uint32_t sb = kb > b0 ? kb : b0;
                     len = sb < b1 ? b1 - sb : 0;
@@ -567,7 +591,7 @@ __device__ void edge_derive(const EdgeArgs &a, int64_t e, int32_t i, int32_t j, 
 // [Xi Xj Y K : 4 L^2][hist : gw if in LDS][Tm : Hw] then uint32 lists.
 __device__ __forceinline__ EdgeShared carve(const EdgeArgs &a, uint64_t *sm, uint32_t *meta,
                                             uint32_t *wave_cnt, uint64_t **hist, uint32_t *Th,
-                                            uint32_t *Tl) {
+                                            int th_step, uint32_t *Tl) {
     const int LL = a.L * a.L;
     EdgeShared S;
     S.Xi = sm;
@@ -575,8 +599,9 @@ __device__ __forceinline__ EdgeShared carve(const EdgeArgs &a, uint64_t *sm, uin
     S.Y = sm + 2 * LL;
     S.K = sm + 3 * LL;
     *hist = sm + 4 * LL;
-    S.Tm = *hist + (a.hist_in_lds ? a.gw : 0);
+    S.Tm = *hist + hist_words(a);
     S.Th = Th;
+    S.th_step = th_step;
     S.Tl = Tl;
     S.meta = meta;
     S.wave_cnt = wave_cnt;
@@ -593,14 +618,15 @@ __global__ void __launch_bounds__(64) k_edges_light(EdgeArgs a) {
     const ScanScratch F{fl_r, fl_start, fl_scan};
     const int LL = a.L * a.L;
     uint64_t *hist;
-    uint64_t *after = sm_edge + 4 * LL + (a.hist_in_lds ? a.gw : 0) + a.Hw;
-    uint32_t *Th = (uint32_t *)after;
-    uint32_t *Tl = Th + TCAP;
-    EdgeShared S = carve(a, sm_edge, meta, wave_cnt, &hist, Th, Tl);
+    uint64_t *after = sm_edge + 4 * LL + hist_words(a) + a.Hw;
+    // one list of tcap entries: low members from the front, hub members from
+    // the back (|T| <= min degree <= tcap)
+    uint32_t *Tl = (uint32_t *)after;
+    uint32_t *Th = Tl + (a.tcap - 1);
+    EdgeShared S = carve(a, sm_edge, meta, wave_cnt, &hist, Th, -1, Tl);
     int lane = threadIdx.x;
     uint32_t bad = 0;
-    if (a.hist_in_lds)
-        for (int q = lane; q < a.gw; q += WAVE) hist[q] = 0;
+    for (int q = lane; q < hist_words(a); q += WAVE) hist[q] = 0;
     __syncthreads();
     auto one_edge = [&](int64_t e) {
         int32_t i = a.ei[e], j = a.ej[e];
@@ -619,8 +645,10 @@ __global__ void __launch_bounds__(64) k_edges_light(EdgeArgs a) {
     if (!a.batch) {
         for (int64_t e = blockIdx.x; e < a.m; e += gridDim.x) one_edge(e);
         if (a.hist_in_lds)
-            for (int q = lane; q < a.gw; q += WAVE)
-                if (hist[q]) atomicAdd((unsigned long long *)&a.gacc[q], (unsigned long long)hist[q]);
+            for (int q = lane; q < a.gw; q += WAVE) {
+                uint64_t v = hist_take(a, hist, q);
+                if (v) atomicAdd((unsigned long long *)&a.gacc[q], (unsigned long long)v);
+            }
     } else {
         // chunks of consecutive edges (the edges of one graph are
         // contiguous); the histogram is flushed into a graph's own vector
@@ -630,12 +658,11 @@ __global__ void __launch_bounds__(64) k_edges_light(EdgeArgs a) {
             const int Lg = a.gL[g];
             uint64_t *dst = a.gacc + a.goff[g];
             for (int q = lane; q < a.gw; q += WAVE) {
-                uint64_t v = hist[q];
+                uint64_t v = hist_take(a, hist, q);
                 if (!v) continue;
                 int jq = remap_global(q, a.L, Lg);
                 if (jq < 0) bad |= ST_INTERNAL;
                 else atomicAdd((unsigned long long *)&dst[jq], (unsigned long long)v);
-                hist[q] = 0;
             }
             __syncthreads();
         };
@@ -673,16 +700,15 @@ __global__ void __launch_bounds__(EDGE_THREADS_HEAVY) k_edges_heavy(EdgeArgs a) 
     const int NT = EDGE_THREADS_HEAVY;
     const int LL = a.L * a.L;
     uint64_t *hist;
-    uint64_t *after = sm_edgeh + 4 * LL + (a.hist_in_lds ? a.gw : 0) + a.Hw;
+    uint64_t *after = sm_edgeh + 4 * LL + hist_words(a) + a.Hw;
     uint64_t *TMs = after;                        // type masks of the hub core
     uint32_t *Th = (uint32_t *)(TMs + (size_t)a.L * a.Hw);
     uint32_t *Tl = a.tbuf + (size_t)blockIdx.x * (size_t)a.n;
-    EdgeShared S = carve(a, sm_edgeh, meta, wave_cnt, &hist, Th, Tl);
+    EdgeShared S = carve(a, sm_edgeh, meta, wave_cnt, &hist, Th, 1, Tl);
     int tid = threadIdx.x;
     for (int q = tid; q < a.L * a.Hw; q += NT) TMs[q] = a.TM[q];
     uint32_t bad = 0;
-    if (a.hist_in_lds)
-        for (int q = tid; q < a.gw; q += NT) hist[q] = 0;
+    for (int q = tid; q < hist_words(a); q += NT) hist[q] = 0;
     uint64_t count = a.counters[C_EDGE_HEAVY];
     __syncthreads();
     while (true) {
@@ -702,8 +728,10 @@ __global__ void __launch_bounds__(EDGE_THREADS_HEAVY) k_edges_heavy(EdgeArgs a) 
         __syncthreads();
     }
     if (a.hist_in_lds)
-        for (int q = tid; q < a.gw; q += NT)
-            if (hist[q]) atomicAdd((unsigned long long *)&a.gacc[q], (unsigned long long)hist[q]);
+        for (int q = tid; q < a.gw; q += NT) {
+            uint64_t v = hist_take(a, hist, q);
+            if (v) atomicAdd((unsigned long long *)&a.gacc[q], (unsigned long long)v);
+        }
     if (bad) atomicOr(a.status, bad);
 }
 
@@ -723,8 +751,9 @@ hipError_t launch_hub_build(const int64_t *nrp, const int32_t *ncol, const int64
 
 size_t edge_lds_bytes(const EdgeArgs &args, bool heavy) {
     int LL = args.L * args.L;
-    size_t sh = (size_t)(4 * LL + (args.hist_in_lds ? args.gw : 0) + args.Hw) * sizeof(uint64_t);
-    if (!heavy) sh += (size_t)2 * TCAP * sizeof(uint32_t);
+    const int hw = args.hist_in_lds == 2 ? (args.gw + 1) / 2 : args.hist_in_lds ? args.gw : 0;
+    size_t sh = (size_t)(4 * LL + hw + args.Hw) * sizeof(uint64_t);
+    if (!heavy) sh += (size_t)args.tcap * sizeof(uint32_t);
     else sh += (size_t)args.L * args.Hw * sizeof(uint64_t) +
                (size_t)(args.hub_base < args.n ? (args.n - args.hub_base) : 0) * sizeof(uint32_t);
     return sh;

@@ -122,7 +122,8 @@ struct EdgeArgs {
     uint64_t *rows;      // may be null
     uint64_t *gacc;      // global accumulators
     int gw;
-    int hist_in_lds;
+    int hist_in_lds;             // 0: global atomics, 1: uint64 LDS histogram, 2: uint32 LDS histogram
+    int tcap;                    // triangle-list entries in LDS (light kernel)
     uint32_t *heavy_list;
     uint64_t *counters;
     uint32_t *tbuf;      // heavy: per-workgroup low-member buffers of n entries
