@@ -169,8 +169,12 @@ const char *tg_last_error(void);
  *       heavy-edge kernel; each owns a list of n*4 bytes of workspace.
  *   TG_TUNE_TBUF_BYTES   (default 8 GiB, >= 1): workspace bytes for those
  *       lists; the slot count is cut to fit (at least one slot).
- * The last four change tg_workspace_bytes and tg_batch_workspace_bytes, so
- * they must be set before the workspace is sized.
+ *   TG_TUNE_RANGE_BYTES  (default 0, >= 0): a heavy group with at least
+ *       one wedge per target id is also split so that one task's map entries
+ *       take at most this many bytes; 0 turns this off.
+ * CYCLE_SLOTS, MAP_BYTES, EDGE_SLOTS and TBUF_BYTES change
+ * tg_workspace_bytes and tg_batch_workspace_bytes, so they must be set
+ * before the workspace is sized.
  * tg_set_tuning returns TG_E_INVALID_ARG for an unknown knob or a value out
  * of range; tg_get_tuning returns the current value (-1 if unknown). */
 typedef enum {
@@ -179,7 +183,8 @@ typedef enum {
     TG_TUNE_CYCLE_SLOTS = 2,
     TG_TUNE_MAP_BYTES = 3,
     TG_TUNE_EDGE_SLOTS = 4,
-    TG_TUNE_TBUF_BYTES = 5
+    TG_TUNE_TBUF_BYTES = 5,
+    TG_TUNE_RANGE_BYTES = 6
 } tg_tune;
 tg_status tg_set_tuning(int32_t knob, int64_t value);
 int64_t tg_get_tuning(int32_t knob);

@@ -35,8 +35,9 @@ static const size_t TBUF_BUDGET = size_t(8) << 30;
 static const int MAX_HEAVY_SLOTS = 1024;
 
 // Scheduling knobs (tg_set_tuning), per host thread.
-thread_local int64_t g_tune[6] = {TASK_WEDGES, SEQ_CLEAR_BYTES, MAX_HEAVY_SLOTS,
-                                   (int64_t)MAP_BUDGET, MAX_HEAVY_SLOTS, (int64_t)TBUF_BUDGET};
+thread_local int64_t g_tune[7] = {TASK_WEDGES, SEQ_CLEAR_BYTES, MAX_HEAVY_SLOTS,
+                                   (int64_t)MAP_BUDGET, MAX_HEAVY_SLOTS, (int64_t)TBUF_BUDGET,
+                                   TASK_RANGE_BYTES};
 
 static size_t sort_tmp_bytes(int64_t n, int64_t nnz) {
     size_t a = 0, b = 0, c = 0;
@@ -337,7 +338,8 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     // ---- 4-cycles from degree-ordered wedges
     HIPCHK(launch_fill_u64(NC, 0, m * LL, st));
     HIPCHK(launch_cyc_work(nrp, ncol, neid, eslot, nlow, n, la_l, la_h, lb_l, lb_h, counters,
-                           (uint64_t)g_tune[TG_TUNE_TASK_WEDGES], st));
+                           (uint64_t)g_tune[TG_TUNE_TASK_WEDGES], L,
+                           (uint64_t)g_tune[TG_TUNE_RANGE_BYTES], st));
     timing_mark("cyc_work");
     CycleArgs ca;
     ca.tasks = nullptr;
@@ -584,6 +586,9 @@ tg_status tg_set_tuning(int32_t knob, int64_t value) {
     case TG_TUNE_TBUF_BYTES:
         if (value < 1) return TG_E_INVALID_ARG;
         break;
+    case TG_TUNE_RANGE_BYTES:
+        if (value < 0) return TG_E_INVALID_ARG;
+        break;
     default:
         return TG_E_INVALID_ARG;
     }
@@ -592,7 +597,7 @@ tg_status tg_set_tuning(int32_t knob, int64_t value) {
 }
 
 int64_t tg_get_tuning(int32_t knob) {
-    if (knob < 0 || knob > TG_TUNE_TBUF_BYTES) return -1;
+    if (knob < 0 || knob > TG_TUNE_RANGE_BYTES) return -1;
     return tg::g_tune[knob];
 }
 

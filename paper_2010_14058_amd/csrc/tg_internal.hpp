@@ -32,6 +32,7 @@ constexpr int64_t TASK_WEDGES = 1 << 18;  // default wedges per heavy task (targ
 constexpr int TASK_MAX_PARTS = 64;        // most target ranges per heavy group
 constexpr int64_t TASK_EXTRA = 1 << 16;   // task slots beyond one per node, shared by both passes
 constexpr int SEQ_CLEAR_BYTES = 16;       // default bytes per wedge below which a range is cleared by streaming
+constexpr int64_t TASK_RANGE_BYTES = 0;  // default map-byte bound per task of a dense heavy group (0: off)
 constexpr int TCAP = 1024;            // triangle set kept in LDS by the light edge kernel
 constexpr int EDGE_THREADS_HEAVY = 256;
 constexpr int64_t BATCH_EDGE_CHUNK = 256;  // consecutive edges per work item in batches
@@ -199,7 +200,7 @@ hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8
 hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32_t *neid,
                            const uint32_t *eslot, const uint32_t *nlow, int64_t n, uint32_t *la_l,
                            uint4 *la_h, uint32_t *lb_l, uint4 *lb_h, uint64_t *counters,
-                           uint64_t task_wedges, hipStream_t st);
+                           uint64_t task_wedges, int L, uint64_t range_bytes, hipStream_t st);
 int heavy_chunk_for(int L);
 hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned grid, hipStream_t st);
 hipError_t launch_edges(bool heavy, const EdgeArgs &args, unsigned grid, hipStream_t st);

@@ -568,12 +568,25 @@ __device__ __forceinline__ void block_scan_chunk(uint32_t v, uint32_t *s, uint32
     __syncthreads();
 }
 
-// First id c in [lo, hi] whose row starts at or after offset off (row
-// starts are nondecreasing).
-__device__ __forceinline__ int32_t row_at(const int64_t *nrp, int32_t lo, int32_t hi, int64_t off) {
+// Boundary k of a split of target ids [rb, re) into `parts` ranges: the
+// first id c with mass(rb, c) / mass(rb, re) + (c - rb) / (re - rb) >=
+// 2k / parts, where mass is adjacency (row starts are nondecreasing).  Each
+// range then holds at most 2 / parts of the adjacency mass (targets are met
+// in proportion to their degree) and at most 2 / parts of the ids (the map
+// entries a range touches).
+__device__ __forceinline__ int32_t range_cut(const int64_t *nrp, int32_t rb, int32_t re, uint32_t k,
+                                             uint32_t parts) {
+    if (k == 0) return rb;
+    if (k >= parts) return re;
+    const int64_t base = nrp[rb];
+    const double inv_mass = 1.0 / (double)(nrp[re] - base > 0 ? nrp[re] - base : 1);
+    const double inv_ids = 1.0 / (double)(re - rb);
+    const double target = 2.0 * (double)k / (double)parts;
+    int32_t lo = rb, hi = re;
     while (lo < hi) {
         int32_t mid = lo + ((hi - lo) >> 1);
-        if (nrp[mid] < off) lo = mid + 1; else hi = mid;
+        double f = (double)(nrp[mid] - base) * inv_mass + (double)(mid - rb) * inv_ids;
+        if (f < target) lo = mid + 1; else hi = mid;
     }
     return lo;
 }
@@ -616,10 +629,8 @@ __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
                 int32_t re = PASS == 0 ? g : (int32_t)a.n;
                 int32_t lo = rb, hi = re;
                 if (tk.z > 1) {
-                    int64_t base = a.nrp[rb], mass = a.nrp[re] - base;
-                    lo = tk.y ? row_at(a.nrp, rb, re, base + mass * tk.y / tk.z) : rb;
-                    hi = tk.y + 1 < tk.z ? row_at(a.nrp, rb, re, base + mass * (tk.y + 1) / tk.z)
-                                         : re;
+                    lo = range_cut(a.nrp, rb, re, tk.y, tk.z);
+                    hi = range_cut(a.nrp, rb, re, tk.y + 1, tk.z);
                 }
                 int64_t nitem = PASS == 0 ? (int64_t)a.nlow[g] : a.nrp[g + 1] - a.nrp[g];
                 int ew = nitem < 65536 ? (L + 1) / 2 : L;
@@ -743,6 +754,12 @@ __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
     }
 }
 
+// Bytes of one target's entry in a heavy group's map: L 16-bit counts when
+// the group has fewer than 2^16 items, else L 32-bit counts.
+__device__ __forceinline__ uint64_t map_bytes_per_id(int64_t items, int L) {
+    return items < 65536 ? (uint64_t)((L + 1) / 2) * 4 : (uint64_t)L * 4;
+}
+
 // Wave-wide list appends of the groups found by the lanes of a wave (one
 // counter update per wave and list).  Every lane of the wave calls this with
 // its own node v and wedge count w (0: no group).  Light groups go to
@@ -751,7 +768,8 @@ __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
 // wave whose splits do not fit keeps its groups whole).
 __device__ void push_groups(int32_t v, uint64_t w, uint32_t *light, uint4 *heavy,
                             uint64_t *counters, int c_light, int c_heavy, int c_wedges,
-                            int c_wedges_heavy, uint64_t task_wedges) {
+                            int c_wedges_heavy, uint64_t task_wedges, int64_t range_ids,
+                            uint64_t map_bytes_per_id, uint64_t range_bytes) {
     const int lane = lane_id();
     const uint64_t below = (1ull << lane) - 1ull;
     const bool is_light = w && w <= (uint64_t)LIGHT_MAXW;
@@ -776,6 +794,13 @@ __device__ void push_groups(int32_t v, uint64_t w, uint32_t *light, uint4 *heavy
     uint32_t parts = 0;
     if (is_heavy) {
         uint64_t q = (w + task_wedges - 1) / task_wedges;
+        // a group with at least one wedge per target id reuses map lines:
+        // split its id range so one task's map entries stay within
+        // range_bytes (and so in cache between its count and emit walks)
+        if (range_bytes && range_ids > 0 && w >= (uint64_t)range_ids) {
+            uint64_t rb = ((uint64_t)range_ids * map_bytes_per_id + range_bytes - 1) / range_bytes;
+            if (rb > q) q = rb;
+        }
         parts = (uint32_t)(q > (uint64_t)TASK_MAX_PARTS ? TASK_MAX_PARTS : q);
     }
     uint32_t extra = wave_incl_scan(parts ? parts - 1 : 0u);
@@ -828,7 +853,8 @@ __global__ void __launch_bounds__(256) k_cyc_work(
     const uint32_t *__restrict__ neid, const uint32_t *__restrict__ eslot,
     const uint32_t *__restrict__ nlow, int64_t n, uint32_t *__restrict__ listA_light,
     uint4 *__restrict__ listA_heavy, uint32_t *__restrict__ listB_light,
-    uint4 *__restrict__ listB_heavy, uint64_t *__restrict__ counters, uint64_t task_wedges) {
+    uint4 *__restrict__ listB_heavy, uint64_t *__restrict__ counters, uint64_t task_wedges,
+    int L, uint64_t range_bytes) {
     __shared__ int64_t s_thr;
     if (threadIdx.x == 0) {
         int64_t lo = 0, hi = n;
@@ -850,10 +876,14 @@ __global__ void __launch_bounds__(256) k_cyc_work(
         if (v < thr)
             for (int64_t s = nrp[v]; s < nrp[v + 1]; ++s)
                 node_wedges(nrp, ncol, neid, eslot, nlow, (int32_t)v, s, wa, wb);
+        const int64_t nl = v < thr ? (int64_t)nlow[v] : 0;
+        const int64_t dg = v < thr ? nrp[v + 1] - nrp[v] : 0;
         push_groups((int32_t)v, wa, listA_light, listA_heavy, counters, C_A_LIGHT, C_A_HEAVY,
-                    C_WEDGES_A, C_WEDGES_A_HEAVY, task_wedges);
+                    C_WEDGES_A, C_WEDGES_A_HEAVY, task_wedges, v,
+                    map_bytes_per_id(nl, L), range_bytes);
         push_groups((int32_t)v, wb, listB_light, listB_heavy, counters, C_B_LIGHT, C_B_HEAVY,
-                    C_WEDGES_B, C_WEDGES_B_HEAVY, task_wedges);
+                    C_WEDGES_B, C_WEDGES_B_HEAVY, task_wedges, n - 1 - v,
+                    map_bytes_per_id(dg, L), range_bytes);
     }
     for (int64_t v = thr + wid; v < n; v += nwaves) {
         uint64_t wa = 0, wb = 0;
@@ -861,10 +891,13 @@ __global__ void __launch_bounds__(256) k_cyc_work(
             node_wedges(nrp, ncol, neid, eslot, nlow, (int32_t)v, s, wa, wb);
         wa = wave_sum_u64(wa);
         wb = wave_sum_u64(wb);
+        const int64_t nl = (int64_t)nlow[v], dg = nrp[v + 1] - nrp[v];
         push_groups((int32_t)v, lane == 0 ? wa : 0ull, listA_light, listA_heavy, counters,
-                    C_A_LIGHT, C_A_HEAVY, C_WEDGES_A, C_WEDGES_A_HEAVY, task_wedges);
+                    C_A_LIGHT, C_A_HEAVY, C_WEDGES_A, C_WEDGES_A_HEAVY, task_wedges, v,
+                    map_bytes_per_id(nl, L), range_bytes);
         push_groups((int32_t)v, lane == 0 ? wb : 0ull, listB_light, listB_heavy, counters,
-                    C_B_LIGHT, C_B_HEAVY, C_WEDGES_B, C_WEDGES_B_HEAVY, task_wedges);
+                    C_B_LIGHT, C_B_HEAVY, C_WEDGES_B, C_WEDGES_B_HEAVY, task_wedges, n - 1 - v,
+                    map_bytes_per_id(dg, L), range_bytes);
     }
 }
 
@@ -980,7 +1013,7 @@ hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8
 hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32_t *neid,
                            const uint32_t *eslot, const uint32_t *nlow, int64_t n, uint32_t *la_l,
                            uint4 *la_h, uint32_t *lb_l, uint4 *lb_h, uint64_t *counters,
-                           uint64_t task_wedges, hipStream_t st) {
+                           uint64_t task_wedges, int L, uint64_t range_bytes, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     int dev = 0, cus = 0;
     hipError_t err = hipGetDevice(&dev);
@@ -992,7 +1025,7 @@ hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32
     unsigned grid = (unsigned)(want < cap ? want : cap);
     k_cyc_work<<<grid, 256, 0, st>>>(nrp, ncol, neid, eslot, nlow, n, la_l, la_h, lb_l,
                                                  lb_h, counters,
-                                                 task_wedges);
+                                                 task_wedges, L, range_bytes);
     LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -196,14 +196,17 @@ def test_invalid_inputs():
     assert _status(G.Graph(rp, col, base.types, 2, "range")) == 2
 
 
-@pytest.mark.parametrize("clear_bytes", [0, 1 << 20])
-def test_split_heavy_tasks(oracle_mod, clear_bytes):
+@pytest.mark.parametrize("knobs", [dict(task_wedges=64, clear_bytes=0),
+                                   dict(task_wedges=64, clear_bytes=1 << 20),
+                                   dict(range_bytes=512)],
+                         ids=["walk_clear", "streamed_clear", "id_ranges"])
+def test_split_heavy_tasks(oracle_mod, knobs):
     """Heavy 4-cycle groups split into many target ranges (64 wedges per
-    task), with map ranges cleared by wedge walks (0) or by streaming (large
-    threshold): the counts must not change."""
+    task, or 512 bytes of map entries per task), with map ranges cleared by
+    wedge walks or by streaming: the counts must not change."""
     import paper_2010_14058_amd as P
 
-    old = P.set_tuning(task_wedges=64, clear_bytes=clear_bytes)
+    old = P.set_tuning(**knobs)
     try:
         g = G.chung_lu_typed(20000, 16.0, 2.1, 3000.0, 5, type_probs=G.zipf_probs(5, 1.2),
                              homophily=0.6, seed=5, name="cl_20k_split")
