@@ -437,6 +437,19 @@ def main():
         "work": {k: int(v) for k, v in stats.items()},
     }
 
+    # sparse per-edge form of the table (outside the timed steps)
+    torch.cuda.synchronize()
+    t_sp = time.perf_counter()
+    off, keys, counts = P.sparse_rows(rows, L, workspace=ws)
+    torch.cuda.synchronize()
+    sp_ms = (time.perf_counter() - t_sp) * 1e3
+    nnz_total = int(keys.numel())
+    result["sparse_output"] = {
+        "nonzeros": nnz_total, "mean_per_edge": nnz_total / max(g.m, 1),
+        "bytes": nnz_total * 10 + (g.m + 1) * 8, "dense_bytes": g.m * W * 8,
+        "ms": round(sp_ms, 3)}
+    del off, keys, counts
+
     if not args.skip_cpu:
         threads = host_threads()
         log(f"[bench] CPU oracle baseline on {threads} threads ...")

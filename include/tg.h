@@ -137,6 +137,28 @@ tg_status tg_count_batch(const int64_t *row_ptr, const int32_t *col, const uint8
                          uint64_t *per_edge, uint64_t *graph_globals, void *workspace,
                          size_t ws_bytes, void *stream);
 
+/* Sparse per-edge output (Sec. 4.6: an edge keeps only its nonzero typed
+ * graphlet counts, with a lookup table from key to description, here
+ * tg_key_describe).  Built from a dense per-edge table `rows` (device uint64
+ * [m][tg_row_width(L)], as written by tg_count_typed_graphlets) in two calls:
+ *   tg_sparse_offsets   writes edge_off (device int64 [m+1]): edge e's pairs
+ *                       are entries [edge_off[e], edge_off[e+1]) and
+ *                       edge_off[m] is their total; needs a workspace of
+ *                       tg_sparse_workspace_bytes(m) bytes.
+ *   tg_sparse_fill      writes keys (device uint16) and counts (device
+ *                       uint64), each of edge_off[m] entries: the column id
+ *                       and the count of every nonzero entry, edges in
+ *                       canonical order, columns ascending within an edge.
+ * The caller owns every buffer and sizes keys/counts from edge_off[m].
+ * Both calls return when their results are complete on `stream`.  Errors:
+ * TG_E_L_RANGE, TG_E_INVALID_ARG (m < 0, missing pointers), TG_E_WORKSPACE
+ * (workspace too small), TG_E_DEVICE. */
+size_t tg_sparse_workspace_bytes(int64_t m);
+tg_status tg_sparse_offsets(const uint64_t *rows, int64_t m, int32_t L, int64_t *edge_off,
+                            void *workspace, size_t ws_bytes, void *stream);
+tg_status tg_sparse_fill(const uint64_t *rows, int64_t m, int32_t L, const int64_t *edge_off,
+                         uint16_t *keys, uint64_t *counts, void *stream);
+
 /* Meaning of per-edge column `col` for L types: orbit 1 = tri, 2 = path3
  * (with *t the third node's type and *t2 = -1), else the orbit number 3..12
  * of Table 3 with the unordered type pair (*t <= *t2). */

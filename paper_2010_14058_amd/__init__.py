@@ -147,3 +147,34 @@ def count_batch(plan: BatchPlan, *, per_edge: bool = False, out_globals=None, ou
                          rows.data_ptr() if rows is not None and rows.numel() else 0,
                          glob.data_ptr(), ws.data_ptr(), ws.numel(), stream.cuda_stream)
     return glob, rows
+
+
+def sparse_rows(rows, L: int, *, workspace: Workspace | None = None, stream=None):
+    """Nonzero entries of a dense per-edge table (Sec. 4.6's sparse form).
+
+    rows: device int64 tensor [m, row_width(L)] holding uint64 counts, as
+    returned by :func:`count_typed_graphlets`.  Returns device tensors
+    ``(edge_off int64 [m+1], keys int16 [nnz], counts int64 [nnz])``: edge e
+    owns entries ``edge_off[e]:edge_off[e+1]``; keys are column ids (uint16
+    bit patterns, see ``key_describe``), columns ascending within an edge.
+    """
+    import torch
+
+    dev = rows.device
+    rows = rows.contiguous()
+    m = rows.shape[0]
+    if rows.dim() != 2 or rows.shape[1] != row_width(L):
+        raise ValueError("rows must be [m, row_width(L)]")
+    off = torch.empty(m + 1, dtype=torch.int64, device=dev)
+    ws = (workspace or Workspace(dev)).get(_lib.sparse_workspace_bytes(m))
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    _lib.sparse_offsets_raw(rows.data_ptr() if m else 0, m, L, off.data_ptr(), ws.data_ptr(),
+                            ws.numel(), stream.cuda_stream)
+    total = int(off[m].item())
+    keys = torch.empty(total, dtype=torch.int16, device=dev)
+    counts = torch.empty(total, dtype=torch.int64, device=dev)
+    if total:
+        _lib.sparse_fill_raw(rows.data_ptr(), m, L, off.data_ptr(), keys.data_ptr(),
+                             counts.data_ptr(), stream.cuda_stream)
+    return off, keys, counts

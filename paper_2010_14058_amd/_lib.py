@@ -38,6 +38,11 @@ SIGNATURES = {
     "tg_last_stats": (_c.c_int32, [_c.POINTER(_c.c_int64), _c.c_int32]),
     "tg_set_tuning": (_c.c_int, [_c.c_int32, _c.c_int64]),
     "tg_last_error": (_c.c_char_p, []),
+    "tg_sparse_workspace_bytes": (_c.c_size_t, [_c.c_int64]),
+    "tg_sparse_offsets": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int32, _c.c_void_p, _c.c_void_p,
+                                     _c.c_size_t, _c.c_void_p]),
+    "tg_sparse_fill": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int32, _c.c_void_p, _c.c_void_p,
+                                  _c.c_void_p, _c.c_void_p]),
     "tg_get_tuning": (_c.c_int64, [_c.c_int32]),
 }
 
@@ -166,3 +171,21 @@ def count_batch_raw(row_ptr: int, col: int, types: int, n: int, nnz: int, node_p
                                globals_len, per_edge, globals_ptr, ws, ws_bytes, stream)
     if rc:
         raise TGError(rc, "tg_count_batch")
+
+
+def sparse_workspace_bytes(m: int) -> int:
+    return int(load().tg_sparse_workspace_bytes(m))
+
+
+def sparse_offsets_raw(rows_ptr: int, m: int, L: int, off_ptr: int, ws_ptr: int, ws_bytes: int,
+                       stream: int) -> None:
+    rc = load().tg_sparse_offsets(rows_ptr, m, L, off_ptr, ws_ptr, ws_bytes, stream)
+    if rc:
+        raise TGError(rc, "tg_sparse_offsets")
+
+
+def sparse_fill_raw(rows_ptr: int, m: int, L: int, off_ptr: int, keys_ptr: int, counts_ptr: int,
+                    stream: int) -> None:
+    rc = load().tg_sparse_fill(rows_ptr, m, L, off_ptr, keys_ptr, counts_ptr, stream)
+    if rc:
+        raise TGError(rc, "tg_sparse_fill")

@@ -98,3 +98,19 @@ def test_tuning_knobs():
         P.set_tuning(clear_bytes=-1)
     P.set_tuning(**base)
     assert P.get_tuning() == base
+
+
+def test_sparse_argument_checks():
+    """Argument checks of the sparse-output calls happen before any device work."""
+    from paper_2010_14058_amd import _lib as L
+
+    lib = L.load()
+    assert L.sparse_workspace_bytes(10) > 0
+    assert lib.tg_sparse_workspace_bytes(-1) == 0
+    assert lib.tg_sparse_offsets(None, 4, 0, None, None, 0, None) == 4   # TG_E_L_RANGE
+    assert lib.tg_sparse_offsets(None, -1, 3, 1, 1, 0, None) == 1        # negative m
+    assert lib.tg_sparse_offsets(None, 4, 3, 1, 1, 1 << 40, None) == 1   # rows missing
+    assert lib.tg_sparse_offsets(1, 4, 3, 1, 1, 0, None) == 5            # workspace too small
+    assert lib.tg_sparse_fill(None, 4, 17, 1, 1, 1, None) == 4
+    assert lib.tg_sparse_fill(1, 4, 3, 1, None, 1, None) == 1
+    assert lib.tg_sparse_fill(None, 0, 3, 1, None, None, None) == 0      # nothing to do
