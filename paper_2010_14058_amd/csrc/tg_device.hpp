@@ -46,6 +46,19 @@ static __device__ __forceinline__ int owner_of(const uint32_t *s, int len, uint3
     return lo;
 }
 
+// owner_of for a thread whose item index f only grows: o is the owner of
+// the previous f; most steps stay in the same item (one LDS read), else the
+// search restarts above o.
+static __device__ __forceinline__ int owner_next(const uint32_t *s, int len, uint32_t f, int o) {
+    if (s[o] > f) return o;
+    int lo = o + 1, hi = len;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (s[mid] <= f) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
 static __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     int lane = lane_id();
 #pragma unroll

@@ -448,8 +448,9 @@ __device__ void edge_cliques(const EdgeArgs &a, int32_t i, int32_t j, const Edge
         F.scan[tid] = incl;
         group_sync<NT>();
         const uint32_t total = F.scan[items - 1];
+        int o = 0;
         for (uint32_t f = tid; f < total; f += NT) {
-            int o = owner_of(F.scan, (int)items, f);
+            o = owner_next(F.scan, (int)items, f, o);
             uint32_t excl = o ? F.scan[o - 1] : 0;
             int32_t r = (int32_t)F.r[o];
             int32_t x = a.ncol[F.start[o] + (f - excl)];

@@ -501,8 +501,9 @@ __global__ void __launch_bounds__(64) k_cyc_light(CycleArgs a) {
                 uint32_t total = __shfl(incl, WAVE - 1, WAVE);
                 int nitems = (int)((ie - cb) < WAVE ? (ie - cb) : WAVE);
                 __syncthreads();
+                int o = 0;
                 for (uint32_t f = lane; f < total; f += WAVE) {
-                    int o = owner_of(it_scan, nitems, f);
+                    o = owner_next(it_scan, nitems, f, o);
                     uint32_t excl = o ? it_scan[o - 1] : 0;
                     int32_t x = it_x[o];
                     uint32_t y = (uint32_t)a.ncol[it_tb[o] + (f - excl)];
@@ -693,8 +694,9 @@ __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
                     for (int q = tid; q < nitems * LL; q += HEAVY_THREADS) acc[q] = 0;
                     __syncthreads();
                 }
+                int o = 0;
                 for (uint32_t f = tid; f < total; f += HEAVY_THREADS) {
-                    int o = owner_of(it_scan, nitems, f);
+                    o = owner_next(it_scan, nitems, f, o);
                     uint32_t excl = o ? it_scan[o - 1] : 0;
                     int32_t x = it_x[o];
                     uint32_t y = (uint32_t)a.ncol[it_tb[o] + (f - excl)];
