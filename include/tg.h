@@ -194,6 +194,8 @@ const char *tg_last_error(void);
  *   TG_TUNE_RANGE_BYTES  (default 0, >= 0): a heavy group with at least
  *       one wedge per target id is also split so that one task's map entries
  *       take at most this many bytes; 0 turns this off.
+ *   TG_TUNE_DERIVE_EDGES (default 0 = automatic, 0..4): edges of the light
+ *       kernel whose per-type-pair derivation runs together in one wave.
  * CYCLE_SLOTS, MAP_BYTES, EDGE_SLOTS and TBUF_BYTES change
  * tg_workspace_bytes and tg_batch_workspace_bytes, so they must be set
  * before the workspace is sized.
@@ -206,7 +208,8 @@ typedef enum {
     TG_TUNE_MAP_BYTES = 3,
     TG_TUNE_EDGE_SLOTS = 4,
     TG_TUNE_TBUF_BYTES = 5,
-    TG_TUNE_RANGE_BYTES = 6
+    TG_TUNE_RANGE_BYTES = 6,
+    TG_TUNE_DERIVE_EDGES = 7
 } tg_tune;
 tg_status tg_set_tuning(int32_t knob, int64_t value);
 int64_t tg_get_tuning(int32_t knob);

@@ -125,7 +125,7 @@ def phase_times() -> list[tuple[str, float]]:
 
 
 TUNE_KNOBS = {"task_wedges": 0, "clear_bytes": 1, "cycle_slots": 2, "map_bytes": 3,
-              "edge_slots": 4, "tbuf_bytes": 5, "range_bytes": 6}
+              "edge_slots": 4, "tbuf_bytes": 5, "range_bytes": 6, "derive_edges": 7}
 
 
 def set_tuning(**knobs) -> dict:

@@ -35,9 +35,9 @@ static const size_t TBUF_BUDGET = size_t(8) << 30;
 static const int MAX_HEAVY_SLOTS = 1024;
 
 // Scheduling knobs (tg_set_tuning), per host thread.
-thread_local int64_t g_tune[7] = {TASK_WEDGES, SEQ_CLEAR_BYTES, MAX_HEAVY_SLOTS,
+thread_local int64_t g_tune[8] = {TASK_WEDGES, SEQ_CLEAR_BYTES, MAX_HEAVY_SLOTS,
                                    (int64_t)MAP_BUDGET, MAX_HEAVY_SLOTS, (int64_t)TBUF_BUDGET,
-                                   TASK_RANGE_BYTES};
+                                   TASK_RANGE_BYTES, 0};
 
 static size_t sort_tmp_bytes(int64_t n, int64_t nnz) {
     size_t a = 0, b = 0, c = 0;
@@ -380,6 +380,18 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     // max_deg <= 1024
     if (batch && max_deg <= 1024 && (size_t)gw * sizeof(uint32_t) <= 32768) ea.hist_in_lds = 2;
     ea.tcap = (int)(max_deg < TCAP ? (max_deg > 0 ? max_deg : 1) : TCAP);
+    // derive several edges together when their type pairs leave lanes idle
+    // (a batch flushes its histogram per graph, so it derives edge by edge)
+    {
+        const int P = L * (L + 1) / 2;
+        // automatic: up to 3 edges (measured best on the power-law graph
+        // with L = 5; a fourth slot costs more occupancy than it gains)
+        int eb = g_tune[TG_TUNE_DERIVE_EDGES] > 0 ? (int)g_tune[TG_TUNE_DERIVE_EDGES] : 64 / P;
+        if (g_tune[TG_TUNE_DERIVE_EDGES] == 0 && eb > 3) eb = 3;
+        if (eb > 4) eb = 4;
+        if (eb < 1 || batch) eb = 1;
+        ea.derive_batch = eb;
+    }
     ea.heavy_list = le; ea.counters = counters; ea.tbuf = tbuf; ea.n = n; ea.status = status;
     ea.hub_base = hub_base; ea.Hw = Hw; ea.hstart = hstart; ea.nlow = nlow; ea.HB = HB; ea.hpre = hpre; ea.TM = TM;
     ea.sh_base = sh_base; ea.nw = nw; ea.SB = SB; ea.SP = SP;
@@ -398,6 +410,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     EdgeArgs eh = ea;
     if (batch) eh.hist_in_lds = 0;  // heavy edges of many graphs: direct per-graph atomics
     else eh.hist_in_lds = ea.hist_in_lds ? 1 : 0;
+    eh.derive_batch = 1;
     HIPCHK(launch_edges(true, eh, (unsigned)y.heavy_edge_slots, st));
     timing_mark("edges_heavy");
     if (batch)
@@ -589,6 +602,9 @@ tg_status tg_set_tuning(int32_t knob, int64_t value) {
     case TG_TUNE_RANGE_BYTES:
         if (value < 0) return TG_E_INVALID_ARG;
         break;
+    case TG_TUNE_DERIVE_EDGES:
+        if (value < 0 || value > 4) return TG_E_INVALID_ARG;
+        break;
     default:
         return TG_E_INVALID_ARG;
     }
@@ -597,7 +613,7 @@ tg_status tg_set_tuning(int32_t knob, int64_t value) {
 }
 
 int64_t tg_get_tuning(int32_t knob) {
-    if (knob < 0 || knob > TG_TUNE_RANGE_BYTES) return -1;
+    if (knob < 0 || knob > TG_TUNE_DERIVE_EDGES) return -1;
     return tg::g_tune[knob];
 }
 

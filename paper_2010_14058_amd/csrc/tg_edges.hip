@@ -483,33 +483,36 @@ __device__ void edge_cliques(const EdgeArgs &a, int32_t i, int32_t j, const Edge
 // aggregate quantities (inclusion-exclusion in the spirit of Theorem 1;
 // Lemmas 1-4 for g4, g5, g9, g11), the row write and the histogram.
 template <int NT>
-__device__ void edge_derive(const EdgeArgs &a, int64_t e, int32_t i, int32_t j, const EdgeShared &S,
-                            uint64_t *hist, int tid, uint32_t &bad) {
-    const int64_t gid = a.batch ? (int64_t)a.ngraph[i] : 0;
+__device__ void edge_derive(const EdgeArgs &a, int nb, const int64_t *slot_e, const int32_t *slot_i,
+                            const int32_t *slot_j, const uint64_t *xyk, uint64_t *hist, int tid,
+                            uint32_t &bad) {
+    // nb edges at once (their Xi, Xj, Y, K in consecutive LDS slots of
+    // 4 L^2 words), so that the per-pair work of several edges fills a wave
     const int L = a.L;
-    const uint64_t *Xi = S.Xi, *Xj = S.Xj, *Y = S.Y, *K = S.K;
-    const int ta = a.ntype[i], tb = a.ntype[j];
     const int LL = L * L;
     const int P = L * (L + 1) / 2;
     const int W = 2 * L + 10 * P;
-    const uint32_t *tri_e = a.tri + (size_t)e * L;
-    const uint32_t *di = a.tdeg + (size_t)i * L;
-    const uint32_t *dj = a.tdeg + (size_t)j * L;
-    const uint64_t *Ai = a.A + (size_t)i * LL, *Aj = a.A + (size_t)j * LL;
-    const uint64_t *Di = a.D + (size_t)i * LL, *Dj = a.D + (size_t)j * LL;
-    const uint64_t *NC = a.NC + (size_t)e * LL;
-    uint64_t *row = a.rows ? a.rows + (size_t)e * W : nullptr;
     const int n2 = (int)binom_small(L + 1, 2);
     const int n3 = (int)binom_small(L + 2, 3);
     const int n4 = (int)binom_small(L + 3, 4);
 
-    if (tid == 0) hist_add(a, hist, rank2(ta, tb), 1, gid);
-    for (int t = tid; t < L; t += NT) {
-        int64_t nTt = tri_e[t];
-        int64_t si = (int64_t)di[t] - nTt - (tb == t);
-        int64_t sj = (int64_t)dj[t] - nTt - (ta == t);
+    for (int b = tid; b < nb; b += NT) {
+        const int32_t i = slot_i[b], j = slot_j[b];
+        const int64_t gid = a.batch ? (int64_t)a.ngraph[i] : 0;
+        hist_add(a, hist, rank2(a.ntype[i], a.ntype[j]), 1, gid);
+    }
+    for (int it = tid; it < nb * L; it += NT) {
+        const int b = it / L, t = it - b * L;
+        const int64_t e = slot_e[b];
+        const int32_t i = slot_i[b], j = slot_j[b];
+        const int64_t gid = a.batch ? (int64_t)a.ngraph[i] : 0;
+        const int ta = a.ntype[i], tb = a.ntype[j];
+        int64_t nTt = a.tri[(size_t)e * L + t];
+        int64_t si = (int64_t)a.tdeg[(size_t)i * L + t] - nTt - (tb == t);
+        int64_t sj = (int64_t)a.tdeg[(size_t)j * L + t] - nTt - (ta == t);
         if (si < 0 || sj < 0) bad |= ST_INTERNAL;
-        if (row) {
+        if (a.rows) {
+            uint64_t *row = a.rows + (size_t)e * W;
             row[t] = (uint64_t)nTt;
             row[L + t] = (uint64_t)(si + sj);
         }
@@ -518,7 +521,21 @@ __device__ void edge_derive(const EdgeArgs &a, int64_t e, int32_t i, int32_t j, 
         hist_add(a, hist, n2 + n3 + r3, (uint64_t)nTt, gid);
     }
     const int hbase = n2 + 2 * n3;
-    for (int p = tid; p < P; p += NT) {
+    for (int it = tid; it < nb * P; it += NT) {
+        const int b = it / P, p = it - b * P;
+        const int64_t e = slot_e[b];
+        const int32_t i = slot_i[b], j = slot_j[b];
+        const int64_t gid = a.batch ? (int64_t)a.ngraph[i] : 0;
+        const int ta = a.ntype[i], tb = a.ntype[j];
+        const uint64_t *Xi = xyk + (size_t)b * 4 * LL, *Xj = Xi + LL, *Y = Xi + 2 * LL,
+                       *K = Xi + 3 * LL;
+        const uint32_t *tri_e = a.tri + (size_t)e * L;
+        const uint32_t *di = a.tdeg + (size_t)i * L;
+        const uint32_t *dj = a.tdeg + (size_t)j * L;
+        const uint64_t *Ai = a.A + (size_t)i * LL, *Aj = a.A + (size_t)j * LL;
+        const uint64_t *Di = a.D + (size_t)i * LL, *Dj = a.D + (size_t)j * LL;
+        const uint64_t *NC = a.NC + (size_t)e * LL;
+        uint64_t *row = a.rows ? a.rows + (size_t)e * W : nullptr;
         // pair (t, u), t <= u, from its lexicographic index
         int t = 0, rem = p;
         while (rem >= L - t) { rem -= L - t; ++t; }
@@ -589,7 +606,7 @@ __device__ void edge_derive(const EdgeArgs &a, int64_t e, int32_t i, int32_t j, 
 }
 
 // LDS layout shared by both edge kernels (dynamic part), in uint64 words:
-// [Xi Xj Y K : 4 L^2][hist : gw if in LDS][Tm : Hw] then uint32 lists.
+// [Xi Xj Y K : 4 L^2 per derive slot][hist][Tm : Hw] then uint32 lists.
 __device__ __forceinline__ EdgeShared carve(const EdgeArgs &a, uint64_t *sm, uint32_t *meta,
                                             uint32_t *wave_cnt, uint64_t **hist, uint32_t *Th,
                                             int th_step, uint32_t *Tl) {
@@ -599,7 +616,7 @@ __device__ __forceinline__ EdgeShared carve(const EdgeArgs &a, uint64_t *sm, uin
     S.Xj = sm + LL;
     S.Y = sm + 2 * LL;
     S.K = sm + 3 * LL;
-    *hist = sm + 4 * LL;
+    *hist = sm + 4 * LL * a.derive_batch;
     S.Tm = *hist + hist_words(a);
     S.Th = Th;
     S.th_step = th_step;
@@ -619,7 +636,8 @@ __global__ void __launch_bounds__(64) k_edges_light(EdgeArgs a) {
     const ScanScratch F{fl_r, fl_start, fl_scan};
     const int LL = a.L * a.L;
     uint64_t *hist;
-    uint64_t *after = sm_edge + 4 * LL + hist_words(a) + a.Hw;
+    const int EB = a.derive_batch;
+    uint64_t *after = sm_edge + 4 * LL * EB + hist_words(a) + a.Hw;
     // one list of tcap entries: low members from the front, hub members from
     // the back (|T| <= min degree <= tcap)
     uint32_t *Tl = (uint32_t *)after;
@@ -629,6 +647,11 @@ __global__ void __launch_bounds__(64) k_edges_light(EdgeArgs a) {
     uint32_t bad = 0;
     for (int q = lane; q < hist_words(a); q += WAVE) hist[q] = 0;
     __syncthreads();
+    __shared__ int64_t slot_e[4];
+    __shared__ int32_t slot_i[4], slot_j[4];
+    int nb = 0;  // edges waiting for their derivation
+    // build T, the gathers and the cliques of edge e into derive slot nb;
+    // edges of the heavy path are queued instead
     auto one_edge = [&](int64_t e) {
         int32_t i = a.ei[e], j = a.ej[e];
         int64_t di = a.nrp[i + 1] - a.nrp[i], dj = a.nrp[j + 1] - a.nrp[j];
@@ -638,13 +661,33 @@ __global__ void __launch_bounds__(64) k_edges_light(EdgeArgs a) {
                     (uint32_t)e;
             return;
         }
-        edge_build<WAVE>(a, i, j, S, lane);
-        edge_cliques<WAVE>(a, i, j, S, a.TM, F, lane);
-        edge_derive<WAVE>(a, e, i, j, S, hist, lane, bad);
+        EdgeShared Sb = S;
+        Sb.Xi = S.Xi + (size_t)nb * 4 * LL;
+        Sb.Xj = Sb.Xi + LL;
+        Sb.Y = Sb.Xi + 2 * LL;
+        Sb.K = Sb.Xi + 3 * LL;
+        edge_build<WAVE>(a, i, j, Sb, lane);
+        edge_cliques<WAVE>(a, i, j, Sb, a.TM, F, lane);
+        if (lane == 0) {
+            slot_e[nb] = e;
+            slot_i[nb] = i;
+            slot_j[nb] = j;
+        }
+        ++nb;
+    };
+    auto derive_all = [&]() {
+        if (!nb) return;
         __syncthreads();
+        edge_derive<WAVE>(a, nb, slot_e, slot_i, slot_j, S.Xi, hist, lane, bad);
+        __syncthreads();
+        nb = 0;
     };
     if (!a.batch) {
-        for (int64_t e = blockIdx.x; e < a.m; e += gridDim.x) one_edge(e);
+        for (int64_t e = blockIdx.x; e < a.m; e += gridDim.x) {
+            one_edge(e);
+            if (nb == EB) derive_all();
+        }
+        derive_all();
         if (a.hist_in_lds)
             for (int q = lane; q < a.gw; q += WAVE) {
                 uint64_t v = hist_take(a, hist, q);
@@ -679,6 +722,7 @@ __global__ void __launch_bounds__(64) k_edges_light(EdgeArgs a) {
                     cur = g;
                 }
                 one_edge(e);
+                derive_all();
             }
             flush(cur);
         }
@@ -695,13 +739,15 @@ __global__ void __launch_bounds__(EDGE_THREADS_HEAVY) k_edges_heavy(EdgeArgs a) 
     __shared__ uint32_t meta[4];
     __shared__ uint32_t wave_cnt[EDGE_THREADS_HEAVY / WAVE];
     __shared__ uint64_t s_idx;
+    __shared__ int64_t slot_e[1];
+    __shared__ int32_t slot_i[1], slot_j[1];
     __shared__ uint32_t fl_r[EDGE_THREADS_HEAVY], fl_scan[EDGE_THREADS_HEAVY];
     __shared__ int64_t fl_start[EDGE_THREADS_HEAVY];
     const ScanScratch F{fl_r, fl_start, fl_scan};
     const int NT = EDGE_THREADS_HEAVY;
     const int LL = a.L * a.L;
     uint64_t *hist;
-    uint64_t *after = sm_edgeh + 4 * LL + hist_words(a) + a.Hw;
+    uint64_t *after = sm_edgeh + 4 * LL * a.derive_batch + hist_words(a) + a.Hw;
     uint64_t *TMs = after;                        // type masks of the hub core
     uint32_t *Th = (uint32_t *)(TMs + (size_t)a.L * a.Hw);
     uint32_t *Tl = a.tbuf + (size_t)blockIdx.x * (size_t)a.n;
@@ -724,7 +770,13 @@ __global__ void __launch_bounds__(EDGE_THREADS_HEAVY) k_edges_heavy(EdgeArgs a) 
         __threadfence_block();
         __syncthreads();
         edge_cliques<NT>(a, i, j, S, TMs, F, tid);
-        edge_derive<NT>(a, e, i, j, S, hist, tid, bad);
+        if (tid == 0) {
+            slot_e[0] = e;
+            slot_i[0] = i;
+            slot_j[0] = j;
+        }
+        __syncthreads();
+        edge_derive<NT>(a, 1, slot_e, slot_i, slot_j, S.Xi, hist, tid, bad);
         __threadfence_block();
         __syncthreads();
     }
@@ -753,7 +805,7 @@ hipError_t launch_hub_build(const int64_t *nrp, const int32_t *ncol, const int64
 size_t edge_lds_bytes(const EdgeArgs &args, bool heavy) {
     int LL = args.L * args.L;
     const int hw = args.hist_in_lds == 2 ? (args.gw + 1) / 2 : args.hist_in_lds ? args.gw : 0;
-    size_t sh = (size_t)(4 * LL + hw + args.Hw) * sizeof(uint64_t);
+    size_t sh = (size_t)(4 * LL * args.derive_batch + hw + args.Hw) * sizeof(uint64_t);
     if (!heavy) sh += (size_t)args.tcap * sizeof(uint32_t);
     else sh += (size_t)args.L * args.Hw * sizeof(uint64_t) +
                (size_t)(args.hub_base < args.n ? (args.n - args.hub_base) : 0) * sizeof(uint32_t);

@@ -125,6 +125,7 @@ struct EdgeArgs {
     int gw;
     int hist_in_lds;             // 0: global atomics, 1: uint64 LDS histogram, 2: uint32 LDS histogram
     int tcap;                    // triangle-list entries in LDS (light kernel)
+    int derive_batch;            // edges whose derivation runs together (LDS slots of 4 L^2 words)
     uint32_t *heavy_list;
     uint64_t *counters;
     uint32_t *tbuf;      // heavy: per-workgroup low-member buffers of n entries

@@ -215,3 +215,18 @@ def test_split_heavy_tasks(oracle_mod, knobs):
         check(oracle_mod, G.config_graph(2, scale=0.01))
     finally:
         P.set_tuning(**old)
+
+
+@pytest.mark.parametrize("derive_edges", [1, 2, 3, 4])
+def test_derive_batching(oracle_mod, derive_edges):
+    """The light kernel derives several edges' rows in one wave; every batch
+    size gives the same counts (L = 3 and L = 5, heavy edges interleaved)."""
+    import paper_2010_14058_amd as P
+
+    old = P.set_tuning(derive_edges=derive_edges)
+    try:
+        check(oracle_mod, G.config_graph(2, scale=0.005))
+        g = G.chung_lu_typed(3000, 12.0, 2.1, 1500.0, 3, seed=9, name="cl_3k_L3")
+        check(oracle_mod, g)
+    finally:
+        P.set_tuning(**old)
