@@ -188,6 +188,7 @@ struct EdgeShared {
     uint32_t *Tl;           // low members, ascending
     uint32_t *meta;         // [0] |Tl| [1] |Th| [2] first word of Tm [3] last word
     uint32_t *wave_cnt;     // ordered_append scratch
+    uint64_t *Gw;           // per-wave copies of Xi, Xj, Y (3 L^2 words each) or null
 };
 
 // Build T (hub mask/list and sorted low list) and the gathers X_i, X_j, Y.
@@ -197,7 +198,14 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
     const int Hw = a.Hw;
     const int32_t base = a.hub_base;
     for (int q = tid; q < 4 * LL; q += NT) S.Xi[q] = 0;
+    if (S.Gw)
+        for (int q = tid; q < (NT / WAVE) * 3 * LL; q += NT) S.Gw[q] = 0;
     for (int q = tid; q < Hw; q += NT) S.Tm[q] = 0;
+    // gathers go to this wave's private copy when there is one (fewer
+    // conflicting LDS atomics), summed into Xi, Xj, Y at the end
+    uint64_t *gXi = S.Gw ? S.Gw + (size_t)(tid / WAVE) * 3 * LL : S.Xi;
+    uint64_t *gXj = S.Gw ? gXi + LL : S.Xj;
+    uint64_t *gY = S.Gw ? gXi + 2 * LL : S.Y;
     if (tid == 0) {
         S.meta[0] = 0;
         S.meta[1] = 0;
@@ -251,7 +259,7 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
             }
             if (found) {
                 S.Tl[pos] = (uint32_t)x;
-                gather_member(a, x, i_small ? p : q, i_small ? q : p, S.Xi, S.Xj, S.Y);
+                gather_member(a, x, i_small ? p : q, i_small ? q : p, gXi, gXj, gY);
             }
         }
         if (tid == 0 && !unordered) S.meta[0] = count;
@@ -274,7 +282,8 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
                 int32_t k = base + hk;
                 uint32_t pos = atomicAdd(&S.meta[1], 1u);
                 S.Th[(ptrdiff_t)pos * S.th_step] = (uint32_t)k;
-                gather_member(a, k, hub_slot(a, i, hx_i, hk), hub_slot(a, j, hx_j, hk), S.Xi, S.Xj, S.Y);
+                gather_member(a, k, hub_slot(a, i, hx_i, hk), hub_slot(a, j, hx_j, hk), gXi, gXj,
+                              gY);
             }
         }
     } else {
@@ -303,10 +312,18 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
             atomicMax(&S.meta[3], (uint32_t)(hk >> 6));
             uint32_t pos = atomicAdd(&S.meta[1], 1u);
             S.Th[(ptrdiff_t)pos * S.th_step] = (uint32_t)x;
-            gather_member(a, x, i_small ? p : q, i_small ? q : p, S.Xi, S.Xj, S.Y);
+            gather_member(a, x, i_small ? p : q, i_small ? q : p, gXi, gXj, gY);
         }
     }
     group_sync<NT>();
+    if (S.Gw) {
+        for (int q = tid; q < 3 * LL; q += NT) {
+            uint64_t v = 0;
+            for (int w = 0; w < NT / WAVE; ++w) v += S.Gw[(size_t)w * 3 * LL + q];
+            S.Xi[q] = v;  // Xi, Xj, Y are consecutive
+        }
+        group_sync<NT>();
+    }
 }
 
 // Inclusive scan of one value per thread over the NT threads.
@@ -623,6 +640,7 @@ __device__ __forceinline__ EdgeShared carve(const EdgeArgs &a, uint64_t *sm, uin
     S.Tl = Tl;
     S.meta = meta;
     S.wave_cnt = wave_cnt;
+    S.Gw = nullptr;
     return S;
 }
 
@@ -749,9 +767,11 @@ __global__ void __launch_bounds__(EDGE_THREADS_HEAVY) k_edges_heavy(EdgeArgs a) 
     uint64_t *hist;
     uint64_t *after = sm_edgeh + 4 * LL * a.derive_batch + hist_words(a) + a.Hw;
     uint64_t *TMs = after;                        // type masks of the hub core
-    uint32_t *Th = (uint32_t *)(TMs + (size_t)a.L * a.Hw);
+    uint64_t *Gw = TMs + (size_t)a.L * a.Hw;      // per-wave gather copies
+    uint32_t *Th = (uint32_t *)(Gw + (size_t)(NT / WAVE) * 3 * LL);
     uint32_t *Tl = a.tbuf + (size_t)blockIdx.x * (size_t)a.n;
     EdgeShared S = carve(a, sm_edgeh, meta, wave_cnt, &hist, Th, 1, Tl);
+    S.Gw = Gw;
     int tid = threadIdx.x;
     for (int q = tid; q < a.L * a.Hw; q += NT) TMs[q] = a.TM[q];
     uint32_t bad = 0;
@@ -808,6 +828,7 @@ size_t edge_lds_bytes(const EdgeArgs &args, bool heavy) {
     size_t sh = (size_t)(4 * LL * args.derive_batch + hw + args.Hw) * sizeof(uint64_t);
     if (!heavy) sh += (size_t)args.tcap * sizeof(uint32_t);
     else sh += (size_t)args.L * args.Hw * sizeof(uint64_t) +
+               (size_t)(EDGE_THREADS_HEAVY / WAVE) * 3 * LL * sizeof(uint64_t) +
                (size_t)(args.hub_base < args.n ? (args.n - args.hub_base) : 0) * sizeof(uint32_t);
     return sh;
 }
