@@ -624,7 +624,10 @@ __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
             uint64_t idx = atomicAdd((unsigned long long *)&a.counters[a.next_idx], 1ull);
             s_task[0] = -1;
             if (idx < count) {
-                uint4 tk = a.tasks[idx];
+                // groups were queued by increasing id, and the largest groups
+                // belong to the highest-ranked nodes: take them first so the
+                // longest tasks do not form the tail
+                uint4 tk = a.tasks[count - 1 - idx];
                 int32_t g = (int32_t)tk.x;
                 int32_t rb = PASS == 0 ? 0 : g + 1;
                 int32_t re = PASS == 0 ? g : (int32_t)a.n;
