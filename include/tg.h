@@ -180,7 +180,7 @@ const char *tg_last_error(void);
  * the counts.
  *   TG_TUNE_TASK_WEDGES  (default 262144, >= 1): a heavy wedge group is split
  *       into target-id ranges of about this many wedges each (at most 64).
- *   TG_TUNE_CLEAR_BYTES  (default 16, >= 0): a task clears its map range by
+ *   TG_TUNE_CLEAR_BYTES  (default 64, >= 0): a task clears its map range by
  *       streaming zeros when the range costs at most this many bytes per
  *       wedge of the task, else by a walk over its wedges; 0 never streams.
  *   TG_TUNE_CYCLE_SLOTS  (default 1024, 1..65536): most workgroups of the heavy

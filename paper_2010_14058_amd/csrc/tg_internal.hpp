@@ -31,7 +31,7 @@ constexpr int HEAVY_CHUNK = 128;      // items staged per round in the heavy pat
 constexpr int64_t TASK_WEDGES = 1 << 18;  // default wedges per heavy task (target range)
 constexpr int TASK_MAX_PARTS = 64;        // most target ranges per heavy group
 constexpr int64_t TASK_EXTRA = 1 << 16;   // task slots beyond one per node, shared by both passes
-constexpr int SEQ_CLEAR_BYTES = 16;       // default bytes per wedge below which a range is cleared by streaming
+constexpr int SEQ_CLEAR_BYTES = 64;       // default bytes per wedge below which a range is cleared by streaming
 constexpr int64_t TASK_RANGE_BYTES = 0;  // default map-byte bound per task of a dense heavy group (0: off)
 constexpr int TCAP = 1024;            // triangle set kept in LDS by the light edge kernel
 constexpr int EDGE_THREADS_HEAVY = 256;

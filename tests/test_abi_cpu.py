@@ -81,10 +81,10 @@ def test_tuning_knobs():
     import paper_2010_14058_amd as P
 
     base = P.get_tuning()
-    assert base["task_wedges"] == 1 << 18 and base["clear_bytes"] == 16
+    assert base["task_wedges"] == 1 << 18 and base["clear_bytes"] == 64
     assert base["cycle_slots"] >= 1 and base["edge_slots"] >= 1
     old = P.set_tuning(task_wedges=100, clear_bytes=0)
-    assert old == {"task_wedges": 1 << 18, "clear_bytes": 16}
+    assert old == {"task_wedges": 1 << 18, "clear_bytes": 64}
     now = P.get_tuning()
     assert now["task_wedges"] == 100 and now["clear_bytes"] == 0
     ws = P.workspace_bytes(1000, 8000, 5)
