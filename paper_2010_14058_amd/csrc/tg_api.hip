@@ -33,6 +33,8 @@ static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 static const size_t MAP_BUDGET = size_t(32) << 30;
 static const size_t TBUF_BUDGET = size_t(8) << 30;
 static const int MAX_HEAVY_SLOTS = 1024;
+// Largest per-edge buffer of triangle-set sums for a separate derivation pass.
+static const size_t XYK_BUDGET = size_t(16) << 30;
 
 // Scheduling knobs (tg_set_tuning), per host thread.
 thread_local int64_t g_tune[8] = {TASK_WEDGES, SEQ_CLEAR_BYTES, MAX_HEAVY_SLOTS,
@@ -126,6 +128,9 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G) {
     y.off_sort_tmp = take(y.sort_tmp_bytes);
     y.off_hstart = take(sizeof(int64_t) * (n + 1));
     y.off_eslot = take(sizeof(uint32_t) * (2 * y.m + 1));
+    // deferred derivation (single graphs): Xi, Xj, Y, K of every edge
+    y.defer = G == 0 && (size_t)y.m * 4 * LL * sizeof(uint64_t) <= XYK_BUDGET;
+    if (y.defer) y.off_xyk = take(sizeof(uint64_t) * (size_t)(y.m + 1) * 4 * LL);
     y.off_nlow = take(sizeof(uint32_t) * (n + 1));
     const size_t hw = HUB_MAX / 64;
     y.off_HB = take(sizeof(uint64_t) * HUB_MAX * hw);
@@ -402,6 +407,13 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     ea.goff = batch ? batch->goff : nullptr;
     ea.G = batch ? batch->G : 1;
     if (batch) ea.gacc = global_counts;
+    uint64_t *xyk = y.defer ? at<uint64_t>(ws, y.off_xyk) : nullptr;
+    ea.xyk = xyk;
+    EdgeArgs ed = ea;  // the separate derivation pass keeps the histogram
+    if (xyk) {
+        ea.hist_in_lds = 0;
+        ea.derive_batch = 1;
+    }
     unsigned edge_grid = (unsigned)(cus > 0 ? cus * 24 : 2048);
     int64_t units = batch ? (m + BATCH_EDGE_CHUNK - 1) / BATCH_EDGE_CHUNK : m;
     if ((int64_t)edge_grid > units) edge_grid = (unsigned)(units > 0 ? units : 1);
@@ -411,8 +423,14 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     if (batch) eh.hist_in_lds = 0;  // heavy edges of many graphs: direct per-graph atomics
     else eh.hist_in_lds = ea.hist_in_lds ? 1 : 0;
     eh.derive_batch = 1;
+    if (xyk) eh.hist_in_lds = 0;
     HIPCHK(launch_edges(true, eh, (unsigned)y.heavy_edge_slots, st));
     timing_mark("edges_heavy");
+    if (xyk) {
+        ed.hist_in_lds = (size_t)gw * sizeof(uint64_t) <= 32768 ? 1 : 0;
+        HIPCHK(launch_derive(ed, (unsigned)(cus > 0 ? cus * 8 : 2048), st));
+        timing_mark("derive");
+    }
     if (batch)
         HIPCHK(launch_batch_finalize(global_counts, batch->gL, batch->goff, batch->G, status, st));
     else if (global_counts)

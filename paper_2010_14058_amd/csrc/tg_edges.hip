@@ -499,6 +499,121 @@ __device__ void edge_cliques(const EdgeArgs &a, int32_t i, int32_t j, const Edge
 // Every orbit of Table 3 for edge e from the triangle, clique, cycle and
 // aggregate quantities (inclusion-exclusion in the spirit of Theorem 1;
 // Lemmas 1-4 for g4, g5, g9, g11), the row write and the histogram.
+// Derivation (Sec. 4 identities, Lemmas 1-4) of one edge's 3-node entries
+// for type t, and of its 4-node orbits for type pair p; xyk holds the edge's
+// Xi, Xj, Y, K (4 L^2 words, in LDS or global memory).
+__device__ __forceinline__ void derive_three(const EdgeArgs &a, int64_t e, int32_t i, int32_t j,
+                                             int t, uint64_t *hist, uint32_t &bad) {
+    const int L = a.L;
+    const int P = L * (L + 1) / 2;
+    const int W = 2 * L + 10 * P;
+    const int n2 = (int)binom_small(L + 1, 2);
+    const int n3 = (int)binom_small(L + 2, 3);
+    const int64_t gid = a.batch ? (int64_t)a.ngraph[i] : 0;
+    const int ta = a.ntype[i], tb = a.ntype[j];
+    int64_t nTt = a.tri[(size_t)e * L + t];
+    int64_t si = (int64_t)a.tdeg[(size_t)i * L + t] - nTt - (tb == t);
+    int64_t sj = (int64_t)a.tdeg[(size_t)j * L + t] - nTt - (ta == t);
+    if (si < 0 || sj < 0) bad |= ST_INTERNAL;
+    if (a.rows) {
+        uint64_t *row = a.rows + (size_t)e * W;
+        row[t] = (uint64_t)nTt;
+        row[L + t] = (uint64_t)(si + sj);
+    }
+    int r3 = rank3(ta, tb, t);
+    hist_add(a, hist, n2 + r3, (uint64_t)(si + sj), gid);
+    hist_add(a, hist, n2 + n3 + r3, (uint64_t)nTt, gid);
+}
+
+__device__ __forceinline__ void derive_pair(const EdgeArgs &a, int64_t e, int32_t i, int32_t j,
+                                            int p, const uint64_t *xyk, uint64_t *hist,
+                                            uint32_t &bad) {
+    const int L = a.L;
+    const int LL = L * L;
+    const int P = L * (L + 1) / 2;
+    const int W = 2 * L + 10 * P;
+    const int n2 = (int)binom_small(L + 1, 2);
+    const int n3 = (int)binom_small(L + 2, 3);
+    const int n4 = (int)binom_small(L + 3, 4);
+    const int hbase = n2 + 2 * n3;
+    const int64_t gid = a.batch ? (int64_t)a.ngraph[i] : 0;
+    const int ta = a.ntype[i], tb = a.ntype[j];
+    const uint64_t *Xi = xyk, *Xj = Xi + LL, *Y = Xi + 2 * LL, *K = Xi + 3 * LL;
+    const uint32_t *tri_e = a.tri + (size_t)e * L;
+    const uint32_t *di = a.tdeg + (size_t)i * L;
+    const uint32_t *dj = a.tdeg + (size_t)j * L;
+    const uint64_t *Ai = a.A + (size_t)i * LL, *Aj = a.A + (size_t)j * LL;
+    const uint64_t *Di = a.D + (size_t)i * LL, *Dj = a.D + (size_t)j * LL;
+    const uint64_t *NC = a.NC + (size_t)e * LL;
+    uint64_t *row = a.rows ? a.rows + (size_t)e * W : nullptr;
+    // pair (t, u), t <= u, from its lexicographic index
+    int t = 0, rem = p;
+    while (rem >= L - t) { rem -= L - t; ++t; }
+    const int u = t + rem;
+    const bool same = t == u;
+    const int r4 = rank4(ta, tb, t, u);
+    const int qa = t * L + u, qb = u * L + t;   // ordered (t,u) and (u,t)
+    const int64_t nTt = tri_e[t], nTu = tri_e[u];
+    const int64_t Sit = (int64_t)di[t] - nTt - (tb == t), Siu = (int64_t)di[u] - nTu - (tb == u);
+    const int64_t Sjt = (int64_t)dj[t] - nTt - (ta == t), Sju = (int64_t)dj[u] - nTu - (ta == u);
+    auto emit = [&](int o, int64_t v) {
+        if (v < 0) bad |= ST_INTERNAL;
+        if (row) row[2 * L + (o - 3) * P + p] = (uint64_t)v;
+        // graphlet of each orbit (Sec. 4.4): h3 = g3+g4, h4 = g5,
+        // h5 = g6, h6 = g7+g8+g9, h7 = g10+g11, h8 = g12
+        const int h = o <= 4 ? 3 : o == 5 ? 4 : o == 6 ? 5 : o <= 9 ? 6 : o <= 11 ? 7 : 8;
+        hist_add(a, hist, hbase + (h - 3) * n4 + r4, (uint64_t)v, gid);
+    };
+    // cliques and chordal cycles
+    const int64_t K0 = (int64_t)K[qa], K1 = (int64_t)K[qb];
+    if (same && (K0 & 1)) bad |= ST_INTERNAL;
+    if (!same && K0 != K1) bad |= ST_INTERNAL;
+    const int64_t g12 = same ? K0 / 2 : K0;
+    emit(12, g12);
+    emit(11, (same ? nTt * (nTt - 1) / 2 : nTt * nTu) - g12);                 // Lemma 4
+    const int64_t Xi0 = (int64_t)Xi[qa], Xi1 = (int64_t)Xi[qb];
+    const int64_t Xj0 = (int64_t)Xj[qa], Xj1 = (int64_t)Xj[qb];
+    // C_i(x,y): pairs k in T^x, r in S_i^y adjacent; likewise C_j
+    const int64_t Ci0 = Xi0 - nTt * (tb == u) - K0, Ci1 = Xi1 - nTu * (tb == t) - K1;
+    const int64_t Cj0 = Xj0 - nTt * (ta == u) - K0, Cj1 = Xj1 - nTu * (ta == t) - K1;
+    const int64_t g10 = same ? Ci0 + Cj0 : Ci0 + Cj0 + Ci1 + Cj1;
+    emit(10, g10);
+    emit(9, (same ? nTt * (Sit + Sjt) : nTt * (Siu + Sju) + nTu * (Sit + Sjt)) - g10);  // Lemma 3
+    // 4-cycles: non-induced cycles minus chordal and clique instances
+    const int64_t Cyc0 = (int64_t)NC[qa] - Ci1 - Cj0 - K0;
+    const int64_t Cyc1 = (int64_t)NC[qb] - Ci0 - Cj1 - K1;
+    const int64_t g6 = same ? Cyc0 : Cyc0 + Cyc1;
+    emit(6, g6);
+    emit(4, (same ? Sit * Sjt : Sit * Sju + Siu * Sjt) - g6);                 // Lemma 1
+    // tailed-triangle tails: adjacent pairs inside S_i (resp. S_j)
+    const int64_t sgi0 = (int64_t)Ai[qa] - Xi0 - (tb == t) * nTu;
+    const int64_t sgi1 = (int64_t)Ai[qb] - Xi1 - (tb == u) * nTt;
+    const int64_t sgj0 = (int64_t)Aj[qa] - Xj0 - (ta == t) * nTu;
+    const int64_t sgj1 = (int64_t)Aj[qb] - Xj1 - (ta == u) * nTt;
+    const int64_t Ei0 = sgi0 - Ci1, Ei1 = sgi1 - Ci0;
+    const int64_t Ej0 = sgj0 - Cj1, Ej1 = sgj1 - Cj0;
+    if (same && ((Ei0 + Ej0) & 1)) bad |= ST_INTERNAL;
+    if (!same && (Ei0 != Ei1 || Ej0 != Ej1)) bad |= ST_INTERNAL;
+    const int64_t g7 = same ? (Ei0 + Ej0) / 2 : Ei0 + Ej0;
+    emit(7, g7);
+    emit(5, (same ? Sit * (Sit - 1) / 2 + Sjt * (Sjt - 1) / 2 : Sit * Siu + Sjt * Sju) - g7);  // Lemma 2
+    // 4-path end edges: neighbours of S_i / S_j outside the edge's sets
+    const int64_t Y0 = (int64_t)Y[qa], Y1 = (int64_t)Y[qb];
+    const int64_t dli0 = (int64_t)Di[qa] - Y0 - (tb == t) * (int64_t)dj[u];
+    const int64_t dli1 = (int64_t)Di[qb] - Y1 - (tb == u) * (int64_t)dj[t];
+    const int64_t dlj0 = (int64_t)Dj[qa] - Y0 - (ta == t) * (int64_t)di[u];
+    const int64_t dlj1 = (int64_t)Dj[qb] - Y1 - (ta == u) * (int64_t)di[t];
+    const int64_t Pi0 = dli0 - Sit * (ta == u) - sgi0 - Cyc0;
+    const int64_t Pi1 = dli1 - Siu * (ta == t) - sgi1 - Cyc1;
+    const int64_t Pj0 = dlj0 - Sjt * (tb == u) - sgj0 - Cyc1;
+    const int64_t Pj1 = dlj1 - Sju * (tb == t) - sgj1 - Cyc0;
+    emit(3, same ? Pi0 + Pj0 : Pi0 + Pi1 + Pj0 + Pj1);
+    // tailed-triangle edges opposite the tail's node
+    const int64_t Q0 = Y0 - Xi0 - Cj0 - nTt * (ta == u);
+    const int64_t Q1 = Y1 - Xi1 - Cj1 - nTu * (ta == t);
+    emit(8, same ? Q0 : Q0 + Q1);
+}
+
 template <int NT>
 __device__ void edge_derive(const EdgeArgs &a, int nb, const int64_t *slot_e, const int32_t *slot_i,
                             const int32_t *slot_j, const uint64_t *xyk, uint64_t *hist, int tid,
@@ -508,117 +623,19 @@ __device__ void edge_derive(const EdgeArgs &a, int nb, const int64_t *slot_e, co
     const int L = a.L;
     const int LL = L * L;
     const int P = L * (L + 1) / 2;
-    const int W = 2 * L + 10 * P;
-    const int n2 = (int)binom_small(L + 1, 2);
-    const int n3 = (int)binom_small(L + 2, 3);
-    const int n4 = (int)binom_small(L + 3, 4);
-
     for (int b = tid; b < nb; b += NT) {
         const int32_t i = slot_i[b], j = slot_j[b];
         const int64_t gid = a.batch ? (int64_t)a.ngraph[i] : 0;
         hist_add(a, hist, rank2(a.ntype[i], a.ntype[j]), 1, gid);
     }
     for (int it = tid; it < nb * L; it += NT) {
-        const int b = it / L, t = it - b * L;
-        const int64_t e = slot_e[b];
-        const int32_t i = slot_i[b], j = slot_j[b];
-        const int64_t gid = a.batch ? (int64_t)a.ngraph[i] : 0;
-        const int ta = a.ntype[i], tb = a.ntype[j];
-        int64_t nTt = a.tri[(size_t)e * L + t];
-        int64_t si = (int64_t)a.tdeg[(size_t)i * L + t] - nTt - (tb == t);
-        int64_t sj = (int64_t)a.tdeg[(size_t)j * L + t] - nTt - (ta == t);
-        if (si < 0 || sj < 0) bad |= ST_INTERNAL;
-        if (a.rows) {
-            uint64_t *row = a.rows + (size_t)e * W;
-            row[t] = (uint64_t)nTt;
-            row[L + t] = (uint64_t)(si + sj);
-        }
-        int r3 = rank3(ta, tb, t);
-        hist_add(a, hist, n2 + r3, (uint64_t)(si + sj), gid);
-        hist_add(a, hist, n2 + n3 + r3, (uint64_t)nTt, gid);
+        const int b = it / L;
+        derive_three(a, slot_e[b], slot_i[b], slot_j[b], it - b * L, hist, bad);
     }
-    const int hbase = n2 + 2 * n3;
     for (int it = tid; it < nb * P; it += NT) {
-        const int b = it / P, p = it - b * P;
-        const int64_t e = slot_e[b];
-        const int32_t i = slot_i[b], j = slot_j[b];
-        const int64_t gid = a.batch ? (int64_t)a.ngraph[i] : 0;
-        const int ta = a.ntype[i], tb = a.ntype[j];
-        const uint64_t *Xi = xyk + (size_t)b * 4 * LL, *Xj = Xi + LL, *Y = Xi + 2 * LL,
-                       *K = Xi + 3 * LL;
-        const uint32_t *tri_e = a.tri + (size_t)e * L;
-        const uint32_t *di = a.tdeg + (size_t)i * L;
-        const uint32_t *dj = a.tdeg + (size_t)j * L;
-        const uint64_t *Ai = a.A + (size_t)i * LL, *Aj = a.A + (size_t)j * LL;
-        const uint64_t *Di = a.D + (size_t)i * LL, *Dj = a.D + (size_t)j * LL;
-        const uint64_t *NC = a.NC + (size_t)e * LL;
-        uint64_t *row = a.rows ? a.rows + (size_t)e * W : nullptr;
-        // pair (t, u), t <= u, from its lexicographic index
-        int t = 0, rem = p;
-        while (rem >= L - t) { rem -= L - t; ++t; }
-        const int u = t + rem;
-        const bool same = t == u;
-        const int r4 = rank4(ta, tb, t, u);
-        const int qa = t * L + u, qb = u * L + t;   // ordered (t,u) and (u,t)
-        const int64_t nTt = tri_e[t], nTu = tri_e[u];
-        const int64_t Sit = (int64_t)di[t] - nTt - (tb == t), Siu = (int64_t)di[u] - nTu - (tb == u);
-        const int64_t Sjt = (int64_t)dj[t] - nTt - (ta == t), Sju = (int64_t)dj[u] - nTu - (ta == u);
-        auto emit = [&](int o, int64_t v) {
-            if (v < 0) bad |= ST_INTERNAL;
-            if (row) row[2 * L + (o - 3) * P + p] = (uint64_t)v;
-            // graphlet of each orbit (Sec. 4.4): h3 = g3+g4, h4 = g5,
-            // h5 = g6, h6 = g7+g8+g9, h7 = g10+g11, h8 = g12
-            const int h = o <= 4 ? 3 : o == 5 ? 4 : o == 6 ? 5 : o <= 9 ? 6 : o <= 11 ? 7 : 8;
-            hist_add(a, hist, hbase + (h - 3) * n4 + r4, (uint64_t)v, gid);
-        };
-        // cliques and chordal cycles
-        const int64_t K0 = (int64_t)K[qa], K1 = (int64_t)K[qb];
-        if (same && (K0 & 1)) bad |= ST_INTERNAL;
-        if (!same && K0 != K1) bad |= ST_INTERNAL;
-        const int64_t g12 = same ? K0 / 2 : K0;
-        emit(12, g12);
-        emit(11, (same ? nTt * (nTt - 1) / 2 : nTt * nTu) - g12);                 // Lemma 4
-        const int64_t Xi0 = (int64_t)Xi[qa], Xi1 = (int64_t)Xi[qb];
-        const int64_t Xj0 = (int64_t)Xj[qa], Xj1 = (int64_t)Xj[qb];
-        // C_i(x,y): pairs k in T^x, r in S_i^y adjacent; likewise C_j
-        const int64_t Ci0 = Xi0 - nTt * (tb == u) - K0, Ci1 = Xi1 - nTu * (tb == t) - K1;
-        const int64_t Cj0 = Xj0 - nTt * (ta == u) - K0, Cj1 = Xj1 - nTu * (ta == t) - K1;
-        const int64_t g10 = same ? Ci0 + Cj0 : Ci0 + Cj0 + Ci1 + Cj1;
-        emit(10, g10);
-        emit(9, (same ? nTt * (Sit + Sjt) : nTt * (Siu + Sju) + nTu * (Sit + Sjt)) - g10);  // Lemma 3
-        // 4-cycles: non-induced cycles minus chordal and clique instances
-        const int64_t Cyc0 = (int64_t)NC[qa] - Ci1 - Cj0 - K0;
-        const int64_t Cyc1 = (int64_t)NC[qb] - Ci0 - Cj1 - K1;
-        const int64_t g6 = same ? Cyc0 : Cyc0 + Cyc1;
-        emit(6, g6);
-        emit(4, (same ? Sit * Sjt : Sit * Sju + Siu * Sjt) - g6);                 // Lemma 1
-        // tailed-triangle tails: adjacent pairs inside S_i (resp. S_j)
-        const int64_t sgi0 = (int64_t)Ai[qa] - Xi0 - (tb == t) * nTu;
-        const int64_t sgi1 = (int64_t)Ai[qb] - Xi1 - (tb == u) * nTt;
-        const int64_t sgj0 = (int64_t)Aj[qa] - Xj0 - (ta == t) * nTu;
-        const int64_t sgj1 = (int64_t)Aj[qb] - Xj1 - (ta == u) * nTt;
-        const int64_t Ei0 = sgi0 - Ci1, Ei1 = sgi1 - Ci0;
-        const int64_t Ej0 = sgj0 - Cj1, Ej1 = sgj1 - Cj0;
-        if (same && ((Ei0 + Ej0) & 1)) bad |= ST_INTERNAL;
-        if (!same && (Ei0 != Ei1 || Ej0 != Ej1)) bad |= ST_INTERNAL;
-        const int64_t g7 = same ? (Ei0 + Ej0) / 2 : Ei0 + Ej0;
-        emit(7, g7);
-        emit(5, (same ? Sit * (Sit - 1) / 2 + Sjt * (Sjt - 1) / 2 : Sit * Siu + Sjt * Sju) - g7);  // Lemma 2
-        // 4-path end edges: neighbours of S_i / S_j outside the edge's sets
-        const int64_t Y0 = (int64_t)Y[qa], Y1 = (int64_t)Y[qb];
-        const int64_t dli0 = (int64_t)Di[qa] - Y0 - (tb == t) * (int64_t)dj[u];
-        const int64_t dli1 = (int64_t)Di[qb] - Y1 - (tb == u) * (int64_t)dj[t];
-        const int64_t dlj0 = (int64_t)Dj[qa] - Y0 - (ta == t) * (int64_t)di[u];
-        const int64_t dlj1 = (int64_t)Dj[qb] - Y1 - (ta == u) * (int64_t)di[t];
-        const int64_t Pi0 = dli0 - Sit * (ta == u) - sgi0 - Cyc0;
-        const int64_t Pi1 = dli1 - Siu * (ta == t) - sgi1 - Cyc1;
-        const int64_t Pj0 = dlj0 - Sjt * (tb == u) - sgj0 - Cyc1;
-        const int64_t Pj1 = dlj1 - Sju * (tb == t) - sgj1 - Cyc0;
-        emit(3, same ? Pi0 + Pj0 : Pi0 + Pi1 + Pj0 + Pj1);
-        // tailed-triangle edges opposite the tail's node
-        const int64_t Q0 = Y0 - Xi0 - Cj0 - nTt * (ta == u);
-        const int64_t Q1 = Y1 - Xi1 - Cj1 - nTu * (ta == t);
-        emit(8, same ? Q0 : Q0 + Q1);
+        const int b = it / P;
+        derive_pair(a, slot_e[b], slot_i[b], slot_j[b], it - b * P, xyk + (size_t)b * 4 * LL, hist,
+                    bad);
     }
 }
 
@@ -645,6 +662,9 @@ __device__ __forceinline__ EdgeShared carve(const EdgeArgs &a, uint64_t *sm, uin
 }
 
 // Light edges: one wave per edge (|T| <= min degree <= TCAP, lists in LDS).
+// DEFER: the edge's Xi, Xj, Y, K go to a.xyk and k_derive does the rest, so
+// this kernel carries no derivation state (fewer registers, more waves).
+template <bool DEFER>
 __global__ void __launch_bounds__(64) k_edges_light(EdgeArgs a) {
     extern __shared__ uint64_t sm_edge[];
     __shared__ uint32_t meta[4];
@@ -686,6 +706,11 @@ __global__ void __launch_bounds__(64) k_edges_light(EdgeArgs a) {
         Sb.K = Sb.Xi + 3 * LL;
         edge_build<WAVE>(a, i, j, Sb, lane);
         edge_cliques<WAVE>(a, i, j, Sb, a.TM, F, lane);
+        if constexpr (DEFER) {
+            uint64_t *dst = a.xyk + (size_t)e * 4 * LL;
+            for (int q = lane; q < 4 * LL; q += WAVE) dst[q] = Sb.Xi[q];
+            return;
+        }
         if (lane == 0) {
             slot_e[nb] = e;
             slot_i[nb] = i;
@@ -694,6 +719,7 @@ __global__ void __launch_bounds__(64) k_edges_light(EdgeArgs a) {
         ++nb;
     };
     auto derive_all = [&]() {
+        if constexpr (DEFER) return;
         if (!nb) return;
         __syncthreads();
         edge_derive<WAVE>(a, nb, slot_e, slot_i, slot_j, S.Xi, hist, lane, bad);
@@ -790,18 +816,54 @@ __global__ void __launch_bounds__(EDGE_THREADS_HEAVY) k_edges_heavy(EdgeArgs a) 
         __threadfence_block();
         __syncthreads();
         edge_cliques<NT>(a, i, j, S, TMs, F, tid);
-        if (tid == 0) {
-            slot_e[0] = e;
-            slot_i[0] = i;
-            slot_j[0] = j;
+        if (a.xyk) {
+            uint64_t *dst = a.xyk + (size_t)e * 4 * LL;
+            for (int q = tid; q < 4 * LL; q += NT) dst[q] = S.Xi[q];
+        } else {
+            if (tid == 0) {
+                slot_e[0] = e;
+                slot_i[0] = i;
+                slot_j[0] = j;
+            }
+            __syncthreads();
+            edge_derive<NT>(a, 1, slot_e, slot_i, slot_j, S.Xi, hist, tid, bad);
         }
-        __syncthreads();
-        edge_derive<NT>(a, 1, slot_e, slot_i, slot_j, S.Xi, hist, tid, bad);
         __threadfence_block();
         __syncthreads();
     }
     if (a.hist_in_lds)
         for (int q = tid; q < a.gw; q += NT) {
+            uint64_t v = hist_take(a, hist, q);
+            if (v) atomicAdd((unsigned long long *)&a.gacc[q], (unsigned long long)v);
+        }
+    if (bad) atomicOr(a.status, bad);
+}
+
+// Deferred derivation: one thread per (edge, type pair) over the whole
+// edge set, reading each edge's Xi, Xj, Y, K from a.xyk; the 3-node entries
+// ride on the pairs p < L and the 2-node entry on p = 0.
+__global__ void __launch_bounds__(256) k_derive(EdgeArgs a) {
+    extern __shared__ uint64_t sm_der[];
+    uint64_t *hist = sm_der;
+    const int L = a.L;
+    const int LL = L * L;
+    const int P = L * (L + 1) / 2;
+    for (int q = threadIdx.x; q < hist_words(a); q += blockDim.x) hist[q] = 0;
+    __syncthreads();
+    uint32_t bad = 0;
+    const int64_t total = a.m * P;
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+         it += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = it / P;
+        const int p = (int)(it - e * P);
+        const int32_t i = a.ei[e], j = a.ej[e];
+        if (p == 0) hist_add(a, hist, rank2(a.ntype[i], a.ntype[j]), 1, 0);
+        if (p < L) derive_three(a, e, i, j, p, hist, bad);
+        derive_pair(a, e, i, j, p, a.xyk + (size_t)e * 4 * LL, hist, bad);
+    }
+    __syncthreads();
+    if (a.hist_in_lds)
+        for (int q = threadIdx.x; q < a.gw; q += blockDim.x) {
             uint64_t v = hist_take(a, hist, q);
             if (v) atomicAdd((unsigned long long *)&a.gacc[q], (unsigned long long)v);
         }
@@ -836,8 +898,16 @@ size_t edge_lds_bytes(const EdgeArgs &args, bool heavy) {
 hipError_t launch_edges(bool heavy, const EdgeArgs &args, unsigned grid, hipStream_t st) {
     if (grid == 0) return hipSuccess;
     size_t sh = edge_lds_bytes(args, heavy);
-    if (!heavy) k_edges_light<<<grid, 64, sh, st>>>(args);
-    else k_edges_heavy<<<grid, EDGE_THREADS_HEAVY, sh, st>>>(args);
+    if (heavy) k_edges_heavy<<<grid, EDGE_THREADS_HEAVY, sh, st>>>(args);
+    else if (args.xyk) k_edges_light<true><<<grid, 64, sh, st>>>(args);
+    else k_edges_light<false><<<grid, 64, sh, st>>>(args);
+    return hipGetLastError();
+}
+
+hipError_t launch_derive(const EdgeArgs &args, unsigned grid, hipStream_t st) {
+    if (grid == 0 || args.m == 0) return hipSuccess;
+    const int hw = args.hist_in_lds == 2 ? (args.gw + 1) / 2 : args.hist_in_lds ? args.gw : 0;
+    k_derive<<<grid, 256, (size_t)hw * sizeof(uint64_t), st>>>(args);
     return hipGetLastError();
 }
 

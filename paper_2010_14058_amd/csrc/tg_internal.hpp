@@ -49,6 +49,7 @@ struct Layout {
     int L;
     int heavy_slots;          // dense cycle maps (one per heavy workgroup)
     int heavy_edge_slots;     // global triangle buffers of the heavy edge kernel
+    bool defer;               // derivation in its own pass (off_xyk valid)
     size_t sort_tmp_bytes;
     size_t off_status, off_counters;
     size_t off_deg, off_ucount, off_eoff, off_order, off_newid, off_ntype, off_nrp, off_ndeg;
@@ -57,7 +58,7 @@ struct Layout {
     size_t off_tdeg, off_tri, off_tri_slot, off_A, off_D, off_NC;
     size_t off_listA_light, off_listA_heavy, off_listB_light, off_listB_heavy, off_list_edge;
     size_t off_maps, off_tbuf, off_gacc, off_sort_tmp;
-    size_t off_hstart, off_HB, off_hpre, off_TM, off_eslot, off_nlow;
+    size_t off_hstart, off_HB, off_hpre, off_TM, off_eslot, off_nlow, off_xyk;
     size_t off_node_graph, off_ngraph, off_gedge;   // batched graphs only
     size_t off_SB, off_SP;                          // super-hub bitmaps
     int sh_max;
@@ -126,6 +127,7 @@ struct EdgeArgs {
     int hist_in_lds;             // 0: global atomics, 1: uint64 LDS histogram, 2: uint32 LDS histogram
     int tcap;                    // triangle-list entries in LDS (light kernel)
     int derive_batch;            // edges whose derivation runs together (LDS slots of 4 L^2 words)
+    uint64_t *xyk;               // deferred derivation: Xi, Xj, Y, K per edge ([m][4 L^2]), or null
     uint32_t *heavy_list;
     uint64_t *counters;
     uint32_t *tbuf;      // heavy: per-workgroup low-member buffers of n entries
@@ -205,6 +207,7 @@ hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32
 int heavy_chunk_for(int L);
 hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned grid, hipStream_t st);
 hipError_t launch_edges(bool heavy, const EdgeArgs &args, unsigned grid, hipStream_t st);
+hipError_t launch_derive(const EdgeArgs &args, unsigned grid, hipStream_t st);
 hipError_t launch_global_finalize(const uint64_t *gacc, int L, int gw, uint64_t *out,
                                   uint32_t *status, hipStream_t st);
 
