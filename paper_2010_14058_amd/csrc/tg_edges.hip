@@ -417,34 +417,77 @@ __device__ void edge_cliques(const EdgeArgs &a, int32_t i, int32_t j, const Edge
                     const uint32_t oend = F.scan[o] < fe ? F.scan[o] : fe;
                     const uint32_t excl = o ? F.scan[o - 1] : 0;
                     const uint64_t *rowk = a.HB + (size_t)hk * Hw;
-                    uint32_t cnt[TG_MAX_L];
+                    if constexpr (NT == WAVE) {
+                        // one wave per edge: registers decide how many waves fit
+                        // two 16-bit tallies per register: a member's run covers at
+                        // most 16 blocks of 512 bits, so a tally stays below 2^13
+                        uint32_t cnt[TG_MAX_L / 2];
 #pragma unroll
-                    for (int t = 0; t < TG_MAX_L; ++t) cnt[t] = 0;
-                    for (; f < oend; ++f) {
-                        const uint32_t q = ((uint32_t)F.start[o] + (f - excl)) * 8;
-                        const ulonglong2 *rp = reinterpret_cast<const ulonglong2 *>(rowk + q);
-                        ulonglong2 r0 = rp[0], r1 = rp[1], r2 = rp[2], r3 = rp[3];
-                        uint64_t w[8] = {r0.x, r0.y, r1.x, r1.y, r2.x, r2.y, r3.x, r3.y};
+                        for (int t = 0; t < TG_MAX_L / 2; ++t) cnt[t] = 0;
+                        for (; f < oend; ++f) {
+                            const uint32_t q = ((uint32_t)F.start[o] + (f - excl)) * 8;
+                            const ulonglong2 *rp = reinterpret_cast<const ulonglong2 *>(rowk + q);
+#pragma unroll 1
+                            for (int half = 0; half < 2; ++half) {
+                                ulonglong2 r0 = rp[2 * half], r1 = rp[2 * half + 1];
+                                uint64_t w[4] = {r0.x, r0.y, r1.x, r1.y};
 #pragma unroll
-                        for (int bq = 0; bq < 8; ++bq) {
-                            const int word = (int)q + bq;
-                            uint64_t v = w[bq] & S.Tm[word];
-                            // keep members above k only
-                            if (word < (hk >> 6)) v = 0;
-                            else if (word == (hk >> 6))
-                                v &= (hk & 63) == 63 ? 0ull : (~0ull << ((hk & 63) + 1));
-                            if (!v) continue;
+                                for (int bq = 0; bq < 4; ++bq) {
+                                    const int word = (int)q + 4 * half + bq;
+                                    uint64_t v = w[bq] & S.Tm[word];
+                                    // keep members above k only
+                                    if (word < (hk >> 6)) v = 0;
+                                    else if (word == (hk >> 6))
+                                        v &= (hk & 63) == 63 ? 0ull : (~0ull << ((hk & 63) + 1));
+                                    if (!v) continue;
 #pragma unroll
-                            for (int t = 0; t < TG_MAX_L; ++t)
-                                if (t < L) cnt[t] += (uint32_t)__popcll(v & TMs[t * Hw + word]);
+                                    for (int t = 0; t < TG_MAX_L; ++t)
+                                        if (t < L)
+                                            cnt[t >> 1] += (uint32_t)__popcll(v & TMs[t * Hw + word])
+                                                           << (16 * (t & 1));
+                                }
+                            }
                         }
+#pragma unroll
+                        for (int t = 0; t < TG_MAX_L; ++t) {
+                            const uint32_t c = (cnt[t >> 1] >> (16 * (t & 1))) & 0xffffu;
+                            if (t < L && c) {
+                                unsigned long long *Kp = (unsigned long long *)S.K;
+                                atomicAdd(&Kp[tk * L + t], (unsigned long long)c);
+                                atomicAdd(&Kp[t * L + tk], (unsigned long long)c);
+                            }
+                        }
+                    } else {
+                        uint32_t cnt[TG_MAX_L];
+#pragma unroll
+                        for (int t = 0; t < TG_MAX_L; ++t) cnt[t] = 0;
+                        for (; f < oend; ++f) {
+                            const uint32_t q = ((uint32_t)F.start[o] + (f - excl)) * 8;
+                            const ulonglong2 *rp = reinterpret_cast<const ulonglong2 *>(rowk + q);
+                            ulonglong2 r0 = rp[0], r1 = rp[1], r2 = rp[2], r3 = rp[3];
+                            uint64_t w[8] = {r0.x, r0.y, r1.x, r1.y, r2.x, r2.y, r3.x, r3.y};
+#pragma unroll
+                            for (int bq = 0; bq < 8; ++bq) {
+                                const int word = (int)q + bq;
+                                uint64_t v = w[bq] & S.Tm[word];
+                                // keep members above k only
+                                if (word < (hk >> 6)) v = 0;
+                                else if (word == (hk >> 6))
+                                    v &= (hk & 63) == 63 ? 0ull : (~0ull << ((hk & 63) + 1));
+                                if (!v) continue;
+#pragma unroll
+                                for (int t = 0; t < TG_MAX_L; ++t)
+                                    if (t < L) cnt[t] += (uint32_t)__popcll(v & TMs[t * Hw + word]);
+                            }
+                        }
+#pragma unroll
+                        for (int t = 0; t < TG_MAX_L; ++t)
+                            if (t < L && cnt[t]) {
+                                unsigned long long *Kp = (unsigned long long *)S.K;
+                                atomicAdd(&Kp[tk * L + t], (unsigned long long)cnt[t]);
+                                atomicAdd(&Kp[t * L + tk], (unsigned long long)cnt[t]);
+                            }
                     }
-#pragma unroll
-                    for (int t = 0; t < TG_MAX_L; ++t)
-                        if (t < L && cnt[t]) {
-                            atomicAdd((unsigned long long *)&S.K[tk * L + t], (unsigned long long)cnt[t]);
-                            atomicAdd((unsigned long long *)&S.K[t * L + tk], (unsigned long long)cnt[t]);
-                        }
                     ++o;
                 }
                 group_sync<NT>();
