@@ -230,16 +230,30 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
         // waves append on their own, with no barrier per chunk
         const bool unordered = NT > WAVE && i >= a.sh_base && j >= a.sh_base;
         uint32_t count = 0;
+        // software pipeline over the chunks: candidate ids are loaded two
+        // chunks ahead and the other endpoint's bitmap words one chunk ahead,
+        // so the dependent loads of a chunk overlap the work of the previous
+        const uint64_t *sbrow = probe ? a.SB + (size_t)so * a.nw : nullptr;
+        const int64_t orow = a.nrp[other];
+        int32_t x1 = sb + tid < se ? a.ncol[sb + tid] : 0;
+        uint64_t w1 = probe && sb + tid < se ? sbrow[x1 >> 6] : 0ull;
+        int32_t x2 = sb + NT + tid < se ? a.ncol[sb + NT + tid] : 0;
         for (int64_t p0 = sb; p0 < se; p0 += NT) {
-            int64_t p = p0 + tid;
+            const int64_t p = p0 + tid;
+            const int32_t x = x1;
+            const uint64_t w = w1;
+            x1 = x2;
+            w1 = probe && p + NT < se ? sbrow[x1 >> 6] : 0ull;
+            x2 = p + 2 * NT < se ? a.ncol[p + 2 * NT] : 0;
             bool found = false;
             int64_t q = 0;
-            int32_t x = 0;
             if (p < se) {
-                x = a.ncol[p];
                 if (probe) {
-                    found = sh_bit(a.SB, a.nw, so, x);
-                    if (found) q = sh_slot(a.SB, a.SP, a.nw, a.nrp[other], so, x);
+                    found = (w >> (x & 63)) & 1ull;
+                    if (found) {
+                        const uint64_t below = (x & 63) ? (w & ((1ull << (x & 63)) - 1)) : 0ull;
+                        q = orow + a.SP[(size_t)so * a.nw + (x >> 6)] + (uint32_t)__popcll(below);
+                    }
                 } else {
                     q = lower_bound(a.ncol, lb, le, x);
                     found = q < le && a.ncol[q] == x;
