@@ -58,7 +58,7 @@ def host_threads() -> int:
 
 
 def algorithmic_bytes(g, L, stats, heavy_edge_info):
-    """Bytes each kernel must move with no cache reuse."""
+    """Bytes each kernel must move with no cache reuse, from this run's unit counts."""
     n, m, nnz = g.n, g.m, g.nnz
     d = g.degrees().astype(np.float64)
     sum_d2 = float(np.sum(d * d))
@@ -69,6 +69,8 @@ def algorithmic_bytes(g, L, stats, heavy_edge_info):
     hv_d, hv_t, hv_m = heavy_edge_info
     edge_fixed = 40 * L * L + 8 * W          # A_i, A_j, D_i, D_j, NC reads + row write
     per_t = 12 * L + 8                        # tri(i,k), tri(j,k), d_k^., slot ids
+    xyk = 32 * L * L                          # X_i, X_j, Y, K: written by the edge kernels,
+                                              # read by the derivation pass
     b = {
         "prep": 8 * (n + 1) + 4 * nnz + n + 8 * (n + 1) + 8 * nnz + 8 * m + 4 * n * L,
         "tri": 4 * sum_d2 + 4 * L * m,
@@ -78,8 +80,9 @@ def algorithmic_bytes(g, L, stats, heavy_edge_info):
         "cycA_heavy": stats["heavy_wedges_pass_a"] * per_wedge,
         "cycB_light": (stats["wedges_pass_b"] - stats["heavy_wedges_pass_b"]) * per_wedge,
         "cycB_heavy": stats["heavy_wedges_pass_b"] * per_wedge,
-        "edges_light": 4 * (sum_d2 - hv_d) + (m - hv_m) * edge_fixed + (tri_slots - hv_t) * per_t,
-        "edges_heavy": 4 * hv_d + hv_m * edge_fixed + hv_t * per_t,
+        "edges_light": 4 * (sum_d2 - hv_d) + (m - hv_m) * xyk + (tri_slots - hv_t) * per_t,
+        "edges_heavy": 4 * hv_d + hv_m * xyk + hv_t * per_t,
+        "derive": m * (edge_fixed + xyk),
     }
     return {k: float(v) for k, v in b.items()}
 

@@ -363,7 +363,7 @@ int tgo_edge_paper_g(const graph *g, int32_t i, int32_t j, uint64_t *row, uint8_
     return rc;
 }
 
-/* --------------------------------------------------------- public driver */
+/* --------------------------------------------------- public entry points */
 
 int tgo_edge_definition(int64_t n, const int64_t *row_ptr, const int32_t *col,
                         const uint8_t *types, int L, int32_t i, int32_t j, uint64_t *row) {
