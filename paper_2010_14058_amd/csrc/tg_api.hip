@@ -414,7 +414,11 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
         ea.hist_in_lds = 0;
         ea.derive_batch = 1;
     }
-    unsigned edge_grid = (unsigned)(cus > 0 ? cus * 24 : 2048);
+    // edge costs are very uneven: many small workgroups balance the light
+    // kernel far better than a few long grid-stride loops, except where each
+    // workgroup ends by flushing a whole global histogram (fused, one graph)
+    const int64_t per_cu = (xyk || batch) ? 2048 : 24;
+    unsigned edge_grid = (unsigned)((cus > 0 ? cus : 256) * per_cu);
     int64_t units = batch ? (m + BATCH_EDGE_CHUNK - 1) / BATCH_EDGE_CHUNK : m;
     if ((int64_t)edge_grid > units) edge_grid = (unsigned)(units > 0 ? units : 1);
     HIPCHK(launch_edges(false, ea, edge_grid, st));

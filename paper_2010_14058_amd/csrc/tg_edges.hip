@@ -722,7 +722,7 @@ __device__ __forceinline__ EdgeShared carve(const EdgeArgs &a, uint64_t *sm, uin
 // DEFER: the edge's Xi, Xj, Y, K go to a.xyk and k_derive does the rest, so
 // this kernel carries no derivation state (fewer registers, more waves).
 template <bool DEFER>
-__global__ void __launch_bounds__(64) k_edges_light(EdgeArgs a) {
+__device__ __forceinline__ void edges_light_body(const EdgeArgs &a) {
     extern __shared__ uint64_t sm_edge[];
     __shared__ uint32_t meta[4];
     __shared__ uint32_t wave_cnt[1];
@@ -830,6 +830,17 @@ __global__ void __launch_bounds__(64) k_edges_light(EdgeArgs a) {
     }
     bad = wave_or(bad);
     if (lane == 0 && bad) atomicOr(a.status, bad);
+}
+
+// The deferred variant holds no derivation state; a register budget for five
+// waves per SIMD keeps more edges in flight.
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5)))
+k_edges_light_deferred(EdgeArgs a) {
+    edges_light_body<true>(a);
+}
+
+__global__ void __launch_bounds__(64) k_edges_light_fused(EdgeArgs a) {
+    edges_light_body<false>(a);
 }
 
 // Heavy edges: one 256-thread workgroup per edge, pulled from a queue; the
@@ -956,8 +967,8 @@ hipError_t launch_edges(bool heavy, const EdgeArgs &args, unsigned grid, hipStre
     if (grid == 0) return hipSuccess;
     size_t sh = edge_lds_bytes(args, heavy);
     if (heavy) k_edges_heavy<<<grid, EDGE_THREADS_HEAVY, sh, st>>>(args);
-    else if (args.xyk) k_edges_light<true><<<grid, 64, sh, st>>>(args);
-    else k_edges_light<false><<<grid, 64, sh, st>>>(args);
+    else if (args.xyk) k_edges_light_deferred<<<grid, 64, sh, st>>>(args);
+    else k_edges_light_fused<<<grid, 64, sh, st>>>(args);
     return hipGetLastError();
 }
 
