@@ -359,7 +359,9 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     HIPCHK(hipGetDevice(&dev));
     int cus = 0;
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    unsigned light_grid = (unsigned)(cus > 0 ? cus * 16 : 1024);
+    // light groups differ in size up to 512 wedges: many small workgroups
+    // balance them (each clears its LDS map per group anyway)
+    unsigned light_grid = (unsigned)((cus > 0 ? cus : 256) * 1024);
     for (int pass = 0; pass < 2; ++pass) {
         ca.list = pass == 0 ? la_l : lb_l;
         ca.count_idx = pass == 0 ? C_A_LIGHT : C_B_LIGHT;
