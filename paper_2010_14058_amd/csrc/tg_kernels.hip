@@ -292,17 +292,21 @@ __global__ void k_tri(const int64_t *__restrict__ nrp, const int32_t *__restrict
         }
     }
     uint64_t tot = 0;
+    // every lane of the group ends with all totals; lane t % 8 stores type t,
+    // so a slot's row is written by neighbouring lanes at once
+    const int LP = tri_pitch(L);
+    const size_t si = e < m ? (size_t)eslot[2 * e] * LP : 0;
+    const size_t sj = e < m ? (size_t)eslot[2 * e + 1] * LP : 0;
 #pragma unroll
     for (int t = 0; t < TG_MAX_L; ++t) {
         if (t < L) {
             uint32_t v = cnt[t];
 #pragma unroll
             for (int d = 1; d < TRI_LANES; d <<= 1) v += __shfl_xor(v, d, WAVE);
-            if (gl == 0 && e < m) {
+            if ((t % TRI_LANES) == gl && e < m) {
                 tri[e * L + t] = v;
-                const int LP = tri_pitch(L);
-                tri_slot[(size_t)eslot[2 * e] * LP + t] = v;
-                tri_slot[(size_t)eslot[2 * e + 1] * LP + t] = v;
+                tri_slot[si + t] = v;
+                tri_slot[sj + t] = v;
             }
             tot += v;
         }
