@@ -264,13 +264,23 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     else HIPCHK(launch_fill_u64(gacc, 0, gw, st));
 
     // ---- input checks: batch descriptor, rows, degrees, edge numbering
+    uint64_t max_gsize = 0;
+    int deg_bits = 0;
+    bool graph_major = false;
     if (batch) {
         HIPCHK(launch_batch_graphs(batch->node_ptr, batch->gL, batch->goff, batch->G, n, L,
-                                   batch->globals_len, node_graph, status, st));
+                                   batch->globals_len, node_graph, status, counters + C_MAX_GSIZE,
+                                   st));
         uint32_t bst = 0;
         HIPCHK(hipMemcpyAsync(&bst, status, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(&max_gsize, counters + C_MAX_GSIZE, sizeof(uint64_t),
+                              hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (bst) return status_from_bits(bst);
+        // graph-major order when (graph, degree) fit the key's upper 32 bits;
+        // degrees are below the largest graph's size
+        deg_bits = bits_for((int64_t)max_gsize + 1);
+        graph_major = bits_for(batch->G + 1) + deg_bits <= 32;
     }
     HIPCHK(launch_check_rows(row_ptr, col, types, n, nnz, L, deg, ucount, status, node_graph,
                              batch ? batch->gL : nullptr, st));
@@ -288,8 +298,9 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     if (probe.upper != m) return TG_E_NOT_SIMPLE;
     if (batch) HIPCHK(launch_batch_edges(batch->node_ptr, eoff, batch->G, gedge, st));
 
-    // ---- relabel by (degree, id): rank order = internal id order
-    HIPCHK(launch_node_keys(deg, n, key_a, st));
+    // ---- relabel by (degree, id), or (graph, degree, id) for a batch:
+    //      rank order = internal id order
+    HIPCHK(launch_node_keys(deg, n, graph_major ? node_graph : nullptr, deg_bits, key_a, st));
     HIPCHK(rocprim::radix_sort_keys(stmp, stmp_bytes, key_a, key_b, (size_t)n, 0, 64, st));
     HIPCHK(launch_relabel(key_b, types, deg, n, order, newid, ntype, ndeg, counters + C_HUB_CAND,
                           node_graph, ngraph, st));
@@ -302,13 +313,15 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     uint64_t cand[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(cand, counters + C_HUB_CAND, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost,
                           st));
-    int64_t max_deg = 0;  // the top-ranked node has the largest degree
-    if (n > 0)
+    int64_t max_deg = 0;  // in degree order the top-ranked node has the largest degree
+    if (n > 0 && !graph_major)
         HIPCHK(hipMemcpyAsync(&max_deg, ndeg + (n - 1), sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (probe.status) return status_from_bits(probe.status);
+    if (graph_major) max_deg = max_gsize > 0 ? (int64_t)max_gsize - 1 : 0;  // a bound
     // hub core: the highest-ranked nodes of degree >= HUB_DMIN, at most HUB_MAX
-    const uint64_t hub_cand = cand[0], sh_cand = cand[1];
+    // (none in graph-major order, where the top ids are not the top degrees)
+    const uint64_t hub_cand = graph_major ? 0 : cand[0], sh_cand = graph_major ? 0 : cand[1];
     const int H = (int)(hub_cand < (uint64_t)HUB_MAX ? hub_cand : (uint64_t)HUB_MAX);
     // super-hubs: the highest-ranked nodes of degree >= SH_DMIN that fit
     const int S = (int)(sh_cand < (uint64_t)y.sh_max ? sh_cand : (uint64_t)y.sh_max);

@@ -71,7 +71,7 @@ enum Counter {
     C_A_LIGHT = 0, C_A_HEAVY, C_B_LIGHT, C_B_HEAVY, C_EDGE_HEAVY,
     C_A_NEXT, C_B_NEXT, C_EDGE_NEXT, C_WEDGES_A, C_WEDGES_B,
     C_WEDGES_A_HEAVY, C_WEDGES_B_HEAVY, C_TRI_SUM, C_HUB_CAND, C_SH_CAND,
-    C_TASK_EXTRA, C_HEAVY_GROUPS,
+    C_TASK_EXTRA, C_HEAVY_GROUPS, C_MAX_GSIZE,
     C_NUM
 };
 
@@ -163,12 +163,14 @@ hipError_t launch_check_rows(const int64_t *rp, const int32_t *col, const uint8_
                              const int32_t *node_graph, const int32_t *gL, hipStream_t st);
 hipError_t launch_batch_graphs(const int64_t *node_ptr, const int32_t *gL, const int64_t *goff,
                                int64_t G, int64_t n, int L_max, int64_t globals_len,
-                               int32_t *node_graph, uint32_t *status, hipStream_t st);
+                               int32_t *node_graph, uint32_t *status, uint64_t *max_gsize,
+                               hipStream_t st);
 hipError_t launch_batch_edges(const int64_t *node_ptr, const int64_t *eoff, int64_t G,
                               int64_t *gedge_ptr, hipStream_t st);
 hipError_t launch_batch_finalize(uint64_t *globals, const int32_t *gL, const int64_t *goff, int64_t G,
                                  uint32_t *status, hipStream_t st);
-hipError_t launch_node_keys(const uint32_t *deg, int64_t n, uint64_t *keys, hipStream_t st);
+hipError_t launch_node_keys(const uint32_t *deg, int64_t n, const int32_t *node_graph, int deg_bits,
+                            uint64_t *keys, hipStream_t st);
 hipError_t launch_relabel(const uint64_t *sorted, const uint8_t *types, const uint32_t *deg, int64_t n,
                           int32_t *order, int32_t *newid, uint8_t *ntype, int64_t *ndeg,
                           uint64_t *hub_cand, const int32_t *node_graph, int32_t *ngraph,

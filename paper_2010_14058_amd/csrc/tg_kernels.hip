@@ -79,7 +79,7 @@ __global__ void k_check_rows(const int64_t *__restrict__ rp, const int32_t *__re
 __global__ void k_batch_graphs(const int64_t *__restrict__ node_ptr, const int32_t *__restrict__ gL,
                                const int64_t *__restrict__ goff, int64_t G, int64_t n, int L_max,
                                int64_t globals_len, int32_t *__restrict__ node_graph,
-                               uint32_t *__restrict__ status) {
+                               uint32_t *__restrict__ status, uint64_t *__restrict__ max_gsize) {
     int64_t g = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
     int lane = lane_id();
     if (g >= G) return;
@@ -97,6 +97,7 @@ __global__ void k_batch_graphs(const int64_t *__restrict__ node_ptr, const int32
         return;
     }
     for (int64_t v = a + lane; v < b; v += WAVE) node_graph[v] = (int32_t)g;
+    if (lane == 0 && b > a) atomicMax((unsigned long long *)max_gsize, (unsigned long long)(b - a));
 }
 
 __global__ void k_batch_edges(const int64_t *__restrict__ node_ptr, const int64_t *__restrict__ eoff,
@@ -129,9 +130,18 @@ __global__ void k_batch_finalize(uint64_t *__restrict__ glob, const int32_t *__r
 }
 
 // keys[v] = degree << 32 | v (rank order = sorted order)
-__global__ void k_node_keys(const uint32_t *__restrict__ deg, int64_t n, uint64_t *__restrict__ keys) {
+// Sort keys of the relabelling: (degree, id), or for a batch whose sizes fit,
+// (graph, degree, id) so each graph's nodes stay contiguous (graphlets never
+// span graphs, so a per-graph degree order serves the cycle orientation as
+// well) and the id in the low 32 bits.
+__global__ void k_node_keys(const uint32_t *__restrict__ deg, int64_t n,
+                            const int32_t *__restrict__ node_graph, int deg_bits,
+                            uint64_t *__restrict__ keys) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n) keys[v] = ((uint64_t)deg[v] << 32) | (uint64_t)v;
+    if (v >= n) return;
+    uint64_t k = ((uint64_t)deg[v] << 32) | (uint64_t)v;
+    if (node_graph) k |= (uint64_t)node_graph[v] << (32 + deg_bits);
+    keys[v] = k;
 }
 
 __global__ void k_relabel(const uint64_t *__restrict__ sorted, const uint8_t *__restrict__ types,
@@ -955,8 +965,9 @@ hipError_t launch_check_rows(const int64_t *rp, const int32_t *col, const uint8_
     return hipSuccess;
 }
 
-hipError_t launch_node_keys(const uint32_t *deg, int64_t n, uint64_t *keys, hipStream_t st) {
-    k_node_keys<<<blocks_for(n, 256), 256, 0, st>>>(deg, n, keys);
+hipError_t launch_node_keys(const uint32_t *deg, int64_t n, const int32_t *node_graph, int deg_bits,
+                            uint64_t *keys, hipStream_t st) {
+    k_node_keys<<<blocks_for(n, 256), 256, 0, st>>>(deg, n, node_graph, deg_bits, keys);
     LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1070,10 +1081,11 @@ hipError_t launch_global_finalize(const uint64_t *gacc, int L, int gw, uint64_t 
 
 hipError_t launch_batch_graphs(const int64_t *node_ptr, const int32_t *gL, const int64_t *goff,
                                int64_t G, int64_t n, int L_max, int64_t globals_len,
-                               int32_t *node_graph, uint32_t *status, hipStream_t st) {
+                               int32_t *node_graph, uint32_t *status, uint64_t *max_gsize,
+                               hipStream_t st) {
     if (G <= 0) return hipSuccess;
     k_batch_graphs<<<blocks_for(G, 4), 256, 0, st>>>(node_ptr, gL, goff, G, n, L_max, globals_len,
-                                                     node_graph, status);
+                                                     node_graph, status, max_gsize);
     LAUNCH_CHECK();
     return hipSuccess;
 }
