@@ -233,23 +233,25 @@ __global__ void k_tdeg(const int64_t *__restrict__ nrp, const int32_t *__restric
                        const uint8_t *__restrict__ ntype, int64_t n, int L, int32_t hub_base,
                        uint32_t *__restrict__ tdeg, int64_t *__restrict__ hstart,
                        uint32_t *__restrict__ nlow) {
-    int64_t v = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
-    int lane = lane_id();
-    if (v >= n) return;
-    if (lane == 0) {
-        hstart[v] = lower_bound(ncol, nrp[v], nrp[v + 1], hub_base);
-        nlow[v] = (uint32_t)(lower_bound(ncol, nrp[v], nrp[v + 1], (int32_t)v) - nrp[v]);
-    }
-    uint32_t c = 0;
-    for (int64_t base = nrp[v]; base < nrp[v + 1]; base += WAVE) {
-        int64_t s = base + lane;
-        int t = s < nrp[v + 1] ? (int)ntype[ncol[s]] : -1;
-        for (int tt = 0; tt < L; ++tt) {
-            uint64_t bal = __ballot(t == tt);
-            if (lane == tt) c += (uint32_t)__popcll(bal);
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE); v < n;
+         v += nwaves) {
+        if (lane == 0) {
+            hstart[v] = lower_bound(ncol, nrp[v], nrp[v + 1], hub_base);
+            nlow[v] = (uint32_t)(lower_bound(ncol, nrp[v], nrp[v + 1], (int32_t)v) - nrp[v]);
         }
+        uint32_t c = 0;
+        for (int64_t base = nrp[v]; base < nrp[v + 1]; base += WAVE) {
+            int64_t s = base + lane;
+            int t = s < nrp[v + 1] ? (int)ntype[ncol[s]] : -1;
+            for (int tt = 0; tt < L; ++tt) {
+                uint64_t bal = __ballot(t == tt);
+                if (lane == tt) c += (uint32_t)__popcll(bal);
+            }
+        }
+        if (lane < L) tdeg[v * L + lane] = c;
     }
-    if (lane < L) tdeg[v * L + lane] = c;
 }
 
 // ------------------------------------------------------- typed triangles
@@ -267,64 +269,70 @@ __global__ void k_tri(const int64_t *__restrict__ nrp, const int32_t *__restrict
                       uint32_t *__restrict__ tri_slot, int64_t m, int L,
                       uint32_t *__restrict__ tri, uint64_t *__restrict__ tri_sum, int32_t sh_base,
                       int64_t nw, const uint64_t *__restrict__ SB) {
-    int64_t wave = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
-    int lane = lane_id();
-    int grp = lane / TRI_LANES, gl = lane % TRI_LANES;
-    int64_t e = wave * TRI_GROUPS + grp;
-    uint32_t cnt[TG_MAX_L];
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    const int lane = lane_id();
+    const int grp = lane / TRI_LANES, gl = lane % TRI_LANES;
+    uint64_t tot_all = 0;
+    // a bounded grid walks the edges: per-edge work is small, so launching
+    // one workgroup per 32 edges would leave the dispatcher as the limit
+    for (int64_t wv = wave; wv * TRI_GROUPS < m; wv += nwaves) {
+        const int64_t e = wv * TRI_GROUPS + grp;
+        uint32_t cnt[TG_MAX_L];
 #pragma unroll
-    for (int t = 0; t < TG_MAX_L; ++t) cnt[t] = 0;
-    if (e < m) {
-        int32_t i = ei[e], j = ej[e];
-        int64_t sb = nrp[i], se = nrp[i + 1], bb = nrp[j], be = nrp[j + 1];
-        int32_t big = j;
-        if (se - sb > be - bb) {
-            int64_t t0 = sb, t1 = se;
-            sb = bb; se = be; bb = t0; be = t1;
-            big = i;
-        }
-        const bool probe = big >= sh_base;
-        const int sidx = big - sh_base;
-        for (int64_t s = sb + gl; s < se; s += TRI_LANES) {
-            int32_t x = ncol[s];
-            bool found;
-            if (probe) {
-                found = sh_bit(SB, nw, sidx, x);
-            } else {
-                int64_t q = lower_bound(ncol, bb, be, x);
-                found = q < be && ncol[q] == x;
+        for (int t = 0; t < TG_MAX_L; ++t) cnt[t] = 0;
+        if (e < m) {
+            int32_t i = ei[e], j = ej[e];
+            int64_t sb = nrp[i], se = nrp[i + 1], bb = nrp[j], be = nrp[j + 1];
+            int32_t big = j;
+            if (se - sb > be - bb) {
+                int64_t t0 = sb, t1 = se;
+                sb = bb; se = be; bb = t0; be = t1;
+                big = i;
             }
-            if (found) {
-                int tx = ntype[x];
+            const bool probe = big >= sh_base;
+            const int sidx = big - sh_base;
+            for (int64_t s = sb + gl; s < se; s += TRI_LANES) {
+                int32_t x = ncol[s];
+                bool found;
+                if (probe) {
+                    found = sh_bit(SB, nw, sidx, x);
+                } else {
+                    int64_t q = lower_bound(ncol, bb, be, x);
+                    found = q < be && ncol[q] == x;
+                }
+                if (found) {
+                    int tx = ntype[x];
 #pragma unroll
-                for (int t = 0; t < TG_MAX_L; ++t) cnt[t] += (t == tx);
+                    for (int t = 0; t < TG_MAX_L; ++t) cnt[t] += (t == tx);
+                }
             }
         }
+        uint64_t tot = 0;
+        // every lane of the group ends with all totals; lane t % 8 stores type t,
+        // so a slot's row is written by neighbouring lanes at once
+        const int LP = tri_pitch(L);
+        const size_t si = e < m ? (size_t)eslot[2 * e] * LP : 0;
+        const size_t sj = e < m ? (size_t)eslot[2 * e + 1] * LP : 0;
+#pragma unroll
+        for (int t = 0; t < TG_MAX_L; ++t) {
+            if (t < L) {
+                uint32_t v = cnt[t];
+#pragma unroll
+                for (int d = 1; d < TRI_LANES; d <<= 1) v += __shfl_xor(v, d, WAVE);
+                if ((t % TRI_LANES) == gl && e < m) {
+                    tri[e * L + t] = v;
+                    tri_slot[si + t] = v;
+                    tri_slot[sj + t] = v;
+                }
+                tot += v;
+            }
+        }
+        // one count per group (lanes of a group hold the same totals)
+        tot_all += gl == 0 ? tot : 0ull;
     }
-    uint64_t tot = 0;
-    // every lane of the group ends with all totals; lane t % 8 stores type t,
-    // so a slot's row is written by neighbouring lanes at once
-    const int LP = tri_pitch(L);
-    const size_t si = e < m ? (size_t)eslot[2 * e] * LP : 0;
-    const size_t sj = e < m ? (size_t)eslot[2 * e + 1] * LP : 0;
-#pragma unroll
-    for (int t = 0; t < TG_MAX_L; ++t) {
-        if (t < L) {
-            uint32_t v = cnt[t];
-#pragma unroll
-            for (int d = 1; d < TRI_LANES; d <<= 1) v += __shfl_xor(v, d, WAVE);
-            if ((t % TRI_LANES) == gl && e < m) {
-                tri[e * L + t] = v;
-                tri_slot[si + t] = v;
-                tri_slot[sj + t] = v;
-            }
-            tot += v;
-        }
-    }
-    // one count per group (lanes of a group hold the same totals)
-    tot = gl == 0 ? tot : 0ull;
-    tot = wave_sum_u64(tot);
-    if (lane == 0 && tot) atomicAdd((unsigned long long *)tri_sum, (unsigned long long)tot);
+    tot_all = wave_sum_u64(tot_all);
+    if (lane == 0 && tot_all) atomicAdd((unsigned long long *)tri_sum, (unsigned long long)tot_all);
 }
 
 // One workgroup per super-hub: bitmap of its neighbours over all nodes and
@@ -387,25 +395,27 @@ __global__ void k_node_aggr(const int64_t *__restrict__ nrp, const int32_t *__re
     int LL = L * L;
     uint64_t *sA = sm_aggr + (size_t)w * 2 * LL;
     uint64_t *sD = sA + LL;
-    int64_t u = (int64_t)blockIdx.x * (blockDim.x / WAVE) + w;
-    if (u >= n) return;
-    for (int q = lane; q < LL; q += WAVE) { sA[q] = 0; sD[q] = 0; }
-    wave_sync();
-    for (int64_t s = nrp[u] + lane; s < nrp[u + 1]; s += WAVE) {
-        int32_t k = ncol[s];
-        int t = ntype[k];
-        const uint32_t *ts = tri_slot + (size_t)s * tri_pitch(L);
-        for (int t2 = 0; t2 < L; ++t2) {
-            uint32_t a = ts[t2];
-            uint32_t d = tdeg[(size_t)k * L + t2];
-            if (a) atomicAdd((unsigned long long *)&sA[t * L + t2], (unsigned long long)a);
-            if (d) atomicAdd((unsigned long long *)&sD[t * L + t2], (unsigned long long)d);
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / WAVE) + w; u < n; u += nwaves) {
+        for (int q = lane; q < LL; q += WAVE) { sA[q] = 0; sD[q] = 0; }
+        wave_sync();
+        for (int64_t s = nrp[u] + lane; s < nrp[u + 1]; s += WAVE) {
+            int32_t k = ncol[s];
+            int t = ntype[k];
+            const uint32_t *ts = tri_slot + (size_t)s * tri_pitch(L);
+            for (int t2 = 0; t2 < L; ++t2) {
+                uint32_t a = ts[t2];
+                uint32_t d = tdeg[(size_t)k * L + t2];
+                if (a) atomicAdd((unsigned long long *)&sA[t * L + t2], (unsigned long long)a);
+                if (d) atomicAdd((unsigned long long *)&sD[t * L + t2], (unsigned long long)d);
+            }
         }
-    }
-    wave_sync();
-    for (int q = lane; q < LL; q += WAVE) {
-        A[(size_t)u * LL + q] = sA[q];
-        D[(size_t)u * LL + q] = sD[q];
+        wave_sync();
+        for (int q = lane; q < LL; q += WAVE) {
+            A[(size_t)u * LL + q] = sA[q];
+            D[(size_t)u * LL + q] = sD[q];
+        }
+        wave_sync();
     }
 }
 
@@ -947,6 +957,19 @@ static inline unsigned blocks_for(int64_t items, int per_block) {
     return (unsigned)((items + per_block - 1) / per_block);
 }
 
+// Blocks for a grid-stride kernel: enough to fill the device, no more (per
+// item work that is small leaves the workgroup dispatcher as the limit
+// when every few items get a workgroup of their own).
+static inline unsigned blocks_bounded(int64_t items, int per_block, int per_cu) {
+    unsigned b = blocks_for(items, per_block);
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        cus > 0 && b > (unsigned)cus * per_cu)
+        b = (unsigned)cus * per_cu;
+    return b > 0 ? b : 1;
+}
+
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     int64_t b = (count + 255) / 256;
@@ -1004,7 +1027,8 @@ hipError_t launch_finish_csr(const uint64_t *keys, const uint32_t *vals, int64_t
 hipError_t launch_tdeg(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype, int64_t n,
                        int L, int32_t hub_base, uint32_t *tdeg, int64_t *hstart, uint32_t *nlow,
                        hipStream_t st) {
-    k_tdeg<<<blocks_for(n, 4), 256, 0, st>>>(nrp, ncol, ntype, n, L, hub_base, tdeg, hstart, nlow);
+    k_tdeg<<<blocks_bounded(n, 4, 32), 256, 0, st>>>(nrp, ncol, ntype, n, L, hub_base, tdeg,
+                                                     hstart, nlow);
     LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1015,8 +1039,8 @@ hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *nt
                       uint64_t *tri_sum, int32_t sh_base, int64_t nw, const uint64_t *SB,
                       hipStream_t st) {
     if (m == 0) return hipSuccess;
-    k_tri<<<blocks_for(m, 4 * TRI_GROUPS), 256, 0, st>>>(nrp, ncol, ntype, ei, ej, eslot, tri_slot, m, L, tri,
-                                                         tri_sum, sh_base, nw, SB);
+    k_tri<<<blocks_bounded(m, 4 * TRI_GROUPS, 32), 256, 0, st>>>(
+        nrp, ncol, ntype, ei, ej, eslot, tri_slot, m, L, tri, tri_sum, sh_base, nw, SB);
     LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1025,7 +1049,8 @@ hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8
                             const uint32_t *tri_slot, const uint32_t *tdeg,
                             int64_t n, int L, uint64_t *A, uint64_t *D, hipStream_t st) {
     size_t sh = (size_t)4 * 2 * L * L * sizeof(uint64_t);
-    k_node_aggr<<<blocks_for(n, 4), 256, sh, st>>>(nrp, ncol, ntype, tri_slot, tdeg, n, L, A, D);
+    k_node_aggr<<<blocks_bounded(n, 4, 32), 256, sh, st>>>(nrp, ncol, ntype, tri_slot, tdeg, n, L,
+                                                           A, D);
     LAUNCH_CHECK();
     return hipSuccess;
 }
