@@ -31,19 +31,18 @@ __global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t count) {
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += stride) p[q] = v;
 }
 
-// One wave per input row: row checks, degree, number of larger neighbours.
+// One wave per input row (grid-stride): row checks, degree, number of larger
+// neighbours.
 __global__ void k_check_rows(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
                              const uint8_t *__restrict__ types, int64_t n, int64_t nnz, int L,
                              uint32_t *__restrict__ deg, int64_t *__restrict__ ucount,
                              uint32_t *__restrict__ status, const int32_t *__restrict__ node_graph,
                              const int32_t *__restrict__ gL) {
-    int64_t u = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
-    int lane = lane_id();
-    if (u > n) return;
-    if (u == n) {  // sentinel of the exclusive scan
-        if (lane == 0) ucount[n] = 0;
-        return;
-    }
+    const int lane = lane_id();
+    if (blockIdx.x == 0 && threadIdx.x == 0) ucount[n] = 0;  // sentinel of the exclusive scan
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE); u < n;
+         u += nwaves) {
     int64_t b = rp[u], e = rp[u + 1];
     uint32_t bad = 0;
     if (b < 0 || e > nnz || e < b || (u == 0 && b != 0) || (u == n - 1 && e != nnz)) {
@@ -52,7 +51,7 @@ __global__ void k_check_rows(const int64_t *__restrict__ rp, const int32_t *__re
             deg[u] = 0;
             ucount[u] = 0;
         }
-        return;
+        continue;
     }
     uint64_t up = 0;
     const int32_t gu = node_graph ? node_graph[u] : 0;
@@ -71,6 +70,7 @@ __global__ void k_check_rows(const int64_t *__restrict__ rp, const int32_t *__re
         deg[u] = (uint32_t)(e - b);
         ucount[u] = (int64_t)up;
         if (bad) atomicOr(status, bad);
+    }
     }
 }
 
@@ -170,7 +170,7 @@ __global__ void k_relabel(const uint64_t *__restrict__ sorted, const uint8_t *__
         atomicAdd((unsigned long long *)(hub_cand + 1), (unsigned long long)__popcll(sbal));
 }
 
-// One wave per input row: canonical edge id of every slot, the relabelled
+// One wave per input row (grid-stride): canonical edge id of every slot, the relabelled
 // slot key (row << bits | col), and the canonical endpoints of each edge.
 __global__ void k_slot_keys(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
                             const int64_t *__restrict__ ucount, const int64_t *__restrict__ eoff,
@@ -178,9 +178,10 @@ __global__ void k_slot_keys(const int64_t *__restrict__ rp, const int32_t *__res
                             uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
                             int32_t *__restrict__ ei, int32_t *__restrict__ ej,
                             uint32_t *__restrict__ status) {
-    int64_t u = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
-    int lane = lane_id();
-    if (u >= n) return;
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE); u < n;
+         u += nwaves) {
     int64_t b = rp[u], e = rp[u + 1];
     int64_t ustart = e - ucount[u];
     uint32_t bad = 0;
@@ -207,6 +208,7 @@ __global__ void k_slot_keys(const int64_t *__restrict__ rp, const int32_t *__res
     }
     bad = wave_or(bad);
     if (lane == 0 && bad) atomicOr(status, bad);
+    }
 }
 
 // Sorted keys (row << bits | column) to the relabelled CSR, plus the slot of
@@ -982,7 +984,7 @@ hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s
 hipError_t launch_check_rows(const int64_t *rp, const int32_t *col, const uint8_t *types, int64_t n,
                              int64_t nnz, int L, uint32_t *deg, int64_t *ucount, uint32_t *status,
                              const int32_t *node_graph, const int32_t *gL, hipStream_t st) {
-    k_check_rows<<<blocks_for(n + 1, 4), 256, 0, st>>>(rp, col, types, n, nnz, L, deg, ucount, status,
+    k_check_rows<<<blocks_bounded(n > 0 ? n : 1, 4, 32), 256, 0, st>>>(rp, col, types, n, nnz, L, deg, ucount, status,
                                                        node_graph, gL);
     LAUNCH_CHECK();
     return hipSuccess;
@@ -1010,7 +1012,7 @@ hipError_t launch_slot_keys(const int64_t *rp, const int32_t *col, const int64_t
                             const int64_t *eoff, const int32_t *newid, int64_t n, int bits,
                             uint64_t *keys, uint32_t *vals, int32_t *ei, int32_t *ej,
                             uint32_t *status, hipStream_t st) {
-    k_slot_keys<<<blocks_for(n, 4), 256, 0, st>>>(rp, col, ucount, eoff, newid, n, bits, keys, vals,
+    k_slot_keys<<<blocks_bounded(n, 4, 32), 256, 0, st>>>(rp, col, ucount, eoff, newid, n, bits, keys, vals,
                                                   ei, ej, status);
     LAUNCH_CHECK();
     return hipSuccess;

@@ -12,48 +12,62 @@
 namespace tg {
 namespace {
 
-// One wave per edge row: number of nonzero entries.
+// One wave per edge row (grid-stride): number of nonzero entries.
 __global__ void __launch_bounds__(256) k_row_nnz(const uint64_t *__restrict__ rows, int64_t m, int W,
                                                  int64_t *__restrict__ cnt) {
-    const int64_t e = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     const int lane = lane_id();
-    if (e > m) return;
-    if (e == m) {  // the scan's last element: offsets[m] becomes the total
-        if (lane == 0) cnt[m] = 0;
-        return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) cnt[m] = 0;  // the scan's last element: the total
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t e = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; e < m;
+         e += nwaves) {
+        const uint64_t *row = rows + (size_t)e * W;
+        int64_t c = 0;
+        for (int q0 = 0; q0 < W; q0 += WAVE) {
+            const int q = q0 + lane;
+            const bool nz = q < W && row[q] != 0ull;
+            c += __popcll(__ballot(nz));
+        }
+        if (lane == 0) cnt[e] = c;
     }
-    const uint64_t *row = rows + (size_t)e * W;
-    int64_t c = 0;
-    for (int q0 = 0; q0 < W; q0 += WAVE) {
-        const int q = q0 + lane;
-        const bool nz = q < W && row[q] != 0ull;
-        c += __popcll(__ballot(nz));
-    }
-    if (lane == 0) cnt[e] = c;
 }
 
-// One wave per edge row: its nonzero entries at the edge's offset.
+// One wave per edge row (grid-stride): its nonzero entries at the edge's
+// offset.
 __global__ void __launch_bounds__(256) k_row_fill(const uint64_t *__restrict__ rows, int64_t m, int W,
                                                   const int64_t *__restrict__ off,
                                                   uint16_t *__restrict__ keys,
                                                   uint64_t *__restrict__ counts) {
-    const int64_t e = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     const int lane = lane_id();
-    if (e >= m) return;
-    const uint64_t *row = rows + (size_t)e * W;
     const uint64_t below = (1ull << lane) - 1ull;
-    int64_t pos = off[e];
-    for (int q0 = 0; q0 < W; q0 += WAVE) {
-        const int q = q0 + lane;
-        const uint64_t v = q < W ? row[q] : 0ull;
-        const uint64_t bal = __ballot(v != 0ull);
-        if (v) {
-            const int64_t at = pos + __popcll(bal & below);
-            keys[at] = (uint16_t)q;
-            counts[at] = v;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t e = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; e < m;
+         e += nwaves) {
+        const uint64_t *row = rows + (size_t)e * W;
+        int64_t pos = off[e];
+        for (int q0 = 0; q0 < W; q0 += WAVE) {
+            const int q = q0 + lane;
+            const uint64_t v = q < W ? row[q] : 0ull;
+            const uint64_t bal = __ballot(v != 0ull);
+            if (v) {
+                const int64_t at = pos + __popcll(bal & below);
+                keys[at] = (uint16_t)q;
+                counts[at] = v;
+            }
+            pos += __popcll(bal);
         }
-        pos += __popcll(bal);
     }
+}
+
+// Workgroups for a grid-stride launch over `waves` rows, four waves a
+// workgroup: enough to fill the device, no more.
+unsigned row_blocks(int64_t waves) {
+    int64_t b = (waves + 3) / 4;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        cus > 0 && b > (int64_t)cus * 32)
+        b = (int64_t)cus * 32;
+    return b > 0 ? (unsigned)b : 1u;
 }
 
 size_t scan_tmp_bytes(int64_t m) {
@@ -90,8 +104,7 @@ tg_status tg_sparse_offsets(const uint64_t *rows, int64_t m, int32_t L, int64_t 
     const size_t cnt_bytes = ((size_t)(m + 1) * sizeof(int64_t) + 255) / 256 * 256;
     void *tmp = static_cast<char *>(workspace) + cnt_bytes;
     size_t tmp_bytes = ws_bytes - cnt_bytes;
-    const unsigned blocks = (unsigned)((m + 1 + 3) / 4);
-    k_row_nnz<<<blocks, 256, 0, st>>>(rows, m, W, cnt);
+    k_row_nnz<<<row_blocks(m), 256, 0, st>>>(rows, m, W, cnt);
     if (hipGetLastError() != hipSuccess) return TG_E_DEVICE;
     if (rocprim::exclusive_scan(tmp, tmp_bytes, cnt, edge_off, int64_t(0), (size_t)(m + 1),
                                 rocprim::plus<int64_t>(), st) != hipSuccess)
@@ -107,7 +120,7 @@ tg_status tg_sparse_fill(const uint64_t *rows, int64_t m, int32_t L, const int64
     if (m == 0) return TG_OK;
     hipStream_t st = (hipStream_t)stream;
     const int W = tg_row_width(L);
-    k_row_fill<<<(unsigned)((m + 3) / 4), 256, 0, st>>>(rows, m, W, edge_off, keys, counts);
+    k_row_fill<<<row_blocks(m), 256, 0, st>>>(rows, m, W, edge_off, keys, counts);
     if (hipGetLastError() != hipSuccess) return TG_E_DEVICE;
     return hipStreamSynchronize(st) == hipSuccess ? TG_OK : TG_E_DEVICE;
 }
