@@ -102,7 +102,8 @@ size_t tg_workspace_bytes(int64_t n, int64_t nnz, int32_t L);
  *   per_edge              device uint64 [nnz/2][tg_row_width(L)] or NULL to
  *                         skip the per-edge table (global counts only).
  *   global_counts         device uint64 [tg_global_width(L)], or NULL.
- *   workspace             device buffer of ws_bytes >= tg_workspace_bytes().
+ *   workspace             device buffer of ws_bytes >= tg_workspace_bytes(),
+ *                         256-byte aligned (TG_E_INVALID_ARG otherwise).
  *   stream                hipStream_t as void*.
  * Returns when the counts are complete (see Stream above). */
 tg_status tg_count_typed_graphlets(const int64_t *row_ptr, const int32_t *col,
@@ -126,7 +127,8 @@ tg_status tg_count_typed_graphlets(const int64_t *row_ptr, const int32_t *col,
  *   per_edge          NULL, or device uint64 [nnz/2][tg_row_width(L_max)]
  *                     rows of the union's edges in canonical order (the
  *                     edges of graph g are contiguous), laid out for L_max.
- *   workspace         at least tg_batch_workspace_bytes(n, nnz, G, L_max).
+ *   workspace         at least tg_batch_workspace_bytes(n, nnz, G, L_max),
+ *                     256-byte aligned.
  * Validation, streams and errors as for tg_count_typed_graphlets; an
  * inconsistent descriptor or a cross-graph edge gives TG_E_BATCH. */
 size_t tg_batch_workspace_bytes(int64_t n, int64_t nnz, int64_t G, int32_t L_max);

@@ -28,6 +28,9 @@ static int bits_for(int64_t n) {
 }
 
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+// Workspace regions start at multiples of 256 bytes from the base, and some
+// are read 16 bytes at a time, so the base must be 256-byte aligned.
+static bool ws_aligned(const void *p) { return ((uintptr_t)p & 255u) == 0; }
 
 // Bytes of dense cycle maps allowed; the number of heavy workgroups follows.
 static const size_t MAP_BUDGET = size_t(32) << 30;
@@ -111,7 +114,7 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G) {
     y.off_neid = take(sizeof(uint32_t) * (nnz + 1));
     y.off_ei = take(sizeof(int32_t) * (y.m + 1));
     y.off_ej = take(sizeof(int32_t) * (y.m + 1));
-    y.off_tdeg = take(sizeof(uint32_t) * (n + 1) * L);
+    y.off_tdeg = take(sizeof(uint32_t) * (size_t)(n + 1) * tri_pitch(L));
     y.off_tri = take(sizeof(uint32_t) * (y.m + 1) * L);
     y.off_tri_slot = take(sizeof(uint32_t) * (size_t)(nnz + 1) * tri_pitch(L));
     y.off_A = take(sizeof(uint64_t) * (n + 1) * LL);
@@ -521,7 +524,7 @@ tg_status tg_count_typed_graphlets(const int64_t *row_ptr, const int32_t *col,
     if (s != TG_OK) return s;
     if (n > 0 && (!row_ptr || !types)) return TG_E_INVALID_ARG;
     if (nnz > 0 && !col) return TG_E_INVALID_ARG;
-    if (!workspace) return TG_E_INVALID_ARG;
+    if (!workspace || !tg::ws_aligned(workspace)) return TG_E_INVALID_ARG;
     if (ws_bytes < y.total) return TG_E_WORKSPACE;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (n == 0) {
@@ -550,7 +553,7 @@ tg_status tg_count_batch(const int64_t *row_ptr, const int32_t *col, const uint8
     tg_status s = tg::plan_layout(n, nnz, L_max, &y, G);
     if (s != TG_OK) return s;
     if (!row_ptr || !types || !graph_node_ptr || !graph_L || !graph_global_off || !graph_globals ||
-        !workspace || (nnz > 0 && !col) || n < 1 || globals_len < 1)
+        !workspace || !tg::ws_aligned(workspace) || (nnz > 0 && !col) || n < 1 || globals_len < 1)
         return TG_E_INVALID_ARG;
     if (ws_bytes < y.total) return TG_E_WORKSPACE;
     tg::BatchIn b{graph_node_ptr, graph_L, graph_global_off, G, globals_len};

@@ -136,20 +136,29 @@ __device__ __forceinline__ bool hub_adj(const EdgeArgs &a, int hy, int hx) {
 
 // Accumulate the triangle-set gathers of member k: X_i(t, .) += |T_ik^.|,
 // X_j(t, .) += |T_jk^.|, Y(t, .) += d_k^.
+// The three rows have tri_pitch(L) words (a multiple of 4, 16-byte aligned),
+// read four words per load.
 __device__ __forceinline__ void gather_member(const EdgeArgs &a, int32_t k, int64_t s_i, int64_t s_j,
                                               uint64_t *Xi, uint64_t *Xj, uint64_t *Y) {
     const int L = a.L;
     const int LP = tri_pitch(L);
-    const uint32_t *ri = a.tri_slot + (size_t)s_i * LP;
-    const uint32_t *rj = a.tri_slot + (size_t)s_j * LP;
-    int t = a.ntype[k];
-    for (int t2 = 0; t2 < L; ++t2) {
-        uint32_t vi = ri[t2];
-        uint32_t vj = rj[t2];
-        uint32_t vy = a.tdeg[(size_t)k * L + t2];
-        if (vi) atomicAdd((unsigned long long *)&Xi[t * L + t2], (unsigned long long)vi);
-        if (vj) atomicAdd((unsigned long long *)&Xj[t * L + t2], (unsigned long long)vj);
-        if (vy) atomicAdd((unsigned long long *)&Y[t * L + t2], (unsigned long long)vy);
+    const uint4 *ri = reinterpret_cast<const uint4 *>(a.tri_slot + (size_t)s_i * LP);
+    const uint4 *rj = reinterpret_cast<const uint4 *>(a.tri_slot + (size_t)s_j * LP);
+    const uint4 *ry = reinterpret_cast<const uint4 *>(a.tdeg + (size_t)k * LP);
+    const int t = a.ntype[k];
+    for (int c = 0; c < LP; c += 4) {
+        const uint4 vi = ri[c >> 2], vj = rj[c >> 2], vy = ry[c >> 2];
+        const uint32_t wi[4] = {vi.x, vi.y, vi.z, vi.w};
+        const uint32_t wj[4] = {vj.x, vj.y, vj.z, vj.w};
+        const uint32_t wy[4] = {vy.x, vy.y, vy.z, vy.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int t2 = c + q;
+            if (t2 >= L) break;
+            if (wi[q]) atomicAdd((unsigned long long *)&Xi[t * L + t2], (unsigned long long)wi[q]);
+            if (wj[q]) atomicAdd((unsigned long long *)&Xj[t * L + t2], (unsigned long long)wj[q]);
+            if (wy[q]) atomicAdd((unsigned long long *)&Y[t * L + t2], (unsigned long long)wy[q]);
+        }
     }
 }
 
@@ -569,8 +578,9 @@ __device__ __forceinline__ void derive_three(const EdgeArgs &a, int64_t e, int32
     const int64_t gid = a.batch ? (int64_t)a.ngraph[i] : 0;
     const int ta = a.ntype[i], tb = a.ntype[j];
     int64_t nTt = a.tri[(size_t)e * L + t];
-    int64_t si = (int64_t)a.tdeg[(size_t)i * L + t] - nTt - (tb == t);
-    int64_t sj = (int64_t)a.tdeg[(size_t)j * L + t] - nTt - (ta == t);
+    const int LP = tri_pitch(L);
+    int64_t si = (int64_t)a.tdeg[(size_t)i * LP + t] - nTt - (tb == t);
+    int64_t sj = (int64_t)a.tdeg[(size_t)j * LP + t] - nTt - (ta == t);
     if (si < 0 || sj < 0) bad |= ST_INTERNAL;
     if (a.rows) {
         uint64_t *row = a.rows + (size_t)e * W;
@@ -597,8 +607,8 @@ __device__ __forceinline__ void derive_pair(const EdgeArgs &a, int64_t e, int32_
     const int ta = a.ntype[i], tb = a.ntype[j];
     const uint64_t *Xi = xyk, *Xj = Xi + LL, *Y = Xi + 2 * LL, *K = Xi + 3 * LL;
     const uint32_t *tri_e = a.tri + (size_t)e * L;
-    const uint32_t *di = a.tdeg + (size_t)i * L;
-    const uint32_t *dj = a.tdeg + (size_t)j * L;
+    const uint32_t *di = a.tdeg + (size_t)i * tri_pitch(L);
+    const uint32_t *dj = a.tdeg + (size_t)j * tri_pitch(L);
     const uint64_t *Ai = a.A + (size_t)i * LL, *Aj = a.A + (size_t)j * LL;
     const uint64_t *Di = a.D + (size_t)i * LL, *Dj = a.D + (size_t)j * LL;
     const uint64_t *NC = a.NC + (size_t)e * LL;

@@ -116,7 +116,8 @@ struct EdgeArgs {
     const uint8_t *ntype;
     const uint32_t *neid;
     const int32_t *ei, *ej;
-    const uint32_t *tri, *tdeg;
+    const uint32_t *tri;
+    const uint32_t *tdeg;        // typed degrees per node, rows of tri_pitch(L)
     const uint32_t *tri_slot;    // typed triangle counts per slot, rows of tri_pitch(L)
     const uint64_t *A, *D, *NC;
     int64_t m;

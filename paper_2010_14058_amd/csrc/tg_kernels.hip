@@ -229,8 +229,8 @@ __global__ void k_finish_csr(const uint64_t *__restrict__ keys, const uint32_t *
     }
 }
 
-// One wave per internal node: typed degrees d_v^t and the first slot of the
-// row's hub suffix (neighbours with internal id >= hub_base).
+// One wave per internal node: typed degrees d_v^t (rows padded to
+// tri_pitch(L) words) and the first slot of the row's hub suffix (neighbours with internal id >= hub_base).
 __global__ void k_tdeg(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
                        const uint8_t *__restrict__ ntype, int64_t n, int L, int32_t hub_base,
                        uint32_t *__restrict__ tdeg, int64_t *__restrict__ hstart,
@@ -252,7 +252,8 @@ __global__ void k_tdeg(const int64_t *__restrict__ nrp, const int32_t *__restric
                 if (lane == tt) c += (uint32_t)__popcll(bal);
             }
         }
-        if (lane < L) tdeg[v * L + lane] = c;
+        const int LP = tri_pitch(L);
+        if (lane < LP) tdeg[v * LP + lane] = lane < L ? c : 0u;
     }
 }
 
@@ -405,9 +406,10 @@ __global__ void k_node_aggr(const int64_t *__restrict__ nrp, const int32_t *__re
             int32_t k = ncol[s];
             int t = ntype[k];
             const uint32_t *ts = tri_slot + (size_t)s * tri_pitch(L);
+            const uint32_t *dk = tdeg + (size_t)k * tri_pitch(L);
             for (int t2 = 0; t2 < L; ++t2) {
                 uint32_t a = ts[t2];
-                uint32_t d = tdeg[(size_t)k * L + t2];
+                uint32_t d = dk[t2];
                 if (a) atomicAdd((unsigned long long *)&sA[t * L + t2], (unsigned long long)a);
                 if (d) atomicAdd((unsigned long long *)&sD[t * L + t2], (unsigned long long)d);
             }

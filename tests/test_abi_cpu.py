@@ -114,3 +114,24 @@ def test_sparse_argument_checks():
     assert lib.tg_sparse_fill(None, 4, 17, 1, 1, 1, None) == 4
     assert lib.tg_sparse_fill(1, 4, 3, 1, None, 1, None) == 1
     assert lib.tg_sparse_fill(None, 0, 3, 1, None, None, None) == 0      # nothing to do
+
+
+def test_workspace_alignment_checked_first():
+    """A workspace that is not 256-byte aligned is refused before any device
+    work (the pointers are never dereferenced)."""
+    from paper_2010_14058_amd import _lib as L
+
+    lib = L.load()
+    n, nnz, nt = 100, 400, 3
+    need = lib.tg_workspace_bytes(n, nnz, nt)
+    assert need > 0
+    fake = 1 << 20
+    assert lib.tg_count_typed_graphlets(fake, fake, fake, n, nnz, nt, None, None,
+                                        fake + 16, need, None) == 1   # TG_E_INVALID_ARG
+    assert lib.tg_count_typed_graphlets(fake, fake, fake, n, nnz, nt, None, None,
+                                        fake, need - 1, None) == 5    # TG_E_WORKSPACE
+    G = 2
+    bneed = lib.tg_batch_workspace_bytes(n, nnz, G, nt)
+    assert bneed > 0
+    assert lib.tg_count_batch(fake, fake, fake, n, nnz, fake, fake, G, nt, fake, 10, None, fake,
+                              fake + 64, bneed, None) == 1
