@@ -13,6 +13,10 @@ timed steps.  ``roofline`` covers the kernel with the largest average time
 (HIP events on the library's stream), priced with the algorithmic bytes of
 that kernel.  ``cpu_baseline`` is the CPU oracle (the paper's algorithm) on
 a bounded random sample of the same graph's edges, timed on the host.
+
+Scheduling knobs: a tuned profile ``paper_2010_14058_amd/tuned/<workload>.json``
+(written by ``--autotune --tune-out PATH``) is applied when present and
+reported under ``tuning``; ``--no-tuned`` keeps the library defaults.
 """
 
 from __future__ import annotations
@@ -31,8 +35,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
-TCAP = 1024             # light clique path capacity (both degrees above: heavy path)
 CSRC = os.path.join(ROOT, "paper_2010_14058_amd", "csrc")
+TUNED_DIR = os.path.join(ROOT, "paper_2010_14058_amd", "tuned")
 
 
 def log(*a):
@@ -85,6 +89,29 @@ def algorithmic_bytes(g, L, stats, heavy_edge_info):
         "derive": m * (edge_fixed + xyk),
     }
     return {k: float(v) for k, v in b.items()}
+
+
+def setup_tuning(args, workload: str, run) -> dict:
+    """Knobs for the timed run: tune now (--autotune), else the workload's
+    tuned profile when there is one, else the library defaults."""
+    import paper_2010_14058_amd as P
+    from paper_2010_14058_amd import autotune as AT
+
+    path = os.path.join(TUNED_DIR, workload + ".json")
+    if args.autotune:
+        space = AT.BATCH_SPACE if args.mode == "batch" else AT.SINGLE_SPACE
+        log(f"[bench] autotuning {len(space)} knobs on {workload}")
+        res = AT.tune(run, space, log=log)
+        if args.tune_out:
+            AT.save(res, args.tune_out, workload)
+        return {"profile": "tuned in this run", "knobs": res.best,
+                "start_ms": round(res.start_ms, 3), "best_ms": round(res.best_ms, 3),
+                "trials": len(res.trials)}
+    if os.path.exists(path) and not args.no_tuned:
+        prof = AT.load(path)
+        AT.apply(prof)
+        return {"profile": os.path.relpath(path, ROOT), "knobs": prof["knobs"]}
+    return {"profile": None, "knobs": P.get_tuning()}
 
 
 def load_traffic(kernel: str):
@@ -146,6 +173,15 @@ def bench_batch(args):
     ws = P.Workspace(dev)
     glob = torch.empty(int(plan.goff_host[-1]), dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream(dev)
+
+    def run_once():
+        from paper_2010_14058_amd import autotune as AT
+
+        P.count_batch(plan, out_globals=glob, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        return AT.digest_of(glob)
+
+    tuning = setup_tuning(args, G.CONFIG_NAMES[4], run_once)
     P.set_timing(True)
     for w in range(args.warmup):
         P.count_batch(plan, out_globals=glob, workspace=ws, stream=stream)
@@ -210,6 +246,7 @@ def bench_batch(args):
         "single_call_path": {"graphs_per_s": single_gps, "graphs_timed": S,
                              "identical_counts": bool(same)},
         "speedup_vs_single_call": batch_gps / single_gps,
+        "tuning": tuning,
         "phases_ms": {k: round(v, 3) for k, v in phase_avg.items()},
         "work": {k: int(v) for k, v in stats.items()},
     }
@@ -329,6 +366,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing only)")
     ap.add_argument("--skip-cpu", action="store_true", help="no CPU baseline (profiling runs)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the scheduling knobs on this workload before timing")
+    ap.add_argument("--tune-out", default=None, help="with --autotune: write the profile here")
+    ap.add_argument("--no-tuned", action="store_true",
+                    help="ignore the tuned profile, time the library defaults")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -376,6 +418,15 @@ def main():
         del a, b
         log("[bench] calibration copy of 1 GiB done")
 
+    def run_once():
+        from paper_2010_14058_amd import autotune as AT
+
+        P.count_typed_graphlets(rp, col, ty, L, out_rows=rows, out_global=glob, workspace=ws,
+                                stream=stream)
+        torch.cuda.synchronize()
+        return AT.digest_of(glob, rows)
+
+    tuning = setup_tuning(args, st["name"], run_once)
     P.set_timing(True)
     for w in range(args.warmup):
         P.count_typed_graphlets(rp, col, ty, L, out_rows=rows, out_global=glob, workspace=ws,
@@ -397,11 +448,11 @@ def main():
     stats = P.last_stats()
     phase_avg = {k: v / max(args.steps, 1) for k, v in phase_sum.items()}
 
-    # heavy clique edges: both degrees above the light capacity
+    # heavy clique edges: both degrees above the light-edge bucket
     uv = g.edges()
     d = g.degrees()
     du, dv = d[uv[:, 0]], d[uv[:, 1]]
-    hv = np.minimum(du, dv) > TCAP
+    hv = np.minimum(du, dv) > P.get_tuning()["edge_deg"]
     hv_idx = torch.from_numpy(np.nonzero(hv)[0]).to(dev)
     hv_t = float(rows.index_select(0, hv_idx)[:, :L].sum().item()) if hv_idx.numel() else 0.0
     # sum over heavy edges of d_i + d_j (sum_v d_v^2 is the same sum over all edges)
@@ -436,6 +487,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "avg_ms": dom_ms},
         "pipeline_algorithmic_GBps": total_alg / (ms_per_step * 1e-3) / 1e9,
+        "tuning": tuning,
         "phases_ms": {k: round(v, 3) for k, v in phase_avg.items()},
         "work": {k: int(v) for k, v in stats.items()},
     }

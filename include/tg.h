@@ -177,8 +177,8 @@ tg_status tg_global_key_describe(int32_t L, int32_t idx, int32_t *graphlet,
  * next counting call on the thread. */
 const char *tg_last_error(void);
 
-/* Tuning knobs of the heavy 4-cycle path, kept per host thread and applied
- * to later calls on that thread.  They change how work is scheduled, never
+/* Scheduling knobs (work splits, workgroup counts, degree buckets), kept
+ * per host thread and applied to later calls on that thread.  They change how work is scheduled, never
  * the counts.
  *   TG_TUNE_TASK_WEDGES  (default 262144, >= 1): a heavy wedge group is split
  *       into target-id ranges of about this many wedges each (at most 64).
@@ -198,6 +198,13 @@ const char *tg_last_error(void);
  *       take at most this many bytes; 0 turns this off.
  *   TG_TUNE_DERIVE_EDGES (default 0 = automatic, 0..4): edges of the light
  *       kernel whose per-type-pair derivation runs together in one wave.
+ *   TG_TUNE_LIGHT_WEDGES (default 512, 1..512): degree bucket of the 4-cycle
+ *       groups: a group of at most this many wedges is counted by one wave
+ *       with a map in LDS, a larger one by the heavy (task) kernel.
+ *   TG_TUNE_EDGE_DEG     (default 1024, 1..1024): degree bucket of the edges:
+ *       an edge whose smaller endpoint degree is at most this is counted by
+ *       one wave with its triangle set in LDS, else by a 256-thread
+ *       workgroup of the heavy-edge kernel.
  * CYCLE_SLOTS, MAP_BYTES, EDGE_SLOTS and TBUF_BYTES change
  * tg_workspace_bytes and tg_batch_workspace_bytes, so they must be set
  * before the workspace is sized.
@@ -211,7 +218,9 @@ typedef enum {
     TG_TUNE_EDGE_SLOTS = 4,
     TG_TUNE_TBUF_BYTES = 5,
     TG_TUNE_RANGE_BYTES = 6,
-    TG_TUNE_DERIVE_EDGES = 7
+    TG_TUNE_DERIVE_EDGES = 7,
+    TG_TUNE_LIGHT_WEDGES = 8,
+    TG_TUNE_EDGE_DEG = 9
 } tg_tune;
 tg_status tg_set_tuning(int32_t knob, int64_t value);
 int64_t tg_get_tuning(int32_t knob);

@@ -125,7 +125,8 @@ def phase_times() -> list[tuple[str, float]]:
 
 
 TUNE_KNOBS = {"task_wedges": 0, "clear_bytes": 1, "cycle_slots": 2, "map_bytes": 3,
-              "edge_slots": 4, "tbuf_bytes": 5, "range_bytes": 6, "derive_edges": 7}
+              "edge_slots": 4, "tbuf_bytes": 5, "range_bytes": 6, "derive_edges": 7,
+              "light_wedges": 8, "edge_deg": 9}
 
 
 def set_tuning(**knobs) -> dict:

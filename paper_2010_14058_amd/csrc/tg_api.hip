@@ -40,9 +40,9 @@ static const int MAX_HEAVY_SLOTS = 1024;
 static const size_t XYK_BUDGET = size_t(16) << 30;
 
 // Scheduling knobs (tg_set_tuning), per host thread.
-thread_local int64_t g_tune[8] = {TASK_WEDGES, SEQ_CLEAR_BYTES, MAX_HEAVY_SLOTS,
-                                   (int64_t)MAP_BUDGET, MAX_HEAVY_SLOTS, (int64_t)TBUF_BUDGET,
-                                   TASK_RANGE_BYTES, 0};
+thread_local int64_t g_tune[10] = {TASK_WEDGES, SEQ_CLEAR_BYTES, MAX_HEAVY_SLOTS,
+                                    (int64_t)MAP_BUDGET, MAX_HEAVY_SLOTS, (int64_t)TBUF_BUDGET,
+                                    TASK_RANGE_BYTES, 0, LIGHT_MAXW, TCAP};
 
 static size_t sort_tmp_bytes(int64_t n, int64_t nnz) {
     size_t a = 0, b = 0, c = 0;
@@ -360,7 +360,8 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     HIPCHK(launch_fill_u64(NC, 0, m * LL, st));
     HIPCHK(launch_cyc_work(nrp, ncol, neid, eslot, nlow, n, la_l, la_h, lb_l, lb_h, counters,
                            (uint64_t)g_tune[TG_TUNE_TASK_WEDGES], L,
-                           (uint64_t)g_tune[TG_TUNE_RANGE_BYTES], st));
+                           (uint64_t)g_tune[TG_TUNE_RANGE_BYTES],
+                           (uint64_t)g_tune[TG_TUNE_LIGHT_WEDGES], st));
     timing_mark("cyc_work");
     CycleArgs ca;
     ca.tasks = nullptr;
@@ -402,7 +403,9 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     // each at most 2 * max_deg^2): 32-bit entries hold that sum when
     // max_deg <= 1024
     if (batch && max_deg <= 1024 && (size_t)gw * sizeof(uint32_t) <= 32768) ea.hist_in_lds = 2;
-    ea.tcap = (int)(max_deg < TCAP ? (max_deg > 0 ? max_deg : 1) : TCAP);
+    // light edges: smaller endpoint degree at most tcap (the LDS list size)
+    const int64_t ecut = g_tune[TG_TUNE_EDGE_DEG];
+    ea.tcap = (int)(max_deg < ecut ? (max_deg > 0 ? max_deg : 1) : ecut);
     // derive several edges together when their type pairs leave lanes idle
     // (a batch flushes its histogram per graph, so it derives edge by edge)
     {
@@ -645,6 +648,12 @@ tg_status tg_set_tuning(int32_t knob, int64_t value) {
     case TG_TUNE_DERIVE_EDGES:
         if (value < 0 || value > 4) return TG_E_INVALID_ARG;
         break;
+    case TG_TUNE_LIGHT_WEDGES:
+        if (value < 1 || value > tg::LIGHT_MAXW) return TG_E_INVALID_ARG;
+        break;
+    case TG_TUNE_EDGE_DEG:
+        if (value < 1 || value > tg::TCAP) return TG_E_INVALID_ARG;
+        break;
     default:
         return TG_E_INVALID_ARG;
     }
@@ -653,7 +662,7 @@ tg_status tg_set_tuning(int32_t knob, int64_t value) {
 }
 
 int64_t tg_get_tuning(int32_t knob) {
-    if (knob < 0 || knob > TG_TUNE_DERIVE_EDGES) return -1;
+    if (knob < 0 || knob > TG_TUNE_EDGE_DEG) return -1;
     return tg::g_tune[knob];
 }
 

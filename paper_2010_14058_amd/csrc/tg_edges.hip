@@ -728,7 +728,7 @@ __device__ __forceinline__ EdgeShared carve(const EdgeArgs &a, uint64_t *sm, uin
     return S;
 }
 
-// Light edges: one wave per edge (|T| <= min degree <= TCAP, lists in LDS).
+// Light edges: one wave per edge (|T| <= min degree <= tcap, lists in LDS).
 // DEFER: the edge's Xi, Xj, Y, K go to a.xyk and k_derive does the rest, so
 // this kernel carries no derivation state (fewer registers, more waves).
 template <bool DEFER>
@@ -760,7 +760,7 @@ __device__ __forceinline__ void edges_light_body(const EdgeArgs &a) {
     auto one_edge = [&](int64_t e) {
         int32_t i = a.ei[e], j = a.ej[e];
         int64_t di = a.nrp[i + 1] - a.nrp[i], dj = a.nrp[j + 1] - a.nrp[j];
-        if ((di < dj ? di : dj) > TCAP) {
+        if ((di < dj ? di : dj) > a.tcap) {
             if (lane == 0)
                 a.heavy_list[atomicAdd((unsigned long long *)&a.counters[C_EDGE_HEAVY], 1ull)] =
                     (uint32_t)e;

@@ -126,7 +126,7 @@ struct EdgeArgs {
     uint64_t *gacc;      // global accumulators
     int gw;
     int hist_in_lds;             // 0: global atomics, 1: uint64 LDS histogram, 2: uint32 LDS histogram
-    int tcap;                    // triangle-list entries in LDS (light kernel)
+    int tcap;                    // light/heavy edge cut on the smaller degree = LDS list size
     int derive_batch;            // edges whose derivation runs together (LDS slots of 4 L^2 words)
     uint64_t *xyk;               // deferred derivation: Xi, Xj, Y, K per edge ([m][4 L^2]), or null
     uint32_t *heavy_list;
@@ -206,7 +206,8 @@ hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8
 hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32_t *neid,
                            const uint32_t *eslot, const uint32_t *nlow, int64_t n, uint32_t *la_l,
                            uint4 *la_h, uint32_t *lb_l, uint4 *lb_h, uint64_t *counters,
-                           uint64_t task_wedges, int L, uint64_t range_bytes, hipStream_t st);
+                           uint64_t task_wedges, int L, uint64_t range_bytes,
+                           uint64_t light_max, hipStream_t st);
 int heavy_chunk_for(int L);
 hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned grid, hipStream_t st);
 hipError_t launch_edges(bool heavy, const EdgeArgs &args, unsigned grid, hipStream_t st);

@@ -487,7 +487,8 @@ __device__ __forceinline__ int hash_slot(uint32_t y) {
 }
 
 // Light groups: one 64-thread workgroup per group, LDS open-addressing map
-// keyed by target with 16-bit counters per type (group wedges <= LIGHT_MAXW).
+// keyed by target with 16-bit counters per type (group wedges at most the
+// light bucket bound, itself at most LIGHT_MAXW).
 template <int PASS>
 __global__ void __launch_bounds__(64) k_cyc_light(CycleArgs a) {
     extern __shared__ uint32_t sm_light[];
@@ -538,7 +539,7 @@ __global__ void __launch_bounds__(64) k_cyc_light(CycleArgs a) {
                     int tx = a.ntype[x];
                     int h = hash_slot(y);
                     if (phase == 0) {
-                        // the group has at most LIGHT_MAXW < LIGHT_HCAP distinct keys,
+                        // the group has at most LIGHT_MAXW < LIGHT_HCAP distinct keys
                         // so the probe ends; the bound only guards corrupted input
                         bool ok = false;
                         for (int probe = 0; probe < LIGHT_HCAP; ++probe) {
@@ -802,11 +803,11 @@ __device__ __forceinline__ uint64_t map_bytes_per_id(int64_t items, int L) {
 __device__ void push_groups(int32_t v, uint64_t w, uint32_t *light, uint4 *heavy,
                             uint64_t *counters, int c_light, int c_heavy, int c_wedges,
                             int c_wedges_heavy, uint64_t task_wedges, int64_t range_ids,
-                            uint64_t map_bytes_per_id, uint64_t range_bytes) {
+                            uint64_t map_bytes_per_id, uint64_t range_bytes, uint64_t light_max) {
     const int lane = lane_id();
     const uint64_t below = (1ull << lane) - 1ull;
-    const bool is_light = w && w <= (uint64_t)LIGHT_MAXW;
-    const bool is_heavy = w > (uint64_t)LIGHT_MAXW;
+    const bool is_light = w && w <= light_max;
+    const bool is_heavy = w > light_max;
     uint64_t bl = __ballot(is_light);
     if (bl) {
         uint64_t base = 0;
@@ -887,7 +888,7 @@ __global__ void __launch_bounds__(256) k_cyc_work(
     const uint32_t *__restrict__ nlow, int64_t n, uint32_t *__restrict__ listA_light,
     uint4 *__restrict__ listA_heavy, uint32_t *__restrict__ listB_light,
     uint4 *__restrict__ listB_heavy, uint64_t *__restrict__ counters, uint64_t task_wedges,
-    int L, uint64_t range_bytes) {
+    int L, uint64_t range_bytes, uint64_t light_max) {
     __shared__ int64_t s_thr;
     if (threadIdx.x == 0) {
         int64_t lo = 0, hi = n;
@@ -913,10 +914,10 @@ __global__ void __launch_bounds__(256) k_cyc_work(
         const int64_t dg = v < thr ? nrp[v + 1] - nrp[v] : 0;
         push_groups((int32_t)v, wa, listA_light, listA_heavy, counters, C_A_LIGHT, C_A_HEAVY,
                     C_WEDGES_A, C_WEDGES_A_HEAVY, task_wedges, v,
-                    map_bytes_per_id(nl, L), range_bytes);
+                    map_bytes_per_id(nl, L), range_bytes, light_max);
         push_groups((int32_t)v, wb, listB_light, listB_heavy, counters, C_B_LIGHT, C_B_HEAVY,
                     C_WEDGES_B, C_WEDGES_B_HEAVY, task_wedges, n - 1 - v,
-                    map_bytes_per_id(dg, L), range_bytes);
+                    map_bytes_per_id(dg, L), range_bytes, light_max);
     }
     for (int64_t v = thr + wid; v < n; v += nwaves) {
         uint64_t wa = 0, wb = 0;
@@ -927,10 +928,10 @@ __global__ void __launch_bounds__(256) k_cyc_work(
         const int64_t nl = (int64_t)nlow[v], dg = nrp[v + 1] - nrp[v];
         push_groups((int32_t)v, lane == 0 ? wa : 0ull, listA_light, listA_heavy, counters,
                     C_A_LIGHT, C_A_HEAVY, C_WEDGES_A, C_WEDGES_A_HEAVY, task_wedges, v,
-                    map_bytes_per_id(nl, L), range_bytes);
+                    map_bytes_per_id(nl, L), range_bytes, light_max);
         push_groups((int32_t)v, lane == 0 ? wb : 0ull, listB_light, listB_heavy, counters,
                     C_B_LIGHT, C_B_HEAVY, C_WEDGES_B, C_WEDGES_B_HEAVY, task_wedges, n - 1 - v,
-                    map_bytes_per_id(dg, L), range_bytes);
+                    map_bytes_per_id(dg, L), range_bytes, light_max);
     }
 }
 
@@ -1062,7 +1063,8 @@ hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8
 hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32_t *neid,
                            const uint32_t *eslot, const uint32_t *nlow, int64_t n, uint32_t *la_l,
                            uint4 *la_h, uint32_t *lb_l, uint4 *lb_h, uint64_t *counters,
-                           uint64_t task_wedges, int L, uint64_t range_bytes, hipStream_t st) {
+                           uint64_t task_wedges, int L, uint64_t range_bytes,
+                           uint64_t light_max, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     int dev = 0, cus = 0;
     hipError_t err = hipGetDevice(&dev);
@@ -1072,9 +1074,8 @@ hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32
     int64_t want = (n + 4 * WAVE - 1) / (4 * WAVE) + 1;
     int64_t cap = (int64_t)(cus > 0 ? cus : 256) * 16;
     unsigned grid = (unsigned)(want < cap ? want : cap);
-    k_cyc_work<<<grid, 256, 0, st>>>(nrp, ncol, neid, eslot, nlow, n, la_l, la_h, lb_l,
-                                                 lb_h, counters,
-                                                 task_wedges, L, range_bytes);
+    k_cyc_work<<<grid, 256, 0, st>>>(nrp, ncol, neid, eslot, nlow, n, la_l, la_h, lb_l, lb_h,
+                                     counters, task_wedges, L, range_bytes, light_max);
     LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -96,6 +96,12 @@ def test_tuning_knobs():
         P.set_tuning(task_wedges=0)
     with pytest.raises(P.TGError):
         P.set_tuning(clear_bytes=-1)
+    # degree buckets: defaults are the largest buckets the kernels support
+    assert base["light_wedges"] == 512 and base["edge_deg"] == 1024
+    P.set_tuning(light_wedges=1, edge_deg=1)
+    for bad in ({"light_wedges": 0}, {"light_wedges": 513}, {"edge_deg": 0}, {"edge_deg": 1025}):
+        with pytest.raises(P.TGError):
+            P.set_tuning(**bad)
     P.set_tuning(**base)
     assert P.get_tuning() == base
 

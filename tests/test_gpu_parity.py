@@ -230,3 +230,41 @@ def test_derive_batching(oracle_mod, derive_edges):
         check(oracle_mod, g)
     finally:
         P.set_tuning(**old)
+
+
+@pytest.mark.parametrize("knobs", [dict(light_wedges=1, edge_deg=1),
+                                   dict(light_wedges=64, edge_deg=16),
+                                   dict(light_wedges=512, edge_deg=1024)],
+                         ids=["all_heavy", "small_buckets", "largest_buckets"])
+def test_degree_buckets(oracle_mod, knobs):
+    """The degree buckets only move 4-cycle groups and edges between the
+    one-wave and the workgroup kernels: with every group and edge sent to
+    the workgroup kernels, with small buckets and with the largest ones the
+    counts are the same (a single graph and a batch)."""
+    import paper_2010_14058_amd as P
+
+    old = P.set_tuning(**knobs)
+    try:
+        g = G.chung_lu_typed(4000, 10.0, 2.1, 600.0, 4, seed=21, name="cl_4k_buckets")
+        check(oracle_mod, g)
+        st = P.last_stats()
+        d = g.degrees()
+        uv = g.edges()
+        assert st["heavy_edges"] == int(np.sum(np.minimum(d[uv[:, 0]], d[uv[:, 1]]) >
+                                               knobs["edge_deg"]))
+        check(oracle_mod, G.config_graph(1))
+        b = G.batch_graphs(60, seed=4)
+        u = b.union
+        import torch
+
+        dev = torch.device("cuda:0")
+        plan = P.BatchPlan(torch.from_numpy(u.row_ptr).to(dev), torch.from_numpy(u.col).to(dev),
+                           torch.from_numpy(u.types).to(dev), b.node_ptr, b.L)
+        glob, _ = P.count_batch(plan)
+        got = glob.cpu().numpy().view(np.uint64)
+        for q in range(b.G):
+            gg = b.graph(q)
+            want = oracle_mod.global_counts(gg, oracle_mod.all_edge_rows(gg))
+            np.testing.assert_array_equal(got[plan.goff_host[q]:plan.goff_host[q + 1]], want)
+    finally:
+        P.set_tuning(**old)
