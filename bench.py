@@ -289,7 +289,7 @@ def bench_serve(args):
     span = specs[-1]["arrival"] if specs else 1.0
     log(f"[bench] {len(reqs)} requests, {offered_edges} edges, arrivals over {span:.3f}s "
         f"({time.perf_counter() - t0:.1f}s to generate)")
-    ex = S.GpuExecutor(workers=args.workers)
+    ex = S.GpuExecutor(workers=args.workers, single_edges=args.single_edges)
     # warm the executor (library load, allocator) on a tiny batch
     warm = G.random_small_graph(20, 0.3, 6, 1)
     ex.run([S.Request(-1, warm.row_ptr, warm.col, warm.types, warm.L)], 0)
@@ -334,7 +334,7 @@ def bench_serve(args):
         "data": "synthetic",
         "config": {"workload": G.CONFIG_NAMES[5], "requests": len(reqs), "rate_per_s": args.rate,
                    "workers": args.workers, "hbm_budget_GB": args.hbm_budget_gb,
-                   "max_batch_edges": args.max_batch_edges},
+                   "max_batch_edges": args.max_batch_edges, "single_edges": args.single_edges},
         "offered_edges_per_s": offered_edges / max(span, 1e-9),
         "p50_latency_ms": rep["p50_latency_ms"],
         "p99_latency_ms": rep["p99_latency_ms"],
@@ -355,6 +355,8 @@ def main():
     ap.add_argument("--requests", type=int, default=400, help="serve mode: number of requests")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve mode: arrivals per second")
     ap.add_argument("--workers", type=int, default=2, help="serve mode: concurrent batches")
+    ap.add_argument("--single-edges", type=int, default=1 << 17,
+                    help="serve mode: requests with at least this many edges run as single calls")
     ap.add_argument("--hbm-budget-gb", type=float, default=96.0, help="serve mode: admission budget")
     ap.add_argument("--max-batch-edges", type=int, default=8_000_000,
                     help="serve mode: edges per batch at most")

@@ -200,6 +200,29 @@ struct EdgeShared {
     uint64_t *Gw;           // per-wave copies of Xi, Xj, Y (3 L^2 words each) or null
 };
 
+// Inclusive scan of one value per thread over the NT threads; *total (if
+// given) receives the sum over all of them.
+template <int NT>
+__device__ __forceinline__ uint32_t group_incl_scan(uint32_t v, uint32_t *wave_cnt,
+                                                    uint32_t *total = nullptr) {
+    uint32_t incl = wave_incl_scan(v);
+    if (NT == WAVE) {
+        if (total) *total = __shfl(incl, WAVE - 1, WAVE);
+        return incl;
+    }
+    int w = threadIdx.x / WAVE;
+    if (lane_id() == WAVE - 1) wave_cnt[w] = incl;
+    __syncthreads();
+    uint32_t add = 0, all = 0;
+    for (int q = 0; q < NT / WAVE; ++q) {
+        if (q < w) add += wave_cnt[q];
+        all += wave_cnt[q];
+    }
+    __syncthreads();
+    if (total) *total = all;
+    return incl + add;
+}
+
 // Build T (hub mask/list and sorted low list) and the gathers X_i, X_j, Y.
 template <int NT>
 __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeShared &S, int tid) {
@@ -291,23 +314,37 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
     // hub members
     const bool hi = i >= base, hj = j >= base;
     if (hi && hj) {
+        // T's hub mask is the AND of the two bit rows: its members are listed
+        // in hub order (a scan of the words' popcounts gives each word its
+        // place), then gathered one member per thread, so every thread has
+        // independent loads however the members fall into words
         const int hx_i = i - base, hx_j = j - base;
-        for (int q = tid; q < Hw; q += NT) {
-            uint64_t m = a.HB[(size_t)hx_i * Hw + q] & a.HB[(size_t)hx_j * Hw + q];
-            S.Tm[q] = m;
-            if (!m) continue;
-            atomicMin(&S.meta[2], (uint32_t)q);
-            atomicMax(&S.meta[3], (uint32_t)q);
-            while (m) {
-                int b = __ffsll((unsigned long long)m) - 1;
-                m &= m - 1;
-                int hk = q * 64 + b;
-                int32_t k = base + hk;
-                uint32_t pos = atomicAdd(&S.meta[1], 1u);
-                S.Th[(ptrdiff_t)pos * S.th_step] = (uint32_t)k;
-                gather_member(a, k, hub_slot(a, i, hx_i, hk), hub_slot(a, j, hx_j, hk), gXi, gXj,
-                              gY);
+        uint32_t nh = 0;
+        for (int q0 = 0; q0 < Hw; q0 += NT) {
+            const int q = q0 + tid;
+            uint64_t m = q < Hw ? a.HB[(size_t)hx_i * Hw + q] & a.HB[(size_t)hx_j * Hw + q] : 0ull;
+            if (q < Hw) S.Tm[q] = m;
+            if (m) {
+                atomicMin(&S.meta[2], (uint32_t)q);
+                atomicMax(&S.meta[3], (uint32_t)q);
             }
+            const uint32_t c = (uint32_t)__popcll(m);
+            uint32_t all = 0;
+            uint32_t pos = nh + group_incl_scan<NT>(c, S.wave_cnt, &all) - c;
+            while (m) {
+                const int b = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1;
+                S.Th[(ptrdiff_t)pos * S.th_step] = (uint32_t)(base + q * 64 + b);
+                ++pos;
+            }
+            nh += all;
+        }
+        if (tid == 0) S.meta[1] = nh;
+        group_sync<NT>();
+        for (uint32_t f = tid; f < nh; f += NT) {
+            const int32_t k = (int32_t)S.Th[(ptrdiff_t)f * S.th_step];
+            const int hk = k - base;
+            gather_member(a, k, hub_slot(a, i, hx_i, hk), hub_slot(a, j, hx_j, hk), gXi, gXj, gY);
         }
     } else {
         // scan the shorter hub suffix; test the other endpoint by its bit row
@@ -347,20 +384,6 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
         }
         group_sync<NT>();
     }
-}
-
-// Inclusive scan of one value per thread over the NT threads.
-template <int NT>
-__device__ __forceinline__ uint32_t group_incl_scan(uint32_t v, uint32_t *wave_cnt) {
-    uint32_t incl = wave_incl_scan(v);
-    if (NT == WAVE) return incl;
-    int w = threadIdx.x / WAVE;
-    if (lane_id() == WAVE - 1) wave_cnt[w] = incl;
-    __syncthreads();
-    uint32_t add = 0;
-    for (int q = 0; q < w; ++q) add += wave_cnt[q];
-    __syncthreads();
-    return incl + add;
 }
 
 // Scratch of the flattened low-member scans (NT entries each).

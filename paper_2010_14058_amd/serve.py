@@ -9,12 +9,15 @@ Requests carry one typed graph each and arrive over time.  The server
 * uploads an admitted request's CSR to the device, where it stays until the
   request completes;
 * runs several workers, each with its own HIP stream and workspace; a free
-  worker takes every admitted request not yet started as one batch, so
-  requests that arrive while others are on the GPU join the next batch and
-  batches of different workers overlap on the device;
-* runs each batch through ``tg_count_batch`` and hands every request its own
-  global count vector; if a batch fails, its requests are re-run one by one
-  so only the offending request gets the error.
+  worker takes every admitted request not yet started as one batch (up to
+  an edge budget), so requests that arrive while others are on the GPU join
+  the next batch and batches of different workers overlap on the device;
+* runs the small requests of a batch through one ``tg_count_batch`` call and
+  each large one (at least ``single_edges`` edges) through its own
+  single-graph call, which keeps the hub core and super-hub bitmaps that a
+  batch's graph-major order gives up; every request gets its own global
+  count vector; if a batch fails, its requests are re-run one by one so only
+  the offending request gets the error.
 
 The executor (batch of requests -> per-request results) is injectable; the
 default one calls the HIP library.
@@ -203,17 +206,22 @@ class Server:
 
 
 class GpuExecutor:
-    """Runs a batch of requests with tg_count_batch on one HIP device.
+    """Runs a batch of requests on one HIP device.
 
     Worker w uses its own stream and workspace.  A request's CSR is uploaded
-    at admission and concatenated on the device into the batch's union CSR.
+    at admission.  Requests of fewer than ``single_edges`` edges are
+    concatenated on the device into one union CSR and counted by one
+    ``tg_count_batch`` call; larger ones are counted one
+    ``tg_count_typed_graphlets`` call each (global counts only), on the same
+    stream.
     """
 
-    def __init__(self, device: str = "cuda:0", workers: int = 2):
+    def __init__(self, device: str = "cuda:0", workers: int = 2, single_edges: int = 1 << 17):
         import torch
 
         from . import Workspace
 
+        self.single_edges = int(single_edges)
         self.dev = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(workers)]
         self.ws = [Workspace(self.dev) for _ in range(workers)]
@@ -236,32 +244,54 @@ class GpuExecutor:
     def run(self, batch: list[Request], w: int) -> list[np.ndarray]:
         import torch
 
-        from . import BatchPlan, count_batch
+        from . import count_typed_graphlets
 
         stream = self.streams[w % len(self.streams)]
+        ws = self.ws[w % len(self.ws)]
+        out: list = [None] * len(batch)
         with torch.cuda.stream(stream):
             for r in batch:
                 if r.device is None:
                     r.device = self.upload(r)
                 stream.wait_event(r.device["ready"])
-            nodes = np.array([0] + [r.n for r in batch], dtype=np.int64)
-            node_off = np.cumsum(nodes)
-            nnz = np.array([0] + [2 * r.m for r in batch], dtype=np.int64)
-            nnz_off = np.cumsum(nnz)
-            row_parts = [torch.zeros(1, dtype=torch.int64, device=self.dev)]
-            col_parts, type_parts = [], []
+            small = [q for q, r in enumerate(batch) if r.m < self.single_edges]
+            if small:
+                for q, res in zip(small, self._run_batched([batch[q] for q in small], ws, stream)):
+                    out[q] = res
             for q, r in enumerate(batch):
-                row_parts.append(r.device["row_ptr"][1:] + int(nnz_off[q]))
-                col_parts.append(r.device["col"] + int(node_off[q]))
-                type_parts.append(r.device["types"])
-            row_ptr = torch.cat(row_parts)
-            col = torch.cat(col_parts) if col_parts else torch.zeros(0, dtype=torch.int32,
-                                                                     device=self.dev)
-            types = torch.cat(type_parts)
-            gl = np.array([r.L for r in batch], dtype=np.int32)
-            plan = BatchPlan(row_ptr, col.to(torch.int32), types, node_off, gl)
-            glob, _ = count_batch(plan, workspace=self.ws[w % len(self.ws)], stream=stream)
-            host = glob.cpu().numpy().view(np.uint64)
+                if r.m < self.single_edges:
+                    continue
+                d = r.device
+                _, g1 = count_typed_graphlets(d["row_ptr"], d["col"], d["types"], r.L,
+                                              per_edge=False, workspace=ws, stream=stream)
+                out[q] = g1.cpu().numpy().view(np.uint64).copy()
+        return out
+
+    def _run_batched(self, batch: list[Request], ws, stream) -> list[np.ndarray]:
+        """One tg_count_batch call over the union of the requests' graphs
+        (on the current stream, which is ``stream``)."""
+        import torch
+
+        from . import BatchPlan, count_batch
+
+        nodes = np.array([0] + [r.n for r in batch], dtype=np.int64)
+        node_off = np.cumsum(nodes)
+        nnz = np.array([0] + [2 * r.m for r in batch], dtype=np.int64)
+        nnz_off = np.cumsum(nnz)
+        row_parts = [torch.zeros(1, dtype=torch.int64, device=self.dev)]
+        col_parts, type_parts = [], []
+        for q, r in enumerate(batch):
+            row_parts.append(r.device["row_ptr"][1:] + int(nnz_off[q]))
+            col_parts.append(r.device["col"] + int(node_off[q]))
+            type_parts.append(r.device["types"])
+        row_ptr = torch.cat(row_parts)
+        col = torch.cat(col_parts) if col_parts else torch.zeros(0, dtype=torch.int32,
+                                                                 device=self.dev)
+        types = torch.cat(type_parts)
+        gl = np.array([r.L for r in batch], dtype=np.int32)
+        plan = BatchPlan(row_ptr, col.to(torch.int32), types, node_off, gl)
+        glob, _ = count_batch(plan, workspace=ws, stream=stream)
+        host = glob.cpu().numpy().view(np.uint64)
         return [host[plan.goff_host[q]:plan.goff_host[q + 1]].copy() for q in range(len(batch))]
 
 

@@ -34,7 +34,8 @@ def test_results_identical_alone_and_in_mix(oracle_mod):
     col = bad.col.copy()
     col[rp[0]] = 0 if rp[1] > rp[0] else col[rp[0]]
     reqs[7] = S.Request(7, rp, col, bad.types, bad.L, arrival=reqs[7].arrival)
-    ex = S.GpuExecutor(workers=2)
+    # requests of at least 2000 edges run as single-graph calls inside their batch
+    ex = S.GpuExecutor(workers=2, single_edges=2000)
     srv = S.Server(hbm_budget=64 << 30, executor=ex, workers=2, max_batch_edges=20_000)
     print(f"[gpu] serving {len(reqs)} requests", flush=True)
     S.replay(srv, reqs)
@@ -43,6 +44,7 @@ def test_results_identical_alone_and_in_mix(oracle_mod):
     print(rep, flush=True)
     assert rep["requests"] == len(reqs)
     assert srv.batches < len(reqs)           # requests were batched
+    assert any(r.m >= 2000 for r in reqs) and any(r.m < 2000 for r in reqs)
     for q, (r, g) in enumerate(zip(reqs, graphs)):
         if q == 7:
             assert r.status == 2 and r.result is None
