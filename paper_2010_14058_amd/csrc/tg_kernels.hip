@@ -749,20 +749,21 @@ __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
                         int tx = a.ntype[x];
                         int ty = a.ntype[y];
                         uint64_t *ac = acc + (size_t)o * LL;
-                        for (int t = 0; t < L; ++t) {
-                            uint32_t c;
-                            if (narrow) {
-                                c = __hip_atomic_load(&my[t >> 1], __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_WORKGROUP);
-                                c = (c >> ((t & 1) * 16)) & 0xffffu;
-                            } else {
-                                c = __hip_atomic_load(&my[t], __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+                        // one load per map word: two 16-bit counts a word when
+                        // narrow (atomic loads are not merged by the compiler)
+                        for (int w = 0; w < EW; ++w) {
+                            const uint32_t word = __hip_atomic_load(
+                                &my[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            for (int h = 0; h < (narrow ? 2 : 1); ++h) {
+                                const int t = narrow ? 2 * w + h : w;
+                                if (t >= L) break;
+                                const uint32_t c = narrow ? (word >> (16 * h)) & 0xffffu : word;
+                                const uint32_t val = c - (t == tx ? 1u : 0u);
+                                if (val)
+                                    atomicAdd(
+                                        (unsigned long long *)&ac[pass_entry<PASS>(t, ty, L)],
+                                        (unsigned long long)val);
                             }
-                            uint32_t val = c - (t == tx ? 1u : 0u);
-                            if (val)
-                                atomicAdd((unsigned long long *)&ac[pass_entry<PASS>(t, ty, L)],
-                                          (unsigned long long)val);
                         }
                     }
                 }
