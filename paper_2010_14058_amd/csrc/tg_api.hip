@@ -111,6 +111,7 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G) {
     y.off_val_a = take(sizeof(uint32_t) * (nnz + 1));
     y.off_val_b = take(sizeof(uint32_t) * (nnz + 1));
     y.off_ncol = take(sizeof(int32_t) * (nnz + 1));
+    y.off_ctype = take((size_t)nnz + 1);
     y.off_neid = take(sizeof(uint32_t) * (nnz + 1));
     y.off_ei = take(sizeof(int32_t) * (y.m + 1));
     y.off_ej = take(sizeof(int32_t) * (y.m + 1));
@@ -339,7 +340,8 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
                                      2 * bits, st));
     uint32_t *eslot = at<uint32_t>(ws, y.off_eslot);
     uint32_t *nlow = at<uint32_t>(ws, y.off_nlow);
-    HIPCHK(launch_finish_csr(key_b, val_b, nnz, bits, eslot, ncol, neid, st));
+    uint8_t *ctype = at<uint8_t>(ws, y.off_ctype);
+    HIPCHK(launch_finish_csr(key_b, val_b, nnz, bits, ntype, eslot, ncol, neid, ctype, st));
     int64_t *hstart = at<int64_t>(ws, y.off_hstart);
     uint64_t *HB = at<uint64_t>(ws, y.off_HB);
     uint32_t *hpre = at<uint32_t>(ws, y.off_hpre);
@@ -368,7 +370,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     ca.eslot = eslot;
     ca.nlow = nlow;
     ca.clear_bytes = (uint64_t)g_tune[TG_TUNE_CLEAR_BYTES];
-    ca.nrp = nrp; ca.ncol = ncol; ca.ntype = ntype; ca.neid = neid; ca.ei = ei;
+    ca.nrp = nrp; ca.ncol = ncol; ca.ntype = ntype; ca.neid = neid; ca.ctype = ctype; ca.ei = ei;
     ca.counters = counters; ca.L = L; ca.n = n; ca.NC = NC; ca.maps = maps;
     ca.chunk = heavy_chunk_for(L);
     ca.status = status;

@@ -54,7 +54,7 @@ struct Layout {
     size_t off_status, off_counters;
     size_t off_deg, off_ucount, off_eoff, off_order, off_newid, off_ntype, off_nrp, off_ndeg;
     size_t off_key_a, off_key_b, off_val_a, off_val_b;
-    size_t off_ncol, off_neid, off_ei, off_ej;
+    size_t off_ncol, off_neid, off_ei, off_ej, off_ctype;
     size_t off_tdeg, off_tri, off_tri_slot, off_A, off_D, off_NC;
     size_t off_listA_light, off_listA_heavy, off_listB_light, off_listB_heavy, off_list_edge;
     size_t off_maps, off_tbuf, off_gacc, off_sort_tmp;
@@ -92,6 +92,7 @@ struct CycleArgs {
     const int32_t *ncol;
     const uint8_t *ntype;
     const uint32_t *neid;
+    const uint8_t *ctype;      // type of the neighbour at each adjacency slot
     const int32_t *ei;
     const uint32_t *list;      // light groups
     const uint4 *tasks;        // heavy tasks: group, part, parts, wedges of the group
@@ -181,8 +182,8 @@ hipError_t launch_slot_keys(const int64_t *rp, const int32_t *col, const int64_t
                             uint64_t *keys, uint32_t *vals, int32_t *ei, int32_t *ej,
                             uint32_t *status, hipStream_t st);
 hipError_t launch_finish_csr(const uint64_t *keys, const uint32_t *vals, int64_t nnz, int bits,
-                             uint32_t *eslot,
-                             int32_t *ncol, uint32_t *neid, hipStream_t st);
+                             const uint8_t *ntype, uint32_t *eslot, int32_t *ncol, uint32_t *neid,
+                             uint8_t *ctype, hipStream_t st);
 hipError_t launch_tdeg(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype, int64_t n,
                        int L, int32_t hub_base, uint32_t *tdeg, int64_t *hstart, uint32_t *nlow,
                        hipStream_t st);

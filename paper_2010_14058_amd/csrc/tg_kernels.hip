@@ -215,8 +215,9 @@ __global__ void k_slot_keys(const int64_t *__restrict__ rp, const int32_t *__res
 // every edge in both of its rows: eslot[2e] in the row of its smaller end,
 // eslot[2e + 1] in the row of its larger end.
 __global__ void k_finish_csr(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
-                             int64_t nnz, int bits, uint32_t *__restrict__ eslot,
-                             int32_t *__restrict__ ncol, uint32_t *__restrict__ neid) {
+                             int64_t nnz, int bits, const uint8_t *__restrict__ ntype,
+                             uint32_t *__restrict__ eslot, int32_t *__restrict__ ncol,
+                             uint32_t *__restrict__ neid, uint8_t *__restrict__ ctype) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s < nnz) {
         uint64_t k = keys[s];
@@ -225,6 +226,7 @@ __global__ void k_finish_csr(const uint64_t *__restrict__ keys, const uint32_t *
         uint32_t e = vals[s];
         ncol[s] = c;
         neid[s] = e;
+        ctype[s] = ntype[c];
         eslot[2 * (size_t)e + (r < c ? 0 : 1)] = (uint32_t)s;
     }
 }
@@ -496,7 +498,7 @@ __global__ void __launch_bounds__(64) k_cyc_light(CycleArgs a) {
     const int LW = (L + 1) / 2;
     uint32_t *keys = sm_light;
     uint32_t *cnt = keys + LIGHT_HCAP;
-    __shared__ int32_t it_x[WAVE];
+    __shared__ int32_t it_tx[WAVE];  // type of each staged item (the centre)
     __shared__ int64_t it_tb[WAVE];
     __shared__ uint32_t it_scan[WAVE];
     __shared__ uint32_t it_eid[WAVE];
@@ -520,7 +522,7 @@ __global__ void __launch_bounds__(64) k_cyc_light(CycleArgs a) {
                     int64_t tb, te;
                     target_range<PASS>(a, g, x, e, tb, te);
                     len = (uint32_t)(te - tb);
-                    it_x[lane] = x;
+                    it_tx[lane] = a.ntype[x];
                     it_tb[lane] = tb;
                     it_eid[lane] = e;
                     it_flip[lane] = phase ? orient_flip<PASS>(a, g, x, e) : 0;
@@ -534,9 +536,9 @@ __global__ void __launch_bounds__(64) k_cyc_light(CycleArgs a) {
                 for (uint32_t f = lane; f < total; f += WAVE) {
                     o = owner_next(it_scan, nitems, f, o);
                     uint32_t excl = o ? it_scan[o - 1] : 0;
-                    int32_t x = it_x[o];
-                    uint32_t y = (uint32_t)a.ncol[it_tb[o] + (f - excl)];
-                    int tx = a.ntype[x];
+                    const int tx = it_tx[o];
+                    const int64_t ys = it_tb[o] + (f - excl);
+                    uint32_t y = (uint32_t)a.ncol[ys];
                     int h = hash_slot(y);
                     if (phase == 0) {
                         // the group has at most LIGHT_MAXW < LIGHT_HCAP distinct keys
@@ -559,7 +561,7 @@ __global__ void __launch_bounds__(64) k_cyc_light(CycleArgs a) {
                             atomicOr(a.status, ST_INTERNAL);
                             continue;
                         }
-                        int ty = a.ntype[y];
+                        int ty = a.ctype[ys];
                         uint32_t e = it_eid[o];
                         int flip = it_flip[o];
                         uint64_t *nc = a.NC + (size_t)e * L * L;
@@ -638,7 +640,7 @@ __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
     const int LL = L * L;
     const int CH = a.chunk;
     uint64_t *acc = sm_heavy;  // CH * L * L
-    __shared__ int32_t it_x[HEAVY_CHUNK];
+    __shared__ int32_t it_tx[HEAVY_CHUNK];  // type of each staged item (the centre)
     __shared__ int64_t it_tb[HEAVY_CHUNK];
     __shared__ uint32_t it_scan[HEAVY_CHUNK];
     __shared__ uint32_t it_eid[HEAVY_CHUNK];
@@ -715,7 +717,7 @@ __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
                         if (tb < te && a.ncol[te - 1] >= hi) te = lower_bound(a.ncol, tb, te, hi);
                     }
                     len = (uint32_t)(te > tb ? te - tb : 0);
-                    it_x[tid] = x;
+                    it_tx[tid] = a.ntype[x];
                     it_tb[tid] = tb;
                     it_eid[tid] = e;
                     it_flip[tid] = orient_flip<PASS>(a, g, x, e);
@@ -730,15 +732,15 @@ __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
                 for (uint32_t f = tid; f < total; f += HEAVY_THREADS) {
                     o = owner_next(it_scan, nitems, f, o);
                     uint32_t excl = o ? it_scan[o - 1] : 0;
-                    int32_t x = it_x[o];
-                    uint32_t y = (uint32_t)a.ncol[it_tb[o] + (f - excl)];
+                    const int tx = it_tx[o];
+                    const int64_t ys = it_tb[o] + (f - excl);
+                    uint32_t y = (uint32_t)a.ncol[ys];
                     uint32_t *my = map + (size_t)y * EW;
                     if (phase == 0) {
                         for (int t = 0; t < EW; ++t) my[t] = 0u;
                     } else if (phase == 1) {
                         // the map is private to this workgroup: workgroup scope
                         // keeps the update in the XCD's L2
-                        int tx = a.ntype[x];
                         if (narrow)
                             __hip_atomic_fetch_add(&my[tx >> 1], 1u << ((tx & 1) * 16),
                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -746,8 +748,7 @@ __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
                             __hip_atomic_fetch_add(&my[tx], 1u, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
                     } else {
-                        int tx = a.ntype[x];
-                        int ty = a.ntype[y];
+                        int ty = a.ctype[ys];
                         uint64_t *ac = acc + (size_t)o * LL;
                         // one load per map word: two 16-bit counts a word when
                         // narrow (atomic loads are not merged by the compiler)
@@ -1023,9 +1024,11 @@ hipError_t launch_slot_keys(const int64_t *rp, const int32_t *col, const int64_t
 }
 
 hipError_t launch_finish_csr(const uint64_t *keys, const uint32_t *vals, int64_t nnz, int bits,
-                             uint32_t *eslot, int32_t *ncol, uint32_t *neid, hipStream_t st) {
+                             const uint8_t *ntype, uint32_t *eslot, int32_t *ncol, uint32_t *neid,
+                             uint8_t *ctype, hipStream_t st) {
     if (nnz == 0) return hipSuccess;
-    k_finish_csr<<<blocks_for(nnz, 256), 256, 0, st>>>(keys, vals, nnz, bits, eslot, ncol, neid);
+    k_finish_csr<<<blocks_for(nnz, 256), 256, 0, st>>>(keys, vals, nnz, bits, ntype, eslot, ncol,
+                                                       neid, ctype);
     LAUNCH_CHECK();
     return hipSuccess;
 }
