@@ -346,16 +346,16 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     uint64_t *HB = at<uint64_t>(ws, y.off_HB);
     uint32_t *hpre = at<uint32_t>(ws, y.off_hpre);
     uint64_t *TM = at<uint64_t>(ws, y.off_TM);
-    HIPCHK(launch_tdeg(nrp, ncol, ntype, n, L, hub_base, tdeg, hstart, nlow, st));
+    HIPCHK(launch_tdeg(nrp, ncol, ctype, n, L, hub_base, tdeg, hstart, nlow, st));
     HIPCHK(launch_hub_build(nrp, ncol, hstart, ntype, n, H, Hw, L, HB, hpre, TM, st));
     HIPCHK(launch_superhubs(nrp, ncol, n, S, nw, SB, SP, st));
     timing_mark("prep");
 
     // ---- typed triangles and node aggregates
-    HIPCHK(launch_tri(nrp, ncol, ntype, ei, ej, eslot, tri_slot, m, L, tri, counters + C_TRI_SUM, sh_base, nw, SB,
+    HIPCHK(launch_tri(nrp, ncol, ctype, ei, ej, eslot, tri_slot, m, L, tri, counters + C_TRI_SUM, sh_base, nw, SB,
                       st));
     timing_mark("tri");
-    HIPCHK(launch_node_aggr(nrp, ncol, ntype, tri_slot, tdeg, n, L, A, D, st));
+    HIPCHK(launch_node_aggr(nrp, ncol, ctype, tri_slot, tdeg, n, L, A, D, st));
     timing_mark("aggr");
 
     // ---- 4-cycles from degree-ordered wedges
@@ -397,6 +397,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     // ---- cliques, derivation, rows and global counts
     EdgeArgs ea;
     ea.nrp = nrp; ea.ncol = ncol; ea.ntype = ntype; ea.neid = neid; ea.ei = ei; ea.ej = ej;
+    ea.ctype = ctype;
     ea.tri = tri; ea.tdeg = tdeg; ea.tri_slot = tri_slot; ea.A = A; ea.D = D; ea.NC = NC; ea.m = m; ea.L = L;
     ea.rows = per_edge; ea.gacc = gacc; ea.gw = gw;
     ea.hist_in_lds = (size_t)gw * sizeof(uint64_t) <= 32768 ? 1 : 0;

@@ -134,18 +134,18 @@ __device__ __forceinline__ bool hub_adj(const EdgeArgs &a, int hy, int hx) {
     return (a.HB[(size_t)hy * a.Hw + (hx >> 6)] >> (hx & 63)) & 1ull;
 }
 
-// Accumulate the triangle-set gathers of member k: X_i(t, .) += |T_ik^.|,
+// Accumulate the triangle-set gathers of member k of type t: X_i(t, .) += |T_ik^.|,
 // X_j(t, .) += |T_jk^.|, Y(t, .) += d_k^.
 // The three rows have tri_pitch(L) words (a multiple of 4, 16-byte aligned),
 // read four words per load.
-__device__ __forceinline__ void gather_member(const EdgeArgs &a, int32_t k, int64_t s_i, int64_t s_j,
-                                              uint64_t *Xi, uint64_t *Xj, uint64_t *Y) {
+__device__ __forceinline__ void gather_member(const EdgeArgs &a, int32_t k, int t, int64_t s_i,
+                                              int64_t s_j, uint64_t *Xi, uint64_t *Xj,
+                                              uint64_t *Y) {
     const int L = a.L;
     const int LP = tri_pitch(L);
     const uint4 *ri = reinterpret_cast<const uint4 *>(a.tri_slot + (size_t)s_i * LP);
     const uint4 *rj = reinterpret_cast<const uint4 *>(a.tri_slot + (size_t)s_j * LP);
     const uint4 *ry = reinterpret_cast<const uint4 *>(a.tdeg + (size_t)k * LP);
-    const int t = a.ntype[k];
     for (int c = 0; c < LP; c += 4) {
         const uint4 vi = ri[c >> 2], vj = rj[c >> 2], vy = ry[c >> 2];
         const uint32_t wi[4] = {vi.x, vi.y, vi.z, vi.w};
@@ -305,7 +305,7 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
             }
             if (found) {
                 S.Tl[pos] = (uint32_t)x;
-                gather_member(a, x, i_small ? p : q, i_small ? q : p, gXi, gXj, gY);
+                gather_member(a, x, a.ctype[p], i_small ? p : q, i_small ? q : p, gXi, gXj, gY);
             }
         }
         if (tid == 0 && !unordered) S.meta[0] = count;
@@ -344,7 +344,8 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
         for (uint32_t f = tid; f < nh; f += NT) {
             const int32_t k = (int32_t)S.Th[(ptrdiff_t)f * S.th_step];
             const int hk = k - base;
-            gather_member(a, k, hub_slot(a, i, hx_i, hk), hub_slot(a, j, hx_j, hk), gXi, gXj, gY);
+            gather_member(a, k, a.ntype[k], hub_slot(a, i, hx_i, hk), hub_slot(a, j, hx_j, hk), gXi,
+                          gXj, gY);
         }
     } else {
         // scan the shorter hub suffix; test the other endpoint by its bit row
@@ -372,7 +373,7 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
             atomicMax(&S.meta[3], (uint32_t)(hk >> 6));
             uint32_t pos = atomicAdd(&S.meta[1], 1u);
             S.Th[(ptrdiff_t)pos * S.th_step] = (uint32_t)x;
-            gather_member(a, x, i_small ? p : q, i_small ? q : p, gXi, gXj, gY);
+            gather_member(a, x, a.ctype[p], i_small ? p : q, i_small ? q : p, gXi, gXj, gY);
         }
     }
     group_sync<NT>();

@@ -118,7 +118,8 @@ struct EdgeArgs {
     const uint32_t *neid;
     const int32_t *ei, *ej;
     const uint32_t *tri;
-    const uint32_t *tdeg;        // typed degrees per node, rows of tri_pitch(L)
+    const uint32_t *tdeg;
+    const uint8_t *ctype;        // type of the neighbour at each adjacency slot        // typed degrees per node, rows of tri_pitch(L)
     const uint32_t *tri_slot;    // typed triangle counts per slot, rows of tri_pitch(L)
     const uint64_t *A, *D, *NC;
     int64_t m;
@@ -184,7 +185,7 @@ hipError_t launch_slot_keys(const int64_t *rp, const int32_t *col, const int64_t
 hipError_t launch_finish_csr(const uint64_t *keys, const uint32_t *vals, int64_t nnz, int bits,
                              const uint8_t *ntype, uint32_t *eslot, int32_t *ncol, uint32_t *neid,
                              uint8_t *ctype, hipStream_t st);
-hipError_t launch_tdeg(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype, int64_t n,
+hipError_t launch_tdeg(const int64_t *nrp, const int32_t *ncol, const uint8_t *ctype, int64_t n,
                        int L, int32_t hub_base, uint32_t *tdeg, int64_t *hstart, uint32_t *nlow,
                        hipStream_t st);
 hipError_t launch_hub_build(const int64_t *nrp, const int32_t *ncol, const int64_t *hstart,
@@ -194,14 +195,14 @@ hipError_t launch_hub_build(const int64_t *nrp, const int32_t *ncol, const int64
 // to a multiple of 4, for 16-byte loads.
 __host__ __device__ inline int tri_pitch(int L) { return (L + 3) & ~3; }
 
-hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype,
+hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *ctype,
                       const int32_t *ei, const int32_t *ej, const uint32_t *eslot,
                       uint32_t *tri_slot, int64_t m, int L, uint32_t *tri,
                       uint64_t *tri_sum, int32_t sh_base, int64_t nw, const uint64_t *SB,
                       hipStream_t st);
 hipError_t launch_superhubs(const int64_t *nrp, const int32_t *ncol, int64_t n, int S, int64_t nw,
                             uint64_t *SB, uint32_t *SP, hipStream_t st);
-hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype,
+hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8_t *ctype,
                             const uint32_t *tri_slot, const uint32_t *tdeg,
                             int64_t n, int L, uint64_t *A, uint64_t *D, hipStream_t st);
 hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32_t *neid,

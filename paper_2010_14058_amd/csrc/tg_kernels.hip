@@ -234,7 +234,7 @@ __global__ void k_finish_csr(const uint64_t *__restrict__ keys, const uint32_t *
 // One wave per internal node: typed degrees d_v^t (rows padded to
 // tri_pitch(L) words) and the first slot of the row's hub suffix (neighbours with internal id >= hub_base).
 __global__ void k_tdeg(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
-                       const uint8_t *__restrict__ ntype, int64_t n, int L, int32_t hub_base,
+                       const uint8_t *__restrict__ ctype, int64_t n, int L, int32_t hub_base,
                        uint32_t *__restrict__ tdeg, int64_t *__restrict__ hstart,
                        uint32_t *__restrict__ nlow) {
     const int lane = lane_id();
@@ -248,7 +248,7 @@ __global__ void k_tdeg(const int64_t *__restrict__ nrp, const int32_t *__restric
         uint32_t c = 0;
         for (int64_t base = nrp[v]; base < nrp[v + 1]; base += WAVE) {
             int64_t s = base + lane;
-            int t = s < nrp[v + 1] ? (int)ntype[ncol[s]] : -1;
+            int t = s < nrp[v + 1] ? (int)ctype[s] : -1;
             for (int tt = 0; tt < L; ++tt) {
                 uint64_t bal = __ballot(t == tt);
                 if (lane == tt) c += (uint32_t)__popcll(bal);
@@ -269,7 +269,7 @@ constexpr int TRI_GROUPS = 8;
 constexpr int TRI_LANES = WAVE / TRI_GROUPS;
 
 __global__ void k_tri(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
-                      const uint8_t *__restrict__ ntype, const int32_t *__restrict__ ei,
+                      const uint8_t *__restrict__ ctype, const int32_t *__restrict__ ei,
                       const int32_t *__restrict__ ej, const uint32_t *__restrict__ eslot,
                       uint32_t *__restrict__ tri_slot, int64_t m, int L,
                       uint32_t *__restrict__ tri, uint64_t *__restrict__ tri_sum, int32_t sh_base,
@@ -307,7 +307,7 @@ __global__ void k_tri(const int64_t *__restrict__ nrp, const int32_t *__restrict
                     found = q < be && ncol[q] == x;
                 }
                 if (found) {
-                    int tx = ntype[x];
+                    int tx = ctype[s];
 #pragma unroll
                     for (int t = 0; t < TG_MAX_L; ++t) cnt[t] += (t == tx);
                 }
@@ -391,7 +391,7 @@ __global__ void __launch_bounds__(256) k_superhubs(const int64_t *__restrict__ n
 
 // One wave per internal node u; LDS holds A_u and D_u (L x L uint64 each).
 __global__ void k_node_aggr(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
-                            const uint8_t *__restrict__ ntype, const uint32_t *__restrict__ tri_slot,
+                            const uint8_t *__restrict__ ctype, const uint32_t *__restrict__ tri_slot,
                             const uint32_t *__restrict__ tdeg,
                             int64_t n, int L, uint64_t *__restrict__ A, uint64_t *__restrict__ D) {
     extern __shared__ uint64_t sm_aggr[];
@@ -406,7 +406,7 @@ __global__ void k_node_aggr(const int64_t *__restrict__ nrp, const int32_t *__re
         wave_sync();
         for (int64_t s = nrp[u] + lane; s < nrp[u + 1]; s += WAVE) {
             int32_t k = ncol[s];
-            int t = ntype[k];
+            int t = ctype[s];
             const uint32_t *ts = tri_slot + (size_t)s * tri_pitch(L);
             const uint32_t *dk = tdeg + (size_t)k * tri_pitch(L);
             for (int t2 = 0; t2 < L; ++t2) {
@@ -1033,32 +1033,32 @@ hipError_t launch_finish_csr(const uint64_t *keys, const uint32_t *vals, int64_t
     return hipSuccess;
 }
 
-hipError_t launch_tdeg(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype, int64_t n,
+hipError_t launch_tdeg(const int64_t *nrp, const int32_t *ncol, const uint8_t *ctype, int64_t n,
                        int L, int32_t hub_base, uint32_t *tdeg, int64_t *hstart, uint32_t *nlow,
                        hipStream_t st) {
-    k_tdeg<<<blocks_bounded(n, 4, 32), 256, 0, st>>>(nrp, ncol, ntype, n, L, hub_base, tdeg,
+    k_tdeg<<<blocks_bounded(n, 4, 32), 256, 0, st>>>(nrp, ncol, ctype, n, L, hub_base, tdeg,
                                                      hstart, nlow);
     LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype,
+hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *ctype,
                       const int32_t *ei, const int32_t *ej, const uint32_t *eslot,
                       uint32_t *tri_slot, int64_t m, int L, uint32_t *tri,
                       uint64_t *tri_sum, int32_t sh_base, int64_t nw, const uint64_t *SB,
                       hipStream_t st) {
     if (m == 0) return hipSuccess;
     k_tri<<<blocks_bounded(m, 4 * TRI_GROUPS, 32), 256, 0, st>>>(
-        nrp, ncol, ntype, ei, ej, eslot, tri_slot, m, L, tri, tri_sum, sh_base, nw, SB);
+        nrp, ncol, ctype, ei, ej, eslot, tri_slot, m, L, tri, tri_sum, sh_base, nw, SB);
     LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8_t *ntype,
+hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8_t *ctype,
                             const uint32_t *tri_slot, const uint32_t *tdeg,
                             int64_t n, int L, uint64_t *A, uint64_t *D, hipStream_t st) {
     size_t sh = (size_t)4 * 2 * L * L * sizeof(uint64_t);
-    k_node_aggr<<<blocks_bounded(n, 4, 32), 256, sh, st>>>(nrp, ncol, ntype, tri_slot, tdeg, n, L,
+    k_node_aggr<<<blocks_bounded(n, 4, 32), 256, sh, st>>>(nrp, ncol, ctype, tri_slot, tdeg, n, L,
                                                            A, D);
     LAUNCH_CHECK();
     return hipSuccess;
