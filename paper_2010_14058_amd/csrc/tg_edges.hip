@@ -49,17 +49,21 @@ __global__ void k_hub_rows(const int64_t *__restrict__ nrp, const int32_t *__res
     }
 }
 
-// TM[t][q]: bit b set iff hub 64q+b has type t.
+// TM[q][t] (t < tm_pitch(L)): bit b set iff hub 64q+b has type t, for
+// t < L - 1; the padding entry is zero.  A word's masks are adjacent, so the
+// hub-pair count reads them 16 bytes at a time.
 __global__ void k_hub_types(const uint8_t *__restrict__ ntype, int64_t n, int H, int Hw, int L,
                             uint64_t *__restrict__ TM) {
+    const int TP = tm_pitch(L);
     int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= L * Hw) return;
-    int t = idx / Hw, q = idx - t * Hw;
+    if (idx >= TP * Hw) return;
+    int q = idx / TP, t = idx - q * TP;
     uint64_t m = 0;
-    for (int b = 0; b < 64; ++b) {
-        int h = q * 64 + b;
-        if (h < H && ntype[n - H + h] == t) m |= 1ull << b;
-    }
+    if (t < L - 1)
+        for (int b = 0; b < 64; ++b) {
+            int h = q * 64 + b;
+            if (h < H && ntype[n - H + h] == t) m |= 1ull << b;
+        }
     TM[idx] = m;
 }
 
@@ -405,6 +409,7 @@ __device__ void edge_cliques(const EdgeArgs &a, int32_t i, int32_t j, const Edge
                              const uint64_t *TMs, const ScanScratch &F, int tid) {
     const int L = a.L;
     const int Hw = a.Hw;
+    const int TP = tm_pitch(L);
     const int32_t base = a.hub_base;
     const uint32_t nTl = S.meta[0], nTh = S.meta[1];
     // both endpoints super-hubs: low membership of T by two bitmap probes
@@ -487,11 +492,23 @@ __device__ void edge_cliques(const EdgeArgs &a, int32_t i, int32_t j, const Edge
                                     else if (word == (hk >> 6))
                                         v &= (hk & 63) == 63 ? 0ull : (~0ull << ((hk & 63) + 1));
                                     if (!v) continue;
+                                    // types 0..L-2 by their masks, type L-1 by
+                                    // what they leave
+                                    uint32_t rest = (uint32_t)__popcll(v);
+                                    const ulonglong2 *tw =
+                                        reinterpret_cast<const ulonglong2 *>(TMs + (size_t)word * TP);
+#pragma unroll
+                                    for (int t = 0; t < TG_MAX_L - 1; t += 2) {
+                                        if (t >= TP) break;
+                                        const ulonglong2 m2 = tw[t >> 1];
+                                        const uint32_t c0 = (uint32_t)__popcll(v & m2.x);
+                                        const uint32_t c1 = (uint32_t)__popcll(v & m2.y);
+                                        cnt[t >> 1] += c0 | (c1 << 16);
+                                        rest -= c0 + c1;
+                                    }
 #pragma unroll
                                     for (int t = 0; t < TG_MAX_L; ++t)
-                                        if (t < L)
-                                            cnt[t >> 1] += (uint32_t)__popcll(v & TMs[t * Hw + word])
-                                                           << (16 * (t & 1));
+                                        if (t == L - 1) cnt[t >> 1] += rest << (16 * (t & 1));
                                 }
                             }
                         }
@@ -522,9 +539,24 @@ __device__ void edge_cliques(const EdgeArgs &a, int32_t i, int32_t j, const Edge
                                 else if (word == (hk >> 6))
                                     v &= (hk & 63) == 63 ? 0ull : (~0ull << ((hk & 63) + 1));
                                 if (!v) continue;
+                                // types 0..L-2 by their masks, type L-1 by what
+                                // they leave
+                                uint32_t rest = (uint32_t)__popcll(v);
+                                const ulonglong2 *tw =
+                                    reinterpret_cast<const ulonglong2 *>(TMs + (size_t)word * TP);
+#pragma unroll
+                                for (int t = 0; t < TG_MAX_L - 1; t += 2) {
+                                    if (t >= TP) break;
+                                    const ulonglong2 m2 = tw[t >> 1];
+                                    const uint32_t c0 = (uint32_t)__popcll(v & m2.x);
+                                    const uint32_t c1 = (uint32_t)__popcll(v & m2.y);
+                                    cnt[t] += c0;
+                                    cnt[t + 1] += c1;
+                                    rest -= c0 + c1;
+                                }
 #pragma unroll
                                 for (int t = 0; t < TG_MAX_L; ++t)
-                                    if (t < L) cnt[t] += (uint32_t)__popcll(v & TMs[t * Hw + word]);
+                                    if (t == L - 1) cnt[t] += rest;
                             }
                         }
 #pragma unroll
@@ -894,14 +926,17 @@ __global__ void __launch_bounds__(EDGE_THREADS_HEAVY) k_edges_heavy(EdgeArgs a) 
     const int LL = a.L * a.L;
     uint64_t *hist;
     uint64_t *after = sm_edgeh + 4 * LL * a.derive_batch + hist_words(a) + a.Hw;
-    uint64_t *TMs = after;                        // type masks of the hub core
-    uint64_t *Gw = TMs + (size_t)a.L * a.Hw;      // per-wave gather copies
+    // type masks of the hub core, 16-byte aligned for their paired loads
+    uint64_t *TMs =
+        reinterpret_cast<uint64_t *>((reinterpret_cast<uintptr_t>(after) + 15) & ~uintptr_t(15));
+    const int TMw = tm_pitch(a.L) * a.Hw;
+    uint64_t *Gw = TMs + TMw;                     // per-wave gather copies
     uint32_t *Th = (uint32_t *)(Gw + (size_t)(NT / WAVE) * 3 * LL);
     uint32_t *Tl = a.tbuf + (size_t)blockIdx.x * (size_t)a.n;
     EdgeShared S = carve(a, sm_edgeh, meta, wave_cnt, &hist, Th, 1, Tl);
     S.Gw = Gw;
     int tid = threadIdx.x;
-    for (int q = tid; q < a.L * a.Hw; q += NT) TMs[q] = a.TM[q];
+    for (int q = tid; q < TMw; q += NT) TMs[q] = a.TM[q];
     uint32_t bad = 0;
     for (int q = tid; q < hist_words(a); q += NT) hist[q] = 0;
     uint64_t count = a.counters[C_EDGE_HEAVY];
@@ -982,7 +1017,9 @@ hipError_t launch_hub_build(const int64_t *nrp, const int32_t *ncol, const int64
     k_hub_rows<<<(unsigned)((H + 3) / 4), 256, sh, st>>>(nrp, ncol, hstart, n, H, Hw, HB, pre);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_hub_types<<<(unsigned)((L * Hw + 255) / 256), 256, 0, st>>>(ntype, n, H, Hw, L, TM);
+    if (tm_pitch(L) > 0)
+        k_hub_types<<<(unsigned)((tm_pitch(L) * Hw + 255) / 256), 256, 0, st>>>(ntype, n, H, Hw, L,
+                                                                              TM);
     return hipGetLastError();
 }
 
@@ -991,7 +1028,7 @@ size_t edge_lds_bytes(const EdgeArgs &args, bool heavy) {
     const int hw = args.hist_in_lds == 2 ? (args.gw + 1) / 2 : args.hist_in_lds ? args.gw : 0;
     size_t sh = (size_t)(4 * LL * args.derive_batch + hw + args.Hw) * sizeof(uint64_t);
     if (!heavy) sh += (size_t)args.tcap * sizeof(uint32_t);
-    else sh += (size_t)args.L * args.Hw * sizeof(uint64_t) +
+    else sh += (size_t)(tm_pitch(args.L) * args.Hw + 1) * sizeof(uint64_t) +
                (size_t)(EDGE_THREADS_HEAVY / WAVE) * 3 * LL * sizeof(uint64_t) +
                (size_t)(args.hub_base < args.n ? (args.n - args.hub_base) : 0) * sizeof(uint32_t);
     return sh;

@@ -143,7 +143,7 @@ struct EdgeArgs {
     const uint32_t *nlow;        // neighbours below the node itself, per node
     const uint64_t *HB;          // [H][Hw] hub adjacency bits
     const uint32_t *hpre;        // [H][Hw] exclusive prefix popcounts
-    const uint64_t *TM;          // [L][Hw] hubs of each type
+    const uint64_t *TM;          // [Hw][tm_pitch(L)] hubs of types 0..L-2 per word, zero padded
     // super-hubs: internal ids sh_base..n-1 with a bitmap over all nodes
     int32_t sh_base;
     int64_t nw;                  // 64-bit words per super-hub bitmap
@@ -194,6 +194,9 @@ hipError_t launch_hub_build(const int64_t *nrp, const int32_t *ncol, const int64
 // Row pitch (uint32 words) of per-slot typed triangle counts: L rounded up
 // to a multiple of 4, for 16-byte loads.
 __host__ __device__ inline int tri_pitch(int L) { return (L + 3) & ~3; }
+// Words per hub-core word in the type-mask table: masks of types 0..L-2
+// (the last type is what the others leave), padded to an even count.
+__host__ __device__ inline int tm_pitch(int L) { return L & ~1; }
 
 hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *ctype,
                       const int32_t *ei, const int32_t *ej, const uint32_t *eslot,
