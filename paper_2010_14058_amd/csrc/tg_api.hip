@@ -372,7 +372,6 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     ca.clear_bytes = (uint64_t)g_tune[TG_TUNE_CLEAR_BYTES];
     ca.nrp = nrp; ca.ncol = ncol; ca.ntype = ntype; ca.neid = neid; ca.ctype = ctype; ca.ei = ei;
     ca.counters = counters; ca.L = L; ca.n = n; ca.NC = NC; ca.maps = maps;
-    ca.chunk = heavy_chunk_for(L);
     ca.status = status;
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
@@ -390,6 +389,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
         ca.tasks = pass == 0 ? la_h : lb_h;
         ca.count_idx = pass == 0 ? C_A_HEAVY : C_B_HEAVY;
         ca.next_idx = pass == 0 ? C_A_NEXT : C_B_NEXT;
+        ca.chunk = heavy_chunk_for(L, pass == 0 ? HEAVY_THREADS_A : HEAVY_THREADS_B);
         HIPCHK(launch_cycles(pass, true, ca, (unsigned)y.heavy_slots, st));
         timing_mark(pass == 0 ? "cycA_heavy" : "cycB_heavy");
     }

@@ -26,8 +26,12 @@ enum : uint32_t {
 // Tunables of the cycle and clique passes.
 constexpr int LIGHT_HCAP = 1024;      // LDS hash slots per light group
 constexpr int64_t LIGHT_MAXW = 512;   // a group is light if it has at most this many wedges
-constexpr int HEAVY_THREADS = 256;    // threads of a heavy-group workgroup
-constexpr int HEAVY_CHUNK = 128;      // items staged per round in the heavy path
+// Threads of a heavy 4-cycle workgroup, per pass: pass A's maps are spread
+// over all ids, so fewer, larger workgroups (fewer maps sharing an XCD's L2)
+// pay; pass B's targets are compact.  A workgroup stages up to half as many
+// items per round as it has threads.
+constexpr int HEAVY_THREADS_A = 512;
+constexpr int HEAVY_THREADS_B = 256;
 constexpr int64_t TASK_WEDGES = 1 << 18;  // default wedges per heavy task (target range)
 constexpr int TASK_MAX_PARTS = 64;        // most target ranges per heavy group
 constexpr int64_t TASK_EXTRA = 1 << 16;   // task slots beyond one per node, shared by both passes
@@ -213,7 +217,7 @@ hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32
                            uint4 *la_h, uint32_t *lb_l, uint4 *lb_h, uint64_t *counters,
                            uint64_t task_wedges, int L, uint64_t range_bytes,
                            uint64_t light_max, hipStream_t st);
-int heavy_chunk_for(int L);
+int heavy_chunk_for(int L, int threads);
 hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned grid, hipStream_t st);
 hipError_t launch_edges(bool heavy, const EdgeArgs &args, unsigned grid, hipStream_t st);
 hipError_t launch_derive(const EdgeArgs &args, unsigned grid, hipStream_t st);

@@ -586,8 +586,9 @@ __global__ void __launch_bounds__(64) k_cyc_light(CycleArgs a) {
     }
 }
 
-// Block-wide inclusive scan of up to HEAVY_CHUNK values held by threads
-// [0, HEAVY_CHUNK); result in s[0..HEAVY_CHUNK).
+// Block-wide inclusive scan of up to NT/2 values held by threads [0, NT/2);
+// result in s[0..NT/2).
+template <int NT>
 __device__ __forceinline__ void block_scan_chunk(uint32_t v, uint32_t *s, uint32_t *wave_tot) {
     int tid = threadIdx.x;
     int w = tid / WAVE;
@@ -596,7 +597,7 @@ __device__ __forceinline__ void block_scan_chunk(uint32_t v, uint32_t *s, uint32
     __syncthreads();
     uint32_t add = 0;
     for (int q = 0; q < w; ++q) add += wave_tot[q];
-    if (tid < HEAVY_CHUNK) s[tid] = incl + add;
+    if (tid < NT / 2) s[tid] = incl + add;
     __syncthreads();
 }
 
@@ -633,8 +634,10 @@ __device__ __forceinline__ int32_t range_cut(const int64_t *nrp, int32_t rb, int
 // (a count never exceeds the item count).  The entries of the range are
 // cleared by streaming zeros over the range when that is cheaper than a walk
 // over the wedges; then a count walk and an emit walk.
-template <int PASS>
-__global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
+template <int PASS, int NT>
+__global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
+    constexpr int HEAVY_THREADS = NT;
+    constexpr int HEAVY_CHUNK = NT / 2;
     extern __shared__ uint64_t sm_heavy[];
     const int L = a.L;
     const int LL = L * L;
@@ -722,7 +725,7 @@ __global__ void __launch_bounds__(HEAVY_THREADS) k_cyc_heavy(CycleArgs a) {
                     it_eid[tid] = e;
                     it_flip[tid] = orient_flip<PASS>(a, g, x, e);
                 }
-                block_scan_chunk(len, it_scan, wave_tot);
+                block_scan_chunk<NT>(len, it_scan, wave_tot);
                 uint32_t total = it_scan[nitems - 1];
                 if (phase == 2) {
                     for (int q = tid; q < nitems * LL; q += HEAVY_THREADS) acc[q] = 0;
@@ -1084,9 +1087,13 @@ hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32
     return hipSuccess;
 }
 
-int heavy_chunk_for(int L) {
-    int ch = 32768 / (L * L * 8);
-    if (ch > HEAVY_CHUNK) ch = HEAVY_CHUNK;
+// Items per staging round: at most threads / 2, with LDS accumulators of
+// L^2 words per item within 32 KB (256 threads) or 50 KB (512 threads), so
+// a workgroup stays under 64 KB of LDS for every L.
+int heavy_chunk_for(int L, int threads) {
+    const int budget = threads >= 512 ? 51200 : 32768;
+    int ch = budget / (L * L * 8);
+    if (ch > threads / 2) ch = threads / 2;
     if (ch < 1) ch = 1;
     return ch;
 }
@@ -1099,8 +1106,8 @@ hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned g
         else k_cyc_light<1><<<grid, 64, sh, st>>>(args);
     } else {
         size_t sh = (size_t)args.chunk * args.L * args.L * sizeof(uint64_t);
-        if (pass == 0) k_cyc_heavy<0><<<grid, HEAVY_THREADS, sh, st>>>(args);
-        else k_cyc_heavy<1><<<grid, HEAVY_THREADS, sh, st>>>(args);
+        if (pass == 0) k_cyc_heavy<0, HEAVY_THREADS_A><<<grid, HEAVY_THREADS_A, sh, st>>>(args);
+        else k_cyc_heavy<1, HEAVY_THREADS_B><<<grid, HEAVY_THREADS_B, sh, st>>>(args);
     }
     LAUNCH_CHECK();
     return hipSuccess;
