@@ -30,7 +30,7 @@ constexpr int64_t LIGHT_MAXW = 512;   // a group is light if it has at most this
 // over all ids, so fewer, larger workgroups (fewer maps sharing an XCD's L2)
 // pay; pass B's targets are compact.  A workgroup stages up to half as many
 // items per round as it has threads.
-constexpr int HEAVY_THREADS_A = 512;
+constexpr int HEAVY_THREADS_A = 1024;
 constexpr int HEAVY_THREADS_B = 256;
 constexpr int64_t TASK_WEDGES = 1 << 18;  // default wedges per heavy task (target range)
 constexpr int TASK_MAX_PARTS = 64;        // most target ranges per heavy group
