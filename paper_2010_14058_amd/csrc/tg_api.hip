@@ -352,8 +352,8 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     timing_mark("prep");
 
     // ---- typed triangles and node aggregates
-    HIPCHK(launch_tri(nrp, ncol, ctype, ei, ej, eslot, tri_slot, m, L, tri, counters + C_TRI_SUM, sh_base, nw, SB,
-                      st));
+    HIPCHK(launch_tri(nrp, ncol, ctype, ei, ej, eslot, tri_slot, m, L, tri, counters + C_TRI_SUM,
+                      sh_base, nw, SB, hub_base, Hw, HB, st));
     timing_mark("tri");
     HIPCHK(launch_node_aggr(nrp, ncol, ctype, tri_slot, tdeg, n, L, A, D, st));
     timing_mark("aggr");

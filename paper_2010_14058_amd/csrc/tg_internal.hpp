@@ -206,7 +206,7 @@ hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *ct
                       const int32_t *ei, const int32_t *ej, const uint32_t *eslot,
                       uint32_t *tri_slot, int64_t m, int L, uint32_t *tri,
                       uint64_t *tri_sum, int32_t sh_base, int64_t nw, const uint64_t *SB,
-                      hipStream_t st);
+                      int32_t hub_base, int Hw, const uint64_t *HB, hipStream_t st);
 hipError_t launch_superhubs(const int64_t *nrp, const int32_t *ncol, int64_t n, int S, int64_t nw,
                             uint64_t *SB, uint32_t *SP, hipStream_t st);
 hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8_t *ctype,

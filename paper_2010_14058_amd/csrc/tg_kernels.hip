@@ -263,8 +263,9 @@ __global__ void k_tdeg(const int64_t *__restrict__ nrp, const int32_t *__restric
 
 // Typed triangles: a wave takes TRI_GROUPS consecutive edges, one group of
 // WAVE/TRI_GROUPS lanes per edge; a group walks the shorter row and tests each
-// node against the longer one (its super-hub bitmap when it has one, else a
-// binary search), counting hits by type.
+// node against the longer one (its super-hub bitmap when it has one, the
+// hub-core bit matrix when both are hubs, else a binary search), counting
+// hits by type.
 constexpr int TRI_GROUPS = 8;
 constexpr int TRI_LANES = WAVE / TRI_GROUPS;
 
@@ -273,7 +274,8 @@ __global__ void k_tri(const int64_t *__restrict__ nrp, const int32_t *__restrict
                       const int32_t *__restrict__ ej, const uint32_t *__restrict__ eslot,
                       uint32_t *__restrict__ tri_slot, int64_t m, int L,
                       uint32_t *__restrict__ tri, uint64_t *__restrict__ tri_sum, int32_t sh_base,
-                      int64_t nw, const uint64_t *__restrict__ SB) {
+                      int64_t nw, const uint64_t *__restrict__ SB, int32_t hub_base, int Hw,
+                      const uint64_t *__restrict__ HB) {
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
     const int lane = lane_id();
@@ -297,11 +299,17 @@ __global__ void k_tri(const int64_t *__restrict__ nrp, const int32_t *__restrict
             }
             const bool probe = big >= sh_base;
             const int sidx = big - sh_base;
+            const bool big_hub = big >= hub_base;
+            const uint64_t *hrow = big_hub ? HB + (size_t)(big - hub_base) * Hw : nullptr;
             for (int64_t s = sb + gl; s < se; s += TRI_LANES) {
                 int32_t x = ncol[s];
                 bool found;
                 if (probe) {
                     found = sh_bit(SB, nw, sidx, x);
+                } else if (big_hub && x >= hub_base) {
+                    // both in the hub core: its bit matrix
+                    const int hx = x - hub_base;
+                    found = (hrow[hx >> 6] >> (hx & 63)) & 1ull;
                 } else {
                     int64_t q = lower_bound(ncol, bb, be, x);
                     found = q < be && ncol[q] == x;
@@ -1049,10 +1057,11 @@ hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *ct
                       const int32_t *ei, const int32_t *ej, const uint32_t *eslot,
                       uint32_t *tri_slot, int64_t m, int L, uint32_t *tri,
                       uint64_t *tri_sum, int32_t sh_base, int64_t nw, const uint64_t *SB,
-                      hipStream_t st) {
+                      int32_t hub_base, int Hw, const uint64_t *HB, hipStream_t st) {
     if (m == 0) return hipSuccess;
     k_tri<<<blocks_bounded(m, 4 * TRI_GROUPS, 32), 256, 0, st>>>(
-        nrp, ncol, ctype, ei, ej, eslot, tri_slot, m, L, tri, tri_sum, sh_base, nw, SB);
+        nrp, ncol, ctype, ei, ej, eslot, tri_slot, m, L, tri, tri_sum, sh_base, nw, SB, hub_base,
+        Hw, HB);
     LAUNCH_CHECK();
     return hipSuccess;
 }
