@@ -373,6 +373,8 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     ca.nrp = nrp; ca.ncol = ncol; ca.ntype = ntype; ca.neid = neid; ca.ctype = ctype; ca.ei = ei;
     ca.counters = counters; ca.L = L; ca.n = n; ca.NC = NC; ca.maps = maps;
     ca.status = status;
+    ca.deg_sorted = graph_major ? 0 : 1;
+    ca.max_deg = max_deg;
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     int cus = 0;

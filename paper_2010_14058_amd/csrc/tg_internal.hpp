@@ -112,6 +112,8 @@ struct CycleArgs {
     uint32_t *maps;
     int chunk;
     uint32_t *status;
+    int deg_sorted;            // node ids ranked by degree (not the graph-major batch order)
+    int64_t max_deg;           // largest degree (or a bound)
 };
 
 // Arguments of the per-edge clique / derivation kernels.

@@ -632,6 +632,58 @@ __device__ __forceinline__ int32_t range_cut(const int64_t *nrp, int32_t rb, int
     return lo;
 }
 
+// Map entries by target degree class.  The count of centres of one type at
+// target w never exceeds w's degree, so targets of degree < 16 keep 4-bit
+// counts, < 256 8-bit, < 65536 16-bit and the rest 32-bit.  With ids ranked
+// by degree each class is one id range; the classes are laid out one after
+// the other (class c: ids [start[c], start[c+1]), class_words(c) words per
+// id, from word off[c]), so a task's entries are one contiguous word range.
+struct MapClasses {
+    int32_t s1, s2, s3;         // first ids of classes 1..3 (class 0 starts at 0)
+    uint64_t o1, o2, o3;        // their first words
+};
+
+__device__ __forceinline__ int class_words(int c, int L) { return (L * (4 << c) + 31) >> 5; }
+
+__device__ __forceinline__ int map_class(const MapClasses &m, int32_t w) {
+    return (w >= m.s1) + (w >= m.s2) + (w >= m.s3);
+}
+
+// First word of target w's entry (w may be n: the end of the layout).
+__device__ __forceinline__ uint64_t map_word(const MapClasses &m, int32_t w, int c, int L) {
+    const int32_t st = c == 0 ? 0 : c == 1 ? m.s1 : c == 2 ? m.s2 : m.s3;
+    const uint64_t of = c == 0 ? 0ull : c == 1 ? m.o1 : c == 2 ? m.o2 : m.o3;
+    return of + (uint64_t)(w - st) * (uint64_t)class_words(c, L);
+}
+
+// First node id of degree >= d (degrees nondecreasing in id).
+__device__ __forceinline__ int32_t first_of_degree(const int64_t *nrp, int64_t n, int64_t d) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (nrp[mid + 1] - nrp[mid] < d) lo = mid + 1; else hi = mid;
+    }
+    return (int32_t)lo;
+}
+
+__device__ MapClasses map_classes(const CycleArgs &a) {
+    MapClasses m;
+    const int32_t n = (int32_t)a.n;
+    if (a.deg_sorted) {
+        m.s1 = first_of_degree(a.nrp, a.n, 16);
+        m.s2 = first_of_degree(a.nrp, a.n, 256);
+        m.s3 = first_of_degree(a.nrp, a.n, 65536);
+    } else {
+        // degrees are not ordered by id: one class for every id
+        m.s1 = m.s2 = 0;
+        m.s3 = a.max_deg >= 65536 ? 0 : n;
+    }
+    m.o1 = (uint64_t)m.s1 * class_words(0, a.L);
+    m.o2 = m.o1 + (uint64_t)(m.s2 - m.s1) * class_words(1, a.L);
+    m.o3 = m.o2 + (uint64_t)(m.s3 - m.s2) * class_words(2, a.L);
+    return m;
+}
+
 // Heavy tasks: one 256-thread workgroup per task, pulled from a queue.  A
 // task is a heavy group restricted to one range of target ids; a group with
 // many wedges is split into ranges of about equal adjacency mass (targets are
@@ -658,9 +710,12 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
     __shared__ int it_flip[HEAVY_CHUNK];
     __shared__ uint32_t wave_tot[HEAVY_THREADS / WAVE];
     __shared__ int32_t s_task[4];  // group, first target, end target, streamed clear
+    __shared__ MapClasses s_mc;
     int tid = threadIdx.x;
     uint32_t *map = a.maps + (size_t)blockIdx.x * (size_t)a.n * L;
     uint64_t count = a.counters[a.count_idx];
+    if (tid == 0) s_mc = map_classes(a);
+    __syncthreads();
     while (true) {
         if (tid == 0) {
             uint64_t idx = atomicAdd((unsigned long long *)&a.counters[a.next_idx], 1ull);
@@ -678,13 +733,14 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
                     lo = range_cut(a.nrp, rb, re, tk.y, tk.z);
                     hi = range_cut(a.nrp, rb, re, tk.y + 1, tk.z);
                 }
-                int64_t nitem = PASS == 0 ? (int64_t)a.nlow[g] : a.nrp[g + 1] - a.nrp[g];
-                int ew = nitem < 65536 ? (L + 1) / 2 : L;
+                const MapClasses mc = s_mc;
+                const uint64_t w0 = map_word(mc, lo, map_class(mc, lo), L);
+                const uint64_t w1 = map_word(mc, hi, map_class(mc, hi), L);
                 uint64_t wt = tk.w / tk.z;
                 s_task[0] = g;
                 s_task[1] = lo;
                 s_task[2] = hi;
-                s_task[3] = (uint64_t)(hi - lo) * ew * 4 <= wt * a.clear_bytes ? 1 : 0;
+                s_task[3] = (w1 - w0) * 4 <= wt * a.clear_bytes ? 1 : 0;
             }
         }
         __syncthreads();
@@ -696,12 +752,12 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
         if (g < 0) break;
         int64_t ib, ie;
         item_range<PASS>(a, g, ib, ie);
-        const bool narrow = ie - ib < 65536;
-        const int EW = narrow ? (L + 1) / 2 : L;
+        const MapClasses mc = s_mc;
         if (hi <= lo) continue;
         if (streamed) {
-            uint32_t *p0 = map + (size_t)lo * EW;
-            size_t cnt = (size_t)(hi - lo) * EW;
+            const uint64_t w0 = map_word(mc, lo, map_class(mc, lo), L);
+            uint32_t *p0 = map + w0;
+            size_t cnt = (size_t)(map_word(mc, hi, map_class(mc, hi), L) - w0);
             size_t head = ((16 - ((uintptr_t)p0 & 15)) & 15) / 4;
             if (head > cnt) head = cnt;
             if ((size_t)tid < head) p0[tid] = 0u;
@@ -745,37 +801,39 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
                     uint32_t excl = o ? it_scan[o - 1] : 0;
                     const int tx = it_tx[o];
                     const int64_t ys = it_tb[o] + (f - excl);
-                    uint32_t y = (uint32_t)a.ncol[ys];
-                    uint32_t *my = map + (size_t)y * EW;
+                    const int32_t y = a.ncol[ys];
+                    const int cls = map_class(mc, y);
+                    const int bits = 4 << cls;
+                    uint32_t *my = map + map_word(mc, y, cls, L);
                     if (phase == 0) {
-                        for (int t = 0; t < EW; ++t) my[t] = 0u;
+                        const int ew = class_words(cls, L);
+                        for (int q = 0; q < ew; ++q) my[q] = 0u;
                     } else if (phase == 1) {
                         // the map is private to this workgroup: workgroup scope
                         // keeps the update in the XCD's L2
-                        if (narrow)
-                            __hip_atomic_fetch_add(&my[tx >> 1], 1u << ((tx & 1) * 16),
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        else
-                            __hip_atomic_fetch_add(&my[tx], 1u, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                        const int bit = tx * bits;
+                        __hip_atomic_fetch_add(&my[bit >> 5], 1u << (bit & 31), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
                     } else {
                         int ty = a.ctype[ys];
                         uint64_t *ac = acc + (size_t)o * LL;
-                        // one load per map word: two 16-bit counts a word when
-                        // narrow (atomic loads are not merged by the compiler)
-                        for (int w = 0; w < EW; ++w) {
-                            const uint32_t word = __hip_atomic_load(
-                                &my[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                            for (int h = 0; h < (narrow ? 2 : 1); ++h) {
-                                const int t = narrow ? 2 * w + h : w;
-                                if (t >= L) break;
-                                const uint32_t c = narrow ? (word >> (16 * h)) & 0xffffu : word;
-                                const uint32_t val = c - (t == tx ? 1u : 0u);
-                                if (val)
-                                    atomicAdd(
-                                        (unsigned long long *)&ac[pass_entry<PASS>(t, ty, L)],
-                                        (unsigned long long)val);
+                        // one load per map word (atomic loads are not merged by
+                        // the compiler), the counts of its types extracted
+                        const uint32_t mask = bits == 32 ? 0xffffffffu : (1u << bits) - 1u;
+                        int wq = -1;
+                        uint32_t word = 0;
+                        for (int t = 0; t < L; ++t) {
+                            const int bit = t * bits;
+                            if ((bit >> 5) != wq) {
+                                wq = bit >> 5;
+                                word = __hip_atomic_load(&my[wq], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
                             }
+                            const uint32_t c = (word >> (bit & 31)) & mask;
+                            const uint32_t val = c - (t == tx ? 1u : 0u);
+                            if (val)
+                                atomicAdd((unsigned long long *)&ac[pass_entry<PASS>(t, ty, L)],
+                                          (unsigned long long)val);
                         }
                     }
                 }
