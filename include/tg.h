@@ -185,7 +185,7 @@ const char *tg_last_error(void);
  *   TG_TUNE_CLEAR_BYTES  (default 64, >= 0): a task clears its map range by
  *       streaming zeros when the range costs at most this many bytes per
  *       wedge of the task, else by a walk over its wedges; 0 never streams.
- *   TG_TUNE_CYCLE_SLOTS  (default 1024, 1..65536): most workgroups of the heavy
+ *   TG_TUNE_CYCLE_SLOTS  (default 2048, 1..65536): most workgroups of the heavy
  *       4-cycle kernels; each owns a dense map of n*L*4 bytes of workspace.
  *   TG_TUNE_MAP_BYTES    (default 32 GiB, >= 1): workspace bytes for those
  *       maps; the slot count is cut to fit (at least one slot).
