@@ -684,16 +684,15 @@ __device__ MapClasses map_classes(const CycleArgs &a) {
     return m;
 }
 
-// Heavy tasks: one 256-thread workgroup per task, pulled from a queue.  A
+// Heavy tasks: one NT-thread workgroup per task, pulled from a queue.  A
 // task is a heavy group restricted to one range of target ids; a group with
 // many wedges is split into ranges of about equal adjacency mass (targets are
 // met in proportion to their degree), so its work spreads over workgroups and
 // each range has every wedge that reaches its targets.  The map is a dense
-// uint32 array private to the workgroup, indexed by target: L 32-bit counts
-// per target, or L 16-bit counts when the group has fewer than 2^16 items
-// (a count never exceeds the item count).  The entries of the range are
-// cleared by streaming zeros over the range when that is cheaper than a walk
-// over the wedges; then a count walk and an emit walk.
+// uint32 array private to the workgroup, indexed by target, with L counts per
+// target sized by the target's degree class (above).  The entries of the
+// range are cleared by streaming zeros over its word range when that is
+// cheaper than a walk over the wedges; then a count walk and an emit walk.
 template <int PASS, int NT>
 __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
     constexpr int HEAVY_THREADS = NT;
@@ -859,11 +858,9 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
     }
 }
 
-// Bytes of one target's entry in a heavy group's map: L 16-bit counts when
-// the group has fewer than 2^16 items, else L 32-bit counts.
-__device__ __forceinline__ uint64_t map_bytes_per_id(int64_t items, int L) {
-    return items < 65536 ? (uint64_t)((L + 1) / 2) * 4 : (uint64_t)L * 4;
-}
+// Bytes of one target's map entry assumed by the id-range splits (the
+// 16-bit class; targets of smaller degree take less, of degree >= 2^16 more).
+__device__ __forceinline__ uint64_t map_bytes_per_id(int L) { return (uint64_t)((L + 1) / 2) * 4; }
 
 // Wave-wide list appends of the groups found by the lanes of a wave (one
 // counter update per wave and list).  Every lane of the wave calls this with
@@ -981,14 +978,12 @@ __global__ void __launch_bounds__(256) k_cyc_work(
         if (v < thr)
             for (int64_t s = nrp[v]; s < nrp[v + 1]; ++s)
                 node_wedges(nrp, ncol, neid, eslot, nlow, (int32_t)v, s, wa, wb);
-        const int64_t nl = v < thr ? (int64_t)nlow[v] : 0;
-        const int64_t dg = v < thr ? nrp[v + 1] - nrp[v] : 0;
         push_groups((int32_t)v, wa, listA_light, listA_heavy, counters, C_A_LIGHT, C_A_HEAVY,
                     C_WEDGES_A, C_WEDGES_A_HEAVY, task_wedges, v,
-                    map_bytes_per_id(nl, L), range_bytes, light_max);
+                    map_bytes_per_id(L), range_bytes, light_max);
         push_groups((int32_t)v, wb, listB_light, listB_heavy, counters, C_B_LIGHT, C_B_HEAVY,
                     C_WEDGES_B, C_WEDGES_B_HEAVY, task_wedges, n - 1 - v,
-                    map_bytes_per_id(dg, L), range_bytes, light_max);
+                    map_bytes_per_id(L), range_bytes, light_max);
     }
     for (int64_t v = thr + wid; v < n; v += nwaves) {
         uint64_t wa = 0, wb = 0;
@@ -996,13 +991,12 @@ __global__ void __launch_bounds__(256) k_cyc_work(
             node_wedges(nrp, ncol, neid, eslot, nlow, (int32_t)v, s, wa, wb);
         wa = wave_sum_u64(wa);
         wb = wave_sum_u64(wb);
-        const int64_t nl = (int64_t)nlow[v], dg = nrp[v + 1] - nrp[v];
         push_groups((int32_t)v, lane == 0 ? wa : 0ull, listA_light, listA_heavy, counters,
                     C_A_LIGHT, C_A_HEAVY, C_WEDGES_A, C_WEDGES_A_HEAVY, task_wedges, v,
-                    map_bytes_per_id(nl, L), range_bytes, light_max);
+                    map_bytes_per_id(L), range_bytes, light_max);
         push_groups((int32_t)v, lane == 0 ? wb : 0ull, listB_light, listB_heavy, counters,
                     C_B_LIGHT, C_B_HEAVY, C_WEDGES_B, C_WEDGES_B_HEAVY, task_wedges, n - 1 - v,
-                    map_bytes_per_id(dg, L), range_bytes, light_max);
+                    map_bytes_per_id(L), range_bytes, light_max);
     }
 }
 
