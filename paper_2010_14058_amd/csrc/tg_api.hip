@@ -374,6 +374,12 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     ca.nrp = nrp; ca.ncol = ncol; ca.ntype = ntype; ca.neid = neid; ca.ctype = ctype; ca.ei = ei;
     ca.counters = counters; ca.L = L; ca.n = n; ca.NC = NC; ca.maps = maps;
     ca.status = status;
+    {
+        // hash slots: the smallest power of two above the light bucket
+        int lg = 1;
+        while ((int64_t(1) << lg) <= g_tune[TG_TUNE_LIGHT_WEDGES]) ++lg;
+        ca.light_log2 = lg;
+    }
     ca.deg_sorted = graph_major ? 0 : 1;
     ca.max_deg = max_deg;
     int dev = 0;

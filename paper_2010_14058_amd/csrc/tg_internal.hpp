@@ -24,7 +24,6 @@ enum : uint32_t {
 };
 
 // Tunables of the cycle and clique passes.
-constexpr int LIGHT_HCAP = 1024;      // LDS hash slots per light group
 constexpr int64_t LIGHT_MAXW = 512;   // a group is light if it has at most this many wedges
 // Threads of a heavy 4-cycle workgroup, per pass: pass A's maps are spread
 // over all ids, so fewer, larger workgroups (fewer maps sharing an XCD's L2)
@@ -112,6 +111,7 @@ struct CycleArgs {
     uint32_t *maps;
     int chunk;
     uint32_t *status;
+    int light_log2;            // log2 of the light kernel's hash slots (> light bucket)
     int deg_sorted;            // node ids ranked by degree (not the graph-major batch order)
     int64_t max_deg;           // largest degree (or a bound)
 };

@@ -492,20 +492,25 @@ __device__ __forceinline__ int pass_entry(int t, int ty, int L) {
 
 constexpr uint32_t EMPTY_KEY = 0xffffffffu;
 
-__device__ __forceinline__ int hash_slot(uint32_t y) {
-    return (int)((y * 0x9E3779B1u) >> (32 - 10));  // LIGHT_HCAP = 1024
+__device__ __forceinline__ int hash_slot(uint32_t y, int log2_slots) {
+    return (int)((y * 0x9E3779B1u) >> (32 - log2_slots));
 }
 
 // Light groups: one 64-thread workgroup per group, LDS open-addressing map
 // keyed by target with 16-bit counters per type (group wedges at most the
-// light bucket bound, itself at most LIGHT_MAXW).
+// light bucket bound, itself at most LIGHT_MAXW); the map has the smallest
+// power-of-two slot count above that bound, so smaller buckets take less LDS
+// and fit more workgroups on a CU.
 template <int PASS>
 __global__ void __launch_bounds__(64) k_cyc_light(CycleArgs a) {
     extern __shared__ uint32_t sm_light[];
     const int L = a.L;
     const int LW = (L + 1) / 2;
     uint32_t *keys = sm_light;
-    uint32_t *cnt = keys + LIGHT_HCAP;
+    // slots: the smallest power of two above the light bucket, so a group's
+    // distinct targets (at most its wedges) always find a free slot
+    const int HC = 1 << a.light_log2;
+    uint32_t *cnt = keys + HC;
     __shared__ int32_t it_tx[WAVE];  // type of each staged item (the centre)
     __shared__ int64_t it_tb[WAVE];
     __shared__ uint32_t it_scan[WAVE];
@@ -513,8 +518,8 @@ __global__ void __launch_bounds__(64) k_cyc_light(CycleArgs a) {
     __shared__ int it_flip[WAVE];
     int lane = threadIdx.x;
     uint64_t count = a.counters[a.count_idx];
-    for (int q = lane; q < LIGHT_HCAP; q += WAVE) keys[q] = EMPTY_KEY;
-    for (int q = lane; q < LIGHT_HCAP * LW; q += WAVE) cnt[q] = 0;
+    for (int q = lane; q < HC; q += WAVE) keys[q] = EMPTY_KEY;
+    for (int q = lane; q < HC * LW; q += WAVE) cnt[q] = 0;
     __syncthreads();
     for (uint64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
         int32_t g = (int32_t)a.list[idx];
@@ -547,25 +552,25 @@ __global__ void __launch_bounds__(64) k_cyc_light(CycleArgs a) {
                     const int tx = it_tx[o];
                     const int64_t ys = it_tb[o] + (f - excl);
                     uint32_t y = (uint32_t)a.ncol[ys];
-                    int h = hash_slot(y);
+                    int h = hash_slot(y, a.light_log2);
                     if (phase == 0) {
-                        // the group has at most LIGHT_MAXW < LIGHT_HCAP distinct keys
-                        // so the probe ends; the bound only guards corrupted input
+                        // the group has fewer distinct keys than slots, so the
+                        // probe ends; the bound only guards corrupted input
                         bool ok = false;
-                        for (int probe = 0; probe < LIGHT_HCAP; ++probe) {
+                        for (int probe = 0; probe < HC; ++probe) {
                             uint32_t old = atomicCAS(&keys[h], EMPTY_KEY, y);
                             if (old == EMPTY_KEY || old == y) { ok = true; break; }
-                            h = (h + 1) & (LIGHT_HCAP - 1);
+                            h = (h + 1) & (HC - 1);
                         }
                         if (ok) atomicAdd(&cnt[h * LW + (tx >> 1)], 1u << ((tx & 1) * 16));
                         else atomicOr(a.status, ST_INTERNAL);
                     } else {
                         int probe = 0;
-                        while (keys[h] != y && probe < LIGHT_HCAP) {
-                            h = (h + 1) & (LIGHT_HCAP - 1);
+                        while (keys[h] != y && probe < HC) {
+                            h = (h + 1) & (HC - 1);
                             ++probe;
                         }
-                        if (probe == LIGHT_HCAP) {
+                        if (probe == HC) {
                             atomicOr(a.status, ST_INTERNAL);
                             continue;
                         }
@@ -588,8 +593,8 @@ __global__ void __launch_bounds__(64) k_cyc_light(CycleArgs a) {
                 __syncthreads();
             }
         }
-        for (int q = lane; q < LIGHT_HCAP; q += WAVE) keys[q] = EMPTY_KEY;
-        for (int q = lane; q < LIGHT_HCAP * LW; q += WAVE) cnt[q] = 0;
+        for (int q = lane; q < HC; q += WAVE) keys[q] = EMPTY_KEY;
+        for (int q = lane; q < HC * LW; q += WAVE) cnt[q] = 0;
         __syncthreads();
     }
 }
@@ -1162,7 +1167,7 @@ int heavy_chunk_for(int L, int threads) {
 hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned grid, hipStream_t st) {
     if (grid == 0) return hipSuccess;
     if (!heavy) {
-        size_t sh = (size_t)LIGHT_HCAP * (1 + (args.L + 1) / 2) * sizeof(uint32_t);
+        size_t sh = ((size_t)1 << args.light_log2) * (1 + (args.L + 1) / 2) * sizeof(uint32_t);
         if (pass == 0) k_cyc_light<0><<<grid, 64, sh, st>>>(args);
         else k_cyc_light<1><<<grid, 64, sh, st>>>(args);
     } else {
