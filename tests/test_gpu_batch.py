@@ -128,3 +128,59 @@ def test_batch_invalid_inputs():
     assert _batch_status(rp, col, [0, 1, 0, 1], [0, 2, 3], [2, 2]) == 9
     # a type outside its graph's range (graph 1 has L = 1)
     assert _batch_status(rp, col, [0, 1, 0, 1], [0, 2, 4], [2, 1]) == 3
+
+
+def _union(parts, L_max):
+    offs = np.cumsum([0] + [p.n for p in parts])
+    rp = [np.zeros(1, np.int64)]
+    cols, types = [], []
+    base = 0
+    for p, o in zip(parts, offs[:-1]):
+        rp.append(p.row_ptr[1:] + base)
+        base += p.nnz
+        cols.append(p.col + o)
+        types.append(p.types)
+    u = G.Graph(np.concatenate(rp), np.concatenate(cols).astype(np.int32),
+                np.concatenate(types), L_max, "mix")
+    return G.GraphBatch(u, offs.astype(np.int64), np.array([p.L for p in parts], np.int32))
+
+
+def test_batch_with_degree_above_16_bits():
+    """A batch whose first graph has a node of degree 70000: the batch is
+    relabelled graph by graph (node ids not ranked by degree), so every
+    4-cycle map entry takes 32-bit counts, with every group sent to the
+    heavy path; each graph's vector equals its single-graph call."""
+    import torch
+
+    import paper_2010_14058_amd as P
+    from gpu_util import run_gpu
+
+    rng = np.random.default_rng(13)
+    leaves = 70_000
+    n = leaves + 2
+    a = [np.zeros(leaves, np.int64), np.full(leaves // 4, 1, np.int64)]
+    b = [np.arange(2, n, dtype=np.int64), rng.choice(np.arange(2, n), leaves // 4, replace=False)]
+    extra = rng.integers(2, n, size=(60_000, 2))
+    extra = extra[extra[:, 0] != extra[:, 1]]
+    u = np.concatenate(a + [extra[:, 0], np.array([0])])
+    v = np.concatenate(b + [extra[:, 1], np.array([1])])
+    e = np.unique(np.sort(np.stack([u, v], 1), axis=1), axis=0)
+    rp, col = G.csr_from_edges(n, e[:, 0], e[:, 1])
+    hub = G.Graph(rp, col, rng.integers(0, 3, size=n).astype(np.uint8), 3, "hub70k_batch")
+    assert hub.degrees().max() > 65535
+    parts = [hub, G.random_small_graph(15, 0.4, 3, 5), G.chung_lu_typed(800, 8.0, 2.1, 90.0, 3,
+                                                                        seed=6)]
+    bt = _union(parts, 3)
+    old = P.set_tuning(light_wedges=1)
+    try:
+        print(f"[gpu] batch with a 70k hub: n={bt.union.n} m={bt.union.m}", flush=True)
+        plan = _plan(bt)
+        glob, _ = P.count_batch(plan)
+        torch.cuda.synchronize()
+        glob = glob.cpu().numpy().view(np.uint64)
+        assert P.last_stats()["heavy_groups"] > 0
+        for g, p in enumerate(parts):
+            _, single = run_gpu(p, per_edge=False)
+            np.testing.assert_array_equal(glob[plan.goff_host[g]:plan.goff_host[g + 1]], single)
+    finally:
+        P.set_tuning(**old)
