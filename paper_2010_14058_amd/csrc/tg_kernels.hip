@@ -639,25 +639,45 @@ __device__ __forceinline__ int32_t range_cut(const int64_t *nrp, int32_t rb, int
 
 // Map entries by target degree class.  The count of centres of one type at
 // target w never exceeds w's degree, so targets of degree < 16 keep 4-bit
-// counts, < 256 8-bit, < 65536 16-bit and the rest 32-bit.  With ids ranked
-// by degree each class is one id range; the classes are laid out one after
-// the other (class c: ids [start[c], start[c+1]), class_words(c) words per
-// id, from word off[c]), so a task's entries are one contiguous word range.
+// counts, < 64 6-bit, < 256 8-bit, < 1024 10-bit, < 65536 16-bit and the
+// rest 32-bit.  A word holds F = 32 / bits fields (none crosses a word), so
+// an entry takes ceil(L / F) words.  With ids ranked by degree each class is
+// one id range; the classes are laid out one after the other (class c: ids
+// [s[c], s[c+1]) from word o[c]), so a task's entries are one contiguous word
+// range.
+constexpr int MAP_CLASSES = 6;
+
 struct MapClasses {
-    int32_t s1, s2, s3;         // first ids of classes 1..3 (class 0 starts at 0)
-    uint64_t o1, o2, o3;        // their first words
+    int32_t s[MAP_CLASSES];     // first id of each class (s[0] = 0)
+    uint64_t o[MAP_CLASSES];    // first word of each class
 };
 
-__device__ __forceinline__ int class_words(int c, int L) { return (L * (4 << c) + 31) >> 5; }
-
-__device__ __forceinline__ int map_class(const MapClasses &m, int32_t w) {
-    return (w >= m.s1) + (w >= m.s2) + (w >= m.s3);
+__device__ __forceinline__ int class_bits(int c) {
+    return c == 0 ? 4 : c == 1 ? 6 : c == 2 ? 8 : c == 3 ? 10 : c == 4 ? 16 : 32;
 }
 
-// First word of target w's entry (w may be n: the end of the layout).
+__device__ __forceinline__ int class_words(int c, int L) {
+    const int F = 32 / class_bits(c);
+    return (L + F - 1) / F;
+}
+
+__device__ __forceinline__ int map_class(const MapClasses &m, int32_t w) {
+    int c = 0;
+#pragma unroll
+    for (int q = 1; q < MAP_CLASSES; ++q) c += w >= m.s[q];
+    return c;
+}
+
+// First word of target w's entry in class c (w may be n: the layout's end).
 __device__ __forceinline__ uint64_t map_word(const MapClasses &m, int32_t w, int c, int L) {
-    const int32_t st = c == 0 ? 0 : c == 1 ? m.s1 : c == 2 ? m.s2 : m.s3;
-    const uint64_t of = c == 0 ? 0ull : c == 1 ? m.o1 : c == 2 ? m.o2 : m.o3;
+    int32_t st = 0;
+    uint64_t of = 0;
+#pragma unroll
+    for (int q = 0; q < MAP_CLASSES; ++q)
+        if (q == c) {
+            st = m.s[q];
+            of = m.o[q];
+        }
     return of + (uint64_t)(w - st) * (uint64_t)class_words(c, L);
 }
 
@@ -674,18 +694,18 @@ __device__ __forceinline__ int32_t first_of_degree(const int64_t *nrp, int64_t n
 __device__ MapClasses map_classes(const CycleArgs &a) {
     MapClasses m;
     const int32_t n = (int32_t)a.n;
+    m.s[0] = 0;
     if (a.deg_sorted) {
-        m.s1 = first_of_degree(a.nrp, a.n, 16);
-        m.s2 = first_of_degree(a.nrp, a.n, 256);
-        m.s3 = first_of_degree(a.nrp, a.n, 65536);
+        const int64_t lim[MAP_CLASSES - 1] = {16, 64, 256, 1024, 65536};
+        for (int c = 1; c < MAP_CLASSES; ++c) m.s[c] = first_of_degree(a.nrp, a.n, lim[c - 1]);
     } else {
-        // degrees are not ordered by id: one class for every id
-        m.s1 = m.s2 = 0;
-        m.s3 = a.max_deg >= 65536 ? 0 : n;
+        // degrees are not ordered by id: one class (16- or 32-bit) for every id
+        for (int c = 1; c < MAP_CLASSES - 1; ++c) m.s[c] = 0;
+        m.s[MAP_CLASSES - 1] = a.max_deg >= 65536 ? 0 : n;
     }
-    m.o1 = (uint64_t)m.s1 * class_words(0, a.L);
-    m.o2 = m.o1 + (uint64_t)(m.s2 - m.s1) * class_words(1, a.L);
-    m.o3 = m.o2 + (uint64_t)(m.s3 - m.s2) * class_words(2, a.L);
+    m.o[0] = 0;
+    for (int c = 1; c < MAP_CLASSES; ++c)
+        m.o[c] = m.o[c - 1] + (uint64_t)(m.s[c] - m.s[c - 1]) * class_words(c - 1, a.L);
     return m;
 }
 
@@ -807,7 +827,8 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
                     const int64_t ys = it_tb[o] + (f - excl);
                     const int32_t y = a.ncol[ys];
                     const int cls = map_class(mc, y);
-                    const int bits = 4 << cls;
+                    const int bits = class_bits(cls);
+                    const int F = 32 / bits;
                     uint32_t *my = map + map_word(mc, y, cls, L);
                     if (phase == 0) {
                         const int ew = class_words(cls, L);
@@ -815,9 +836,8 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
                     } else if (phase == 1) {
                         // the map is private to this workgroup: workgroup scope
                         // keeps the update in the XCD's L2
-                        const int bit = tx * bits;
-                        __hip_atomic_fetch_add(&my[bit >> 5], 1u << (bit & 31), __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                        __hip_atomic_fetch_add(&my[tx / F], 1u << ((tx % F) * bits),
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     } else {
                         int ty = a.ctype[ys];
                         uint64_t *ac = acc + (size_t)o * LL;
@@ -827,13 +847,12 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
                         int wq = -1;
                         uint32_t word = 0;
                         for (int t = 0; t < L; ++t) {
-                            const int bit = t * bits;
-                            if ((bit >> 5) != wq) {
-                                wq = bit >> 5;
+                            if (t / F != wq) {
+                                wq = t / F;
                                 word = __hip_atomic_load(&my[wq], __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_WORKGROUP);
                             }
-                            const uint32_t c = (word >> (bit & 31)) & mask;
+                            const uint32_t c = (word >> ((t % F) * bits)) & mask;
                             const uint32_t val = c - (t == tx ? 1u : 0u);
                             if (val)
                                 atomicAdd((unsigned long long *)&ac[pass_entry<PASS>(t, ty, L)],
