@@ -442,6 +442,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     if (batch) ea.gacc = global_counts;
     uint64_t *xyk = y.defer ? at<uint64_t>(ws, y.off_xyk) : nullptr;
     ea.xyk = xyk;
+    ea.xyk_u32 = max_deg < 65536 ? 1 : 0;
     EdgeArgs ed = ea;  // the separate derivation pass keeps the histogram
     if (xyk) {
         ea.hist_in_lds = 0;

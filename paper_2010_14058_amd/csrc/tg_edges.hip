@@ -618,6 +618,21 @@ __device__ void edge_cliques(const EdgeArgs &a, int32_t i, int32_t j, const Edge
     group_sync<NT>();
 }
 
+// One edge's Xi, Xj, Y, K (4 L^2 words in LDS) to its xyk row.  Each entry
+// is at most max_deg^2 (a sum over at most max_deg common neighbours of a
+// count at most max_deg), so with every degree below 2^16 it fits 32 bits.
+__device__ __forceinline__ void store_xyk(const EdgeArgs &a, int64_t e, const uint64_t *src,
+                                          int tid, int nt) {
+    const int n = 4 * a.L * a.L;
+    if (a.xyk_u32) {
+        uint32_t *dst = reinterpret_cast<uint32_t *>(a.xyk) + (size_t)e * n;
+        for (int q = tid; q < n; q += nt) dst[q] = (uint32_t)src[q];
+    } else {
+        uint64_t *dst = a.xyk + (size_t)e * n;
+        for (int q = tid; q < n; q += nt) dst[q] = src[q];
+    }
+}
+
 // Every orbit of Table 3 for edge e from the triangle, clique, cycle and
 // aggregate quantities (inclusion-exclusion in the spirit of Theorem 1;
 // Lemmas 1-4 for g4, g5, g9, g11), the row write and the histogram.
@@ -648,8 +663,9 @@ __device__ __forceinline__ void derive_three(const EdgeArgs &a, int64_t e, int32
     hist_add(a, hist, n2 + n3 + r3, (uint64_t)nTt, gid);
 }
 
+template <typename XT>
 __device__ __forceinline__ void derive_pair(const EdgeArgs &a, int64_t e, int32_t i, int32_t j,
-                                            int p, const uint64_t *xyk, uint64_t *hist,
+                                            int p, const XT *xyk, uint64_t *hist,
                                             uint32_t &bad) {
     const int L = a.L;
     const int LL = L * L;
@@ -661,7 +677,7 @@ __device__ __forceinline__ void derive_pair(const EdgeArgs &a, int64_t e, int32_
     const int hbase = n2 + 2 * n3;
     const int64_t gid = a.batch ? (int64_t)a.ngraph[i] : 0;
     const int ta = a.ntype[i], tb = a.ntype[j];
-    const uint64_t *Xi = xyk, *Xj = Xi + LL, *Y = Xi + 2 * LL, *K = Xi + 3 * LL;
+    const XT *Xi = xyk, *Xj = Xi + LL, *Y = Xi + 2 * LL, *K = Xi + 3 * LL;
     const uint32_t *tri_e = a.tri + (size_t)e * L;
     const uint32_t *di = a.tdeg + (size_t)i * tri_pitch(L);
     const uint32_t *dj = a.tdeg + (size_t)j * tri_pitch(L);
@@ -830,8 +846,7 @@ __device__ __forceinline__ void edges_light_body(const EdgeArgs &a) {
         edge_build<WAVE>(a, i, j, Sb, lane);
         edge_cliques<WAVE>(a, i, j, Sb, a.TM, F, lane);
         if constexpr (DEFER) {
-            uint64_t *dst = a.xyk + (size_t)e * 4 * LL;
-            for (int q = lane; q < 4 * LL; q += WAVE) dst[q] = Sb.Xi[q];
+            store_xyk(a, e, Sb.Xi, lane, WAVE);
             return;
         }
         if (lane == 0) {
@@ -954,8 +969,7 @@ __global__ void __launch_bounds__(EDGE_THREADS_HEAVY) k_edges_heavy(EdgeArgs a) 
         __syncthreads();
         edge_cliques<NT>(a, i, j, S, TMs, F, tid);
         if (a.xyk) {
-            uint64_t *dst = a.xyk + (size_t)e * 4 * LL;
-            for (int q = tid; q < 4 * LL; q += NT) dst[q] = S.Xi[q];
+            store_xyk(a, e, S.Xi, tid, NT);
         } else {
             if (tid == 0) {
                 slot_e[0] = e;
@@ -996,7 +1010,11 @@ __global__ void __launch_bounds__(256) k_derive(EdgeArgs a) {
         const int32_t i = a.ei[e], j = a.ej[e];
         if (p == 0) hist_add(a, hist, rank2(a.ntype[i], a.ntype[j]), 1, 0);
         if (p < L) derive_three(a, e, i, j, p, hist, bad);
-        derive_pair(a, e, i, j, p, a.xyk + (size_t)e * 4 * LL, hist, bad);
+        if (a.xyk_u32)
+            derive_pair(a, e, i, j, p, reinterpret_cast<const uint32_t *>(a.xyk) + (size_t)e * 4 * LL,
+                        hist, bad);
+        else
+            derive_pair(a, e, i, j, p, a.xyk + (size_t)e * 4 * LL, hist, bad);
     }
     __syncthreads();
     if (a.hist_in_lds)

@@ -137,6 +137,7 @@ struct EdgeArgs {
     int tcap;                    // light/heavy edge cut on the smaller degree = LDS list size
     int derive_batch;            // edges whose derivation runs together (LDS slots of 4 L^2 words)
     uint64_t *xyk;               // deferred derivation: Xi, Xj, Y, K per edge ([m][4 L^2]), or null
+    int xyk_u32;                 // xyk entries stored as uint32 (every degree below 2^16)
     uint32_t *heavy_list;
     uint64_t *counters;
     uint32_t *tbuf;      // heavy: per-workgroup low-member buffers of n entries
