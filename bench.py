@@ -73,8 +73,9 @@ def algorithmic_bytes(g, L, stats, heavy_edge_info):
     hv_d, hv_t, hv_m = heavy_edge_info
     edge_fixed = 40 * L * L + 8 * W          # A_i, A_j, D_i, D_j, NC reads + row write
     per_t = 12 * L + 8                        # tri(i,k), tri(j,k), d_k^., slot ids
-    xyk = 32 * L * L                          # X_i, X_j, Y, K: written by the edge kernels,
-                                              # read by the derivation pass
+    # X_i, X_j, Y, K: written by the edge kernels, read by the derivation
+    # pass; 32-bit words while every degree is below 2^16
+    xyk = (16 if float(d.max(initial=0)) < 65536 else 32) * L * L
     b = {
         "prep": 8 * (n + 1) + 4 * nnz + n + 8 * (n + 1) + 8 * nnz + 8 * m + 4 * n * L,
         "tri": 4 * sum_d2 + 4 * L * m,
