@@ -71,15 +71,15 @@ def algorithmic_bytes(g, L, stats, heavy_edge_info):
     tri_slots = float(stats["triangle_slots"])
     per_wedge = 16 + 4 * L
     hv_d, hv_t, hv_m = heavy_edge_info
-    edge_fixed = 40 * L * L + 8 * W          # A_i, A_j, D_i, D_j, NC reads + row write
+    narrow = float(d.max(initial=0)) < 65536  # 32-bit node aggregates and X_i, X_j, Y, K
+    edge_fixed = (16 if narrow else 32) * L * L + 8 * L * L + 8 * W  # A_i, A_j, D_i, D_j, NC, row
     per_t = 12 * L + 8                        # tri(i,k), tri(j,k), d_k^., slot ids
-    # X_i, X_j, Y, K: written by the edge kernels, read by the derivation
-    # pass; 32-bit words while every degree is below 2^16
-    xyk = (16 if float(d.max(initial=0)) < 65536 else 32) * L * L
+    # X_i, X_j, Y, K: written by the edge kernels, read by the derivation pass
+    xyk = (16 if narrow else 32) * L * L
     b = {
         "prep": 8 * (n + 1) + 4 * nnz + n + 8 * (n + 1) + 8 * nnz + 8 * m + 4 * n * L,
         "tri": 4 * sum_d2 + 4 * L * m,
-        "aggr": nnz * (8 + 8 * L) + 16 * n * L * L,
+        "aggr": nnz * (8 + 8 * L) + (8 if narrow else 16) * n * L * L,
         "cyc_work": 8 * nnz,
         "cycA_light": (stats["wedges_pass_a"] - stats["heavy_wedges_pass_a"]) * per_wedge,
         "cycA_heavy": stats["heavy_wedges_pass_a"] * per_wedge,

@@ -356,7 +356,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     HIPCHK(launch_tri(nrp, ncol, ctype, ei, ej, eslot, tri_slot, m, L, tri, counters + C_TRI_SUM,
                       sh_base, nw, SB, hub_base, Hw, HB, st));
     timing_mark("tri");
-    HIPCHK(launch_node_aggr(nrp, ncol, ctype, tri_slot, tdeg, n, L, A, D, st));
+    HIPCHK(launch_node_aggr(nrp, ncol, ctype, tri_slot, tdeg, n, L, A, D, max_deg < 65536, st));
     timing_mark("aggr");
 
     // ---- 4-cycles from degree-ordered wedges
@@ -408,6 +408,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     ea.nrp = nrp; ea.ncol = ncol; ea.ntype = ntype; ea.neid = neid; ea.ei = ei; ea.ej = ej;
     ea.ctype = ctype;
     ea.tri = tri; ea.tdeg = tdeg; ea.tri_slot = tri_slot; ea.A = A; ea.D = D; ea.NC = NC; ea.m = m; ea.L = L;
+    ea.ad_u32 = max_deg < 65536 ? 1 : 0;  // node aggregates below 2^32
     ea.rows = per_edge; ea.gacc = gacc; ea.gw = gw;
     ea.hist_in_lds = (size_t)gw * sizeof(uint64_t) <= 32768 ? 1 : 0;
     // a batch chunk flushes after at most BATCH_EDGE_CHUNK (256) edges, each

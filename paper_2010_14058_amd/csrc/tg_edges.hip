@@ -681,8 +681,11 @@ __device__ __forceinline__ void derive_pair(const EdgeArgs &a, int64_t e, int32_
     const uint32_t *tri_e = a.tri + (size_t)e * L;
     const uint32_t *di = a.tdeg + (size_t)i * tri_pitch(L);
     const uint32_t *dj = a.tdeg + (size_t)j * tri_pitch(L);
-    const uint64_t *Ai = a.A + (size_t)i * LL, *Aj = a.A + (size_t)j * LL;
-    const uint64_t *Di = a.D + (size_t)i * LL, *Dj = a.D + (size_t)j * LL;
+    // node aggregates, 32- or 64-bit words
+    auto agg = [&](const uint64_t *base, int32_t v, int q) -> int64_t {
+        const size_t at = (size_t)v * LL + q;
+        return a.ad_u32 ? (int64_t)reinterpret_cast<const uint32_t *>(base)[at] : (int64_t)base[at];
+    };
     const uint64_t *NC = a.NC + (size_t)e * LL;
     uint64_t *row = a.rows ? a.rows + (size_t)e * W : nullptr;
     // pair (t, u), t <= u, from its lexicographic index
@@ -725,10 +728,10 @@ __device__ __forceinline__ void derive_pair(const EdgeArgs &a, int64_t e, int32_
     emit(6, g6);
     emit(4, (same ? Sit * Sjt : Sit * Sju + Siu * Sjt) - g6);                 // Lemma 1
     // tailed-triangle tails: adjacent pairs inside S_i (resp. S_j)
-    const int64_t sgi0 = (int64_t)Ai[qa] - Xi0 - (tb == t) * nTu;
-    const int64_t sgi1 = (int64_t)Ai[qb] - Xi1 - (tb == u) * nTt;
-    const int64_t sgj0 = (int64_t)Aj[qa] - Xj0 - (ta == t) * nTu;
-    const int64_t sgj1 = (int64_t)Aj[qb] - Xj1 - (ta == u) * nTt;
+    const int64_t sgi0 = agg(a.A, i, qa) - Xi0 - (tb == t) * nTu;
+    const int64_t sgi1 = agg(a.A, i, qb) - Xi1 - (tb == u) * nTt;
+    const int64_t sgj0 = agg(a.A, j, qa) - Xj0 - (ta == t) * nTu;
+    const int64_t sgj1 = agg(a.A, j, qb) - Xj1 - (ta == u) * nTt;
     const int64_t Ei0 = sgi0 - Ci1, Ei1 = sgi1 - Ci0;
     const int64_t Ej0 = sgj0 - Cj1, Ej1 = sgj1 - Cj0;
     if (same && ((Ei0 + Ej0) & 1)) bad |= ST_INTERNAL;
@@ -738,10 +741,10 @@ __device__ __forceinline__ void derive_pair(const EdgeArgs &a, int64_t e, int32_
     emit(5, (same ? Sit * (Sit - 1) / 2 + Sjt * (Sjt - 1) / 2 : Sit * Siu + Sjt * Sju) - g7);  // Lemma 2
     // 4-path end edges: neighbours of S_i / S_j outside the edge's sets
     const int64_t Y0 = (int64_t)Y[qa], Y1 = (int64_t)Y[qb];
-    const int64_t dli0 = (int64_t)Di[qa] - Y0 - (tb == t) * (int64_t)dj[u];
-    const int64_t dli1 = (int64_t)Di[qb] - Y1 - (tb == u) * (int64_t)dj[t];
-    const int64_t dlj0 = (int64_t)Dj[qa] - Y0 - (ta == t) * (int64_t)di[u];
-    const int64_t dlj1 = (int64_t)Dj[qb] - Y1 - (ta == u) * (int64_t)di[t];
+    const int64_t dli0 = agg(a.D, i, qa) - Y0 - (tb == t) * (int64_t)dj[u];
+    const int64_t dli1 = agg(a.D, i, qb) - Y1 - (tb == u) * (int64_t)dj[t];
+    const int64_t dlj0 = agg(a.D, j, qa) - Y0 - (ta == t) * (int64_t)di[u];
+    const int64_t dlj1 = agg(a.D, j, qb) - Y1 - (ta == u) * (int64_t)di[t];
     const int64_t Pi0 = dli0 - Sit * (ta == u) - sgi0 - Cyc0;
     const int64_t Pi1 = dli1 - Siu * (ta == t) - sgi1 - Cyc1;
     const int64_t Pj0 = dlj0 - Sjt * (tb == u) - sgj0 - Cyc1;

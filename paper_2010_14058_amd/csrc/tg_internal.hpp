@@ -128,6 +128,7 @@ struct EdgeArgs {
     const uint8_t *ctype;        // type of the neighbour at each adjacency slot        // typed degrees per node, rows of tri_pitch(L)
     const uint32_t *tri_slot;    // typed triangle counts per slot, rows of tri_pitch(L)
     const uint64_t *A, *D, *NC;
+    int ad_u32;                  // A and D stored as uint32 (every degree below 2^16)
     int64_t m;
     int L;
     uint64_t *rows;      // may be null
@@ -214,7 +215,8 @@ hipError_t launch_superhubs(const int64_t *nrp, const int32_t *ncol, int64_t n, 
                             uint64_t *SB, uint32_t *SP, hipStream_t st);
 hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8_t *ctype,
                             const uint32_t *tri_slot, const uint32_t *tdeg,
-                            int64_t n, int L, uint64_t *A, uint64_t *D, hipStream_t st);
+                            int64_t n, int L, uint64_t *A, uint64_t *D, bool ad_u32,
+                            hipStream_t st);
 hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32_t *neid,
                            const uint32_t *eslot, const uint32_t *nlow, int64_t n, uint32_t *la_l,
                            uint4 *la_h, uint32_t *lb_l, uint4 *lb_h, uint64_t *counters,

@@ -398,10 +398,14 @@ __global__ void __launch_bounds__(256) k_superhubs(const int64_t *__restrict__ n
 // ------------------------------------------------------ node aggregates
 
 // One wave per internal node u; LDS holds A_u and D_u (L x L uint64 each).
+// An entry of A_u sums at most d_u triangle counts of at most d_u, one of
+// D_u at most d_u degrees, so with every degree below 2^16 both are stored
+// as uint32 (ad_u32).
 __global__ void k_node_aggr(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
                             const uint8_t *__restrict__ ctype, const uint32_t *__restrict__ tri_slot,
                             const uint32_t *__restrict__ tdeg,
-                            int64_t n, int L, uint64_t *__restrict__ A, uint64_t *__restrict__ D) {
+                            int64_t n, int L, uint64_t *__restrict__ A, uint64_t *__restrict__ D,
+                            int ad_u32) {
     extern __shared__ uint64_t sm_aggr[];
     int w = threadIdx.x / WAVE;
     int lane = lane_id();
@@ -425,9 +429,17 @@ __global__ void k_node_aggr(const int64_t *__restrict__ nrp, const int32_t *__re
             }
         }
         wave_sync();
-        for (int q = lane; q < LL; q += WAVE) {
-            A[(size_t)u * LL + q] = sA[q];
-            D[(size_t)u * LL + q] = sD[q];
+        if (ad_u32) {
+            uint32_t *A32 = reinterpret_cast<uint32_t *>(A), *D32 = reinterpret_cast<uint32_t *>(D);
+            for (int q = lane; q < LL; q += WAVE) {
+                A32[(size_t)u * LL + q] = (uint32_t)sA[q];
+                D32[(size_t)u * LL + q] = (uint32_t)sD[q];
+            }
+        } else {
+            for (int q = lane; q < LL; q += WAVE) {
+                A[(size_t)u * LL + q] = sA[q];
+                D[(size_t)u * LL + q] = sD[q];
+            }
         }
         wave_sync();
     }
@@ -1144,10 +1156,11 @@ hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *ct
 
 hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8_t *ctype,
                             const uint32_t *tri_slot, const uint32_t *tdeg,
-                            int64_t n, int L, uint64_t *A, uint64_t *D, hipStream_t st) {
+                            int64_t n, int L, uint64_t *A, uint64_t *D, bool ad_u32,
+                            hipStream_t st) {
     size_t sh = (size_t)4 * 2 * L * L * sizeof(uint64_t);
     k_node_aggr<<<blocks_bounded(n, 4, 32), 256, sh, st>>>(nrp, ncol, ctype, tri_slot, tdeg, n, L,
-                                                           A, D);
+                                                           A, D, ad_u32 ? 1 : 0);
     LAUNCH_CHECK();
     return hipSuccess;
 }
