@@ -72,7 +72,7 @@ def algorithmic_bytes(g, L, stats, heavy_edge_info):
     per_wedge = 16 + 4 * L
     hv_d, hv_t, hv_m = heavy_edge_info
     narrow = float(d.max(initial=0)) < 65536  # 32-bit node aggregates and X_i, X_j, Y, K
-    edge_fixed = (16 if narrow else 32) * L * L + 8 * L * L + 8 * W  # A_i, A_j, D_i, D_j, NC, row
+    edge_fixed = (20 if narrow else 40) * L * L + 8 * W  # A_i, A_j, D_i, D_j, NC, row
     per_t = 12 * L + 8                        # tri(i,k), tri(j,k), d_k^., slot ids
     # X_i, X_j, Y, K: written by the edge kernels, read by the derivation pass
     xyk = (16 if narrow else 32) * L * L

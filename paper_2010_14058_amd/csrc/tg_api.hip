@@ -360,7 +360,8 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     timing_mark("aggr");
 
     // ---- 4-cycles from degree-ordered wedges
-    HIPCHK(launch_fill_u64(NC, 0, m * LL, st));
+    const bool nc32 = max_deg < 65536;  // 4-cycles through an edge below 2^32
+    HIPCHK(launch_fill_u64(NC, 0, nc32 ? (m * LL + 1) / 2 : m * LL, st));
     HIPCHK(launch_cyc_work(nrp, ncol, neid, eslot, nlow, n, la_l, la_h, lb_l, lb_h, counters,
                            (uint64_t)g_tune[TG_TUNE_TASK_WEDGES], L,
                            (uint64_t)g_tune[TG_TUNE_RANGE_BYTES],
@@ -372,7 +373,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     ca.nlow = nlow;
     ca.clear_bytes = (uint64_t)g_tune[TG_TUNE_CLEAR_BYTES];
     ca.nrp = nrp; ca.ncol = ncol; ca.ntype = ntype; ca.neid = neid; ca.ctype = ctype; ca.ei = ei;
-    ca.counters = counters; ca.L = L; ca.n = n; ca.NC = NC; ca.maps = maps;
+    ca.counters = counters; ca.L = L; ca.n = n; ca.NC = NC; ca.nc_u32 = nc32 ? 1 : 0; ca.maps = maps;
     ca.status = status;
     {
         // hash slots: the smallest power of two above the light bucket
@@ -409,6 +410,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     ea.ctype = ctype;
     ea.tri = tri; ea.tdeg = tdeg; ea.tri_slot = tri_slot; ea.A = A; ea.D = D; ea.NC = NC; ea.m = m; ea.L = L;
     ea.ad_u32 = max_deg < 65536 ? 1 : 0;  // node aggregates below 2^32
+    ea.nc_u32 = nc32 ? 1 : 0;
     ea.rows = per_edge; ea.gacc = gacc; ea.gw = gw;
     ea.hist_in_lds = (size_t)gw * sizeof(uint64_t) <= 32768 ? 1 : 0;
     // a batch chunk flushes after at most BATCH_EDGE_CHUNK (256) edges, each

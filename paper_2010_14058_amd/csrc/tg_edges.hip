@@ -686,7 +686,6 @@ __device__ __forceinline__ void derive_pair(const EdgeArgs &a, int64_t e, int32_
         const size_t at = (size_t)v * LL + q;
         return a.ad_u32 ? (int64_t)reinterpret_cast<const uint32_t *>(base)[at] : (int64_t)base[at];
     };
-    const uint64_t *NC = a.NC + (size_t)e * LL;
     uint64_t *row = a.rows ? a.rows + (size_t)e * W : nullptr;
     // pair (t, u), t <= u, from its lexicographic index
     int t = 0, rem = p;
@@ -722,8 +721,13 @@ __device__ __forceinline__ void derive_pair(const EdgeArgs &a, int64_t e, int32_
     emit(10, g10);
     emit(9, (same ? nTt * (Sit + Sjt) : nTt * (Siu + Sju) + nTu * (Sit + Sjt)) - g10);  // Lemma 3
     // 4-cycles: non-induced cycles minus chordal and clique instances
-    const int64_t Cyc0 = (int64_t)NC[qa] - Ci1 - Cj0 - K0;
-    const int64_t Cyc1 = (int64_t)NC[qb] - Ci0 - Cj1 - K1;
+    const size_t nce = (size_t)e * LL;
+    const int64_t NC0 = a.nc_u32 ? (int64_t)reinterpret_cast<const uint32_t *>(a.NC)[nce + qa]
+                                 : (int64_t)a.NC[nce + qa];
+    const int64_t NC1 = a.nc_u32 ? (int64_t)reinterpret_cast<const uint32_t *>(a.NC)[nce + qb]
+                                 : (int64_t)a.NC[nce + qb];
+    const int64_t Cyc0 = NC0 - Ci1 - Cj0 - K0;
+    const int64_t Cyc1 = NC1 - Ci0 - Cj1 - K1;
     const int64_t g6 = same ? Cyc0 : Cyc0 + Cyc1;
     emit(6, g6);
     emit(4, (same ? Sit * Sjt : Sit * Sju + Siu * Sjt) - g6);                 // Lemma 1

@@ -108,6 +108,7 @@ struct CycleArgs {
     int L;
     int64_t n;
     uint64_t *NC;
+    int nc_u32;                  // NC stored as uint32 (every degree below 2^16)
     uint32_t *maps;
     int chunk;
     uint32_t *status;
@@ -129,6 +130,7 @@ struct EdgeArgs {
     const uint32_t *tri_slot;    // typed triangle counts per slot, rows of tri_pitch(L)
     const uint64_t *A, *D, *NC;
     int ad_u32;                  // A and D stored as uint32 (every degree below 2^16)
+    int nc_u32;                  // NC stored as uint32 (every degree below 2^16)
     int64_t m;
     int L;
     uint64_t *rows;      // may be null

@@ -508,6 +508,15 @@ __device__ __forceinline__ int hash_slot(uint32_t y, int log2_slots) {
     return (int)((y * 0x9E3779B1u) >> (32 - log2_slots));
 }
 
+// Adds v to NC entry idx.  An entry counts 4-cycles through one edge, at
+// most (d_i - 1)(d_j - 1), so with every degree below 2^16 NC holds uint32.
+__device__ __forceinline__ void nc_add(const CycleArgs &a, size_t idx, uint64_t v) {
+    if (a.nc_u32)
+        atomicAdd(reinterpret_cast<unsigned int *>(a.NC) + idx, (unsigned int)v);
+    else
+        atomicAdd((unsigned long long *)&a.NC[idx], (unsigned long long)v);
+}
+
 // Light groups: one 64-thread workgroup per group, LDS open-addressing map
 // keyed by target with 16-bit counters per type (group wedges at most the
 // light bucket bound, itself at most LIGHT_MAXW); the map has the smallest
@@ -589,7 +598,7 @@ __global__ void __launch_bounds__(64) k_cyc_light(CycleArgs a) {
                         int ty = a.ctype[ys];
                         uint32_t e = it_eid[o];
                         int flip = it_flip[o];
-                        uint64_t *nc = a.NC + (size_t)e * L * L;
+                        const size_t nc0 = (size_t)e * L * L;
                         for (int t = 0; t < L; ++t) {
                             uint32_t c = (cnt[h * LW + (t >> 1)] >> ((t & 1) * 16)) & 0xffffu;
                             uint32_t val = c - (t == tx ? 1u : 0u);
@@ -597,7 +606,7 @@ __global__ void __launch_bounds__(64) k_cyc_light(CycleArgs a) {
                                 int pq = pass_entry<PASS>(t, ty, L);
                                 int p = pq / L, q = pq - p * L;
                                 int canon = flip ? q * L + p : pq;
-                                atomicAdd((unsigned long long *)&nc[canon], (unsigned long long)val);
+                                nc_add(a, nc0 + canon, val);
                             }
                         }
                     }
@@ -881,8 +890,7 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
                         int pq = q - o * LL;
                         int p = pq / L, r = pq - p * L;
                         int canon = it_flip[o] ? r * L + p : pq;
-                        atomicAdd((unsigned long long *)&a.NC[(size_t)it_eid[o] * LL + canon],
-                                  (unsigned long long)v);
+                        nc_add(a, (size_t)it_eid[o] * LL + canon, v);
                     }
                     __syncthreads();
                 }
