@@ -356,12 +356,14 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     HIPCHK(launch_tri(nrp, ncol, ctype, ei, ej, eslot, tri_slot, m, L, tri, counters + C_TRI_SUM,
                       sh_base, nw, SB, hub_base, Hw, HB, st));
     timing_mark("tri");
-    HIPCHK(launch_node_aggr(nrp, ncol, ctype, tri_slot, tdeg, n, L, A, D, max_deg < 65536, st));
+    // every degree below 2^16: node aggregates, per-edge 4-cycle counts and
+    // derivation inputs stay below 2^32 and are held as 32-bit words
+    const bool words32 = max_deg < 65536;
+    HIPCHK(launch_node_aggr(nrp, ncol, ctype, tri_slot, tdeg, n, L, A, D, words32, st));
     timing_mark("aggr");
 
     // ---- 4-cycles from degree-ordered wedges
-    const bool nc32 = max_deg < 65536;  // 4-cycles through an edge below 2^32
-    HIPCHK(launch_fill_u64(NC, 0, nc32 ? (m * LL + 1) / 2 : m * LL, st));
+    HIPCHK(launch_fill_u64(NC, 0, words32 ? (m * LL + 1) / 2 : m * LL, st));
     HIPCHK(launch_cyc_work(nrp, ncol, neid, eslot, nlow, n, la_l, la_h, lb_l, lb_h, counters,
                            (uint64_t)g_tune[TG_TUNE_TASK_WEDGES], L,
                            (uint64_t)g_tune[TG_TUNE_RANGE_BYTES],
@@ -373,7 +375,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     ca.nlow = nlow;
     ca.clear_bytes = (uint64_t)g_tune[TG_TUNE_CLEAR_BYTES];
     ca.nrp = nrp; ca.ncol = ncol; ca.ntype = ntype; ca.neid = neid; ca.ctype = ctype; ca.ei = ei;
-    ca.counters = counters; ca.L = L; ca.n = n; ca.NC = NC; ca.nc_u32 = nc32 ? 1 : 0; ca.maps = maps;
+    ca.counters = counters; ca.L = L; ca.n = n; ca.NC = NC; ca.nc_u32 = words32 ? 1 : 0; ca.maps = maps;
     ca.status = status;
     {
         // hash slots: the smallest power of two above the light bucket
@@ -409,8 +411,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     ea.nrp = nrp; ea.ncol = ncol; ea.ntype = ntype; ea.neid = neid; ea.ei = ei; ea.ej = ej;
     ea.ctype = ctype;
     ea.tri = tri; ea.tdeg = tdeg; ea.tri_slot = tri_slot; ea.A = A; ea.D = D; ea.NC = NC; ea.m = m; ea.L = L;
-    ea.ad_u32 = max_deg < 65536 ? 1 : 0;  // node aggregates below 2^32
-    ea.nc_u32 = nc32 ? 1 : 0;
+    ea.agg_u32 = words32 ? 1 : 0;  // A, D and NC entries below 2^32
     ea.rows = per_edge; ea.gacc = gacc; ea.gw = gw;
     ea.hist_in_lds = (size_t)gw * sizeof(uint64_t) <= 32768 ? 1 : 0;
     // a batch chunk flushes after at most BATCH_EDGE_CHUNK (256) edges, each
@@ -445,7 +446,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     if (batch) ea.gacc = global_counts;
     uint64_t *xyk = y.defer ? at<uint64_t>(ws, y.off_xyk) : nullptr;
     ea.xyk = xyk;
-    ea.xyk_u32 = max_deg < 65536 ? 1 : 0;
+    ea.xyk_u32 = words32 ? 1 : 0;
     EdgeArgs ed = ea;  // the separate derivation pass keeps the histogram
     if (xyk) {
         ea.hist_in_lds = 0;

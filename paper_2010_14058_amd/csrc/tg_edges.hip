@@ -12,6 +12,7 @@
 // Alg. 3) are counted as popcounts of AND-ed hub words for hub-hub pairs and
 // by scanning the short rows of low members for the rest.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include "tg_device.hpp"
 
@@ -663,10 +664,12 @@ __device__ __forceinline__ void derive_three(const EdgeArgs &a, int64_t e, int32
     hist_add(a, hist, n2 + n3 + r3, (uint64_t)nTt, gid);
 }
 
-template <typename XT>
+// XT: word of the xyk entries; NARROW: A, D and NC held as uint32.
+template <typename XT, bool NARROW>
 __device__ __forceinline__ void derive_pair(const EdgeArgs &a, int64_t e, int32_t i, int32_t j,
                                             int p, const XT *xyk, uint64_t *hist,
                                             uint32_t &bad) {
+    using AT = typename std::conditional<NARROW, uint32_t, uint64_t>::type;
     const int L = a.L;
     const int LL = L * L;
     const int P = L * (L + 1) / 2;
@@ -681,11 +684,10 @@ __device__ __forceinline__ void derive_pair(const EdgeArgs &a, int64_t e, int32_
     const uint32_t *tri_e = a.tri + (size_t)e * L;
     const uint32_t *di = a.tdeg + (size_t)i * tri_pitch(L);
     const uint32_t *dj = a.tdeg + (size_t)j * tri_pitch(L);
-    // node aggregates, 32- or 64-bit words
-    auto agg = [&](const uint64_t *base, int32_t v, int q) -> int64_t {
-        const size_t at = (size_t)v * LL + q;
-        return a.ad_u32 ? (int64_t)reinterpret_cast<const uint32_t *>(base)[at] : (int64_t)base[at];
-    };
+    const AT *Ab = reinterpret_cast<const AT *>(a.A), *Db = reinterpret_cast<const AT *>(a.D);
+    const AT *Ai = Ab + (size_t)i * LL, *Aj = Ab + (size_t)j * LL;
+    const AT *Di = Db + (size_t)i * LL, *Dj = Db + (size_t)j * LL;
+    const AT *NC = reinterpret_cast<const AT *>(a.NC) + (size_t)e * LL;
     uint64_t *row = a.rows ? a.rows + (size_t)e * W : nullptr;
     // pair (t, u), t <= u, from its lexicographic index
     int t = 0, rem = p;
@@ -721,21 +723,16 @@ __device__ __forceinline__ void derive_pair(const EdgeArgs &a, int64_t e, int32_
     emit(10, g10);
     emit(9, (same ? nTt * (Sit + Sjt) : nTt * (Siu + Sju) + nTu * (Sit + Sjt)) - g10);  // Lemma 3
     // 4-cycles: non-induced cycles minus chordal and clique instances
-    const size_t nce = (size_t)e * LL;
-    const int64_t NC0 = a.nc_u32 ? (int64_t)reinterpret_cast<const uint32_t *>(a.NC)[nce + qa]
-                                 : (int64_t)a.NC[nce + qa];
-    const int64_t NC1 = a.nc_u32 ? (int64_t)reinterpret_cast<const uint32_t *>(a.NC)[nce + qb]
-                                 : (int64_t)a.NC[nce + qb];
-    const int64_t Cyc0 = NC0 - Ci1 - Cj0 - K0;
-    const int64_t Cyc1 = NC1 - Ci0 - Cj1 - K1;
+    const int64_t Cyc0 = (int64_t)NC[qa] - Ci1 - Cj0 - K0;
+    const int64_t Cyc1 = (int64_t)NC[qb] - Ci0 - Cj1 - K1;
     const int64_t g6 = same ? Cyc0 : Cyc0 + Cyc1;
     emit(6, g6);
     emit(4, (same ? Sit * Sjt : Sit * Sju + Siu * Sjt) - g6);                 // Lemma 1
     // tailed-triangle tails: adjacent pairs inside S_i (resp. S_j)
-    const int64_t sgi0 = agg(a.A, i, qa) - Xi0 - (tb == t) * nTu;
-    const int64_t sgi1 = agg(a.A, i, qb) - Xi1 - (tb == u) * nTt;
-    const int64_t sgj0 = agg(a.A, j, qa) - Xj0 - (ta == t) * nTu;
-    const int64_t sgj1 = agg(a.A, j, qb) - Xj1 - (ta == u) * nTt;
+    const int64_t sgi0 = (int64_t)Ai[qa] - Xi0 - (tb == t) * nTu;
+    const int64_t sgi1 = (int64_t)Ai[qb] - Xi1 - (tb == u) * nTt;
+    const int64_t sgj0 = (int64_t)Aj[qa] - Xj0 - (ta == t) * nTu;
+    const int64_t sgj1 = (int64_t)Aj[qb] - Xj1 - (ta == u) * nTt;
     const int64_t Ei0 = sgi0 - Ci1, Ei1 = sgi1 - Ci0;
     const int64_t Ej0 = sgj0 - Cj1, Ej1 = sgj1 - Cj0;
     if (same && ((Ei0 + Ej0) & 1)) bad |= ST_INTERNAL;
@@ -745,10 +742,10 @@ __device__ __forceinline__ void derive_pair(const EdgeArgs &a, int64_t e, int32_
     emit(5, (same ? Sit * (Sit - 1) / 2 + Sjt * (Sjt - 1) / 2 : Sit * Siu + Sjt * Sju) - g7);  // Lemma 2
     // 4-path end edges: neighbours of S_i / S_j outside the edge's sets
     const int64_t Y0 = (int64_t)Y[qa], Y1 = (int64_t)Y[qb];
-    const int64_t dli0 = agg(a.D, i, qa) - Y0 - (tb == t) * (int64_t)dj[u];
-    const int64_t dli1 = agg(a.D, i, qb) - Y1 - (tb == u) * (int64_t)dj[t];
-    const int64_t dlj0 = agg(a.D, j, qa) - Y0 - (ta == t) * (int64_t)di[u];
-    const int64_t dlj1 = agg(a.D, j, qb) - Y1 - (ta == u) * (int64_t)di[t];
+    const int64_t dli0 = (int64_t)Di[qa] - Y0 - (tb == t) * (int64_t)dj[u];
+    const int64_t dli1 = (int64_t)Di[qb] - Y1 - (tb == u) * (int64_t)dj[t];
+    const int64_t dlj0 = (int64_t)Dj[qa] - Y0 - (ta == t) * (int64_t)di[u];
+    const int64_t dlj1 = (int64_t)Dj[qb] - Y1 - (ta == u) * (int64_t)di[t];
     const int64_t Pi0 = dli0 - Sit * (ta == u) - sgi0 - Cyc0;
     const int64_t Pi1 = dli1 - Siu * (ta == t) - sgi1 - Cyc1;
     const int64_t Pj0 = dlj0 - Sjt * (tb == u) - sgj0 - Cyc1;
@@ -760,7 +757,7 @@ __device__ __forceinline__ void derive_pair(const EdgeArgs &a, int64_t e, int32_
     emit(8, same ? Q0 : Q0 + Q1);
 }
 
-template <int NT>
+template <int NT, bool NARROW>
 __device__ void edge_derive(const EdgeArgs &a, int nb, const int64_t *slot_e, const int32_t *slot_i,
                             const int32_t *slot_j, const uint64_t *xyk, uint64_t *hist, int tid,
                             uint32_t &bad) {
@@ -780,8 +777,8 @@ __device__ void edge_derive(const EdgeArgs &a, int nb, const int64_t *slot_e, co
     }
     for (int it = tid; it < nb * P; it += NT) {
         const int b = it / P;
-        derive_pair(a, slot_e[b], slot_i[b], slot_j[b], it - b * P, xyk + (size_t)b * 4 * LL, hist,
-                    bad);
+        derive_pair<uint64_t, NARROW>(a, slot_e[b], slot_i[b], slot_j[b], it - b * P,
+                                      xyk + (size_t)b * 4 * LL, hist, bad);
     }
 }
 
@@ -810,7 +807,8 @@ __device__ __forceinline__ EdgeShared carve(const EdgeArgs &a, uint64_t *sm, uin
 // Light edges: one wave per edge (|T| <= min degree <= tcap, lists in LDS).
 // DEFER: the edge's Xi, Xj, Y, K go to a.xyk and k_derive does the rest, so
 // this kernel carries no derivation state (fewer registers, more waves).
-template <bool DEFER>
+// NARROW: A, D and NC held as uint32 (used by the fused derivation only).
+template <bool DEFER, bool NARROW>
 __device__ __forceinline__ void edges_light_body(const EdgeArgs &a) {
     extern __shared__ uint64_t sm_edge[];
     __shared__ uint32_t meta[4];
@@ -867,7 +865,7 @@ __device__ __forceinline__ void edges_light_body(const EdgeArgs &a) {
         if constexpr (DEFER) return;
         if (!nb) return;
         __syncthreads();
-        edge_derive<WAVE>(a, nb, slot_e, slot_i, slot_j, S.Xi, hist, lane, bad);
+        edge_derive<WAVE, NARROW>(a, nb, slot_e, slot_i, slot_j, S.Xi, hist, lane, bad);
         __syncthreads();
         nb = 0;
     };
@@ -924,16 +922,21 @@ __device__ __forceinline__ void edges_light_body(const EdgeArgs &a) {
 // waves per SIMD keeps more edges in flight.
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5)))
 k_edges_light_deferred(EdgeArgs a) {
-    edges_light_body<true>(a);
+    edges_light_body<true, false>(a);
 }
 
+template <bool NARROW>
 __global__ void __launch_bounds__(64) k_edges_light_fused(EdgeArgs a) {
-    edges_light_body<false>(a);
+    edges_light_body<false, NARROW>(a);
 }
 
 // Heavy edges: one 256-thread workgroup per edge, pulled from a queue; the
 // low list lives in a global buffer of n entries private to the workgroup,
-// the hub list (at most H entries) in LDS.
+// the hub list (at most H entries) in LDS.  MODE 0 stores each edge's Xi,
+// Xj, Y, K for the separate derivation; 1 and 2 derive in place with 32-bit
+// and 64-bit A, D and NC (one instance each, so that the deferred one holds
+// no derivation state).
+template <int MODE>
 __global__ void __launch_bounds__(EDGE_THREADS_HEAVY) k_edges_heavy(EdgeArgs a) {
     extern __shared__ uint64_t sm_edgeh[];
     __shared__ uint32_t meta[4];
@@ -975,7 +978,7 @@ __global__ void __launch_bounds__(EDGE_THREADS_HEAVY) k_edges_heavy(EdgeArgs a) 
         __threadfence_block();
         __syncthreads();
         edge_cliques<NT>(a, i, j, S, TMs, F, tid);
-        if (a.xyk) {
+        if constexpr (MODE == 0) {
             store_xyk(a, e, S.Xi, tid, NT);
         } else {
             if (tid == 0) {
@@ -984,7 +987,7 @@ __global__ void __launch_bounds__(EDGE_THREADS_HEAVY) k_edges_heavy(EdgeArgs a) 
                 slot_j[0] = j;
             }
             __syncthreads();
-            edge_derive<NT>(a, 1, slot_e, slot_i, slot_j, S.Xi, hist, tid, bad);
+            edge_derive<NT, MODE == 1>(a, 1, slot_e, slot_i, slot_j, S.Xi, hist, tid, bad);
         }
         __threadfence_block();
         __syncthreads();
@@ -1000,15 +1003,12 @@ __global__ void __launch_bounds__(EDGE_THREADS_HEAVY) k_edges_heavy(EdgeArgs a) 
 // Deferred derivation: one thread per (edge, type pair) over the whole
 // edge set, reading each edge's Xi, Xj, Y, K from a.xyk; the 3-node entries
 // ride on the pairs p < L and the 2-node entry on p = 0.
-__global__ void __launch_bounds__(256) k_derive(EdgeArgs a) {
-    extern __shared__ uint64_t sm_der[];
-    uint64_t *hist = sm_der;
+template <typename XT, bool NARROW>
+__device__ void derive_edges(const EdgeArgs &a, uint64_t *hist, uint32_t &bad) {
     const int L = a.L;
     const int LL = L * L;
     const int P = L * (L + 1) / 2;
-    for (int q = threadIdx.x; q < hist_words(a); q += blockDim.x) hist[q] = 0;
-    __syncthreads();
-    uint32_t bad = 0;
+    const XT *xyk = reinterpret_cast<const XT *>(a.xyk);
     const int64_t total = a.m * P;
     for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
          it += (int64_t)gridDim.x * blockDim.x) {
@@ -1017,12 +1017,20 @@ __global__ void __launch_bounds__(256) k_derive(EdgeArgs a) {
         const int32_t i = a.ei[e], j = a.ej[e];
         if (p == 0) hist_add(a, hist, rank2(a.ntype[i], a.ntype[j]), 1, 0);
         if (p < L) derive_three(a, e, i, j, p, hist, bad);
-        if (a.xyk_u32)
-            derive_pair(a, e, i, j, p, reinterpret_cast<const uint32_t *>(a.xyk) + (size_t)e * 4 * LL,
-                        hist, bad);
-        else
-            derive_pair(a, e, i, j, p, a.xyk + (size_t)e * 4 * LL, hist, bad);
+        derive_pair<XT, NARROW>(a, e, i, j, p, xyk + (size_t)e * 4 * LL, hist, bad);
     }
+}
+
+// One instance per word width (chosen at launch), so each keeps the
+// registers of a single derivation loop.
+template <typename XT, bool NARROW>
+__global__ void __launch_bounds__(256) k_derive(EdgeArgs a) {
+    extern __shared__ uint64_t sm_der[];
+    uint64_t *hist = sm_der;
+    for (int q = threadIdx.x; q < hist_words(a); q += blockDim.x) hist[q] = 0;
+    __syncthreads();
+    uint32_t bad = 0;
+    derive_edges<XT, NARROW>(a, hist, bad);
     __syncthreads();
     if (a.hist_in_lds)
         for (int q = threadIdx.x; q < a.gw; q += blockDim.x) {
@@ -1062,16 +1070,29 @@ size_t edge_lds_bytes(const EdgeArgs &args, bool heavy) {
 hipError_t launch_edges(bool heavy, const EdgeArgs &args, unsigned grid, hipStream_t st) {
     if (grid == 0) return hipSuccess;
     size_t sh = edge_lds_bytes(args, heavy);
-    if (heavy) k_edges_heavy<<<grid, EDGE_THREADS_HEAVY, sh, st>>>(args);
-    else if (args.xyk) k_edges_light_deferred<<<grid, 64, sh, st>>>(args);
-    else k_edges_light_fused<<<grid, 64, sh, st>>>(args);
+    if (heavy) {
+        if (args.xyk) k_edges_heavy<0><<<grid, EDGE_THREADS_HEAVY, sh, st>>>(args);
+        else if (args.agg_u32) k_edges_heavy<1><<<grid, EDGE_THREADS_HEAVY, sh, st>>>(args);
+        else k_edges_heavy<2><<<grid, EDGE_THREADS_HEAVY, sh, st>>>(args);
+    } else if (args.xyk) {
+        k_edges_light_deferred<<<grid, 64, sh, st>>>(args);
+    } else if (args.agg_u32) {
+        k_edges_light_fused<true><<<grid, 64, sh, st>>>(args);
+    } else {
+        k_edges_light_fused<false><<<grid, 64, sh, st>>>(args);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_derive(const EdgeArgs &args, unsigned grid, hipStream_t st) {
     if (grid == 0 || args.m == 0) return hipSuccess;
     const int hw = args.hist_in_lds == 2 ? (args.gw + 1) / 2 : args.hist_in_lds ? args.gw : 0;
-    k_derive<<<grid, 256, (size_t)hw * sizeof(uint64_t), st>>>(args);
+    const size_t sh = (size_t)hw * sizeof(uint64_t);
+    // the 32-bit xyk words come with 32-bit A, D and NC (both follow from
+    // the largest degree)
+    if (args.xyk_u32 && args.agg_u32) k_derive<uint32_t, true><<<grid, 256, sh, st>>>(args);
+    else if (args.agg_u32) k_derive<uint64_t, true><<<grid, 256, sh, st>>>(args);
+    else k_derive<uint64_t, false><<<grid, 256, sh, st>>>(args);
     return hipGetLastError();
 }
 

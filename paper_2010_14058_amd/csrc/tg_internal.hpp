@@ -129,8 +129,7 @@ struct EdgeArgs {
     const uint8_t *ctype;        // type of the neighbour at each adjacency slot        // typed degrees per node, rows of tri_pitch(L)
     const uint32_t *tri_slot;    // typed triangle counts per slot, rows of tri_pitch(L)
     const uint64_t *A, *D, *NC;
-    int ad_u32;                  // A and D stored as uint32 (every degree below 2^16)
-    int nc_u32;                  // NC stored as uint32 (every degree below 2^16)
+    int agg_u32;                 // A, D and NC stored as uint32 (every degree below 2^16)
     int64_t m;
     int L;
     uint64_t *rows;      // may be null
