@@ -918,9 +918,10 @@ __device__ __forceinline__ void edges_light_body(const EdgeArgs &a) {
     if (lane == 0 && bad) atomicOr(a.status, bad);
 }
 
-// The deferred variant holds no derivation state; a register budget for five
-// waves per SIMD keeps more edges in flight.
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5)))
+// The deferred variant holds no derivation state; a register budget for six
+// waves per SIMD keeps more edges in flight (a few spilled registers cost
+// less than the fifth-to-sixth wave gains; seven or eight spill too much).
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6)))
 k_edges_light_deferred(EdgeArgs a) {
     edges_light_body<true, false>(a);
 }
