@@ -269,7 +269,10 @@ __global__ void k_tdeg(const int64_t *__restrict__ nrp, const int32_t *__restric
 constexpr int TRI_GROUPS = 8;
 constexpr int TRI_LANES = WAVE / TRI_GROUPS;
 
-__global__ void k_tri(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
+// A register budget for eight waves per SIMD (two registers spill) hides more
+// of the probes' latency than seven waves do.
+__global__ void __attribute__((amdgpu_waves_per_eu(8)))
+k_tri(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
                       const uint8_t *__restrict__ ctype, const int32_t *__restrict__ ei,
                       const int32_t *__restrict__ ej, const uint32_t *__restrict__ eslot,
                       uint32_t *__restrict__ tri_slot, int64_t m, int L,
