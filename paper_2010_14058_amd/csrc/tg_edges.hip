@@ -197,13 +197,30 @@ __device__ __forceinline__ uint32_t ordered_append(bool flag, uint32_t &count, u
 struct EdgeShared {
     uint64_t *Xi, *Xj, *Y, *K;
     uint64_t *Tm;           // hub members as bits over hub indices
-    uint32_t *Th;           // hub members, unordered; member q at Th[q * th_step]
+    uint32_t *Th;           // hub members' hub indices; member q at Th[q * th_step]
+                            // (uint16 words, step 1, in the workgroup kernel)
     int th_step;            // +1, or -1 when Th grows down from the end of Tl's buffer
     uint32_t *Tl;           // low members, ascending
     uint32_t *meta;         // [0] |Tl| [1] |Th| [2] first word of Tm [3] last word
     uint32_t *wave_cnt;     // ordered_append scratch
     uint64_t *Gw;           // per-wave copies of Xi, Xj, Y (3 L^2 words each) or null
 };
+
+// Hub-member list: hub index (below HUB_MAX <= 2^16) of member q.  The
+// one-wave kernel shares a uint32 buffer with the low members (Th grows down
+// from its end); the workgroup kernel keeps a uint16 list of its own, half
+// the LDS, so that one more workgroup fits on a CU.
+template <int NT>
+__device__ __forceinline__ void th_put(const EdgeShared &S, uint32_t q, int hk) {
+    if constexpr (NT == WAVE) S.Th[(ptrdiff_t)q * S.th_step] = (uint32_t)hk;
+    else reinterpret_cast<uint16_t *>(S.Th)[q] = (uint16_t)hk;
+}
+
+template <int NT>
+__device__ __forceinline__ int th_get(const EdgeShared &S, uint32_t q) {
+    if constexpr (NT == WAVE) return (int)S.Th[(ptrdiff_t)q * S.th_step];
+    else return (int)reinterpret_cast<const uint16_t *>(S.Th)[q];
+}
 
 // Inclusive scan of one value per thread over the NT threads; *total (if
 // given) receives the sum over all of them.
@@ -339,7 +356,7 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
             while (m) {
                 const int b = __ffsll((unsigned long long)m) - 1;
                 m &= m - 1;
-                S.Th[(ptrdiff_t)pos * S.th_step] = (uint32_t)(base + q * 64 + b);
+                th_put<NT>(S, pos, q * 64 + b);
                 ++pos;
             }
             nh += all;
@@ -347,8 +364,8 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
         if (tid == 0) S.meta[1] = nh;
         group_sync<NT>();
         for (uint32_t f = tid; f < nh; f += NT) {
-            const int32_t k = (int32_t)S.Th[(ptrdiff_t)f * S.th_step];
-            const int hk = k - base;
+            const int hk = th_get<NT>(S, f);
+            const int32_t k = base + hk;
             gather_member(a, k, a.ntype[k], hub_slot(a, i, hx_i, hk), hub_slot(a, j, hx_j, hk), gXi,
                           gXj, gY);
         }
@@ -377,7 +394,7 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
             atomicMin(&S.meta[2], (uint32_t)(hk >> 6));
             atomicMax(&S.meta[3], (uint32_t)(hk >> 6));
             uint32_t pos = atomicAdd(&S.meta[1], 1u);
-            S.Th[(ptrdiff_t)pos * S.th_step] = (uint32_t)x;
+            th_put<NT>(S, pos, hk);
             gather_member(a, x, a.ctype[p], i_small ? p : q, i_small ? q : p, gXi, gXj, gY);
         }
     }
@@ -430,9 +447,8 @@ __device__ void edge_cliques(const EdgeArgs &a, int32_t i, int32_t j, const Edge
                 while (bb * (bb - 1) / 2 > f) --bb;
                 while ((bb + 1) * bb / 2 <= f) ++bb;
                 const uint32_t aa = f - bb * (bb - 1) / 2;
-                const int32_t k = (int32_t)S.Th[(ptrdiff_t)aa * S.th_step];
-                const int32_t x = (int32_t)S.Th[(ptrdiff_t)bb * S.th_step];
-                const int hk = k - base, hx = x - base;
+                const int hk = th_get<NT>(S, aa), hx = th_get<NT>(S, bb);
+                const int32_t k = base + hk, x = base + hx;
                 if ((a.HB[(size_t)hk * Hw + (hx >> 6)] >> (hx & 63)) & 1ull) {
                     const int tk = a.ntype[k], tx = a.ntype[x];
                     atomicAdd((unsigned long long *)&S.K[tk * L + tx], 1ull);
@@ -448,7 +464,7 @@ __device__ void edge_cliques(const EdgeArgs &a, int32_t i, int32_t j, const Edge
                 const uint32_t members = nTh - c0 < (uint32_t)NT ? nTh - c0 : (uint32_t)NT;
                 uint32_t len = 0;
                 if ((uint32_t)tid < members) {
-                    const int32_t k = (int32_t)S.Th[(ptrdiff_t)(c0 + tid) * S.th_step];
+                    const int32_t k = base + th_get<NT>(S, c0 + tid);
                     const uint32_t kb = (uint32_t)(k - base) >> 9;
                     const uint32_t sb = kb > b0 ? kb : b0;
                     len = sb < b1 ? b1 - sb : 0;
@@ -1064,7 +1080,7 @@ size_t edge_lds_bytes(const EdgeArgs &args, bool heavy) {
     if (!heavy) sh += (size_t)args.tcap * sizeof(uint32_t);
     else sh += (size_t)(tm_pitch(args.L) * args.Hw + 1) * sizeof(uint64_t) +
                (size_t)(EDGE_THREADS_HEAVY / WAVE) * 3 * LL * sizeof(uint64_t) +
-               (size_t)(args.hub_base < args.n ? (args.n - args.hub_base) : 0) * sizeof(uint32_t);
+               (size_t)(args.hub_base < args.n ? (args.n - args.hub_base) : 0) * sizeof(uint16_t);
     return sh;
 }
 
