@@ -189,7 +189,7 @@ const char *tg_last_error(void);
  *       4-cycle kernels; each owns a dense map of n*L*4 bytes of workspace.
  *   TG_TUNE_MAP_BYTES    (default 32 GiB, >= 1): workspace bytes for those
  *       maps; the slot count is cut to fit (at least one slot).
- *   TG_TUNE_EDGE_SLOTS   (default 1024, 1..65536): most workgroups of the
+ *   TG_TUNE_EDGE_SLOTS   (default 1280, 1..65536): most workgroups of the
  *       heavy-edge kernel; each owns a list of n*4 bytes of workspace.
  *   TG_TUNE_TBUF_BYTES   (default 8 GiB, >= 1): workspace bytes for those
  *       lists; the slot count is cut to fit (at least one slot).

@@ -35,7 +35,7 @@ SINGLE_SPACE: Dict[str, List[int]] = {
     "task_wedges": [1 << 16, 1 << 17, 1 << 18, 1 << 19],
     "clear_bytes": [0, 16, 64, 256],
     "cycle_slots": [512, 1024, 1536, 2048],
-    "edge_slots": [512, 1024, 1536, 2048],
+    "edge_slots": [512, 1024, 1280, 1536, 2048],
     "derive_edges": [0, 1, 2, 3],
     "light_wedges": [128, 256, 512],
     "edge_deg": [256, 512, 1024],

@@ -35,7 +35,7 @@ static bool ws_aligned(const void *p) { return ((uintptr_t)p & 255u) == 0; }
 // Bytes of dense cycle maps allowed; the number of heavy workgroups follows.
 static const size_t MAP_BUDGET = size_t(32) << 30;
 static const size_t TBUF_BUDGET = size_t(8) << 30;
-static const int MAX_HEAVY_SLOTS = 1024;   // heavy-edge workgroups
+static const int MAX_HEAVY_SLOTS = 1280;   // heavy-edge workgroups (5 per CU)
 static const int MAX_CYCLE_SLOTS = 2048;   // heavy 4-cycle workgroups (map budget permitting)
 // Largest per-edge buffer of triangle-set sums for a separate derivation pass.
 static const size_t XYK_BUDGET = size_t(16) << 30;

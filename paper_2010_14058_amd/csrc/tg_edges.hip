@@ -953,8 +953,12 @@ __global__ void __launch_bounds__(64) k_edges_light_fused(EdgeArgs a) {
 // Xj, Y, K for the separate derivation; 1 and 2 derive in place with 32-bit
 // and 64-bit A, D and NC (one instance each, so that the deferred one holds
 // no derivation state).
+// The deferred instance runs under a register budget for five waves per SIMD
+// (some registers spill): with the uint16 hub list, five workgroups fit a
+// CU's LDS.
 template <int MODE>
-__global__ void __launch_bounds__(EDGE_THREADS_HEAVY) k_edges_heavy(EdgeArgs a) {
+__global__ void __launch_bounds__(EDGE_THREADS_HEAVY)
+__attribute__((amdgpu_waves_per_eu(MODE == 0 ? 5 : 1))) k_edges_heavy(EdgeArgs a) {
     extern __shared__ uint64_t sm_edgeh[];
     __shared__ uint32_t meta[4];
     __shared__ uint32_t wave_cnt[EDGE_THREADS_HEAVY / WAVE];
