@@ -102,7 +102,7 @@ def setup_tuning(args, workload: str, run) -> dict:
     if args.autotune:
         space = AT.BATCH_SPACE if args.mode == "batch" else AT.SINGLE_SPACE
         log(f"[bench] autotuning {len(space)} knobs on {workload}")
-        res = AT.tune(run, space, log=log)
+        res = AT.tune(run, space, min_gain=args.tune_min_gain, log=log)
         if args.tune_out:
             AT.save(res, args.tune_out, workload)
         return {"profile": "tuned in this run", "knobs": res.best,
@@ -372,6 +372,8 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="tune the scheduling knobs on this workload before timing")
     ap.add_argument("--tune-out", default=None, help="with --autotune: write the profile here")
+    ap.add_argument("--tune-min-gain", type=float, default=0.02,
+                    help="with --autotune: least relative gain that changes a knob")
     ap.add_argument("--no-tuned", action="store_true",
                     help="ignore the tuned profile, time the library defaults")
     ap.add_argument("--calib-copy", action="store_true",

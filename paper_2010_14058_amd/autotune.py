@@ -38,7 +38,7 @@ SINGLE_SPACE: Dict[str, List[int]] = {
     "edge_slots": [512, 1024, 1280, 1536, 2048],
     "derive_edges": [0, 1, 2, 3],
     "light_wedges": [128, 256, 512],
-    "edge_deg": [256, 512, 1024],
+    "edge_deg": [512, 640, 768, 832, 896, 1024],
 }
 BATCH_SPACE: Dict[str, List[int]] = {
     "light_wedges": [64, 128, 256, 512],
