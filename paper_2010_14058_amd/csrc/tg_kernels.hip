@@ -1200,7 +1200,9 @@ hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32
 // L^2 words per item within 32 KB (256 threads) or 50 KB (512 or more), so
 // a workgroup stays under 64 KB of LDS for every L.
 int heavy_chunk_for(int L, int threads) {
-    const int budget = threads >= 512 ? 51200 : 32768;  // staging arrays: 24 B per item
+    // LDS for the per-item tallies: a 1024-thread workgroup runs alone on
+    // its CU (registers), so it may take twice the budget of smaller ones
+    const int budget = threads >= 1024 ? 102400 : threads >= 512 ? 51200 : 32768;
     int ch = budget / (L * L * 8);
     if (ch > threads / 2) ch = threads / 2;
     if (ch < 1) ch = 1;
