@@ -86,3 +86,22 @@ def test_profile_roundtrip(tmp_path, restore_knobs):
     assert now["light_wedges"] == 256 and now["edge_deg"] == 512
     with pytest.raises(ValueError):
         AT.tune(lambda: 0, {"no_such_knob": [1]}, log=None)
+
+
+def test_shipped_profiles_apply(restore_knobs):
+    """Every profile under paper_2010_14058_amd/tuned/ names its workload,
+    holds only known knobs, and is accepted by the library as it stands."""
+    import glob
+    import os
+
+    d = os.path.join(os.path.dirname(AT.__file__), "tuned")
+    paths = sorted(glob.glob(os.path.join(d, "*.json")))
+    assert paths
+    for p in paths:
+        prof = AT.load(p)
+        assert prof["workload"] == os.path.basename(p)[:-5]
+        AT.apply(prof)
+        now = _lib.get_tuning()
+        for k, v in prof["knobs"].items():
+            assert now[k] == v, (p, k)
+        assert prof["best_ms"] <= prof["start_ms"]
