@@ -657,10 +657,8 @@ __device__ __forceinline__ void store_xyk(const EdgeArgs &a, int64_t e, const ui
 // for type t, and of its 4-node orbits for type pair p; xyk holds the edge's
 // Xi, Xj, Y, K (4 L^2 words, in LDS or global memory).
 __device__ __forceinline__ void derive_three(const EdgeArgs &a, int64_t e, int32_t i, int32_t j,
-                                             int t, uint64_t *hist, uint32_t &bad) {
+                                             int t, uint64_t *hist, uint32_t &bad, uint64_t *row) {
     const int L = a.L;
-    const int P = L * (L + 1) / 2;
-    const int W = 2 * L + 10 * P;
     const int n2 = (int)binom_small(L + 1, 2);
     const int n3 = (int)binom_small(L + 2, 3);
     const int64_t gid = a.batch ? (int64_t)a.ngraph[i] : 0;
@@ -670,8 +668,7 @@ __device__ __forceinline__ void derive_three(const EdgeArgs &a, int64_t e, int32
     int64_t si = (int64_t)a.tdeg[(size_t)i * LP + t] - nTt - (tb == t);
     int64_t sj = (int64_t)a.tdeg[(size_t)j * LP + t] - nTt - (ta == t);
     if (si < 0 || sj < 0) bad |= ST_INTERNAL;
-    if (a.rows) {
-        uint64_t *row = a.rows + (size_t)e * W;
+    if (row) {
         row[t] = (uint64_t)nTt;
         row[L + t] = (uint64_t)(si + sj);
     }
@@ -684,12 +681,11 @@ __device__ __forceinline__ void derive_three(const EdgeArgs &a, int64_t e, int32
 template <typename XT, bool NARROW>
 __device__ __forceinline__ void derive_pair(const EdgeArgs &a, int64_t e, int32_t i, int32_t j,
                                             int p, const XT *xyk, uint64_t *hist,
-                                            uint32_t &bad) {
+                                            uint32_t &bad, uint64_t *row) {
     using AT = typename std::conditional<NARROW, uint32_t, uint64_t>::type;
     const int L = a.L;
     const int LL = L * L;
     const int P = L * (L + 1) / 2;
-    const int W = 2 * L + 10 * P;
     const int n2 = (int)binom_small(L + 1, 2);
     const int n3 = (int)binom_small(L + 2, 3);
     const int n4 = (int)binom_small(L + 3, 4);
@@ -704,7 +700,6 @@ __device__ __forceinline__ void derive_pair(const EdgeArgs &a, int64_t e, int32_
     const AT *Ai = Ab + (size_t)i * LL, *Aj = Ab + (size_t)j * LL;
     const AT *Di = Db + (size_t)i * LL, *Dj = Db + (size_t)j * LL;
     const AT *NC = reinterpret_cast<const AT *>(a.NC) + (size_t)e * LL;
-    uint64_t *row = a.rows ? a.rows + (size_t)e * W : nullptr;
     // pair (t, u), t <= u, from its lexicographic index
     int t = 0, rem = p;
     while (rem >= L - t) { rem -= L - t; ++t; }
@@ -782,6 +777,7 @@ __device__ void edge_derive(const EdgeArgs &a, int nb, const int64_t *slot_e, co
     const int L = a.L;
     const int LL = L * L;
     const int P = L * (L + 1) / 2;
+    const int W = 2 * L + 10 * P;
     for (int b = tid; b < nb; b += NT) {
         const int32_t i = slot_i[b], j = slot_j[b];
         const int64_t gid = a.batch ? (int64_t)a.ngraph[i] : 0;
@@ -789,12 +785,14 @@ __device__ void edge_derive(const EdgeArgs &a, int nb, const int64_t *slot_e, co
     }
     for (int it = tid; it < nb * L; it += NT) {
         const int b = it / L;
-        derive_three(a, slot_e[b], slot_i[b], slot_j[b], it - b * L, hist, bad);
+        derive_three(a, slot_e[b], slot_i[b], slot_j[b], it - b * L, hist, bad,
+                     a.rows ? a.rows + (size_t)slot_e[b] * W : nullptr);
     }
     for (int it = tid; it < nb * P; it += NT) {
         const int b = it / P;
         derive_pair<uint64_t, NARROW>(a, slot_e[b], slot_i[b], slot_j[b], it - b * P,
-                                      xyk + (size_t)b * 4 * LL, hist, bad);
+                                      xyk + (size_t)b * 4 * LL, hist, bad,
+                                      a.rows ? a.rows + (size_t)slot_e[b] * W : nullptr);
     }
 }
 
@@ -1024,21 +1022,35 @@ __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 5 : 1))) k_edges_heavy(EdgeArgs a
 // Deferred derivation: one thread per (edge, type pair) over the whole
 // edge set, reading each edge's Xi, Xj, Y, K from a.xyk; the 3-node entries
 // ride on the pairs p < L and the 2-node entry on p = 0.
+// A block takes EB = blockDim / P consecutive edges at a time, one thread per
+// (edge, type pair); their rows are assembled in LDS (rbuf, EB rows) and then
+// written out whole, so the table is written in full lines.
 template <typename XT, bool NARROW>
-__device__ void derive_edges(const EdgeArgs &a, uint64_t *hist, uint32_t &bad) {
+__device__ void derive_edges(const EdgeArgs &a, uint64_t *hist, uint64_t *rbuf, uint32_t &bad) {
     const int L = a.L;
     const int LL = L * L;
     const int P = L * (L + 1) / 2;
+    const int W = 2 * L + 10 * P;
+    const int EB = (int)blockDim.x / P;
     const XT *xyk = reinterpret_cast<const XT *>(a.xyk);
-    const int64_t total = a.m * P;
-    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
-         it += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t e = it / P;
-        const int p = (int)(it - e * P);
-        const int32_t i = a.ei[e], j = a.ej[e];
-        if (p == 0) hist_add(a, hist, rank2(a.ntype[i], a.ntype[j]), 1, 0);
-        if (p < L) derive_three(a, e, i, j, p, hist, bad);
-        derive_pair<XT, NARROW>(a, e, i, j, p, xyk + (size_t)e * 4 * LL, hist, bad);
+    const int tid = threadIdx.x;
+    const int b = tid / P, p = tid - b * P;
+    for (int64_t e0 = (int64_t)blockIdx.x * EB; e0 < a.m; e0 += (int64_t)gridDim.x * EB) {
+        const int nb = a.m - e0 < EB ? (int)(a.m - e0) : EB;
+        if (b < nb) {
+            const int64_t e = e0 + b;
+            const int32_t i = a.ei[e], j = a.ej[e];
+            uint64_t *row = rbuf ? rbuf + (size_t)b * W : nullptr;
+            if (p == 0) hist_add(a, hist, rank2(a.ntype[i], a.ntype[j]), 1, 0);
+            if (p < L) derive_three(a, e, i, j, p, hist, bad, row);
+            derive_pair<XT, NARROW>(a, e, i, j, p, xyk + (size_t)e * 4 * LL, hist, bad, row);
+        }
+        if (rbuf) {  // the same for the whole block
+            __syncthreads();
+            uint64_t *dst = a.rows + (size_t)e0 * W;
+            for (int q = tid; q < nb * W; q += blockDim.x) dst[q] = rbuf[q];
+            __syncthreads();
+        }
     }
 }
 
@@ -1051,7 +1063,7 @@ __global__ void __launch_bounds__(256) k_derive(EdgeArgs a) {
     for (int q = threadIdx.x; q < hist_words(a); q += blockDim.x) hist[q] = 0;
     __syncthreads();
     uint32_t bad = 0;
-    derive_edges<XT, NARROW>(a, hist, bad);
+    derive_edges<XT, NARROW>(a, hist, a.rows ? sm_der + hist_words(a) : nullptr, bad);
     __syncthreads();
     if (a.hist_in_lds)
         for (int q = threadIdx.x; q < a.gw; q += blockDim.x) {
@@ -1108,7 +1120,11 @@ hipError_t launch_edges(bool heavy, const EdgeArgs &args, unsigned grid, hipStre
 hipError_t launch_derive(const EdgeArgs &args, unsigned grid, hipStream_t st) {
     if (grid == 0 || args.m == 0) return hipSuccess;
     const int hw = args.hist_in_lds == 2 ? (args.gw + 1) / 2 : args.hist_in_lds ? args.gw : 0;
-    const size_t sh = (size_t)hw * sizeof(uint64_t);
+    // LDS: the histogram, then the rows of blockDim / P edges
+    const int P = args.L * (args.L + 1) / 2;
+    const int W = 2 * args.L + 10 * P;
+    const size_t rw = args.rows ? (size_t)(256 / P) * W : 0;
+    const size_t sh = ((size_t)hw + rw) * sizeof(uint64_t);
     // the 32-bit xyk words come with 32-bit A, D and NC (both follow from
     // the largest degree)
     if (args.xyk_u32 && args.agg_u32) k_derive<uint32_t, true><<<grid, 256, sh, st>>>(args);
