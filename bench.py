@@ -54,6 +54,8 @@ def kernel_source_sha() -> str:
 
 
 def host_threads() -> int:
+    """Worker threads for the CPU oracle: every CPU this process may run on,
+    capped at 16 (the CPU share one GPU gets on the benchmark machines)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
@@ -61,35 +63,118 @@ def host_threads() -> int:
     return max(1, min(16, n))
 
 
-def algorithmic_bytes(g, L, stats, heavy_edge_info):
-    """Bytes each kernel must move with no cache reuse, from this run's unit counts."""
+def host_info() -> dict:
+    """CPU model, sockets, cores and threads of the host (lscpu), and the
+    CPUs this process may use."""
+    info = {}
+    try:
+        import subprocess
+
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            info[k.strip()] = v.strip()
+    except Exception:  # lscpu missing: report what os says
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"model": info.get("Model name"), "sockets": info.get("Socket(s)"),
+            "cores_per_socket": info.get("Core(s) per socket"),
+            "threads_per_core": info.get("Thread(s) per core"), "cpus": info.get("CPU(s)"),
+            "usable_cpus": usable, "oracle_threads": host_threads()}
+
+
+def rank_order(d: np.ndarray) -> np.ndarray:
+    """Node ids in the library's internal order: ascending (degree, id)."""
+    ids = np.arange(d.size, dtype=np.int64)
+    return np.lexsort((ids, d))
+
+
+def ceil_log2p1(x: np.ndarray) -> np.ndarray:
+    """Steps of a binary search over x entries: ceil(log2(x + 1))."""
+    return np.ceil(np.log2(x.astype(np.float64) + 1.0))
+
+
+def algorithmic_bytes(g, L, stats, members, members_heavy, edge_deg):
+    """Bytes each kernel must move with no cache reuse, from this run's unit
+    counts and the graph.
+
+    Cycle passes: 8 B per wedge, 4 B to build (the target id read while
+    counting) and 4 B to probe (the same target met again when emitting).
+    Triangles and the triangle-set build: the shorter row of each edge is
+    walked (4 B per entry and its 1-byte type) and each entry is probed in
+    the other endpoint: one 8-byte bitmap word when that endpoint has a
+    super-hub bitmap (or both are in the hub core), else a binary search of
+    ceil(log2(d + 1)) 4-byte reads.  Clique walks are not priced (a lower
+    bound).  Per-edge and per-node fixed reads and writes as listed."""
     n, m, nnz = g.n, g.m, g.nnz
-    d = g.degrees().astype(np.float64)
-    sum_d2 = float(np.sum(d * d))
+    d = g.degrees().astype(np.int64)
+    uv = g.edges()
     P = L * (L + 1) // 2
     W = 2 * L + 10 * P
-    tri_slots = float(stats["triangle_slots"])
-    per_wedge = 16 + 4 * L
-    hv_d, hv_t, hv_m = heavy_edge_info
-    narrow = float(d.max(initial=0)) < 65536  # 32-bit node aggregates and X_i, X_j, Y, K
-    edge_fixed = (20 if narrow else 40) * L * L + 8 * W  # A_i, A_j, D_i, D_j, NC, row
-    per_t = 12 * L + 8                        # tri(i,k), tri(j,k), d_k^., slot ids
-    # X_i, X_j, Y, K: written by the edge kernels, read by the derivation pass
-    xyk = (16 if narrow else 32) * L * L
-    b = {
+    LP = (L + 3) & ~3
+    LL = L * L
+    narrow = int(d.max(initial=0)) < 65536
+    aw = 4 if narrow else 8                 # word of A, D, NC and X_i, X_j, Y, K
+    order = rank_order(d)
+    rank = np.empty(n, np.int64)
+    rank[order] = np.arange(n)
+    H = int(stats.get("hub_core", 0))
+    S = int(stats.get("superhubs", 0))
+    is_hub = rank >= n - H
+    is_sh = rank >= n - S
+    # hub-core neighbours per node
+    src = np.repeat(np.arange(n), d)
+    hubcnt = np.bincount(src, weights=is_hub[g.col].astype(np.float64), minlength=n)
+    du, dv = d[uv[:, 0]], d[uv[:, 1]]
+    s_is_u = du <= dv
+    ds = np.where(s_is_u, du, dv).astype(np.float64)
+    b = np.where(s_is_u, uv[:, 1], uv[:, 0])
+    s = np.where(s_is_u, uv[:, 0], uv[:, 1])
+    hs = hubcnt[s]
+    bs = 4.0 * ceil_log2p1(d[b])
+    probe = np.where(is_sh[b], 8.0 * ds,
+                     np.where(is_hub[b], 8.0 * hs + bs * (ds - hs), bs * ds))
+    tri = float(np.sum(5.0 * ds + probe)) + m * (8 + 8 + 32 + 4 * L + 8 * LP)
+    # triangle-set build: low prefixes (non-hub neighbours) walked and
+    # probed, hub members from two bit rows or the shorter hub suffix
+    low = d - hubcnt
+    lu, lv = low[uv[:, 0]], low[uv[:, 1]]
+    ls = np.minimum(lu, lv)
+    lo_other = np.where(lu <= lv, uv[:, 1], uv[:, 0])
+    lprobe = np.where(is_sh[lo_other], 8.0 * ls, 4.0 * ceil_log2p1(low[lo_other]) * ls)
+    hw = 8 * (((H + 63) // 64 + 7) // 8) if H else 0
+    both_hub = is_hub[uv[:, 0]] & is_hub[uv[:, 1]]
+    hu, hv = hubcnt[uv[:, 0]], hubcnt[uv[:, 1]]
+    hsmall = np.minimum(hu, hv)
+    hpart = np.where(both_hub, 16.0 * hw, 5.0 * hsmall + 8.0 * hsmall)
+    per_edge_build = 5.0 * ls + lprobe + hpart
+    heavy = np.minimum(du, dv) > int(edge_deg)
+    per_member = 12 * LP + 8                    # three gathered rows and two slots
+    hv_share = float(np.sum(per_edge_build[heavy]))
+    b_all = float(np.sum(per_edge_build))
+    nh = int(heavy.sum())
+    xyk = 4 * LL * aw
+    wa, wah = stats["wedges_pass_a"], stats["heavy_wedges_pass_a"]
+    wb, wbh = stats["wedges_pass_b"], stats["heavy_wedges_pass_b"]
+    out = {
         "prep": 8 * (n + 1) + 4 * nnz + n + 8 * (n + 1) + 8 * nnz + 8 * m + 4 * n * L,
-        "tri": 4 * sum_d2 + 4 * L * m,
-        "aggr": nnz * (8 + 8 * L) + (8 if narrow else 16) * n * L * L,
-        "cyc_work": 8 * nnz,
-        "cycA_light": (stats["wedges_pass_a"] - stats["heavy_wedges_pass_a"]) * per_wedge,
-        "cycA_heavy": stats["heavy_wedges_pass_a"] * per_wedge,
-        "cycB_light": (stats["wedges_pass_b"] - stats["heavy_wedges_pass_b"]) * per_wedge,
-        "cycB_heavy": stats["heavy_wedges_pass_b"] * per_wedge,
-        "edges_light": 4 * (sum_d2 - hv_d) + (m - hv_m) * xyk + (tri_slots - hv_t) * per_t,
-        "edges_heavy": 4 * hv_d + hv_m * xyk + hv_t * per_t,
-        "derive": m * (edge_fixed + xyk),
+        "tri": tri,
+        "aggr": nnz * (4 + 1 + 8 * LP) + 2 * aw * n * LL,
+        "cyc_work": 28 * nnz,
+        "cycA_light": 8 * (wa - wah),
+        "cycA_heavy": 8 * wah,
+        "cycB_light": 8 * (wb - wbh),
+        "cycB_heavy": 8 * wbh,
+        "edges_light": (b_all - hv_share) + (members - members_heavy) * per_member
+                       + (m - nh) * (xyk + 56),
+        "edges_heavy": hv_share + members_heavy * per_member + nh * (xyk + 56),
+        "derive": m * (5 * LL * aw + xyk + 4 * L + 8 * LP + 8 * W),
     }
-    return {k: float(v) for k, v in b.items()}
+    scratch = {"cycA_heavy": (16 + 4 * L) * wah, "cycB_heavy": (16 + 4 * L) * wbh}
+    return {k: float(v) for k, v in out.items()}, scratch
 
 
 def setup_tuning(args, workload: str, run) -> dict:
@@ -348,6 +433,322 @@ def bench_serve(args):
     print(json.dumps(result), flush=True)
 
 
+def stream_peak(dev, nbytes=1 << 31, reps=10) -> dict:
+    """Measured streaming bandwidth of the device: a plain device-to-device
+    copy of `nbytes`, timed with HIP events over `reps` copies (bytes read
+    plus bytes written per copy)."""
+    import torch
+
+    a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"GBps": 2 * nbytes / (ms * 1e-3) / 1e9, "copy_bytes": nbytes, "ms_per_copy": ms,
+            "method": "device-to-device copy, read + write bytes over HIP-event time"}
+
+
+def transfer_timings(g, rows, dev) -> dict:
+    """Host-device transfer rates: the graph's input arrays to the device
+    (pageable and pinned host memory) and a slice of the per-edge table back
+    to pinned host memory (the full-table time is that rate applied to the
+    table's size)."""
+    import torch
+
+    arrays = [g.row_ptr, g.col, g.types]
+    nbytes = sum(a.nbytes for a in arrays)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [torch.from_numpy(a).to(dev) for a in arrays]
+    torch.cuda.synchronize()
+    pageable_s = time.perf_counter() - t0
+    pinned = [torch.from_numpy(a).pin_memory() for a in arrays]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [p.to(dev, non_blocking=True) for p in pinned]
+    torch.cuda.synchronize()
+    pinned_s = time.perf_counter() - t0
+    del outs, pinned
+    res = {"h2d_input_bytes": nbytes, "h2d_pageable_ms": pageable_s * 1e3,
+           "h2d_pageable_GBps": nbytes / pageable_s / 1e9, "h2d_pinned_ms": pinned_s * 1e3,
+           "h2d_pinned_GBps": nbytes / pinned_s / 1e9}
+    if rows is not None and rows.numel():
+        k = max(1, min(rows.shape[0], (1 << 31) // (rows.shape[1] * 8)))
+        host = torch.empty((k, rows.shape[1]), dtype=rows.dtype, pin_memory=True)
+        host.copy_(rows[:k])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        host.copy_(rows[:k])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sl = k * rows.shape[1] * 8
+        full = rows.shape[0] * rows.shape[1] * 8
+        res.update({"d2h_slice_bytes": sl, "d2h_pinned_GBps": sl / dt / 1e9,
+                    "d2h_full_table_ms_at_that_rate": full / (sl / dt) * 1e3})
+        del host
+    return res
+
+
+def time_graph(P, torch, g, dev, steps, warmup, rows, glob, ws, stream, tag):
+    """Warm-up calls, then `steps` timed calls of the library on g; returns
+    wall-clock seconds, per-step event times and the per-phase averages."""
+    L = g.L
+    P.set_timing(True)
+    for w in range(warmup):
+        P.count_typed_graphlets(g._dev[0], g._dev[1], g._dev[2], L, out_rows=rows,
+                                out_global=glob, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        log(f"[bench] {tag} warmup {w + 1}/{warmup} done")
+    phase_sum = {}
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for q in range(steps):
+        evs[q][0].record(stream)
+        P.count_typed_graphlets(g._dev[0], g._dev[1], g._dev[2], L, out_rows=rows,
+                                out_global=glob, workspace=ws, stream=stream)
+        evs[q][1].record(stream)
+        for name, ms in P.phase_times():
+            phase_sum[name] = phase_sum.get(name, 0.0) + ms
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    step_ms = [a.elapsed_time(b) for a, b in evs]
+    P.set_timing(False)
+    return elapsed, step_ms, {k: v / max(steps, 1) for k, v in phase_sum.items()}
+
+
+def roofline_of(P, torch, g, rows, stats, phase_avg, peak_stream):
+    """Per-kernel algorithmic bytes and rates; the roofline entry of the
+    kernel with the largest average time."""
+    L = g.L
+    uv = g.edges()
+    d = g.degrees()
+    edge_deg = P.get_tuning()["edge_deg"]
+    hv = np.minimum(d[uv[:, 0]], d[uv[:, 1]]) > edge_deg
+    hv_idx = torch.from_numpy(np.nonzero(hv)[0]).to(rows.device)
+    members = float(stats["triangle_slots"])
+    members_heavy = float(rows.index_select(0, hv_idx)[:, :L].sum().item()) if hv_idx.numel() else 0.0
+    abytes, scratch = algorithmic_bytes(g, L, stats, members, members_heavy, edge_deg)
+    kernels = [k for k in abytes if k != "prep" and k in phase_avg]
+    per_kernel = {}
+    over = []
+    for k in kernels:
+        gbps = abytes[k] / (phase_avg[k] * 1e-3) / 1e9 if phase_avg[k] > 0 else 0.0
+        per_kernel[k] = {"ms": round(phase_avg[k], 3), "algorithmic_GB": round(abytes[k] / 1e9, 3),
+                         "algorithmic_GBps": round(gbps, 1)}
+        if gbps > HBM_PEAK_GBS:
+            over.append(k)
+    if over:
+        log(f"[bench] WARNING: byte model above the HBM peak for {over}")
+    dom = max(kernels, key=lambda k: phase_avg[k])
+    dom_ms = phase_avg[dom]
+    achieved = abytes[dom] / (dom_ms * 1e-3) / 1e9
+    units = {"cycA_heavy": ("wedge", stats["heavy_wedges_pass_a"]),
+             "cycB_heavy": ("wedge", stats["heavy_wedges_pass_b"])}.get(dom, ("edge", g.m))
+    roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(dom),
+            "avg_ms": dom_ms, "algorithmic_bytes_per_launch": abytes[dom],
+            "work_unit": units[0], "units_per_launch": int(units[1]),
+            "streaming_peak_GBps": peak_stream, "frac_of_streaming_peak":
+                achieved / peak_stream if peak_stream else None}
+    if dom in scratch:
+        roof["map_scratch_bytes_per_launch"] = scratch[dom]
+    return roof, per_kernel, over, abytes
+
+
+def parity_sample(g, rows, dev, k_uniform, per_hub, top, threads, seed):
+    """Sampled rows of the GPU table against the oracle (uniform edges and
+    edges at the top-degree nodes)."""
+    import torch
+
+    import oracle
+
+    uv = g.edges()
+    rng = np.random.default_rng(seed)
+    pick = set(rng.choice(uv.shape[0], size=min(k_uniform, uv.shape[0]), replace=False).tolist())
+    d = g.degrees()
+    for h in np.argsort(-d, kind="stable")[:top]:
+        inc = np.nonzero((uv[:, 0] == h) | (uv[:, 1] == h))[0]
+        pick.update(rng.choice(inc, size=min(per_hub, inc.size), replace=False).tolist())
+    pick = np.array(sorted(pick), dtype=np.int64)
+    t0 = time.perf_counter()
+    want = oracle.edge_rows(g, uv[pick], method="paper", threads=threads)
+    dt = time.perf_counter() - t0
+    got = rows.index_select(0, torch.from_numpy(pick).to(dev)).cpu().numpy().view(np.uint64)
+    same = int(np.sum(np.all(got == want, axis=1)))
+    return same, int(pick.size), dt
+
+
+def bench_single(args):
+    import torch
+
+    import paper_2010_14058_amd as P
+    from tg_synth import graphs as G
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    defaults = P.get_tuning()
+    host = host_info()
+    peak = stream_peak(dev)
+    log(f"[bench] streaming copy: {peak['GBps']:.1f} GB/s")
+    if args.calib_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("[bench] calibration copy of 1 GiB done")
+
+    t0 = time.perf_counter()
+    g = G.config_graph(2, seed=0, scale=args.scale)
+    st = g.stats()
+    gen_s = time.perf_counter() - t0
+    log(f"[bench] graph {st['name']}: n={st['n']} m={st['m']} max_degree={st['max_degree']} "
+        f"same_type={st['same_type_edge_fraction']:.4f} ({gen_s:.1f}s)")
+    L = g.L
+    g._dev = (torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev),
+              torch.from_numpy(g.types).to(dev))
+    W = P.row_width(L)
+    rows = torch.empty((g.m, W), dtype=torch.int64, device=dev)
+    glob = torch.empty(P.global_width(L), dtype=torch.int64, device=dev)
+    ws = P.Workspace(dev)
+
+    def run_once():
+        from paper_2010_14058_amd import autotune as AT
+
+        P.count_typed_graphlets(*g._dev, L, out_rows=rows, out_global=glob, workspace=ws,
+                                stream=stream)
+        torch.cuda.synchronize()
+        return AT.digest_of(glob, rows)
+
+    tuning = setup_tuning(args, st["name"], run_once)
+    elapsed, step_ms, phase_avg = time_graph(P, torch, g, dev, args.steps, args.warmup, rows,
+                                             glob, ws, stream, "power-law")
+    log(f"[bench] {args.steps} timed steps in {elapsed:.3f}s")
+    stats = P.last_stats()
+    roof, per_kernel, over, abytes = roofline_of(P, torch, g, rows, stats, phase_avg,
+                                                 peak["GBps"])
+    ms_per_step = elapsed * 1e3 / args.steps
+    result = {
+        "metric": "edges/sec (typed 3+4-node counts)",
+        "value": g.m * args.steps / elapsed,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": st["name"], "n": st["n"], "m": st["m"], "L": L,
+                   "max_degree": st["max_degree"],
+                   "same_type_edge_fraction": round(st["same_type_edge_fraction"], 4),
+                   "per_edge_table_GB": round(g.m * W * 8 / 1e9, 2)},
+        "roofline": roof,
+        "ms_per_step_median_events": float(np.median(step_ms)),
+        "step_ms_events": [round(x, 3) for x in step_ms],
+        "kernels": per_kernel,
+        "byte_model_above_peak": over,
+        "pipeline_algorithmic_GBps": sum(abytes.values()) / (ms_per_step * 1e-3) / 1e9,
+        "tuning": tuning,
+        "phases_ms": {k: round(v, 3) for k, v in phase_avg.items()},
+        "work": {k: int(v) for k, v in stats.items()},
+        "host": host,
+        "generation_s": round(gen_s, 2),
+    }
+    result["transfers"] = transfer_timings(g, rows, dev)
+    log(f"[bench] transfers: {result['transfers']}")
+
+    # sparse per-edge form of the table (outside the timed steps)
+    torch.cuda.synchronize()
+    t_sp = time.perf_counter()
+    off, keys, counts = P.sparse_rows(rows, L, workspace=ws)
+    torch.cuda.synchronize()
+    sp_ms = (time.perf_counter() - t_sp) * 1e3
+    nnz_total = int(keys.numel())
+    result["sparse_output"] = {
+        "nonzeros": nnz_total, "mean_per_edge": nnz_total / max(g.m, 1),
+        "bytes": nnz_total * 10 + (g.m + 1) * 8, "dense_bytes": g.m * W * 8,
+        "ms": round(sp_ms, 3)}
+    del off, keys, counts
+
+    if not args.skip_cpu:
+        threads = host_threads()
+        log(f"[bench] CPU oracle baseline on {threads} threads ...")
+        pick, orows, cb = cpu_baseline(g, threads)
+        cb["sample"] += (f"; host {host['model']}, {host['sockets']} socket(s) x "
+                         f"{host['cores_per_socket']} cores x {host['threads_per_core']} "
+                         f"threads, {host['usable_cpus']} CPUs usable, oracle capped at 16 threads")
+        result["cpu_baseline"] = cb
+        sel = torch.from_numpy(pick).to(dev)
+        grows = rows.index_select(0, sel).cpu().numpy().view(np.uint64)
+        same = int(np.sum(np.all(grows == orows, axis=1)))
+        result["parity_sample"] = f"{same}/{len(pick)} sampled rows identical to the oracle"
+        log(f"[bench] {result['parity_sample']}")
+
+    del rows, glob, g._dev
+    ws.buf = None
+    torch.cuda.empty_cache()
+    if args.config3_steps > 0:
+        P.set_tuning(**defaults)
+        result["config3"] = bench_config3(args, P, torch, G, dev, stream, peak["GBps"])
+    print(json.dumps(result), flush=True)
+
+
+def bench_config3(args, P, torch, G, dev, stream, peak_gbps):
+    """The tripartite configuration at full size: edges/s, phases, roofline
+    of its dominant kernel and a sampled parity check against the oracle."""
+    t0 = time.perf_counter()
+    g = G.config_graph(3, seed=0, scale=args.scale)
+    st = g.stats()
+    gen_s = time.perf_counter() - t0
+    log(f"[bench] graph {st['name']}: n={st['n']} m={st['m']} max_degree={st['max_degree']} "
+        f"({gen_s:.1f}s)")
+    L = g.L
+    g._dev = (torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev),
+              torch.from_numpy(g.types).to(dev))
+    rows = torch.empty((g.m, P.row_width(L)), dtype=torch.int64, device=dev)
+    glob = torch.empty(P.global_width(L), dtype=torch.int64, device=dev)
+    ws = P.Workspace(dev)
+    elapsed, step_ms, phase_avg = time_graph(P, torch, g, dev, args.config3_steps, 1, rows, glob,
+                                             ws, stream, "tripartite")
+    stats = P.last_stats()
+    roof, per_kernel, over, _ = roofline_of(P, torch, g, rows, stats, phase_avg, peak_gbps)
+    out = {"workload": st["name"], "n": st["n"], "m": st["m"], "L": L,
+           "max_degree": st["max_degree"], "steps": args.config3_steps, "warmup": 1,
+           "value": g.m * args.config3_steps / elapsed, "unit": "edges/s",
+           "ms_per_step": elapsed * 1e3 / args.config3_steps,
+           "ms_per_step_median_events": float(np.median(step_ms)),
+           "tuning": "library defaults", "roofline": roof, "kernels": per_kernel,
+           "byte_model_above_peak": over,
+           "phases_ms": {k: round(v, 3) for k, v in phase_avg.items()},
+           "work": {k: int(v) for k, v in stats.items()}, "generation_s": round(gen_s, 2)}
+    if not args.skip_cpu:
+        same, k, dt = parity_sample(g, rows, dev, 64, 4, 8, host_threads(), 29)
+        out["parity_sample"] = (f"{same}/{k} sampled rows (64 uniform edges, 4 at each of the "
+                                f"8 highest-degree nodes) identical to the oracle; {dt:.1f} s")
+        log(f"[bench] tripartite: {out['parity_sample']}")
+    del rows, glob, g._dev
+    ws.buf = None
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--mode", choices=["single", "batch", "serve"], default="single",
@@ -378,6 +779,9 @@ def main():
                     help="ignore the tuned profile, time the library defaults")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--config3-steps", type=int, default=3,
+                    help="single mode: timed steps of the full-size tripartite graph after the "
+                         "headline (0 skips it)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -392,135 +796,7 @@ def main():
         bench_serve(args)
         return
 
-    import torch
-
-    import paper_2010_14058_amd as P
-    from tg_synth import graphs as G
-
-    dev = torch.device("cuda:0")
-    t0 = time.perf_counter()
-    g = G.config_graph(2, seed=0, scale=args.scale)
-    st = g.stats()
-    log(f"[bench] graph {st['name']}: n={st['n']} m={st['m']} max_degree={st['max_degree']} "
-        f"same_type={st['same_type_edge_fraction']:.4f} ({time.perf_counter() - t0:.1f}s)")
-    L = g.L
-    rp = torch.from_numpy(g.row_ptr).to(dev)
-    col = torch.from_numpy(g.col).to(dev)
-    ty = torch.from_numpy(g.types).to(dev)
-    W = P.row_width(L)
-    rows = torch.empty((g.m, W), dtype=torch.int64, device=dev)
-    glob = torch.empty(P.global_width(L), dtype=torch.int64, device=dev)
-    ws = P.Workspace(dev)
-    stream = torch.cuda.current_stream(dev)
-
-    if args.calib_copy:
-        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
-        b = torch.empty_like(a)
-        a.fill_(1)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-        log("[bench] calibration copy of 1 GiB done")
-
-    def run_once():
-        from paper_2010_14058_amd import autotune as AT
-
-        P.count_typed_graphlets(rp, col, ty, L, out_rows=rows, out_global=glob, workspace=ws,
-                                stream=stream)
-        torch.cuda.synchronize()
-        return AT.digest_of(glob, rows)
-
-    tuning = setup_tuning(args, st["name"], run_once)
-    P.set_timing(True)
-    for w in range(args.warmup):
-        P.count_typed_graphlets(rp, col, ty, L, out_rows=rows, out_global=glob, workspace=ws,
-                                stream=stream)
-        torch.cuda.synchronize()
-        log(f"[bench] warmup {w + 1}/{args.warmup} done")
-
-    phase_sum = {}
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for s in range(args.steps):
-        P.count_typed_graphlets(rp, col, ty, L, out_rows=rows, out_global=glob, workspace=ws,
-                                stream=stream)
-        for name, ms in P.phase_times():
-            phase_sum[name] = phase_sum.get(name, 0.0) + ms
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    log(f"[bench] {args.steps} timed steps in {elapsed:.3f}s")
-    stats = P.last_stats()
-    phase_avg = {k: v / max(args.steps, 1) for k, v in phase_sum.items()}
-
-    # heavy clique edges: both degrees above the light-edge bucket
-    uv = g.edges()
-    d = g.degrees()
-    du, dv = d[uv[:, 0]], d[uv[:, 1]]
-    hv = np.minimum(du, dv) > P.get_tuning()["edge_deg"]
-    hv_idx = torch.from_numpy(np.nonzero(hv)[0]).to(dev)
-    hv_t = float(rows.index_select(0, hv_idx)[:, :L].sum().item()) if hv_idx.numel() else 0.0
-    # sum over heavy edges of d_i + d_j (sum_v d_v^2 is the same sum over all edges)
-    heavy_info = (float(np.sum((du[hv] + dv[hv]).astype(np.float64))), hv_t, float(hv.sum()))
-    abytes = algorithmic_bytes(g, L, stats, heavy_info)
-    kernels = [k for k in abytes if k not in ("prep",) and k in phase_avg]
-    dom = max(kernels, key=lambda k: phase_avg[k])
-    dom_ms = phase_avg[dom]
-    achieved = abytes[dom] / (dom_ms * 1e-3) / 1e9
-    traffic = load_traffic(dom)
-    total_alg = sum(abytes.values())
-    ms_per_step = elapsed * 1e3 / args.steps
-
-    result = {
-        "metric": "edges/sec (typed 3+4-node counts)",
-        "value": g.m * args.steps / elapsed,
-        "unit": "edges/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64",
-        "data": "synthetic",
-        "config": {"workload": st["name"], "n": st["n"], "m": st["m"], "L": L,
-                   "max_degree": st["max_degree"],
-                   "same_type_edge_fraction": round(st["same_type_edge_fraction"], 4),
-                   "per_edge_table_GB": round(g.m * W * 8 / 1e9, 2)},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "avg_ms": dom_ms},
-        "pipeline_algorithmic_GBps": total_alg / (ms_per_step * 1e-3) / 1e9,
-        "tuning": tuning,
-        "phases_ms": {k: round(v, 3) for k, v in phase_avg.items()},
-        "work": {k: int(v) for k, v in stats.items()},
-    }
-
-    # sparse per-edge form of the table (outside the timed steps)
-    torch.cuda.synchronize()
-    t_sp = time.perf_counter()
-    off, keys, counts = P.sparse_rows(rows, L, workspace=ws)
-    torch.cuda.synchronize()
-    sp_ms = (time.perf_counter() - t_sp) * 1e3
-    nnz_total = int(keys.numel())
-    result["sparse_output"] = {
-        "nonzeros": nnz_total, "mean_per_edge": nnz_total / max(g.m, 1),
-        "bytes": nnz_total * 10 + (g.m + 1) * 8, "dense_bytes": g.m * W * 8,
-        "ms": round(sp_ms, 3)}
-    del off, keys, counts
-
-    if not args.skip_cpu:
-        threads = host_threads()
-        log(f"[bench] CPU oracle baseline on {threads} threads ...")
-        pick, orows, cb = cpu_baseline(g, threads)
-        result["cpu_baseline"] = cb
-        sel = torch.from_numpy(pick).to(dev)
-        grows = rows.index_select(0, sel).cpu().numpy().view(np.uint64)
-        same = int(np.sum(np.all(grows == orows, axis=1)))
-        result["parity_sample"] = f"{same}/{len(pick)} sampled rows identical to the oracle"
-        log(f"[bench] {result['parity_sample']}")
-    print(json.dumps(result), flush=True)
+    bench_single(args)
 
 
 if __name__ == "__main__":

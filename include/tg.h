@@ -205,7 +205,14 @@ const char *tg_last_error(void);
  *       an edge whose smaller endpoint degree is at most this is counted by
  *       one wave with its triangle set in LDS, else by a 256-thread
  *       workgroup of the heavy-edge kernel.
- * CYCLE_SLOTS, MAP_BYTES, EDGE_SLOTS and TBUF_BYTES change
+ *   TG_TUNE_SH_MAX       (default 2048, 0..2048): most super-hubs, the
+ *       highest-ranked nodes of degree >= TG_TUNE_SH_DEG that get a bitmap
+ *       over all nodes (constant-time membership and slot lookups); the
+ *       workspace budget for the bitmaps (512 MiB) may cut it further.  A
+ *       node of that degree without a bitmap is probed by binary search.
+ *   TG_TUNE_SH_DEG       (default 1024, 32..2^31-1): smallest degree of a
+ *       super-hub.
+ * CYCLE_SLOTS, MAP_BYTES, EDGE_SLOTS, TBUF_BYTES and SH_MAX change
  * tg_workspace_bytes and tg_batch_workspace_bytes, so they must be set
  * before the workspace is sized.
  * tg_set_tuning returns TG_E_INVALID_ARG for an unknown knob or a value out
@@ -220,7 +227,9 @@ typedef enum {
     TG_TUNE_RANGE_BYTES = 6,
     TG_TUNE_DERIVE_EDGES = 7,
     TG_TUNE_LIGHT_WEDGES = 8,
-    TG_TUNE_EDGE_DEG = 9
+    TG_TUNE_EDGE_DEG = 9,
+    TG_TUNE_SH_MAX = 10,
+    TG_TUNE_SH_DEG = 11
 } tg_tune;
 tg_status tg_set_tuning(int32_t knob, int64_t value);
 int64_t tg_get_tuning(int32_t knob);
@@ -239,8 +248,11 @@ int32_t tg_phase_times(float *ms, const char **names, int32_t max_phases);
  * [1] groups on the light cycle path (both passes), [2] groups on the heavy
  * cycle path, [3] edges on the heavy clique path, [4] wedges of pass B,
  * [5] pass-A wedges in heavy groups, [6] pass-B wedges in heavy groups,
- * [7] sum over edges of |T_ij| (three times the triangle count).
- * Returns the number written. */
+ * [7] sum over edges of |T_ij| (three times the triangle count),
+ * [8] nodes of at least the super-hub degree, [9] super-hubs given a bitmap
+ * (the rest of [8] is probed by binary search), [10] hub-core size.
+ * Returns the number written (at most TG_NUM_STATS). */
+#define TG_NUM_STATS 11
 int32_t tg_last_stats(int64_t *stats, int32_t max_stats);
 
 #ifdef __cplusplus

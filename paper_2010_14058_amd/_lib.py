@@ -126,7 +126,7 @@ def phase_times() -> list[tuple[str, float]]:
 
 TUNE_KNOBS = {"task_wedges": 0, "clear_bytes": 1, "cycle_slots": 2, "map_bytes": 3,
               "edge_slots": 4, "tbuf_bytes": 5, "range_bytes": 6, "derive_edges": 7,
-              "light_wedges": 8, "edge_deg": 9}
+              "light_wedges": 8, "edge_deg": 9, "sh_max": 10, "sh_deg": 11}
 
 
 def set_tuning(**knobs) -> dict:
@@ -146,11 +146,12 @@ def get_tuning() -> dict:
 
 
 def last_stats() -> dict:
-    st = (ctypes.c_int64 * 8)()
-    load().tg_last_stats(st, 8)
+    st = (ctypes.c_int64 * 11)()
+    load().tg_last_stats(st, 11)
     return {"wedges_pass_a": st[0], "light_groups": st[1], "heavy_groups": st[2],
             "heavy_edges": st[3], "wedges_pass_b": st[4], "heavy_wedges_pass_a": st[5],
-            "heavy_wedges_pass_b": st[6], "triangle_slots": st[7]}
+            "heavy_wedges_pass_b": st[6], "triangle_slots": st[7], "superhub_candidates": st[8],
+            "superhubs": st[9], "hub_core": st[10]}
 
 
 def count_raw(row_ptr_ptr: int, col_ptr: int, types_ptr: int, n: int, nnz: int, L: int,

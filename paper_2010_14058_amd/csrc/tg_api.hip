@@ -41,9 +41,9 @@ static const int MAX_CYCLE_SLOTS = 2048;   // heavy 4-cycle workgroups (map budg
 static const size_t XYK_BUDGET = size_t(16) << 30;
 
 // Scheduling knobs (tg_set_tuning), per host thread.
-thread_local int64_t g_tune[10] = {TASK_WEDGES, SEQ_CLEAR_BYTES, MAX_CYCLE_SLOTS,
-                                    (int64_t)MAP_BUDGET, MAX_HEAVY_SLOTS, (int64_t)TBUF_BUDGET,
-                                    TASK_RANGE_BYTES, 0, LIGHT_MAXW, TCAP};
+thread_local int64_t g_tune[TG_TUNE_SH_DEG + 1] = {
+    TASK_WEDGES, SEQ_CLEAR_BYTES, MAX_CYCLE_SLOTS, (int64_t)MAP_BUDGET, MAX_HEAVY_SLOTS,
+    (int64_t)TBUF_BUDGET, TASK_RANGE_BYTES, 0, LIGHT_MAXW, TCAP, SH_MAX, SH_DMIN};
 
 static size_t sort_tmp_bytes(int64_t n, int64_t nnz) {
     size_t a = 0, b = 0, c = 0;
@@ -146,7 +146,7 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G) {
         const int64_t nw = (n + 63) / 64;
         const size_t per_sh = (size_t)nw * (sizeof(uint64_t) + sizeof(uint32_t));
         int64_t shm = (int64_t)(SH_BUDGET / (per_sh > 0 ? per_sh : 1));
-        if (shm > SH_MAX) shm = SH_MAX;
+        if (shm > g_tune[TG_TUNE_SH_MAX]) shm = g_tune[TG_TUNE_SH_MAX];
         y.sh_max = (int)shm;
         y.off_SB = take(sizeof(uint64_t) * (size_t)nw * (size_t)(shm > 0 ? shm : 1));
         y.off_SP = take(sizeof(uint32_t) * (size_t)nw * (size_t)(shm > 0 ? shm : 1));
@@ -167,7 +167,7 @@ struct Timing {
     std::vector<const char *> names;
     int used = 0;
     hipStream_t stream = nullptr;
-    int64_t stats[8] = {0};
+    int64_t stats[TG_NUM_STATS] = {0};
 };
 thread_local Timing g_timing;
 
@@ -308,7 +308,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     HIPCHK(launch_node_keys(deg, n, graph_major ? node_graph : nullptr, deg_bits, key_a, st));
     HIPCHK(rocprim::radix_sort_keys(stmp, stmp_bytes, key_a, key_b, (size_t)n, 0, 64, st));
     HIPCHK(launch_relabel(key_b, types, deg, n, order, newid, ntype, ndeg, counters + C_HUB_CAND,
-                          node_graph, ngraph, st));
+                          (uint32_t)g_tune[TG_TUNE_SH_DEG], node_graph, ngraph, st));
     HIPCHK(rocprim::exclusive_scan(stmp, stmp_bytes, ndeg, nrp, int64_t(0), (size_t)(n + 1),
                                    rocprim::plus<int64_t>(), st));
     const int bits = bits_for(n);
@@ -328,7 +328,9 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     // (none in graph-major order, where the top ids are not the top degrees)
     const uint64_t hub_cand = graph_major ? 0 : cand[0], sh_cand = graph_major ? 0 : cand[1];
     const int H = (int)(hub_cand < (uint64_t)HUB_MAX ? hub_cand : (uint64_t)HUB_MAX);
-    // super-hubs: the highest-ranked nodes of degree >= SH_DMIN that fit
+    // super-hubs: the highest-ranked nodes of degree >= the super-hub degree
+    // (tuning knob) that fit; nodes of that degree beyond them are probed by
+    // binary search like any other
     const int S = (int)(sh_cand < (uint64_t)y.sh_max ? sh_cand : (uint64_t)y.sh_max);
     const int32_t sh_base = (int32_t)(n - S);
     const int64_t nw = (n + 63) / 64;
@@ -491,6 +493,9 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     g_timing.stats[5] = (int64_t)cnt_host[C_WEDGES_A_HEAVY];
     g_timing.stats[6] = (int64_t)cnt_host[C_WEDGES_B_HEAVY];
     g_timing.stats[7] = (int64_t)cnt_host[C_TRI_SUM];
+    g_timing.stats[8] = (int64_t)sh_cand;
+    g_timing.stats[9] = (int64_t)S;
+    g_timing.stats[10] = (int64_t)H;
     if (probe.status) return status_from_bits(probe.status) == TG_OK ? TG_E_INTERNAL
                                                                     : status_from_bits(probe.status);
     return TG_OK;
@@ -671,6 +676,13 @@ tg_status tg_set_tuning(int32_t knob, int64_t value) {
     case TG_TUNE_EDGE_DEG:
         if (value < 1 || value > tg::TCAP) return TG_E_INVALID_ARG;
         break;
+    case TG_TUNE_SH_MAX:
+        if (value < 0 || value > tg::SH_MAX) return TG_E_INVALID_ARG;
+        break;
+    case TG_TUNE_SH_DEG:
+        // at least the hub-core degree, so that super-hubs stay inside the core
+        if (value < tg::HUB_DMIN || value > INT32_MAX) return TG_E_INVALID_ARG;
+        break;
     default:
         return TG_E_INVALID_ARG;
     }
@@ -679,14 +691,14 @@ tg_status tg_set_tuning(int32_t knob, int64_t value) {
 }
 
 int64_t tg_get_tuning(int32_t knob) {
-    if (knob < 0 || knob > TG_TUNE_EDGE_DEG) return -1;
+    if (knob < 0 || knob > TG_TUNE_SH_DEG) return -1;
     return tg::g_tune[knob];
 }
 
 const char *tg_last_error(void) { return tg::g_last_error; }
 
 int32_t tg_last_stats(int64_t *stats, int32_t max_stats) {
-    int cnt = max_stats < 8 ? max_stats : 8;
+    int cnt = max_stats < TG_NUM_STATS ? max_stats : TG_NUM_STATS;
     for (int q = 0; q < cnt; ++q) stats[q] = tg::g_timing.stats[q];
     return cnt;
 }

@@ -41,8 +41,8 @@ constexpr int EDGE_THREADS_HEAVY = 256;
 constexpr int64_t BATCH_EDGE_CHUNK = 256;  // consecutive edges per work item in batches
 constexpr int HUB_DMIN = 32;          // smallest degree of a hub-core node
 constexpr int HUB_MAX = 8192;         // largest hub core (bit-matrix HUB_MAX^2 bits)
-constexpr int SH_DMIN = 1024;         // smallest degree of a super-hub (full-row bitmap)
-constexpr int SH_MAX = 2048;          // most super-hubs
+constexpr int SH_DMIN = 1024;         // default smallest degree of a super-hub (full-row bitmap)
+constexpr int SH_MAX = 2048;          // most super-hubs (the default cap)
 constexpr size_t SH_BUDGET = size_t(512) << 20;  // bytes of super-hub bitmaps and prefixes
 
 // Device-side layout of everything the library keeps in the caller's
@@ -125,8 +125,8 @@ struct EdgeArgs {
     const uint32_t *neid;
     const int32_t *ei, *ej;
     const uint32_t *tri;
-    const uint32_t *tdeg;
-    const uint8_t *ctype;        // type of the neighbour at each adjacency slot        // typed degrees per node, rows of tri_pitch(L)
+    const uint32_t *tdeg;        // typed degrees per node, rows of tri_pitch(L)
+    const uint8_t *ctype;        // type of the neighbour at each adjacency slot
     const uint32_t *tri_slot;    // typed triangle counts per slot, rows of tri_pitch(L)
     const uint64_t *A, *D, *NC;
     int agg_u32;                 // A, D and NC stored as uint32 (every degree below 2^16)
@@ -185,8 +185,8 @@ hipError_t launch_node_keys(const uint32_t *deg, int64_t n, const int32_t *node_
                             uint64_t *keys, hipStream_t st);
 hipError_t launch_relabel(const uint64_t *sorted, const uint8_t *types, const uint32_t *deg, int64_t n,
                           int32_t *order, int32_t *newid, uint8_t *ntype, int64_t *ndeg,
-                          uint64_t *hub_cand, const int32_t *node_graph, int32_t *ngraph,
-                          hipStream_t st);
+                          uint64_t *hub_cand, uint32_t sh_deg, const int32_t *node_graph,
+                          int32_t *ngraph, hipStream_t st);
 hipError_t launch_slot_keys(const int64_t *rp, const int32_t *col, const int64_t *ucount,
                             const int64_t *eoff, const int32_t *newid, int64_t n, int bits,
                             uint64_t *keys, uint32_t *vals, int32_t *ei, int32_t *ej,

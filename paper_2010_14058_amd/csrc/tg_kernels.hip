@@ -148,8 +148,8 @@ __global__ void k_relabel(const uint64_t *__restrict__ sorted, const uint8_t *__
                           const uint32_t *__restrict__ deg, int64_t n,
                           int32_t *__restrict__ order, int32_t *__restrict__ newid,
                           uint8_t *__restrict__ ntype, int64_t *__restrict__ ndeg,
-                          uint64_t *__restrict__ hub_cand, const int32_t *__restrict__ node_graph,
-                          int32_t *__restrict__ ngraph) {
+                          uint64_t *__restrict__ hub_cand, uint32_t sh_deg,
+                          const int32_t *__restrict__ node_graph, int32_t *__restrict__ ngraph) {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool cand = false;
     if (r < n) {
@@ -165,7 +165,7 @@ __global__ void k_relabel(const uint64_t *__restrict__ sorted, const uint8_t *__
     uint64_t bal = __ballot(cand);
     if (lane_id() == 0 && bal)
         atomicAdd((unsigned long long *)hub_cand, (unsigned long long)__popcll(bal));
-    uint64_t sbal = __ballot(r < n && ndeg[r] >= SH_DMIN);
+    uint64_t sbal = __ballot(r < n && ndeg[r] >= (int64_t)sh_deg);
     if (lane_id() == 0 && sbal)
         atomicAdd((unsigned long long *)(hub_cand + 1), (unsigned long long)__popcll(sbal));
 }
@@ -1114,11 +1114,11 @@ hipError_t launch_node_keys(const uint32_t *deg, int64_t n, const int32_t *node_
 
 hipError_t launch_relabel(const uint64_t *sorted, const uint8_t *types, const uint32_t *deg, int64_t n,
                           int32_t *order, int32_t *newid, uint8_t *ntype, int64_t *ndeg,
-                          uint64_t *hub_cand, const int32_t *node_graph, int32_t *ngraph,
-                          hipStream_t st) {
+                          uint64_t *hub_cand, uint32_t sh_deg, const int32_t *node_graph,
+                          int32_t *ngraph, hipStream_t st) {
     k_relabel<<<blocks_for(n > 0 ? n : 1, 256), 256, 0, st>>>(sorted, types, deg, n, order, newid,
-                                                              ntype, ndeg, hub_cand, node_graph,
-                                                              ngraph);
+                                                              ntype, ndeg, hub_cand, sh_deg,
+                                                              node_graph, ngraph);
     LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -79,6 +79,86 @@ def test_config2_full_size_sampled(oracle_mod):
     assert checked >= 300
 
 
+def collapsed_rows(rows, L):
+    """Typed rows [m, 2L + 10P] summed over the types of each column block:
+    the untyped row [m, 12] (Prop. 1), computed on the device in chunks."""
+    import torch
+
+    P = L * (L + 1) // 2
+    out = torch.empty((rows.shape[0], 12), dtype=torch.int64, device=rows.device)
+    step = 1 << 21
+    for a in range(0, rows.shape[0], step):
+        r = rows[a:a + step]
+        out[a:a + step, 0] = r[:, :L].sum(dim=1)
+        out[a:a + step, 1] = r[:, L:2 * L].sum(dim=1)
+        out[a:a + step, 2:] = r[:, 2 * L:].reshape(r.shape[0], 10, P).sum(dim=2)
+    return out
+
+
+def test_config3_full_size_sampled(oracle_mod):
+    """The tripartite configuration (1.25M nodes, 20.4M edges, L = 3) at full
+    size: sampled rows against the oracle (uniform edges, edges at the top
+    hubs and at nodes of super-hub degree beyond the super-hub cap, which are
+    probed by binary search), the corrected `prop:1` on every row, the
+    global vector against the oracle's from the GPU rows, and an untyped
+    (L = 1) run equal to the typed rows summed over types (Prop. 1)."""
+    import torch
+
+    import paper_2010_14058_amd as P
+
+    g = G.config_graph(3)
+    assert g.n == 1_250_000 and g.L == 3
+    print(f"[gpu] {g.name}: n={g.n} m={g.m} L={g.L}", flush=True)
+    rp, col, ty = to_device(g)
+    ws = P.Workspace(rp.device)
+    rows, glob = P.count_typed_graphlets(rp, col, ty, g.L, workspace=ws)
+    torch.cuda.synchronize()
+    st = P.last_stats()
+    d = g.degrees()
+    sh_deg = P.get_tuning()["sh_deg"]
+    assert st["superhub_candidates"] == int(np.sum(d >= sh_deg)), st
+    assert st["superhub_candidates"] > st["superhubs"], st
+    # internal rank order is (degree, id): the super-hubs are the top ranks,
+    # the remaining nodes of super-hub degree are the lowest-ranked of them
+    cand = np.nonzero(d >= sh_deg)[0]
+    cand = cand[np.lexsort((cand, d[cand]))]
+    overflow = cand[: cand.size - st["superhubs"]]
+    uv = g.edges()
+    rng = np.random.default_rng(17)
+    idx = set(sample_edges(g, 300, 13).tolist())
+    for h in overflow[rng.choice(overflow.size, size=min(6, overflow.size), replace=False)]:
+        inc = np.nonzero((uv[:, 0] == h) | (uv[:, 1] == h))[0]
+        idx.update(rng.choice(inc, size=min(12, inc.size), replace=False).tolist())
+    idx = np.array(sorted(idx), dtype=np.int64)
+    got = rows.index_select(0, torch.from_numpy(idx).to(rows.device)).cpu().numpy().view(np.uint64)
+    want = oracle_mod.edge_rows(g, uv[idx], method="paper")
+    if not np.array_equal(got, want):
+        bad = np.argwhere(got != want)
+        e, c = bad[0]
+        names = oracle_mod.column_names(g.L)
+        raise AssertionError(f"{g.name}: {len(bad)} mismatches; first edge {uv[idx[e]].tolist()} "
+                             f"col {names[c]} gpu={got[e, c]} oracle={want[e, c]}")
+    L = g.L
+    # corrected prop:1 on every row, on the device
+    dd = torch.from_numpy(d.astype(np.int64)).to(rows.device)
+    ui = torch.from_numpy(uv[:, 0]).to(rows.device)
+    vi = torch.from_numpy(uv[:, 1]).to(rows.device)
+    three = 2 * rows[:, :L].sum(dim=1) + rows[:, L:2 * L].sum(dim=1)
+    assert torch.equal(three, dd[ui] + dd[vi] - 2)
+    # untyped run = typed rows summed over types
+    ty0 = torch.zeros_like(ty)
+    rows1, glob1 = P.count_typed_graphlets(rp, col, ty0, 1, workspace=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(rows1, collapsed_rows(rows, L))
+    del rows1, ty0, three
+    glob_h = glob.cpu().numpy().view(np.uint64)
+    full = rows.cpu().numpy().view(np.uint64)
+    del rows
+    np.testing.assert_array_equal(glob_h, oracle_mod.global_counts(g, full))
+    print(f"[gpu] {g.name}: {idx.size} sampled rows identical, "
+          f"{overflow.size} nodes of super-hub degree without a bitmap", flush=True)
+
+
 def test_degree_above_16_bits(oracle_mod):
     """A hub of degree 70000 over random leaf edges (and a second hub sharing
     a third of its leaves): the hub's 4-cycle group has more than 2^16

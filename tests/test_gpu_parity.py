@@ -114,6 +114,35 @@ def test_power_law_medium(oracle_mod):
     check(oracle_mod, g)
 
 
+@pytest.mark.parametrize("knobs", [dict(sh_max=2), dict(sh_max=0), dict(sh_deg=32)],
+                         ids=["two_superhubs", "no_superhubs", "superhub_degree_32"])
+def test_superhub_overflow(oracle_mod, knobs):
+    """Nodes of super-hub degree without a bitmap: with the super-hub cap at
+    2 (or 0) the other nodes of degree >= 1024 are probed by binary search in
+    the triangle, clique and gather walks; with the super-hub degree at 32
+    most hub-core nodes get bitmaps, and edges joining two super-hubs reach
+    the one-wave clique kernel."""
+    import paper_2010_14058_amd as P
+
+    old = P.set_tuning(**knobs)
+    try:
+        g = G.chung_lu_typed(20000, 16.0, 2.1, 3000.0, 5, type_probs=G.zipf_probs(5, 1.2),
+                             homophily=0.6, seed=5, name="cl_20k_sh")
+        check(oracle_mod, g)
+        st = P.last_stats()
+        d = g.degrees()
+        cap = knobs.get("sh_max", 2048)
+        deg = knobs.get("sh_deg", 1024)
+        assert st["superhub_candidates"] == int(np.sum(d >= deg)), st
+        assert st["superhubs"] == min(cap, st["superhub_candidates"]), st
+        if "sh_max" in knobs:
+            assert st["superhub_candidates"] > st["superhubs"], st
+        else:
+            assert st["superhubs"] > 1000, st
+    finally:
+        P.set_tuning(**old)
+
+
 def test_max_and_min_L(oracle_mod):
     g16 = G.chung_lu_typed(800, 10.0, 2.1, 120.0, 16, seed=3, name="cl_L16")
     check(oracle_mod, g16)
