@@ -111,6 +111,31 @@ tg_status tg_count_typed_graphlets(const int64_t *row_ptr, const int32_t *col,
                                    uint64_t *per_edge, uint64_t *global_counts,
                                    void *workspace, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * counts as tg_count_typed_graphlets, with the workspace taken from a
+ * static device array of TG_NOALLOC_SCRATCH_BYTES bytes that the library
+ * holds on each device it runs on until the process ends.  The call
+ * allocates nothing (no hipMalloc, no hipFree, no allocating library
+ * routine).
+ *   row_ptr, col, types, n, nnz, L, per_edge, global_counts, stream
+ *                         as for tg_count_typed_graphlets (device pointers,
+ *                         caller-owned outputs).
+ * The workspace layout of the graph must fit the array: a graph whose
+ * per-node and per-edge regions (with one heavy 4-cycle map and one
+ * heavy-edge list) exceed it gives TG_E_TOO_LARGE before any device work;
+ * smaller graphs run with as many heavy workgroups and super-hub bitmaps as
+ * the rest of the array holds.  Every call on a device shares that
+ * device's array and finds the previous call's contents there (the library
+ * clears what must start at zero): calls that overlap on one device, on any
+ * streams or host threads, race and give undefined results; serialise them.
+ * Other errors as for tg_count_typed_graphlets. */
+#define TG_NOALLOC_SCRATCH_BYTES (256u << 20)
+tg_status tg_count_typed_graphlets_noalloc(const int64_t *row_ptr, const int32_t *col,
+                                           const uint8_t *types, int64_t n, int64_t nnz,
+                                           int32_t L, uint64_t *per_edge,
+                                           uint64_t *global_counts, void *stream);
+
 /* Batched counting of many graphs in one call.  The graphs are given as one
  * CSR over all their nodes (a disjoint union): graph g owns the nodes
  * [graph_node_ptr[g], graph_node_ptr[g+1]) and no edge joins two graphs;

@@ -24,6 +24,9 @@ SIGNATURES = {
     "tg_count_typed_graphlets": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int64,
                                             _c.c_int64, _c.c_int32, _c.c_void_p, _c.c_void_p,
                                             _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "tg_count_typed_graphlets_noalloc": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                                    _c.c_int64, _c.c_int64, _c.c_int32,
+                                                    _c.c_void_p, _c.c_void_p, _c.c_void_p]),
     "tg_batch_workspace_bytes": (_c.c_size_t, [_c.c_int64, _c.c_int64, _c.c_int64, _c.c_int32]),
     "tg_count_batch": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int64,
                                   _c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int32, _c.c_void_p,
@@ -160,6 +163,17 @@ def count_raw(row_ptr_ptr: int, col_ptr: int, types_ptr: int, n: int, nnz: int, 
                                          global_ptr, ws_ptr, ws_bytes, stream)
     if rc:
         raise TGError(rc, "tg_count_typed_graphlets")
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20
+
+
+def count_noalloc_raw(row_ptr_ptr: int, col_ptr: int, types_ptr: int, n: int, nnz: int, L: int,
+                      per_edge_ptr: int, global_ptr: int, stream: int) -> None:
+    rc = load().tg_count_typed_graphlets_noalloc(row_ptr_ptr, col_ptr, types_ptr, n, nnz, L,
+                                                 per_edge_ptr, global_ptr, stream)
+    if rc:
+        raise TGError(rc, "tg_count_typed_graphlets_noalloc")
 
 
 def batch_workspace_bytes(n: int, nnz: int, G: int, L_max: int) -> int:

@@ -7,6 +7,7 @@
 
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "tg_internal.hpp"
@@ -65,7 +66,19 @@ static size_t sort_tmp_bytes(int64_t n, int64_t nnz) {
     return mx + 256;
 }
 
-tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G) {
+Budget budget_from_tuning() {
+    Budget b;
+    b.map_bytes = (size_t)g_tune[TG_TUNE_MAP_BYTES];
+    b.cycle_slots = g_tune[TG_TUNE_CYCLE_SLOTS];
+    b.tbuf_bytes = (size_t)g_tune[TG_TUNE_TBUF_BYTES];
+    b.edge_slots = g_tune[TG_TUNE_EDGE_SLOTS];
+    b.sh_max = g_tune[TG_TUNE_SH_MAX];
+    b.sh_bytes = SH_BUDGET;
+    b.xyk_bytes = XYK_BUDGET;
+    return b;
+}
+
+tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G, const Budget &bud) {
     if (L < 1 || L > TG_MAX_L) return TG_E_L_RANGE;
     if (n < 0 || nnz < 0 || (nnz & 1)) return TG_E_INVALID_ARG;
     if (n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 32)) return TG_E_TOO_LARGE;
@@ -77,13 +90,13 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G) {
     y.L = L;
     int64_t LL = (int64_t)L * L;
     size_t per_map = (size_t)(n > 0 ? n : 1) * L * sizeof(uint32_t);
-    int64_t slots = (int64_t)((size_t)g_tune[TG_TUNE_MAP_BYTES] / per_map);
-    if (slots > g_tune[TG_TUNE_CYCLE_SLOTS]) slots = g_tune[TG_TUNE_CYCLE_SLOTS];
+    int64_t slots = (int64_t)(bud.map_bytes / per_map);
+    if (slots > bud.cycle_slots) slots = bud.cycle_slots;
     if (slots < 1) slots = 1;
     y.heavy_slots = (int)slots;
     size_t per_t = (size_t)(n > 0 ? n : 1) * sizeof(uint32_t);
-    int64_t eslots = (int64_t)((size_t)g_tune[TG_TUNE_TBUF_BYTES] / per_t);
-    if (eslots > g_tune[TG_TUNE_EDGE_SLOTS]) eslots = g_tune[TG_TUNE_EDGE_SLOTS];
+    int64_t eslots = (int64_t)(bud.tbuf_bytes / per_t);
+    if (eslots > bud.edge_slots) eslots = bud.edge_slots;
     if (eslots < 1) eslots = 1;
     y.heavy_edge_slots = (int)eslots;
     y.sort_tmp_bytes = sort_tmp_bytes(n, nnz);
@@ -134,7 +147,7 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G) {
     y.off_hstart = take(sizeof(int64_t) * (n + 1));
     y.off_eslot = take(sizeof(uint32_t) * (2 * y.m + 1));
     // deferred derivation (single graphs): Xi, Xj, Y, K of every edge
-    y.defer = G == 0 && (size_t)y.m * 4 * LL * sizeof(uint64_t) <= XYK_BUDGET;
+    y.defer = G == 0 && (size_t)y.m * 4 * LL * sizeof(uint64_t) <= bud.xyk_bytes;
     if (y.defer) y.off_xyk = take(sizeof(uint64_t) * (size_t)(y.m + 1) * 4 * LL);
     y.off_nlow = take(sizeof(uint32_t) * (n + 1));
     const size_t hw = HUB_MAX / 64;
@@ -145,8 +158,8 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G) {
     {
         const int64_t nw = (n + 63) / 64;
         const size_t per_sh = (size_t)nw * (sizeof(uint64_t) + sizeof(uint32_t));
-        int64_t shm = (int64_t)(SH_BUDGET / (per_sh > 0 ? per_sh : 1));
-        if (shm > g_tune[TG_TUNE_SH_MAX]) shm = g_tune[TG_TUNE_SH_MAX];
+        int64_t shm = (int64_t)(bud.sh_bytes / (per_sh > 0 ? per_sh : 1));
+        if (shm > bud.sh_max) shm = bud.sh_max;
         y.sh_max = (int)shm;
         y.off_SB = take(sizeof(uint64_t) * (size_t)nw * (size_t)(shm > 0 ? shm : 1));
         y.off_SP = take(sizeof(uint32_t) * (size_t)nw * (size_t)(shm > 0 ? shm : 1));
@@ -501,6 +514,79 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     return TG_OK;
 }
 
+// --------------------------------------------------- allocation-free entry
+
+// Scratch of tg_count_typed_graphlets_noalloc: a file-scope device array,
+// one copy per device (at its own address), held until the process ends.
+// Host code never passes `scratch` itself to a kernel: it is a host-side
+// stand-in; the device address comes from hipGetSymbolAddress, once per
+// device, and every use goes through that pointer.
+static __device__ __align__(256) unsigned char scratch[TG_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of the current device's scratch (looked up on the first
+// call on that device, with the device current).
+static tg_status scratch_for_current_device(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_failed(e, "hipGetDevice");
+    if (dev < 0 || dev >= MAX_DEVICES) return TG_E_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_failed(e, "hipGetSymbolAddress(scratch)");
+        if (!p || !ws_aligned(p)) return TG_E_INTERNAL;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TG_OK;
+}
+
+// Workspace layout inside the scratch: the per-node and per-edge regions
+// with one heavy 4-cycle map, one heavy-edge list and no super-hub bitmaps
+// must fit; what is left goes to the separate derivation pass's inputs
+// (when they take at most half of it), then half of the rest to more
+// cycle maps, a quarter to heavy-edge lists and a quarter to super-hub
+// bitmaps, each also capped by the calling thread's knobs.
+static tg_status plan_noalloc(int64_t n, int64_t nnz, int L, Layout *y) {
+    if (L < 1 || L > TG_MAX_L) return TG_E_L_RANGE;
+    if (n < 0 || nnz < 0 || (nnz & 1)) return TG_E_INVALID_ARG;
+    const size_t cap = (size_t)TG_NOALLOC_SCRATCH_BYTES;
+    const size_t slack = size_t(1) << 16;  // region alignment
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    const size_t per_map = nn * L * sizeof(uint32_t), per_t = nn * sizeof(uint32_t);
+    const size_t per_sh = (size_t)((n + 63) / 64) * (sizeof(uint64_t) + sizeof(uint32_t));
+    Budget b{per_map, 1, per_t, 1, 0, 0, 0};
+    tg_status s = plan_layout(n, nnz, L, y, 0, b);
+    if (s != TG_OK) return s;
+    if (y->total + slack > cap) return TG_E_TOO_LARGE;
+    size_t rem = cap - y->total - slack;
+    const size_t xyk = (size_t)(nnz / 2) * 4 * L * L * sizeof(uint64_t);
+    if (xyk <= rem / 2) {
+        b.xyk_bytes = xyk;
+        rem -= xyk;
+    }
+    int64_t cs = 1 + (int64_t)(rem / 2 / per_map);
+    if (cs > g_tune[TG_TUNE_CYCLE_SLOTS]) cs = g_tune[TG_TUNE_CYCLE_SLOTS];
+    int64_t es = 1 + (int64_t)(rem / 4 / per_t);
+    if (es > g_tune[TG_TUNE_EDGE_SLOTS]) es = g_tune[TG_TUNE_EDGE_SLOTS];
+    int64_t sh = (int64_t)(rem / 4 / per_sh);
+    if (sh > g_tune[TG_TUNE_SH_MAX]) sh = g_tune[TG_TUNE_SH_MAX];
+    b.cycle_slots = cs;
+    b.map_bytes = (size_t)cs * per_map;
+    b.edge_slots = es;
+    b.tbuf_bytes = (size_t)es * per_t;
+    b.sh_max = sh;
+    b.sh_bytes = (size_t)sh * per_sh;
+    s = plan_layout(n, nnz, L, y, 0, b);
+    if (s != TG_OK) return s;
+    return y->total <= cap ? TG_OK : TG_E_INTERNAL;
+}
+
 }  // namespace tg
 
 // ================================================================ C ABI
@@ -560,6 +646,33 @@ tg_status tg_count_typed_graphlets(const int64_t *row_ptr, const int32_t *col,
     }
     return tg::run(row_ptr, col, types, n, nnz, L, per_edge, global_counts, workspace, y, st,
                    nullptr);
+}
+
+tg_status tg_count_typed_graphlets_noalloc(const int64_t *row_ptr, const int32_t *col,
+                                           const uint8_t *types, int64_t n, int64_t nnz,
+                                           int32_t L, uint64_t *per_edge,
+                                           uint64_t *global_counts, void *stream) {
+    tg::Layout y;
+    tg_status s = tg::plan_noalloc(n, nnz, L, &y);
+    if (s != TG_OK) return s;
+    if (n > 0 && (!row_ptr || !types)) return TG_E_INVALID_ARG;
+    if (nnz > 0 && !col) return TG_E_INVALID_ARG;
+    void *ws = nullptr;
+    s = tg::scratch_for_current_device(&ws);
+    if (s != TG_OK) return s;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (n == 0) {
+        if (global_counts && tg::launch_fill_u64(global_counts, 0, tg_global_width(L), st) !=
+                                 hipSuccess)
+            return TG_E_DEVICE;
+        return hipStreamSynchronize(st) == hipSuccess ? TG_OK : TG_E_DEVICE;
+    }
+    // no phase events (their creation is not needed by the counts)
+    const bool timing = tg::g_timing.enabled;
+    tg::g_timing.enabled = false;
+    s = tg::run(row_ptr, col, types, n, nnz, L, per_edge, global_counts, ws, y, st, nullptr);
+    tg::g_timing.enabled = timing;
+    return s;
 }
 
 size_t tg_batch_workspace_bytes(int64_t n, int64_t nnz, int64_t G, int32_t L_max) {

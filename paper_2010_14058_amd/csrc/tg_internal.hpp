@@ -78,7 +78,26 @@ enum Counter {
     C_NUM
 };
 
-tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G = 0);
+// Workspace budgets of the per-workgroup scratch regions: the heavy 4-cycle
+// maps (n L words each), the heavy-edge member lists (n words each), the
+// super-hub bitmaps and the per-edge inputs of the separate derivation pass.
+struct Budget {
+    size_t map_bytes;
+    int64_t cycle_slots;
+    size_t tbuf_bytes;
+    int64_t edge_slots;
+    int64_t sh_max;
+    size_t sh_bytes;
+    size_t xyk_bytes;
+};
+
+// The budgets the scheduling knobs of the calling thread give.
+Budget budget_from_tuning();
+
+tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G, const Budget &b);
+inline tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G = 0) {
+    return plan_layout(n, nnz, L, lay, G, budget_from_tuning());
+}
 
 // Batch descriptor (device pointers) of tg_count_batch.
 struct BatchIn {

@@ -141,3 +141,18 @@ def test_workspace_alignment_checked_first():
     assert bneed > 0
     assert lib.tg_count_batch(fake, fake, fake, n, nnz, fake, fake, G, nt, fake, 10, None, fake,
                               fake + 64, bneed, None) == 1
+
+
+def test_noalloc_rejects_oversized_graph():
+    """A graph whose workspace exceeds the static scratch is refused before
+    any device work (no GPU needed to see it)."""
+    L = _lib()
+    lib = L.load()
+    dummy = ctypes.c_void_p(8)  # never dereferenced: the size check comes first
+    rc = lib.tg_count_typed_graphlets_noalloc(dummy, dummy, dummy, 50_000_000, 0, 5, None, None,
+                                              None)
+    assert rc == 8  # TG_E_TOO_LARGE
+    assert lib.tg_count_typed_graphlets_noalloc(dummy, dummy, dummy, 10, 3, 5, None, None,
+                                                None) == 1  # odd nnz
+    assert lib.tg_count_typed_graphlets_noalloc(dummy, dummy, dummy, 10, 2, 0, None, None,
+                                                None) == 4  # L out of range
