@@ -16,4 +16,12 @@ from .oracle import (  # noqa: F401
     all_edge_rows,
     global_counts,
     column_names,
+    PA_BLOCKS,
+    pa_row_width,
+    pa_global_width,
+    pa_column_names,
+    pa_edge_rows,
+    pa_all_edge_rows,
+    pa_global_counts,
+    pa_global_describe,
 )

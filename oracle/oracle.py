@@ -45,6 +45,13 @@ def _load():
         lib.tgo_edges.argtypes = [i64, p, p, p, ctypes.c_int, p, i64, ctypes.c_int,
                                   ctypes.c_int, p]
         lib.tgo_global_from_rows.argtypes = [p, ctypes.c_int, p, i64, p, p]
+        lib.tgo_pa_row_width.argtypes = [ctypes.c_int]
+        lib.tgo_pa_global_width.argtypes = [ctypes.c_int]
+        lib.tgo_pa_global_width.restype = i64
+        lib.tgo_pa_edges.argtypes = [i64, p, p, p, ctypes.c_int, p, i64, ctypes.c_int,
+                                     ctypes.c_int, p]
+        lib.tgo_pa_global_from_rows.argtypes = [p, ctypes.c_int, p, i64, p, p]
+        lib.tgo_pa_global_describe.argtypes = [ctypes.c_int, i64, p, p]
         _lib = lib
     return _lib
 
@@ -121,3 +128,73 @@ def global_counts(g, rows: np.ndarray) -> np.ndarray:
     _check(_load().tgo_global_from_rows(_ptr(ty), g.L, _ptr(uv), uv.shape[0], _ptr(rows),
                                         _ptr(out)))
     return out
+
+
+# ------------------------------------------------ position-aware (Sec. 5)
+
+PA_BLOCKS = ["tri", "path_i", "path_j", "g3i", "g3j", "g4", "g5i", "g5j", "g6", "g7i", "g7j",
+             "g8", "g9i", "g9j", "g10i", "g10j", "g11", "g12"]
+PA_PAIR_BLOCKS = {"g5i", "g5j", "g7i", "g7j", "g11", "g12"}
+
+
+def pa_row_width(L: int) -> int:
+    return _load().tgo_pa_row_width(L)
+
+
+def pa_global_width(L: int) -> int:
+    return int(_load().tgo_pa_global_width(L))
+
+
+def pa_column_names(L: int) -> list[str]:
+    """Names of the position-aware row's columns: block[x,y] for ordered
+    role pairs, block{t,u} for unordered ones, block[t] for 3-node blocks."""
+    names = []
+    for b in PA_BLOCKS:
+        if b in ("tri", "path_i", "path_j"):
+            names += [f"{b}[{t}]" for t in range(L)]
+        elif b in PA_PAIR_BLOCKS:
+            names += [f"{b}{{{t},{u}}}" for t in range(L) for u in range(t, L)]
+        else:
+            names += [f"{b}[{x},{y}]" for x in range(L) for y in range(L)]
+    return names
+
+
+def pa_edge_rows(g, uv: np.ndarray, method: str = "paper", threads: int | None = None) -> np.ndarray:
+    """Position-aware rows for edges uv[k, 2], each oriented as given."""
+    rp, col, ty = _arrays(g)
+    uv = np.ascontiguousarray(uv, dtype=np.int64).reshape(-1, 2)
+    out = np.zeros((uv.shape[0], pa_row_width(g.L)), dtype=np.uint64)
+    if uv.shape[0] == 0:
+        return out
+    threads = threads or os.cpu_count() or 1
+    m = 1 if method == "paper" else 0
+    _check(_load().tgo_pa_edges(g.n, _ptr(rp), _ptr(col), _ptr(ty), g.L, _ptr(uv),
+                                uv.shape[0], m, int(threads), _ptr(out)))
+    return out
+
+
+def pa_all_edge_rows(g, method: str = "paper", threads: int | None = None) -> np.ndarray:
+    """Position-aware rows of every edge (u < v, oriented u -> v), lexicographic."""
+    return pa_edge_rows(g, g.edges(), method=method, threads=threads)
+
+
+def pa_global_counts(g, rows: np.ndarray) -> np.ndarray:
+    """Global position-aware counts (classes under type-preserving
+    isomorphism) from the position-aware rows of all edges."""
+    uv = np.ascontiguousarray(g.edges(), dtype=np.int64)
+    rows = np.ascontiguousarray(rows, dtype=np.uint64)
+    ty = np.ascontiguousarray(g.types, dtype=np.uint8)
+    out = np.zeros(pa_global_width(g.L), dtype=np.uint64)
+    _check(_load().tgo_pa_global_from_rows(_ptr(ty), g.L, _ptr(uv), uv.shape[0], _ptr(rows),
+                                           _ptr(out)))
+    return out
+
+
+def pa_global_describe(L: int, idx: int):
+    """(graphlet 0..8, types by node position) of global class idx."""
+    h = ctypes.c_int()
+    ts = (ctypes.c_int * 4)()
+    k = _load().tgo_pa_global_describe(L, idx, ctypes.byref(h), ts)
+    if k == 0:
+        raise IndexError(idx)
+    return h.value, tuple(ts[:k])

@@ -150,3 +150,199 @@ def global_instances(n, edges, types, L):
         key = r4[tuple(sorted(int(types[x]) for x in quad))]
         out[n2 + 2 * n3 + (h - 3) * n4 + key] += 1
     return out
+
+
+# ------------------------------------------------ position-aware (Sec. 5)
+#
+# Templates with numbered positions (the same drawings as above):
+#   3: 4-path 0-1-2-3; 4: 4-star centre 0; 5: 4-cycle 0-1-2-3-0;
+#   6: tailed triangle 0,1,2 with tail 2-3; 7: chordal cycle 0-1-2-3-0
+#   with chord 0-2; 8: 4-clique.
+# For an edge of a matched template, seen oriented (i at template position
+# pi, j at pj), ROLE gives the block of the position-aware row and the
+# positions whose types are its (x, y) key (ordered), or the two positions
+# of an unordered key.  It is written from the drawings, position by
+# position, not from the sets S_i, S_j, T and I.
+
+PA_PAIR = {"g5i", "g5j", "g7i", "g7j", "g11", "g12"}
+
+
+def _cyc_next(p, other):
+    """Cycle 0-1-2-3-0: the neighbour of p that is not `other`."""
+    a, b = (p + 1) % 4, (p + 3) % 4
+    return a if b == other else b
+
+
+def role(h, pi, pj):
+    if h == 3:                                   # path 0-1-2-3
+        e = {pi, pj}
+        if e == {1, 2}:                          # centre edge: x hangs at i, y at j
+            return "g4", pi - 1 if pi == 1 else 3, pj - 1 if pj == 1 else 3
+        if e == {0, 1}:                          # the path continues from position 1
+            return ("g3i" if pi == 1 else "g3j"), 2, 3
+        return ("g3i" if pi == 2 else "g3j"), 1, 0  # edge {2, 3}, continues from 2
+    if h == 4:                                   # star, centre 0
+        others = [q for q in (1, 2, 3) if q not in (pi, pj)]
+        return ("g5i" if pi == 0 else "g5j"), others[0], others[1]
+    if h == 5:                                   # cycle
+        return "g6", _cyc_next(pi, pj), _cyc_next(pj, pi)
+    if h == 6:                                   # triangle 0,1,2; tail 2-3
+        e = {pi, pj}
+        if e == {2, 3}:                          # the tail edge
+            return ("g7i" if pi == 2 else "g7j"), 0, 1
+        if e == {0, 1}:                          # triangle edge away from the tail
+            return "g8", 2, 3
+        third = ({0, 1} - e).pop()               # triangle edge at position 2
+        return ("g9i" if pi == 2 else "g9j"), third, 3
+    if h == 7:                                   # cycle 0-1-2-3-0, chord 0-2
+        e = {pi, pj}
+        if e == {0, 2}:
+            return "g11", 1, 3
+        chord_end = pi if pi in (0, 2) else pj   # the outer edge's chord end
+        rim = pj if chord_end == pi else pi
+        return ("g10i" if chord_end == pi else "g10j"), 2 - chord_end, 4 - rim
+    others = [q for q in range(4) if q not in (pi, pj)]
+    return "g12", others[0], others[1]
+
+
+def pa_column_index(L):
+    """name -> column of the documented position-aware row layout."""
+    names, c = {}, 0
+    for b in ["tri", "path_i", "path_j"]:
+        for t in range(L):
+            names[f"{b}[{t}]"] = c
+            c += 1
+    for b in ["g3i", "g3j", "g4", "g5i", "g5j", "g6", "g7i", "g7j", "g8", "g9i", "g9j", "g10i",
+              "g10j", "g11", "g12"]:
+        if b in PA_PAIR:
+            for t, u in _pairs(L):
+                names[f"{b}{{{t},{u}}}"] = c
+                c += 1
+        else:
+            for x in range(L):
+                for y in range(L):
+                    names[f"{b}[{x},{y}]"] = c
+                    c += 1
+    return names
+
+
+def _matches(nodes, adj):
+    """All bijections (node -> template position) onto the matching template."""
+    edges = {frozenset((a, b)) for a, b in itertools.combinations(nodes, 2) if adj[a][b]}
+    for h, tmpl in _TEMPLATE_SETS.items():
+        if len(tmpl) != len(edges):
+            continue
+        out = []
+        for perm in itertools.permutations(range(4)):
+            mp = {nodes[p]: q for p, q in zip(range(4), perm)}
+            if {frozenset(mp[x] for x in e) for e in edges} == set(tmpl):
+                out.append(mp)
+        if out:
+            return h, out
+    return None, []
+
+
+def pa_per_edge_rows(n, edges, types, L):
+    """Position-aware rows for edges in the orientation given (i, j)."""
+    adj = adjacency(n, edges)
+    col = pa_column_index(L)
+    rows = np.zeros((len(edges), len(col)), dtype=np.uint64)
+    for q, (i, j) in enumerate(edges):
+        for k in range(n):
+            if k in (i, j):
+                continue
+            a, b = adj[i][k], adj[j][k]
+            t = int(types[k])
+            if a and b:
+                rows[q, col[f"tri[{t}]"]] += 1
+            elif a:
+                rows[q, col[f"path_i[{t}]"]] += 1
+            elif b:
+                rows[q, col[f"path_j[{t}]"]] += 1
+    where = {}
+    for q, (i, j) in enumerate(edges):
+        where[frozenset((i, j))] = q
+    for quad in itertools.combinations(range(n), 4):
+        if not _connected(list(quad), adj):
+            continue
+        h, maps = _matches(list(quad), adj)
+        mp = maps[0]
+        pos_node = {p: v for v, p in mp.items()}
+        for e, q in where.items():
+            if not e <= set(quad):
+                continue
+            i, j = edges[q]
+            block, px, py = role(h, mp[i], mp[j])
+            tx, ty = int(types[pos_node[px]]), int(types[pos_node[py]])
+            if block in PA_PAIR:
+                tx, ty = sorted((tx, ty))
+                rows[q, col[f"{block}{{{tx},{ty}}}"]] += 1
+            else:
+                rows[q, col[f"{block}[{tx},{ty}]"]] += 1
+    return rows
+
+
+def _canon(h, maps, types):
+    """Smallest types-by-position tuple over every matching bijection (the
+    class of the typed instance under type-preserving isomorphism)."""
+    best = None
+    for mp in maps:
+        lab = [0] * 4
+        for v, p in mp.items():
+            lab[p] = int(types[v])
+        lab = tuple(lab)
+        if best is None or lab < best:
+            best = lab
+    return best
+
+
+def pa_global_instances(n, edges, types, L):
+    """Instance counts per class, keyed (graphlet, canonical labelling):
+    h0 (sorted pair), h1 (centre, sorted ends), h2 (sorted triple), h3..h8
+    the smallest types-by-position tuple over the template's matches."""
+    adj = adjacency(n, edges)
+    out = {}
+
+    def add(key):
+        out[key] = out.get(key, 0) + 1
+
+    for a, b in edges:
+        add((0, tuple(sorted((int(types[a]), int(types[b]))))))
+    for tri in itertools.combinations(range(n), 3):
+        es = [(x, y) for x, y in itertools.combinations(tri, 2) if adj[x][y]]
+        if len(es) == 3:
+            add((2, tuple(sorted(int(types[x]) for x in tri))))
+        elif len(es) == 2:
+            centre = [x for x in tri if all(x in e for e in es)][0]
+            ends = sorted(int(types[x]) for x in tri if x != centre)
+            add((1, (int(types[centre]), ends[0], ends[1])))
+    for quad in itertools.combinations(range(n), 4):
+        if not _connected(list(quad), adj):
+            continue
+        h, maps = _matches(list(quad), adj)
+        add((h, _canon(h, maps, types)))
+    return out
+
+
+def pa_class_key(h, lab, L):
+    """The brute force's class key of a types-by-position labelling of
+    graphlet h (as pa_global_instances keys it)."""
+    if h == 0:
+        return (0, tuple(sorted(lab)))
+    if h == 2:
+        return (2, tuple(sorted(lab)))
+    if h == 1:
+        return (1, (lab[0],) + tuple(sorted(lab[1:])))
+    # every position permutation that maps the template onto itself
+    tmpl = set(_TEMPLATE_SETS[h])
+    best = None
+    for perm in itertools.permutations(range(4)):
+        if {frozenset(perm[x] for x in e) for e in tmpl} != tmpl:
+            continue
+        img = [0] * 4
+        for q in range(4):
+            img[perm[q]] = lab[q]
+        img = tuple(img)
+        if best is None or img < best:
+            best = img
+    return (h, best)
