@@ -186,6 +186,75 @@ tg_status tg_sparse_offsets(const uint64_t *rows, int64_t m, int32_t L, int64_t 
 tg_status tg_sparse_fill(const uint64_t *rows, int64_t m, int32_t L, const int64_t *edge_off,
                          uint16_t *keys, uint64_t *counts, void *stream);
 
+/* Position-aware typed graphlets (Sec. 5; Def. of a position-aware typed
+ * graphlet instance: node types must coincide via the isomorphism).  The
+ * per-edge counts keep the role each of the two other nodes k, r plays
+ * relative to the edge (i, j), oriented with i the edge's first endpoint in
+ * canonical order (i < j in the input's ids); the global counts are kept per
+ * class of typed graphlets under type-preserving isomorphism.  Folding the
+ * roles of each block gives the typed row of tg_count_typed_graphlets.
+ *
+ * Per-edge row (tg_pa_row_width(L) = 3L + 9 L^2 + 6 P columns), blocks in
+ * this order; an ordered block holds (x, y) at x*L + y, an unordered block
+ * {t <= u} at the lexicographic pair index, a 3-node block t at t.  With
+ * S_i the neighbours of i that are neither j nor adjacent to j, S_j
+ * likewise, T the common neighbours and I the nodes adjacent to neither:
+ *   0 TRI [t]     |T^t|              1 PATH_I [t]  |S_i^t| (3-path k-i-j)
+ *   2 PATH_J [t]  |S_j^t| (i-j-k)
+ *   3 G3I (x,y)   k in S_i^x, r in I^y, k~r: 4-path r-k-i-j
+ *   4 G3J (x,y)   k in S_j^x, r in I^y, k~r: 4-path i-j-k-r
+ *   5 G4 (x,y)    k in S_i^x, r in S_j^y, not k~r: 4-path k-i-j-r
+ *   6 G5I {t,u}   k, r in S_i, not k~r: 4-star centred at i
+ *   7 G5J {t,u}   the same at j
+ *   8 G6 (x,y)    k in S_i^x, r in S_j^y, k~r: 4-cycle i-j-r-k
+ *   9 G7I {t,u}   k, r in S_i, k~r: triangle i-k-r with tail j
+ *  10 G7J {t,u}   the same at j
+ *  11 G8 (x,y)    k in T^x, r in I^y, k~r: triangle i-j-k, tail r at k
+ *  12 G9I (x,y)   k in T^x, r in S_i^y, not k~r: tail r at i
+ *  13 G9J (x,y)   k in T^x, r in S_j^y, not k~r: tail r at j
+ *  14 G10I (x,y)  k in T^x, r in S_i^y, k~r: chordal cycle, chord i-k
+ *  15 G10J (x,y)  k in T^x, r in S_j^y, k~r: chordal cycle, chord j-k
+ *  16 G11 {t,u}   k, r in T, not k~r: chordal cycle, chord i-j
+ *  17 G12 {t,u}   k, r in T, k~r: 4-clique
+ * Global layout (tg_pa_global_width(L) classes): graphlets h0..h8 in order,
+ * each class described by the types at the positions of a drawing: h0 edge
+ * (0,1); h1 3-path 1-0-2 (0 the centre); h2 triangle; h3 4-path 0-1-2-3;
+ * h4 4-star with centre 0; h5 4-cycle 0-1-2-3-0; h6 tailed triangle with
+ * triangle 0,1,2 and tail 2-3; h7 chordal cycle 0-1-2-3-0 with chord 0-2;
+ * h8 4-clique.  With rk2(x, y) = min + max(max+1)/2 (co-lexicographic rank
+ * of an unordered pair over any alphabet), rk3 / rk4 the co-lexicographic
+ * ranks of sorted multisets and P = L(L+1)/2, the index inside each block:
+ *   h0 rk2(t0,t1); h1 t0*P + rk2(t1,t2); h2 rk3; h3 rk2(t0*L+t1, t3*L+t2);
+ *   h4 t0*C(L+2,3) + rk3(t1,t2,t3); h5 rk2(rk2(t0,t2), rk2(t1,t3));
+ *   h6 (t3*L + t2)*P + rk2(t0,t1); h7 rk2(t0,t2)*P + rk2(t1,t3); h8 rk4.
+ * Each entry counts instances (per-edge sums divided by the graphlet's
+ * edge count). */
+int32_t tg_pa_row_width(int32_t L);
+int64_t tg_pa_global_width(int32_t L);
+
+/* Position-aware counts of one graph, arguments, workspace
+ * (tg_workspace_bytes), streams and errors as for tg_count_typed_graphlets;
+ * per_edge is device uint64 [nnz/2][tg_pa_row_width(L)] or NULL,
+ * global_counts device uint64 [tg_pa_global_width(L)] or NULL.  The
+ * position-aware derivation runs as its own pass over per-edge inputs
+ * held in the workspace: a graph whose (nnz/2) * 32 L^2 bytes exceed 16 GiB
+ * gives TG_E_TOO_LARGE before any device work. */
+tg_status tg_count_position_aware(const int64_t *row_ptr, const int32_t *col,
+                                  const uint8_t *types, int64_t n, int64_t nnz, int32_t L,
+                                  uint64_t *per_edge, uint64_t *global_counts, void *workspace,
+                                  size_t ws_bytes, void *stream);
+
+/* Meaning of position-aware column `col`: *block 0..17 as listed above,
+ * *t, *t2 the role types (x, y), the unordered pair t <= t2, or the type
+ * and -1 for the 3-node blocks. */
+tg_status tg_pa_key_describe(int32_t L, int32_t col, int32_t *block, int32_t *t, int32_t *t2);
+
+/* Meaning of position-aware global entry `idx`: *graphlet 0..8, *k its node
+ * count and types_by_position[0..k-1] the types at the drawing's positions
+ * of one member of the class (the rest set to -1). */
+tg_status tg_pa_global_key_describe(int32_t L, int64_t idx, int32_t *graphlet,
+                                    int32_t types_by_position[4], int32_t *k);
+
 /* Meaning of per-edge column `col` for L types: orbit 1 = tri, 2 = path3
  * (with *t the third node's type and *t2 = -1), else the orbit number 3..12
  * of Table 3 with the unordered type pair (*t <= *t2). */

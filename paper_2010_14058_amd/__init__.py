@@ -16,6 +16,10 @@ from ._lib import (  # noqa: F401
     global_width,
     key_describe,
     last_stats,
+    pa_global_key_describe,
+    pa_global_width,
+    pa_key_describe,
+    pa_row_width,
     phase_times,
     row_width,
     set_timing,
@@ -81,6 +85,44 @@ def count_typed_graphlets(row_ptr, col, types, L: int, *, per_edge: bool = True,
     _lib.count_raw(row_ptr.data_ptr(), col.data_ptr() if nnz else 0, types.data_ptr(), n, nnz, L,
                    rows.data_ptr() if rows is not None and rows.numel() else 0,
                    glob.data_ptr(), ws.data_ptr(), ws.numel(), stream.cuda_stream)
+    return rows, glob
+
+
+def count_position_aware(row_ptr, col, types, L: int, *, per_edge: bool = True, out_rows=None,
+                         out_global=None, workspace: Workspace | None = None, stream=None):
+    """Position-aware typed graphlet counts (Sec. 5) of one graph held in
+    device tensors; arguments as for :func:`count_typed_graphlets`.  Returns
+    ``(rows [nnz/2, pa_row_width(L)] or None, glob [pa_global_width(L)])``,
+    int64 tensors holding the uint64 counts, each edge's row oriented from
+    its first to its second endpoint in canonical order."""
+    import torch
+
+    dev = row_ptr.device
+    if dev.type != "cuda":
+        raise ValueError("inputs must be device tensors")
+    if row_ptr.dtype != torch.int64 or col.dtype != torch.int32 or types.dtype != torch.uint8:
+        raise TypeError("row_ptr int64, col int32, types uint8 expected")
+    row_ptr, col, types = row_ptr.contiguous(), col.contiguous(), types.contiguous()
+    n, nnz = row_ptr.numel() - 1, col.numel()
+    W = pa_row_width(L)
+    if W == 0:
+        raise _lib.TGError(4, "count_position_aware")
+    rows = None
+    if per_edge:
+        rows = out_rows if out_rows is not None else torch.empty((nnz // 2, W), dtype=torch.int64,
+                                                                 device=dev)
+    glob = out_global if out_global is not None else torch.empty(pa_global_width(L),
+                                                                 dtype=torch.int64, device=dev)
+    wsb = workspace_bytes(n, nnz, L)
+    if wsb == 0:
+        raise _lib.TGError(1, "tg_workspace_bytes")
+    ws = (workspace or Workspace(dev)).get(wsb)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    _lib.count_position_aware_raw(row_ptr.data_ptr(), col.data_ptr() if nnz else 0,
+                                  types.data_ptr(), n, nnz, L,
+                                  rows.data_ptr() if rows is not None and rows.numel() else 0,
+                                  glob.data_ptr(), ws.data_ptr(), ws.numel(), stream.cuda_stream)
     return rows, glob
 
 

@@ -47,6 +47,15 @@ SIGNATURES = {
     "tg_sparse_fill": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int32, _c.c_void_p, _c.c_void_p,
                                   _c.c_void_p, _c.c_void_p]),
     "tg_get_tuning": (_c.c_int64, [_c.c_int32]),
+    "tg_pa_row_width": (_c.c_int32, [_c.c_int32]),
+    "tg_pa_global_width": (_c.c_int64, [_c.c_int32]),
+    "tg_count_position_aware": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int64,
+                                           _c.c_int64, _c.c_int32, _c.c_void_p, _c.c_void_p,
+                                           _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "tg_pa_key_describe": (_c.c_int, [_c.c_int32, _c.c_int32, _c.POINTER(_c.c_int32),
+                                      _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
+    "tg_pa_global_key_describe": (_c.c_int, [_c.c_int32, _c.c_int64, _c.POINTER(_c.c_int32),
+                                             _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
 }
 
 _lib = None
@@ -205,3 +214,45 @@ def sparse_fill_raw(rows_ptr: int, m: int, L: int, off_ptr: int, keys_ptr: int, 
     rc = load().tg_sparse_fill(rows_ptr, m, L, off_ptr, keys_ptr, counts_ptr, stream)
     if rc:
         raise TGError(rc, "tg_sparse_fill")
+
+
+# ------------------------------------------------ position-aware (Sec. 5)
+
+PA_BLOCKS = ["tri", "path_i", "path_j", "g3i", "g3j", "g4", "g5i", "g5j", "g6", "g7i", "g7j",
+             "g8", "g9i", "g9j", "g10i", "g10j", "g11", "g12"]
+
+
+def pa_row_width(L: int) -> int:
+    return load().tg_pa_row_width(L)
+
+
+def pa_global_width(L: int) -> int:
+    return int(load().tg_pa_global_width(L))
+
+
+def pa_key_describe(L: int, col: int):
+    """(block name, t, t2) of position-aware column col."""
+    b, t, u = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    rc = load().tg_pa_key_describe(L, col, ctypes.byref(b), ctypes.byref(t), ctypes.byref(u))
+    if rc:
+        raise TGError(rc, "tg_pa_key_describe")
+    return PA_BLOCKS[b.value], t.value, u.value
+
+
+def pa_global_key_describe(L: int, idx: int):
+    """(graphlet 0..8, types by drawing position) of global class idx."""
+    h, k = ctypes.c_int32(), ctypes.c_int32()
+    ts = (ctypes.c_int32 * 4)()
+    rc = load().tg_pa_global_key_describe(L, idx, ctypes.byref(h), ts, ctypes.byref(k))
+    if rc:
+        raise TGError(rc, "tg_pa_global_key_describe")
+    return h.value, tuple(ts[: k.value])
+
+
+def count_position_aware_raw(row_ptr: int, col: int, types: int, n: int, nnz: int, L: int,
+                             per_edge: int, glob: int, ws: int, ws_bytes: int,
+                             stream: int) -> None:
+    rc = load().tg_count_position_aware(row_ptr, col, types, n, nnz, L, per_edge, glob, ws,
+                                        ws_bytes, stream)
+    if rc:
+        raise TGError(rc, "tg_count_position_aware")

@@ -167,6 +167,7 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G, con
     y.off_node_graph = take(sizeof(int32_t) * (G > 0 ? n + 1 : 1));
     y.off_ngraph = take(sizeof(int32_t) * (G > 0 ? n + 1 : 1));
     y.off_gedge = take(sizeof(int64_t) * (G + 1));
+    y.off_pacc = take(sizeof(uint64_t) * (size_t)pa_layout(L).gstart[9]);
     y.total = off;
     return TG_OK;
 }
@@ -226,9 +227,12 @@ static T *at(void *base, size_t off) {
     return reinterpret_cast<T *>(static_cast<char *>(base) + off);
 }
 
+// One counting call.  pa: per_edge and global_counts receive the
+// position-aware layout (needs the separate derivation pass, y.defer).
 static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *types, int64_t n,
                      int64_t nnz, int L, uint64_t *per_edge, uint64_t *global_counts, void *ws,
-                     const Layout &y, hipStream_t st, const BatchIn *batch) {
+                     const Layout &y, hipStream_t st, const BatchIn *batch, bool pa = false) {
+    if (pa && (batch || !y.defer)) return TG_E_INTERNAL;
     const int64_t m = y.m;
     const int LL = L * L;
     const int gw = tg_global_width(L);
@@ -483,16 +487,29 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     if (xyk) eh.hist_in_lds = 0;
     HIPCHK(launch_edges(true, eh, (unsigned)y.heavy_edge_slots, st));
     timing_mark("edges_heavy");
-    if (xyk) {
+    if (pa) {
+        const PaLayout pl = pa_layout(L);
+        uint64_t *pacc = at<uint64_t>(ws, y.off_pacc);
+        HIPCHK(launch_fill_u64(pacc, 0, pl.gstart[9], st));
+        ed.gacc = pacc;
+        ed.gw = (int)pl.gstart[9];
+        ed.hist_in_lds = (size_t)ed.gw * sizeof(uint64_t) <= 32768 ? 1 : 0;
+        HIPCHK(launch_derive_pa(ed, pl, (unsigned)(cus > 0 ? cus * 8 : 2048), st));
+        timing_mark("derive");
+        if (global_counts) HIPCHK(launch_pa_finalize(pacc, pl, global_counts, status, st));
+        timing_mark("global");
+    } else if (xyk) {
         ed.hist_in_lds = (size_t)gw * sizeof(uint64_t) <= 32768 ? 1 : 0;
         HIPCHK(launch_derive(ed, (unsigned)(cus > 0 ? cus * 8 : 2048), st));
         timing_mark("derive");
     }
-    if (batch)
+    if (pa) {
+        // position-aware globals done above
+    } else if (batch)
         HIPCHK(launch_batch_finalize(global_counts, batch->gL, batch->goff, batch->G, status, st));
     else if (global_counts)
         HIPCHK(launch_global_finalize(gacc, L, gw, global_counts, status, st));
-    timing_mark("global");
+    if (!pa) timing_mark("global");
 
     HIPCHK(hipMemcpyAsync(&probe.status, status, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     uint64_t cnt_host[C_NUM];
@@ -673,6 +690,138 @@ tg_status tg_count_typed_graphlets_noalloc(const int64_t *row_ptr, const int32_t
     s = tg::run(row_ptr, col, types, n, nnz, L, per_edge, global_counts, ws, y, st, nullptr);
     tg::g_timing.enabled = timing;
     return s;
+}
+
+int32_t tg_pa_row_width(int32_t L) {
+    if (L < 1 || L > TG_MAX_L) return 0;
+    return tg::pa_layout(L).start[tg::PB_NUM];
+}
+
+int64_t tg_pa_global_width(int32_t L) {
+    if (L < 1 || L > TG_MAX_L) return 0;
+    return tg::pa_layout(L).gstart[9];
+}
+
+tg_status tg_count_position_aware(const int64_t *row_ptr, const int32_t *col,
+                                  const uint8_t *types, int64_t n, int64_t nnz, int32_t L,
+                                  uint64_t *per_edge, uint64_t *global_counts, void *workspace,
+                                  size_t ws_bytes, void *stream) {
+    tg::Layout y;
+    tg_status s = tg::plan_layout(n, nnz, L, &y);
+    if (s != TG_OK) return s;
+    if (n > 0 && (!row_ptr || !types)) return TG_E_INVALID_ARG;
+    if (nnz > 0 && !col) return TG_E_INVALID_ARG;
+    if (!workspace || !tg::ws_aligned(workspace)) return TG_E_INVALID_ARG;
+    if (ws_bytes < y.total) return TG_E_WORKSPACE;
+    if (!y.defer) return TG_E_TOO_LARGE;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (n == 0) {
+        if (global_counts && tg::launch_fill_u64(global_counts, 0, tg_pa_global_width(L), st) !=
+                                 hipSuccess)
+            return TG_E_DEVICE;
+        return hipStreamSynchronize(st) == hipSuccess ? TG_OK : TG_E_DEVICE;
+    }
+    return tg::run(row_ptr, col, types, n, nnz, L, per_edge, global_counts, workspace, y, st,
+                   nullptr, true);
+}
+
+namespace {
+// Unordered pair {lo <= hi} at co-lexicographic rank r.
+void unrank_pair(int64_t r, int64_t *lo, int64_t *hi) {
+    int64_t h = 0;
+    while ((h + 1) * (h + 2) / 2 <= r) ++h;
+    *hi = h;
+    *lo = r - h * (h + 1) / 2;
+}
+
+// Sorted multiset of k <= 4 types at co-lexicographic rank r.
+void unrank_multiset(int64_t r, int k, int32_t *out) {
+    for (int pos = k - 1; pos >= 0; --pos) {
+        int64_t c = pos;
+        while (tg::binom_host(c + 1, pos + 1) <= r) ++c;
+        r -= tg::binom_host(c, pos + 1);
+        out[pos] = (int32_t)(c - pos);
+    }
+}
+}  // namespace
+
+tg_status tg_pa_key_describe(int32_t L, int32_t c, int32_t *block, int32_t *t, int32_t *t2) {
+    if (L < 1 || L > TG_MAX_L) return TG_E_L_RANGE;
+    if (!block || !t || !t2 || c < 0 || c >= tg_pa_row_width(L)) return TG_E_INVALID_ARG;
+    const tg::PaLayout pl = tg::pa_layout(L);
+    int b = 0;
+    while (c >= pl.start[b + 1]) ++b;
+    const int q = c - pl.start[b];
+    *block = b;
+    const int w = pl.start[b + 1] - pl.start[b];
+    if (b <= tg::PB_PATH_J) {
+        *t = q;
+        *t2 = -1;
+    } else if (w == L * L) {
+        *t = q / L;
+        *t2 = q % L;
+    } else {
+        int p = q, a = 0;
+        while (p >= L - a) { p -= L - a; ++a; }
+        *t = a;
+        *t2 = a + p;
+    }
+    return TG_OK;
+}
+
+tg_status tg_pa_global_key_describe(int32_t L, int64_t idx, int32_t *graphlet,
+                                    int32_t types_by_position[4], int32_t *k) {
+    if (L < 1 || L > TG_MAX_L) return TG_E_L_RANGE;
+    if (!graphlet || !types_by_position || !k || idx < 0 || idx >= tg_pa_global_width(L))
+        return TG_E_INVALID_ARG;
+    const tg::PaLayout pl = tg::pa_layout(L);
+    int h = 0;
+    while (idx >= pl.gstart[h + 1]) ++h;
+    const int64_t r = idx - pl.gstart[h];
+    const int64_t P = L * (L + 1) / 2, c3 = tg::binom_host(L + 2, 3);
+    int32_t *o = types_by_position;
+    for (int q = 0; q < 4; ++q) o[q] = -1;
+    int64_t lo, hi, lo2, hi2;
+    switch (h) {
+        case 0: unrank_pair(r, &lo, &hi); o[0] = (int32_t)lo; o[1] = (int32_t)hi; *k = 2; break;
+        case 1:
+            o[0] = (int32_t)(r / P);
+            unrank_pair(r % P, &lo, &hi);
+            o[1] = (int32_t)lo; o[2] = (int32_t)hi; *k = 3;
+            break;
+        case 2: unrank_multiset(r, 3, o); *k = 3; break;
+        case 3:
+            unrank_pair(r, &lo, &hi);   // halves A = lo, B = hi
+            o[0] = (int32_t)(lo / L); o[1] = (int32_t)(lo % L);
+            o[3] = (int32_t)(hi / L); o[2] = (int32_t)(hi % L); *k = 4;
+            break;
+        case 4: o[0] = (int32_t)(r / c3); unrank_multiset(r % c3, 3, o + 1); *k = 4; break;
+        case 5: {
+            int64_t p1, p2;
+            unrank_pair(r, &p1, &p2);
+            unrank_pair(p1, &lo, &hi);
+            unrank_pair(p2, &lo2, &hi2);
+            o[0] = (int32_t)lo; o[2] = (int32_t)hi; o[1] = (int32_t)lo2; o[3] = (int32_t)hi2;
+            *k = 4;
+            break;
+        }
+        case 6: {
+            const int64_t zq = r / P;
+            unrank_pair(r % P, &lo, &hi);
+            o[0] = (int32_t)lo; o[1] = (int32_t)hi;
+            o[2] = (int32_t)(zq % L); o[3] = (int32_t)(zq / L); *k = 4;
+            break;
+        }
+        case 7:
+            unrank_pair(r / P, &lo, &hi);
+            unrank_pair(r % P, &lo2, &hi2);
+            o[0] = (int32_t)lo; o[2] = (int32_t)hi; o[1] = (int32_t)lo2; o[3] = (int32_t)hi2;
+            *k = 4;
+            break;
+        default: unrank_multiset(r, 4, o); *k = 4; break;
+    }
+    *graphlet = h;
+    return TG_OK;
 }
 
 size_t tg_batch_workspace_bytes(int64_t n, int64_t nnz, int64_t G, int32_t L_max) {

@@ -64,6 +64,7 @@ struct Layout {
     size_t off_hstart, off_HB, off_hpre, off_TM, off_eslot, off_nlow, off_xyk;
     size_t off_node_graph, off_ngraph, off_gedge;   // batched graphs only
     size_t off_SB, off_SP;                          // super-hub bitmaps
+    size_t off_pacc;                                // position-aware global accumulators
     int sh_max;
     int64_t G;
     size_t total;
@@ -186,6 +187,24 @@ struct EdgeArgs {
     const int64_t *goff;         // [G+1]
     int64_t G;
 };
+
+// Position-aware rows (tg_position.hip): blocks in row order; a block is L
+// wide (3-node), L^2 (ordered role pairs) or L(L+1)/2 (unordered pairs).
+enum PaBlock {
+    PB_TRI, PB_PATH_I, PB_PATH_J, PB_G3I, PB_G3J, PB_G4, PB_G5I, PB_G5J, PB_G6, PB_G7I, PB_G7J,
+    PB_G8, PB_G9I, PB_G9J, PB_G10I, PB_G10J, PB_G11, PB_G12, PB_NUM
+};
+
+struct PaLayout {
+    int start[PB_NUM + 1];   // first column of each block; start[PB_NUM] = row width
+    int64_t gstart[10];      // first global class of graphlets h0..h8; gstart[9] = width
+};
+
+PaLayout pa_layout(int L);
+hipError_t launch_derive_pa(const EdgeArgs &args, const PaLayout &pl, unsigned grid,
+                            hipStream_t st);
+hipError_t launch_pa_finalize(const uint64_t *acc, const PaLayout &pl, uint64_t *out,
+                              uint32_t *status, hipStream_t st);
 
 // Launch wrappers (tg_kernels.hip).
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t st);

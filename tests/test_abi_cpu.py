@@ -156,3 +156,43 @@ def test_noalloc_rejects_oversized_graph():
                                                 None) == 1  # odd nnz
     assert lib.tg_count_typed_graphlets_noalloc(dummy, dummy, dummy, 10, 2, 0, None, None,
                                                 None) == 4  # L out of range
+
+
+@pytest.mark.parametrize("nt", [1, 2, 3, 5])
+def test_pa_layout_matches_oracle(oracle_mod, nt):
+    """The library's position-aware row and global layouts (closed-form
+    ranks) agree with the oracle's (tables built by enumeration): column by
+    column, and class by class up to type-preserving isomorphism."""
+    L = _lib()
+    assert L.pa_row_width(nt) == oracle_mod.pa_row_width(nt) == 3 * nt + 9 * nt * nt + 6 * (
+        nt * (nt + 1) // 2)
+    W = L.pa_global_width(nt)
+    assert W == oracle_mod.pa_global_width(nt)
+    for c, name in enumerate(oracle_mod.pa_column_names(nt)):
+        b, t, u = L.pa_key_describe(nt, c)
+        if u < 0:
+            mine = f"{b}[{t}]"
+        elif b in BF.PA_PAIR:
+            mine = f"{b}{{{t},{u}}}"
+        else:
+            mine = f"{b}[{t},{u}]"
+        assert mine == name
+    for idx in range(W):
+        h, lab = L.pa_global_key_describe(nt, idx)
+        h2, lab2 = oracle_mod.pa_global_describe(nt, idx)
+        assert h == h2
+        assert BF.pa_class_key(h, lab, nt) == BF.pa_class_key(h2, lab2, nt), (idx, lab, lab2)
+
+
+def test_pa_widths_all_L():
+    import math
+
+    L = _lib()
+    for nt in range(1, 17):
+        P = nt * (nt + 1) // 2
+        classes = [P, nt * P, math.comb(nt + 2, 3), (nt ** 4 + nt ** 2) // 2,
+                   nt * math.comb(nt + 2, 3), (nt ** 4 + 2 * nt ** 3 + 3 * nt ** 2 + 2 * nt) // 8,
+                   nt * nt * P, P * P, math.comb(nt + 3, 4)]
+        assert L.pa_global_width(nt) == sum(classes)
+        assert L.pa_row_width(nt) == 3 * nt + 9 * nt * nt + 6 * P
+    assert L.pa_row_width(0) == 0 and L.pa_global_width(17) == 0
