@@ -18,9 +18,10 @@
  *   current HIP device.  The caller allocates and owns all of them; the
  *   library allocates no device memory and frees nothing.
  * Stream: every kernel runs on the given hipStream_t (passed as void*, NULL
- *   means the null stream).  The call synchronises that stream twice during
- *   the input checks and once at the end, to read back the device-side
- *   consistency checks, so the counts are complete when it returns.
+ *   means the null stream).  The call synchronises that stream once during
+ *   the input checks (twice for a batch) and once at the end, to read back
+ *   the device-side checks, so the counts are complete when it returns
+ *   (tg_count_batch_async: never).
  * Errors: every call returns tg_status.  Input checks run before any output
  *   is written; on an input error the outputs are left untouched.  Device
  *   faults reported by HIP map to TG_E_DEVICE; a failed internal check
@@ -163,6 +164,36 @@ tg_status tg_count_batch(const int64_t *row_ptr, const int32_t *col, const uint8
                          const int64_t *graph_global_off, int64_t globals_len,
                          uint64_t *per_edge, uint64_t *graph_globals, void *workspace,
                          size_t ws_bytes, void *stream);
+
+/* tg_count_batch without any host synchronisation, so that a caller can
+ * record it into a HIP graph (stream capture) and replay it: a batch of many
+ * small graphs as one graph launch (the task-parallel scheme of Sec. 4.7
+ * scheduled by the device's own work queues).  Arguments as for
+ * tg_count_batch, plus:
+ *   max_graph_nodes   1 <= max_graph_nodes <= n: an upper bound on every
+ *                     graph's node count, given by the caller (it sizes the
+ *                     kernels' word widths and sort keys without a read-back);
+ *                     a graph above it gives TG_E_BATCH.
+ *   status_out        device int32: receives the call's tg_status on the
+ *                     stream, after the counts.  The outputs are valid only
+ *                     if it reads TG_OK once the stream has reached that
+ *                     point.
+ * The function returns TG_OK once every kernel is enqueued (host-side
+ * argument errors are returned directly, before any device work); device-side
+ * input errors (not simple, type range, batch descriptor) go to *status_out
+ * only, and every kernel after a failed check does nothing.  It records no
+ * memory-set operation, no allocation and no host copy, and it enqueues the
+ * same kernels with the same arguments for the same inputs, so a recorded
+ * graph can be replayed as long as the inputs, outputs and workspace stay at
+ * the same addresses.  Work statistics (tg_last_stats) and phase timing are
+ * not collected. */
+tg_status tg_count_batch_async(const int64_t *row_ptr, const int32_t *col, const uint8_t *types,
+                               int64_t n, int64_t nnz, const int64_t *graph_node_ptr,
+                               const int32_t *graph_L, int64_t G, int32_t L_max,
+                               int64_t max_graph_nodes, const int64_t *graph_global_off,
+                               int64_t globals_len, uint64_t *per_edge, uint64_t *graph_globals,
+                               void *workspace, size_t ws_bytes, int32_t *status_out,
+                               void *stream);
 
 /* Sparse per-edge output (Sec. 4.6: an edge keeps only its nonzero typed
  * graphlet counts, with a lookup table from key to description, here

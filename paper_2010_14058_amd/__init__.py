@@ -156,6 +156,9 @@ class BatchPlan:
         self.L_max = int(L_max if L_max is not None else gl_host.max())
         self.n = self.row_ptr.numel() - 1
         self.nnz = self.col.numel()
+        np_host = np.asarray(node_ptr.cpu() if hasattr(node_ptr, "cpu") else node_ptr,
+                             dtype=np.int64)
+        self.max_graph_nodes = int(np.max(np.diff(np_host))) if self.G else 0
 
 
 def count_batch(plan: BatchPlan, *, per_edge: bool = False, out_globals=None, out_rows=None,
@@ -189,6 +192,26 @@ def count_batch(plan: BatchPlan, *, per_edge: bool = False, out_globals=None, ou
                          rows.data_ptr() if rows is not None and rows.numel() else 0,
                          glob.data_ptr(), ws.data_ptr(), ws.numel(), stream.cuda_stream)
     return glob, rows
+
+
+def count_batch_async(plan: BatchPlan, out_globals, status, workspace, stream, *,
+                      out_rows=None, max_graph_nodes: int | None = None) -> None:
+    """Enqueue the batch on `stream` with no host synchronisation (so it can
+    be recorded into a HIP graph): out_globals (int64 [plan.goff_host[-1]])
+    receives the per-graph global vectors and status (device int32 [1]) the
+    call's status code, both valid once the stream reaches them.  The
+    workspace must already hold at least tg_batch_workspace_bytes (the
+    call allocates nothing)."""
+    wsb = batch_workspace_bytes(plan.n, plan.nnz, plan.G, plan.L_max)
+    ws = workspace.get(wsb)
+    _lib.count_batch_async_raw(plan.row_ptr.data_ptr(), plan.col.data_ptr() if plan.nnz else 0,
+                               plan.types.data_ptr(), plan.n, plan.nnz, plan.node_ptr.data_ptr(),
+                               plan.graph_L.data_ptr(), plan.G, plan.L_max,
+                               max_graph_nodes or plan.max_graph_nodes, plan.goff.data_ptr(),
+                               int(plan.goff_host[-1]),
+                               out_rows.data_ptr() if out_rows is not None else 0,
+                               out_globals.data_ptr(), ws.data_ptr(), ws.numel(),
+                               status.data_ptr(), stream.cuda_stream)
 
 
 def sparse_rows(rows, L: int, *, workspace: Workspace | None = None, stream=None):

@@ -32,6 +32,11 @@ SIGNATURES = {
                                   _c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int32, _c.c_void_p,
                                   _c.c_int64, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_size_t,
                                   _c.c_void_p]),
+    "tg_count_batch_async": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int64,
+                                        _c.c_int64, _c.c_void_p, _c.c_void_p, _c.c_int64,
+                                        _c.c_int32, _c.c_int64, _c.c_void_p, _c.c_int64,
+                                        _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_size_t,
+                                        _c.c_void_p, _c.c_void_p]),
     "tg_key_describe": (_c.c_int, [_c.c_int32, _c.c_int32, _c.POINTER(_c.c_int32),
                                    _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
     "tg_global_key_describe": (_c.c_int, [_c.c_int32, _c.c_int32, _c.POINTER(_c.c_int32),
@@ -196,6 +201,17 @@ def count_batch_raw(row_ptr: int, col: int, types: int, n: int, nnz: int, node_p
                                globals_len, per_edge, globals_ptr, ws, ws_bytes, stream)
     if rc:
         raise TGError(rc, "tg_count_batch")
+
+
+def count_batch_async_raw(row_ptr: int, col: int, types: int, n: int, nnz: int, node_ptr: int,
+                          graph_L: int, G: int, L_max: int, max_graph_nodes: int, goff: int,
+                          globals_len: int, per_edge: int, globals_ptr: int, ws: int,
+                          ws_bytes: int, status_out: int, stream: int) -> None:
+    rc = load().tg_count_batch_async(row_ptr, col, types, n, nnz, node_ptr, graph_L, G, L_max,
+                                     max_graph_nodes, goff, globals_len, per_edge, globals_ptr, ws,
+                                     ws_bytes, status_out, stream)
+    if rc:
+        raise TGError(rc, "tg_count_batch_async")
 
 
 def sparse_workspace_bytes(m: int) -> int:

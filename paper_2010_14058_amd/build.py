@@ -9,7 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libtg.so")
-SOURCES = ["tg_api.hip", "tg_kernels.hip", "tg_edges.hip", "tg_sparse.hip", "tg_position.hip"]
+SOURCES = ["tg_api.hip", "tg_kernels.hip", "tg_edges.hip", "tg_sparse.hip", "tg_position.hip",
+           "tg_sort.hip"]
 
 HIPCC_FLAGS = [
     "-O3",

@@ -2,9 +2,6 @@
 // checks, the launch sequence and the C ABI declared in include/tg.h.
 #include <hip/hip_runtime.h>
 
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_scan.hpp>
-
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -46,24 +43,9 @@ thread_local int64_t g_tune[TG_TUNE_SH_DEG + 1] = {
     TASK_WEDGES, SEQ_CLEAR_BYTES, MAX_CYCLE_SLOTS, (int64_t)MAP_BUDGET, MAX_HEAVY_SLOTS,
     (int64_t)TBUF_BUDGET, TASK_RANGE_BYTES, 0, LIGHT_MAXW, TCAP, SH_MAX, SH_DMIN};
 
+// Temporary storage of the preparation's sorts and prefix sums.
 static size_t sort_tmp_bytes(int64_t n, int64_t nnz) {
-    size_t a = 0, b = 0, c = 0;
-    uint64_t *k = nullptr;
-    uint32_t *v = nullptr;
-    int64_t *s = nullptr;
-    if (rocprim::radix_sort_keys(nullptr, a, k, k, (size_t)(n > 0 ? n : 1), 0, 64) != hipSuccess ||
-        rocprim::radix_sort_pairs(nullptr, b, k, k, v, v, (size_t)(nnz > 0 ? nnz : 1), 0, 64) !=
-            hipSuccess ||
-        rocprim::exclusive_scan(nullptr, c, s, s, int64_t(0), (size_t)(n + 1),
-                                rocprim::plus<int64_t>()) != hipSuccess) {
-        // no device to ask (e.g. a build host): a bound well above what the
-        // radix sorts and scans request; the run re-checks the real need
-        return (size_t)(64 << 20) + (size_t)(n + nnz + 2) * 16;
-    }
-    size_t mx = a;
-    if (b > mx) mx = b;
-    if (c > mx) mx = c;
-    return mx + 256;
+    return sort_tmp_need((n > nnz ? n : nnz) + 1);
 }
 
 Budget budget_from_tuning() {
@@ -122,8 +104,8 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G, con
     int64_t nk = nnz > n ? nnz : n;
     y.off_key_a = take(sizeof(uint64_t) * (nk + 1));
     y.off_key_b = take(sizeof(uint64_t) * (nk + 1));
-    y.off_val_a = take(sizeof(uint32_t) * (nnz + 1));
-    y.off_val_b = take(sizeof(uint32_t) * (nnz + 1));
+    y.off_val_a = take(sizeof(uint32_t) * (nk + 1));
+    y.off_val_b = take(sizeof(uint32_t) * (nk + 1));
     y.off_ncol = take(sizeof(int32_t) * (nnz + 1));
     y.off_ctype = take((size_t)nnz + 1);
     y.off_neid = take(sizeof(uint32_t) * (nnz + 1));
@@ -208,7 +190,8 @@ void timing_mark(const char *name) {
 static tg_status status_from_bits(uint32_t bits) {
     if (bits & (ST_BATCH | ST_CROSS_GRAPH)) return TG_E_BATCH;
     if (bits & ST_TYPE_RANGE) return TG_E_TYPE_RANGE;
-    if (bits & (ST_COL_RANGE | ST_UNSORTED | ST_SELF_LOOP | ST_ASYMMETRIC)) return TG_E_NOT_SIMPLE;
+    if (bits & (ST_COL_RANGE | ST_UNSORTED | ST_SELF_LOOP | ST_ASYMMETRIC | ST_EDGE_COUNT))
+        return TG_E_NOT_SIMPLE;
     if (bits) return TG_E_INTERNAL;
     return TG_OK;
 }
@@ -229,10 +212,16 @@ static T *at(void *base, size_t off) {
 
 // One counting call.  pa: per_edge and global_counts receive the
 // position-aware layout (needs the separate derivation pass, y.defer).
+// status_out (batches only): the call does not synchronise with the host at
+// all; it needs the batch's declared largest graph (batch->max_nodes, checked
+// on the device) and writes its tg_status to status_out on the device.
 static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *types, int64_t n,
                      int64_t nnz, int L, uint64_t *per_edge, uint64_t *global_counts, void *ws,
-                     const Layout &y, hipStream_t st, const BatchIn *batch, bool pa = false) {
+                     const Layout &y, hipStream_t st, const BatchIn *batch, bool pa = false,
+                     int32_t *status_out = nullptr) {
     if (pa && (batch || !y.defer)) return TG_E_INTERNAL;
+    const bool async = status_out != nullptr;
+    if (async && (!batch || batch->max_nodes < 1)) return TG_E_INTERNAL;
     const int64_t m = y.m;
     const int LL = L * L;
     const int gw = tg_global_width(L);
@@ -270,8 +259,8 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     uint32_t *tbuf = at<uint32_t>(ws, y.off_tbuf);
     uint64_t *gacc = at<uint64_t>(ws, y.off_gacc);
     void *stmp = at<void>(ws, y.off_sort_tmp);
-    size_t stmp_bytes = y.sort_tmp_bytes;
-    if (sort_tmp_bytes(n, nnz) > stmp_bytes) return TG_E_INTERNAL;
+    int64_t *stmp64 = static_cast<int64_t *>(stmp);
+    if (sort_tmp_bytes(n, nnz) > y.sort_tmp_bytes) return TG_E_INTERNAL;
 
     int32_t *node_graph = batch ? at<int32_t>(ws, y.off_node_graph) : nullptr;
     int32_t *ngraph = batch ? at<int32_t>(ws, y.off_ngraph) : nullptr;
@@ -285,65 +274,70 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     if (batch) HIPCHK(launch_fill_u64(global_counts, 0, batch->globals_len, st));
     else HIPCHK(launch_fill_u64(gacc, 0, gw, st));
 
-    // ---- input checks: batch descriptor, rows, degrees, edge numbering
+    // ---- input checks: batch descriptor, rows, degrees, edge numbering.
+    // Every kernel after a check returns at once once an input check has
+    // failed, so the host needs to look at the status only where it sizes
+    // later launches (hub core, super-hubs, largest degree).
     uint64_t max_gsize = 0;
-    int deg_bits = 0;
-    bool graph_major = false;
     if (batch) {
         HIPCHK(launch_batch_graphs(batch->node_ptr, batch->gL, batch->goff, batch->G, n, L,
-                                   batch->globals_len, node_graph, status, counters + C_MAX_GSIZE,
-                                   st));
-        uint32_t bst = 0;
-        HIPCHK(hipMemcpyAsync(&bst, status, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(&max_gsize, counters + C_MAX_GSIZE, sizeof(uint64_t),
-                              hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (bst) return status_from_bits(bst);
-        // graph-major order when (graph, degree) fit the key's upper 32 bits;
-        // degrees are below the largest graph's size
-        deg_bits = bits_for((int64_t)max_gsize + 1);
-        graph_major = bits_for(batch->G + 1) + deg_bits <= 32;
+                                   batch->globals_len, batch->max_nodes, node_graph, status,
+                                   counters + C_MAX_GSIZE, st));
+        if (async) {
+            max_gsize = (uint64_t)batch->max_nodes;
+        } else {
+            uint32_t bst = 0;
+            HIPCHK(hipMemcpyAsync(&bst, status, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(&max_gsize, counters + C_MAX_GSIZE, sizeof(uint64_t),
+                                  hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (bst) return status_from_bits(bst);
+        }
     }
     HIPCHK(launch_check_rows(row_ptr, col, types, n, nnz, L, deg, ucount, status, node_graph,
                              batch ? batch->gL : nullptr, st));
-    HIPCHK(rocprim::exclusive_scan(stmp, stmp_bytes, ucount, eoff, int64_t(0), (size_t)(n + 1),
-                                   rocprim::plus<int64_t>(), st));
-    struct {
-        uint32_t status;
-        uint32_t pad;
-        int64_t upper;
-    } probe;
-    HIPCHK(hipMemcpyAsync(&probe.status, status, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(&probe.upper, eoff + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (probe.status) return status_from_bits(probe.status);
-    if (probe.upper != m) return TG_E_NOT_SIMPLE;
-    if (batch) HIPCHK(launch_batch_edges(batch->node_ptr, eoff, batch->G, gedge, st));
+    HIPCHK(launch_excl_scan(ucount, eoff, n + 1, stmp64, status, st));
+    HIPCHK(launch_check_edge_count(eoff, n, m, status, st));
+    if (batch) HIPCHK(launch_batch_edges(batch->node_ptr, eoff, batch->G, gedge, status, st));
 
-    // ---- relabel by (degree, id), or (graph, degree, id) for a batch:
-    //      rank order = internal id order
-    HIPCHK(launch_node_keys(deg, n, graph_major ? node_graph : nullptr, deg_bits, key_a, st));
-    HIPCHK(rocprim::radix_sort_keys(stmp, stmp_bytes, key_a, key_b, (size_t)n, 0, 64, st));
-    HIPCHK(launch_relabel(key_b, types, deg, n, order, newid, ntype, ndeg, counters + C_HUB_CAND,
-                          (uint32_t)g_tune[TG_TUNE_SH_DEG], node_graph, ngraph, st));
-    HIPCHK(rocprim::exclusive_scan(stmp, stmp_bytes, ndeg, nrp, int64_t(0), (size_t)(n + 1),
-                                   rocprim::plus<int64_t>(), st));
+    // ---- relabel by (degree, id), or (graph, degree, id) for a batch
+    //      (each graph's nodes contiguous): rank order = internal id order.
+    //      Degrees are below the node count (of the largest graph).
+    const int deg_bits = bits_for(batch ? (int64_t)max_gsize : n);
+    const int key_bits = deg_bits + (batch ? bits_for(batch->G) : 0);
+    HIPCHK(launch_node_keys(deg, n, node_graph, deg_bits, key_a, val_a, status, st));
+    uint64_t *sk = nullptr;
+    uint32_t *sv = nullptr;
+    HIPCHK(radix_sort(key_a, key_b, val_a, val_b, n, key_bits, stmp, status, st, &sk, &sv));
+    HIPCHK(launch_relabel(sv, types, deg, n, order, newid, ntype, ndeg, counters + C_HUB_CAND,
+                          (uint32_t)g_tune[TG_TUNE_SH_DEG], node_graph, ngraph, status, st));
+    HIPCHK(launch_excl_scan(ndeg, nrp, n + 1, stmp64, status, st));
     const int bits = bits_for(n);
     HIPCHK(launch_slot_keys(row_ptr, col, ucount, eoff, newid, n, bits, key_a, val_a, ei, ej, status,
                             st));
-    HIPCHK(hipMemcpyAsync(&probe.status, status, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    // hub core and super-hubs: single graphs only (in a batch the top ids are
+    // not the top degrees); the largest degree sizes the word widths
     uint64_t cand[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(cand, counters + C_HUB_CAND, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost,
-                          st));
-    int64_t max_deg = 0;  // in degree order the top-ranked node has the largest degree
-    if (n > 0 && !graph_major)
-        HIPCHK(hipMemcpyAsync(&max_deg, ndeg + (n - 1), sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (probe.status) return status_from_bits(probe.status);
-    if (graph_major) max_deg = max_gsize > 0 ? (int64_t)max_gsize - 1 : 0;  // a bound
+    int64_t max_deg = 0;
+    if (batch) {
+        max_deg = max_gsize > 0 ? (int64_t)max_gsize - 1 : 0;  // a bound
+    }
+    if (!async) {
+        uint32_t bits_now = 0;
+        HIPCHK(hipMemcpyAsync(&bits_now, status, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        if (!batch) {
+            HIPCHK(hipMemcpyAsync(cand, counters + C_HUB_CAND, 2 * sizeof(uint64_t),
+                                  hipMemcpyDeviceToHost, st));
+            // in degree order the top-ranked node has the largest degree
+            if (n > 0)
+                HIPCHK(hipMemcpyAsync(&max_deg, ndeg + (n - 1), sizeof(int64_t),
+                                      hipMemcpyDeviceToHost, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        if (bits_now) return status_from_bits(bits_now);
+    }
     // hub core: the highest-ranked nodes of degree >= HUB_DMIN, at most HUB_MAX
-    // (none in graph-major order, where the top ids are not the top degrees)
-    const uint64_t hub_cand = graph_major ? 0 : cand[0], sh_cand = graph_major ? 0 : cand[1];
+    const uint64_t hub_cand = batch ? 0 : cand[0], sh_cand = batch ? 0 : cand[1];
     const int H = (int)(hub_cand < (uint64_t)HUB_MAX ? hub_cand : (uint64_t)HUB_MAX);
     // super-hubs: the highest-ranked nodes of degree >= the super-hub degree
     // (tuning knob) that fit; nodes of that degree beyond them are probed by
@@ -356,29 +350,28 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     // bit rows padded to whole 64-byte blocks (8 words) for vector loads
     const int Hw = H > 0 ? (((H + 63) / 64 + 7) / 8) * 8 : 0;
     const int32_t hub_base = (int32_t)(n - H);
-    HIPCHK(rocprim::radix_sort_pairs(stmp, stmp_bytes, key_a, key_b, val_a, val_b, (size_t)nnz, 0,
-                                     2 * bits, st));
+    HIPCHK(radix_sort(key_a, key_b, val_a, val_b, nnz, 2 * bits, stmp, status, st, &sk, &sv));
     uint32_t *eslot = at<uint32_t>(ws, y.off_eslot);
     uint32_t *nlow = at<uint32_t>(ws, y.off_nlow);
     uint8_t *ctype = at<uint8_t>(ws, y.off_ctype);
-    HIPCHK(launch_finish_csr(key_b, val_b, nnz, bits, ntype, eslot, ncol, neid, ctype, st));
+    HIPCHK(launch_finish_csr(sk, sv, nnz, bits, ntype, eslot, ncol, neid, ctype, status, st));
     int64_t *hstart = at<int64_t>(ws, y.off_hstart);
     uint64_t *HB = at<uint64_t>(ws, y.off_HB);
     uint32_t *hpre = at<uint32_t>(ws, y.off_hpre);
     uint64_t *TM = at<uint64_t>(ws, y.off_TM);
-    HIPCHK(launch_tdeg(nrp, ncol, ctype, n, L, hub_base, tdeg, hstart, nlow, st));
+    HIPCHK(launch_tdeg(nrp, ncol, ctype, n, L, hub_base, tdeg, hstart, nlow, status, st));
     HIPCHK(launch_hub_build(nrp, ncol, hstart, ntype, n, H, Hw, L, HB, hpre, TM, st));
     HIPCHK(launch_superhubs(nrp, ncol, n, S, nw, SB, SP, st));
     timing_mark("prep");
 
     // ---- typed triangles and node aggregates
     HIPCHK(launch_tri(nrp, ncol, ctype, ei, ej, eslot, tri_slot, m, L, tri, counters + C_TRI_SUM,
-                      sh_base, nw, SB, hub_base, Hw, HB, st));
+                      sh_base, nw, SB, hub_base, Hw, HB, status, st));
     timing_mark("tri");
     // every degree below 2^16: node aggregates, per-edge 4-cycle counts and
     // derivation inputs stay below 2^32 and are held as 32-bit words
     const bool words32 = max_deg < 65536;
-    HIPCHK(launch_node_aggr(nrp, ncol, ctype, tri_slot, tdeg, n, L, A, D, words32, st));
+    HIPCHK(launch_node_aggr(nrp, ncol, ctype, tri_slot, tdeg, n, L, A, D, words32, status, st));
     timing_mark("aggr");
 
     // ---- 4-cycles from degree-ordered wedges
@@ -386,7 +379,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     HIPCHK(launch_cyc_work(nrp, ncol, neid, eslot, nlow, n, la_l, la_h, lb_l, lb_h, counters,
                            (uint64_t)g_tune[TG_TUNE_TASK_WEDGES], L,
                            (uint64_t)g_tune[TG_TUNE_RANGE_BYTES],
-                           (uint64_t)g_tune[TG_TUNE_LIGHT_WEDGES], st));
+                           (uint64_t)g_tune[TG_TUNE_LIGHT_WEDGES], status, st));
     timing_mark("cyc_work");
     CycleArgs ca;
     ca.tasks = nullptr;
@@ -402,7 +395,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
         while ((int64_t(1) << lg) <= g_tune[TG_TUNE_LIGHT_WEDGES]) ++lg;
         ca.light_log2 = lg;
     }
-    ca.deg_sorted = graph_major ? 0 : 1;
+    ca.deg_sorted = batch ? 0 : 1;
     ca.max_deg = max_deg;
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
@@ -511,7 +504,12 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
         HIPCHK(launch_global_finalize(gacc, L, gw, global_counts, status, st));
     if (!pa) timing_mark("global");
 
-    HIPCHK(hipMemcpyAsync(&probe.status, status, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    if (async) {
+        HIPCHK(launch_status_code(status, status_out, st));
+        return TG_OK;
+    }
+    uint32_t end_bits = 0;
+    HIPCHK(hipMemcpyAsync(&end_bits, status, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     uint64_t cnt_host[C_NUM];
     HIPCHK(hipMemcpyAsync(cnt_host, counters, sizeof(cnt_host), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -526,8 +524,8 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     g_timing.stats[8] = (int64_t)sh_cand;
     g_timing.stats[9] = (int64_t)S;
     g_timing.stats[10] = (int64_t)H;
-    if (probe.status) return status_from_bits(probe.status) == TG_OK ? TG_E_INTERNAL
-                                                                    : status_from_bits(probe.status);
+    if (end_bits) return status_from_bits(end_bits) == TG_OK ? TG_E_INTERNAL
+                                                              : status_from_bits(end_bits);
     return TG_OK;
 }
 
@@ -843,9 +841,35 @@ tg_status tg_count_batch(const int64_t *row_ptr, const int32_t *col, const uint8
         !workspace || !tg::ws_aligned(workspace) || (nnz > 0 && !col) || n < 1 || globals_len < 1)
         return TG_E_INVALID_ARG;
     if (ws_bytes < y.total) return TG_E_WORKSPACE;
-    tg::BatchIn b{graph_node_ptr, graph_L, graph_global_off, G, globals_len};
+    tg::BatchIn b{graph_node_ptr, graph_L, graph_global_off, G, globals_len, -1};
     return tg::run(row_ptr, col, types, n, nnz, L_max, per_edge, graph_globals, workspace, y,
                    reinterpret_cast<hipStream_t>(stream), &b);
+}
+
+tg_status tg_count_batch_async(const int64_t *row_ptr, const int32_t *col, const uint8_t *types,
+                               int64_t n, int64_t nnz, const int64_t *graph_node_ptr,
+                               const int32_t *graph_L, int64_t G, int32_t L_max,
+                               int64_t max_graph_nodes, const int64_t *graph_global_off,
+                               int64_t globals_len, uint64_t *per_edge, uint64_t *graph_globals,
+                               void *workspace, size_t ws_bytes, int32_t *status_out,
+                               void *stream) {
+    if (G < 1 || max_graph_nodes < 1 || max_graph_nodes > n) return TG_E_INVALID_ARG;
+    tg::Layout y;
+    tg_status s = tg::plan_layout(n, nnz, L_max, &y, G);
+    if (s != TG_OK) return s;
+    if (!row_ptr || !types || !graph_node_ptr || !graph_L || !graph_global_off || !graph_globals ||
+        !workspace || !tg::ws_aligned(workspace) || (nnz > 0 && !col) || n < 1 || globals_len < 1 ||
+        !status_out)
+        return TG_E_INVALID_ARG;
+    if (ws_bytes < y.total) return TG_E_WORKSPACE;
+    tg::BatchIn b{graph_node_ptr, graph_L, graph_global_off, G, globals_len, max_graph_nodes};
+    // no phase events: the call may be recorded into a graph
+    const bool timing = tg::g_timing.enabled;
+    tg::g_timing.enabled = false;
+    s = tg::run(row_ptr, col, types, n, nnz, L_max, per_edge, graph_globals, workspace, y,
+                reinterpret_cast<hipStream_t>(stream), &b, false, status_out);
+    tg::g_timing.enabled = timing;
+    return s;
 }
 
 tg_status tg_key_describe(int32_t L, int32_t c, int32_t *orbit, int32_t *t, int32_t *t2) {

@@ -85,6 +85,12 @@ static __device__ __forceinline__ uint32_t load_agent(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// True once an input check has failed (the status word written by earlier
+// kernels of the call): later kernels return at once.
+static __device__ __forceinline__ bool input_failed(const uint32_t *status) {
+    return (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_INPUT) != 0;
+}
+
 // C(n, r) for r <= 4 (co-lexicographic ranks of type multisets).
 static __device__ __forceinline__ int64_t binom_small(int64_t n, int r) {
     if (n < r) return 0;

@@ -840,6 +840,7 @@ __device__ __forceinline__ void edges_light_body(const EdgeArgs &a) {
     uint32_t *Th = Tl + (a.tcap - 1);
     EdgeShared S = carve(a, sm_edge, meta, wave_cnt, &hist, Th, -1, Tl);
     int lane = threadIdx.x;
+    if (input_failed(a.status)) return;
     uint32_t bad = 0;
     for (int q = lane; q < hist_words(a); q += WAVE) hist[q] = 0;
     __syncthreads();
@@ -980,6 +981,7 @@ __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 5 : 1))) k_edges_heavy(EdgeArgs a
     EdgeShared S = carve(a, sm_edgeh, meta, wave_cnt, &hist, Th, 1, Tl);
     S.Gw = Gw;
     int tid = threadIdx.x;
+    if (input_failed(a.status)) return;
     for (int q = tid; q < TMw; q += NT) TMs[q] = a.TM[q];
     uint32_t bad = 0;
     for (int q = tid; q < hist_words(a); q += NT) hist[q] = 0;
@@ -1059,6 +1061,7 @@ __device__ void derive_edges(const EdgeArgs &a, uint64_t *hist, uint64_t *rbuf, 
 template <typename XT, bool NARROW>
 __global__ void __launch_bounds__(256) k_derive(EdgeArgs a) {
     extern __shared__ uint64_t sm_der[];
+    if (input_failed(a.status)) return;
     uint64_t *hist = sm_der;
     for (int q = threadIdx.x; q < hist_words(a); q += blockDim.x) hist[q] = 0;
     __syncthreads();

@@ -21,7 +21,14 @@ enum : uint32_t {
     ST_NOT_DIVISIBLE = 1u << 6,
     ST_BATCH = 1u << 7,       // inconsistent batch descriptor
     ST_CROSS_GRAPH = 1u << 8, // an edge joins two graphs of a batch
+    ST_EDGE_COUNT = 1u << 9,  // entries above the diagonal are not half the adjacency
 };
+
+// Bits that mean the input is unusable: every kernel after the input checks
+// returns at once when one is set (so a call that never reads the status
+// back on the host stays in bounds).
+constexpr uint32_t ST_INPUT = ST_COL_RANGE | ST_UNSORTED | ST_SELF_LOOP | ST_TYPE_RANGE |
+                              ST_ASYMMETRIC | ST_BATCH | ST_CROSS_GRAPH | ST_EDGE_COUNT;
 
 // Tunables of the cycle and clique passes.
 constexpr int64_t LIGHT_MAXW = 512;   // a group is light if it has at most this many wedges
@@ -107,6 +114,7 @@ struct BatchIn {
     const int64_t *goff;       // [G+1]
     int64_t G;
     int64_t globals_len;
+    int64_t max_nodes;         // declared bound on a graph's node count (checked), or -1
 };
 
 // Arguments of the 4-cycle passes.
@@ -206,35 +214,48 @@ hipError_t launch_derive_pa(const EdgeArgs &args, const PaLayout &pl, unsigned g
 hipError_t launch_pa_finalize(const uint64_t *acc, const PaLayout &pl, uint64_t *out,
                               uint32_t *status, hipStream_t st);
 
+// Prefix sums and radix sorts (tg_sort.hip).  `gate` is the status word:
+// they do nothing once an input check has failed.
+int64_t scan_tiles(int64_t count);
+size_t sort_tmp_need(int64_t count);
+hipError_t launch_excl_scan(const int64_t *in, int64_t *out, int64_t count, int64_t *tmp,
+                            const uint32_t *gate, hipStream_t st);
+hipError_t radix_sort(uint64_t *keys, uint64_t *keys_tmp, uint32_t *vals, uint32_t *vals_tmp,
+                      int64_t count, int end_bit, void *tmp, const uint32_t *gate,
+                      hipStream_t st, uint64_t **out_keys, uint32_t **out_vals);
+
 // Launch wrappers (tg_kernels.hip).
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t st);
 hipError_t launch_check_rows(const int64_t *rp, const int32_t *col, const uint8_t *types, int64_t n,
                              int64_t nnz, int L, uint32_t *deg, int64_t *ucount, uint32_t *status,
                              const int32_t *node_graph, const int32_t *gL, hipStream_t st);
+hipError_t launch_check_edge_count(const int64_t *eoff, int64_t n, int64_t m, uint32_t *status,
+                                   hipStream_t st);
+hipError_t launch_status_code(const uint32_t *status, int32_t *out, hipStream_t st);
 hipError_t launch_batch_graphs(const int64_t *node_ptr, const int32_t *gL, const int64_t *goff,
                                int64_t G, int64_t n, int L_max, int64_t globals_len,
-                               int32_t *node_graph, uint32_t *status, uint64_t *max_gsize,
-                               hipStream_t st);
+                               int64_t max_nodes, int32_t *node_graph, uint32_t *status,
+                               uint64_t *max_gsize, hipStream_t st);
 hipError_t launch_batch_edges(const int64_t *node_ptr, const int64_t *eoff, int64_t G,
-                              int64_t *gedge_ptr, hipStream_t st);
+                              int64_t *gedge_ptr, const uint32_t *status, hipStream_t st);
 hipError_t launch_batch_finalize(uint64_t *globals, const int32_t *gL, const int64_t *goff, int64_t G,
                                  uint32_t *status, hipStream_t st);
 hipError_t launch_node_keys(const uint32_t *deg, int64_t n, const int32_t *node_graph, int deg_bits,
-                            uint64_t *keys, hipStream_t st);
-hipError_t launch_relabel(const uint64_t *sorted, const uint8_t *types, const uint32_t *deg, int64_t n,
-                          int32_t *order, int32_t *newid, uint8_t *ntype, int64_t *ndeg,
+                            uint64_t *keys, uint32_t *ids, const uint32_t *status, hipStream_t st);
+hipError_t launch_relabel(const uint32_t *sorted_ids, const uint8_t *types, const uint32_t *deg,
+                          int64_t n, int32_t *order, int32_t *newid, uint8_t *ntype, int64_t *ndeg,
                           uint64_t *hub_cand, uint32_t sh_deg, const int32_t *node_graph,
-                          int32_t *ngraph, hipStream_t st);
+                          int32_t *ngraph, const uint32_t *status, hipStream_t st);
 hipError_t launch_slot_keys(const int64_t *rp, const int32_t *col, const int64_t *ucount,
                             const int64_t *eoff, const int32_t *newid, int64_t n, int bits,
                             uint64_t *keys, uint32_t *vals, int32_t *ei, int32_t *ej,
                             uint32_t *status, hipStream_t st);
 hipError_t launch_finish_csr(const uint64_t *keys, const uint32_t *vals, int64_t nnz, int bits,
                              const uint8_t *ntype, uint32_t *eslot, int32_t *ncol, uint32_t *neid,
-                             uint8_t *ctype, hipStream_t st);
+                             uint8_t *ctype, const uint32_t *status, hipStream_t st);
 hipError_t launch_tdeg(const int64_t *nrp, const int32_t *ncol, const uint8_t *ctype, int64_t n,
                        int L, int32_t hub_base, uint32_t *tdeg, int64_t *hstart, uint32_t *nlow,
-                       hipStream_t st);
+                       const uint32_t *status, hipStream_t st);
 hipError_t launch_hub_build(const int64_t *nrp, const int32_t *ncol, const int64_t *hstart,
                             const uint8_t *ntype, int64_t n, int H, int Hw, int L, uint64_t *HB,
                             uint32_t *pre, uint64_t *TM, hipStream_t st);
@@ -249,18 +270,19 @@ hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *ct
                       const int32_t *ei, const int32_t *ej, const uint32_t *eslot,
                       uint32_t *tri_slot, int64_t m, int L, uint32_t *tri,
                       uint64_t *tri_sum, int32_t sh_base, int64_t nw, const uint64_t *SB,
-                      int32_t hub_base, int Hw, const uint64_t *HB, hipStream_t st);
+                      int32_t hub_base, int Hw, const uint64_t *HB, const uint32_t *status,
+                      hipStream_t st);
 hipError_t launch_superhubs(const int64_t *nrp, const int32_t *ncol, int64_t n, int S, int64_t nw,
                             uint64_t *SB, uint32_t *SP, hipStream_t st);
 hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8_t *ctype,
                             const uint32_t *tri_slot, const uint32_t *tdeg,
                             int64_t n, int L, uint64_t *A, uint64_t *D, bool ad_u32,
-                            hipStream_t st);
+                            const uint32_t *status, hipStream_t st);
 hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32_t *neid,
                            const uint32_t *eslot, const uint32_t *nlow, int64_t n, uint32_t *la_l,
                            uint4 *la_h, uint32_t *lb_l, uint4 *lb_h, uint64_t *counters,
                            uint64_t task_wedges, int L, uint64_t range_bytes,
-                           uint64_t light_max, hipStream_t st);
+                           uint64_t light_max, const uint32_t *status, hipStream_t st);
 int heavy_chunk_for(int L, int threads);
 hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned grid, hipStream_t st);
 hipError_t launch_edges(bool heavy, const EdgeArgs &args, unsigned grid, hipStream_t st);

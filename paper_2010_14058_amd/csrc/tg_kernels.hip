@@ -39,6 +39,7 @@ __global__ void k_check_rows(const int64_t *__restrict__ rp, const int32_t *__re
                              uint32_t *__restrict__ status, const int32_t *__restrict__ node_graph,
                              const int32_t *__restrict__ gL) {
     const int lane = lane_id();
+    if (input_failed(status)) return;  // inconsistent batch descriptor
     if (blockIdx.x == 0 && threadIdx.x == 0) ucount[n] = 0;  // sentinel of the exclusive scan
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
     for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE); u < n;
@@ -78,14 +79,16 @@ __global__ void k_check_rows(const int64_t *__restrict__ rp, const int32_t *__re
 // (one wave per graph, written only for a consistent descriptor).
 __global__ void k_batch_graphs(const int64_t *__restrict__ node_ptr, const int32_t *__restrict__ gL,
                                const int64_t *__restrict__ goff, int64_t G, int64_t n, int L_max,
-                               int64_t globals_len, int32_t *__restrict__ node_graph,
-                               uint32_t *__restrict__ status, uint64_t *__restrict__ max_gsize) {
+                               int64_t globals_len, int64_t max_nodes,
+                               int32_t *__restrict__ node_graph, uint32_t *__restrict__ status,
+                               uint64_t *__restrict__ max_gsize) {
     int64_t g = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
     int lane = lane_id();
     if (g >= G) return;
     int64_t a = node_ptr[g], b = node_ptr[g + 1];
     int Lg = gL[g];
     bool ok = a >= 0 && b >= a && b <= n && Lg >= 1 && Lg <= L_max;
+    if (max_nodes >= 0 && b - a > max_nodes) ok = false;  // above the declared bound
     if (g == 0 && (a != 0 || goff[0] != 0)) ok = false;
     if (g == G - 1 && (b != n || goff[G] != globals_len)) ok = false;
     if (ok) {
@@ -101,7 +104,9 @@ __global__ void k_batch_graphs(const int64_t *__restrict__ node_ptr, const int32
 }
 
 __global__ void k_batch_edges(const int64_t *__restrict__ node_ptr, const int64_t *__restrict__ eoff,
-                              int64_t G, int64_t *__restrict__ gedge_ptr) {
+                              int64_t G, int64_t *__restrict__ gedge_ptr,
+                              const uint32_t *__restrict__ status) {
+    if (input_failed(status)) return;
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g <= G) gedge_ptr[g] = eoff[node_ptr[g]];
 }
@@ -110,6 +115,7 @@ __global__ void k_batch_edges(const int64_t *__restrict__ node_ptr, const int64_
 __global__ void k_batch_finalize(uint64_t *__restrict__ glob, const int32_t *__restrict__ gL,
                                  const int64_t *__restrict__ goff, int64_t G,
                                  uint32_t *__restrict__ status) {
+    if (input_failed(status)) return;
     const uint64_t E[9] = {1, 2, 3, 3, 3, 4, 4, 5, 6};
     for (int64_t g = blockIdx.x; g < G; g += gridDim.x) {
         int Lg = gL[g];
@@ -129,31 +135,35 @@ __global__ void k_batch_finalize(uint64_t *__restrict__ glob, const int32_t *__r
     }
 }
 
-// keys[v] = degree << 32 | v (rank order = sorted order)
-// Sort keys of the relabelling: (degree, id), or for a batch whose sizes fit,
-// (graph, degree, id) so each graph's nodes stay contiguous (graphlets never
-// span graphs, so a per-graph degree order serves the cycle orientation as
-// well) and the id in the low 32 bits.
+// Sort keys of the relabelling: the degree, or for a batch (graph, degree)
+// so each graph's nodes stay contiguous (graphlets never span graphs, so a
+// per-graph degree order serves the cycle orientation as well); the values
+// are the node ids, so a stable sort ranks nodes by (degree, id).
 __global__ void k_node_keys(const uint32_t *__restrict__ deg, int64_t n,
                             const int32_t *__restrict__ node_graph, int deg_bits,
-                            uint64_t *__restrict__ keys) {
+                            uint64_t *__restrict__ keys, uint32_t *__restrict__ ids,
+                            const uint32_t *__restrict__ status) {
+    if (input_failed(status)) return;
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
-    uint64_t k = ((uint64_t)deg[v] << 32) | (uint64_t)v;
-    if (node_graph) k |= (uint64_t)node_graph[v] << (32 + deg_bits);
+    uint64_t k = (uint64_t)deg[v];
+    if (node_graph) k |= (uint64_t)node_graph[v] << deg_bits;
     keys[v] = k;
+    ids[v] = (uint32_t)v;
 }
 
-__global__ void k_relabel(const uint64_t *__restrict__ sorted, const uint8_t *__restrict__ types,
+__global__ void k_relabel(const uint32_t *__restrict__ sorted_ids, const uint8_t *__restrict__ types,
                           const uint32_t *__restrict__ deg, int64_t n,
                           int32_t *__restrict__ order, int32_t *__restrict__ newid,
                           uint8_t *__restrict__ ntype, int64_t *__restrict__ ndeg,
                           uint64_t *__restrict__ hub_cand, uint32_t sh_deg,
-                          const int32_t *__restrict__ node_graph, int32_t *__restrict__ ngraph) {
+                          const int32_t *__restrict__ node_graph, int32_t *__restrict__ ngraph,
+                          const uint32_t *__restrict__ status) {
+    if (input_failed(status)) return;
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool cand = false;
     if (r < n) {
-        int32_t v = (int32_t)(sorted[r] & 0xffffffffu);
+        int32_t v = (int32_t)sorted_ids[r];
         order[r] = v;
         if (node_graph) ngraph[r] = node_graph[v];
         newid[v] = (int32_t)r;
@@ -178,6 +188,7 @@ __global__ void k_slot_keys(const int64_t *__restrict__ rp, const int32_t *__res
                             uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
                             int32_t *__restrict__ ei, int32_t *__restrict__ ej,
                             uint32_t *__restrict__ status) {
+    if (input_failed(status)) return;  // includes an edge count that is not nnz / 2
     const int lane = lane_id();
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
     for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE); u < n;
@@ -217,7 +228,9 @@ __global__ void k_slot_keys(const int64_t *__restrict__ rp, const int32_t *__res
 __global__ void k_finish_csr(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
                              int64_t nnz, int bits, const uint8_t *__restrict__ ntype,
                              uint32_t *__restrict__ eslot, int32_t *__restrict__ ncol,
-                             uint32_t *__restrict__ neid, uint8_t *__restrict__ ctype) {
+                             uint32_t *__restrict__ neid, uint8_t *__restrict__ ctype,
+                             const uint32_t *__restrict__ status) {
+    if (input_failed(status)) return;
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s < nnz) {
         uint64_t k = keys[s];
@@ -236,7 +249,8 @@ __global__ void k_finish_csr(const uint64_t *__restrict__ keys, const uint32_t *
 __global__ void k_tdeg(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
                        const uint8_t *__restrict__ ctype, int64_t n, int L, int32_t hub_base,
                        uint32_t *__restrict__ tdeg, int64_t *__restrict__ hstart,
-                       uint32_t *__restrict__ nlow) {
+                       uint32_t *__restrict__ nlow, const uint32_t *__restrict__ status) {
+    if (input_failed(status)) return;
     const int lane = lane_id();
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
     for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE); v < n;
@@ -278,7 +292,8 @@ k_tri(const int64_t *__restrict__ nrp, const int32_t *__restrict__ ncol,
                       uint32_t *__restrict__ tri_slot, int64_t m, int L,
                       uint32_t *__restrict__ tri, uint64_t *__restrict__ tri_sum, int32_t sh_base,
                       int64_t nw, const uint64_t *__restrict__ SB, int32_t hub_base, int Hw,
-                      const uint64_t *__restrict__ HB) {
+                      const uint64_t *__restrict__ HB, const uint32_t *__restrict__ status) {
+    if (input_failed(status)) return;
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
     const int lane = lane_id();
@@ -408,7 +423,8 @@ __global__ void k_node_aggr(const int64_t *__restrict__ nrp, const int32_t *__re
                             const uint8_t *__restrict__ ctype, const uint32_t *__restrict__ tri_slot,
                             const uint32_t *__restrict__ tdeg,
                             int64_t n, int L, uint64_t *__restrict__ A, uint64_t *__restrict__ D,
-                            int ad_u32) {
+                            int ad_u32, const uint32_t *__restrict__ status) {
+    if (input_failed(status)) return;
     extern __shared__ uint64_t sm_aggr[];
     int w = threadIdx.x / WAVE;
     int lane = lane_id();
@@ -541,6 +557,7 @@ __global__ void __launch_bounds__(64) k_cyc_light(CycleArgs a) {
     __shared__ uint32_t it_eid[WAVE];
     __shared__ int it_flip[WAVE];
     int lane = threadIdx.x;
+    if (input_failed(a.status)) return;
     uint64_t count = a.counters[a.count_idx];
     for (int q = lane; q < HC; q += WAVE) keys[q] = EMPTY_KEY;
     for (int q = lane; q < HC * LW; q += WAVE) cnt[q] = 0;
@@ -760,6 +777,7 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
     __shared__ int32_t s_task[4];  // group, first target, end target, streamed clear
     __shared__ MapClasses s_mc;
     int tid = threadIdx.x;
+    if (input_failed(a.status)) return;
     uint32_t *map = a.maps + (size_t)blockIdx.x * (size_t)a.n * L;
     uint64_t count = a.counters[a.count_idx];
     if (tid == 0) s_mc = map_classes(a);
@@ -1003,7 +1021,8 @@ __global__ void __launch_bounds__(256) k_cyc_work(
     const uint32_t *__restrict__ nlow, int64_t n, uint32_t *__restrict__ listA_light,
     uint4 *__restrict__ listA_heavy, uint32_t *__restrict__ listB_light,
     uint4 *__restrict__ listB_heavy, uint64_t *__restrict__ counters, uint64_t task_wedges,
-    int L, uint64_t range_bytes, uint64_t light_max) {
+    int L, uint64_t range_bytes, uint64_t light_max, const uint32_t *__restrict__ status) {
+    if (input_failed(status)) return;
     __shared__ int64_t s_thr;
     if (threadIdx.x == 0) {
         int64_t lo = 0, hi = n;
@@ -1050,6 +1069,7 @@ __global__ void __launch_bounds__(256) k_cyc_work(
 // Global counts: divide each graphlet block by its edge count.
 __global__ void k_global_finalize(const uint64_t *__restrict__ gacc, int L,
                                   uint64_t *__restrict__ out, uint32_t *__restrict__ status) {
+    if (input_failed(status)) return;
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     int n2 = (int)binom_small(L + 1, 2), n3 = (int)binom_small(L + 2, 3),
         n4 = (int)binom_small(L + 3, 4);
@@ -1064,6 +1084,27 @@ __global__ void k_global_finalize(const uint64_t *__restrict__ gacc, int L,
     uint64_t v = gacc[q];
     if (v % E[h]) atomicOr(status, ST_NOT_DIVISIBLE);
     out[q] = v / E[h];
+}
+
+// The number of entries above the diagonal must be half the adjacency (a
+// symmetric graph); otherwise the edge numbering would leave [0, m).
+__global__ void k_check_edge_count(const int64_t *__restrict__ eoff, int64_t n, int64_t m,
+                                   uint32_t *__restrict__ status) {
+    if (input_failed(status)) return;
+    if (eoff[n] != m) atomicOr(status, ST_EDGE_COUNT);
+}
+
+// The call's status code from the status bits (the same mapping as the
+// host side's), for calls that never read the status back themselves.
+__global__ void k_status_code(const uint32_t *__restrict__ status, int32_t *__restrict__ out) {
+    const uint32_t b = *status;
+    tg_status s = TG_OK;
+    if (b & (ST_BATCH | ST_CROSS_GRAPH)) s = TG_E_BATCH;
+    else if (b & ST_TYPE_RANGE) s = TG_E_TYPE_RANGE;
+    else if (b & (ST_COL_RANGE | ST_UNSORTED | ST_SELF_LOOP | ST_ASYMMETRIC | ST_EDGE_COUNT))
+        s = TG_E_NOT_SIMPLE;
+    else if (b) s = TG_E_INTERNAL;
+    *out = (int32_t)s;
 }
 
 // ------------------------------------------------------ launch wrappers
@@ -1105,20 +1146,34 @@ hipError_t launch_check_rows(const int64_t *rp, const int32_t *col, const uint8_
     return hipSuccess;
 }
 
-hipError_t launch_node_keys(const uint32_t *deg, int64_t n, const int32_t *node_graph, int deg_bits,
-                            uint64_t *keys, hipStream_t st) {
-    k_node_keys<<<blocks_for(n, 256), 256, 0, st>>>(deg, n, node_graph, deg_bits, keys);
+hipError_t launch_check_edge_count(const int64_t *eoff, int64_t n, int64_t m, uint32_t *status,
+                                   hipStream_t st) {
+    k_check_edge_count<<<1, 1, 0, st>>>(eoff, n, m, status);
     LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_relabel(const uint64_t *sorted, const uint8_t *types, const uint32_t *deg, int64_t n,
-                          int32_t *order, int32_t *newid, uint8_t *ntype, int64_t *ndeg,
+hipError_t launch_status_code(const uint32_t *status, int32_t *out, hipStream_t st) {
+    k_status_code<<<1, 1, 0, st>>>(status, out);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_node_keys(const uint32_t *deg, int64_t n, const int32_t *node_graph, int deg_bits,
+                            uint64_t *keys, uint32_t *ids, const uint32_t *status, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_node_keys<<<blocks_for(n, 256), 256, 0, st>>>(deg, n, node_graph, deg_bits, keys, ids, status);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_relabel(const uint32_t *sorted_ids, const uint8_t *types, const uint32_t *deg,
+                          int64_t n, int32_t *order, int32_t *newid, uint8_t *ntype, int64_t *ndeg,
                           uint64_t *hub_cand, uint32_t sh_deg, const int32_t *node_graph,
-                          int32_t *ngraph, hipStream_t st) {
-    k_relabel<<<blocks_for(n > 0 ? n : 1, 256), 256, 0, st>>>(sorted, types, deg, n, order, newid,
-                                                              ntype, ndeg, hub_cand, sh_deg,
-                                                              node_graph, ngraph);
+                          int32_t *ngraph, const uint32_t *status, hipStream_t st) {
+    k_relabel<<<blocks_for(n > 0 ? n : 1, 256), 256, 0, st>>>(sorted_ids, types, deg, n, order,
+                                                              newid, ntype, ndeg, hub_cand, sh_deg,
+                                                              node_graph, ngraph, status);
     LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1135,19 +1190,19 @@ hipError_t launch_slot_keys(const int64_t *rp, const int32_t *col, const int64_t
 
 hipError_t launch_finish_csr(const uint64_t *keys, const uint32_t *vals, int64_t nnz, int bits,
                              const uint8_t *ntype, uint32_t *eslot, int32_t *ncol, uint32_t *neid,
-                             uint8_t *ctype, hipStream_t st) {
+                             uint8_t *ctype, const uint32_t *status, hipStream_t st) {
     if (nnz == 0) return hipSuccess;
     k_finish_csr<<<blocks_for(nnz, 256), 256, 0, st>>>(keys, vals, nnz, bits, ntype, eslot, ncol,
-                                                       neid, ctype);
+                                                       neid, ctype, status);
     LAUNCH_CHECK();
     return hipSuccess;
 }
 
 hipError_t launch_tdeg(const int64_t *nrp, const int32_t *ncol, const uint8_t *ctype, int64_t n,
                        int L, int32_t hub_base, uint32_t *tdeg, int64_t *hstart, uint32_t *nlow,
-                       hipStream_t st) {
+                       const uint32_t *status, hipStream_t st) {
     k_tdeg<<<blocks_bounded(n, 4, 32), 256, 0, st>>>(nrp, ncol, ctype, n, L, hub_base, tdeg,
-                                                     hstart, nlow);
+                                                     hstart, nlow, status);
     LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1156,11 +1211,12 @@ hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *ct
                       const int32_t *ei, const int32_t *ej, const uint32_t *eslot,
                       uint32_t *tri_slot, int64_t m, int L, uint32_t *tri,
                       uint64_t *tri_sum, int32_t sh_base, int64_t nw, const uint64_t *SB,
-                      int32_t hub_base, int Hw, const uint64_t *HB, hipStream_t st) {
+                      int32_t hub_base, int Hw, const uint64_t *HB, const uint32_t *status,
+                      hipStream_t st) {
     if (m == 0) return hipSuccess;
     k_tri<<<blocks_bounded(m, 4 * TRI_GROUPS, 32), 256, 0, st>>>(
         nrp, ncol, ctype, ei, ej, eslot, tri_slot, m, L, tri, tri_sum, sh_base, nw, SB, hub_base,
-        Hw, HB);
+        Hw, HB, status);
     LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1168,10 +1224,10 @@ hipError_t launch_tri(const int64_t *nrp, const int32_t *ncol, const uint8_t *ct
 hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8_t *ctype,
                             const uint32_t *tri_slot, const uint32_t *tdeg,
                             int64_t n, int L, uint64_t *A, uint64_t *D, bool ad_u32,
-                            hipStream_t st) {
+                            const uint32_t *status, hipStream_t st) {
     size_t sh = (size_t)4 * 2 * L * L * sizeof(uint64_t);
     k_node_aggr<<<blocks_bounded(n, 4, 32), 256, sh, st>>>(nrp, ncol, ctype, tri_slot, tdeg, n, L,
-                                                           A, D, ad_u32 ? 1 : 0);
+                                                           A, D, ad_u32 ? 1 : 0, status);
     LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1180,7 +1236,7 @@ hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32
                            const uint32_t *eslot, const uint32_t *nlow, int64_t n, uint32_t *la_l,
                            uint4 *la_h, uint32_t *lb_l, uint4 *lb_h, uint64_t *counters,
                            uint64_t task_wedges, int L, uint64_t range_bytes,
-                           uint64_t light_max, hipStream_t st) {
+                           uint64_t light_max, const uint32_t *status, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     int dev = 0, cus = 0;
     hipError_t err = hipGetDevice(&dev);
@@ -1191,7 +1247,7 @@ hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32
     int64_t cap = (int64_t)(cus > 0 ? cus : 256) * 16;
     unsigned grid = (unsigned)(want < cap ? want : cap);
     k_cyc_work<<<grid, 256, 0, st>>>(nrp, ncol, neid, eslot, nlow, n, la_l, la_h, lb_l, lb_h,
-                                     counters, task_wedges, L, range_bytes, light_max);
+                                     counters, task_wedges, L, range_bytes, light_max, status);
     LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1233,18 +1289,18 @@ hipError_t launch_global_finalize(const uint64_t *gacc, int L, int gw, uint64_t 
 
 hipError_t launch_batch_graphs(const int64_t *node_ptr, const int32_t *gL, const int64_t *goff,
                                int64_t G, int64_t n, int L_max, int64_t globals_len,
-                               int32_t *node_graph, uint32_t *status, uint64_t *max_gsize,
-                               hipStream_t st) {
+                               int64_t max_nodes, int32_t *node_graph, uint32_t *status,
+                               uint64_t *max_gsize, hipStream_t st) {
     if (G <= 0) return hipSuccess;
     k_batch_graphs<<<blocks_for(G, 4), 256, 0, st>>>(node_ptr, gL, goff, G, n, L_max, globals_len,
-                                                     node_graph, status, max_gsize);
+                                                     max_nodes, node_graph, status, max_gsize);
     LAUNCH_CHECK();
     return hipSuccess;
 }
 
 hipError_t launch_batch_edges(const int64_t *node_ptr, const int64_t *eoff, int64_t G,
-                              int64_t *gedge_ptr, hipStream_t st) {
-    k_batch_edges<<<blocks_for(G + 1, 256), 256, 0, st>>>(node_ptr, eoff, G, gedge_ptr);
+                              int64_t *gedge_ptr, const uint32_t *status, hipStream_t st) {
+    k_batch_edges<<<blocks_for(G + 1, 256), 256, 0, st>>>(node_ptr, eoff, G, gedge_ptr, status);
     LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -192,6 +192,7 @@ __device__ __forceinline__ void pa_pair(const EdgeArgs &a, const PaLayout &pl, c
 template <typename XT, bool NARROW>
 __global__ void __launch_bounds__(256) k_derive_pa(EdgeArgs a, PaLayout pl) {
     extern __shared__ uint64_t sm_pa[];
+    if (input_failed(a.status)) return;
     const int L = a.L;
     const int LL = L * L;
     const int P = L * (L + 1) / 2;
@@ -237,7 +238,7 @@ __global__ void __launch_bounds__(256) k_derive_pa(EdgeArgs a, PaLayout pl) {
 __global__ void k_pa_finalize(const uint64_t *__restrict__ acc, PaLayout pl,
                               uint64_t *__restrict__ out, uint32_t *__restrict__ status) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= pl.gstart[9]) return;
+    if (q >= pl.gstart[9] || input_failed(status)) return;
     int h = 0;
     while (q >= pl.gstart[h + 1]) ++h;
     const uint64_t E[9] = {1, 2, 3, 3, 3, 4, 4, 5, 6};

@@ -5,8 +5,6 @@
 // function of the dense table.
 #include <hip/hip_runtime.h>
 
-#include <rocprim/device/device_scan.hpp>
-
 #include "tg_device.hpp"
 
 namespace tg {
@@ -70,14 +68,8 @@ unsigned row_blocks(int64_t waves) {
     return b > 0 ? (unsigned)b : 1u;
 }
 
-size_t scan_tmp_bytes(int64_t m) {
-    size_t b = 0;
-    int64_t *p = nullptr;
-    if (rocprim::exclusive_scan(nullptr, b, p, p, int64_t(0), (size_t)(m + 1),
-                                rocprim::plus<int64_t>()) != hipSuccess)
-        return (size_t)(16 << 20) + (size_t)(m + 1) * 16;  // no device to ask: generous bound
-    return b + 256;
-}
+// Tile sums of the prefix sum over m + 1 entries.
+size_t scan_tmp_bytes(int64_t m) { return (size_t)(scan_tiles(m + 1) + 1) * sizeof(int64_t); }
 
 }  // namespace
 }  // namespace tg
@@ -102,13 +94,10 @@ tg_status tg_sparse_offsets(const uint64_t *rows, int64_t m, int32_t L, int64_t 
     const int W = tg_row_width(L);
     int64_t *cnt = static_cast<int64_t *>(workspace);
     const size_t cnt_bytes = ((size_t)(m + 1) * sizeof(int64_t) + 255) / 256 * 256;
-    void *tmp = static_cast<char *>(workspace) + cnt_bytes;
-    size_t tmp_bytes = ws_bytes - cnt_bytes;
+    int64_t *tmp = reinterpret_cast<int64_t *>(static_cast<char *>(workspace) + cnt_bytes);
     k_row_nnz<<<row_blocks(m), 256, 0, st>>>(rows, m, W, cnt);
     if (hipGetLastError() != hipSuccess) return TG_E_DEVICE;
-    if (rocprim::exclusive_scan(tmp, tmp_bytes, cnt, edge_off, int64_t(0), (size_t)(m + 1),
-                                rocprim::plus<int64_t>(), st) != hipSuccess)
-        return TG_E_DEVICE;
+    if (launch_excl_scan(cnt, edge_off, m + 1, tmp, nullptr, st) != hipSuccess) return TG_E_DEVICE;
     return hipStreamSynchronize(st) == hipSuccess ? TG_OK : TG_E_DEVICE;
 }
 
