@@ -79,7 +79,9 @@ typedef enum tg_status {
     TG_E_DEVICE = 6,      /* a HIP call failed */
     TG_E_INTERNAL = 7,    /* an internal consistency check failed */
     TG_E_TOO_LARGE = 8,   /* n or nnz beyond the supported range (see below) */
-    TG_E_BATCH = 9        /* batch descriptor inconsistent, or an edge joins two graphs */
+    TG_E_BATCH = 9,       /* batch descriptor inconsistent, or an edge joins two graphs */
+    TG_E_OOM = 10,        /* the request can never fit the serving arena or a worker's region */
+    TG_E_TIMEOUT = 11     /* tg_server_wait: the request is not finished yet */
 } tg_status;
 
 /* Human-readable name of a status code (static string). */
@@ -194,6 +196,88 @@ tg_status tg_count_batch_async(const int64_t *row_ptr, const int32_t *col, const
                                int64_t globals_len, uint64_t *per_edge, uint64_t *graph_globals,
                                void *workspace, size_t ws_bytes, int32_t *status_out,
                                void *stream);
+
+/* Serving with continuous batching.  A server counts a stream of requests,
+ * each one typed graph (the local counts of Problem 1 reduced to its global
+ * counts, Problem 2), with the global vector of each request left in device
+ * memory until the caller releases it.  All device memory is the caller's
+ * `arena` (256-byte aligned, arena_bytes): `workers` regions of
+ * worker_bytes each (one batch's union CSR, descriptor, outputs and
+ * workspace), the rest a pool from which each admitted request takes one
+ * block (its CSR, types and global vector) until it is released.
+ *   Admission: requests are admitted in arrival order when their block fits
+ *     the pool (by HBM footprint); a request waits while it does not.
+ *   Batching: each worker (a host thread with its own HIP stream) takes the
+ *     admitted requests not yet started as one batched call (up to its region
+ *     and max_batch_edges edges), so requests that arrive while others run
+ *     join the next batch and workers overlap on the device; a request of at
+ *     least single_edges edges runs alone as a single-graph call.  A failing
+ *     batch is re-run request by request: only the offending request fails.
+ *   Knobs: the workers use the scheduling knobs of the creating thread
+ *     (tg_set_tuning), with the heavy-map and heavy-list budgets cut to a
+ *     quarter and an eighth of worker_bytes.
+ * Results are exact and independent of the batch a request lands in. */
+typedef struct tg_server tg_server;
+
+typedef enum { TG_MEM_HOST = 0, TG_MEM_DEVICE = 1 } tg_mem;
+
+/* One request's graph: CSR and types as for tg_count_typed_graphlets, in
+ * host memory (copied at submission; the caller may free it on return) or
+ * in device memory (read when the request runs: it must stay valid until the
+ * request is done). */
+typedef struct {
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const uint8_t *types;
+    int64_t n, nnz;
+    int32_t L;
+    int32_t mem;            /* tg_mem */
+} tg_graph_desc;
+
+typedef struct {
+    int32_t state;          /* 0 waiting, 1 admitted, 2 running, 3 done */
+    int32_t status;         /* tg_status once done, else -1 */
+    const uint64_t *global_counts;  /* device, tg_global_width(L) entries, once
+                                       done with TG_OK, until released */
+    double t_submit, t_admit, t_start, t_done;  /* seconds since creation, -1 if not yet */
+    int64_t batch;          /* batch that ran it (-1 before) */
+} tg_request_info;
+
+/* Starts the workers.  TG_E_INVALID_ARG: null or unaligned arena, workers
+ * outside 1..64, worker_bytes < 4096, single_edges or max_batch_edges < 1;
+ * TG_E_OOM: the worker regions leave no pool; TG_E_DEVICE: no current
+ * device. */
+tg_status tg_server_create(void *arena, size_t arena_bytes, int32_t workers, size_t worker_bytes,
+                           int64_t single_edges, int64_t max_batch_edges, tg_server **out);
+/* Queues a request and returns its ticket; TG_E_OOM if its block is larger
+ * than the whole pool (it could never be admitted); a request whose
+ * workspace cannot fit a worker's region finishes with TG_E_OOM. */
+tg_status tg_server_submit(tg_server *s, const tg_graph_desc *g, int64_t *ticket);
+/* State, status, result pointer and timestamps of a ticket (non-blocking). */
+tg_status tg_server_poll(tg_server *s, int64_t ticket, tg_request_info *info);
+/* Blocks until the request is done or timeout_s seconds have passed
+ * (TG_E_TIMEOUT). */
+tg_status tg_server_wait(tg_server *s, int64_t ticket, double timeout_s);
+/* Hands out up to max_tickets tickets of requests that finished since the
+ * previous call (each ticket once, in completion order), waiting up to
+ * timeout_s seconds when there is none; returns how many were written. */
+int32_t tg_server_take_done(tg_server *s, int64_t *tickets, int32_t max_tickets,
+                            double timeout_s);
+/* Frees a finished request's block (its CSR and result); the ticket is then
+ * invalid.  TG_E_INVALID_ARG for an unknown, released or unfinished ticket. */
+tg_status tg_server_release(tg_server *s, int64_t ticket);
+/* Counters: [0] submitted, [1] finished, [2] rejected (TG_E_OOM), [3]
+ * batches, [4] single-graph calls, [5] pool bytes in use, [6] peak pool
+ * bytes, [7] pool size, [8] microseconds workers spent running batches (sum
+ * over workers), [9] waiting, [10] admitted not started, [11] first device
+ * error (tg_status) of a worker.  Returns the number written. */
+#define TG_SERVER_NUM_STATS 12
+int32_t tg_server_stats(tg_server *s, int64_t *stats, int32_t max_stats);
+/* Finishes every submitted request (results not yet released become
+ * invalid and their memory serves the remaining requests), stops the
+ * workers and frees the server; returns the first device error of a
+ * worker, or TG_OK. */
+tg_status tg_server_destroy(tg_server *s);
 
 /* Sparse per-edge output (Sec. 4.6: an edge keeps only its nonzero typed
  * graphlet counts, with a lookup table from key to description, here

@@ -16,6 +16,23 @@ LIB_PATH = os.path.join(PKG, "libtg.so")
 
 # Every function the header declares, with its ctypes signature.
 _c = ctypes
+
+
+class GraphDesc(ctypes.Structure):
+    """tg_graph_desc"""
+    _fields_ = [("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("types", ctypes.c_void_p), ("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("L", ctypes.c_int32), ("mem", ctypes.c_int32)]
+
+
+class RequestInfo(ctypes.Structure):
+    """tg_request_info"""
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("global_counts", ctypes.c_void_p), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("batch", ctypes.c_int64)]
+
+
 SIGNATURES = {
     "tg_status_str": (_c.c_char_p, [_c.c_int]),
     "tg_row_width": (_c.c_int32, [_c.c_int32]),
@@ -52,6 +69,16 @@ SIGNATURES = {
     "tg_sparse_fill": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int32, _c.c_void_p, _c.c_void_p,
                                   _c.c_void_p, _c.c_void_p]),
     "tg_get_tuning": (_c.c_int64, [_c.c_int32]),
+    "tg_server_create": (_c.c_int, [_c.c_void_p, _c.c_size_t, _c.c_int32, _c.c_size_t,
+                                    _c.c_int64, _c.c_int64, _c.POINTER(_c.c_void_p)]),
+    "tg_server_submit": (_c.c_int, [_c.c_void_p, _c.POINTER(GraphDesc), _c.POINTER(_c.c_int64)]),
+    "tg_server_poll": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.POINTER(RequestInfo)]),
+    "tg_server_wait": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_double]),
+    "tg_server_take_done": (_c.c_int32, [_c.c_void_p, _c.POINTER(_c.c_int64), _c.c_int32,
+                                         _c.c_double]),
+    "tg_server_release": (_c.c_int, [_c.c_void_p, _c.c_int64]),
+    "tg_server_stats": (_c.c_int32, [_c.c_void_p, _c.POINTER(_c.c_int64), _c.c_int32]),
+    "tg_server_destroy": (_c.c_int, [_c.c_void_p]),
     "tg_pa_row_width": (_c.c_int32, [_c.c_int32]),
     "tg_pa_global_width": (_c.c_int64, [_c.c_int32]),
     "tg_count_position_aware": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int64,

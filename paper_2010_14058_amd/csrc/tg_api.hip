@@ -620,6 +620,8 @@ const char *tg_status_str(tg_status s) {
         case TG_E_INTERNAL: return "internal consistency check failed";
         case TG_E_TOO_LARGE: return "graph too large";
         case TG_E_BATCH: return "inconsistent batch descriptor or an edge between two graphs";
+        case TG_E_OOM: return "request does not fit the serving memory";
+        case TG_E_TIMEOUT: return "request not finished";
     }
     return "unknown status";
 }
