@@ -239,9 +239,12 @@ def cpu_baseline(g, threads, target_s=15.0, seed=123):
     }
 
 
-def bench_batch(args):
-    """Batched configuration: 1e5 small typed Chung-Lu graphs in one call,
-    against the same graphs counted one call per graph."""
+def run_batch_workload(args, graphs: int, single_sample: int, oracle_graphs: int, steps: int,
+                       tune: bool = True):
+    """The batched configuration: 1e5 small typed Chung-Lu graphs counted by
+    one call (eagerly, and replayed from a HIP graph recorded from the call
+    without host synchronisation), against the same graphs counted one call
+    per graph."""
     import torch
 
     import oracle
@@ -250,10 +253,11 @@ def bench_batch(args):
 
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    b = G.batch_graphs(args.graphs, seed=0)
+    b = G.batch_graphs(graphs, seed=0)
     u = b.union
+    gen_s = time.perf_counter() - t0
     log(f"[bench] batch of {b.G} graphs: n={u.n} m={u.m} max_degree={int(u.degrees().max())} "
-        f"L_max={u.L} ({time.perf_counter() - t0:.1f}s)")
+        f"L_max={u.L} ({gen_s:.1f}s)")
     plan = P.BatchPlan(torch.from_numpy(u.row_ptr).to(dev), torch.from_numpy(u.col).to(dev),
                        torch.from_numpy(u.types).to(dev), b.node_ptr, b.L)
     ws = P.Workspace(dev)
@@ -267,28 +271,63 @@ def bench_batch(args):
         torch.cuda.synchronize()
         return AT.digest_of(glob)
 
-    tuning = setup_tuning(args, G.CONFIG_NAMES[4], run_once)
+    defaults = P.get_tuning()
+    if tune:
+        tuning = setup_tuning(args, G.CONFIG_NAMES[4], run_once)
+    else:
+        from paper_2010_14058_amd import autotune as AT
+
+        path = os.path.join(TUNED_DIR, G.CONFIG_NAMES[4] + ".json")
+        tuning = {"profile": None, "knobs": P.get_tuning()}
+        if os.path.exists(path) and not args.no_tuned:
+            prof = AT.load(path)
+            AT.apply(prof)
+            tuning = {"profile": os.path.relpath(path, ROOT), "knobs": prof["knobs"]}
+    # eager calls (the call checks its inputs and reads the status back)
     P.set_timing(True)
-    for w in range(args.warmup):
-        P.count_batch(plan, out_globals=glob, workspace=ws, stream=stream)
-        torch.cuda.synchronize()
-        log(f"[bench] warmup {w + 1}/{args.warmup} done")
-    phase_sum = {}
+    P.count_batch(plan, out_globals=glob, workspace=ws, stream=stream)
     torch.cuda.synchronize()
+    phase_sum = {}
     t_start = time.perf_counter()
-    for s in range(args.steps):
+    for _ in range(steps):
         P.count_batch(plan, out_globals=glob, workspace=ws, stream=stream)
         for name, ms in P.phase_times():
             phase_sum[name] = phase_sum.get(name, 0.0) + ms
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
+    eager_s = time.perf_counter() - t_start
+    P.set_timing(False)
+    eager = glob.cpu().numpy().view(np.uint64).copy()
     stats = P.last_stats()
-    phase_avg = {k: v / args.steps for k, v in phase_sum.items()}
-    bglob = glob.cpu().numpy().view(np.uint64)
-    log(f"[bench] batched: {args.steps} steps in {elapsed:.3f}s")
-
+    # the same call recorded into a HIP graph and replayed
+    out = torch.full_like(glob, -1)
+    status = torch.full((1,), -1, dtype=torch.int32, device=dev)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        P.count_batch_async(plan, out, status, ws, side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        P.count_batch_async(plan, out, status, ws, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_r = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    replay_s = time.perf_counter() - t_r
+    replay_ev_ms = e0.elapsed_time(e1) / steps
+    replay_ok = int(status.item()) == 0 and np.array_equal(out.cpu().numpy().view(np.uint64), eager)
+    del graph
+    log(f"[bench] batch: eager {eager_s * 1e3 / steps:.1f} ms per call, replay "
+        f"{replay_s * 1e3 / steps:.1f} ms per launch, identical={replay_ok}")
     # the same graphs, one library call each (a prefix of the batch)
-    S = min(args.single_sample, b.G)
+    S = min(single_sample, b.G)
     singles = []
     for g in range(S):
         gg = b.graph(g)
@@ -296,7 +335,6 @@ def bench_batch(args):
                         torch.from_numpy(gg.types).to(dev), gg.L))
     sws = P.Workspace(dev)
     outs = [torch.empty(P.global_width(L), dtype=torch.int64, device=dev) for *_, L in singles]
-    P.set_timing(False)
     for q in range(min(50, S)):
         rp, col, ty, L = singles[q]
         P.count_typed_graphlets(rp, col, ty, L, per_edge=False, out_global=outs[q], workspace=sws)
@@ -308,57 +346,75 @@ def bench_batch(args):
     torch.cuda.synchronize()
     single_s = time.perf_counter() - t1
     same = all(np.array_equal(outs[q].cpu().numpy().view(np.uint64),
-                              bglob[plan.goff_host[q]:plan.goff_host[q + 1]]) for q in range(S))
-    log(f"[bench] single-graph calls: {S} graphs in {single_s:.3f}s, identical={same}")
-
-    batch_gps = b.G * args.steps / elapsed
+                              eager[plan.goff_host[q]:plan.goff_host[q + 1]]) for q in range(S))
     single_gps = S / single_s
-    result = {
-        "metric": "batched graphs/sec (typed 3+4-node counts)",
-        "value": batch_gps,
-        "unit": "graphs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64",
-        "data": "synthetic",
-        "config": {"workload": G.CONFIG_NAMES[4], "graphs": b.G, "n": u.n, "m": u.m,
-                   "L_max": int(u.L), "max_degree": int(u.degrees().max())},
-        "edges_per_s": u.m * args.steps / elapsed,
+    res = {
+        "workload": G.CONFIG_NAMES[4], "graphs": b.G, "n": u.n, "m": u.m, "L_max": int(u.L),
+        "max_degree": int(u.degrees().max()), "generation_s": round(gen_s, 2),
+        "replay_graphs_per_s": b.G * steps / replay_s,
+        "replay_ms_per_launch_events": replay_ev_ms,
+        "replay_identical_to_eager": bool(replay_ok),
+        "eager_graphs_per_s": b.G * steps / eager_s,
+        "eager_ms_per_call": eager_s * 1e3 / steps,
+        "edges_per_s_replay": u.m * steps / replay_s,
         "single_call_path": {"graphs_per_s": single_gps, "graphs_timed": S,
                              "identical_counts": bool(same)},
-        "speedup_vs_single_call": batch_gps / single_gps,
+        "speedup_replay_vs_single_call": (b.G * steps / replay_s) / single_gps,
         "tuning": tuning,
-        "phases_ms": {k: round(v, 3) for k, v in phase_avg.items()},
+        "phases_ms": {k: round(v / steps, 3) for k, v in phase_sum.items()},
         "work": {k: int(v) for k, v in stats.items()},
     }
-    if not args.skip_cpu:
-        threads = host_threads()
-        k = min(b.G, 4000)
+    if oracle_graphs > 0:
+        k = min(b.G, oracle_graphs)
         t2 = time.perf_counter()
         ok = True
         for g in range(k):
             gg = b.graph(g)
             rows = oracle.edge_rows(gg, gg.edges(), method="paper", threads=1)
             want = oracle.global_counts(gg, rows)
-            ok &= bool(np.array_equal(want, bglob[plan.goff_host[g]:plan.goff_host[g + 1]]))
+            ok &= bool(np.array_equal(want, eager[plan.goff_host[g]:plan.goff_host[g + 1]]))
         dt = time.perf_counter() - t2
-        result["cpu_baseline"] = {"value": k / dt, "unit": "graphs/s", "cores": 1, "kind": "oracle",
-                                  "sample": f"the first {k} graphs of the batch, paper algorithm, "
-                                            f"one thread, {dt:.1f} s"}
-        result["parity_sample"] = f"{k} graphs' global vectors identical to the oracle: {ok}"
-        log(f"[bench] {result['parity_sample']}")
+        res["cpu_baseline"] = {"value": k / dt, "unit": "graphs/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the first {k} graphs of the batch, paper algorithm, "
+                                         f"one thread, {dt:.1f} s"}
+        res["parity_sample"] = f"{k} graphs' global vectors identical to the oracle: {ok}"
+        log(f"[bench] {res['parity_sample']}")
+    P.set_tuning(**defaults)
+    del plan, ws, glob, out, sws, singles, outs
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_batch(args):
+    res = run_batch_workload(args, args.graphs, args.single_sample, 4000, args.steps)
+    result = {
+        "metric": "batched graphs/sec (typed 3+4-node counts)",
+        "value": res["replay_graphs_per_s"],
+        "unit": "graphs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": 1e3 * res["graphs"] / res["replay_graphs_per_s"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": res["workload"], "graphs": res["graphs"], "n": res["n"],
+                   "m": res["m"], "L_max": res["L_max"], "max_degree": res["max_degree"]},
+    }
+    result.update({k: v for k, v in res.items() if k not in result["config"]})
     print(json.dumps(result), flush=True)
 
 
-def bench_serve(args):
-    """Serving configuration: Poisson arrivals of typed Chung-Lu graphs
-    (edges log-uniform in [1e2, 1e6], n = m/5, exponent 2.2, L = 6 Zipf
-    types), continuous batching with admission by HBM footprint."""
+def run_serve_workload(args, requests: int, pool: int, rate: float, workers: int,
+                       budget_gb: float, single_edges: int, max_batch_edges: int):
+    """The serving configuration: a Poisson stream of `requests` requests at
+    `rate` per second, each one typed Chung-Lu graph (edges log-uniform in
+    [1e2, 1e6], n = m/5, exponent 2.2, L = 6 with Zipf(1.2) types) drawn from
+    a pool of `pool` generated graphs, served by the native server (admission
+    by HBM footprint, continuous batching on `workers` streams); against the
+    pool's graphs counted one call each."""
     import torch
 
     import paper_2010_14058_amd as P
@@ -366,32 +422,39 @@ def bench_serve(args):
     from tg_synth import graphs as G
 
     t0 = time.perf_counter()
-    specs = G.serving_requests(args.requests, rate=args.rate, seed=0)
-    reqs = []
-    for q, sp in enumerate(specs):
-        g = G.serving_graph(sp)
-        reqs.append(S.Request(q, g.row_ptr, g.col, g.types, g.L, arrival=sp["arrival"]))
+    specs = G.serving_requests(pool, rate=rate, seed=0)
+    graphs = [G.serving_graph(sp) for sp in specs]
+    rng = np.random.default_rng(np.random.SeedSequence(1).spawn(1)[0])
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=requests))
+    pick = rng.integers(0, pool, size=requests)
+    reqs = [S.Request(q, graphs[k].row_ptr, graphs[k].col, graphs[k].types, graphs[k].L,
+                      arrival=float(arrivals[q])) for q, k in enumerate(pick)]
     offered_edges = sum(r.m for r in reqs)
-    span = specs[-1]["arrival"] if specs else 1.0
-    log(f"[bench] {len(reqs)} requests, {offered_edges} edges, arrivals over {span:.3f}s "
-        f"({time.perf_counter() - t0:.1f}s to generate)")
-    ex = S.GpuExecutor(workers=args.workers, single_edges=args.single_edges)
-    # warm the executor (library load, allocator) on a tiny batch
-    warm = G.random_small_graph(20, 0.3, 6, 1)
-    ex.run([S.Request(-1, warm.row_ptr, warm.col, warm.types, warm.L)], 0)
-    torch.cuda.synchronize()
-    srv = S.Server(hbm_budget=int(args.hbm_budget_gb * (1 << 30)), executor=ex,
-                   workers=args.workers, max_batch_edges=args.max_batch_edges)
+    span = float(arrivals[-1]) if requests else 1.0
+    gen_s = time.perf_counter() - t0
+    log(f"[bench] serving: {requests} requests from a pool of {pool} graphs, {offered_edges} "
+        f"edges, arrivals over {span:.2f}s ({gen_s:.1f}s to generate)")
+    defaults = P.get_tuning()
+    path = os.path.join(TUNED_DIR, G.CONFIG_NAMES[4] + ".json")
+    if os.path.exists(path) and not args.no_tuned:
+        from paper_2010_14058_amd import autotune as AT
+
+        AT.apply(AT.load(path))          # the batch profile for the workers
+    srv = S.Server(hbm_budget=int(budget_gb * (1 << 30)), workers=workers,
+                   single_edges=single_edges, max_batch_edges=max_batch_edges)
     S.replay(srv, reqs)
     srv.close()
     rep = srv.report()
+    del srv
+    torch.cuda.empty_cache()
+    P.set_tuning(**defaults)
     log(f"[bench] serving report: {rep}")
-
-    # the plain path: the same requests, one library call each, back to back
+    # the plain path: the pool's graphs, one library call each
     dev = torch.device("cuda:0")
     ws = P.Workspace(dev)
-    dev_graphs = [(torch.from_numpy(r.row_ptr).to(dev), torch.from_numpy(r.col).to(dev),
-                   torch.from_numpy(r.types).to(dev), r.L) for r in reqs]
+    dev_graphs = [(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev),
+                   torch.from_numpy(g.types).to(dev), g.L) for g in graphs]
+    P.count_typed_graphlets(*dev_graphs[0][:3], dev_graphs[0][3], per_edge=False, workspace=ws)
     torch.cuda.synchronize()
     outs = []
     t1 = time.perf_counter()
@@ -400,36 +463,57 @@ def bench_serve(args):
         outs.append(g1)
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t1
-    same = all(np.array_equal(o.cpu().numpy().view(np.uint64), r.result)
-               for o, r in zip(outs, reqs) if r.status == 0)
-    plain = {"edges_per_s": offered_edges / plain_s, "graphs_per_s": len(reqs) / plain_s,
-             "seconds": plain_s, "identical_counts": bool(same)}
-    log(f"[bench] plain one-call-per-request path: {plain}")
+    pool_edges = sum(g.m for g in graphs)
+    by_pool = {}
+    for r, k in zip(reqs, pick):
+        if r.status == 0:
+            by_pool.setdefault(int(k), r.result)
+    same = all(np.array_equal(outs[k].cpu().numpy().view(np.uint64), res)
+               for k, res in by_pool.items())
+    all_same = all(np.array_equal(r.result, by_pool[int(k)]) for r, k in zip(reqs, pick)
+                   if r.status == 0)
+    plain = {"edges_per_s": pool_edges / plain_s, "graphs_per_s": pool / plain_s,
+             "seconds": plain_s, "graphs": pool, "identical_counts": bool(same and all_same)}
+    log(f"[bench] plain one-call-per-graph path: {plain}")
+    del ws, dev_graphs, outs
+    torch.cuda.empty_cache()
+    return {
+        "workload": G.CONFIG_NAMES[5], "requests": requests, "graph_pool": pool,
+        "rate_per_s": rate, "workers": workers, "hbm_budget_GB": budget_gb,
+        "max_batch_edges": max_batch_edges, "single_edges": single_edges,
+        "served_edges_per_s": rep["served_edges_per_s"],
+        "served_graphs_per_s": rep["served_graphs_per_s"],
+        "offered_edges_per_s": offered_edges / max(span, 1e-9),
+        "offered_requests_per_s": requests / max(span, 1e-9),
+        "p50_latency_ms": rep["p50_latency_ms"], "p99_latency_ms": rep["p99_latency_ms"],
+        "plain_path": plain,
+        "speedup_vs_plain": {"edges": rep["served_edges_per_s"] / plain["edges_per_s"],
+                             "graphs": rep["served_graphs_per_s"] / plain["graphs_per_s"]},
+        "serving": rep, "generation_s": round(gen_s, 2),
+    }
+
+
+def bench_serve(args):
+    res = run_serve_workload(args, args.requests, args.pool, args.rate, args.workers,
+                             args.hbm_budget_gb, args.single_edges, args.max_batch_edges)
     result = {
         "metric": "served edges/sec (typed 3+4-node counts, Poisson arrivals)",
-        "value": rep["served_edges_per_s"],
+        "value": res["served_edges_per_s"],
         "unit": "edges/s",
         "n_gpus": 1,
-        "steps": len(reqs),
-        "warmup": 1,
+        "steps": res["requests"],
+        "warmup": 0,
         "ms_per_step": None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": G.CONFIG_NAMES[5], "requests": len(reqs), "rate_per_s": args.rate,
-                   "workers": args.workers, "hbm_budget_GB": args.hbm_budget_gb,
-                   "max_batch_edges": args.max_batch_edges, "single_edges": args.single_edges},
-        "offered_edges_per_s": offered_edges / max(span, 1e-9),
-        "p50_latency_ms": rep["p50_latency_ms"],
-        "p99_latency_ms": rep["p99_latency_ms"],
-        "served_graphs_per_s": rep["served_graphs_per_s"],
-        "plain_path": plain,
-        "speedup_vs_plain": {"edges": rep["served_edges_per_s"] / plain["edges_per_s"],
-                             "graphs": rep["served_graphs_per_s"] / plain["graphs_per_s"]},
-        "serving": rep,
+        "config": {"workload": res["workload"], "requests": res["requests"],
+                   "graph_pool": res["graph_pool"], "rate_per_s": res["rate_per_s"],
+                   "workers": res["workers"], "hbm_budget_GB": res["hbm_budget_GB"]},
     }
+    result.update({k: v for k, v in res.items() if k not in result["config"]})
     print(json.dumps(result), flush=True)
 
 
@@ -704,9 +788,16 @@ def bench_single(args):
     del rows, glob, g._dev
     ws.buf = None
     torch.cuda.empty_cache()
-    if args.config3_steps > 0:
+    if args.config3_steps > 0 and not args.no_extra:
         P.set_tuning(**defaults)
         result["config3"] = bench_config3(args, P, torch, G, dev, stream, peak["GBps"])
+    if not args.no_extra:
+        P.set_tuning(**defaults)
+        result["batch"] = run_batch_workload(args, args.graphs, args.single_sample,
+                                             0 if args.skip_cpu else 1000, 3, tune=False)
+        result["serve"] = run_serve_workload(args, args.requests, args.pool, args.rate,
+                                             args.workers, args.hbm_budget_gb, args.single_edges,
+                                             args.max_batch_edges)
     print(json.dumps(result), flush=True)
 
 
@@ -754,7 +845,9 @@ def main():
     ap.add_argument("--mode", choices=["single", "batch", "serve"], default="single",
                     help="single: the 10M-edge power-law graph (headline); batch: 1e5 small "
                          "graphs in one call; serve: Poisson request stream")
-    ap.add_argument("--requests", type=int, default=400, help="serve mode: number of requests")
+    ap.add_argument("--requests", type=int, default=20000, help="serve mode: number of requests")
+    ap.add_argument("--pool", type=int, default=400,
+                    help="serve mode: distinct graphs the requests are drawn from")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve mode: arrivals per second")
     ap.add_argument("--workers", type=int, default=2, help="serve mode: concurrent batches")
     ap.add_argument("--single-edges", type=int, default=1 << 17,
@@ -779,6 +872,9 @@ def main():
                     help="ignore the tuned profile, time the library defaults")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="single mode: only the headline graph (no tripartite, batch or serving "
+                         "summaries)")
     ap.add_argument("--config3-steps", type=int, default=3,
                     help="single mode: timed steps of the full-size tripartite graph after the "
                          "headline (0 skips it)")

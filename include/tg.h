@@ -279,6 +279,17 @@ int32_t tg_server_stats(tg_server *s, int64_t *stats, int32_t max_stats);
  * worker, or TG_OK. */
 tg_status tg_server_destroy(tg_server *s);
 
+/* The canonical edge list (the edge of each per-edge row): edge_uv (device
+ * int64 [nnz/2][2]) receives (u, v), u < v, in lexicographic order, the
+ * order of the rows of tg_count_typed_graphlets (the unique edge ids of the
+ * parallel scheme, Sec. 4.7).  For a graph that call accepts (sorted rows);
+ * TG_E_NOT_SIMPLE if the entries above the diagonal are not half of nnz
+ * (nothing is written then).  Workspace: tg_edge_list_workspace_bytes(n)
+ * bytes, 256-byte aligned.  Returns when the list is complete on `stream`. */
+size_t tg_edge_list_workspace_bytes(int64_t n);
+tg_status tg_edge_list(const int64_t *row_ptr, const int32_t *col, int64_t n, int64_t nnz,
+                       int64_t *edge_uv, void *workspace, size_t ws_bytes, void *stream);
+
 /* Sparse per-edge output (Sec. 4.6: an edge keeps only its nonzero typed
  * graphlet counts, with a lookup table from key to description, here
  * tg_key_describe).  Built from a dense per-edge table `rows` (device uint64

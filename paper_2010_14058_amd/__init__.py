@@ -214,6 +214,25 @@ def count_batch_async(plan: BatchPlan, out_globals, status, workspace, stream, *
                                status.data_ptr(), stream.cuda_stream)
 
 
+def edge_list(row_ptr, col, *, workspace: Workspace | None = None, stream=None):
+    """Canonical (u < v, lexicographic) edge list of a device CSR: an int64
+    tensor [nnz/2, 2], the edges of the per-edge rows in order."""
+    import torch
+
+    dev = row_ptr.device
+    n, nnz = row_ptr.numel() - 1, col.numel()
+    uv = torch.empty((nnz // 2, 2), dtype=torch.int64, device=dev)
+    ws = (workspace or Workspace(dev)).get(_lib.load().tg_edge_list_workspace_bytes(n))
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    rc = _lib.load().tg_edge_list(row_ptr.data_ptr(), col.data_ptr() if nnz else 0, n, nnz,
+                                  uv.data_ptr() if nnz else 0, ws.data_ptr(), ws.numel(),
+                                  stream.cuda_stream)
+    if rc:
+        raise _lib.TGError(rc, "tg_edge_list")
+    return uv
+
+
 def sparse_rows(rows, L: int, *, workspace: Workspace | None = None, stream=None):
     """Nonzero entries of a dense per-edge table (Sec. 4.6's sparse form).
 

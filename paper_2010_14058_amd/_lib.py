@@ -63,6 +63,9 @@ SIGNATURES = {
     "tg_last_stats": (_c.c_int32, [_c.POINTER(_c.c_int64), _c.c_int32]),
     "tg_set_tuning": (_c.c_int, [_c.c_int32, _c.c_int64]),
     "tg_last_error": (_c.c_char_p, []),
+    "tg_edge_list_workspace_bytes": (_c.c_size_t, [_c.c_int64]),
+    "tg_edge_list": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int64, _c.c_void_p,
+                                _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "tg_sparse_workspace_bytes": (_c.c_size_t, [_c.c_int64]),
     "tg_sparse_offsets": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int32, _c.c_void_p, _c.c_void_p,
                                      _c.c_size_t, _c.c_void_p]),

@@ -71,12 +71,77 @@ unsigned row_blocks(int64_t waves) {
 // Tile sums of the prefix sum over m + 1 entries.
 size_t scan_tmp_bytes(int64_t m) { return (size_t)(scan_tiles(m + 1) + 1) * sizeof(int64_t); }
 
+// Neighbours above the row's own id (rows sorted): its canonical edges.
+__global__ void k_upper_count(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                              int64_t n, int64_t *__restrict__ cnt) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u == 0) cnt[n] = 0;
+    if (u >= n) return;
+    cnt[u] = rp[u + 1] - upper_bound(col, rp[u], rp[u + 1], (int32_t)u);
+}
+
+// One wave per row: the row's canonical edges (u, x), x > u, at eoff[u] on.
+__global__ void k_edge_list(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                            int64_t n, const int64_t *__restrict__ eoff,
+                            int64_t *__restrict__ uv, const uint32_t *__restrict__ status) {
+    if (input_failed(status)) return;
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; u < n;
+         u += nwaves) {
+        const int64_t first = rp[u + 1] - (eoff[u + 1] - eoff[u]);
+        for (int64_t s = first + lane; s < rp[u + 1]; s += WAVE) {
+            const int64_t e = eoff[u] + (s - first);
+            uv[2 * e] = u;
+            uv[2 * e + 1] = col[s];
+        }
+    }
+}
+
+__global__ void k_edge_count_check(const int64_t *__restrict__ eoff, int64_t n, int64_t m,
+                                   uint32_t *__restrict__ status) {
+    *status = eoff[n] == m ? 0u : ST_EDGE_COUNT;
+}
+
 }  // namespace
 }  // namespace tg
 
 using namespace tg;
 
 extern "C" {
+
+size_t tg_edge_list_workspace_bytes(int64_t n) {
+    if (n < 0) return 0;
+    return 2 * (((size_t)(n + 2) * sizeof(int64_t) + 255) / 256 * 256) + scan_tmp_bytes(n + 1) +
+           256;
+}
+
+tg_status tg_edge_list(const int64_t *row_ptr, const int32_t *col, int64_t n, int64_t nnz,
+                       int64_t *edge_uv, void *workspace, size_t ws_bytes, void *stream) {
+    if (n < 0 || nnz < 0 || (nnz & 1) || (n > 0 && !row_ptr) || (nnz > 0 && (!col || !edge_uv)) ||
+        !workspace || ((uintptr_t)workspace & 255u))
+        return TG_E_INVALID_ARG;
+    if (ws_bytes < tg_edge_list_workspace_bytes(n)) return TG_E_WORKSPACE;
+    if (n == 0 || nnz == 0) return TG_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t arr = ((size_t)(n + 2) * sizeof(int64_t) + 255) / 256 * 256;
+    char *w = static_cast<char *>(workspace);
+    int64_t *cnt = reinterpret_cast<int64_t *>(w);
+    int64_t *eoff = reinterpret_cast<int64_t *>(w + arr);
+    uint32_t *status = reinterpret_cast<uint32_t *>(w + 2 * arr);
+    int64_t *tmp = reinterpret_cast<int64_t *>(w + 2 * arr + 256);
+    k_upper_count<<<(unsigned)((n + 256) / 256), 256, 0, st>>>(row_ptr, col, n, cnt);
+    if (hipGetLastError() != hipSuccess) return TG_E_DEVICE;
+    if (launch_excl_scan(cnt, eoff, n + 1, tmp, nullptr, st) != hipSuccess) return TG_E_DEVICE;
+    k_edge_count_check<<<1, 1, 0, st>>>(eoff, n, nnz / 2, status);
+    k_edge_list<<<row_blocks(n), 256, 0, st>>>(row_ptr, col, n, eoff, edge_uv, status);
+    if (hipGetLastError() != hipSuccess) return TG_E_DEVICE;
+    uint32_t bits = 0;
+    if (hipMemcpyAsync(&bits, status, sizeof(bits), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return TG_E_DEVICE;
+    return bits ? TG_E_NOT_SIMPLE : TG_OK;
+}
 
 size_t tg_sparse_workspace_bytes(int64_t m) {
     if (m < 0) return 0;

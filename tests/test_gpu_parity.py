@@ -297,3 +297,23 @@ def test_degree_buckets(oracle_mod, knobs):
             np.testing.assert_array_equal(got[plan.goff_host[q]:plan.goff_host[q + 1]], want)
     finally:
         P.set_tuning(**old)
+
+
+def test_edge_list():
+    """The canonical edge list is the order of the per-edge rows."""
+    import torch
+
+    import paper_2010_14058_amd as P
+
+    for g in (G.config_graph(1), G.config_graph(2, scale=0.005),
+              graph_from_edges(6, [(0, 5), (1, 2)], [0, 1, 0, 1, 0, 1], 2, "sparse")):
+        rp, col, _ = to_device(g)
+        uv = P.edge_list(rp, col)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(uv.cpu().numpy(), g.edges())
+    # more entries above the diagonal than half the adjacency: refused
+    rp = torch.tensor([0, 2, 2, 2], dtype=torch.int64, device="cuda")
+    col = torch.tensor([1, 2], dtype=torch.int32, device="cuda")
+    with pytest.raises(P.TGError) as e:
+        P.edge_list(rp, col)
+    assert e.value.code == 2
