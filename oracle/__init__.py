@@ -25,3 +25,8 @@ from .oracle import (  # noqa: F401
     pa_global_counts,
     pa_global_describe,
 )
+from .embedding import (  # noqa: F401
+    graphlet_edge_weights,
+    laplacian_spectrum,
+    embedding,
+)
