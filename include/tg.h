@@ -81,7 +81,8 @@ typedef enum tg_status {
     TG_E_TOO_LARGE = 8,   /* n or nnz beyond the supported range (see below) */
     TG_E_BATCH = 9,       /* batch descriptor inconsistent, or an edge joins two graphs */
     TG_E_OOM = 10,        /* the request can never fit the serving arena or a worker's region */
-    TG_E_TIMEOUT = 11     /* tg_server_wait: the request is not finished yet */
+    TG_E_TIMEOUT = 11,    /* tg_server_wait: the request is not finished yet */
+    TG_E_NO_CONVERGENCE = 12 /* tg_graphlet_embedding: iteration limit reached */
 } tg_status;
 
 /* Human-readable name of a status code (static string). */
@@ -289,6 +290,72 @@ tg_status tg_server_destroy(tg_server *s);
 size_t tg_edge_list_workspace_bytes(int64_t n);
 tg_status tg_edge_list(const int64_t *row_ptr, const int32_t *col, int64_t n, int64_t nnz,
                        int64_t *edge_uv, void *workspace, size_t ws_bytes, void *stream);
+
+/* Typed-graphlet spectral embeddings (Alg. 5), in two calls.
+ *
+ * tg_graphlet_weights: W_e, the number of instances of one typed graphlet
+ * that contain edge e, for every edge, read off the per-edge rows: the
+ * graphlet's orbits (Sec. 4.4: h1 path3; h2 tri; h3 g3+g4; h4 g5; h5 g6;
+ * h6 g7+g8+g9; h7 g10+g11; h8 g12) at the type (pair) that completes the
+ * edge's endpoint types to the graphlet's type multiset; 0 where the
+ * endpoint types are not part of it (h0, the edge itself: 1 or 0).
+ *   per_edge      device uint64 [m][tg_row_width(L)] (tg_count_typed_graphlets)
+ *   edge_uv       device int64 [m][2] (tg_edge_list): the edge of each row
+ *   types         device uint8 [n]
+ *   graphlet      0..8 (h0..h8); types_sorted (host int32 [4]) its sorted
+ *                 type multiset, 2, 3 or 4 entries as the graphlet has nodes
+ *   weights       device uint64 [m], written
+ * TG_E_L_RANGE, TG_E_INVALID_ARG (m < 0, graphlet out of range, missing
+ * pointers), TG_E_TYPE_RANGE (multiset entries unsorted or outside [0, L)),
+ * TG_E_DEVICE.  Returns when the weights are complete on `stream`.
+ *
+ * tg_graphlet_embedding: with D_ii = sum_j W_ij the typed-graphlet degree,
+ * the eigenvectors of the `dim` smallest eigenvalues of the normalised
+ * Laplacian I - D^{-1/2} W D^{-1/2}, each row scaled to unit length.
+ * Nodes with D_ii = 0 are in no instance: their rows are zero and they do
+ * not take part in the Laplacian (a graph whose weighted edges form c
+ * components has eigenvalue 0 c times).  Eigenvectors of a repeated
+ * eigenvalue are any orthonormal basis of its eigenspace; signs are
+ * arbitrary.
+ *   row_ptr, col  the graph (device CSR as for tg_count_typed_graphlets:
+ *                 sorted rows, symmetric, no self-loops; TG_E_NOT_SIMPLE
+ *                 otherwise)
+ *   weights       device uint64 [nnz/2], per canonical edge (the order of
+ *                 tg_edge_list)
+ *   dim           1..256
+ *   opts          NULL for the defaults, else read (see tg_embed_opts)
+ *   Z             device float64 [n][dim], written; with a active nodes
+ *                 (D_ii > 0), columns min(dim, a) and up are zero
+ *   eigenvalues   device float64 [dim] or NULL: the eigenvalues of the
+ *                 columns, ascending; entries min(dim, a) and up are 0
+ *   iterations    host int32 or NULL: filter iterations run
+ *   workspace     tg_embedding_workspace_bytes(n, nnz, dim) bytes, device,
+ *                 256-byte aligned, caller-owned
+ * Method: Chebyshev-filtered subspace iteration on (S + I) / 2, S = D^{-1/2}
+ * W D^{-1/2}, with a block of p = dim + max(8, dim / 4) vectors (at most
+ * 256 and at most a), in float64; it stops when every wanted Ritz pair has
+ * residual norm ||M x - theta x|| <= tol.  TG_E_NO_CONVERGENCE after
+ * max_iter iterations (Z and eigenvalues then hold the last Ritz pairs).
+ * Deterministic: the same inputs and seed give the same bits.  Returns
+ * when the results are complete on `stream` (it synchronises the stream
+ * once per iteration). */
+typedef struct tg_embed_opts {
+    int32_t max_iter;   /* iteration limit (<= 0: 500) */
+    int32_t degree;     /* Chebyshev filter degree (<= 0: 10) */
+    double tol;         /* residual tolerance (<= 0: 1e-10) */
+    uint64_t seed;      /* seed of the random start block */
+    int32_t raw;        /* nonzero: Z receives the eigenvectors themselves
+                           (orthonormal columns), rows not rescaled */
+    int32_t reserved;   /* set to 0 */
+} tg_embed_opts;
+tg_status tg_graphlet_weights(const uint64_t *per_edge, int64_t m, int32_t L,
+                              const int64_t *edge_uv, const uint8_t *types, int32_t graphlet,
+                              const int32_t types_sorted[4], uint64_t *weights, void *stream);
+size_t tg_embedding_workspace_bytes(int64_t n, int64_t nnz, int32_t dim);
+tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int64_t n, int64_t nnz,
+                                const uint64_t *weights, int32_t dim, const tg_embed_opts *opts,
+                                double *Z, double *eigenvalues, int32_t *iterations,
+                                void *workspace, size_t ws_bytes, void *stream);
 
 /* Sparse per-edge output (Sec. 4.6: an edge keeps only its nonzero typed
  * graphlet counts, with a lookup table from key to description, here

@@ -7,6 +7,8 @@ PyTorch only supplies device memory and the stream.
 
 from __future__ import annotations
 
+import ctypes
+
 from . import _lib
 from ._lib import (  # noqa: F401
     TGError,
@@ -26,6 +28,8 @@ from ._lib import (  # noqa: F401
     set_tuning,
     workspace_bytes,
 )
+
+NO_CONVERGENCE = 12  # tg_status TG_E_NO_CONVERGENCE
 
 
 class Workspace:
@@ -231,6 +235,62 @@ def edge_list(row_ptr, col, *, workspace: Workspace | None = None, stream=None):
     if rc:
         raise _lib.TGError(rc, "tg_edge_list")
     return uv
+
+
+def graphlet_weights(rows, edge_uv, types, L: int, graphlet: int, types_sorted, *, stream=None):
+    """W_e of Alg. 5 for every edge: the instances of the typed graphlet
+    (graphlet id 0..8, sorted type multiset) that contain it, read off the
+    per-edge rows (``count_typed_graphlets``) with ``edge_list``'s edges.
+    Returns a device int64 tensor [m] holding uint64 counts."""
+    import torch
+
+    dev = rows.device
+    rows = rows.contiguous()
+    m = rows.shape[0]
+    if rows.dim() != 2 or rows.shape[1] != row_width(L) or tuple(edge_uv.shape) != (m, 2):
+        raise ValueError("rows must be [m, row_width(L)] and edge_uv [m, 2]")
+    ms = (ctypes.c_int32 * 4)(*([int(t) for t in types_sorted] + [0] * (4 - len(types_sorted))))
+    w = torch.empty(m, dtype=torch.int64, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    rc = _lib.load().tg_graphlet_weights(rows.data_ptr() if m else 0, m, L,
+                                         edge_uv.contiguous().data_ptr() if m else 0,
+                                         types.data_ptr() if m else 0, graphlet, ms,
+                                         w.data_ptr() if m else 0, stream.cuda_stream)
+    if rc:
+        raise _lib.TGError(rc, "tg_graphlet_weights")
+    return w
+
+
+def graphlet_embedding(row_ptr, col, weights, dim: int, *, max_iter: int = 0, degree: int = 0,
+                       tol: float = 0.0, seed: int = 0, raw: bool = False,
+                       workspace: Workspace | None = None, stream=None, check: bool = True):
+    """Alg. 5's embedding of a device CSR graph with per-edge weights
+    (canonical edge order): ``(Z float64 [n, dim], eigenvalues float64
+    [dim], iterations)``.  Defaults of 0 take the library's (500
+    iterations, degree 10, tolerance 1e-10).  With ``raw`` Z holds the
+    eigenvectors themselves (orthonormal columns) instead of Alg. 5's
+    unit-length rows.  With ``check`` a non-converged solve raises; else the
+    last Ritz pairs are returned."""
+    import torch
+
+    dev = row_ptr.device
+    n, nnz = row_ptr.numel() - 1, col.numel()
+    Z = torch.empty((n, dim), dtype=torch.float64, device=dev)
+    ev = torch.empty(dim, dtype=torch.float64, device=dev)
+    lib = _lib.load()
+    ws = (workspace or Workspace(dev)).get(lib.tg_embedding_workspace_bytes(n, nnz, dim))
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    opts = _lib.EmbedOpts(max_iter, degree, tol, seed, int(raw), 0)
+    its = ctypes.c_int32(0)
+    rc = lib.tg_graphlet_embedding(row_ptr.data_ptr(), col.data_ptr() if nnz else 0, n, nnz,
+                                   weights.data_ptr() if nnz else 0, dim, ctypes.byref(opts),
+                                   Z.data_ptr(), ev.data_ptr(), ctypes.byref(its), ws.data_ptr(),
+                                   ws.numel(), stream.cuda_stream)
+    if rc and (check or rc != NO_CONVERGENCE):
+        raise _lib.TGError(rc, "tg_graphlet_embedding")
+    return Z, ev, int(its.value)
 
 
 def sparse_rows(rows, L: int, *, workspace: Workspace | None = None, stream=None):

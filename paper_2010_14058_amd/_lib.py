@@ -33,6 +33,13 @@ class RequestInfo(ctypes.Structure):
                 ("t_done", ctypes.c_double), ("batch", ctypes.c_int64)]
 
 
+class EmbedOpts(ctypes.Structure):
+    """tg_embed_opts"""
+    _fields_ = [("max_iter", ctypes.c_int32), ("degree", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("raw", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 SIGNATURES = {
     "tg_status_str": (_c.c_char_p, [_c.c_int]),
     "tg_row_width": (_c.c_int32, [_c.c_int32]),
@@ -91,6 +98,14 @@ SIGNATURES = {
                                       _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
     "tg_pa_global_key_describe": (_c.c_int, [_c.c_int32, _c.c_int64, _c.POINTER(_c.c_int32),
                                              _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
+    "tg_graphlet_weights": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int32, _c.c_void_p,
+                                       _c.c_void_p, _c.c_int32, _c.POINTER(_c.c_int32),
+                                       _c.c_void_p, _c.c_void_p]),
+    "tg_embedding_workspace_bytes": (_c.c_size_t, [_c.c_int64, _c.c_int64, _c.c_int32]),
+    "tg_graphlet_embedding": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int64,
+                                         _c.c_void_p, _c.c_int32, _c.POINTER(EmbedOpts),
+                                         _c.c_void_p, _c.c_void_p, _c.POINTER(_c.c_int32),
+                                         _c.c_void_p, _c.c_size_t, _c.c_void_p]),
 }
 
 _lib = None

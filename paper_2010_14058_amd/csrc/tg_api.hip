@@ -622,6 +622,7 @@ const char *tg_status_str(tg_status s) {
         case TG_E_BATCH: return "inconsistent batch descriptor or an edge between two graphs";
         case TG_E_OOM: return "request does not fit the serving memory";
         case TG_E_TIMEOUT: return "request not finished";
+        case TG_E_NO_CONVERGENCE: return "eigensolver did not converge";
     }
     return "unknown status";
 }

@@ -196,3 +196,39 @@ def test_pa_widths_all_L():
         assert L.pa_global_width(nt) == sum(classes)
         assert L.pa_row_width(nt) == 3 * nt + 9 * nt * nt + 6 * P
     assert L.pa_row_width(0) == 0 and L.pa_global_width(17) == 0
+
+
+def test_embedding_argument_checks():
+    """Argument errors of the embedding calls, all caught before any device
+    work."""
+    import ctypes
+
+    import paper_2010_14058_amd as P
+
+    lib = P._lib.load()
+    ms = (ctypes.c_int32 * 4)(0, 0, 0, 0)
+    assert lib.tg_graphlet_weights(None, 0, 0, None, None, 0, ms, None, None) == 4  # L range
+    assert lib.tg_graphlet_weights(None, 0, 2, None, None, 9, ms, None, None) == 1  # graphlet
+    assert lib.tg_graphlet_weights(None, -1, 2, None, None, 0, ms, None, None) == 1
+    bad = (ctypes.c_int32 * 4)(1, 0, 0, 0)
+    assert lib.tg_graphlet_weights(None, 0, 2, None, None, 0, bad, None, None) == 3  # unsorted
+    big = (ctypes.c_int32 * 4)(0, 2, 0, 0)
+    assert lib.tg_graphlet_weights(None, 0, 2, None, None, 0, big, None, None) == 3  # type >= L
+    assert lib.tg_graphlet_weights(None, 0, 2, None, None, 2, ms, None, None) == 0  # m = 0
+    assert lib.tg_embedding_workspace_bytes(10, 20, 0) == 0
+    assert lib.tg_embedding_workspace_bytes(10, 20, 257) == 0
+    ws = lib.tg_embedding_workspace_bytes(1000, 8000, 16)
+    assert ws > 1000 * 24 * 8 * 5
+    opts = P._lib.EmbedOpts(0, 0, 0.0, 0, 0, 0)
+    its = ctypes.c_int32(0)
+    fake = 1 << 20  # never dereferenced: every call below fails its checks first
+    call = lambda n, nnz, dim, wsp, wsb: lib.tg_graphlet_embedding(
+        fake, fake, n, nnz, fake, dim, ctypes.byref(opts), fake, None, ctypes.byref(its), wsp,
+        wsb, None)
+    assert call(1000, 8000, 0, fake, ws) == 1      # dim
+    assert call(1000, 8000, 257, fake, ws) == 1
+    assert call(1000, 8001, 16, fake, ws) == 1     # odd nnz
+    assert call(0, 0, 16, fake, ws) == 1           # n < 1
+    assert call(1000, 8000, 16, fake + 8, ws) == 1  # unaligned workspace
+    assert call(1000, 8000, 16, fake, ws - 1) == 5  # workspace too small
+    assert call(1 << 31, 8000, 16, fake, ws) == 8   # too large
