@@ -27,6 +27,7 @@ from .oracle import (  # noqa: F401
 )
 from .embedding import (  # noqa: F401
     graphlet_edge_weights,
+    components,
     laplacian_spectrum,
     embedding,
 )

@@ -110,7 +110,9 @@ def test_invariants(oracle_mod):
     rows = oracle_mod.all_edge_rows(g)
     w = oracle_mod.graphlet_edge_weights(g, rows, 1, (0, 1, 2))   # typed 3-paths {0,1,2}
     assert w.sum() > 0
-    vals, vecs, act = oracle_mod.laplacian_spectrum(g, w)
+    vals, vecs, nodes = oracle_mod.laplacian_spectrum(g, w)
+    act = np.zeros(g.n, dtype=bool)
+    act[nodes] = True
     assert vals[0] > -1e-12 and vals[-1] < 2 + 1e-12
     # scaling W does not change L
     vals3, _, _ = oracle_mod.laplacian_spectrum(g, w * np.uint64(3))
@@ -126,7 +128,44 @@ def test_invariants(oracle_mod):
     u0 = U[:, 0] * np.sign(U[0, 0])
     np.testing.assert_allclose(u0, np.sqrt(deg) / np.linalg.norm(np.sqrt(deg)), atol=1e-10)
     # embedding rows: unit length where the node is in an instance, else zero
-    _, Z = oracle_mod.embedding(g, w, 6)
+    _, Z, comp = oracle_mod.embedding(g, w, 6)
     norms = np.sqrt((Z * Z).sum(axis=1))
     np.testing.assert_allclose(norms[act], 1.0, atol=1e-12)
     assert not norms[~act].any()
+    np.testing.assert_array_equal(comp >= 0, act)
+
+
+def test_per_component(oracle_mod):
+    """Sec. 8.8: one embedding per component of G^H.  A triangle, a single
+    edge, a 3-path and a 5-cycle (nodes shuffled), an isolated node, and a
+    zero-weight edge joining the triangle to the cycle: each component has
+    its own closed-form spectrum, a component of s <= D nodes gets all its s
+    eigenvectors (so its rows of Z are orthonormal), and the zero-weight
+    edge is in no component."""
+    perm = np.random.default_rng(3).permutation(15)
+    groups = {"tri": [0, 1, 2], "edge": [3, 4], "path": [5, 6, 7], "cyc": [8, 9, 10, 11, 12]}
+    edges = [(0, 1), (1, 2), (0, 2), (3, 4), (5, 6), (6, 7),
+             (8, 9), (9, 10), (10, 11), (11, 12), (8, 12), (2, 8)]
+    pe = sorted(tuple(sorted((int(perm[a]), int(perm[b])))) for a, b in edges)
+    g = _graph(15, pe, [0] * 15, 1)
+    zero = tuple(sorted((int(perm[2]), int(perm[8]))))
+    w = np.array([0 if tuple(e) == zero else 1 for e in g.edges().tolist()], dtype=np.uint64)
+    ev, Z, comp = oracle_mod.embedding(g, w, 4)
+    want = {"tri": [0, 1.5, 1.5], "edge": [0, 2], "path": [0, 1, 2],
+            "cyc": list(np.sort(1 - np.cos(2 * np.pi * np.arange(5) / 5))[:4])}
+    for name, ids in groups.items():
+        nodes = perm[ids]
+        r = int(nodes.min())
+        assert set(comp[nodes].tolist()) == {r}
+        k = len(want[name])
+        np.testing.assert_allclose(ev[r, :k], want[name], atol=1e-12)
+        assert not ev[r, k:].any()
+        Zc = Z[nodes]
+        if len(ids) <= 4:
+            np.testing.assert_allclose(Zc @ Zc.T, np.eye(len(ids)), atol=1e-12)
+            assert not Zc[:, len(ids):].any()
+    for x in perm[[13, 14]]:
+        assert comp[x] == -1 and not Z[x].any()
+    # rows of ev that name no component are zero
+    roots = {int(perm[ids].min()) for ids in groups.values()}
+    assert not ev[[i for i in range(15) if i not in roots]].any()
