@@ -309,14 +309,15 @@ tg_status tg_edge_list(const int64_t *row_ptr, const int32_t *col, int64_t n, in
  * pointers), TG_E_TYPE_RANGE (multiset entries unsorted or outside [0, L)),
  * TG_E_DEVICE.  Returns when the weights are complete on `stream`.
  *
- * tg_graphlet_embedding: with D_ii = sum_j W_ij the typed-graphlet degree,
- * the eigenvectors of the `dim` smallest eigenvalues of the normalised
- * Laplacian I - D^{-1/2} W D^{-1/2}, each row scaled to unit length.
- * Nodes with D_ii = 0 are in no instance: their rows are zero and they do
- * not take part in the Laplacian (a graph whose weighted edges form c
- * components has eigenvalue 0 c times).  Eigenvectors of a repeated
- * eigenvalue are any orthonormal basis of its eigenspace; signs are
- * arbitrary.
+ * tg_graphlet_embedding: Alg. 5 on every connected component of the
+ * typed-graphlet graph G^H (the edges with W > 0), as Sec. 8.8 prescribes
+ * for graphs with several components.  For a component C of s nodes, with
+ * D_ii = sum_j W_ij the typed-graphlet degree, its nodes' rows of Z are the
+ * eigenvectors of the min(dim, s) smallest eigenvalues of C's normalised
+ * Laplacian I - D^{-1/2} W D^{-1/2}, each row scaled to unit length, zero
+ * past column min(dim, s).  Nodes with D_ii = 0 are in no instance and no
+ * component: zero rows.  Eigenvectors of a repeated eigenvalue are any
+ * orthonormal basis of its eigenspace; signs are arbitrary.
  *   row_ptr, col  the graph (device CSR as for tg_count_typed_graphlets:
  *                 sorted rows, symmetric, no self-loops; TG_E_NOT_SIMPLE
  *                 otherwise)
@@ -324,21 +325,26 @@ tg_status tg_edge_list(const int64_t *row_ptr, const int32_t *col, int64_t n, in
  *                 tg_edge_list)
  *   dim           1..256
  *   opts          NULL for the defaults, else read (see tg_embed_opts)
- *   Z             device float64 [n][dim], written; with a active nodes
- *                 (D_ii > 0), columns min(dim, a) and up are zero
- *   eigenvalues   device float64 [dim] or NULL: the eigenvalues of the
- *                 columns, ascending; entries min(dim, a) and up are 0
- *   iterations    host int32 or NULL: filter iterations run
+ *   Z             device float64 [n][dim], written
+ *   eigenvalues   device float64 [n][dim] or NULL: row r holds, ascending,
+ *                 the min(dim, s) eigenvalues of the component whose
+ *                 smallest node id is r; every other entry is 0
+ *   component     device int32 [n] or NULL: the smallest node id of each
+ *                 node's component, -1 for nodes in none
+ *   iterations    host int32 or NULL: the most filter iterations any one
+ *                 component took (0 when every component was solved densely)
  *   workspace     tg_embedding_workspace_bytes(n, nnz, dim) bytes, device,
  *                 256-byte aligned, caller-owned
- * Method: Chebyshev-filtered subspace iteration on (S + I) / 2, S = D^{-1/2}
- * W D^{-1/2}, with a block of p = dim + max(8, dim / 4) vectors (at most
- * 256 and at most a), in float64; it stops when every wanted Ritz pair has
- * residual norm ||M x - theta x|| <= tol.  TG_E_NO_CONVERGENCE after
- * max_iter iterations (Z and eigenvalues then hold the last Ritz pairs).
- * Deterministic: the same inputs and seed give the same bits.  Returns
- * when the results are complete on `stream` (it synchronises the stream
- * once per iteration). */
+ * Method: components by hook-and-compress; those of at most 64 nodes by a
+ * dense Jacobi eigensolver, one workgroup each; larger ones by
+ * Chebyshev-filtered subspace iteration on (S + I) / 2, S = D^{-1/2} W
+ * D^{-1/2}, with a block of p = dim + max(8, dim / 4) vectors (at most 256
+ * and at most s), in float64, until every wanted Ritz pair has residual
+ * norm ||M x - theta x|| <= tol.  TG_E_NO_CONVERGENCE when some component
+ * reached max_iter (its rows then hold its last Ritz vectors).
+ * Deterministic: the same inputs and seed give the same bits.  Returns when
+ * the results are complete on `stream` (the call synchronises the stream
+ * several times). */
 typedef struct tg_embed_opts {
     int32_t max_iter;   /* iteration limit (<= 0: 500) */
     int32_t degree;     /* Chebyshev filter degree (<= 0: 10) */
@@ -354,8 +360,9 @@ tg_status tg_graphlet_weights(const uint64_t *per_edge, int64_t m, int32_t L,
 size_t tg_embedding_workspace_bytes(int64_t n, int64_t nnz, int32_t dim);
 tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int64_t n, int64_t nnz,
                                 const uint64_t *weights, int32_t dim, const tg_embed_opts *opts,
-                                double *Z, double *eigenvalues, int32_t *iterations,
-                                void *workspace, size_t ws_bytes, void *stream);
+                                double *Z, double *eigenvalues, int32_t *component,
+                                int32_t *iterations, void *workspace, size_t ws_bytes,
+                                void *stream);
 
 /* Sparse per-edge output (Sec. 4.6: an edge keeps only its nonzero typed
  * graphlet counts, with a lookup table from key to description, here

@@ -265,19 +265,23 @@ def graphlet_weights(rows, edge_uv, types, L: int, graphlet: int, types_sorted, 
 def graphlet_embedding(row_ptr, col, weights, dim: int, *, max_iter: int = 0, degree: int = 0,
                        tol: float = 0.0, seed: int = 0, raw: bool = False,
                        workspace: Workspace | None = None, stream=None, check: bool = True):
-    """Alg. 5's embedding of a device CSR graph with per-edge weights
-    (canonical edge order): ``(Z float64 [n, dim], eigenvalues float64
-    [dim], iterations)``.  Defaults of 0 take the library's (500
+    """Alg. 5's embedding, per connected component of the typed-graphlet
+    graph (Sec. 8.8), of a device CSR graph with per-edge weights (canonical
+    edge order): ``(Z float64 [n, dim], eigenvalues float64 [n, dim],
+    component int32 [n], iterations)``.  Row r of eigenvalues holds the
+    spectrum of the component whose smallest node id is r; component is -1
+    for nodes in no instance.  Defaults of 0 take the library's (500
     iterations, degree 10, tolerance 1e-10).  With ``raw`` Z holds the
-    eigenvectors themselves (orthonormal columns) instead of Alg. 5's
-    unit-length rows.  With ``check`` a non-converged solve raises; else the
-    last Ritz pairs are returned."""
+    eigenvectors themselves instead of Alg. 5's unit-length rows.  With
+    ``check`` a non-converged solve raises; else the last Ritz pairs are
+    returned."""
     import torch
 
     dev = row_ptr.device
     n, nnz = row_ptr.numel() - 1, col.numel()
     Z = torch.empty((n, dim), dtype=torch.float64, device=dev)
-    ev = torch.empty(dim, dtype=torch.float64, device=dev)
+    ev = torch.empty((n, dim), dtype=torch.float64, device=dev)
+    comp = torch.empty(n, dtype=torch.int32, device=dev)
     lib = _lib.load()
     ws = (workspace or Workspace(dev)).get(lib.tg_embedding_workspace_bytes(n, nnz, dim))
     if stream is None:
@@ -286,11 +290,12 @@ def graphlet_embedding(row_ptr, col, weights, dim: int, *, max_iter: int = 0, de
     its = ctypes.c_int32(0)
     rc = lib.tg_graphlet_embedding(row_ptr.data_ptr(), col.data_ptr() if nnz else 0, n, nnz,
                                    weights.data_ptr() if nnz else 0, dim, ctypes.byref(opts),
-                                   Z.data_ptr(), ev.data_ptr(), ctypes.byref(its), ws.data_ptr(),
-                                   ws.numel(), stream.cuda_stream)
+                                   Z.data_ptr(), ev.data_ptr(), comp.data_ptr(),
+                                   ctypes.byref(its), ws.data_ptr(), ws.numel(),
+                                   stream.cuda_stream)
     if rc and (check or rc != NO_CONVERGENCE):
         raise _lib.TGError(rc, "tg_graphlet_embedding")
-    return Z, ev, int(its.value)
+    return Z, ev, comp, int(its.value)
 
 
 def sparse_rows(rows, L: int, *, workspace: Workspace | None = None, stream=None):

@@ -104,8 +104,9 @@ SIGNATURES = {
     "tg_embedding_workspace_bytes": (_c.c_size_t, [_c.c_int64, _c.c_int64, _c.c_int32]),
     "tg_graphlet_embedding": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int64,
                                          _c.c_void_p, _c.c_int32, _c.POINTER(EmbedOpts),
-                                         _c.c_void_p, _c.c_void_p, _c.POINTER(_c.c_int32),
-                                         _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+                                         _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                         _c.POINTER(_c.c_int32), _c.c_void_p, _c.c_size_t,
+                                         _c.c_void_p]),
 }
 
 _lib = None

@@ -1,23 +1,32 @@
 // Typed-graphlet spectral node embeddings (Alg. 5).  For a typed graphlet
 // H, each edge weighs the number of instances of H that contain it
-// (`k_graphlet_weights`, read off the per-edge typed rows); the embedding is
-// the eigenvectors of the dim smallest eigenvalues of the normalised
-// Laplacian L = I - D^{-1/2} W D^{-1/2}, rows scaled to unit length.
+// (`k_graphlet_weights`, read off the per-edge typed rows).  Sec. 8.8 runs
+// the algorithm on every connected component of the typed-graphlet graph
+// G^H (the edges of nonzero weight): a component's embedding is the
+// eigenvectors of the dim smallest eigenvalues of its normalised Laplacian
+// L = I - D^{-1/2} W D^{-1/2}, rows scaled to unit length.
 //
-// The eigenvectors are those of the largest eigenvalues of M = (S + I) / 2,
-// S = D^{-1/2} W D^{-1/2}, whose spectrum lies in [0, 1]; they are found by
-// Chebyshev-filtered subspace iteration on a block of p = dim + oversample
-// vectors: each iteration filters the block with a Chebyshev polynomial of M
-// that damps [0, b] (b the smallest Ritz value so far) and keeps the top of
-// the spectrum, orthonormalises it (eigen-decomposition of its Gram matrix),
-// and takes Ritz vectors (eigen-decomposition of its projection of M), until
-// the dim wanted residuals ||M x - theta x|| fall below the tolerance.  All
-// of it runs in this file's kernels: a weighted SpMM over the CSR (one wave
-// per row, the block stored row-major so a neighbour's row is one coalesced
-// read), tiled tall-skinny Gram products with a fixed-order reduction, and
-// a one-workgroup cyclic Jacobi eigensolver for the p x p matrices.
-// Nodes of zero weighted degree are in no instance of H: their rows of S
-// are zero and their embedding rows stay zero.
+// Components come from a hook-and-compress pass (each root hooks onto the
+// smaller root of an edge's other end, so every component ends up named by
+// its smallest node id), then a stable sort of the nodes by component.
+// Components of at most DENSE_MAX nodes -- on power-law inputs nearly all
+// but the giant one -- are solved together, one workgroup each: the dense
+// S = D^{-1/2} W D^{-1/2} of the component in LDS and a cyclic Jacobi
+// eigensolver.  A larger component runs Chebyshev-filtered subspace
+// iteration on M = (S + I) / 2 (spectrum in [0, 1]; its largest
+// eigenvalues are the wanted ones) with a block of p = dim + oversample
+// vectors: each iteration filters the block with a Chebyshev polynomial
+// of M that damps [0, b] (b the block's smallest Ritz value) and keeps the
+// top of the spectrum, orthonormalises it (eigen-decomposition of its Gram
+// matrix, twice), and takes Ritz vectors (eigen-decomposition of its
+// projection of M), until the dim wanted residuals ||M x - theta x|| fall
+// below the tolerance.  All of it runs in this file's kernels: a weighted
+// SpMM over the CSR restricted to the component (one wave per row, the
+// block stored row-major so a neighbour's row is one coalesced read),
+// tiled tall-skinny Gram products with a fixed-order reduction, and a
+// one-workgroup Jacobi eigensolver for the p x p matrices.  Nodes of zero
+// weighted degree are in no instance of H and no component: their rows
+// stay zero.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -30,6 +39,7 @@ namespace tg {
 namespace {
 
 constexpr int EMB_MAX_P = 256;     // largest block (dim + oversample)
+constexpr int DENSE_MAX = 64;      // largest component solved densely in LDS
 constexpr int GRAM_ROWS = 2048;    // rows per Gram partial
 constexpr int GRAM_TILE = 32;
 
@@ -151,6 +161,96 @@ __global__ void k_emb_edge_check(const int64_t *__restrict__ eoff, int64_t n, in
     if (eoff[n] != m) *status |= ST_EDGE_COUNT;
 }
 
+// --------------------------------------------------- components of G^H
+
+__device__ __forceinline__ int32_t cc_find(const int32_t *parent, int32_t r) {
+    // parents only ever decrease, so the walk ends
+    for (;;) {
+        const int32_t q = __hip_atomic_load(parent + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (q == r) return r;
+        r = q;
+    }
+}
+
+__global__ void k_cc_init(int32_t *__restrict__ parent, int64_t n) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n) parent[u] = (int32_t)u;
+}
+
+// Every edge of nonzero weight whose ends have different roots hooks the
+// larger root onto the smaller one; *changed records that some did.  One
+// wave per row, lanes over its slots (each edge from its smaller end).
+__global__ void k_cc_hook(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                          const double *__restrict__ wslot, int64_t n, int32_t *parent,
+                          uint32_t *__restrict__ changed) {
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; u < n;
+         u += nwaves) {
+        uint32_t hooked = 0;
+        for (int64_t s = rp[u + 1] - 1 - lane; s >= rp[u]; s -= WAVE) {
+            const int32_t x = col[s];
+            if (x <= u) break;                       // the rest of the row is below u
+            if (wslot[s] == 0.0) continue;
+            const int32_t a = cc_find(parent, (int32_t)u), b = cc_find(parent, x);
+            if (a != b) {
+                atomicMin(parent + (a > b ? a : b), a < b ? a : b);
+                hooked = 1;
+            }
+        }
+        hooked = wave_or(hooked);
+        if (lane == 0 && hooked) atomicOr(changed, 1u);
+    }
+}
+
+__global__ void k_cc_compress(int32_t *parent, int64_t n) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n) parent[u] = cc_find(parent, (int32_t)u);
+}
+
+constexpr uint64_t CC_NONE = 0xFFFFFFFFull;   // sort key of a node in no component
+
+// Sort keys: a node's component (its root), or CC_NONE; values: node ids.
+// Also the per-node outputs that need no solve: component ids (-1 outside
+// every component) and zero embedding rows outside every component.
+__global__ void k_cc_keys(const int32_t *__restrict__ parent, const uint64_t *__restrict__ deg,
+                          int64_t n, int dim, uint64_t *__restrict__ keys,
+                          uint32_t *__restrict__ ids, int32_t *__restrict__ comp,
+                          double *__restrict__ Z) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    const bool act = deg[u] > 0;
+    keys[u] = act ? (uint64_t)parent[u] : CC_NONE;
+    ids[u] = (uint32_t)u;
+    if (comp) comp[u] = act ? parent[u] : -1;
+    if (!act)
+        for (int j = 0; j < dim; ++j) Z[(size_t)u * dim + j] = 0.0;
+}
+
+// flag[i] = 1 where sorted position i starts a component (flag[n] = 0).
+__global__ void k_cc_flags(const uint64_t *__restrict__ key, int64_t n, int64_t *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    flag[i] = (i < n && key[i] != CC_NONE && (i == 0 || key[i] != key[i - 1])) ? 1 : 0;
+}
+
+// seg_start[c] = first sorted position of component c (seg_start[#c] =
+// nact); loc[u] = u's position inside its component.  segx is the
+// exclusive scan of the flags: position i is in component segx[i+1] - 1.
+__global__ void k_cc_segments(const int64_t *__restrict__ flag, const int64_t *__restrict__ segx,
+                              int64_t n, int64_t nact, int64_t *__restrict__ seg_start) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) seg_start[segx[n]] = nact;
+    if (i < nact && flag[i]) seg_start[segx[i]] = i;
+}
+
+__global__ void k_cc_loc(const int64_t *__restrict__ segx, const int64_t *__restrict__ seg_start,
+                         const uint32_t *__restrict__ order, int64_t nact,
+                         int32_t *__restrict__ loc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nact) loc[order[i]] = (int32_t)(i - seg_start[segx[i + 1] - 1]);
+}
+
 // ------------------------------------------------------------- blocks
 
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
@@ -161,39 +261,39 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
-// Random start block in [-1, 1), zero on rows of degree 0.
-__global__ void k_emb_random(double *__restrict__ X, int64_t n, int p, uint64_t seed,
-                             const double *__restrict__ sc) {
+// Random start block in [-1, 1) (s rows of a component, counter-based).
+__global__ void k_emb_random(double *__restrict__ X, int64_t s, int p, uint64_t seed) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n * p) return;
-    const int64_t u = q / p;
+    if (q >= s * p) return;
     const uint64_t r = mix64(seed ^ mix64((uint64_t)q));
-    const double v = (double)(r >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
-    X[q] = sc[u] > 0 ? v : 0.0;
+    X[q] = (double)(r >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
 }
 
-// out = alpha * (S X) + beta * X + gamma * Z, S = D^{-1/2} W D^{-1/2};
-// one wave per row, each lane a set of the p columns.
+// out = alpha * (S X) + beta * X + gamma * Z, S = D^{-1/2} W D^{-1/2}
+// restricted to one component: local row r is node nodes[r], a neighbour x
+// is local row loc[x].  One wave per row, each lane a set of the p columns.
 __global__ void __launch_bounds__(256)
 k_emb_spmm(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
-           const double *__restrict__ wslot, const double *__restrict__ sc, int64_t n, int p,
+           const double *__restrict__ wslot, const double *__restrict__ sc,
+           const uint32_t *__restrict__ nodes, const int32_t *__restrict__ loc, int64_t n, int p,
            const double *__restrict__ X, const double *__restrict__ Z, double alpha, double beta,
            double gamma, double *__restrict__ out) {
     constexpr int CPL = EMB_MAX_P / WAVE;   // columns per lane
     const int lane = lane_id();
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
-    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; u < n;
-         u += nwaves) {
+    for (int64_t r = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; r < n;
+         r += nwaves) {
+        const int64_t u = nodes[r];
         double acc[CPL];
 #pragma unroll
         for (int c = 0; c < CPL; ++c) acc[c] = 0.0;
         const double su = sc[u];
-        if (su > 0) {
+        {
             for (int64_t s = rp[u]; s < rp[u + 1]; ++s) {
                 const int32_t x = col[s];
                 const double coef = wslot[s] * sc[x];
                 if (coef == 0.0) continue;
-                const double *xr = X + (size_t)x * p;
+                const double *xr = X + (size_t)loc[x] * p;
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) {
                     const int j = lane + c * WAVE;
@@ -201,9 +301,9 @@ k_emb_spmm(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
                 }
             }
         }
-        const double *xu = X + (size_t)u * p;
-        const double *zu = Z ? Z + (size_t)u * p : nullptr;
-        double *ou = out + (size_t)u * p;
+        const double *xu = X + (size_t)r * p;
+        const double *zu = Z ? Z + (size_t)r * p : nullptr;
+        double *ou = out + (size_t)r * p;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             const int j = lane + c * WAVE;
@@ -270,110 +370,175 @@ __global__ void k_emb_gram_sum(const double *__restrict__ part, int64_t chunks, 
 
 // ----------------------------------------------- small symmetric eigen
 
-// Cyclic Jacobi on the p x p symmetric A (destroyed): eigenvalues, sorted
-// descending, to w and the matching eigenvectors to the columns of Vs (V is
-// the unsorted accumulator).  Each rotation is the symmetric Schur step
-// (Golub and Van Loan, Sec. 8.5.2) that annihilates a_ij; the p / 2
-// disjoint pairs of a round-robin step rotate together, rows first, then
-// columns.  A pair is skipped once |a_ij| <= 1e-17 sqrt(|a_ii a_jj|) (or
-// a_ij = 0), and the sweeps stop after one that rotates nothing (at most
-// max_sweeps).  One workgroup of 256 threads, matrices in global memory
-// (p <= 256, L2-resident).
-__global__ void __launch_bounds__(256)
-k_emb_jacobi(double *__restrict__ A, double *__restrict__ V, double *__restrict__ w,
-             double *__restrict__ Vs, int p, int max_sweeps) {
-    __shared__ int slot[EMB_MAX_P];
-    __shared__ double rc[EMB_MAX_P / 2], rs[EMB_MAX_P / 2];
-    __shared__ int ri[EMB_MAX_P / 2], rj[EMB_MAX_P / 2];
-    __shared__ int order[EMB_MAX_P];
-    __shared__ int rotated;
+template <int MAXP>
+struct JacobiShared {
+    int slot[MAXP];
+    double rc[MAXP / 2], rs[MAXP / 2];
+    int ri[MAXP / 2], rj[MAXP / 2];
+    int order[MAXP];
+    int rotated;
+};
+
+// Cyclic Jacobi on the p x p symmetric A (row-major, destroyed; LDS or
+// global memory), the whole workgroup (256 threads) taking part: V gets
+// the eigenvectors as columns and sh.order the column order that sorts the
+// eigenvalues (A's final diagonal) descending.  Each rotation is the
+// symmetric Schur step (Golub and Van Loan, Sec. 8.5.2) that annihilates
+// a_ij; the p / 2 disjoint pairs of a round-robin step rotate together,
+// rows first, then columns.  A pair is skipped once |a_ij| <= 1e-17
+// sqrt(|a_ii a_jj|) (or a_ij = 0), and the sweeps stop after one that
+// rotates nothing (at most max_sweeps).
+template <int MAXP>
+__device__ void jacobi_solve(double *A, double *V, int p, int max_sweeps, JacobiShared<MAXP> &sh) {
     const int tid = threadIdx.x;
     const int pe = p + (p & 1);              // even count (index p is a dummy when p is odd)
     const int half = pe / 2;
     for (int q = tid; q < p * p; q += 256) V[q] = (q / p == q % p) ? 1.0 : 0.0;
-    for (int q = tid; q < pe; q += 256) slot[q] = q;
+    for (int q = tid; q < pe; q += 256) sh.slot[q] = q;
     __syncthreads();
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        if (tid == 0) rotated = 0;
+        if (tid == 0) sh.rotated = 0;
         __syncthreads();
         for (int step = 0; step < pe - 1; ++step) {
             // the pairs of this step: slot[k] with slot[pe - 1 - k]
             for (int k = tid; k < half; k += 256) {
-                int i = slot[k], j = slot[pe - 1 - k];
+                int i = sh.slot[k], j = sh.slot[pe - 1 - k];
                 if (i > j) { const int t = i; i = j; j = t; }
                 double c = 1.0, sn = 0.0;
                 if (j < p) {
-                    const double aij = A[(size_t)i * p + j];
-                    const double aii = A[(size_t)i * p + i], ajj = A[(size_t)j * p + j];
+                    const double aij = A[i * p + j];
+                    const double aii = A[i * p + i], ajj = A[j * p + j];
                     if (aij != 0.0 && fabs(aij) > 1e-17 * sqrt(fabs(aii) * fabs(ajj))) {
                         const double tau = (ajj - aii) / (2.0 * aij);
                         const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                         c = 1.0 / sqrt(1.0 + t * t);
                         sn = t * c;
-                        rotated = 1;
+                        sh.rotated = 1;
                     }
                 }
-                ri[k] = i; rj[k] = j; rc[k] = c; rs[k] = sn;
+                sh.ri[k] = i; sh.rj[k] = j; sh.rc[k] = c; sh.rs[k] = sn;
             }
             __syncthreads();
             // rows i, j of A <- J^T A
             for (int q = tid; q < half * p; q += 256) {
                 const int k = q / p, x = q % p;
-                if (rs[k] == 0.0) continue;
-                const int i = ri[k], j = rj[k];
-                const double ai = A[(size_t)i * p + x], aj = A[(size_t)j * p + x];
-                A[(size_t)i * p + x] = rc[k] * ai - rs[k] * aj;
-                A[(size_t)j * p + x] = rs[k] * ai + rc[k] * aj;
+                if (sh.rs[k] == 0.0) continue;
+                const int i = sh.ri[k], j = sh.rj[k];
+                const double ai = A[i * p + x], aj = A[j * p + x];
+                A[i * p + x] = sh.rc[k] * ai - sh.rs[k] * aj;
+                A[j * p + x] = sh.rs[k] * ai + sh.rc[k] * aj;
             }
             __syncthreads();
             // columns i, j of A <- A J and of V <- V J
             for (int q = tid; q < half * p; q += 256) {
                 const int k = q / p, x = q % p;
-                if (rs[k] == 0.0) continue;
-                const int i = ri[k], j = rj[k];
-                const double ai = A[(size_t)x * p + i], aj = A[(size_t)x * p + j];
-                A[(size_t)x * p + i] = rc[k] * ai - rs[k] * aj;
-                A[(size_t)x * p + j] = rs[k] * ai + rc[k] * aj;
-                const double vi = V[(size_t)x * p + i], vj = V[(size_t)x * p + j];
-                V[(size_t)x * p + i] = rc[k] * vi - rs[k] * vj;
-                V[(size_t)x * p + j] = rs[k] * vi + rc[k] * vj;
+                if (sh.rs[k] == 0.0) continue;
+                const int i = sh.ri[k], j = sh.rj[k];
+                const double ai = A[x * p + i], aj = A[x * p + j];
+                A[x * p + i] = sh.rc[k] * ai - sh.rs[k] * aj;
+                A[x * p + j] = sh.rs[k] * ai + sh.rc[k] * aj;
+                const double vi = V[x * p + i], vj = V[x * p + j];
+                V[x * p + i] = sh.rc[k] * vi - sh.rs[k] * vj;
+                V[x * p + j] = sh.rs[k] * vi + sh.rc[k] * vj;
             }
             __syncthreads();
             // the rotation annihilates a_ij: store the zero it stands for
             for (int k = tid; k < half; k += 256) {
-                if (rs[k] == 0.0) continue;
-                A[(size_t)ri[k] * p + rj[k]] = 0.0;
-                A[(size_t)rj[k] * p + ri[k]] = 0.0;
+                if (sh.rs[k] == 0.0) continue;
+                A[sh.ri[k] * p + sh.rj[k]] = 0.0;
+                A[sh.rj[k] * p + sh.ri[k]] = 0.0;
             }
             // round robin: slot 0 stays, the others move one place
             if (tid == 0) {
-                const int last = slot[pe - 1];
-                for (int q = pe - 1; q > 1; --q) slot[q] = slot[q - 1];
-                slot[1] = last;
+                const int last = sh.slot[pe - 1];
+                for (int q = pe - 1; q > 1; --q) sh.slot[q] = sh.slot[q - 1];
+                sh.slot[1] = last;
             }
             __syncthreads();
         }
-        const int any = rotated;
+        const int any = sh.rotated;
         __syncthreads();
         if (!any) break;
     }
     // sort descending by the diagonal (stable insertion sort, one thread)
     if (tid == 0) {
-        for (int q = 0; q < p; ++q) order[q] = q;
+        for (int q = 0; q < p; ++q) sh.order[q] = q;
         for (int a = 1; a < p; ++a) {
-            const int v = order[a];
-            const double dv = A[(size_t)v * p + v];
+            const int v = sh.order[a];
+            const double dv = A[v * p + v];
             int b = a - 1;
-            while (b >= 0 && A[(size_t)order[b] * p + order[b]] < dv) {
-                order[b + 1] = order[b];
+            while (b >= 0 && A[sh.order[b] * p + sh.order[b]] < dv) {
+                sh.order[b + 1] = sh.order[b];
                 --b;
             }
-            order[b + 1] = v;
+            sh.order[b + 1] = v;
         }
     }
     __syncthreads();
-    for (int q = tid; q < p; q += 256) w[q] = A[(size_t)order[q] * p + order[q]];
-    for (int q = tid; q < p * p; q += 256) Vs[q] = V[(size_t)(q / p) * p + order[q % p]];
+}
+
+// The p x p matrices of the subspace iteration (global memory, L2-resident,
+// p <= 256): eigenvalues descending to w, matching eigenvectors to the
+// columns of Vs (V is the unsorted accumulator).  One workgroup.
+__global__ void __launch_bounds__(256)
+k_emb_jacobi(double *__restrict__ A, double *__restrict__ V, double *__restrict__ w,
+             double *__restrict__ Vs, int p, int max_sweeps) {
+    __shared__ JacobiShared<EMB_MAX_P> sh;
+    jacobi_solve<EMB_MAX_P>(A, V, p, max_sweeps, sh);
+    for (int q = threadIdx.x; q < p; q += 256) w[q] = A[sh.order[q] * p + sh.order[q]];
+    for (int q = threadIdx.x; q < p * p; q += 256) Vs[q] = V[(q / p) * p + sh.order[q % p]];
+}
+
+// Components of at most DENSE_MAX nodes, one workgroup each: the dense S of
+// the component in LDS, its Jacobi eigen-decomposition, and the embedding
+// rows of its nodes (the eigenvectors of the min(dim, s) largest
+// eigenvalues of S, i.e. the smallest of L = I - S), with the eigenvalues
+// of L to the root's row of evals.  Larger components return at once.
+__global__ void __launch_bounds__(256)
+k_emb_dense(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+            const double *__restrict__ wslot, const double *__restrict__ sc,
+            const int64_t *__restrict__ seg_start, const uint32_t *__restrict__ order,
+            const int32_t *__restrict__ loc, int dim, int raw, double *__restrict__ Z,
+            double *__restrict__ evals) {
+    __shared__ double A[DENSE_MAX * DENSE_MAX];
+    __shared__ double V[DENSE_MAX * DENSE_MAX];
+    __shared__ double nrm[DENSE_MAX];
+    __shared__ JacobiShared<DENSE_MAX> sh;
+    const int64_t start = seg_start[blockIdx.x];
+    const int s = (int)(seg_start[blockIdx.x + 1] - start);
+    if (s > DENSE_MAX) return;
+    const uint32_t *nodes = order + start;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
+    for (int q = tid; q < s * s; q += 256) A[q] = 0.0;
+    __syncthreads();
+    for (int r = wv; r < s; r += 256 / WAVE) {
+        const int64_t u = nodes[r];
+        const double su = sc[u];
+        for (int64_t q = rp[u] + lane; q < rp[u + 1]; q += WAVE) {
+            const int32_t x = col[q];
+            const double coef = wslot[q] * su * sc[x];
+            if (coef != 0.0) A[r * s + loc[x]] = coef;
+        }
+    }
+    __syncthreads();
+    jacobi_solve<DENSE_MAX>(A, V, s, 60, sh);
+    const int k = dim < s ? dim : s;
+    for (int r = tid; r < s; r += 256) {
+        double q = 0.0;
+        for (int j = 0; j < k; ++j) {
+            const double v = V[r * s + sh.order[j]];
+            q += v * v;
+        }
+        nrm[r] = raw ? 1.0 : q > 0 ? 1.0 / sqrt(q) : 0.0;
+    }
+    __syncthreads();
+    for (int q = tid; q < s * dim; q += 256) {
+        const int r = q / dim, j = q % dim;
+        Z[(size_t)nodes[r] * dim + j] = j < k ? V[r * s + sh.order[j]] * nrm[r] : 0.0;
+    }
+    if (evals)
+        for (int j = tid; j < k; j += 256)
+            evals[(size_t)nodes[0] * dim + j] = 1.0 - A[sh.order[j] * s + sh.order[j]];
 }
 
 // Columns scaled: Q[:, j] = V[:, j] * f(sigma_j) with f = 1/sqrt (to
@@ -462,28 +627,29 @@ __global__ void k_emb_residual_sum(const double *__restrict__ part, int64_t chun
     res[j] = sqrt(s);
 }
 
-// Z[u][0..dim) = X[u][0..dim) / its length (0 for a zero row; unscaled
-// when raw); eigenvalues of L = 2 - 2 theta.
-__global__ void k_emb_output(const double *__restrict__ X, int64_t n, int p, int dim, int raw,
-                             const double *__restrict__ theta, double *__restrict__ Z,
-                             double *__restrict__ evals) {
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u == 0 && evals)
-        for (int j = 0; j < dim; ++j) evals[j] = j < p ? 2.0 - 2.0 * theta[j] : 0.0;
-    if (u >= n) return;
-    const double *xr = X + (size_t)u * p;
-    double s = 0.0;
-    for (int j = 0; j < dim && j < p; ++j) s += xr[j] * xr[j];
-    const double inv = raw ? 1.0 : s > 0 ? 1.0 / sqrt(s) : 0.0;
-    for (int j = 0; j < dim; ++j) Z[(size_t)u * dim + j] = j < p ? xr[j] * inv : 0.0;
+// Z[nodes[r]][0..dim) = X[r][0..dim) / its length (unscaled when raw);
+// the component's eigenvalues of L (2 - 2 theta) to evals (its root's row).
+__global__ void k_emb_output(const double *__restrict__ X, const uint32_t *__restrict__ nodes,
+                             int64_t s, int p, int dim, int raw, const double *__restrict__ theta,
+                             double *__restrict__ Z, double *__restrict__ evals) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r == 0 && evals)
+        for (int j = 0; j < dim && j < p; ++j) evals[j] = 2.0 - 2.0 * theta[j];
+    if (r >= s) return;
+    const double *xr = X + (size_t)r * p;
+    double q = 0.0;
+    for (int j = 0; j < dim && j < p; ++j) q += xr[j] * xr[j];
+    const double inv = raw ? 1.0 : q > 0 ? 1.0 / sqrt(q) : 0.0;
+    double *zr = Z + (size_t)nodes[r] * dim;
+    for (int j = 0; j < dim; ++j) zr[j] = j < p ? xr[j] * inv : 0.0;
 }
 
 // Workspace layout of the embedding.
 struct EmbLayout {
     int p;
     int64_t chunks;
-    size_t cnt, eoff, stmp, status, wslot, sc, deg, X, Y, Yp, Yn, MX, part, G, V, Vs, H, theta,
-        sigma, res, total;
+    size_t cnt, eoff, stmp, status, wslot, sc, deg, parent, keys, keys_tmp, ids, ids_tmp, sort_tmp,
+        seg_start, loc, X, Y, Yp, Yn, MX, part, G, V, Vs, H, theta, sigma, res, total;
 };
 
 EmbLayout emb_layout(int64_t n, int64_t nnz, int dim) {
@@ -506,6 +672,14 @@ EmbLayout emb_layout(int64_t n, int64_t nnz, int dim) {
     y.wslot = take(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
     y.sc = take(sizeof(double) * (size_t)(n > 0 ? n : 1));
     y.deg = take(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+    y.parent = take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    y.keys = take(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+    y.keys_tmp = take(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+    y.ids = take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    y.ids_tmp = take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    y.sort_tmp = take(sort_tmp_need(n > 0 ? n : 1));
+    y.seg_start = take(sizeof(int64_t) * (size_t)(n + 1));
+    y.loc = take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     const size_t blk = sizeof(double) * (size_t)(n > 0 ? n : 1) * p;
     y.X = take(blk);
     y.Y = take(blk);
@@ -522,6 +696,14 @@ EmbLayout emb_layout(int64_t n, int64_t nnz, int dim) {
     y.res = take(sizeof(double) * p);
     y.total = o;
     return y;
+}
+
+uint64_t mix64_host(uint64_t z) {
+    // SplitMix64 finaliser (Steele, Lea and Flood, 2014), as mix64
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
 }
 
 unsigned row_grid(int64_t n) {
@@ -569,8 +751,9 @@ size_t tg_embedding_workspace_bytes(int64_t n, int64_t nnz, int32_t dim) {
 
 tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int64_t n, int64_t nnz,
                                 const uint64_t *weights, int32_t dim, const tg_embed_opts *opts,
-                                double *Z, double *eigenvalues, int32_t *iterations,
-                                void *workspace, size_t ws_bytes, void *stream) {
+                                double *Z, double *eigenvalues, int32_t *component,
+                                int32_t *iterations, void *workspace, size_t ws_bytes,
+                                void *stream) {
     if (n < 1 || nnz < 0 || (nnz & 1) || dim < 1 || dim > EMB_MAX_P || !row_ptr || !Z ||
         (nnz > 0 && (!col || !weights)) || !workspace || ((uintptr_t)workspace & 255u))
         return TG_E_INVALID_ARG;
@@ -614,137 +797,201 @@ tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int6
     if (bits) return TG_E_NOT_SIMPLE;
     int64_t active = 0;
     for (uint64_t d : hdeg) active += d > 0;
-    const int p = (int)(active < p0 ? active : p0);
-    const unsigned rg = row_grid(n);
-    double *X = D(y.X), *Y = D(y.Y), *Yp = D(y.Yp), *Yn = D(y.Yn), *MX = D(y.MX);
-    double *G = D(y.G), *V = D(y.V), *Vs = D(y.Vs), *H = D(y.H);
-    double *theta = D(y.theta), *sigma = D(y.sigma), *res = D(y.res), *part = D(y.part);
-    const int tiles = (p + GRAM_TILE - 1) / GRAM_TILE;
-    if (p == 0) {   // no node is in an instance: zero rows
-        k_emb_output<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(X, n, 0, dim, raw, theta, Z,
-                                                                   eigenvalues);
+    const unsigned rg_n = row_grid(n);
+    auto grid_of = [](int64_t count) { return (unsigned)((count + 255) / 256); };
+    int32_t *parent = reinterpret_cast<int32_t *>(w + y.parent);
+    int32_t *loc = reinterpret_cast<int32_t *>(w + y.loc);
+    int64_t *seg_start = reinterpret_cast<int64_t *>(w + y.seg_start);
+    uint32_t *changed = status + 2;         // its own 8-byte word
+    if (eigenvalues) EMB_CHK(launch_fill_u64(reinterpret_cast<uint64_t *>(eigenvalues), 0,
+                                             n * (int64_t)dim, st));
+    // components of G^H: hook and compress until no edge joins two roots
+    k_cc_init<<<grid_of(n), 256, 0, st>>>(parent, n);
+    EMB_CHK(hipGetLastError());
+    for (int round = 0;; ++round) {
+        if (round > 64) return TG_E_INTERNAL;    // parents strictly decrease: never reached
+        uint32_t flag = 0;
+        EMB_CHK(launch_fill_u64(reinterpret_cast<uint64_t *>(changed), 0, 1, st));
+        k_cc_hook<<<rg_n, 256, 0, st>>>(row_ptr, col, D(y.wslot), n, parent, changed);
+        k_cc_compress<<<grid_of(n), 256, 0, st>>>(parent, n);
         EMB_CHK(hipGetLastError());
-        if (iterations) *iterations = 0;
+        EMB_CHK(hipMemcpyAsync(&flag, changed, sizeof(flag), hipMemcpyDeviceToHost, st));
+        EMB_CHK(hipStreamSynchronize(st));
+        if (!flag) break;
+    }
+    // nodes sorted by component (stable: ascending ids inside one), the
+    // components' start positions and each node's place in its component
+    uint64_t *keys = reinterpret_cast<uint64_t *>(w + y.keys);
+    uint32_t *ids = reinterpret_cast<uint32_t *>(w + y.ids);
+    k_cc_keys<<<grid_of(n), 256, 0, st>>>(parent, deg, n, dim, keys, ids, component, Z);
+    EMB_CHK(hipGetLastError());
+    uint64_t *skeys = nullptr;
+    uint32_t *order = nullptr;
+    EMB_CHK(radix_sort(keys, reinterpret_cast<uint64_t *>(w + y.keys_tmp), ids,
+                       reinterpret_cast<uint32_t *>(w + y.ids_tmp), n, 32, w + y.sort_tmp, nullptr,
+                       st, &skeys, &order));
+    int64_t *flags = cnt, *segx = eoff;    // both free once the slots are weighed
+    k_cc_flags<<<grid_of(n + 1), 256, 0, st>>>(skeys, n, flags);
+    EMB_CHK(hipGetLastError());
+    EMB_CHK(launch_excl_scan(flags, segx, n + 1, reinterpret_cast<int64_t *>(w + y.stmp), nullptr, st));
+    k_cc_segments<<<grid_of(n), 256, 0, st>>>(flags, segx, n, active, seg_start);
+    k_cc_loc<<<grid_of(n), 256, 0, st>>>(segx, seg_start, order, active, loc);
+    EMB_CHK(hipGetLastError());
+    int64_t nseg = 0;
+    EMB_CHK(hipMemcpyAsync(&nseg, segx + n, sizeof(nseg), hipMemcpyDeviceToHost, st));
+    EMB_CHK(hipStreamSynchronize(st));
+    if (iterations) *iterations = 0;
+    if (nseg == 0) {
         EMB_CHK(hipStreamSynchronize(st));
         return TG_OK;
     }
-    auto gram = [&](const double *A, const double *B, double *C) -> hipError_t {
-        k_emb_gram_part<<<dim3((unsigned)y.chunks, (unsigned)(tiles * tiles)), 256, 0, st>>>(
-            A, B, n, p, part);
-        k_emb_gram_sum<<<(unsigned)((p * p + 255) / 256), 256, 0, st>>>(part, y.chunks, p, C);
-        return hipGetLastError();
-    };
-    auto eig = [&](double *A) -> hipError_t {   // A destroyed; Vs, sigma/theta filled
-        k_emb_jacobi<<<1, 256, 0, st>>>(A, V, sigma, Vs, p, 60);
-        return hipGetLastError();
-    };
-    auto apply = [&](const double *A, const double *Q, double *out) -> hipError_t {
-        k_emb_apply<<<dim3((unsigned)((n + 63) / 64), (unsigned)tiles), 256,
-                      (size_t)p * 32 * sizeof(double), st>>>(A, Q, n, p, out);
-        return hipGetLastError();
-    };
-    auto spmm = [&](const double *A, const double *Zb, double alpha, double beta, double gamma,
-                    double *out) -> hipError_t {
-        k_emb_spmm<<<rg, 256, 0, st>>>(row_ptr, col, D(y.wslot), D(y.sc), n, p, A, Zb, alpha,
-                                       beta, gamma, out);
-        return hipGetLastError();
-    };
-    // orthonormalise A into out through the eigen-decomposition of A^T A
-    auto orth = [&](const double *A, double *out) -> hipError_t {
-        hipError_t e = gram(A, A, G);
-        if (e != hipSuccess) return e;
-        if ((e = eig(G)) != hipSuccess) return e;
-        k_emb_scale_cols<<<(unsigned)((p * p + 255) / 256), 256, 0, st>>>(Vs, sigma, p);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        return apply(A, Vs, out);
-    };
-    // Three rotating blocks (the Chebyshev recurrence needs two inputs and
-    // an output), plus Yp (first orthonormalisation pass) and MX (M Q).
-    double *R[3] = {X, Y, Yn};
-    (void)Yp;
-    std::vector<double> h_theta((size_t)p), h_res((size_t)p);
-    const int want = dim < p ? dim : p;
-    // Rayleigh-Ritz on the orthonormal block Q: Ritz vectors to xo, M times
-    // them to mo, Ritz values to theta (descending), residual norms read back.
-    auto rayleigh_ritz = [&](const double *Q, double *xo, double *mo) -> hipError_t {
-        hipError_t e;
-        if ((e = spmm(Q, nullptr, 0.5, 0.5, 0.0, MX)) != hipSuccess) return e;
-        if ((e = gram(Q, MX, H)) != hipSuccess) return e;
-        if ((e = eig(H)) != hipSuccess) return e;
-        if ((e = apply(Q, Vs, xo)) != hipSuccess) return e;
-        if ((e = apply(MX, Vs, mo)) != hipSuccess) return e;
-        if ((e = hipMemcpyAsync(theta, sigma, sizeof(double) * p, hipMemcpyDeviceToDevice, st)) !=
-            hipSuccess)
-            return e;
-        k_emb_residual_part<<<(unsigned)y.chunks, 256, 0, st>>>(xo, mo, theta, n, p, part);
-        k_emb_residual_sum<<<1, 256, 0, st>>>(part, y.chunks, p, res);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = hipMemcpyAsync(h_theta.data(), theta, sizeof(double) * p, hipMemcpyDeviceToHost,
-                                st)) != hipSuccess)
-            return e;
-        if ((e = hipMemcpyAsync(h_res.data(), res, sizeof(double) * p, hipMemcpyDeviceToHost, st)) !=
-            hipSuccess)
-            return e;
-        return hipStreamSynchronize(st);
-    };
-    auto done = [&]() {
-        for (int j = 0; j < want; ++j)
-            if (!(h_res[(size_t)j] <= tol)) return false;
-        return true;
-    };
-    // start: a random block, orthonormalised twice, and its Ritz vectors
-    k_emb_random<<<(unsigned)((n * p + 255) / 256), 256, 0, st>>>(R[0], n, p, seed, D(y.sc));
-    EMB_CHK(hipGetLastError());
-    EMB_CHK(orth(R[0], Yp));
-    EMB_CHK(orth(Yp, R[1]));
-    EMB_CHK(rayleigh_ritz(R[1], R[0], R[2]));
-    int it = 0;
-    bool converged = done();
-    while (!converged && it < max_iter) {
-        ++it;
-        // Damp [0, bnd], bnd the block's smallest Ritz value: by interlacing
-        // it is at most the p-th largest eigenvalue of M, so no wanted one
-        // is damped.  The filter is scaled to 1 at the top of the spectrum
-        // (1); its degree is capped so that its growth stays below 1e6,
-        // which bounds the block's condition number.
-        double bnd = h_theta[(size_t)p - 1];
-        bnd = bnd < 1e-3 ? 1e-3 : bnd > 1.0 - 1e-9 ? 1.0 - 1e-9 : bnd;
-        const double e = bnd / 2, c = bnd / 2;
-        const double t1 = (1.0 - c) / e;
-        int deg = degree;
-        const double cap = std::acosh(1e6) / std::acosh(t1);
-        if (cap < deg) deg = cap < 1 ? 1 : (int)cap;
-        double *prev = R[0], *cur = R[1], *nxt = R[2];
-        double rho_prev = 1.0, rho = t1;
-        EMB_CHK(spmm(prev, nullptr, 0.5 / (e * t1), (0.5 - c) / (e * t1), 0.0, cur));
-        for (int j = 1; j < deg; ++j) {
-            const double rho_next = 2 * t1 * rho - rho_prev;
-            const double k1 = 2 * rho / (rho_next * e);
-            EMB_CHK(spmm(cur, prev, k1 * 0.5, k1 * (0.5 - c), -rho_prev / rho_next, nxt));
-            rho_prev = rho;
-            rho = rho_next;
-            double *t = prev;
-            prev = cur;
-            cur = nxt;
-            nxt = t;
-        }
-        // cur: the filtered block; prev and nxt are free
-        EMB_CHK(orth(cur, Yp));
-        EMB_CHK(orth(Yp, prev));
-        EMB_CHK(rayleigh_ritz(prev, cur, nxt));
-        R[0] = cur;
-        R[1] = prev;
-        R[2] = nxt;
-        converged = done();
-    }
-    X = R[0];
-    if (iterations) *iterations = it;
-    k_emb_output<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(X, n, p, dim, raw, theta, Z,
-                                                               eigenvalues);
+    std::vector<int64_t> hseg((size_t)nseg + 1);
+    EMB_CHK(hipMemcpyAsync(hseg.data(), seg_start, sizeof(int64_t) * (size_t)(nseg + 1),
+                           hipMemcpyDeviceToHost, st));
+    // every small component at once
+    k_emb_dense<<<(unsigned)nseg, 256, 0, st>>>(row_ptr, col, D(y.wslot), D(y.sc), seg_start, order,
+                                                loc, dim, raw, Z, eigenvalues);
     EMB_CHK(hipGetLastError());
     EMB_CHK(hipStreamSynchronize(st));
+
+    // the large components, one after another
+    double *X = D(y.X), *Y = D(y.Y), *Yp = D(y.Yp), *Yn = D(y.Yn), *MX = D(y.MX);
+    double *G = D(y.G), *V = D(y.V), *Vs = D(y.Vs), *H = D(y.H);
+    double *theta = D(y.theta), *sigma = D(y.sigma), *res = D(y.res), *part = D(y.part);
+    bool all_converged = true;
+    int most_iterations = 0;
+    for (int64_t c = 0; c < nseg; ++c) {
+        const int64_t cs = hseg[(size_t)c], ns = hseg[(size_t)c + 1] - cs;
+        if (ns <= DENSE_MAX) continue;
+        const uint32_t *nodes = order + cs;
+        uint32_t root = 0;
+        EMB_CHK(hipMemcpyAsync(&root, nodes, sizeof(root), hipMemcpyDeviceToHost, st));
+        EMB_CHK(hipStreamSynchronize(st));
+        const int p = (int)(ns < p0 ? ns : p0);
+        const int64_t chunks = (ns + GRAM_ROWS - 1) / GRAM_ROWS;
+        const unsigned rg = row_grid(ns);
+        const int tiles = (p + GRAM_TILE - 1) / GRAM_TILE;
+        auto gram = [&](const double *A, const double *B, double *C) -> hipError_t {
+            k_emb_gram_part<<<dim3((unsigned)chunks, (unsigned)(tiles * tiles)), 256, 0, st>>>(
+                A, B, ns, p, part);
+            k_emb_gram_sum<<<(unsigned)((p * p + 255) / 256), 256, 0, st>>>(part, chunks, p, C);
+            return hipGetLastError();
+        };
+        auto eig = [&](double *A) -> hipError_t {   // A destroyed; Vs, sigma filled
+            k_emb_jacobi<<<1, 256, 0, st>>>(A, V, sigma, Vs, p, 60);
+            return hipGetLastError();
+        };
+        auto apply = [&](const double *A, const double *Q, double *out) -> hipError_t {
+            k_emb_apply<<<dim3((unsigned)((ns + 63) / 64), (unsigned)tiles), 256,
+                          (size_t)p * 32 * sizeof(double), st>>>(A, Q, ns, p, out);
+            return hipGetLastError();
+        };
+        auto spmm = [&](const double *A, const double *Zb, double alpha, double beta, double gamma,
+                        double *out) -> hipError_t {
+            k_emb_spmm<<<rg, 256, 0, st>>>(row_ptr, col, D(y.wslot), D(y.sc), nodes, loc, ns, p, A,
+                                           Zb, alpha, beta, gamma, out);
+            return hipGetLastError();
+        };
+        // orthonormalise A into out through the eigen-decomposition of A^T A
+        auto orth = [&](const double *A, double *out) -> hipError_t {
+            hipError_t e = gram(A, A, G);
+            if (e != hipSuccess) return e;
+            if ((e = eig(G)) != hipSuccess) return e;
+            k_emb_scale_cols<<<(unsigned)((p * p + 255) / 256), 256, 0, st>>>(Vs, sigma, p);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            return apply(A, Vs, out);
+        };
+        // Three rotating blocks (the Chebyshev recurrence needs two inputs
+        // and an output), plus Yp (first orthonormalisation pass) and MX.
+        double *R[3] = {X, Y, Yn};
+        std::vector<double> h_theta((size_t)p), h_res((size_t)p);
+        const int want = dim < p ? dim : p;
+        // Rayleigh-Ritz on the orthonormal block Q: Ritz vectors to xo, M
+        // times them to mo, Ritz values to theta (descending), residual
+        // norms read back.
+        auto rayleigh_ritz = [&](const double *Q, double *xo, double *mo) -> hipError_t {
+            hipError_t e;
+            if ((e = spmm(Q, nullptr, 0.5, 0.5, 0.0, MX)) != hipSuccess) return e;
+            if ((e = gram(Q, MX, H)) != hipSuccess) return e;
+            if ((e = eig(H)) != hipSuccess) return e;
+            if ((e = apply(Q, Vs, xo)) != hipSuccess) return e;
+            if ((e = apply(MX, Vs, mo)) != hipSuccess) return e;
+            if ((e = hipMemcpyAsync(theta, sigma, sizeof(double) * p, hipMemcpyDeviceToDevice,
+                                    st)) != hipSuccess)
+                return e;
+            k_emb_residual_part<<<(unsigned)chunks, 256, 0, st>>>(xo, mo, theta, ns, p, part);
+            k_emb_residual_sum<<<1, 256, 0, st>>>(part, chunks, p, res);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = hipMemcpyAsync(h_theta.data(), theta, sizeof(double) * p,
+                                    hipMemcpyDeviceToHost, st)) != hipSuccess)
+                return e;
+            if ((e = hipMemcpyAsync(h_res.data(), res, sizeof(double) * p, hipMemcpyDeviceToHost,
+                                    st)) != hipSuccess)
+                return e;
+            return hipStreamSynchronize(st);
+        };
+        auto done = [&]() {
+            for (int j = 0; j < want; ++j)
+                if (!(h_res[(size_t)j] <= tol)) return false;
+            return true;
+        };
+        // start: a random block, orthonormalised twice, and its Ritz vectors
+        k_emb_random<<<(unsigned)((ns * p + 255) / 256), 256, 0, st>>>(R[0], ns, p,
+                                                                      seed ^ mix64_host(root));
+        EMB_CHK(hipGetLastError());
+        EMB_CHK(orth(R[0], Yp));
+        EMB_CHK(orth(Yp, R[1]));
+        EMB_CHK(rayleigh_ritz(R[1], R[0], R[2]));
+        int it = 0;
+        bool converged = done();
+        while (!converged && it < max_iter) {
+            ++it;
+            // Damp [0, bnd], bnd the block's smallest Ritz value: by
+            // interlacing it is at most the p-th largest eigenvalue of M, so
+            // no wanted one is damped.  The filter is scaled to 1 at the top
+            // of the spectrum (1); its degree is capped so that its growth
+            // stays below 1e6, which bounds the block's condition number.
+            double bnd = h_theta[(size_t)p - 1];
+            bnd = bnd < 1e-3 ? 1e-3 : bnd > 1.0 - 1e-9 ? 1.0 - 1e-9 : bnd;
+            const double e = bnd / 2, cc = bnd / 2;
+            const double t1 = (1.0 - cc) / e;
+            int deg_f = degree;
+            const double cap = std::acosh(1e6) / std::acosh(t1);
+            if (cap < deg_f) deg_f = cap < 1 ? 1 : (int)cap;
+            double *prev = R[0], *cur = R[1], *nxt = R[2];
+            double rho_prev = 1.0, rho = t1;
+            EMB_CHK(spmm(prev, nullptr, 0.5 / (e * t1), (0.5 - cc) / (e * t1), 0.0, cur));
+            for (int j = 1; j < deg_f; ++j) {
+                const double rho_next = 2 * t1 * rho - rho_prev;
+                const double k1 = 2 * rho / (rho_next * e);
+                EMB_CHK(spmm(cur, prev, k1 * 0.5, k1 * (0.5 - cc), -rho_prev / rho_next, nxt));
+                rho_prev = rho;
+                rho = rho_next;
+                double *t = prev;
+                prev = cur;
+                cur = nxt;
+                nxt = t;
+            }
+            // cur: the filtered block; prev and nxt are free
+            EMB_CHK(orth(cur, Yp));
+            EMB_CHK(orth(Yp, prev));
+            EMB_CHK(rayleigh_ritz(prev, cur, nxt));
+            R[0] = cur;
+            R[1] = prev;
+            R[2] = nxt;
+            converged = done();
+        }
+        all_converged = all_converged && converged;
+        most_iterations = it > most_iterations ? it : most_iterations;
+        k_emb_output<<<grid_of(ns), 256, 0, st>>>(R[0], nodes, ns, p, dim, raw, theta, Z,
+                                                  eigenvalues ? eigenvalues + (size_t)root * dim
+                                                              : nullptr);
+        EMB_CHK(hipGetLastError());
+    }
+    if (iterations) *iterations = most_iterations;
+    EMB_CHK(hipStreamSynchronize(st));
 #undef EMB_CHK
-    return converged ? TG_OK : TG_E_NO_CONVERGENCE;
+    return all_converged ? TG_OK : TG_E_NO_CONVERGENCE;
 }
 
 }  // extern "C"

@@ -223,8 +223,8 @@ def test_embedding_argument_checks():
     its = ctypes.c_int32(0)
     fake = 1 << 20  # never dereferenced: every call below fails its checks first
     call = lambda n, nnz, dim, wsp, wsb: lib.tg_graphlet_embedding(
-        fake, fake, n, nnz, fake, dim, ctypes.byref(opts), fake, None, ctypes.byref(its), wsp,
-        wsb, None)
+        fake, fake, n, nnz, fake, dim, ctypes.byref(opts), fake, None, None, ctypes.byref(its),
+        wsp, wsb, None)
     assert call(1000, 8000, 0, fake, ws) == 1      # dim
     assert call(1000, 8000, 257, fake, ws) == 1
     assert call(1000, 8001, 16, fake, ws) == 1     # odd nnz

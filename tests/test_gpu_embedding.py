@@ -2,18 +2,24 @@
 
 * Edge weights W (instances of a typed graphlet containing each edge): bit
   for bit against the oracle's, for every graphlet and type multiset.
-* Spectra and embeddings: eigenvalues against the oracle's dense float64
-  eigen-decomposition, the eigenvector subspace through its projector U U^T
-  (unique whenever the wanted eigenvalues are separated from the next one),
-  and the embedding rows through Z Z^T, for every graphlet where the cut
-  falls in a gap.
+* Components of the typed-graphlet graph G^H (Sec. 8.8 embeds each one on
+  its own): component ids bit for bit.
+* Spectra and embeddings, per component: eigenvalues against the oracle's
+  dense float64 eigen-decomposition, the eigenvector subspace through its
+  projector U U^T (unique whenever the wanted eigenvalues are separated
+  from the next one, or the component has at most dim nodes), and the
+  embedding rows through Z Z^T.  Components of at most 64 nodes go through
+  the dense Jacobi kernel, larger ones through the filtered subspace
+  iteration; the cases cover both, several Gram chunks, and blocks as wide
+  as the component.
 
-Tolerances.  The solver stops at residual norms ||M x - theta x|| <= tol
-(tests: 1e-12), M = (S + I) / 2.  A Ritz value is then within tol^2 / gap
-of an eigenvalue and the subspace within sin(angle) <= tol / gap of the
-true one, both far below float64 rounding of the products (~1e-13 for
-these sizes); the tests allow 1e-9 on eigenvalues of L and 1e-7 on the
-projector for cuts with a gap of at least 1e-3.
+Tolerances.  The subspace iteration stops at residual norms ||M x - theta
+x|| <= tol (tests: 1e-12), M = (S + I) / 2.  A Ritz value is then within
+tol^2 / gap of an eigenvalue and the subspace within sin(angle) <= tol /
+gap of the true one, both far below float64 rounding of the products
+(~1e-13 here); the dense solver is accurate to rounding.  The tests allow
+1e-9 on eigenvalues of L and 1e-7 on projectors of components whose cut
+has a gap of at least 1e-3.
 """
 
 from __future__ import annotations
@@ -59,43 +65,50 @@ def _embed(rp, col, w_np, dim, **kw):
     import paper_2010_14058_amd as P
 
     w = torch.from_numpy(w_np.view(np.int64).copy()).to(device())
-    Z, ev, its = P.graphlet_embedding(rp, col, w, dim, tol=TOL, **kw)
+    Z, ev, comp, its = P.graphlet_embedding(rp, col, w, dim, tol=TOL, **kw)
     torch.cuda.synchronize()
-    return Z.cpu().numpy(), ev.cpu().numpy(), its
+    return Z.cpu().numpy(), ev.cpu().numpy(), comp.cpu().numpy(), its
 
 
 def _check_embedding(oracle_mod, g, rp, col, w, dim, label):
-    vals, vecs, act = oracle_mod.laplacian_spectrum(g, w)
-    a = int(act.sum())
-    k = min(dim, a)
-    print(f"[gpu] embedding {label} dim={dim} active={a}", flush=True)
-    U, ev, its = _embed(rp, col, w, dim, raw=True)
-    Z, ev2, _ = _embed(rp, col, w, dim)
+    """Checks one embedding against the oracle; returns the number of
+    components whose subspace is unique (and so was compared)."""
+    ev_o, U_o, comp_o = oracle_mod.embedding(g, w, dim, raw=True)
+    print(f"[gpu] embedding {label} dim={dim} components={len(np.unique(comp_o[comp_o >= 0]))}",
+          flush=True)
+    U, ev, comp, its = _embed(rp, col, w, dim, raw=True)
+    Z, ev2, comp2, _ = _embed(rp, col, w, dim)
+    np.testing.assert_array_equal(comp, comp_o, err_msg=label)
+    np.testing.assert_array_equal(comp2, comp_o)
     np.testing.assert_array_equal(ev, ev2)
-    np.testing.assert_allclose(ev[:k], vals[:k], rtol=0, atol=1e-9, err_msg=label)
-    assert np.all(ev[k:] == 0) and np.all(U[:, k:] == 0) and np.all(Z[:, k:] == 0)
-    assert np.all(U[~act] == 0) and np.all(Z[~act] == 0)
-    # orthonormal columns
-    np.testing.assert_allclose(U[:, :k].T @ U[:, :k], np.eye(k), rtol=0, atol=1e-10)
-    # Alg. 5's rows: unit length where the eigenvector rows are nonzero
+    np.testing.assert_allclose(ev, ev_o, rtol=0, atol=1e-9, err_msg=label)
+    out = comp < 0
+    assert not U[out].any() and not Z[out].any()
     nrm = np.sqrt((Z * Z).sum(axis=1))
-    rown = np.sqrt((U * U).sum(axis=1))
-    np.testing.assert_allclose(nrm[rown > 0], 1.0, rtol=0, atol=1e-12)
-    gap = vals[k] - vals[k - 1] if k < a else np.inf
-    if gap < 1e-3:
-        return False
-    Uo = np.zeros((g.n, k))
-    Uo[act] = vecs[:, :k]
-    Po, Pg = Uo @ Uo.T, U[:, :k] @ U[:, :k].T
-    np.testing.assert_allclose(Pg, Po, rtol=0, atol=1e-7, err_msg=label)
-    if g.n > 1000:
-        return True
-    # rows of the embedding: Z Z^T on rows whose eigenvector rows are not tiny
-    _, Zo = oracle_mod.embedding(g, w, dim)
-    big = (Uo * Uo).sum(axis=1) > 1e-4
-    np.testing.assert_allclose((Z @ Z.T)[np.ix_(big, big)], (Zo @ Zo.T)[np.ix_(big, big)],
-                               rtol=0, atol=1e-5, err_msg=label)
-    return True
+    np.testing.assert_allclose(nrm[~out], 1.0, rtol=0, atol=1e-12)
+    Zo = None
+    unique = 0
+    for r in np.unique(comp_o[comp_o >= 0]):
+        nodes = np.flatnonzero(comp_o == r)
+        s = nodes.shape[0]
+        k = min(dim, s)
+        Uc, Uoc = U[nodes, :k], U_o[nodes, :k]
+        assert not U[nodes, k:].any() and not Z[nodes, k:].any()
+        np.testing.assert_allclose(Uc.T @ Uc, np.eye(k), rtol=0, atol=1e-10, err_msg=label)
+        if k < s:
+            vals, _, _ = oracle_mod.laplacian_spectrum(g, w, nodes)
+            if vals[k] - vals[k - 1] < 1e-3:
+                continue
+        unique += 1
+        np.testing.assert_allclose(Uc @ Uc.T, Uoc @ Uoc.T, rtol=0, atol=1e-7,
+                                   err_msg=f"{label} component {r}")
+        if g.n <= 1000:
+            if Zo is None:
+                _, Zo, _ = oracle_mod.embedding(g, w, dim)
+            big = nodes[(Uoc * Uoc).sum(axis=1) > 1e-4]
+            np.testing.assert_allclose(Z[big] @ Z[big].T, Zo[big] @ Zo[big].T, rtol=0, atol=1e-5,
+                                       err_msg=f"{label} component {r}")
+    return unique
 
 
 def test_weights_all_graphlets(oracle_mod):
@@ -125,7 +138,7 @@ def test_embedding_every_graphlet(oracle_mod):
             w = oracle_mod.graphlet_edge_weights(g, orows, h, ms)
             for dim in (1, 4, 16):
                 checked += _check_embedding(oracle_mod, g, rp, col, w, dim, f"h{h} {ms}")
-    assert checked >= 60
+    assert checked >= 100
 
 
 def planted_partition(n, k, d_in, d_out, seed):
@@ -141,13 +154,49 @@ def planted_partition(n, k, d_in, d_out, seed):
 
 
 def test_embedding_multi_chunk(oracle_mod):
-    """Two Gram and residual chunks (2048 rows each) with a ragged tail."""
+    """A component of 2,600 nodes: two Gram and residual chunks (2048 rows
+    each) with a ragged tail."""
     g = planted_partition(2600, 5, 12.0, 0.5, 9)
     rp, col, ty, rows, uv = _device_graph(g)
     orows = oracle_mod.all_edge_rows(g)
     for h, ms in ((0, (0, 0)), (1, (0, 0, 0))):
         w = oracle_mod.graphlet_edge_weights(g, orows, h, ms)
-        assert _check_embedding(oracle_mod, g, rp, col, w, 5, f"{g.name} h{h}")
+        assert _check_embedding(oracle_mod, g, rp, col, w, 5, f"{g.name} h{h}") >= 1
+
+
+def many_components(sizes, avg_degree, seed):
+    """Disjoint G(s, p) pieces of the given sizes (each may split further),
+    node ids shuffled so that components interleave."""
+    rng = np.random.default_rng(seed)
+    n = int(sum(sizes))
+    perm = rng.permutation(n)
+    us, vs, base = [], [], 0
+    for s in sizes:
+        iu, ju = np.triu_indices(s, 1)
+        pick = rng.random(iu.shape[0]) < min(1.0, avg_degree / max(s - 1, 1))
+        us.append(perm[base + iu[pick]])
+        vs.append(perm[base + ju[pick]])
+        base += s
+    u, v = np.concatenate(us), np.concatenate(vs)
+    rp, col = G.csr_from_edges(n, np.minimum(u, v), np.maximum(u, v))
+    types = rng.integers(0, 2, n).astype(np.uint8)
+    return G.Graph(rp, col, types, 2, f"pieces_{len(sizes)}_s{seed}")
+
+
+def test_embedding_many_components(oracle_mod):
+    """Dozens of components from 2 to 300 nodes: the dense kernel (<= 64
+    nodes) and the subspace iteration, with blocks narrower than, as wide
+    as, and capped by the component."""
+    sizes = [2, 3, 4, 5, 7, 9, 12, 16, 20, 30, 40, 50, 63, 64, 65, 66, 70, 80, 90, 100, 150, 300]
+    g = many_components(sizes * 2, 5.0, 17)
+    rp, col, ty, rows, uv = _device_graph(g)
+    orows = oracle_mod.all_edge_rows(g)
+    checked = 0
+    for h, ms in ((0, (0, 1)), (0, (0, 0)), (1, (0, 0, 1)), (3, (0, 0, 1, 1))):
+        w = oracle_mod.graphlet_edge_weights(g, orows, h, ms)
+        for dim in (3, 16, 64):
+            checked += _check_embedding(oracle_mod, g, rp, col, w, dim, f"{g.name} h{h} {ms}")
+    assert checked >= 200
 
 
 def test_embedding_degenerate_cases(oracle_mod):
@@ -162,28 +211,33 @@ def test_embedding_degenerate_cases(oracle_mod):
     g = G.Graph(rp_np, col_np, np.zeros(9, dtype=np.uint8), 1, "tri+c4")
     rp, col, ty, rows, uv = _device_graph(g)
     orows = oracle_mod.all_edge_rows(g)
-    # triangles only: 3 active nodes, fewer than dim -> spectrum {0, 1.5, 1.5}
+    # triangles only: one component of 3 nodes, fewer than dim
     w = oracle_mod.graphlet_edge_weights(g, orows, 2, (0, 0, 0))
-    U, ev, its = _embed(rp, col, w, 6, raw=True)
-    np.testing.assert_allclose(ev[:3], [0.0, 1.5, 1.5], atol=1e-12)
-    assert np.all(ev[3:] == 0) and np.all(U[:, 3:] == 0) and np.all(U[3:] == 0)
-    # edges: two components -> eigenvalue 0 twice; node 8 isolated, zero row
+    U, ev, comp, its = _embed(rp, col, w, 6, raw=True)
+    np.testing.assert_array_equal(comp, [0, 0, 0] + [-1] * 6)
+    np.testing.assert_allclose(ev[0, :3], [0.0, 1.5, 1.5], atol=1e-12)
+    assert not ev[0, 3:].any() and not ev[1:].any() and its == 0
+    np.testing.assert_allclose(U[:3, :3] @ U[:3, :3].T, np.eye(3), atol=1e-12)
+    assert not U[:, 3:].any() and not U[3:].any()
+    # edges: two components, each with eigenvalue 0; node 8 in none
     w = oracle_mod.graphlet_edge_weights(g, orows, 0, (0, 0))
-    Z, ev, its = _embed(rp, col, w, 2)
-    np.testing.assert_allclose(ev, [0.0, 0.0], atol=1e-12)
-    assert np.all(Z[8] == 0)
-    # no instance (4-cliques): zero rows and eigenvalues, no iteration
+    Z, ev, comp, its = _embed(rp, col, w, 2)
+    np.testing.assert_array_equal(comp, [0, 0, 0, 3, 3, 3, 3, 3, -1])
+    np.testing.assert_allclose(ev[[0, 3], 0], [0.0, 0.0], atol=1e-12)
+    np.testing.assert_allclose(ev[0, 1], 1.5, atol=1e-12)
+    assert not Z[8].any()
+    # no instance (4-cliques): nothing to embed
     w = oracle_mod.graphlet_edge_weights(g, orows, 8, (0, 0, 0, 0))
     assert not w.any()
-    Z, ev, its = _embed(rp, col, w, 4)
-    assert its == 0 and not Z.any() and not ev.any()
+    Z, ev, comp, its = _embed(rp, col, w, 4)
+    assert its == 0 and not Z.any() and not ev.any() and np.all(comp == -1)
     # no edges at all
     e0 = G.Graph(np.zeros(5, dtype=np.int64), np.zeros(0, dtype=np.int32),
                  np.zeros(4, dtype=np.uint8), 1, "empty")
     rp0, col0, _ = to_device(e0)
-    Z, ev, its = P.graphlet_embedding(rp0, col0, torch.zeros(0, dtype=torch.int64,
-                                                             device=device()), 3)
-    assert its == 0 and not Z.cpu().numpy().any()
+    Z, ev, comp, its = P.graphlet_embedding(rp0, col0, torch.zeros(0, dtype=torch.int64,
+                                                                   device=device()), 3)
+    assert its == 0 and not Z.cpu().numpy().any() and np.all(comp.cpu().numpy() == -1)
 
 
 def test_embedding_deterministic_and_seed_free(oracle_mod):
@@ -193,8 +247,10 @@ def test_embedding_deterministic_and_seed_free(oracle_mod):
     a = _embed(rp, col, w, 8, seed=1)
     b = _embed(rp, col, w, 8, seed=1)
     c = _embed(rp, col, w, 8, seed=2)
-    np.testing.assert_array_equal(a[0], b[0])
-    np.testing.assert_array_equal(a[1], b[1])
+    assert a[3] > 0           # the giant component went through the iteration
+    for x, y in zip(a[:3], b[:3]):
+        np.testing.assert_array_equal(x, y)
+    np.testing.assert_array_equal(a[2], c[2])
     np.testing.assert_allclose(a[1], c[1], rtol=0, atol=1e-9)
 
 
@@ -226,17 +282,17 @@ def test_embedding_input_checks():
 def test_embedding_iteration_limit():
     """max_iter = 1 on a graph whose spectrum needs more: TG_E_NO_CONVERGENCE
     with check, the last Ritz pairs without."""
+    import torch
+
     import paper_2010_14058_amd as P
 
     g = G.chung_lu_typed(3000, 6.0, 2.2, 80.0, 1, seed=4, name="cl3000")
     rp, col, ty, rows, uv = _device_graph(g)
     w = _gpu_weights(g, rows, uv, ty, 0, (0, 0))
-    import torch
-
     wd = torch.from_numpy(w.view(np.int64).copy()).to(device())
     with pytest.raises(P.TGError) as ei:
         P.graphlet_embedding(rp, col, wd, 16, max_iter=1, degree=2, tol=1e-14)
     assert ei.value.code == P.NO_CONVERGENCE
-    Z, ev, its = P.graphlet_embedding(rp, col, wd, 16, max_iter=1, degree=2, tol=1e-14,
-                                      check=False)
+    Z, ev, comp, its = P.graphlet_embedding(rp, col, wd, 16, max_iter=1, degree=2, tol=1e-14,
+                                            check=False)
     assert its == 1
