@@ -269,49 +269,199 @@ __global__ void k_emb_random(double *__restrict__ X, int64_t s, int p, uint64_t 
     X[q] = (double)(r >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
 }
 
-// out = alpha * (S X) + beta * X + gamma * Z, S = D^{-1/2} W D^{-1/2}
-// restricted to one component: local row r is node nodes[r], a neighbour x
-// is local row loc[x].  One wave per row, each lane a set of the p columns.
-__global__ void __launch_bounds__(256)
-k_emb_spmm(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
-           const double *__restrict__ wslot, const double *__restrict__ sc,
-           const uint32_t *__restrict__ nodes, const int32_t *__restrict__ loc, int64_t n, int p,
-           const double *__restrict__ X, const double *__restrict__ Z, double alpha, double beta,
-           double gamma, double *__restrict__ out) {
-    constexpr int CPL = EMB_MAX_P / WAVE;   // columns per lane
+// A block widened from p to q columns: the old columns, then random ones.
+__global__ void k_emb_widen(const double *__restrict__ X, int64_t s, int p, int q, uint64_t seed,
+                            double *__restrict__ Y) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= s * q) return;
+    const int64_t r = t / q;
+    const int j = (int)(t % q);
+    if (j < p) {
+        Y[t] = X[(size_t)r * p + j];
+    } else {
+        const uint64_t z = mix64(seed ^ mix64((uint64_t)t));
+        Y[t] = (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+    }
+}
+
+// ------------------------------------------- S of one large component
+
+// The component's own CSR of S = D^{-1/2} W D^{-1/2}, built once and read
+// by every product: local row r is node nodes[r], only nonzero entries,
+// columns as local rows.  A row of more than SPMM_CH nonzeros (a hub) is
+// cut into items of SPMM_CH, each a wave's work in the products.
+constexpr int SPMM_CH = 512;
+
+__global__ void k_loc_len(const int64_t *__restrict__ rp, const double *__restrict__ wslot,
+                          const uint32_t *__restrict__ nodes, int64_t ns, int64_t *__restrict__ len,
+                          int64_t *__restrict__ hcnt) {
     const int lane = lane_id();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        len[ns] = 0;
+        hcnt[ns] = 0;
+    }
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
-    for (int64_t r = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; r < n;
+    for (int64_t r = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; r < ns;
          r += nwaves) {
         const int64_t u = nodes[r];
-        double acc[CPL];
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) acc[c] = 0.0;
+        uint64_t c = 0;
+        for (int64_t q = rp[u] + lane; q < rp[u + 1]; q += WAVE) c += wslot[q] != 0.0;
+        c = wave_sum_u64(c);
+        if (lane == 0) {
+            len[r] = (int64_t)c;
+            hcnt[r] = c > (uint64_t)SPMM_CH ? (int64_t)((c + SPMM_CH - 1) / SPMM_CH) : 0;
+        }
+    }
+}
+
+__global__ void k_loc_fill(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                           const double *__restrict__ wslot, const double *__restrict__ sc,
+                           const uint32_t *__restrict__ nodes, const int32_t *__restrict__ loc,
+                           int64_t ns, const int64_t *__restrict__ lrp, int32_t *__restrict__ lcol,
+                           double *__restrict__ lval) {
+    const int lane = lane_id();
+    const uint64_t below = (1ull << lane) - 1;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t r = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; r < ns;
+         r += nwaves) {
+        const int64_t u = nodes[r];
         const double su = sc[u];
-        {
-            for (int64_t s = rp[u]; s < rp[u + 1]; ++s) {
-                const int32_t x = col[s];
-                const double coef = wslot[s] * sc[x];
-                if (coef == 0.0) continue;
-                const double *xr = X + (size_t)loc[x] * p;
+        int64_t out = lrp[r];
+        for (int64_t base = rp[u]; base < rp[u + 1]; base += WAVE) {
+            const int64_t q = base + lane;
+            const bool nz = q < rp[u + 1] && wslot[q] != 0.0;
+            const uint64_t bal = __ballot(nz);
+            if (nz) {
+                const int32_t x = col[q];
+                const int64_t at = out + __popcll(bal & below);
+                lcol[at] = loc[x];
+                lval[at] = wslot[q] * su * sc[x];
+            }
+            out += __popcll(bal);
+        }
+    }
+}
+
+__global__ void k_loc_items(const int64_t *__restrict__ hptr, int64_t ns, int32_t *__restrict__ hrow) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= ns) return;
+    for (int64_t i = hptr[r]; i < hptr[r + 1]; ++i) hrow[i] = (int32_t)r;
+}
+
+// acc += the nonzeros [k0, k1) of S times X, a wave split into WAVE / GS
+// groups that take every (WAVE / GS)-th nonzero, each lane CPL columns
+// (j = lane % GS + c * GS); then the groups are summed in a fixed tree.
+template <int GS, int CPL>
+__device__ __forceinline__ void spmm_range(const int32_t *__restrict__ lcol,
+                                           const double *__restrict__ lval, int64_t k0, int64_t k1,
+                                           int p, const double *__restrict__ X, double (&acc)[CPL]) {
+    constexpr int NG = WAVE / GS;
+    const int lane = lane_id(), g = lane / GS, li = lane % GS;
 #pragma unroll
-                for (int c = 0; c < CPL; ++c) {
-                    const int j = lane + c * WAVE;
-                    if (j < p) acc[c] += coef * xr[j];
+    for (int c = 0; c < CPL; ++c) acc[c] = 0.0;
+    int64_t k = k0 + g;
+    for (; k + NG < k1; k += 2 * NG) {
+        const int32_t c0 = lcol[k], c1 = lcol[k + NG];
+        const double v0 = lval[k], v1 = lval[k + NG];
+        const double *x0 = X + (size_t)c0 * p, *x1 = X + (size_t)c1 * p;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int j = li + c * GS;
+            if (j < p) {
+                acc[c] += v0 * x0[j];
+                acc[c] += v1 * x1[j];
+            }
+        }
+    }
+    if (k < k1) {
+        const double v0 = lval[k];
+        const double *x0 = X + (size_t)lcol[k] * p;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int j = li + c * GS;
+            if (j < p) acc[c] += v0 * x0[j];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CPL; ++c)
+        for (int off = GS; off < WAVE; off <<= 1) acc[c] += __shfl_xor(acc[c], off, WAVE);
+}
+
+// out = alpha * (S X) + beta * X + gamma * Zb on the rows of at most
+// SPMM_CH nonzeros, one wave per row.
+template <int GS, int CPL>
+__global__ void __launch_bounds__(256)
+k_spmm_rows(const int64_t *__restrict__ lrp, const int32_t *__restrict__ lcol,
+            const double *__restrict__ lval, int64_t ns, int p, const double *__restrict__ X,
+            const double *__restrict__ Zb, double alpha, double beta, double gamma,
+            double *__restrict__ out) {
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t r = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; r < ns;
+         r += nwaves) {
+        const int64_t k0 = lrp[r], k1 = lrp[r + 1];
+        if (k1 - k0 > SPMM_CH) continue;
+        double acc[CPL];
+        spmm_range<GS, CPL>(lcol, lval, k0, k1, p, X, acc);
+        if (lane < GS) {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int j = lane + c * GS;
+                if (j < p) {
+                    const size_t o = (size_t)r * p + j;
+                    double v = alpha * acc[c] + beta * X[o];
+                    if (Zb) v += gamma * Zb[o];
+                    out[o] = v;
                 }
             }
         }
-        const double *xu = X + (size_t)r * p;
-        const double *zu = Z ? Z + (size_t)r * p : nullptr;
-        double *ou = out + (size_t)r * p;
+    }
+}
+
+// Partial products of the items of the long rows: part[i][0..p).
+template <int GS, int CPL>
+__global__ void __launch_bounds__(256)
+k_spmm_items(const int64_t *__restrict__ lrp, const int32_t *__restrict__ lcol,
+             const double *__restrict__ lval, const int64_t *__restrict__ hptr,
+             const int32_t *__restrict__ hrow, int64_t nitems, int p, const double *__restrict__ X,
+             double *__restrict__ part) {
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; i < nitems;
+         i += nwaves) {
+        const int32_t r = hrow[i];
+        const int64_t k0 = lrp[r] + (i - hptr[r]) * SPMM_CH;
+        const int64_t k1 = k0 + SPMM_CH < lrp[r + 1] ? k0 + SPMM_CH : lrp[r + 1];
+        double acc[CPL];
+        spmm_range<GS, CPL>(lcol, lval, k0, k1, p, X, acc);
+        if (lane < GS) {
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            const int j = lane + c * WAVE;
-            if (j < p) {
-                double v = alpha * su * acc[c] + beta * xu[j];
-                if (zu) v += gamma * zu[j];
-                ou[j] = v;
+            for (int c = 0; c < CPL; ++c) {
+                const int j = lane + c * GS;
+                if (j < p) part[(size_t)i * p + j] = acc[c];
             }
+        }
+    }
+}
+
+// The long rows: their items' partials summed in item order.
+__global__ void __launch_bounds__(256)
+k_spmm_finish(const int64_t *__restrict__ hptr, int64_t ns, int p, const double *__restrict__ X,
+              const double *__restrict__ Zb, double alpha, double beta, double gamma,
+              const double *__restrict__ part, double *__restrict__ out) {
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t r = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; r < ns;
+         r += nwaves) {
+        const int64_t i0 = hptr[r], i1 = hptr[r + 1];
+        if (i0 == i1) continue;
+        for (int j = lane; j < p; j += WAVE) {
+            double acc = 0.0;
+            for (int64_t i = i0; i < i1; ++i) acc += part[(size_t)i * p + j];
+            const size_t o = (size_t)r * p + j;
+            double v = alpha * acc + beta * X[o];
+            if (Zb) v += gamma * Zb[o];
+            out[o] = v;
         }
     }
 }
@@ -370,9 +520,18 @@ __global__ void k_emb_gram_sum(const double *__restrict__ part, int64_t chunks, 
 
 // ----------------------------------------------- small symmetric eigen
 
+// Round-robin pairing of pe (even) indices: at step t, slot 0 holds index
+// 0 and slot q >= 1 holds 1 + ((q - 1 - t) mod (pe - 1)); pair k of the step
+// is (slot k, slot pe - 1 - k).  Over pe - 1 steps every two indices meet
+// once.
+__device__ __forceinline__ int rr_slot(int q, int t, int pe) {
+    if (q == 0) return 0;
+    int r = (q - 1 - t) % (pe - 1);
+    return 1 + (r < 0 ? r + pe - 1 : r);
+}
+
 template <int MAXP>
 struct JacobiShared {
-    int slot[MAXP];
     double rc[MAXP / 2], rs[MAXP / 2];
     int ri[MAXP / 2], rj[MAXP / 2];
     int order[MAXP];
@@ -380,35 +539,33 @@ struct JacobiShared {
 };
 
 // Cyclic Jacobi on the p x p symmetric A (row-major, destroyed; LDS or
-// global memory), the whole workgroup (256 threads) taking part: V gets
+// global memory), the whole workgroup (NT threads) taking part: V gets
 // the eigenvectors as columns and sh.order the column order that sorts the
 // eigenvalues (A's final diagonal) descending.  Each rotation is the
 // symmetric Schur step (Golub and Van Loan, Sec. 8.5.2) that annihilates
 // a_ij; the p / 2 disjoint pairs of a round-robin step rotate together,
-// rows first, then columns.  A pair is skipped once |a_ij| <= 1e-17
+// rows first, then columns.  A pair is skipped once |a_ij| <= 1e-15
 // sqrt(|a_ii a_jj|) (or a_ij = 0), and the sweeps stop after one that
 // rotates nothing (at most max_sweeps).
-template <int MAXP>
+template <int MAXP, int NT>
 __device__ void jacobi_solve(double *A, double *V, int p, int max_sweeps, JacobiShared<MAXP> &sh) {
     const int tid = threadIdx.x;
     const int pe = p + (p & 1);              // even count (index p is a dummy when p is odd)
     const int half = pe / 2;
-    for (int q = tid; q < p * p; q += 256) V[q] = (q / p == q % p) ? 1.0 : 0.0;
-    for (int q = tid; q < pe; q += 256) sh.slot[q] = q;
+    for (int q = tid; q < p * p; q += NT) V[q] = (q / p == q % p) ? 1.0 : 0.0;
     __syncthreads();
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         if (tid == 0) sh.rotated = 0;
         __syncthreads();
         for (int step = 0; step < pe - 1; ++step) {
-            // the pairs of this step: slot[k] with slot[pe - 1 - k]
-            for (int k = tid; k < half; k += 256) {
-                int i = sh.slot[k], j = sh.slot[pe - 1 - k];
+            for (int k = tid; k < half; k += NT) {
+                int i = rr_slot(k, step, pe), j = rr_slot(pe - 1 - k, step, pe);
                 if (i > j) { const int t = i; i = j; j = t; }
                 double c = 1.0, sn = 0.0;
                 if (j < p) {
                     const double aij = A[i * p + j];
                     const double aii = A[i * p + i], ajj = A[j * p + j];
-                    if (aij != 0.0 && fabs(aij) > 1e-17 * sqrt(fabs(aii) * fabs(ajj))) {
+                    if (aij != 0.0 && fabs(aij) > 1e-15 * sqrt(fabs(aii) * fabs(ajj))) {
                         const double tau = (ajj - aii) / (2.0 * aij);
                         const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                         c = 1.0 / sqrt(1.0 + t * t);
@@ -420,7 +577,7 @@ __device__ void jacobi_solve(double *A, double *V, int p, int max_sweeps, Jacobi
             }
             __syncthreads();
             // rows i, j of A <- J^T A
-            for (int q = tid; q < half * p; q += 256) {
+            for (int q = tid; q < half * p; q += NT) {
                 const int k = q / p, x = q % p;
                 if (sh.rs[k] == 0.0) continue;
                 const int i = sh.ri[k], j = sh.rj[k];
@@ -430,7 +587,7 @@ __device__ void jacobi_solve(double *A, double *V, int p, int max_sweeps, Jacobi
             }
             __syncthreads();
             // columns i, j of A <- A J and of V <- V J
-            for (int q = tid; q < half * p; q += 256) {
+            for (int q = tid; q < half * p; q += NT) {
                 const int k = q / p, x = q % p;
                 if (sh.rs[k] == 0.0) continue;
                 const int i = sh.ri[k], j = sh.rj[k];
@@ -443,16 +600,10 @@ __device__ void jacobi_solve(double *A, double *V, int p, int max_sweeps, Jacobi
             }
             __syncthreads();
             // the rotation annihilates a_ij: store the zero it stands for
-            for (int k = tid; k < half; k += 256) {
+            for (int k = tid; k < half; k += NT) {
                 if (sh.rs[k] == 0.0) continue;
                 A[sh.ri[k] * p + sh.rj[k]] = 0.0;
                 A[sh.rj[k] * p + sh.ri[k]] = 0.0;
-            }
-            // round robin: slot 0 stays, the others move one place
-            if (tid == 0) {
-                const int last = sh.slot[pe - 1];
-                for (int q = pe - 1; q > 1; --q) sh.slot[q] = sh.slot[q - 1];
-                sh.slot[1] = last;
             }
             __syncthreads();
         }
@@ -477,16 +628,170 @@ __device__ void jacobi_solve(double *A, double *V, int p, int max_sweeps, Jacobi
     __syncthreads();
 }
 
-// The p x p matrices of the subspace iteration (global memory, L2-resident,
-// p <= 256): eigenvalues descending to w, matching eigenvectors to the
-// columns of Vs (V is the unsorted accumulator).  One workgroup.
+// The Rayleigh-Ritz matrix of the subspace iteration (p <= 256, global
+// memory, L2-resident): cyclic Jacobi as in jacobi_solve, but each thread
+// applies the two-sided rotation to whole 2 x 2 blocks, one pair of pairs
+// (k, l) at a time -- the block of rows (i_k, j_k) and columns (i_l, j_l)
+// becomes J_k^T B J_l, its mirror image the transpose -- so a step costs
+// two barriers.  The rotations are logged (rot_cs, rot_ij, *nsteps steps of
+// p / 2 pairs) for k_jacobi_vecs; the eigenvalues, sorted descending, go to
+// w and their column order to order.  One workgroup of 1024.
+constexpr int RR_SWEEPS = 30;
+constexpr int LDS_P = 192;                              // widest block kept in LDS
+constexpr int LDS_PACKED = LDS_P * (LDS_P + 1) / 2;     // its upper triangle
+
+// Symmetric p x p storage: full row-major (both halves written) or the
+// packed upper triangle (row-major, LDS).
+template <bool PACKED>
+struct Sym {
+    double *a;
+    int p;
+    __device__ __forceinline__ int at(int i, int j) const {
+        if (!PACKED) return i * p + j;
+        if (i > j) { const int t = i; i = j; j = t; }
+        return i * p - i * (i - 1) / 2 + (j - i);
+    }
+    __device__ __forceinline__ double get(int i, int j) const { return a[at(i, j)]; }
+    __device__ __forceinline__ void set(int i, int j, double v) const {
+        a[at(i, j)] = v;
+        if (!PACKED && i != j) a[at(j, i)] = v;
+    }
+};
+
+template <bool PACKED>
+__device__ void jacobi_rr_body(Sym<PACKED> A, int p, double2 *__restrict__ rot_cs,
+                               short2 *__restrict__ rot_ij, int *__restrict__ nsteps,
+                               int *__restrict__ order, double *__restrict__ w) {
+    __shared__ double rc[EMB_MAX_P / 2], rs[EMB_MAX_P / 2];
+    __shared__ int ri[EMB_MAX_P / 2], rj[EMB_MAX_P / 2];
+    __shared__ double dg[EMB_MAX_P];
+    __shared__ int rotated;
+    const int tid = threadIdx.x;
+    const int pe = p + (p & 1);
+    const int half = pe / 2;
+    // the update: thread (kg, l) takes the pairs of pairs (k, l), k = kg,
+    // kg + groups, ... up to l
+    const int groups = 1024 / half;
+    const int my_l = tid % half, my_kg = tid / half;
+    int steps = 0;
+    for (int sweep = 0; sweep < RR_SWEEPS; ++sweep) {
+        if (tid == 0) rotated = 0;
+        __syncthreads();
+        for (int step = 0; step < pe - 1; ++step, ++steps) {
+            for (int k = tid; k < half; k += 1024) {
+                int i = rr_slot(k, step, pe), j = rr_slot(pe - 1 - k, step, pe);
+                if (i > j) { const int t = i; i = j; j = t; }
+                double c = 1.0, sn = 0.0;
+                if (j < p) {
+                    const double aij = A.get(i, j);
+                    const double aii = A.get(i, i), ajj = A.get(j, j);
+                    if (aij != 0.0 && fabs(aij) > 1e-15 * sqrt(fabs(aii) * fabs(ajj))) {
+                        const double tau = (ajj - aii) / (2.0 * aij);
+                        const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        sn = t * c;
+                        rotated = 1;
+                    }
+                }
+                ri[k] = i; rj[k] = j; rc[k] = c; rs[k] = sn;
+                rot_cs[(size_t)steps * half + k] = make_double2(c, sn);
+                rot_ij[(size_t)steps * half + k] = make_short2((short)i, (short)j);
+            }
+            __syncthreads();
+            for (int k = my_kg, l = my_l; my_kg < groups && k <= l; k += groups) {
+                const double ck = rc[k], sk = rs[k], cl = rc[l], sl = rs[l];
+                const int ik = ri[k], jk = rj[k], il = ri[l], jl = rj[l];
+                if (k == l) {
+                    if (sk == 0.0) continue;
+                    const double aii = A.get(ik, ik), ajj = A.get(jk, jk), aij = A.get(ik, jk);
+                    A.set(ik, ik, ck * ck * aii - 2.0 * ck * sk * aij + sk * sk * ajj);
+                    A.set(jk, jk, sk * sk * aii + 2.0 * ck * sk * aij + ck * ck * ajj);
+                    A.set(ik, jk, 0.0);     // annihilated
+                    continue;
+                }
+                if (sk == 0.0 && sl == 0.0) continue;
+                const bool hk = jk < p, hl = jl < p;    // false: the dummy index of odd p
+                const double b00 = A.get(ik, il);
+                const double b01 = hl ? A.get(ik, jl) : 0.0;
+                const double b10 = hk ? A.get(jk, il) : 0.0;
+                const double b11 = hk && hl ? A.get(jk, jl) : 0.0;
+                const double r00 = ck * b00 - sk * b10, r01 = ck * b01 - sk * b11;
+                const double r10 = sk * b00 + ck * b10, r11 = sk * b01 + ck * b11;
+                A.set(ik, il, cl * r00 - sl * r01);
+                if (hl) A.set(ik, jl, sl * r00 + cl * r01);
+                if (hk) A.set(jk, il, cl * r10 - sl * r11);
+                if (hk && hl) A.set(jk, jl, sl * r10 + cl * r11);
+            }
+            __syncthreads();
+        }
+        const int any = rotated;
+        __syncthreads();
+        if (!any) break;
+    }
+    for (int q = tid; q < p; q += 1024) dg[q] = A.get(q, q);
+    __syncthreads();
+    // descending order, ties by index
+    for (int j = tid; j < p; j += 1024) {
+        const double d = dg[j];
+        int r = 0;
+        for (int i = 0; i < p; ++i) r += dg[i] > d || (dg[i] == d && i < j);
+        order[r] = j;
+        w[r] = d;
+    }
+    if (tid == 0) *nsteps = steps;
+}
+
+// p <= LDS_P: the packed upper triangle of H in LDS.
+__global__ void __launch_bounds__(1024)
+k_jacobi_rr_lds(const double *__restrict__ H, int p, double2 *__restrict__ rot_cs,
+                short2 *__restrict__ rot_ij, int *__restrict__ nsteps, int *__restrict__ order,
+                double *__restrict__ w) {
+    __shared__ double a[LDS_PACKED];
+    const Sym<true> A{a, p};
+    for (int q = threadIdx.x; q < p * p; q += 1024) {
+        const int i = q / p, j = q % p;
+        if (i <= j) a[A.at(i, j)] = H[q];
+    }
+    __syncthreads();
+    jacobi_rr_body<true>(A, p, rot_cs, rot_ij, nsteps, order, w);
+}
+
+// Wider blocks: H itself, in global memory (L2-resident), destroyed.
+__global__ void __launch_bounds__(1024)
+k_jacobi_rr(double *__restrict__ H, int p, double2 *__restrict__ rot_cs,
+            short2 *__restrict__ rot_ij, int *__restrict__ nsteps, int *__restrict__ order,
+            double *__restrict__ w) {
+    jacobi_rr_body<false>(Sym<false>{H, p}, p, rot_cs, rot_ij, nsteps, order, w);
+}
+
+// Eigenvectors of the logged rotations: row x of V = e_x^T J_1 J_2 ...,
+// one wave per row held in LDS, the pairs of a step in parallel; written
+// with the columns sorted (Vs[x][q] = V[x][order[q]]).
 __global__ void __launch_bounds__(256)
-k_emb_jacobi(double *__restrict__ A, double *__restrict__ V, double *__restrict__ w,
-             double *__restrict__ Vs, int p, int max_sweeps) {
-    __shared__ JacobiShared<EMB_MAX_P> sh;
-    jacobi_solve<EMB_MAX_P>(A, V, p, max_sweeps, sh);
-    for (int q = threadIdx.x; q < p; q += 256) w[q] = A[sh.order[q] * p + sh.order[q]];
-    for (int q = threadIdx.x; q < p * p; q += 256) Vs[q] = V[(q / p) * p + sh.order[q % p]];
+k_jacobi_vecs(const double2 *__restrict__ rot_cs, const short2 *__restrict__ rot_ij,
+              const int *__restrict__ nsteps, const int *__restrict__ order, int p,
+              double *__restrict__ Vs) {
+    __shared__ double rows[256 / WAVE][EMB_MAX_P];
+    const int lane = lane_id(), wv = threadIdx.x / WAVE;
+    const int x = blockIdx.x * (256 / WAVE) + wv;
+    if (x >= p) return;                      // whole waves only: no workgroup barrier below
+    double *v = rows[wv];
+    const int half = (p + (p & 1)) / 2;
+    for (int q = lane; q < p; q += WAVE) v[q] = q == x ? 1.0 : 0.0;
+    wave_sync();
+    const int T = *nsteps;
+    for (int t = 0; t < T; ++t) {
+        for (int k = lane; k < half; k += WAVE) {
+            const double2 cs = rot_cs[(size_t)t * half + k];
+            if (cs.y == 0.0) continue;
+            const short2 ij = rot_ij[(size_t)t * half + k];
+            const double vi = v[ij.x], vj = v[ij.y];
+            v[ij.x] = cs.x * vi - cs.y * vj;
+            v[ij.y] = cs.y * vi + cs.x * vj;
+        }
+        wave_sync();
+    }
+    for (int q = lane; q < p; q += WAVE) Vs[(size_t)x * p + q] = v[order[q]];
 }
 
 // Components of at most DENSE_MAX nodes, one workgroup each: the dense S of
@@ -521,7 +826,7 @@ k_emb_dense(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
         }
     }
     __syncthreads();
-    jacobi_solve<DENSE_MAX>(A, V, s, 60, sh);
+    jacobi_solve<DENSE_MAX, 256>(A, V, s, 60, sh);
     const int k = dim < s ? dim : s;
     for (int r = tid; r < s; r += 256) {
         double q = 0.0;
@@ -541,17 +846,68 @@ k_emb_dense(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
             evals[(size_t)nodes[0] * dim + j] = 1.0 - A[sh.order[j] * s + sh.order[j]];
 }
 
-// Columns scaled: Q[:, j] = V[:, j] * f(sigma_j) with f = 1/sqrt (to
-// orthonormalise by the Gram matrix's eigen-decomposition); columns whose
-// sigma is not above 1e-24 sigma_max (singular values 1e-12 apart) are
-// zeroed.
-__global__ void k_emb_scale_cols(double *__restrict__ V, const double *__restrict__ sigma, int p) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= p * p) return;
-    const int j = q % p;
-    const double smax = sigma[0];
-    const double sj = sigma[j];
-    V[q] = (sj > 1e-24 * smax && sj > 0) ? V[q] / sqrt(sj) : 0.0;
+// Cholesky QR step: G = R^T R (R upper, right-looking) and Rinv = R^{-1},
+// so that A Rinv has orthonormal columns when G = A^T A.  A pivot below
+// 1e-30 of the largest diagonal is raised to it (a rank-deficient block
+// keeps finite values).  One workgroup; Rinv's column j is solved by thread
+// j by back substitution.  R lives in the packed upper triangle in LDS
+// (p <= LDS_P) or in G's upper triangle.
+template <bool PACKED>
+__device__ void chol_body(Sym<PACKED> R, const double *__restrict__ G, double *__restrict__ Rinv,
+                          int p) {
+    __shared__ double floor_v;
+    const int tid = threadIdx.x;
+    if (PACKED) {
+        for (int q = tid; q < p * p; q += 1024) {
+            const int i = q / p, j = q % p;
+            if (i <= j) R.a[R.at(i, j)] = G[q];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double mx = 0.0;
+        for (int i = 0; i < p; ++i) mx = R.get(i, i) > mx ? R.get(i, i) : mx;
+        floor_v = mx > 0 ? 1e-30 * mx : 1e-300;
+    }
+    __syncthreads();
+    for (int k = 0; k < p; ++k) {
+        if (tid == 0) {
+            const double d = R.get(k, k);
+            R.a[R.at(k, k)] = sqrt(d > floor_v ? d : floor_v);
+        }
+        __syncthreads();
+        const double rkk = R.get(k, k);
+        for (int j = k + 1 + tid; j < p; j += 1024) R.a[R.at(k, j)] /= rkk;
+        __syncthreads();
+        const int wd = p - k - 1;
+        for (int q = tid; q < wd * wd; q += 1024) {
+            const int i = k + 1 + q / wd, j = k + 1 + q % wd;
+            if (j >= i) R.a[R.at(i, j)] -= R.get(k, i) * R.get(k, j);
+        }
+        __syncthreads();
+    }
+    for (int j = tid; j < p; j += 1024) {
+        for (int i = p - 1; i >= 0; --i) {
+            if (i > j) {
+                Rinv[i * p + j] = 0.0;
+                continue;
+            }
+            double sum = i == j ? 1.0 : 0.0;
+            for (int l = i + 1; l <= j; ++l) sum -= R.get(i, l) * Rinv[l * p + j];
+            Rinv[i * p + j] = sum / R.get(i, i);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(1024)
+k_emb_chol_lds(const double *__restrict__ G, double *__restrict__ Rinv, int p) {
+    __shared__ double a[LDS_PACKED];
+    chol_body<true>(Sym<true>{a, p}, G, Rinv, p);
+}
+
+__global__ void __launch_bounds__(1024)
+k_emb_chol(double *__restrict__ G, double *__restrict__ Rinv, int p) {
+    chol_body<false>(Sym<false>{G, p}, G, Rinv, p);
 }
 
 // Y = X Q (n x p times p x p); a workgroup keeps a 32-column tile of Q in
@@ -644,56 +1000,73 @@ __global__ void k_emb_output(const double *__restrict__ X, const uint32_t *__res
     for (int j = 0; j < dim; ++j) zr[j] = j < p ? xr[j] * inv : 0.0;
 }
 
-// Workspace layout of the embedding.
+// Workspace layout of the embedding.  p0 is the starting block width,
+// pmax the widest a stalled component may grow to; blocks hold the largest
+// possible component (n rows) at pmax columns.
 struct EmbLayout {
-    int p;
-    int64_t chunks;
+    int p0, pmax;
+    int64_t chunks, max_items;
     size_t cnt, eoff, stmp, status, wslot, sc, deg, parent, keys, keys_tmp, ids, ids_tmp, sort_tmp,
-        seg_start, loc, X, Y, Yp, Yn, MX, part, G, V, Vs, H, theta, sigma, res, total;
+        seg_start, loc, lrp, hptr, lcol, lval, hrow, spart, X, Y, Yp, Yn, MX, part, G, Vs, H,
+        theta, sigma, res, rot_cs, rot_ij, rr_misc, total;
 };
 
 EmbLayout emb_layout(int64_t n, int64_t nnz, int dim) {
     EmbLayout y{};
     int p = dim + (dim / 4 > 8 ? dim / 4 : 8);
     if (p > EMB_MAX_P) p = EMB_MAX_P;
-    y.p = p;
+    y.p0 = p;
+    y.pmax = 4 * p < EMB_MAX_P ? 4 * p : EMB_MAX_P;
+    const int pm = y.pmax;
     y.chunks = (n + GRAM_ROWS - 1) / GRAM_ROWS;
     if (y.chunks < 1) y.chunks = 1;
+    // a row of more than SPMM_CH nonzeros has at most twice len / SPMM_CH items
+    y.max_items = 2 * (nnz / SPMM_CH) + 1;
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t at = o;
         o = (o + bytes + 255) & ~(size_t)255;
         return at;
     };
+    const size_t n1 = (size_t)(n > 0 ? n : 1), nz1 = (size_t)(nnz > 0 ? nnz : 1);
     y.cnt = take(sizeof(int64_t) * (size_t)(n + 1));
     y.eoff = take(sizeof(int64_t) * (size_t)(n + 1));
     y.stmp = take(sizeof(int64_t) * (size_t)(scan_tiles(n + 1) + 1));
     y.status = take(256);
-    y.wslot = take(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
-    y.sc = take(sizeof(double) * (size_t)(n > 0 ? n : 1));
-    y.deg = take(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
-    y.parent = take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-    y.keys = take(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
-    y.keys_tmp = take(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
-    y.ids = take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
-    y.ids_tmp = take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    y.wslot = take(sizeof(double) * nz1);
+    y.sc = take(sizeof(double) * n1);
+    y.deg = take(sizeof(uint64_t) * n1);
+    y.parent = take(sizeof(int32_t) * n1);
+    y.keys = take(sizeof(uint64_t) * n1);
+    y.keys_tmp = take(sizeof(uint64_t) * n1);
+    y.ids = take(sizeof(uint32_t) * n1);
+    y.ids_tmp = take(sizeof(uint32_t) * n1);
     y.sort_tmp = take(sort_tmp_need(n > 0 ? n : 1));
     y.seg_start = take(sizeof(int64_t) * (size_t)(n + 1));
-    y.loc = take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-    const size_t blk = sizeof(double) * (size_t)(n > 0 ? n : 1) * p;
+    y.loc = take(sizeof(int32_t) * n1);
+    y.lrp = take(sizeof(int64_t) * (size_t)(n + 1));
+    y.hptr = take(sizeof(int64_t) * (size_t)(n + 1));
+    y.lcol = take(sizeof(int32_t) * nz1);
+    y.lval = take(sizeof(double) * nz1);
+    y.hrow = take(sizeof(int32_t) * (size_t)y.max_items);
+    y.spart = take(sizeof(double) * (size_t)y.max_items * pm);
+    const size_t blk = sizeof(double) * n1 * pm;
     y.X = take(blk);
     y.Y = take(blk);
     y.Yp = take(blk);
     y.Yn = take(blk);
     y.MX = take(blk);
-    y.part = take(sizeof(double) * (size_t)y.chunks * p * p);
-    y.G = take(sizeof(double) * (size_t)p * p);
-    y.V = take(sizeof(double) * (size_t)p * p);
-    y.Vs = take(sizeof(double) * (size_t)p * p);
-    y.H = take(sizeof(double) * (size_t)p * p);
-    y.theta = take(sizeof(double) * p);
-    y.sigma = take(sizeof(double) * p);
-    y.res = take(sizeof(double) * p);
+    y.part = take(sizeof(double) * (size_t)y.chunks * pm * pm);
+    y.G = take(sizeof(double) * (size_t)pm * pm);
+    y.Vs = take(sizeof(double) * (size_t)pm * pm);
+    y.H = take(sizeof(double) * (size_t)pm * pm);
+    y.theta = take(sizeof(double) * pm);
+    y.sigma = take(sizeof(double) * pm);
+    y.res = take(sizeof(double) * pm);
+    const size_t rots = (size_t)RR_SWEEPS * (pm + 1) * ((pm + 1) / 2);
+    y.rot_cs = take(sizeof(double2) * rots);
+    y.rot_ij = take(sizeof(short2) * rots);
+    y.rr_misc = take(sizeof(int) * (pm + 1));     // step count, then the column order
     y.total = o;
     return y;
 }
@@ -772,7 +1145,7 @@ tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int6
     int64_t *eoff = reinterpret_cast<int64_t *>(w + y.eoff);
     uint32_t *status = reinterpret_cast<uint32_t *>(w + y.status);
     uint64_t *deg = reinterpret_cast<uint64_t *>(w + y.deg);
-    const int p0 = y.p;
+    const int p0 = y.p0;
     const int64_t m = nnz / 2;
 #define EMB_CHK(x) do { if ((x) != hipSuccess) return TG_E_DEVICE; } while (0)
     // weighted CSR: canonical edge ids of the slots, their weights, degrees
@@ -856,29 +1229,49 @@ tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int6
 
     // the large components, one after another
     double *X = D(y.X), *Y = D(y.Y), *Yp = D(y.Yp), *Yn = D(y.Yn), *MX = D(y.MX);
-    double *G = D(y.G), *V = D(y.V), *Vs = D(y.Vs), *H = D(y.H);
+    double *G = D(y.G), *Vs = D(y.Vs), *H = D(y.H);
     double *theta = D(y.theta), *sigma = D(y.sigma), *res = D(y.res), *part = D(y.part);
+    int64_t *lrp = reinterpret_cast<int64_t *>(w + y.lrp);
+    int64_t *hptr = reinterpret_cast<int64_t *>(w + y.hptr);
+    int32_t *lcol = reinterpret_cast<int32_t *>(w + y.lcol);
+    double *lval = D(y.lval);
+    int32_t *hrow = reinterpret_cast<int32_t *>(w + y.hrow);
+    double *spart = D(y.spart);
+    double2 *rot_cs = reinterpret_cast<double2 *>(w + y.rot_cs);
+    short2 *rot_ij = reinterpret_cast<short2 *>(w + y.rot_ij);
+    int *rr_misc = reinterpret_cast<int *>(w + y.rr_misc);
     bool all_converged = true;
     int most_iterations = 0;
     for (int64_t c = 0; c < nseg; ++c) {
         const int64_t cs = hseg[(size_t)c], ns = hseg[(size_t)c + 1] - cs;
         if (ns <= DENSE_MAX) continue;
         const uint32_t *nodes = order + cs;
-        uint32_t root = 0;
-        EMB_CHK(hipMemcpyAsync(&root, nodes, sizeof(root), hipMemcpyDeviceToHost, st));
-        EMB_CHK(hipStreamSynchronize(st));
-        const int p = (int)(ns < p0 ? ns : p0);
-        const int64_t chunks = (ns + GRAM_ROWS - 1) / GRAM_ROWS;
         const unsigned rg = row_grid(ns);
-        const int tiles = (p + GRAM_TILE - 1) / GRAM_TILE;
+        // the component's S as its own CSR, and the items of its long rows
+        k_loc_len<<<rg, 256, 0, st>>>(row_ptr, D(y.wslot), nodes, ns, cnt, eoff);
+        EMB_CHK(hipGetLastError());
+        EMB_CHK(launch_excl_scan(cnt, lrp, ns + 1, reinterpret_cast<int64_t *>(w + y.stmp), nullptr, st));
+        EMB_CHK(launch_excl_scan(eoff, hptr, ns + 1, reinterpret_cast<int64_t *>(w + y.stmp), nullptr,
+                                 st));
+        k_loc_fill<<<rg, 256, 0, st>>>(row_ptr, col, D(y.wslot), D(y.sc), nodes, loc, ns, lrp, lcol,
+                                       lval);
+        k_loc_items<<<grid_of(ns), 256, 0, st>>>(hptr, ns, hrow);
+        EMB_CHK(hipGetLastError());
+        uint32_t root = 0;
+        int64_t nitems = 0;
+        EMB_CHK(hipMemcpyAsync(&root, nodes, sizeof(root), hipMemcpyDeviceToHost, st));
+        EMB_CHK(hipMemcpyAsync(&nitems, hptr + ns, sizeof(nitems), hipMemcpyDeviceToHost, st));
+        EMB_CHK(hipStreamSynchronize(st));
+        if (nitems > y.max_items) return TG_E_INTERNAL;
+        const int pcap = (int)(ns < y.pmax ? ns : y.pmax);
+        int p = (int)(ns < p0 ? ns : p0);
+        const int want = dim < p ? dim : p;
+        const int64_t chunks = (ns + GRAM_ROWS - 1) / GRAM_ROWS;
+        int tiles = 0;
         auto gram = [&](const double *A, const double *B, double *C) -> hipError_t {
             k_emb_gram_part<<<dim3((unsigned)chunks, (unsigned)(tiles * tiles)), 256, 0, st>>>(
                 A, B, ns, p, part);
             k_emb_gram_sum<<<(unsigned)((p * p + 255) / 256), 256, 0, st>>>(part, chunks, p, C);
-            return hipGetLastError();
-        };
-        auto eig = [&](double *A) -> hipError_t {   // A destroyed; Vs, sigma filled
-            k_emb_jacobi<<<1, 256, 0, st>>>(A, V, sigma, Vs, p, 60);
             return hipGetLastError();
         };
         auto apply = [&](const double *A, const double *Q, double *out) -> hipError_t {
@@ -886,34 +1279,57 @@ tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int6
                           (size_t)p * 32 * sizeof(double), st>>>(A, Q, ns, p, out);
             return hipGetLastError();
         };
+        // out = alpha S A + beta A + gamma Zb
         auto spmm = [&](const double *A, const double *Zb, double alpha, double beta, double gamma,
                         double *out) -> hipError_t {
-            k_emb_spmm<<<rg, 256, 0, st>>>(row_ptr, col, D(y.wslot), D(y.sc), nodes, loc, ns, p, A,
-                                           Zb, alpha, beta, gamma, out);
+#define EMB_SPMM(GSV, CPLV)                                                                       \
+    do {                                                                                          \
+        k_spmm_rows<GSV, CPLV><<<rg, 256, 0, st>>>(lrp, lcol, lval, ns, p, A, Zb, alpha, beta,     \
+                                                   gamma, out);                                   \
+        if (nitems)                                                                               \
+            k_spmm_items<GSV, CPLV><<<row_grid(nitems), 256, 0, st>>>(lrp, lcol, lval, hptr, hrow, \
+                                                                      nitems, p, A, spart);       \
+    } while (0)
+            if (p <= 16) EMB_SPMM(16, 1);
+            else if (p <= 32) EMB_SPMM(32, 1);
+            else if (p <= 64) EMB_SPMM(64, 1);
+            else if (p <= 128) EMB_SPMM(64, 2);
+            else if (p <= 192) EMB_SPMM(64, 3);
+            else EMB_SPMM(64, 4);
+#undef EMB_SPMM
+            if (nitems)
+                k_spmm_finish<<<rg, 256, 0, st>>>(hptr, ns, p, A, Zb, alpha, beta, gamma, spart, out);
             return hipGetLastError();
         };
-        // orthonormalise A into out through the eigen-decomposition of A^T A
+        // Cholesky QR: out = A R^{-1}, A^T A = R^T R
         auto orth = [&](const double *A, double *out) -> hipError_t {
             hipError_t e = gram(A, A, G);
             if (e != hipSuccess) return e;
-            if ((e = eig(G)) != hipSuccess) return e;
-            k_emb_scale_cols<<<(unsigned)((p * p + 255) / 256), 256, 0, st>>>(Vs, sigma, p);
+            if (p <= LDS_P) k_emb_chol_lds<<<1, 1024, 0, st>>>(G, Vs, p);
+            else k_emb_chol<<<1, 1024, 0, st>>>(G, Vs, p);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             return apply(A, Vs, out);
         };
         // Three rotating blocks (the Chebyshev recurrence needs two inputs
         // and an output), plus Yp (first orthonormalisation pass) and MX.
         double *R[3] = {X, Y, Yn};
-        std::vector<double> h_theta((size_t)p), h_res((size_t)p);
-        const int want = dim < p ? dim : p;
+        std::vector<double> h_theta, h_res;
         // Rayleigh-Ritz on the orthonormal block Q: Ritz vectors to xo, M
         // times them to mo, Ritz values to theta (descending), residual
         // norms read back.
         auto rayleigh_ritz = [&](const double *Q, double *xo, double *mo) -> hipError_t {
             hipError_t e;
+            h_theta.assign((size_t)p, 0.0);
+            h_res.assign((size_t)p, 0.0);
             if ((e = spmm(Q, nullptr, 0.5, 0.5, 0.0, MX)) != hipSuccess) return e;
             if ((e = gram(Q, MX, H)) != hipSuccess) return e;
-            if ((e = eig(H)) != hipSuccess) return e;
+            if (p <= LDS_P)
+                k_jacobi_rr_lds<<<1, 1024, 0, st>>>(H, p, rot_cs, rot_ij, rr_misc, rr_misc + 1, sigma);
+            else
+                k_jacobi_rr<<<1, 1024, 0, st>>>(H, p, rot_cs, rot_ij, rr_misc, rr_misc + 1, sigma);
+            k_jacobi_vecs<<<(unsigned)((p + 3) / 4), 256, 0, st>>>(rot_cs, rot_ij, rr_misc, rr_misc + 1,
+                                                                   p, Vs);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
             if ((e = apply(Q, Vs, xo)) != hipSuccess) return e;
             if ((e = apply(MX, Vs, mo)) != hipSuccess) return e;
             if ((e = hipMemcpyAsync(theta, sigma, sizeof(double) * p, hipMemcpyDeviceToDevice,
@@ -930,12 +1346,14 @@ tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int6
                 return e;
             return hipStreamSynchronize(st);
         };
-        auto done = [&]() {
+        auto worst = [&]() {
+            double r = 0.0;
             for (int j = 0; j < want; ++j)
-                if (!(h_res[(size_t)j] <= tol)) return false;
-            return true;
+                r = !(h_res[(size_t)j] <= r) ? h_res[(size_t)j] : r;   // NaN counts as worst
+            return r;
         };
         // start: a random block, orthonormalised twice, and its Ritz vectors
+        tiles = (p + GRAM_TILE - 1) / GRAM_TILE;
         k_emb_random<<<(unsigned)((ns * p + 255) / 256), 256, 0, st>>>(R[0], ns, p,
                                                                       seed ^ mix64_host(root));
         EMB_CHK(hipGetLastError());
@@ -943,9 +1361,36 @@ tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int6
         EMB_CHK(orth(Yp, R[1]));
         EMB_CHK(rayleigh_ritz(R[1], R[0], R[2]));
         int it = 0;
-        bool converged = done();
+        double chk = worst();       // worst wanted residual at the last checkpoint
+        int chk_it = 0;
+        bool converged = chk <= tol;
         while (!converged && it < max_iter) {
             ++it;
+            // Every 25 iterations: a worst wanted residual that fell by less
+            // than 100x means the cut sits in a cluster of eigenvalues wider
+            // than the block; widen the block (its Ritz vectors and fresh
+            // random columns) by half.
+            bool widen = false;
+            if (it - chk_it >= 25) {
+                widen = worst() > 1e-2 * chk && p < pcap;
+                chk = worst();
+                chk_it = it;
+            }
+            if (widen) {
+                const int q = p + (p / 2 > 16 ? p / 2 : 16) < pcap ? p + (p / 2 > 16 ? p / 2 : 16)
+                                                                  : pcap;
+                k_emb_widen<<<(unsigned)((ns * q + 255) / 256), 256, 0, st>>>(
+                    R[0], ns, p, q, seed ^ mix64_host(root + (uint64_t)it), R[1]);
+                EMB_CHK(hipGetLastError());
+                p = q;
+                tiles = (p + GRAM_TILE - 1) / GRAM_TILE;
+                EMB_CHK(orth(R[1], Yp));
+                EMB_CHK(orth(Yp, R[2]));
+                EMB_CHK(rayleigh_ritz(R[2], R[0], R[1]));
+                chk = worst();
+                converged = chk <= tol;
+                continue;
+            }
             // Damp [0, bnd], bnd the block's smallest Ritz value: by
             // interlacing it is at most the p-th largest eigenvalue of M, so
             // no wanted one is damped.  The filter is scaled to 1 at the top
@@ -979,7 +1424,7 @@ tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int6
             R[0] = cur;
             R[1] = prev;
             R[2] = nxt;
-            converged = done();
+            converged = worst() <= tol;
         }
         all_converged = all_converged && converged;
         most_iterations = it > most_iterations ? it : most_iterations;

@@ -197,6 +197,59 @@ def test_embedding_many_components(oracle_mod):
         for dim in (3, 16, 64):
             checked += _check_embedding(oracle_mod, g, rp, col, w, dim, f"{g.name} h{h} {ms}")
     assert checked >= 200
+    # blocks wider than the LDS-resident solvers take (p > 192)
+    w = oracle_mod.graphlet_edge_weights(g, orows, 3, (0, 0, 1, 1))
+    assert _check_embedding(oracle_mod, g, rp, col, w, 200, f"{g.name} wide") >= 30
+
+
+def test_embedding_clustered_spectrum():
+    """Weights given directly: a 10-node weighted cycle with 40 pendant
+    pairs c - a - b, W(c, a) = 1 and W(a, b) = 1000 + 7k.  Each pair adds
+    an eigenvalue near 1 / (2 W(a, b)), so 39 eigenvalues within 5e-4 of
+    each other follow the zero eigenvalue and the cut at dim = 16 falls
+    inside that cluster: the block must widen to hold the cluster before
+    the wanted residuals can fall.  Checked against a dense eigensolve of
+    the same Laplacian: eigenvalues, orthonormality and residuals (the
+    subspace inside the cluster is not unique)."""
+    import torch
+
+    import paper_2010_14058_amd as P
+
+    core = 10
+    edges, wts = [], []
+    for i in range(core):
+        edges.append((i, (i + 1) % core))
+        wts.append(1)
+    nxt = core
+    for k in range(40):
+        c, a, b = k % core, nxt, nxt + 1
+        nxt += 2
+        edges += [(c, a), (a, b)]
+        wts += [1, 1000 + 7 * k]
+    n = nxt
+    e = np.array([tuple(sorted(x)) for x in edges])
+    order = np.lexsort((e[:, 1], e[:, 0]))
+    e, wv = e[order], np.array(wts, dtype=np.uint64)[order]
+    rp_np, col_np = G.csr_from_edges(n, e[:, 0], e[:, 1])
+    g = G.Graph(rp_np, col_np, np.zeros(n, dtype=np.uint8), 1, "clustered")
+    np.testing.assert_array_equal(g.edges(), e)
+    Wd = np.zeros((n, n))
+    Wd[e[:, 0], e[:, 1]] = wv
+    Wd[e[:, 1], e[:, 0]] = wv
+    d = Wd.sum(axis=1)
+    Lap = np.eye(n) - Wd / np.sqrt(np.outer(d, d))
+    vals = np.linalg.eigvalsh(Lap)
+    assert vals[39] - vals[1] < 1e-3 and vals[40] - vals[39] > 0.5    # the cluster
+    rp, col, _ = to_device(g)
+    dim = 16
+    U, ev, comp, its = _embed(rp, col, wv, dim, raw=True)
+    print(f"[gpu] clustered spectrum: {its} iterations", flush=True)
+    assert its > 25                       # the first block stalled
+    assert np.all(comp == 0)
+    np.testing.assert_allclose(ev[0], vals[:dim], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(U.T @ U, np.eye(dim), rtol=0, atol=1e-10)
+    res = np.linalg.norm(Lap @ U - U * ev[0][None, :], axis=0)
+    assert res.max() < 1e-9
 
 
 def test_embedding_degenerate_cases(oracle_mod):
