@@ -31,3 +31,4 @@ from .embedding import (  # noqa: F401
     laplacian_spectrum,
     embedding,
 )
+from . import directed  # noqa: F401,E402

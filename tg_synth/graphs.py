@@ -394,3 +394,22 @@ def serving_graph(req: dict) -> Graph:
     return chung_lu_typed(n, dbar, req["beta"], max(wmax, dbar * 1.01), req["L"],
                           type_probs=zipf_probs(req["L"], 1.2), seed=req["seed"],
                           name=f"req_{req['seed']}")
+
+
+def orient(g: Graph, mutual: float = 0.2, seed: int = 0) -> np.ndarray:
+    """Arc directions of a directed graph whose underlying undirected graph
+    is ``g``: uint8 per CSR slot (u -> col[s]), bit 0 = the arc u -> col[s],
+    bit 1 = the arc col[s] -> u.  Each edge is reciprocal with probability
+    ``mutual``, else one arc of a fair coin's direction."""
+    (rng,) = _rngs(seed, 1)
+    e = g.edges()
+    r = rng.random(e.shape[0])
+    code = np.where(r < mutual, 3, np.where(r < mutual + (1 - mutual) / 2, 1, 2)).astype(np.uint8)
+    src = np.repeat(np.arange(g.n, dtype=np.int64), g.degrees())
+    dst = g.col.astype(np.int64)
+    lo, hi = np.minimum(src, dst), np.maximum(src, dst)
+    # edge id of each slot: rank of (lo, hi) among the edges (lexicographic)
+    eid = np.searchsorted(e[:, 0] * g.n + e[:, 1], lo * g.n + hi)
+    c = code[eid]
+    swapped = ((c & 1) << 1) | ((c >> 1) & 1)
+    return np.where(src < dst, c, swapped).astype(np.uint8)
