@@ -291,6 +291,41 @@ size_t tg_edge_list_workspace_bytes(int64_t n);
 tg_status tg_edge_list(const int64_t *row_ptr, const int32_t *col, int64_t n, int64_t nnz,
                        int64_t *edge_uv, void *workspace, size_t ws_bytes, void *stream);
 
+/* Directed typed graphlets of 2 and 3 nodes (Sec. 4.8: every typed
+ * neighbourhood, and with it T_ij, S_i and S_j of Alg. 1, splits into out-
+ * and in-neighbours; nodes joined both ways form a third case).
+ * Input: the underlying undirected graph as for tg_count_typed_graphlets
+ * (row_ptr, col, types, n, nnz, L; an edge wherever at least one arc is)
+ * and dir (device uint8 [nnz]): for CSR slot s of row u (u -> col[s]), bit
+ * 0 is the arc u -> col[s] and bit 1 the arc col[s] -> u; every slot has
+ * at least one bit and its reverse slot the mirrored bits
+ * (TG_E_NOT_SIMPLE otherwise, as for an unsorted or asymmetric CSR).
+ * Per-edge rows (device uint64 [nnz/2][tg_directed_row_width(L) = 15L], or
+ * NULL), edges in canonical order (i < j), with a, b in {0: out, the
+ * endpoint -> k; 1: in, k -> the endpoint; 2: both}:
+ *   TRI[t][a][b]  at t*9 + a*3 + b   k adjacent to both i and j, of type t,
+ *                                    direction a at i and b at j
+ *   PATH_I[t][a]  at 9L + t*3 + a    k adjacent to i only (k != j)
+ *   PATH_J[t][b]  at 12L + t*3 + b   k adjacent to j only (k != i)
+ * Global counts (device uint64 [tg_directed_global_width(L) = 4L^2 +
+ * 64L^3], or NULL): instances per directed typed graphlet, i.e. per class
+ * of typed digraphs under type-preserving isomorphism, each class at its
+ * canonical key: over every numbering of its nodes, the smallest tuple
+ * (types..., pair codes...), the code of nodes x < y being 0 (no arc), 1
+ * (x -> y), 2 (y -> x) or 3 (both).  2-node classes at (t0*L + t1)*4 +
+ * c01; 3-node classes (3-paths and triangles) at 4L^2 + ((t0*L + t1)*L +
+ * t2)*64 + c01*16 + c02*4 + c12.  Entries that are not canonical keys are
+ * 0.  Workspace: tg_directed_workspace_bytes(n, nnz, L) bytes, device,
+ * 256-byte aligned.  Errors as for tg_count_typed_graphlets.  Returns when
+ * the results are complete on `stream`. */
+int32_t tg_directed_row_width(int32_t L);
+int64_t tg_directed_global_width(int32_t L);
+size_t tg_directed_workspace_bytes(int64_t n, int64_t nnz, int32_t L);
+tg_status tg_count_directed(const int64_t *row_ptr, const int32_t *col, const uint8_t *dir,
+                            const uint8_t *types, int64_t n, int64_t nnz, int32_t L,
+                            uint64_t *per_edge, uint64_t *global_counts, void *workspace,
+                            size_t ws_bytes, void *stream);
+
 /* Typed-graphlet spectral embeddings (Alg. 5), in two calls.
  *
  * tg_graphlet_weights: W_e, the number of instances of one typed graphlet

@@ -172,3 +172,24 @@ def global_from_rows(g, dirs, rows) -> np.ndarray:
             v //= edges
         out[q] = v
     return out
+
+
+def edge_row(g, dirs, i: int, j: int) -> np.ndarray:
+    """The row of one edge (i < j) straight from the CSR slices (for samples
+    of large graphs)."""
+    L = g.L
+    rp, col = g.row_ptr, g.col
+    ni, di = col[rp[i]:rp[i + 1]].astype(np.int64), dirs[rp[i]:rp[i + 1]]
+    nj, dj = col[rp[j]:rp[j + 1]].astype(np.int64), dirs[rp[j]:rp[j + 1]]
+    code = np.array([0, 0, 1, 2])          # direction bits 1, 2, 3 -> out, in, both
+    row = np.zeros(row_width(L), dtype=np.uint64)
+    common, pi, pj = np.intersect1d(ni, nj, assume_unique=True, return_indices=True)
+    for k, a, b in zip(common.tolist(), code[di[pi]].tolist(), code[dj[pj]].tolist()):
+        row[int(g.types[k]) * 9 + a * 3 + b] += 1
+    only_i = ~np.isin(ni, nj) & (ni != j)
+    for k, a in zip(ni[only_i].tolist(), code[di[only_i]].tolist()):
+        row[9 * L + int(g.types[k]) * 3 + a] += 1
+    only_j = ~np.isin(nj, ni) & (nj != i)
+    for k, b in zip(nj[only_j].tolist(), code[dj[only_j]].tolist()):
+        row[12 * L + int(g.types[k]) * 3 + b] += 1
+    return row

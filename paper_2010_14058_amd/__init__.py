@@ -237,6 +237,36 @@ def edge_list(row_ptr, col, *, workspace: Workspace | None = None, stream=None):
     return uv
 
 
+def count_directed(row_ptr, col, dirs, types, L: int, *, per_edge: bool = True,
+                   workspace: Workspace | None = None, stream=None):
+    """Directed typed 2- and 3-node graphlet counts (Sec. 4.8) of a device
+    CSR of the underlying undirected graph with per-slot arc bits ``dirs``
+    (uint8, bit 0: u -> col[s], bit 1: col[s] -> u).  Returns ``(rows,
+    glob)``: rows int64 [nnz/2, 15L] (uint64 bit patterns; None without
+    ``per_edge``) and glob int64 [4L^2 + 64L^3]."""
+    import torch
+
+    dev = row_ptr.device
+    n, nnz = row_ptr.numel() - 1, col.numel()
+    lib = _lib.load()
+    W = lib.tg_directed_row_width(L)
+    G = lib.tg_directed_global_width(L)
+    if W == 0:
+        raise _lib.TGError(4, "tg_count_directed")
+    rows = torch.empty((nnz // 2, W), dtype=torch.int64, device=dev) if per_edge else None
+    glob = torch.empty(G, dtype=torch.int64, device=dev)
+    ws = (workspace or Workspace(dev)).get(lib.tg_directed_workspace_bytes(n, nnz, L))
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    rc = lib.tg_count_directed(row_ptr.data_ptr(), col.data_ptr() if nnz else 0,
+                               dirs.data_ptr() if nnz else 0, types.data_ptr() if n else 0, n,
+                               nnz, L, rows.data_ptr() if (rows is not None and nnz) else 0,
+                               glob.data_ptr(), ws.data_ptr(), ws.numel(), stream.cuda_stream)
+    if rc:
+        raise _lib.TGError(rc, "tg_count_directed")
+    return rows, glob
+
+
 def graphlet_weights(rows, edge_uv, types, L: int, graphlet: int, types_sorted, *, stream=None):
     """W_e of Alg. 5 for every edge: the instances of the typed graphlet
     (graphlet id 0..8, sorted type multiset) that contain it, read off the

@@ -98,6 +98,12 @@ SIGNATURES = {
                                       _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
     "tg_pa_global_key_describe": (_c.c_int, [_c.c_int32, _c.c_int64, _c.POINTER(_c.c_int32),
                                              _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
+    "tg_directed_row_width": (_c.c_int32, [_c.c_int32]),
+    "tg_directed_global_width": (_c.c_int64, [_c.c_int32]),
+    "tg_directed_workspace_bytes": (_c.c_size_t, [_c.c_int64, _c.c_int64, _c.c_int32]),
+    "tg_count_directed": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                     _c.c_int64, _c.c_int64, _c.c_int32, _c.c_void_p,
+                                     _c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "tg_graphlet_weights": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int32, _c.c_void_p,
                                        _c.c_void_p, _c.c_int32, _c.POINTER(_c.c_int32),
                                        _c.c_void_p, _c.c_void_p]),

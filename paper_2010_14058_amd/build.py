@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libtg.so")
 SOURCES = ["tg_api.hip", "tg_kernels.hip", "tg_edges.hip", "tg_sparse.hip", "tg_position.hip",
-           "tg_sort.hip", "tg_server.hip", "tg_embed.hip"]
+           "tg_sort.hip", "tg_server.hip", "tg_embed.hip", "tg_directed.hip"]
 
 HIPCC_FLAGS = [
     "-O3",

@@ -1,0 +1,411 @@
+// Directed typed graphlets (Sec. 4.8): every typed neighbourhood of the
+// underlying undirected graph splits by arc direction -- out (the endpoint
+// -> k), in (k -> the endpoint) or both (reciprocal arcs) -- and with it the
+// sets T_ij, S_i, S_j of Alg. 1.  Per edge (i, j), i < j, the row holds
+//   TRI[t][a][b]  at t*9 + a*3 + b   (k in T_ij, type t, direction a at i,
+//                                     direction b at j)
+//   PATH_I[t][a]  at 9L + t*3 + a    (k in S_i)
+//   PATH_J[t][b]  at 12L + t*3 + b   (k in S_j)
+// with a, b in {0 out, 1 in, 2 both}.  As in Cor. 2, the 3-path counts come
+// from the direction-split typed degrees minus the triangles and the edge
+// itself: only the common neighbours are enumerated (one wave per edge,
+// each element of the shorter list searched in the longer one).
+//
+// Global counts are per directed typed graphlet (class of typed digraphs
+// under type-preserving isomorphism), named by a canonical key: the
+// smallest (types..., pair codes...) over every numbering of the nodes,
+// a pair code for nodes x < y being 0 none, 1 x -> y, 2 y -> x, 3 both.
+// The rows are folded into per-workgroup LDS histograms of canonical keys
+// (global atomics when the key space is too large for LDS), and each
+// 3-node class is divided by its edge count (a triangle is met from its 3
+// edges, a 3-path from its 2).
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "tg_device.hpp"
+
+namespace tg {
+namespace {
+
+constexpr int DIR_LDS_KEYS = 16384;   // widest global layout histogrammed in LDS (128 KiB)
+
+// Direction code of a CSR slot relative to its row's node: 0 out, 1 in, 2 both.
+__device__ __forceinline__ int dir_code(uint8_t d) { return d == 1 ? 0 : d == 2 ? 1 : 2; }
+
+// Checks (sorted rows in range, no self-loops, types in range, direction
+// bits 1..3 mirrored by the reverse slot), entries above the diagonal per
+// row, and the direction-split typed degrees deg3[v][t*3 + a].  One wave
+// per row.
+__global__ void __launch_bounds__(256)
+k_dir_check(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+            const uint8_t *__restrict__ dir, const uint8_t *__restrict__ types, int64_t n,
+            int64_t nnz, int L, int64_t *__restrict__ ucount, uint32_t *__restrict__ deg3,
+            uint32_t *__restrict__ status) {
+    __shared__ uint32_t cnt[256 / WAVE][3 * TG_MAX_L];
+    const int lane = lane_id(), wv = threadIdx.x / WAVE;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ucount[n] = 0;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / WAVE) + wv; u < n; u += nwaves) {
+        for (int q = lane; q < 3 * L; q += WAVE) cnt[wv][q] = 0;
+        wave_sync();
+        const int64_t b = rp[u], e = rp[u + 1];
+        uint32_t bad = 0;
+        uint64_t up = 0;
+        if (b < 0 || e < b || e > nnz || (u == 0 && b != 0) || (u == n - 1 && e != nnz)) {
+            bad = ST_UNSORTED;
+        } else {
+            if (types[u] >= L) bad |= ST_TYPE_RANGE;
+            for (int64_t s = b + lane; s < e; s += WAVE) {
+                const int32_t x = col[s];
+                if (x < 0 || x >= n) {
+                    bad |= ST_COL_RANGE;
+                    continue;
+                }
+                if (x == u) bad |= ST_SELF_LOOP;
+                if (s > b && col[s - 1] >= x) bad |= ST_UNSORTED;
+                if (x > u) ++up;
+                const uint8_t d = dir[s];
+                const int64_t xb = rp[x], xe = rp[x + 1];
+                if (d == 0 || d > 3 || xb < 0 || xe < xb || xe > nnz) {
+                    bad |= ST_ASYMMETRIC;
+                    continue;
+                }
+                const int64_t r = lower_bound(col, xb, xe, (int32_t)u);
+                const uint8_t want = (uint8_t)(((d & 1) << 1) | (d >> 1));
+                if (r >= xe || col[r] != (int32_t)u || dir[r] != want) bad |= ST_ASYMMETRIC;
+                const int t = types[x];
+                if (t < L) atomicAdd(&cnt[wv][t * 3 + dir_code(d)], 1u);
+                else bad |= ST_TYPE_RANGE;
+            }
+        }
+        bad = wave_or(bad);
+        up = wave_sum_u64(up);
+        wave_sync();
+        if (lane == 0) {
+            ucount[u] = bad ? 0 : (int64_t)up;
+            if (bad) atomicOr(status, bad);
+        }
+        for (int q = lane; q < 3 * L; q += WAVE) deg3[(size_t)u * 3 * L + q] = cnt[wv][q];
+        wave_sync();
+    }
+}
+
+__global__ void k_dir_edge_check(const int64_t *__restrict__ eoff, int64_t n, int64_t m,
+                                 uint32_t *__restrict__ status) {
+    if (eoff[n] != m) atomicOr(status, ST_EDGE_COUNT);
+}
+
+// The canonical edge of each upper slot: esrc[e] = u, eslot[e] = s.
+__global__ void k_dir_edges_of(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                               const int64_t *__restrict__ eoff, int64_t n,
+                               int32_t *__restrict__ esrc, int64_t *__restrict__ eslot) {
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; u < n;
+         u += nwaves) {
+        const int64_t e = rp[u + 1], first = e - (eoff[u + 1] - eoff[u]);
+        for (int64_t s = first + lane; s < e; s += WAVE) {
+            const int64_t id = eoff[u] + (s - first);
+            esrc[id] = (int32_t)u;
+            eslot[id] = s;
+        }
+    }
+}
+
+// One wave per edge (i, j): the common neighbours k by searching each
+// element of the shorter list in the longer one, counted per (type of k,
+// direction at i, direction at j) in LDS; then the row.
+__global__ void __launch_bounds__(256)
+k_dir_rows(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+           const uint8_t *__restrict__ dir, const uint8_t *__restrict__ types,
+           const uint32_t *__restrict__ deg3, const int32_t *__restrict__ esrc,
+           const int64_t *__restrict__ eslot, int64_t m, int L, uint64_t *__restrict__ rows) {
+    __shared__ uint32_t tri[256 / WAVE][9 * TG_MAX_L];
+    const int lane = lane_id(), wv = threadIdx.x / WAVE;
+    const int W = 15 * L;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t e = (int64_t)blockIdx.x * (blockDim.x / WAVE) + wv; e < m; e += nwaves) {
+        const int32_t i = esrc[e];
+        const int64_t sij = eslot[e];
+        const int32_t j = col[sij];
+        for (int q = lane; q < 9 * L; q += WAVE) tri[wv][q] = 0;
+        wave_sync();
+        const int64_t ib = rp[i], ie = rp[i + 1], jb = rp[j], je = rp[j + 1];
+        const bool i_short = ie - ib <= je - jb;
+        const int64_t sb = i_short ? ib : jb, se = i_short ? ie : je;
+        const int64_t lb = i_short ? jb : ib, le = i_short ? je : ie;
+        for (int64_t s = sb + lane; s < se; s += WAVE) {
+            const int32_t k = col[s];
+            const int64_t r = lower_bound(col, lb, le, k);
+            if (r < le && col[r] == k) {
+                const int cs = dir_code(dir[s]), cl = dir_code(dir[r]);
+                const int a = i_short ? cs : cl, b = i_short ? cl : cs;
+                atomicAdd(&tri[wv][types[k] * 9 + a * 3 + b], 1u);
+            }
+        }
+        wave_sync();
+        const int ti = types[i], tj = types[j];
+        const int aij = dir_code(dir[sij]);                 // j as seen from i
+        const int bji = dir_code((uint8_t)(((dir[sij] & 1) << 1) | (dir[sij] >> 1)));
+        uint64_t *row = rows + (size_t)e * W;
+        for (int q = lane; q < W; q += WAVE) {
+            uint64_t v;
+            if (q < 9 * L) {
+                v = tri[wv][q];
+            } else if (q < 12 * L) {
+                const int t = (q - 9 * L) / 3, a = (q - 9 * L) % 3;
+                int64_t c = deg3[(size_t)i * 3 * L + t * 3 + a];
+                for (int b = 0; b < 3; ++b) c -= tri[wv][t * 9 + a * 3 + b];
+                if (t == tj && a == aij) --c;
+                v = (uint64_t)c;
+            } else {
+                const int t = (q - 12 * L) / 3, b = (q - 12 * L) % 3;
+                int64_t c = deg3[(size_t)j * 3 * L + t * 3 + b];
+                for (int a = 0; a < 3; ++a) c -= tri[wv][t * 9 + a * 3 + b];
+                if (t == ti && b == bji) --c;
+                v = (uint64_t)c;
+            }
+            row[q] = v;
+        }
+        wave_sync();
+    }
+}
+
+// Canonical key index of a typed digraph on 2 or 3 nodes.  arcs: bit x*3+y
+// is the arc x -> y.
+__device__ __forceinline__ int pair_code(uint32_t arcs, int x, int y) {
+    return (int)((arcs >> (x * 3 + y)) & 1u) | (int)(((arcs >> (y * 3 + x)) & 1u) << 1);
+}
+
+__device__ int64_t canon_key3(int t0, int t1, int t2, uint32_t arcs, int L) {
+    const int ty[3] = {t0, t1, t2};
+    const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    int64_t best = -1;
+    for (int q = 0; q < 6; ++q) {
+        const int p0 = perms[q][0], p1 = perms[q][1], p2 = perms[q][2];
+        const int64_t key = (((int64_t)ty[p0] * L + ty[p1]) * L + ty[p2]) * 64 +
+                            pair_code(arcs, p0, p1) * 16 + pair_code(arcs, p0, p2) * 4 +
+                            pair_code(arcs, p1, p2);
+        if (best < 0 || key < best) best = key;
+    }
+    return 4 * (int64_t)L * L + best;
+}
+
+__device__ __forceinline__ int64_t canon_key2(int t0, int t1, uint32_t arcs, int L) {
+    const int64_t a = ((int64_t)t0 * L + t1) * 4 + pair_code(arcs, 0, 1);
+    const int64_t b = ((int64_t)t1 * L + t0) * 4 + pair_code(arcs, 1, 0);
+    return a < b ? a : b;
+}
+
+// Arcs between endpoint x (0 = i or 1 = j) and node 2 for direction code c.
+__device__ __forceinline__ uint32_t end_arcs(int x, int c) {
+    const uint32_t out = 1u << (x * 3 + 2), in = 1u << (2 * 3 + x);
+    return c == 0 ? out : c == 1 ? in : (out | in);
+}
+
+// Rows -> sums per canonical key: one wave per edge, lanes over columns;
+// histogram in LDS (keys < DIR_LDS_KEYS) or global atomics.
+template <bool LDS>
+__global__ void __launch_bounds__(1024)
+k_dir_global(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+             const uint8_t *__restrict__ dir, const uint8_t *__restrict__ types,
+             const int32_t *__restrict__ esrc, const int64_t *__restrict__ eslot,
+             const uint64_t *__restrict__ rows, int64_t m, int L, int64_t width,
+             unsigned long long *__restrict__ acc) {
+    __shared__ unsigned long long h[LDS ? DIR_LDS_KEYS : 1];
+    if (LDS) {
+        for (int64_t q = threadIdx.x; q < width; q += blockDim.x) h[q] = 0;
+        __syncthreads();
+    }
+    const int lane = lane_id();
+    const int W = 15 * L;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t e = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; e < m;
+         e += nwaves) {
+        const int32_t i = esrc[e];
+        const int64_t sij = eslot[e];
+        const int32_t j = col[sij];
+        const int ti = types[i], tj = types[j];
+        const uint8_t d = dir[sij];
+        const uint32_t eij = ((d & 1) ? 1u << 1 : 0u) | ((d & 2) ? 1u << 3 : 0u);   // 0->1, 1->0
+        const uint64_t *row = rows + (size_t)e * W;
+        if (lane == 0) {
+            const int64_t k2 = canon_key2(ti, tj, eij, L);
+            if (LDS) atomicAdd(&h[k2], 1ull);
+            else atomicAdd(&acc[k2], 1ull);
+        }
+        for (int q = lane; q < W; q += WAVE) {
+            const uint64_t v = row[q];
+            if (!v) continue;
+            int t;
+            uint32_t arcs = eij;
+            if (q < 9 * L) {
+                t = q / 9;
+                arcs |= end_arcs(0, (q / 3) % 3) | end_arcs(1, q % 3);
+            } else if (q < 12 * L) {
+                t = (q - 9 * L) / 3;
+                arcs |= end_arcs(0, (q - 9 * L) % 3);
+            } else {
+                t = (q - 12 * L) / 3;
+                arcs |= end_arcs(1, (q - 12 * L) % 3);
+            }
+            const int64_t key = canon_key3(ti, tj, t, arcs, L);
+            if (LDS) atomicAdd(&h[key], (unsigned long long)v);
+            else atomicAdd(&acc[key], (unsigned long long)v);
+        }
+    }
+    if (LDS) {
+        __syncthreads();
+        for (int64_t q = threadIdx.x; q < width; q += blockDim.x)
+            if (h[q]) atomicAdd(&acc[q], h[q]);
+    }
+}
+
+// Each 3-node class divided by its edge count (3 for a triangle, 2 for a
+// 3-path); a remainder flags ST_NOT_DIVISIBLE.
+__global__ void k_dir_finalize(const unsigned long long *__restrict__ acc, int64_t width, int L,
+                               uint64_t *__restrict__ out, uint32_t *__restrict__ status) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= width) return;
+    uint64_t v = acc[q];
+    const int64_t base = 4 * (int64_t)L * L;
+    if (q >= base && v) {
+        const int c = (int)((q - base) % 64);
+        const int edges = (c >> 4 ? 1 : 0) + ((c >> 2) & 3 ? 1 : 0) + (c & 3 ? 1 : 0);
+        if (edges < 2 || v % (uint64_t)edges) atomicOr(status, ST_NOT_DIVISIBLE);
+        v = edges ? v / (uint64_t)edges : v;
+    }
+    out[q] = v;
+}
+
+struct DirLayout {
+    size_t status, ucount, eoff, stmp, deg3, esrc, eslot, rows, acc, total;
+};
+
+DirLayout dir_layout(int64_t n, int64_t nnz, int L, bool own_rows) {
+    DirLayout y{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = (o + bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    const int64_t m = nnz / 2;
+    y.status = take(256);
+    y.ucount = take(sizeof(int64_t) * (size_t)(n + 1));
+    y.eoff = take(sizeof(int64_t) * (size_t)(n + 1));
+    y.stmp = take(sizeof(int64_t) * (size_t)(scan_tiles(n + 1) + 1));
+    y.deg3 = take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1) * 3 * L);
+    y.esrc = take(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    y.eslot = take(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+    y.rows = take(own_rows ? sizeof(uint64_t) * (size_t)(m > 0 ? m : 1) * 15 * L : 0);
+    y.acc = take(sizeof(uint64_t) * (size_t)(4 * L * L + 64 * L * L * L));
+    y.total = o;
+    return y;
+}
+
+unsigned waves_grid(int64_t items) {
+    int64_t b = (items + 3) / 4;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        cus > 0 && b > (int64_t)cus * 32)
+        b = (int64_t)cus * 32;
+    return b > 0 ? (unsigned)b : 1u;
+}
+
+}  // namespace
+}  // namespace tg
+
+using namespace tg;
+
+extern "C" {
+
+int32_t tg_directed_row_width(int32_t L) { return (L < 1 || L > TG_MAX_L) ? 0 : 15 * L; }
+
+int64_t tg_directed_global_width(int32_t L) {
+    return (L < 1 || L > TG_MAX_L) ? 0 : 4 * (int64_t)L * L + 64 * (int64_t)L * L * L;
+}
+
+size_t tg_directed_workspace_bytes(int64_t n, int64_t nnz, int32_t L) {
+    if (n < 0 || nnz < 0 || L < 1 || L > TG_MAX_L) return 0;
+    return dir_layout(n, nnz, L, true).total;
+}
+
+tg_status tg_count_directed(const int64_t *row_ptr, const int32_t *col, const uint8_t *dir,
+                            const uint8_t *types, int64_t n, int64_t nnz, int32_t L,
+                            uint64_t *per_edge, uint64_t *global_counts, void *workspace,
+                            size_t ws_bytes, void *stream) {
+    if (L < 1 || L > TG_MAX_L) return TG_E_L_RANGE;
+    if (n < 0 || nnz < 0 || (nnz & 1) || !row_ptr || (n > 0 && !types) ||
+        (nnz > 0 && (!col || !dir)) || !workspace || ((uintptr_t)workspace & 255u))
+        return TG_E_INVALID_ARG;
+    if (n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 40)) return TG_E_TOO_LARGE;
+    const DirLayout y = dir_layout(n, nnz, L, per_edge == nullptr);
+    if (ws_bytes < y.total) return TG_E_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    char *w = static_cast<char *>(workspace);
+    uint32_t *status = reinterpret_cast<uint32_t *>(w + y.status);
+    int64_t *ucount = reinterpret_cast<int64_t *>(w + y.ucount);
+    int64_t *eoff = reinterpret_cast<int64_t *>(w + y.eoff);
+    uint32_t *deg3 = reinterpret_cast<uint32_t *>(w + y.deg3);
+    int32_t *esrc = reinterpret_cast<int32_t *>(w + y.esrc);
+    int64_t *eslot = reinterpret_cast<int64_t *>(w + y.eslot);
+    uint64_t *rows = per_edge ? per_edge : reinterpret_cast<uint64_t *>(w + y.rows);
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(w + y.acc);
+    const int64_t m = nnz / 2, width = tg_directed_global_width(L);
+#define DIR_CHK(x) do { if ((x) != hipSuccess) return TG_E_DEVICE; } while (0)
+    DIR_CHK(launch_fill_u64(reinterpret_cast<uint64_t *>(status), 0, 1, st));
+    DIR_CHK(launch_fill_u64(reinterpret_cast<uint64_t *>(acc), 0, width, st));
+    if (n > 0) {
+        k_dir_check<<<waves_grid(n), 256, 0, st>>>(row_ptr, col, dir, types, n, nnz, L, ucount,
+                                                    deg3, status);
+        DIR_CHK(hipGetLastError());
+        DIR_CHK(launch_excl_scan(ucount, eoff, n + 1, reinterpret_cast<int64_t *>(w + y.stmp),
+                                 nullptr, st));
+        k_dir_edge_check<<<1, 1, 0, st>>>(eoff, n, m, status);
+        DIR_CHK(hipGetLastError());
+    } else if (nnz > 0) {
+        return TG_E_INVALID_ARG;
+    }
+    uint32_t bits = 0;
+    DIR_CHK(hipMemcpyAsync(&bits, status, sizeof(bits), hipMemcpyDeviceToHost, st));
+    DIR_CHK(hipStreamSynchronize(st));
+    if (bits & ST_TYPE_RANGE) return TG_E_TYPE_RANGE;
+    if (bits) return TG_E_NOT_SIMPLE;
+    if (m > 0) {
+        k_dir_edges_of<<<waves_grid(n), 256, 0, st>>>(row_ptr, col, eoff, n, esrc, eslot);
+        k_dir_rows<<<waves_grid(m), 256, 0, st>>>(row_ptr, col, dir, types, deg3, esrc, eslot, m,
+                                                   L, rows);
+        DIR_CHK(hipGetLastError());
+        if (global_counts) {
+            int dev = 0, cus = 0;
+            DIR_CHK(hipGetDevice(&dev));
+            DIR_CHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            if (width <= DIR_LDS_KEYS) {
+                int64_t b = (m + 15) / 16;
+                if (b > cus) b = cus;
+                k_dir_global<true><<<(unsigned)(b > 0 ? b : 1), 1024, 0, st>>>(
+                    row_ptr, col, dir, types, esrc, eslot, rows, m, L, width, acc);
+            } else {
+                int64_t b = (m + 15) / 16;
+                if (b > (int64_t)cus * 8) b = (int64_t)cus * 8;
+                k_dir_global<false><<<(unsigned)(b > 0 ? b : 1), 1024, 0, st>>>(
+                    row_ptr, col, dir, types, esrc, eslot, rows, m, L, width, acc);
+            }
+            DIR_CHK(hipGetLastError());
+        }
+    }
+    if (global_counts) {
+        k_dir_finalize<<<(unsigned)((width + 255) / 256), 256, 0, st>>>(acc, width, L, global_counts,
+                                                                        status);
+        DIR_CHK(hipGetLastError());
+        DIR_CHK(hipMemcpyAsync(&bits, status, sizeof(bits), hipMemcpyDeviceToHost, st));
+    }
+    DIR_CHK(hipStreamSynchronize(st));
+#undef DIR_CHK
+    return bits ? TG_E_INTERNAL : TG_OK;
+}
+
+}  // extern "C"

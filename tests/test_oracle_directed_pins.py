@@ -155,3 +155,12 @@ def test_hand_examples(D):
     assert glob[(0 * 2 + 1) * 4 + 2] == 1         # arc 1 -> 2: key (0, 1, 2)
     assert glob[16 + 1 * 64 + 2 * 4 + 3] == 1     # the 3-path, key (0,0,1, 0,2,3)
     assert glob.sum() == 3
+
+
+def test_single_edge_rows(D):
+    """The CSR-slice form of one edge's row equals the set-based rows."""
+    g = G.chung_lu_typed(300, 8.0, 2.2, 40.0, 3, seed=9)
+    dirs = G.orient(g, 0.25, 4)
+    rows = D.edge_rows(g, dirs)
+    for e, (i, j) in enumerate(g.edges().tolist()):
+        np.testing.assert_array_equal(D.edge_row(g, dirs, i, j), rows[e])
