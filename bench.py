@@ -800,6 +800,8 @@ def bench_single(args):
         result["config3"] = bench_config3(args, P, torch, G, dev, stream, peak["GBps"])
     if not args.no_extra:
         P.set_tuning(**defaults)
+        result["directed"] = bench_directed(args, P, torch, G, dev, stream)
+        result["embedding"] = bench_embedding(args, P, torch, G, dev, stream)
         result["batch"] = run_batch_workload(args, args.graphs, args.single_sample,
                                              0 if args.skip_cpu else 1000, 3, tune=False)
         result["serve"] = run_serve_workload(args, args.requests, args.pool, args.rate,
@@ -845,6 +847,103 @@ def bench_config3(args, P, torch, G, dev, stream, peak_gbps):
     ws.buf = None
     torch.cuda.empty_cache()
     return out
+
+
+def bench_directed(args, P, torch, G, dev, stream, steps=3):
+    """Directed typed 3-node counts (Sec. 4.8) on the headline power-law
+    graph with its edges oriented (20% reciprocal, else a fair coin): the
+    whole call (checks, rows, global classes) per step, and a sampled parity
+    check of rows against the oracle."""
+    from oracle import directed as OD   # oracle: parity sample only, outside the timed steps
+
+    g = G.config_graph(2, seed=0, scale=args.scale)
+    dirs = G.orient(g, 0.2, 7)
+    L = g.L
+    rp, col, ty = (torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev),
+                   torch.from_numpy(g.types).to(dev))
+    d = torch.from_numpy(dirs).to(dev)
+    ws = P.Workspace(dev)
+    P.count_directed(rp, col, d, ty, L, workspace=ws, stream=stream)      # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rows, glob = P.count_directed(rp, col, d, ty, L, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # algorithmic bytes of the row pass: the row write, the shorter adjacency
+    # list (ids and direction bytes) and both endpoints' direction-split degrees
+    deg = g.degrees()
+    uv = g.edges()
+    shorter = np.minimum(deg[uv[:, 0]], deg[uv[:, 1]]).astype(np.int64)
+    abytes = g.m * (15 * L * 8 + 2 * 3 * L * 4 + 16) + int(shorter.sum()) * 5
+    out = {"workload": g.name + " oriented (20% reciprocal)", "n": g.n, "m": g.m, "L": L,
+           "steps": steps, "value": g.m * steps / el, "unit": "edges/s",
+           "ms_per_step": el * 1e3 / steps,
+           "algorithmic_bytes_per_step": abytes,
+           "pipeline_algorithmic_GBps": abytes / (el / steps) / 1e9,
+           "global_classes_nonzero": int((glob != 0).sum())}
+    rng = np.random.default_rng(3)
+    pick = rng.choice(g.m, 500, replace=False)
+    grows = rows.index_select(0, torch.from_numpy(pick).to(dev)).cpu().numpy().view(np.uint64)
+    same = sum(int(np.array_equal(grows[q], OD.edge_row(g, dirs, int(uv[e, 0]), int(uv[e, 1]))))
+               for q, e in enumerate(pick.tolist()))
+    out["parity_sample"] = f"{same}/500 sampled rows identical to the oracle"
+    log(f"[bench] directed: {out['value']:.3e} edges/s, {out['parity_sample']}")
+    del rows, glob, rp, col, ty, d
+    ws.buf = None
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_embedding(args, P, torch, G, dev, stream):
+    """Alg. 5 embeddings of the headline power-law graph for a few typed
+    graphlets: weights from the per-edge rows, then the per-component
+    solve; seconds, iterations and component sizes per case."""
+    g = G.config_graph(2, seed=0, scale=args.scale)
+    L = g.L
+    rp, col, ty = (torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev),
+                   torch.from_numpy(g.types).to(dev))
+    ws = P.Workspace(dev)
+    rows, _ = P.count_typed_graphlets(rp, col, ty, L, workspace=ws, stream=stream)
+    uv = P.edge_list(rp, col, workspace=ws, stream=stream)
+    cases = [(2, (0, 0, 0), 16), (1, (0, 0, 1), 16), (5, (0, 0, 1, 1), 16), (1, (0, 0, 1), 128),
+             (0, (0, 1), 128)]
+    weights = {}
+    torch.cuda.synchronize()
+    for h, ms, _ in cases:
+        if (h, ms) not in weights:
+            t0 = time.perf_counter()
+            weights[(h, ms)] = P.graphlet_weights(rows, uv, ty, L, h, ms, stream=stream)
+            torch.cuda.synchronize()
+            log(f"[bench] weights h{h} {ms}: {1e3 * (time.perf_counter() - t0):.2f} ms")
+    del rows, uv
+    ws.buf = None
+    torch.cuda.empty_cache()
+    out = []
+    for h, ms, dim in cases:
+        w = weights[(h, ms)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Z, ev, comp, its = P.graphlet_embedding(rp, col, w, dim, workspace=ws, stream=stream,
+                                                check=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        c = comp.cpu().numpy()
+        sizes = np.bincount(c[c >= 0]) if (c >= 0).any() else np.zeros(1, dtype=np.int64)
+        sizes = sizes[sizes > 0]
+        rec = {"graphlet": f"h{h}", "types": list(ms), "dim": dim, "seconds": round(el, 3),
+               "iterations": its, "converged": bool(its < 500),
+               "weighted_edges": int((w != 0).sum()), "components": int(sizes.size),
+               "largest_component": int(sizes.max()) if sizes.size else 0,
+               "components_over_64": int((sizes > 64).sum())}
+        out.append(rec)
+        log(f"[bench] embedding {rec}")
+        del Z, ev, comp
+    ws.buf = None
+    torch.cuda.empty_cache()
+    return {"workload": g.name, "n": g.n, "m": g.m, "L": L, "tolerance": 1e-10,
+            "method": "per component: dense Jacobi up to 64 nodes, else Chebyshev-filtered "
+                      "subspace iteration (float64)", "cases": out}
 
 
 def main():

@@ -28,7 +28,9 @@ def _mixed_requests(S, count, seed):
         else:
             g = G.er_graph(int(rng.integers(50, 500)), 6.0, 6, seed=500 + q)
         graphs.append(g)
-    reqs = [S.Request(q, g.row_ptr, g.col, g.types, g.L, arrival=0.004 * q)
+    # bursts of 6 requests 20 ms apart: a burst arrives within microseconds,
+    # faster than any request is served, so requests always meet in a batch
+    reqs = [S.Request(q, g.row_ptr, g.col, g.types, g.L, arrival=0.02 * (q // 6))
             for q, g in enumerate(graphs)]
     return graphs, reqs
 
