@@ -948,7 +948,8 @@ def bench_embedding(args, P, torch, G, dev, stream):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=["single", "batch", "serve"], default="single",
+    ap.add_argument("--mode", choices=["single", "batch", "serve", "directed", "embedding"],
+                    default="single",
                     help="single: the 10M-edge power-law graph (headline); batch: 1e5 small "
                          "graphs in one call; serve: Poisson request stream")
     ap.add_argument("--requests", type=int, default=20000, help="serve mode: number of requests")
@@ -996,6 +997,18 @@ def main():
         return
     if args.mode == "serve":
         bench_serve(args)
+        return
+    if args.mode in ("directed", "embedding"):
+        # one extra leg alone (profiling runs): its summary as the JSON line
+        import torch
+
+        import paper_2010_14058_amd as P
+        from tg_synth import graphs as G
+
+        dev = torch.device("cuda:0")
+        stream = torch.cuda.current_stream(dev)
+        leg = bench_directed if args.mode == "directed" else bench_embedding
+        print(json.dumps({args.mode: leg(args, P, torch, G, dev, stream)}), flush=True)
         return
 
     bench_single(args)
