@@ -41,7 +41,6 @@ namespace {
 constexpr int EMB_MAX_P = 256;     // largest block (dim + oversample)
 constexpr int DENSE_MAX = 64;      // largest component solved densely in LDS
 constexpr int GRAM_ROWS = 2048;    // rows per Gram partial
-constexpr int GRAM_TILE = 32;
 
 // ------------------------------------------------------ edge weights
 
@@ -466,45 +465,60 @@ k_spmm_finish(const int64_t *__restrict__ hptr, int64_t ns, int p, const double 
     }
 }
 
+// fp64 matrix cores: v_mfma_f64_16x16x4f64 multiplies a 16 x 4 by a 4 x 16
+// block; lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
+// D[l / 16 + 4r][l % 16] in register r of its 4-wide accumulator.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ dbl4 mfma_f64(double a, double b, dbl4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int MT = 64;     // output tile edge of the dense products
+constexpr int MK = 32;     // depth staged in LDS per step
+
 // Partial Gram tiles: part[chunk][i][j] = sum over the chunk's rows r of
-// A[r][i] * B[r][j], one 32 x 32 output tile per workgroup.
+// A[r][i] * B[r][j].  A workgroup (4 waves) takes a 64 x 64 tile of the
+// p x p result, each wave 16 of its rows against all 64 columns; the rows
+// of the chunk are staged 32 at a time in LDS (coalesced row segments) and
+// fed to the fp64 matrix cores, the rows being the contraction index.
 __global__ void __launch_bounds__(256)
 k_emb_gram_part(const double *__restrict__ A, const double *__restrict__ B, int64_t n, int p,
                 double *__restrict__ part) {
-    __shared__ double sa[GRAM_TILE][GRAM_TILE + 1];
-    __shared__ double sb[GRAM_TILE][GRAM_TILE + 1];
-    const int tiles = (p + GRAM_TILE - 1) / GRAM_TILE;
-    const int ti = blockIdx.y / tiles, tj = blockIdx.y % tiles;
+    __shared__ double as[MK][MT + 1];
+    __shared__ double bs[MK][MT + 1];
+    const int tiles = (p + MT - 1) / MT;
+    const int i0 = (blockIdx.y / tiles) * MT, j0 = (blockIdx.y % tiles) * MT;
     const int64_t r0 = (int64_t)blockIdx.x * GRAM_ROWS;
     const int64_t r1 = r0 + GRAM_ROWS < n ? r0 + GRAM_ROWS : n;
-    const int tid = threadIdx.x;
-    // each thread: 4 outputs (i = tid / 8, j = (tid % 8) * 4 + 0..3)
-    const int oi = tid / 8, oj = (tid % 8) * 4;
-    double acc[4] = {0, 0, 0, 0};
-    for (int64_t rb = r0; rb < r1; rb += GRAM_TILE) {
-        for (int q = tid; q < GRAM_TILE * GRAM_TILE; q += 256) {
-            const int rr = q / GRAM_TILE, cc = q % GRAM_TILE;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+    dbl4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int64_t rb = r0; rb < r1; rb += MK) {
+        for (int q = tid; q < MK * MT; q += 256) {
+            const int rr = q / MT, cc = q % MT;
             const int64_t r = rb + rr;
-            const int ca = ti * GRAM_TILE + cc, cb = tj * GRAM_TILE + cc;
-            sa[rr][cc] = (r < r1 && ca < p) ? A[(size_t)r * p + ca] : 0.0;
-            sb[rr][cc] = (r < r1 && cb < p) ? B[(size_t)r * p + cb] : 0.0;
+            as[rr][cc] = (r < r1 && i0 + cc < p) ? A[(size_t)r * p + i0 + cc] : 0.0;
+            bs[rr][cc] = (r < r1 && j0 + cc < p) ? B[(size_t)r * p + j0 + cc] : 0.0;
         }
         __syncthreads();
-#pragma unroll 4
-        for (int rr = 0; rr < GRAM_TILE; ++rr) {
-            const double av = sa[rr][oi];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) acc[x] += av * sb[rr][oj + x];
+        for (int kk = 0; kk < MK; kk += 4) {
+            const double a = as[kk + lane / 16][wv * 16 + lane % 16];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t] = mfma_f64(a, bs[kk + lane / 16][t * 16 + lane % 16], acc[t]);
         }
         __syncthreads();
     }
     double *dst = part + (size_t)blockIdx.x * p * p;
-    const int gi = ti * GRAM_TILE + oi;
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
-        const int gj = tj * GRAM_TILE + oj + x;
-        if (gi < p && gj < p) dst[(size_t)gi * p + gj] = acc[x];
-    }
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = i0 + wv * 16 + lane / 16 + 4 * r, j = j0 + t * 16 + lane % 16;
+            if (i < p && j < p) dst[(size_t)i * p + j] = acc[t][r];
+        }
 }
 
 // C = sum of the partials, chunk by chunk in order (a fixed order: the same
@@ -910,33 +924,45 @@ k_emb_chol(double *__restrict__ G, double *__restrict__ Rinv, int p) {
     chol_body<false>(Sym<false>{G, p}, G, Rinv, p);
 }
 
-// Y = X Q (n x p times p x p); a workgroup keeps a 32-column tile of Q in
-// LDS and takes 8 rows at a time.
+// Y = X Q (n x p times p x p) on the fp64 matrix cores: a workgroup (4
+// waves) takes a 64-row x 64-column tile of Y, each wave 16 rows; X's rows
+// and Q's rows are staged 32 deep in LDS.
 __global__ void __launch_bounds__(256)
 k_emb_apply(const double *__restrict__ X, const double *__restrict__ Q, int64_t n, int p,
             double *__restrict__ Y) {
-    extern __shared__ double sq[];   // p x 32
-    const int tiles = (p + 31) / 32;
-    const int tj = blockIdx.y;
-    const int tid = threadIdx.x;
-    for (int q = tid; q < p * 32; q += 256) {
-        const int k = q / 32, c = q % 32;
-        const int j = tj * 32 + c;
-        sq[q] = j < p ? Q[(size_t)k * p + j] : 0.0;
+    __shared__ double xs[MT][MK + 1];
+    __shared__ double qs[MK][MT + 1];
+    const int64_t r0 = (int64_t)blockIdx.x * MT;
+    const int c0 = blockIdx.y * MT;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+    dbl4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < p; k0 += MK) {
+        for (int q = tid; q < MT * MK; q += 256) {
+            const int rr = q / MK, kk = q % MK;
+            const int64_t r = r0 + rr;
+            xs[rr][kk] = (r < n && k0 + kk < p) ? X[(size_t)r * p + k0 + kk] : 0.0;
+            const int kq = q / MT, cc = q % MT;
+            qs[kq][cc] = (k0 + kq < p && c0 + cc < p) ? Q[(size_t)(k0 + kq) * p + c0 + cc] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < MK; kk += 4) {
+            const double a = xs[wv * 16 + lane % 16][kk + lane / 16];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t] = mfma_f64(a, qs[kk + lane / 16][t * 16 + lane % 16], acc[t]);
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    (void)tiles;
-    const int ri = tid / 32, c = tid % 32;
-    const int j = tj * 32 + c;
-    for (int64_t r0 = (int64_t)blockIdx.x * 64; r0 < n && r0 < (int64_t)blockIdx.x * 64 + 64;
-         r0 += 8) {
-        const int64_t r = r0 + ri;
-        if (r >= n) continue;
-        const double *xr = X + (size_t)r * p;
-        double acc = 0.0;
-        for (int k = 0; k < p; ++k) acc += xr[k] * sq[k * 32 + c];
-        if (j < p) Y[(size_t)r * p + j] = acc;
-    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t row = r0 + wv * 16 + lane / 16 + 4 * r;
+            const int col = c0 + t * 16 + lane % 16;
+            if (row < n && col < p) Y[(size_t)row * p + col] = acc[t][r];
+        }
 }
 
 // res[j] = ||MX[:, j] - theta_j X[:, j]||^2 partial sums per chunk, then
@@ -1267,16 +1293,16 @@ tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int6
         int p = (int)(ns < p0 ? ns : p0);
         const int want = dim < p ? dim : p;
         const int64_t chunks = (ns + GRAM_ROWS - 1) / GRAM_ROWS;
-        int tiles = 0;
         auto gram = [&](const double *A, const double *B, double *C) -> hipError_t {
-            k_emb_gram_part<<<dim3((unsigned)chunks, (unsigned)(tiles * tiles)), 256, 0, st>>>(
+            const int mt = (p + MT - 1) / MT;
+            k_emb_gram_part<<<dim3((unsigned)chunks, (unsigned)(mt * mt)), 256, 0, st>>>(
                 A, B, ns, p, part);
             k_emb_gram_sum<<<(unsigned)((p * p + 255) / 256), 256, 0, st>>>(part, chunks, p, C);
             return hipGetLastError();
         };
         auto apply = [&](const double *A, const double *Q, double *out) -> hipError_t {
-            k_emb_apply<<<dim3((unsigned)((ns + 63) / 64), (unsigned)tiles), 256,
-                          (size_t)p * 32 * sizeof(double), st>>>(A, Q, ns, p, out);
+            k_emb_apply<<<dim3((unsigned)((ns + MT - 1) / MT), (unsigned)((p + MT - 1) / MT)), 256,
+                          0, st>>>(A, Q, ns, p, out);
             return hipGetLastError();
         };
         // out = alpha S A + beta A + gamma Zb
@@ -1353,7 +1379,6 @@ tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int6
             return r;
         };
         // start: a random block, orthonormalised twice, and its Ritz vectors
-        tiles = (p + GRAM_TILE - 1) / GRAM_TILE;
         k_emb_random<<<(unsigned)((ns * p + 255) / 256), 256, 0, st>>>(R[0], ns, p,
                                                                       seed ^ mix64_host(root));
         EMB_CHK(hipGetLastError());
@@ -1383,8 +1408,7 @@ tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int6
                     R[0], ns, p, q, seed ^ mix64_host(root + (uint64_t)it), R[1]);
                 EMB_CHK(hipGetLastError());
                 p = q;
-                tiles = (p + GRAM_TILE - 1) / GRAM_TILE;
-                EMB_CHK(orth(R[1], Yp));
+                        EMB_CHK(orth(R[1], Yp));
                 EMB_CHK(orth(Yp, R[2]));
                 EMB_CHK(rayleigh_ritz(R[2], R[0], R[1]));
                 chk = worst();
