@@ -316,8 +316,9 @@ tg_status tg_edge_list(const int64_t *row_ptr, const int32_t *col, int64_t n, in
  * c01; 3-node classes (3-paths and triangles) at 4L^2 + ((t0*L + t1)*L +
  * t2)*64 + c01*16 + c02*4 + c12.  Entries that are not canonical keys are
  * 0.  Workspace: tg_directed_workspace_bytes(n, nnz, L) bytes, device,
- * 256-byte aligned.  Errors as for tg_count_typed_graphlets.  Returns when
- * the results are complete on `stream`. */
+ * 256-byte aligned.  Errors as for tg_count_typed_graphlets; n >= 2^31 or
+ * nnz >= 2^33 gives TG_E_TOO_LARGE.  Returns when the results are complete
+ * on `stream`. */
 int32_t tg_directed_row_width(int32_t L);
 int64_t tg_directed_global_width(int32_t L);
 size_t tg_directed_workspace_bytes(int64_t n, int64_t nnz, int32_t L);

@@ -15,10 +15,12 @@
 // under type-preserving isomorphism), named by a canonical key: the
 // smallest (types..., pair codes...) over every numbering of the nodes,
 // a pair code for nodes x < y being 0 none, 1 x -> y, 2 y -> x, 3 both.
-// The rows are folded into per-workgroup LDS histograms of canonical keys
-// (global atomics when the key space is too large for LDS), and each
-// 3-node class is divided by its edge count (a triangle is met from its 3
-// edges, a 3-path from its 2).
+// A row's columns name their classes only through the edge's own class
+// (its endpoint types and direction), so the edges are sorted by that
+// class, the rows summed per class and column in registers, and only the
+// 3L^2 x 15L sums mapped to canonical keys; each 3-node class is then
+// divided by its edge count (a triangle is met from its 3 edges, a 3-path
+// from its 2).
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -28,7 +30,6 @@
 namespace tg {
 namespace {
 
-constexpr int DIR_LDS_KEYS = 16384;   // widest global layout histogrammed in LDS (128 KiB)
 
 // Direction code of a CSR slot relative to its row's node: 0 out, 1 in, 2 both.
 __device__ __forceinline__ int dir_code(uint8_t d) { return d == 1 ? 0 : d == 2 ? 1 : 2; }
@@ -204,61 +205,112 @@ __device__ __forceinline__ uint32_t end_arcs(int x, int c) {
     return c == 0 ? out : c == 1 ? in : (out | in);
 }
 
-// Rows -> sums per canonical key: one wave per edge, lanes over columns;
-// histogram in LDS (keys < DIR_LDS_KEYS) or global atomics.
-template <bool LDS>
-__global__ void __launch_bounds__(1024)
-k_dir_global(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
-             const uint8_t *__restrict__ dir, const uint8_t *__restrict__ types,
-             const int32_t *__restrict__ esrc, const int64_t *__restrict__ eslot,
-             const uint64_t *__restrict__ rows, int64_t m, int L, int64_t width,
-             unsigned long long *__restrict__ acc) {
-    __shared__ unsigned long long h[LDS ? DIR_LDS_KEYS : 1];
-    if (LDS) {
-        for (int64_t q = threadIdx.x; q < width; q += blockDim.x) h[q] = 0;
-        __syncthreads();
-    }
+// Edge class of every edge: (type of i, type of j, direction bits of the
+// edge) as (ti * L + tj) * 3 + bits - 1; sorted by it, the edges of one class
+// are contiguous.
+__global__ void k_dir_class(const int32_t *__restrict__ col, const uint8_t *__restrict__ dir,
+                            const uint8_t *__restrict__ types, const int32_t *__restrict__ esrc,
+                            const int64_t *__restrict__ eslot, int64_t m, int L,
+                            uint64_t *__restrict__ key, uint32_t *__restrict__ val) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    const int64_t s = eslot[e];
+    key[e] = ((uint64_t)types[esrc[e]] * L + types[col[s]]) * 3 + (dir[s] - 1);
+    val[e] = (uint32_t)e;
+}
+
+// Column sums of the rows per edge class: each wave walks a contiguous run
+// of the class-sorted edges, lanes owning columns, summing in registers and
+// adding to csum[class][column] whenever the class changes.
+__global__ void __launch_bounds__(256)
+k_dir_class_sums(const uint64_t *__restrict__ skey, const uint32_t *__restrict__ sval,
+                 const uint64_t *__restrict__ rows, int64_t m, int L, int64_t per_wave,
+                 unsigned long long *__restrict__ csum) {
+    constexpr int CPL = (15 * TG_MAX_L + WAVE - 1) / WAVE;
     const int lane = lane_id();
     const int W = 15 * L;
-    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
-    for (int64_t e = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; e < m;
-         e += nwaves) {
-        const int32_t i = esrc[e];
-        const int64_t sij = eslot[e];
-        const int32_t j = col[sij];
-        const int ti = types[i], tj = types[j];
-        const uint8_t d = dir[sij];
-        const uint32_t eij = ((d & 1) ? 1u << 1 : 0u) | ((d & 2) ? 1u << 3 : 0u);   // 0->1, 1->0
-        const uint64_t *row = rows + (size_t)e * W;
-        if (lane == 0) {
-            const int64_t k2 = canon_key2(ti, tj, eij, L);
-            if (LDS) atomicAdd(&h[k2], 1ull);
-            else atomicAdd(&acc[k2], 1ull);
-        }
-        for (int q = lane; q < W; q += WAVE) {
-            const uint64_t v = row[q];
-            if (!v) continue;
-            int t;
-            uint32_t arcs = eij;
-            if (q < 9 * L) {
-                t = q / 9;
-                arcs |= end_arcs(0, (q / 3) % 3) | end_arcs(1, q % 3);
-            } else if (q < 12 * L) {
-                t = (q - 9 * L) / 3;
-                arcs |= end_arcs(0, (q - 9 * L) % 3);
-            } else {
-                t = (q - 12 * L) / 3;
-                arcs |= end_arcs(1, (q - 12 * L) % 3);
+    const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int64_t e0 = wid * per_wave;
+    const int64_t e1 = e0 + per_wave < m ? e0 + per_wave : m;
+    if (e0 >= e1) return;
+    uint64_t acc[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) acc[c] = 0;
+    uint64_t cls = skey[e0];
+    for (int64_t e = e0; e < e1; ++e) {
+        const uint64_t k = skey[e];
+        if (k != cls) {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int q = lane + c * WAVE;
+                if (q < W && acc[c]) atomicAdd(&csum[cls * W + q], (unsigned long long)acc[c]);
+                acc[c] = 0;
             }
-            const int64_t key = canon_key3(ti, tj, t, arcs, L);
-            if (LDS) atomicAdd(&h[key], (unsigned long long)v);
-            else atomicAdd(&acc[key], (unsigned long long)v);
+            cls = k;
+        }
+        const uint64_t *row = rows + (size_t)sval[e] * W;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int q = lane + c * WAVE;
+            if (q < W) acc[c] += row[q];
         }
     }
-    if (LDS) {
-        __syncthreads();
-        for (int64_t q = threadIdx.x; q < width; q += blockDim.x)
-            if (h[q]) atomicAdd(&acc[q], h[q]);
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const int q = lane + c * WAVE;
+        if (q < W && acc[c]) atomicAdd(&csum[cls * W + q], (unsigned long long)acc[c]);
+    }
+}
+
+// Class sums -> canonical keys: one thread per (edge class, column); the
+// edge itself is counted once per edge of the class (its 2-node key).
+__global__ void k_dir_keys(const unsigned long long *__restrict__ csum,
+                           const unsigned long long *__restrict__ ccount, int L,
+                           unsigned long long *__restrict__ acc) {
+    const int W = 15 * L;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t classes = 3 * (int64_t)L * L;
+    if (t >= classes * (W + 1)) return;
+    const int64_t cls = t / (W + 1);
+    const int q = (int)(t % (W + 1)) - 1;          // -1: the edge's own class
+    const int d = (int)(cls % 3) + 1;
+    const int ti = (int)(cls / 3 / L), tj = (int)(cls / 3 % L);
+    const uint32_t eij = ((d & 1) ? 1u << 1 : 0u) | ((d & 2) ? 1u << 3 : 0u);   // 0->1, 1->0
+    if (q < 0) {
+        const unsigned long long v = ccount[cls];
+        if (v) atomicAdd(&acc[canon_key2(ti, tj, eij, L)], v);
+        return;
+    }
+    const unsigned long long v = csum[cls * W + q];
+    if (!v) return;
+    int tt;
+    uint32_t arcs = eij;
+    if (q < 9 * L) {
+        tt = q / 9;
+        arcs |= end_arcs(0, (q / 3) % 3) | end_arcs(1, q % 3);
+    } else if (q < 12 * L) {
+        tt = (q - 9 * L) / 3;
+        arcs |= end_arcs(0, (q - 9 * L) % 3);
+    } else {
+        tt = (q - 12 * L) / 3;
+        arcs |= end_arcs(1, (q - 12 * L) % 3);
+    }
+    atomicAdd(&acc[canon_key3(ti, tj, tt, arcs, L)], v);
+}
+
+// Number of edges per class (the run lengths of the sorted keys).
+__global__ void k_dir_class_count(const uint64_t *__restrict__ skey, int64_t m,
+                                  unsigned long long *__restrict__ ccount) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    if (e == m - 1 || skey[e] != skey[e + 1]) {
+        // e ends a run: its length is e + 1 minus the start (found by search)
+        int64_t lo = 0, hi = e;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (skey[mid] < skey[e]) lo = mid + 1; else hi = mid;
+        }
+        ccount[skey[e]] = (unsigned long long)(e + 1 - lo);
     }
 }
 
@@ -280,7 +332,8 @@ __global__ void k_dir_finalize(const unsigned long long *__restrict__ acc, int64
 }
 
 struct DirLayout {
-    size_t status, ucount, eoff, stmp, deg3, esrc, eslot, rows, acc, total;
+    size_t status, ucount, eoff, stmp, deg3, esrc, eslot, rows, acc, ckey, ckey_tmp, cval, cval_tmp,
+        sort_tmp, csum, ccount, total;
 };
 
 DirLayout dir_layout(int64_t n, int64_t nnz, int L, bool own_rows) {
@@ -301,6 +354,14 @@ DirLayout dir_layout(int64_t n, int64_t nnz, int L, bool own_rows) {
     y.eslot = take(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
     y.rows = take(own_rows ? sizeof(uint64_t) * (size_t)(m > 0 ? m : 1) * 15 * L : 0);
     y.acc = take(sizeof(uint64_t) * (size_t)(4 * L * L + 64 * L * L * L));
+    const size_t m1 = (size_t)(m > 0 ? m : 1);
+    y.ckey = take(sizeof(uint64_t) * m1);
+    y.ckey_tmp = take(sizeof(uint64_t) * m1);
+    y.cval = take(sizeof(uint32_t) * m1);
+    y.cval_tmp = take(sizeof(uint32_t) * m1);
+    y.sort_tmp = take(sort_tmp_need(m > 0 ? m : 1));
+    y.csum = take(sizeof(uint64_t) * (size_t)(3 * L * L) * 15 * L);
+    y.ccount = take(sizeof(uint64_t) * (size_t)(3 * L * L));
     y.total = o;
     return y;
 }
@@ -341,7 +402,7 @@ tg_status tg_count_directed(const int64_t *row_ptr, const int32_t *col, const ui
     if (n < 0 || nnz < 0 || (nnz & 1) || !row_ptr || (n > 0 && !types) ||
         (nnz > 0 && (!col || !dir)) || !workspace || ((uintptr_t)workspace & 255u))
         return TG_E_INVALID_ARG;
-    if (n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 40)) return TG_E_TOO_LARGE;
+    if (n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 33)) return TG_E_TOO_LARGE;
     const DirLayout y = dir_layout(n, nnz, L, per_edge == nullptr);
     if (ws_bytes < y.total) return TG_E_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
@@ -380,20 +441,30 @@ tg_status tg_count_directed(const int64_t *row_ptr, const int32_t *col, const ui
                                                    L, rows);
         DIR_CHK(hipGetLastError());
         if (global_counts) {
-            int dev = 0, cus = 0;
-            DIR_CHK(hipGetDevice(&dev));
-            DIR_CHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-            if (width <= DIR_LDS_KEYS) {
-                int64_t b = (m + 15) / 16;
-                if (b > cus) b = cus;
-                k_dir_global<true><<<(unsigned)(b > 0 ? b : 1), 1024, 0, st>>>(
-                    row_ptr, col, dir, types, esrc, eslot, rows, m, L, width, acc);
-            } else {
-                int64_t b = (m + 15) / 16;
-                if (b > (int64_t)cus * 8) b = (int64_t)cus * 8;
-                k_dir_global<false><<<(unsigned)(b > 0 ? b : 1), 1024, 0, st>>>(
-                    row_ptr, col, dir, types, esrc, eslot, rows, m, L, width, acc);
-            }
+            uint64_t *ckey = reinterpret_cast<uint64_t *>(w + y.ckey);
+            uint32_t *cval = reinterpret_cast<uint32_t *>(w + y.cval);
+            unsigned long long *csum = reinterpret_cast<unsigned long long *>(w + y.csum);
+            unsigned long long *ccount = reinterpret_cast<unsigned long long *>(w + y.ccount);
+            const int64_t classes = 3 * (int64_t)L * L;
+            DIR_CHK(launch_fill_u64(reinterpret_cast<uint64_t *>(csum), 0, classes * 15 * L, st));
+            DIR_CHK(launch_fill_u64(reinterpret_cast<uint64_t *>(ccount), 0, classes, st));
+            k_dir_class<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(col, dir, types, esrc, eslot, m,
+                                                                      L, ckey, cval);
+            DIR_CHK(hipGetLastError());
+            uint64_t *skey = nullptr;
+            uint32_t *sval = nullptr;
+            int bits_needed = 1;
+            while ((int64_t(1) << bits_needed) < classes) ++bits_needed;
+            DIR_CHK(radix_sort(ckey, reinterpret_cast<uint64_t *>(w + y.ckey_tmp), cval,
+                               reinterpret_cast<uint32_t *>(w + y.cval_tmp), m, bits_needed,
+                               w + y.sort_tmp, nullptr, st, &skey, &sval));
+            const int64_t waves = (int64_t)waves_grid(m) * 4;
+            const int64_t per_wave = (m + waves - 1) / waves;
+            k_dir_class_sums<<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(skey, sval, rows, m, L,
+                                                                          per_wave, csum);
+            k_dir_class_count<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(skey, m, ccount);
+            const int64_t items = classes * (15 * L + 1);
+            k_dir_keys<<<(unsigned)((items + 255) / 256), 256, 0, st>>>(csum, ccount, L, acc);
             DIR_CHK(hipGetLastError());
         }
     }
