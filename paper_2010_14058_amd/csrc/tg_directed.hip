@@ -114,15 +114,22 @@ __global__ void k_dir_edges_of(const int64_t *__restrict__ rp, const int32_t *__
     }
 }
 
+constexpr int DIR_SAMPLE = 1024;   // LDS sample of a long list (entries per wave)
+
 // One wave per edge (i, j): the common neighbours k by searching each
 // element of the shorter list in the longer one, counted per (type of k,
-// direction at i, direction at j) in LDS; then the row.
+// direction at i, direction at j) in LDS; then the row.  When the shorter
+// list fills at least half a wave and the longer one is long, every
+// stride-th entry of the longer list is copied to LDS first (at most
+// DIR_SAMPLE entries): a probe searches the sample in LDS and then only the
+// stride entries between two samples in global memory.
 __global__ void __launch_bounds__(256)
 k_dir_rows(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
            const uint8_t *__restrict__ dir, const uint8_t *__restrict__ types,
            const uint32_t *__restrict__ deg3, const int32_t *__restrict__ esrc,
            const int64_t *__restrict__ eslot, int64_t m, int L, uint64_t *__restrict__ rows) {
     __shared__ uint32_t tri[256 / WAVE][9 * TG_MAX_L];
+    __shared__ int32_t samp[256 / WAVE][DIR_SAMPLE];
     const int lane = lane_id(), wv = threadIdx.x / WAVE;
     const int W = 15 * L;
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
@@ -136,10 +143,29 @@ k_dir_rows(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
         const bool i_short = ie - ib <= je - jb;
         const int64_t sb = i_short ? ib : jb, se = i_short ? ie : je;
         const int64_t lb = i_short ? jb : ib, le = i_short ? je : ie;
+        int64_t stride = 0;
+        int nsamp = 0;
+        if (se - sb >= WAVE / 2 && le - lb > 2 * WAVE) {
+            stride = (le - lb + DIR_SAMPLE - 1) / DIR_SAMPLE;
+            nsamp = (int)((le - lb + stride - 1) / stride);
+            for (int q = lane; q < nsamp; q += WAVE) samp[wv][q] = col[lb + (int64_t)q * stride];
+            wave_sync();
+        }
         for (int64_t s = sb + lane; s < se; s += WAVE) {
             const int32_t k = col[s];
-            const int64_t r = lower_bound(col, lb, le, k);
-            if (r < le && col[r] == k) {
+            int64_t lo = lb, hi = le;
+            if (stride) {
+                int a = 0, b = nsamp;             // first sample above k
+                while (a < b) {
+                    const int mid = (a + b) >> 1;
+                    if (samp[wv][mid] <= k) a = mid + 1; else b = mid;
+                }
+                if (a == 0) continue;             // k below the whole list
+                lo = lb + (int64_t)(a - 1) * stride;
+                hi = lo + stride < le ? lo + stride : le;
+            }
+            const int64_t r = lower_bound(col, lo, hi, k);
+            if (r < hi && col[r] == k) {
                 const int cs = dir_code(dir[s]), cl = dir_code(dir[r]);
                 const int a = i_short ? cs : cl, b = i_short ? cl : cs;
                 atomicAdd(&tri[wv][types[k] * 9 + a * 3 + b], 1u);
