@@ -800,6 +800,7 @@ def bench_single(args):
         result["config3"] = bench_config3(args, P, torch, G, dev, stream, peak["GBps"])
     if not args.no_extra:
         P.set_tuning(**defaults)
+        result["position_aware"] = bench_position_aware(args, P, torch, G, dev, stream)
         result["directed"] = bench_directed(args, P, torch, G, dev, stream)
         result["embedding"] = bench_embedding(args, P, torch, G, dev, stream)
         result["batch"] = run_batch_workload(args, args.graphs, args.single_sample,
@@ -844,6 +845,52 @@ def bench_config3(args, P, torch, G, dev, stream, peak_gbps):
                                 f"8 highest-degree nodes) identical to the oracle; {dt:.1f} s")
         log(f"[bench] tripartite: {out['parity_sample']}")
     del rows, glob, g._dev
+    ws.buf = None
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_position_aware(args, P, torch, G, dev, stream, steps=3):
+    """Position-aware typed counts (Sec. 5) of the headline power-law graph:
+    per-edge rows (3L + 9L^2 + 6P columns) and global classes per step, and
+    a sampled parity check of rows against the oracle."""
+    import oracle   # parity sample only, outside the timed steps
+
+    g = G.config_graph(2, seed=0, scale=args.scale)
+    L = g.L
+    rp, col, ty = (torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev),
+                   torch.from_numpy(g.types).to(dev))
+    W = P.pa_row_width(L)
+    rows = torch.empty((g.m, W), dtype=torch.int64, device=dev)
+    glob = torch.empty(P.pa_global_width(L), dtype=torch.int64, device=dev)
+    ws = P.Workspace(dev)
+    P.count_position_aware(rp, col, ty, L, out_rows=rows, out_global=glob, workspace=ws,
+                           stream=stream)                                  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        P.count_position_aware(rp, col, ty, L, out_rows=rows, out_global=glob, workspace=ws,
+                               stream=stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out = {"workload": g.name, "n": g.n, "m": g.m, "L": L, "row_width": W,
+           "per_edge_table_GB": round(g.m * W * 8 / 1e9, 2), "steps": steps,
+           "value": g.m * steps / el, "unit": "edges/s", "ms_per_step": el * 1e3 / steps,
+           "global_classes_nonzero": int((glob != 0).sum())}
+    uv = g.edges()
+    rng = np.random.default_rng(5)
+    deg = g.degrees()
+    hub = np.flatnonzero(np.maximum(deg[uv[:, 0]], deg[uv[:, 1]]) > 5000)
+    pick = np.unique(np.concatenate([rng.choice(g.m, 64, replace=False),
+                                     rng.choice(hub, min(16, hub.size), replace=False)]))
+    t1 = time.perf_counter()
+    want = oracle.pa_edge_rows(g, uv[pick], threads=host_threads())
+    got = rows.index_select(0, torch.from_numpy(pick).to(dev)).cpu().numpy().view(np.uint64)
+    same = int(np.sum(np.all(got == want, axis=1)))
+    out["parity_sample"] = (f"{same}/{len(pick)} sampled rows (64 uniform, 16 hub-incident) "
+                            f"identical to the oracle; {time.perf_counter() - t1:.1f} s")
+    log(f"[bench] position-aware: {out['value']:.3e} edges/s, {out['parity_sample']}")
+    del rows, glob, rp, col, ty
     ws.buf = None
     torch.cuda.empty_cache()
     return out
@@ -948,7 +995,8 @@ def bench_embedding(args, P, torch, G, dev, stream):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=["single", "batch", "serve", "directed", "embedding"],
+    ap.add_argument("--mode", choices=["single", "batch", "serve", "directed", "embedding",
+                                       "position_aware"],
                     default="single",
                     help="single: the 10M-edge power-law graph (headline); batch: 1e5 small "
                          "graphs in one call; serve: Poisson request stream")
@@ -998,7 +1046,7 @@ def main():
     if args.mode == "serve":
         bench_serve(args)
         return
-    if args.mode in ("directed", "embedding"):
+    if args.mode in ("directed", "embedding", "position_aware"):
         # one extra leg alone (profiling runs): its summary as the JSON line
         import torch
 
@@ -1007,7 +1055,8 @@ def main():
 
         dev = torch.device("cuda:0")
         stream = torch.cuda.current_stream(dev)
-        leg = bench_directed if args.mode == "directed" else bench_embedding
+        leg = {"directed": bench_directed, "embedding": bench_embedding,
+               "position_aware": bench_position_aware}[args.mode]
         print(json.dumps({args.mode: leg(args, P, torch, G, dev, stream)}), flush=True)
         return
 
