@@ -349,3 +349,76 @@ def test_embedding_iteration_limit():
     Z, ev, comp, its = P.graphlet_embedding(rp, col, wd, 16, max_iter=1, degree=2, tol=1e-14,
                                             check=False)
     assert its == 1
+
+
+def test_embedding_full_size_properties(oracle_mod):
+    """The 1M-node, 10M-edge power-law configuration, typed 3-paths {0,0,1}
+    (a 649k-node component and a small one) and edges {0,1} (6,160
+    components) at D = 16: component ids against scipy's connected
+    components of the weighted graph; eigenvalues ascending in [0, 2) with
+    0 first; the eigenvectors orthonormal with Laplacian residuals
+    ||L u - lambda u|| below 1e-8 (scipy sparse products on the host); the
+    small components' spectra and projectors against the oracle's dense
+    solve, on a sample of them."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+
+    import torch
+
+    import paper_2010_14058_amd as P
+
+    g = G.config_graph(2, seed=0)
+    rp, col, ty, rows, uv = _device_graph(g)
+    uvn = uv.cpu().numpy()
+    for h, ms in ((1, (0, 0, 1)), (0, (0, 1))):
+        w = P.graphlet_weights(rows, uv, ty, g.L, h, ms)
+        torch.cuda.synchronize()
+        wn = w.cpu().numpy().view(np.uint64)
+        print(f"[gpu] full-size embedding h{h} {ms}", flush=True)
+        U, ev, comp, its = P.graphlet_embedding(rp, col, w, 16, raw=True, tol=1e-10)
+        torch.cuda.synchronize()
+        U, ev, comp = U.cpu().numpy(), ev.cpu().numpy(), comp.cpu().numpy()
+        keep = wn > 0
+        Wm = sp.coo_matrix((wn[keep].astype(np.float64), (uvn[keep, 0], uvn[keep, 1])),
+                           shape=(g.n, g.n)).tocsr()
+        Wm = Wm + Wm.T
+        deg = np.asarray(Wm.sum(axis=1)).ravel()
+        act = deg > 0
+        nc, lab = connected_components(Wm, directed=False)
+        # components: same partition, each named by its smallest node id
+        first = np.full(nc, g.n, dtype=np.int64)
+        np.minimum.at(first, lab[act], np.flatnonzero(act))
+        want = np.where(act, first[lab], -1)
+        np.testing.assert_array_equal(comp, want)
+        roots, sizes = np.unique(comp[comp >= 0], return_counts=True)
+        s = np.where(act, 1.0 / np.sqrt(np.where(act, deg, 1.0)), 0.0)
+        Sm = sp.diags(s) @ Wm @ sp.diags(s)
+        big = roots[sizes > 64]
+        for r in big.tolist():
+            nodes = np.flatnonzero(comp == r)
+            k = min(16, nodes.size)
+            lam = ev[r, :k]
+            assert abs(lam[0]) < 1e-9 and np.all(np.diff(lam) >= -1e-12) and lam[-1] < 2
+            Uc = U[nodes, :k]
+            np.testing.assert_allclose(Uc.T @ Uc, np.eye(k), rtol=0, atol=1e-9)
+            Ufull = np.zeros((g.n, k))
+            Ufull[nodes] = Uc
+            res = np.linalg.norm(Ufull - Sm @ Ufull - Ufull * lam[None, :], axis=0)
+            assert res.max() < 1e-8, (r, res.max())
+        # a sample of the small components against the oracle's dense solve
+        # (each component's induced subgraph, ids renumbered in order)
+        small = roots[sizes <= 64]
+        rng = np.random.default_rng(1)
+        ce = np.where(comp[uvn[:, 0]] == comp[uvn[:, 1]], comp[uvn[:, 0]], -1)
+        for r in rng.choice(small, min(100, small.size), replace=False).tolist():
+            nodes = np.flatnonzero(comp == r)
+            em = ce == r
+            loc = np.searchsorted(nodes, uvn[em])
+            crp, ccol = G.csr_from_edges(nodes.size, loc[:, 0], loc[:, 1])
+            gc = G.Graph(crp, ccol, g.types[nodes], g.L, f"component {r}")
+            vals, vecs, _ = oracle_mod.laplacian_spectrum(gc, wn[em])
+            k = min(16, nodes.size)
+            np.testing.assert_allclose(ev[r, :k], vals[:k], rtol=0, atol=1e-9)
+            if k == nodes.size or vals[k] - vals[k - 1] > 1e-3:
+                Pg = U[nodes, :k] @ U[nodes, :k].T
+                np.testing.assert_allclose(Pg, vecs[:, :k] @ vecs[:, :k].T, rtol=0, atol=1e-7)
