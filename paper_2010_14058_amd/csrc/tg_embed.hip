@@ -17,16 +17,18 @@
 // eigenvalues are the wanted ones) with a block of p = dim + oversample
 // vectors: each iteration filters the block with a Chebyshev polynomial
 // of M that damps [0, b] (b the block's smallest Ritz value) and keeps the
-// top of the spectrum, orthonormalises it (eigen-decomposition of its Gram
-// matrix, twice), and takes Ritz vectors (eigen-decomposition of its
-// projection of M), until the dim wanted residuals ||M x - theta x|| fall
-// below the tolerance.  All of it runs in this file's kernels: a weighted
-// SpMM over the CSR restricted to the component (one wave per row, the
-// block stored row-major so a neighbour's row is one coalesced read),
-// tiled tall-skinny Gram products with a fixed-order reduction, and a
-// one-workgroup Jacobi eigensolver for the p x p matrices.  Nodes of zero
-// weighted degree are in no instance of H and no component: their rows
-// stay zero.
+// top of the spectrum, orthonormalises it (Cholesky QR, twice), and takes
+// Ritz vectors (eigen-decomposition of its projection of M), until the dim
+// wanted residuals ||M x - theta x|| fall below the tolerance; a block
+// whose residuals stall (a cut inside an eigenvalue cluster) is widened.
+// All of it runs in this file's kernels: an SpMM over the component's own
+// CSR of S (a wave per row, long rows split into fixed items summed in
+// order, the block stored row-major so a neighbour's row is one coalesced
+// read), Gram products and block-times-matrix products on the fp64 matrix
+// cores with a fixed-order reduction over row chunks, and one-workgroup
+// Cholesky and block-Jacobi kernels for the p x p matrices (the packed
+// upper triangle in LDS up to p = 192).  Nodes of zero weighted degree are
+// in no instance of H and no component: their rows stay zero.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
