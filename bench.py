@@ -446,6 +446,9 @@ def run_serve_workload(args, requests: int, pool: int, rate: float, workers: int
     srv.close()
     rep = srv.report()
     del srv
+    import gc
+
+    gc.collect()                 # the arena must be gone before the plain path is timed
     torch.cuda.empty_cache()
     P.set_tuning(**defaults)
     log(f"[bench] serving report: {rep}")
@@ -1004,10 +1007,10 @@ def main():
     ap.add_argument("--pool", type=int, default=400,
                     help="serve mode: distinct graphs the requests are drawn from")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve mode: arrivals per second")
-    ap.add_argument("--workers", type=int, default=2, help="serve mode: concurrent batches")
+    ap.add_argument("--workers", type=int, default=4, help="serve mode: concurrent batches")
     ap.add_argument("--single-edges", type=int, default=1 << 17,
                     help="serve mode: requests with at least this many edges run as single calls")
-    ap.add_argument("--hbm-budget-gb", type=float, default=96.0, help="serve mode: admission budget")
+    ap.add_argument("--hbm-budget-gb", type=float, default=160.0, help="serve mode: admission budget")
     ap.add_argument("--max-batch-edges", type=int, default=8_000_000,
                     help="serve mode: edges per batch at most")
     ap.add_argument("--graphs", type=int, default=100_000, help="batch mode: number of graphs")

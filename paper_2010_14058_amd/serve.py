@@ -143,6 +143,7 @@ class Server:
         self.collector.join()
         self.stats = self.server_stats()
         rc = _lib.load().tg_server_destroy(self.handle)
+        self.arena = None            # results were copied out; the device memory goes back
         if rc:
             raise _lib.TGError(rc, "tg_server_destroy")
 
