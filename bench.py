@@ -926,11 +926,27 @@ def bench_directed(args, P, torch, G, dev, stream, steps=3):
     uv = g.edges()
     shorter = np.minimum(deg[uv[:, 0]], deg[uv[:, 1]]).astype(np.int64)
     abytes = g.m * (15 * L * 8 + 2 * 3 * L * 4 + 16) + int(shorter.sum()) * 5
+    # one more call with per-kernel HIP events (outside the timed steps)
+    P.set_timing(True)
+    rows, glob = P.count_directed(rp, col, d, ty, L, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    ks = P.kernel_sums()
+    P.set_timing(False)
+    rows_ms = ks.get("dir_rows", {}).get("ms", 0.0)
+    roof = None
+    if rows_ms > 0:
+        ach = abytes / (rows_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": "k_dir_rows", "achieved": ach, "peak": 8000.0,
+                "unit": "GB/s", "frac": ach / 8000.0, "traffic": None, "avg_ms": rows_ms,
+                "algorithmic_bytes_per_launch": abytes, "work_unit": "edge",
+                "units_per_launch": g.m}
     out = {"workload": g.name + " oriented (20% reciprocal)", "n": g.n, "m": g.m, "L": L,
            "steps": steps, "value": g.m * steps / el, "unit": "edges/s",
            "ms_per_step": el * 1e3 / steps,
            "algorithmic_bytes_per_step": abytes,
            "pipeline_algorithmic_GBps": abytes / (el / steps) / 1e9,
+           "roofline": roof,
+           "kernels_ms": {k: round(v["ms"], 3) for k, v in ks.items()},
            "global_classes_nonzero": int((glob != 0).sum())}
     rng = np.random.default_rng(3)
     pick = rng.choice(g.m, 500, replace=False)
@@ -970,6 +986,7 @@ def bench_embedding(args, P, torch, G, dev, stream):
     ws.buf = None
     torch.cuda.empty_cache()
     out = []
+    P.set_timing(True)          # per-kernel-class HIP events (a few microseconds per launch)
     for h, ms, dim in cases:
         w = weights[(h, ms)]
         torch.cuda.synchronize()
@@ -978,6 +995,7 @@ def bench_embedding(args, P, torch, G, dev, stream):
                                                 check=False)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        ks = P.kernel_sums()
         c = comp.cpu().numpy()
         sizes = np.bincount(c[c >= 0]) if (c >= 0).any() else np.zeros(1, dtype=np.int64)
         sizes = sizes[sizes > 0]
@@ -985,10 +1003,34 @@ def bench_embedding(args, P, torch, G, dev, stream):
                "iterations": its, "converged": bool(its < 500),
                "weighted_edges": int((w != 0).sum()), "components": int(sizes.size),
                "largest_component": int(sizes.max()) if sizes.size else 0,
-               "components_over_64": int((sizes > 64).sum())}
+               "components_over_64": int((sizes > 64).sum()),
+               "kernels_ms": {k: round(v["ms"], 2) for k, v in ks.items()}}
+        sp = ks.get("spmm")
+        if sp and sp["ms"] > 0:
+            rec["spmm_GBps"] = round(sp["units"] / (sp["ms"] * 1e-3) / 1e9, 1)
+        mf = [ks[k] for k in ("gram", "apply") if k in ks and ks[k]["ms"] > 0]
+        if mf:
+            rec["mfma_TFLOPs"] = round(sum(v["units"] for v in mf) /
+                                       (sum(v["ms"] for v in mf) * 1e-3) / 1e12, 2)
+        if dim == 128 and h == 1 and sp and sp["ms"] > 0:
+            ach = sp["units"] / (sp["ms"] * 1e-3) / 1e9
+            rec["roofline"] = {"bound": "hbm", "kernel": "k_spmm_rows/items/finish",
+                               "achieved": ach, "peak": 8000.0, "unit": "GB/s",
+                               "frac": ach / 8000.0, "traffic": None,
+                               "avg_ms": sp["ms"] / max(sp["calls"], 1),
+                               "algorithmic_bytes_per_launch": sp["units"] / max(sp["calls"], 1),
+                               "work_unit": "nonzero of S (12 + 8p bytes) and block row"}
+            if mf:
+                fl = sum(v["units"] for v in mf)
+                t = sum(v["ms"] for v in mf) * 1e-3
+                rec["roofline_mfma"] = {"bound": "mfma", "kernel": "k_emb_gram_part + k_emb_apply",
+                                        "achieved": fl / t / 1e12, "peak": 78.6,
+                                        "unit": "TFLOP/s", "frac": fl / t / 1e12 / 78.6,
+                                        "traffic": None, "dtype": "f64"}
         out.append(rec)
         log(f"[bench] embedding {rec}")
         del Z, ev, comp
+    P.set_timing(False)
     ws.buf = None
     torch.cuda.empty_cache()
     return {"workload": g.name, "n": g.n, "m": g.m, "L": L, "tolerance": 1e-10,

@@ -501,6 +501,21 @@ tg_status tg_key_describe(int32_t L, int32_t col, int32_t *orbit, int32_t *t, in
 tg_status tg_global_key_describe(int32_t L, int32_t idx, int32_t *graphlet,
                                  int32_t types_sorted[4], int32_t *k);
 
+/* Per-kernel-class device time of the most recent tg_count_directed or
+ * tg_graphlet_embedding call on this host thread, recorded while timing is
+ * on (tg_set_timing): for each class, its name (owned by the library),
+ * the summed milliseconds of its launches (HIP events on the caller's
+ * stream), their number, and the class's algorithmic units over those
+ * launches -- bytes for the bandwidth-bound classes, flops for the
+ * matrix-core classes, 0 where the library does not price the class
+ * (embedding: "spmm" bytes = nonzeros x (12 + 8p) + rows x 8p x (2 or 3),
+ * "gram" and "apply" flops = 2 s p^2, "chol", "jacobi" 0; directed:
+ * "dir_check", "dir_rows", "dir_global" 0, priced by the caller).  Returns
+ * the number of classes written (at most max_classes); any output may be
+ * NULL. */
+int32_t tg_kernel_sums(const char **names, double *ms, double *units, int64_t *calls,
+                       int32_t max_classes);
+
 /* Text naming the HIP call and error behind the most recent TG_E_DEVICE
  * returned by a counting call on this host thread ("" if that call had no
  * HIP failure).  The string is owned by the library and valid until the

@@ -16,6 +16,7 @@ from ._lib import (  # noqa: F401
     get_tuning,
     global_key_describe,
     global_width,
+    kernel_sums,
     key_describe,
     last_stats,
     pa_global_key_describe,

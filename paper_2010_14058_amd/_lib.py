@@ -98,6 +98,8 @@ SIGNATURES = {
                                       _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
     "tg_pa_global_key_describe": (_c.c_int, [_c.c_int32, _c.c_int64, _c.POINTER(_c.c_int32),
                                              _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
+    "tg_kernel_sums": (_c.c_int32, [_c.POINTER(_c.c_char_p), _c.POINTER(_c.c_double),
+                                    _c.POINTER(_c.c_double), _c.POINTER(_c.c_int64), _c.c_int32]),
     "tg_directed_row_width": (_c.c_int32, [_c.c_int32]),
     "tg_directed_global_width": (_c.c_int64, [_c.c_int32]),
     "tg_directed_workspace_bytes": (_c.c_size_t, [_c.c_int64, _c.c_int64, _c.c_int32]),
@@ -191,6 +193,19 @@ def phase_times() -> list[tuple[str, float]]:
     names = (ctypes.c_char_p * 32)()
     cnt = load().tg_phase_times(ms, names, 32)
     return [(names[q].decode(), float(ms[q])) for q in range(max(cnt, 0))]
+
+
+def kernel_sums() -> dict:
+    """Per-class device time of the last directed or embedding call on this
+    thread (timing on): {name: {"ms", "units", "calls"}}."""
+    k = 32
+    names = (ctypes.c_char_p * k)()
+    ms = (ctypes.c_double * k)()
+    units = (ctypes.c_double * k)()
+    calls = (ctypes.c_int64 * k)()
+    cnt = load().tg_kernel_sums(names, ms, units, calls, k)
+    return {names[q].decode(): {"ms": ms[q], "units": units[q], "calls": int(calls[q])}
+            for q in range(cnt)}
 
 
 TUNE_KNOBS = {"task_wedges": 0, "clear_bytes": 1, "cycle_slots": 2, "map_bytes": 3,

@@ -173,6 +173,81 @@ void timing_reset(hipStream_t st) {
     g_timing.stream = st;
 }
 
+// Per-class device time of the instrumented calls (directed counts,
+// embeddings): launches of one class are bracketed by two events on the
+// caller's stream; the elapsed times are added to the class's sums when
+// the call has synchronised the stream (ksum_collect).
+struct KSum {
+    const char *name;
+    double ms, units;
+    int64_t calls;
+};
+struct KPending {
+    int cls;
+    double units;
+    int ev;
+};
+thread_local std::vector<KSum> g_ksums;
+thread_local std::vector<hipEvent_t> g_kev;
+thread_local std::vector<KPending> g_kpend;
+thread_local int g_kev_used = 0;
+thread_local int g_kopen = -1;
+
+}  // namespace
+
+void ksum_reset() {
+    g_ksums.clear();
+    g_kpend.clear();
+    g_kev_used = 0;
+    g_kopen = -1;
+}
+
+void ksum_begin(hipStream_t st) {
+    if (!g_timing.enabled) return;
+    if ((int)g_kev.size() < g_kev_used + 2) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) return;
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return;
+        }
+        g_kev.push_back(a);
+        g_kev.push_back(b);
+    }
+    if (hipEventRecord(g_kev[g_kev_used], st) != hipSuccess) return;
+    g_kopen = g_kev_used;
+    g_kev_used += 2;
+}
+
+void ksum_end(const char *cls, double units, hipStream_t st) {
+    if (!g_timing.enabled || g_kopen < 0) return;
+    if (hipEventRecord(g_kev[g_kopen + 1], st) != hipSuccess) return;
+    int c = -1;
+    for (int q = 0; q < (int)g_ksums.size(); ++q)
+        if (std::strcmp(g_ksums[q].name, cls) == 0) c = q;
+    if (c < 0) {
+        g_ksums.push_back({cls, 0.0, 0.0, 0});
+        c = (int)g_ksums.size() - 1;
+    }
+    g_kpend.push_back({c, units, g_kopen});
+    g_kopen = -1;
+}
+
+void ksum_collect() {
+    if (!g_timing.enabled) return;
+    for (const KPending &k : g_kpend) {
+        float v = 0.f;
+        if (hipEventElapsedTime(&v, g_kev[k.ev], g_kev[k.ev + 1]) != hipSuccess) continue;
+        g_ksums[k.cls].ms += v;
+        g_ksums[k.cls].units += k.units;
+        g_ksums[k.cls].calls += 1;
+    }
+    g_kpend.clear();
+    g_kev_used = 0;
+}
+
+namespace {
+
 void timing_mark(const char *name) {
     if (!g_timing.enabled) return;
     Timing &T = g_timing;
@@ -922,6 +997,18 @@ tg_status tg_global_key_describe(int32_t L, int32_t idx, int32_t *graphlet, int3
 }
 
 void tg_set_timing(int32_t enable) { tg::g_timing.enabled = enable != 0; }
+
+int32_t tg_kernel_sums(const char **names, double *ms, double *units, int64_t *calls,
+                       int32_t max_classes) {
+    const int cnt = (int)tg::g_ksums.size() < max_classes ? (int)tg::g_ksums.size() : max_classes;
+    for (int q = 0; q < cnt; ++q) {
+        if (names) names[q] = tg::g_ksums[q].name;
+        if (ms) ms[q] = tg::g_ksums[q].ms;
+        if (units) units[q] = tg::g_ksums[q].units;
+        if (calls) calls[q] = tg::g_ksums[q].calls;
+    }
+    return cnt < 0 ? 0 : cnt;
+}
 
 int32_t tg_phase_times(float *ms, const char **names, int32_t max_phases) {
     tg::Timing &T = tg::g_timing;

@@ -443,11 +443,14 @@ tg_status tg_count_directed(const int64_t *row_ptr, const int32_t *col, const ui
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(w + y.acc);
     const int64_t m = nnz / 2, width = tg_directed_global_width(L);
 #define DIR_CHK(x) do { if ((x) != hipSuccess) return TG_E_DEVICE; } while (0)
+    ksum_reset();
     DIR_CHK(launch_fill_u64(reinterpret_cast<uint64_t *>(status), 0, 1, st));
     DIR_CHK(launch_fill_u64(reinterpret_cast<uint64_t *>(acc), 0, width, st));
     if (n > 0) {
+        ksum_begin(st);
         k_dir_check<<<waves_grid(n), 256, 0, st>>>(row_ptr, col, dir, types, n, nnz, L, ucount,
                                                     deg3, status);
+        ksum_end("dir_check", 0.0, st);
         DIR_CHK(hipGetLastError());
         DIR_CHK(launch_excl_scan(ucount, eoff, n + 1, reinterpret_cast<int64_t *>(w + y.stmp),
                                  nullptr, st));
@@ -459,12 +462,15 @@ tg_status tg_count_directed(const int64_t *row_ptr, const int32_t *col, const ui
     uint32_t bits = 0;
     DIR_CHK(hipMemcpyAsync(&bits, status, sizeof(bits), hipMemcpyDeviceToHost, st));
     DIR_CHK(hipStreamSynchronize(st));
+    ksum_collect();
     if (bits & ST_TYPE_RANGE) return TG_E_TYPE_RANGE;
     if (bits) return TG_E_NOT_SIMPLE;
     if (m > 0) {
         k_dir_edges_of<<<waves_grid(n), 256, 0, st>>>(row_ptr, col, eoff, n, esrc, eslot);
+        ksum_begin(st);
         k_dir_rows<<<waves_grid(m), 256, 0, st>>>(row_ptr, col, dir, types, deg3, esrc, eslot, m,
                                                    L, rows);
+        ksum_end("dir_rows", 0.0, st);
         DIR_CHK(hipGetLastError());
         if (global_counts) {
             uint64_t *ckey = reinterpret_cast<uint64_t *>(w + y.ckey);
@@ -472,6 +478,7 @@ tg_status tg_count_directed(const int64_t *row_ptr, const int32_t *col, const ui
             unsigned long long *csum = reinterpret_cast<unsigned long long *>(w + y.csum);
             unsigned long long *ccount = reinterpret_cast<unsigned long long *>(w + y.ccount);
             const int64_t classes = 3 * (int64_t)L * L;
+            ksum_begin(st);
             DIR_CHK(launch_fill_u64(reinterpret_cast<uint64_t *>(csum), 0, classes * 15 * L, st));
             DIR_CHK(launch_fill_u64(reinterpret_cast<uint64_t *>(ccount), 0, classes, st));
             k_dir_class<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(col, dir, types, esrc, eslot, m,
@@ -491,6 +498,7 @@ tg_status tg_count_directed(const int64_t *row_ptr, const int32_t *col, const ui
             k_dir_class_count<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(skey, m, ccount);
             const int64_t items = classes * (15 * L + 1);
             k_dir_keys<<<(unsigned)((items + 255) / 256), 256, 0, st>>>(csum, ccount, L, acc);
+            ksum_end("dir_global", 0.0, st);
             DIR_CHK(hipGetLastError());
         }
     }
@@ -501,6 +509,7 @@ tg_status tg_count_directed(const int64_t *row_ptr, const int32_t *col, const ui
         DIR_CHK(hipMemcpyAsync(&bits, status, sizeof(bits), hipMemcpyDeviceToHost, st));
     }
     DIR_CHK(hipStreamSynchronize(st));
+    ksum_collect();
 #undef DIR_CHK
     return bits ? TG_E_INTERNAL : TG_OK;
 }

@@ -1176,6 +1176,7 @@ tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int6
     const int p0 = y.p0;
     const int64_t m = nnz / 2;
 #define EMB_CHK(x) do { if ((x) != hipSuccess) return TG_E_DEVICE; } while (0)
+    ksum_reset();
     // weighted CSR: canonical edge ids of the slots, their weights, degrees
     EMB_CHK(launch_fill_u64(reinterpret_cast<uint64_t *>(status), 0, 1, st));
     k_emb_upper<<<(unsigned)((n + 256) / 256), 256, 0, st>>>(row_ptr, col, n, nnz, cnt, status);
@@ -1250,10 +1251,13 @@ tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int6
     EMB_CHK(hipMemcpyAsync(hseg.data(), seg_start, sizeof(int64_t) * (size_t)(nseg + 1),
                            hipMemcpyDeviceToHost, st));
     // every small component at once
+    ksum_begin(st);
     k_emb_dense<<<(unsigned)nseg, 256, 0, st>>>(row_ptr, col, D(y.wslot), D(y.sc), seg_start, order,
                                                 loc, dim, raw, Z, eigenvalues);
+    ksum_end("dense", 0.0, st);
     EMB_CHK(hipGetLastError());
     EMB_CHK(hipStreamSynchronize(st));
+    ksum_collect();
 
     // the large components, one after another
     double *X = D(y.X), *Y = D(y.Y), *Yp = D(y.Yp), *Yn = D(y.Yn), *MX = D(y.MX);
@@ -1286,30 +1290,44 @@ tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int6
         k_loc_items<<<grid_of(ns), 256, 0, st>>>(hptr, ns, hrow);
         EMB_CHK(hipGetLastError());
         uint32_t root = 0;
-        int64_t nitems = 0;
+        int64_t nitems = 0, nnz_c = 0;
         EMB_CHK(hipMemcpyAsync(&root, nodes, sizeof(root), hipMemcpyDeviceToHost, st));
         EMB_CHK(hipMemcpyAsync(&nitems, hptr + ns, sizeof(nitems), hipMemcpyDeviceToHost, st));
+        EMB_CHK(hipMemcpyAsync(&nnz_c, lrp + ns, sizeof(nnz_c), hipMemcpyDeviceToHost, st));
         EMB_CHK(hipStreamSynchronize(st));
         if (nitems > y.max_items) return TG_E_INTERNAL;
         const int pcap = (int)(ns < y.pmax ? ns : y.pmax);
         int p = (int)(ns < p0 ? ns : p0);
         const int want = dim < p ? dim : p;
         const int64_t chunks = (ns + GRAM_ROWS - 1) / GRAM_ROWS;
+        // flops of an s x p by p x p product (the Gram products likewise)
+        auto dense_flops = [&]() { return 2.0 * (double)ns * (double)p * (double)p; };
         auto gram = [&](const double *A, const double *B, double *C) -> hipError_t {
             const int mt = (p + MT - 1) / MT;
+            ksum_begin(st);
             k_emb_gram_part<<<dim3((unsigned)chunks, (unsigned)(mt * mt)), 256, 0, st>>>(
                 A, B, ns, p, part);
+            ksum_end("gram", dense_flops(), st);
             k_emb_gram_sum<<<(unsigned)((p * p + 255) / 256), 256, 0, st>>>(part, chunks, p, C);
             return hipGetLastError();
         };
         auto apply = [&](const double *A, const double *Q, double *out) -> hipError_t {
+            ksum_begin(st);
             k_emb_apply<<<dim3((unsigned)((ns + MT - 1) / MT), (unsigned)((p + MT - 1) / MT)), 256,
                           0, st>>>(A, Q, ns, p, out);
+            ksum_end("apply", dense_flops(), st);
             return hipGetLastError();
         };
         // out = alpha S A + beta A + gamma Zb
+        // algorithmic bytes of one product: every nonzero's column and value
+        // and the neighbour's block row, each row's own block row read (and
+        // Zb's) and the output row written
+        auto spmm_bytes = [&](bool zb) {
+            return (double)nnz_c * (12.0 + 8.0 * p) + (double)ns * 8.0 * p * (zb ? 3.0 : 2.0);
+        };
         auto spmm = [&](const double *A, const double *Zb, double alpha, double beta, double gamma,
                         double *out) -> hipError_t {
+            ksum_begin(st);
 #define EMB_SPMM(GSV, CPLV)                                                                       \
     do {                                                                                          \
         k_spmm_rows<GSV, CPLV><<<rg, 256, 0, st>>>(lrp, lcol, lval, ns, p, A, Zb, alpha, beta,     \
@@ -1327,14 +1345,17 @@ tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int6
 #undef EMB_SPMM
             if (nitems)
                 k_spmm_finish<<<rg, 256, 0, st>>>(hptr, ns, p, A, Zb, alpha, beta, gamma, spart, out);
+            ksum_end("spmm", spmm_bytes(Zb != nullptr), st);
             return hipGetLastError();
         };
         // Cholesky QR: out = A R^{-1}, A^T A = R^T R
         auto orth = [&](const double *A, double *out) -> hipError_t {
             hipError_t e = gram(A, A, G);
             if (e != hipSuccess) return e;
+            ksum_begin(st);
             if (p <= LDS_P) k_emb_chol_lds<<<1, 1024, 0, st>>>(G, Vs, p);
             else k_emb_chol<<<1, 1024, 0, st>>>(G, Vs, p);
+            ksum_end("chol", 0.0, st);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             return apply(A, Vs, out);
         };
@@ -1351,12 +1372,14 @@ tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int6
             h_res.assign((size_t)p, 0.0);
             if ((e = spmm(Q, nullptr, 0.5, 0.5, 0.0, MX)) != hipSuccess) return e;
             if ((e = gram(Q, MX, H)) != hipSuccess) return e;
+            ksum_begin(st);
             if (p <= LDS_P)
                 k_jacobi_rr_lds<<<1, 1024, 0, st>>>(H, p, rot_cs, rot_ij, rr_misc, rr_misc + 1, sigma);
             else
                 k_jacobi_rr<<<1, 1024, 0, st>>>(H, p, rot_cs, rot_ij, rr_misc, rr_misc + 1, sigma);
             k_jacobi_vecs<<<(unsigned)((p + 3) / 4), 256, 0, st>>>(rot_cs, rot_ij, rr_misc, rr_misc + 1,
                                                                    p, Vs);
+            ksum_end("jacobi", 0.0, st);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             if ((e = apply(Q, Vs, xo)) != hipSuccess) return e;
             if ((e = apply(MX, Vs, mo)) != hipSuccess) return e;
@@ -1372,7 +1395,9 @@ tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int6
             if ((e = hipMemcpyAsync(h_res.data(), res, sizeof(double) * p, hipMemcpyDeviceToHost,
                                     st)) != hipSuccess)
                 return e;
-            return hipStreamSynchronize(st);
+            if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+            ksum_collect();
+            return hipSuccess;
         };
         auto worst = [&]() {
             double r = 0.0;
@@ -1461,6 +1486,7 @@ tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int6
     }
     if (iterations) *iterations = most_iterations;
     EMB_CHK(hipStreamSynchronize(st));
+    ksum_collect();
 #undef EMB_CHK
     return all_converged ? TG_OK : TG_E_NO_CONVERGENCE;
 }

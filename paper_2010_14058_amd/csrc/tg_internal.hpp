@@ -214,6 +214,16 @@ hipError_t launch_derive_pa(const EdgeArgs &args, const PaLayout &pl, unsigned g
 hipError_t launch_pa_finalize(const uint64_t *acc, const PaLayout &pl, uint64_t *out,
                               uint32_t *status, hipStream_t st);
 
+// Per-class kernel timing of the directed and embedding calls (tg_api.hip),
+// active while tg_set_timing is on: ksum_reset at the start of a call,
+// ksum_begin / ksum_end around the launches of a class (units: the class's
+// algorithmic bytes or flops for those launches), ksum_collect once the
+// stream has been synchronised.
+void ksum_reset();
+void ksum_begin(hipStream_t st);
+void ksum_end(const char *cls, double units, hipStream_t st);
+void ksum_collect();
+
 // Prefix sums and radix sorts (tg_sort.hip).  `gate` is the status word:
 // they do nothing once an input check has failed.
 int64_t scan_tiles(int64_t count);
