@@ -509,7 +509,8 @@ tg_status tg_global_key_describe(int32_t L, int32_t idx, int32_t *graphlet,
  * launches -- bytes for the bandwidth-bound classes, flops for the
  * matrix-core classes, 0 where the library does not price the class
  * (embedding: "spmm" bytes = nonzeros x (12 + 8p) + rows x 8p x (2 or 3),
- * "gram" and "apply" flops = 2 s p^2, "chol", "jacobi" 0; directed:
+ * "gram" flops = s p (p + 1) (a symmetric product), "apply" flops = 2 s p^2,
+ * "chol", "jacobi" 0; directed:
  * "dir_check", "dir_rows", "dir_global" 0, priced by the caller).  Returns
  * the number of classes written (at most max_classes); any output may be
  * NULL. */

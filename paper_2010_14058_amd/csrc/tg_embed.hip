@@ -480,8 +480,10 @@ constexpr int MT = 64;     // output tile edge of the dense products
 constexpr int MK = 32;     // depth staged in LDS per step
 
 // Partial Gram tiles: part[chunk][i][j] = sum over the chunk's rows r of
-// A[r][i] * B[r][j].  A workgroup (4 waves) takes a 64 x 64 tile of the
-// p x p result, each wave 16 of its rows against all 64 columns; the rows
+// A[r][i] * B[r][j], for the tiles on and above the diagonal (A^T B is
+// symmetric wherever it is used: A^T A, and Q^T M Q with M symmetric).  A
+// workgroup (4 waves) takes a 64 x 64 tile of the p x p result, each wave
+// 16 of its rows against all 64 columns; the rows
 // of the chunk are staged 32 at a time in LDS (coalesced row segments) and
 // fed to the fp64 matrix cores, the rows being the contraction index.
 __global__ void __launch_bounds__(256)
@@ -489,8 +491,15 @@ k_emb_gram_part(const double *__restrict__ A, const double *__restrict__ B, int6
                 double *__restrict__ part) {
     __shared__ double as[MK][MT + 1];
     __shared__ double bs[MK][MT + 1];
+    // blockIdx.y enumerates the tiles (ti, tj) with ti <= tj: the products
+    // are symmetric, k_emb_gram_sum mirrors the rest
     const int tiles = (p + MT - 1) / MT;
-    const int i0 = (blockIdx.y / tiles) * MT, j0 = (blockIdx.y % tiles) * MT;
+    int ti = 0, rest = blockIdx.y;
+    while (rest >= tiles - ti) {
+        rest -= tiles - ti;
+        ++ti;
+    }
+    const int i0 = ti * MT, j0 = (ti + rest) * MT;
     const int64_t r0 = (int64_t)blockIdx.x * GRAM_ROWS;
     const int64_t r1 = r0 + GRAM_ROWS < n ? r0 + GRAM_ROWS : n;
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
@@ -524,13 +533,16 @@ k_emb_gram_part(const double *__restrict__ A, const double *__restrict__ B, int6
 }
 
 // C = sum of the partials, chunk by chunk in order (a fixed order: the same
-// inputs give the same bits).
+// inputs give the same bits); an entry below the diagonal in a tile below
+// the diagonal tiles takes its mirror image.
 __global__ void k_emb_gram_sum(const double *__restrict__ part, int64_t chunks, int p,
                                double *__restrict__ C) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= p * p) return;
+    const int i = q / p, j = q % p;
+    const int src = (i / MT > j / MT) ? j * p + i : q;
     double s = 0.0;
-    for (int64_t c = 0; c < chunks; ++c) s += part[(size_t)c * p * p + q];
+    for (int64_t c = 0; c < chunks; ++c) s += part[(size_t)c * p * p + src];
     C[q] = s;
 }
 
@@ -1300,14 +1312,16 @@ tg_status tg_graphlet_embedding(const int64_t *row_ptr, const int32_t *col, int6
         int p = (int)(ns < p0 ? ns : p0);
         const int want = dim < p ? dim : p;
         const int64_t chunks = (ns + GRAM_ROWS - 1) / GRAM_ROWS;
-        // flops of an s x p by p x p product (the Gram products likewise)
+        // flops of an s x p by p x p product, and of a symmetric Gram product
+        // (one triangle)
         auto dense_flops = [&]() { return 2.0 * (double)ns * (double)p * (double)p; };
+        auto gram_flops = [&]() { return (double)ns * (double)p * (double)(p + 1); };
         auto gram = [&](const double *A, const double *B, double *C) -> hipError_t {
             const int mt = (p + MT - 1) / MT;
             ksum_begin(st);
-            k_emb_gram_part<<<dim3((unsigned)chunks, (unsigned)(mt * mt)), 256, 0, st>>>(
+            k_emb_gram_part<<<dim3((unsigned)chunks, (unsigned)(mt * (mt + 1) / 2)), 256, 0, st>>>(
                 A, B, ns, p, part);
-            ksum_end("gram", dense_flops(), st);
+            ksum_end("gram", gram_flops(), st);
             k_emb_gram_sum<<<(unsigned)((p * p + 255) / 256), 256, 0, st>>>(part, chunks, p, C);
             return hipGetLastError();
         };
