@@ -114,6 +114,75 @@ __global__ void k_dir_edges_of(const int64_t *__restrict__ rp, const int32_t *__
     }
 }
 
+// Hubs: nodes of degree >= DIR_HUB_DEG get a bitmap of their neighbours
+// (n bits) and the popcount of every bitmap word before it, so that a probe
+// into a hub's row is a bitmap word, a prefix count and the direction byte
+// of the slot they give (at most DIR_HUB_MAX hubs; others are searched).
+constexpr int64_t DIR_HUB_DEG = 256;
+constexpr int64_t DIR_HUB_MAX = 8192;
+
+__global__ void k_dir_hub_ids(const int64_t *__restrict__ rp, int64_t n, int64_t hub_max,
+                              int32_t *__restrict__ hub_id, int32_t *__restrict__ hub_node,
+                              unsigned int *__restrict__ counter) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int32_t h = -1;
+    if (rp[v + 1] - rp[v] >= DIR_HUB_DEG) {
+        const unsigned int q = atomicAdd(counter, 1u);
+        if ((int64_t)q < hub_max) {
+            h = (int32_t)q;
+            hub_node[q] = (int32_t)v;
+        }
+    }
+    hub_id[v] = h;
+}
+
+// One workgroup per hub: its bitmap, then the exclusive prefix popcounts of
+// the bitmap's words.
+__global__ void __launch_bounds__(256)
+k_dir_hub_bits(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+               const int32_t *__restrict__ hub_node, const unsigned int *__restrict__ counter,
+               int64_t hub_max, int64_t nw, unsigned long long *__restrict__ bits,
+               uint32_t *__restrict__ prefix) {
+    const int64_t h = blockIdx.x;
+    const int64_t cnt = *counter < (unsigned int)hub_max ? (int64_t)*counter : hub_max;
+    if (h >= cnt) return;
+    const int32_t v = hub_node[h];
+    unsigned long long *B = bits + (size_t)h * nw;
+    uint32_t *Pf = prefix + (size_t)h * nw;
+    const int tid = threadIdx.x;
+    for (int64_t q = tid; q < nw; q += 256) B[q] = 0ull;
+    __syncthreads();
+    for (int64_t s = rp[v] + tid; s < rp[v + 1]; s += 256) {
+        const int32_t x = col[s];
+        atomicOr(&B[x >> 6], 1ull << (x & 63));
+    }
+    __syncthreads();
+    // prefix popcounts, 256 words at a time (one per thread, coalesced):
+    // a scan inside each wave, then over the four wave totals
+    __shared__ uint32_t wtot[256 / WAVE];
+    const int lane = lane_id(), wv = tid / WAVE;
+    uint32_t run = 0;
+    for (int64_t base = 0; base < nw; base += 256) {
+        const int64_t q = base + tid;
+        // the words were set by other threads' atomics: read them from L2
+        const uint32_t c =
+            q < nw ? (uint32_t)__popcll(__hip_atomic_load(&B[q], __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT))
+                   : 0u;
+        const uint32_t incl = wave_incl_scan(c);
+        if (lane == WAVE - 1) wtot[wv] = incl;
+        __syncthreads();
+        uint32_t before = run;
+        for (int x = 0; x < wv; ++x) before += wtot[x];
+        if (q < nw) Pf[q] = before + incl - c;
+        uint32_t all = 0;
+        for (int x = 0; x < 256 / WAVE; ++x) all += wtot[x];
+        run += all;
+        __syncthreads();
+    }
+}
+
 constexpr int DIR_SAMPLE = 1024;   // LDS sample of a long list (entries per wave)
 
 // One wave per edge (i, j): the common neighbours k by searching each
@@ -127,7 +196,9 @@ __global__ void __launch_bounds__(256)
 k_dir_rows(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
            const uint8_t *__restrict__ dir, const uint8_t *__restrict__ types,
            const uint32_t *__restrict__ deg3, const int32_t *__restrict__ esrc,
-           const int64_t *__restrict__ eslot, int64_t m, int L, uint64_t *__restrict__ rows) {
+           const int64_t *__restrict__ eslot, int64_t m, int L,
+           const int32_t *__restrict__ hub_id, const unsigned long long *__restrict__ hbits,
+           const uint32_t *__restrict__ hprefix, int64_t nw, uint64_t *__restrict__ rows) {
     __shared__ uint32_t tri[256 / WAVE][9 * TG_MAX_L];
     __shared__ int32_t samp[256 / WAVE][DIR_SAMPLE];
     const int lane = lane_id(), wv = threadIdx.x / WAVE;
@@ -143,15 +214,29 @@ k_dir_rows(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
         const bool i_short = ie - ib <= je - jb;
         const int64_t sb = i_short ? ib : jb, se = i_short ? ie : je;
         const int64_t lb = i_short ? jb : ib, le = i_short ? je : ie;
+        const int32_t hl = hub_id[i_short ? j : i];     // the longer row's hub index
         int64_t stride = 0;
         int nsamp = 0;
-        if (se - sb >= WAVE / 2 && le - lb > 2 * WAVE) {
+        if (hl >= 0) {
+            const unsigned long long *B = hbits + (size_t)hl * nw;
+            const uint32_t *Pf = hprefix + (size_t)hl * nw;
+            for (int64_t s = sb + lane; s < se; s += WAVE) {
+                const int32_t k = col[s];
+                const unsigned long long word = B[k >> 6];
+                if (!((word >> (k & 63)) & 1ull)) continue;
+                const int64_t r = lb + Pf[k >> 6] +
+                                  __popcll(word & ((1ull << (k & 63)) - 1ull));
+                const int cs = dir_code(dir[s]), cl = dir_code(dir[r]);
+                const int a = i_short ? cs : cl, b = i_short ? cl : cs;
+                atomicAdd(&tri[wv][types[k] * 9 + a * 3 + b], 1u);
+            }
+        } else if (se - sb >= WAVE / 2 && le - lb > 2 * WAVE) {
             stride = (le - lb + DIR_SAMPLE - 1) / DIR_SAMPLE;
             nsamp = (int)((le - lb + stride - 1) / stride);
             for (int q = lane; q < nsamp; q += WAVE) samp[wv][q] = col[lb + (int64_t)q * stride];
             wave_sync();
         }
-        for (int64_t s = sb + lane; s < se; s += WAVE) {
+        for (int64_t s = sb + lane; hl < 0 && s < se; s += WAVE) {
             const int32_t k = col[s];
             int64_t lo = lb, hi = le;
             if (stride) {
@@ -359,7 +444,8 @@ __global__ void k_dir_finalize(const unsigned long long *__restrict__ acc, int64
 
 struct DirLayout {
     size_t status, ucount, eoff, stmp, deg3, esrc, eslot, rows, acc, ckey, ckey_tmp, cval, cval_tmp,
-        sort_tmp, csum, ccount, total;
+        sort_tmp, csum, ccount, hub_id, hub_node, hbits, hprefix, total;
+    int64_t hub_max, nw;
 };
 
 DirLayout dir_layout(int64_t n, int64_t nnz, int L, bool own_rows) {
@@ -388,6 +474,13 @@ DirLayout dir_layout(int64_t n, int64_t nnz, int L, bool own_rows) {
     y.sort_tmp = take(sort_tmp_need(m > 0 ? m : 1));
     y.csum = take(sizeof(uint64_t) * (size_t)(3 * L * L) * 15 * L);
     y.ccount = take(sizeof(uint64_t) * (size_t)(3 * L * L));
+    // at most nnz / DIR_HUB_DEG nodes reach the hub degree
+    y.hub_max = nnz / DIR_HUB_DEG < DIR_HUB_MAX ? nnz / DIR_HUB_DEG : DIR_HUB_MAX;
+    y.nw = (n + 63) / 64 > 0 ? (n + 63) / 64 : 1;
+    y.hub_id = take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    y.hub_node = take(sizeof(int32_t) * (size_t)(y.hub_max > 0 ? y.hub_max : 1));
+    y.hbits = take(sizeof(uint64_t) * (size_t)y.hub_max * y.nw);
+    y.hprefix = take(sizeof(uint32_t) * (size_t)y.hub_max * y.nw);
     y.total = o;
     return y;
 }
@@ -467,9 +560,23 @@ tg_status tg_count_directed(const int64_t *row_ptr, const int32_t *col, const ui
     if (bits) return TG_E_NOT_SIMPLE;
     if (m > 0) {
         k_dir_edges_of<<<waves_grid(n), 256, 0, st>>>(row_ptr, col, eoff, n, esrc, eslot);
+        int32_t *hub_id = reinterpret_cast<int32_t *>(w + y.hub_id);
+        int32_t *hub_node = reinterpret_cast<int32_t *>(w + y.hub_node);
+        unsigned long long *hbits = reinterpret_cast<unsigned long long *>(w + y.hbits);
+        uint32_t *hprefix = reinterpret_cast<uint32_t *>(w + y.hprefix);
+        unsigned int *hcount = reinterpret_cast<unsigned int *>(status + 4);   // own 16-byte slot
+        ksum_begin(st);
+        DIR_CHK(launch_fill_u64(reinterpret_cast<uint64_t *>(hcount), 0, 1, st));
+        k_dir_hub_ids<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(row_ptr, n, y.hub_max, hub_id,
+                                                                  hub_node, hcount);
+        if (y.hub_max > 0)
+            k_dir_hub_bits<<<(unsigned)y.hub_max, 256, 0, st>>>(row_ptr, col, hub_node, hcount,
+                                                               y.hub_max, y.nw, hbits, hprefix);
+        ksum_end("dir_hubs", 0.0, st);
+        DIR_CHK(hipGetLastError());
         ksum_begin(st);
         k_dir_rows<<<waves_grid(m), 256, 0, st>>>(row_ptr, col, dir, types, deg3, esrc, eslot, m,
-                                                   L, rows);
+                                                   L, hub_id, hbits, hprefix, y.nw, rows);
         ksum_end("dir_rows", 0.0, st);
         DIR_CHK(hipGetLastError());
         if (global_counts) {
