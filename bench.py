@@ -159,21 +159,29 @@ def algorithmic_bytes(g, L, stats, members, members_heavy, edge_deg):
     xyk = 4 * LL * aw
     wa, wah = stats["wedges_pass_a"], stats["heavy_wedges_pass_a"]
     wb, wbh = stats["wedges_pass_b"], stats["heavy_wedges_pass_b"]
+    # heavy wedges of the blocked path (its own phase) and of the task kernel
+    wak, wbk = stats.get("blocked_wedges_pass_a", 0), stats.get("blocked_wedges_pass_b", 0)
     out = {
         "prep": 8 * (n + 1) + 4 * nnz + n + 8 * (n + 1) + 8 * nnz + 8 * m + 4 * n * L,
         "tri": tri,
         "aggr": nnz * (4 + 1 + 8 * LP) + 2 * aw * n * LL,
         "cyc_work": 28 * nnz,
         "cycA_light": 8 * (wa - wah),
-        "cycA_heavy": 8 * wah,
+        "cycA_blk": 8 * wak,
+        "cycA_heavy": 8 * (wah - wak),
         "cycB_light": 8 * (wb - wbh),
-        "cycB_heavy": 8 * wbh,
+        "cycB_blk": 8 * wbk,
+        "cycB_heavy": 8 * (wbh - wbk),
         "edges_light": (b_all - hv_share) + (members - members_heavy) * per_member
                        + (m - nh) * (xyk + 56),
         "edges_heavy": hv_share + members_heavy * per_member + nh * (xyk + 56),
         "derive": m * (5 * LL * aw + xyk + 4 * L + 8 * LP + 8 * W),
     }
-    scratch = {"cycA_heavy": (16 + 4 * L) * wah, "cycB_heavy": (16 + 4 * L) * wbh}
+    # map traffic beyond the 8 algorithmic bytes: per task-kernel wedge a
+    # counter update and L counts read; per blocked wedge a 2-byte record
+    # written and read, three more target reads and one map word
+    scratch = {"cycA_heavy": (16 + 4 * L) * (wah - wak), "cycB_heavy": (16 + 4 * L) * (wbh - wbk),
+               "cycA_blk": (2 + 2 + 12 + 4) * wak, "cycB_blk": (2 + 2 + 12 + 4) * wbk}
     return {k: float(v) for k, v in out.items()}, scratch
 
 
@@ -641,8 +649,10 @@ def roofline_of(P, torch, g, rows, stats, phase_avg, peak_stream):
     dom = max(kernels, key=lambda k: phase_avg[k])
     dom_ms = phase_avg[dom]
     achieved = abytes[dom] / (dom_ms * 1e-3) / 1e9
-    units = {"cycA_heavy": ("wedge", stats["heavy_wedges_pass_a"]),
-             "cycB_heavy": ("wedge", stats["heavy_wedges_pass_b"])}.get(dom, ("edge", g.m))
+    wak, wbk = stats.get("blocked_wedges_pass_a", 0), stats.get("blocked_wedges_pass_b", 0)
+    units = {"cycA_heavy": ("wedge", stats["heavy_wedges_pass_a"] - wak),
+             "cycB_heavy": ("wedge", stats["heavy_wedges_pass_b"] - wbk),
+             "cycA_blk": ("wedge", wak), "cycB_blk": ("wedge", wbk)}.get(dom, ("edge", g.m))
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(dom),
             "avg_ms": dom_ms, "algorithmic_bytes_per_launch": abytes[dom],

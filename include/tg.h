@@ -558,7 +558,24 @@ const char *tg_last_error(void);
  *       node of that degree without a bitmap is probed by binary search.
  *   TG_TUNE_SH_DEG       (default 1024, 32..2^31-1): smallest degree of a
  *       super-hub.
- * CYCLE_SLOTS, MAP_BYTES, EDGE_SLOTS, TBUF_BYTES and SH_MAX change
+ *   TG_TUNE_BLK_WEDGES   (default 2^16, >= 1): smallest heavy pass-A
+ *       4-cycle group (grouped by top vertex) that may be counted by the
+ *       blocked path (single graphs with every
+ *       degree below 2^16, L <= 16 and at most 2^25 nodes): its wedges are
+ *       written once as 2-byte records grouped by target block, counted per
+ *       block in LDS into one map per group, then walked in tasks that read
+ *       that map.  The largest such groups are taken while their maps fit
+ *       the cycle map region (at most 4096 groups per pass) and their wedges
+ *       the records; the rest go to the task kernel.
+ *   TG_TUNE_BLK_TASK     (default 65536, 1024..65536): wedges per walk task
+ *       of the blocked path.
+ *   TG_TUNE_BLK_WEDGES_B (default 2^31 = off, >= 1): the same bound for
+ *       pass-B groups (grouped by the vertex opposite the top), which are
+ *       many and small on power-law graphs.
+ *   TG_TUNE_BLK_BYTES    (default 4 GiB, 0..2^33): workspace bytes for the
+ *       blocked path's records (two bytes per wedge of the blocked groups of
+ *       one pass); 0 turns the blocked path off.
+ * CYCLE_SLOTS, MAP_BYTES, EDGE_SLOTS, TBUF_BYTES, SH_MAX and BLK_BYTES change
  * tg_workspace_bytes and tg_batch_workspace_bytes, so they must be set
  * before the workspace is sized.
  * tg_set_tuning returns TG_E_INVALID_ARG for an unknown knob or a value out
@@ -575,8 +592,13 @@ typedef enum {
     TG_TUNE_LIGHT_WEDGES = 8,
     TG_TUNE_EDGE_DEG = 9,
     TG_TUNE_SH_MAX = 10,
-    TG_TUNE_SH_DEG = 11
+    TG_TUNE_SH_DEG = 11,
+    TG_TUNE_BLK_WEDGES = 12,
+    TG_TUNE_BLK_BYTES = 13,
+    TG_TUNE_BLK_TASK = 14,
+    TG_TUNE_BLK_WEDGES_B = 15
 } tg_tune;
+#define TG_NUM_TUNE 16
 tg_status tg_set_tuning(int32_t knob, int64_t value);
 int64_t tg_get_tuning(int32_t knob);
 
@@ -596,9 +618,11 @@ int32_t tg_phase_times(float *ms, const char **names, int32_t max_phases);
  * [5] pass-A wedges in heavy groups, [6] pass-B wedges in heavy groups,
  * [7] sum over edges of |T_ij| (three times the triangle count),
  * [8] nodes of at least the super-hub degree, [9] super-hubs given a bitmap
- * (the rest of [8] is probed by binary search), [10] hub-core size.
+ * (the rest of [8] is probed by binary search), [10] hub-core size,
+ * [11] groups on the blocked cycle path (both passes), [12] pass-A wedges
+ * in blocked groups, [13] pass-B wedges in blocked groups.
  * Returns the number written (at most TG_NUM_STATS). */
-#define TG_NUM_STATS 11
+#define TG_NUM_STATS 14
 int32_t tg_last_stats(int64_t *stats, int32_t max_stats);
 
 #ifdef __cplusplus

@@ -141,6 +141,12 @@ def load(path: str | None = None):
         raise RuntimeError(
             f"{p} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
             "(the typed-graphlet counts only run on the HIP library)")
+    # torch's HIP libraries first: they bring the HSA runtime that the
+    # library's HIP runtime then shares (loaded the other way round, torch
+    # later initialises on the library's HSA runtime and every launch of
+    # the library fails with hipErrorNoDevice)
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(p)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
@@ -210,7 +216,8 @@ def kernel_sums() -> dict:
 
 TUNE_KNOBS = {"task_wedges": 0, "clear_bytes": 1, "cycle_slots": 2, "map_bytes": 3,
               "edge_slots": 4, "tbuf_bytes": 5, "range_bytes": 6, "derive_edges": 7,
-              "light_wedges": 8, "edge_deg": 9, "sh_max": 10, "sh_deg": 11}
+              "light_wedges": 8, "edge_deg": 9, "sh_max": 10, "sh_deg": 11,
+              "blk_wedges": 12, "blk_bytes": 13, "blk_task": 14, "blk_wedges_b": 15}
 
 
 def set_tuning(**knobs) -> dict:
@@ -230,12 +237,13 @@ def get_tuning() -> dict:
 
 
 def last_stats() -> dict:
-    st = (ctypes.c_int64 * 11)()
-    load().tg_last_stats(st, 11)
+    st = (ctypes.c_int64 * 14)()
+    load().tg_last_stats(st, 14)
     return {"wedges_pass_a": st[0], "light_groups": st[1], "heavy_groups": st[2],
             "heavy_edges": st[3], "wedges_pass_b": st[4], "heavy_wedges_pass_a": st[5],
             "heavy_wedges_pass_b": st[6], "triangle_slots": st[7], "superhub_candidates": st[8],
-            "superhubs": st[9], "hub_core": st[10]}
+            "superhubs": st[9], "hub_core": st[10], "blocked_groups": st[11],
+            "blocked_wedges_pass_a": st[12], "blocked_wedges_pass_b": st[13]}
 
 
 def count_raw(row_ptr_ptr: int, col_ptr: int, types_ptr: int, n: int, nnz: int, L: int,

@@ -39,9 +39,10 @@ static const int MAX_CYCLE_SLOTS = 2048;   // heavy 4-cycle workgroups (map budg
 static const size_t XYK_BUDGET = size_t(16) << 30;
 
 // Scheduling knobs (tg_set_tuning), per host thread.
-thread_local int64_t g_tune[TG_TUNE_SH_DEG + 1] = {
+thread_local int64_t g_tune[TG_NUM_TUNE] = {
     TASK_WEDGES, SEQ_CLEAR_BYTES, MAX_CYCLE_SLOTS, (int64_t)MAP_BUDGET, MAX_HEAVY_SLOTS,
-    (int64_t)TBUF_BUDGET, TASK_RANGE_BYTES, 0, LIGHT_MAXW, TCAP, SH_MAX, SH_DMIN};
+    (int64_t)TBUF_BUDGET, TASK_RANGE_BYTES, 0, LIGHT_MAXW, TCAP, SH_MAX, SH_DMIN,
+    BLK_MIN_WEDGES, (int64_t)BLK_BUDGET, BLK_TASK, BLK_MIN_WEDGES_B};
 
 // Temporary storage of the preparation's sorts and prefix sums.
 static size_t sort_tmp_bytes(int64_t n, int64_t nnz) {
@@ -57,6 +58,7 @@ Budget budget_from_tuning() {
     b.sh_max = g_tune[TG_TUNE_SH_MAX];
     b.sh_bytes = SH_BUDGET;
     b.xyk_bytes = XYK_BUDGET;
+    b.blk_bytes = (size_t)g_tune[TG_TUNE_BLK_BYTES];
     return b;
 }
 
@@ -81,7 +83,24 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G, con
     if (eslots > bud.edge_slots) eslots = bud.edge_slots;
     if (eslots < 1) eslots = 1;
     y.heavy_edge_slots = (int)eslots;
-    y.sort_tmp_bytes = sort_tmp_bytes(n, nnz);
+    // blocked heavy 4-cycle groups: single graphs within the record format
+    // (4-bit centre types, at most 8192 blocks per group); one map per group
+    // from the task maps' slots
+    if (G == 0 && bud.blk_bytes >= 2 && L <= 16 && n > 0 && n <= BLK_MAX_NODES) {
+        // group maps in the degree-class layout take far less than the n L
+        // words of a task map: the selection fits as many as the map
+        // region holds, at most BLK_MAX_GROUPS
+        y.blk_groups = BLK_MAX_GROUPS;
+        y.blk_nb = (int)((n + BLK_IDS - 1) / BLK_IDS);
+        int64_t rec = (int64_t)(bud.blk_bytes / sizeof(uint16_t));
+        if (rec > (int64_t)0xffffffffll) rec = (int64_t)0xffffffffll;
+        y.blk_records = rec;
+        y.blk_nbk = (int64_t)y.blk_groups * y.blk_nb;
+    }
+    {
+        int64_t scan_len = nnz > y.blk_nbk ? nnz : y.blk_nbk;
+        y.sort_tmp_bytes = sort_tmp_bytes(n, scan_len);
+    }
     if (y.sort_tmp_bytes == 0) return TG_E_INTERNAL;
     int gw = (int)(binom_host(L + 1, 2) + 2 * binom_host(L + 2, 3) + 6 * binom_host(L + 3, 4));
 
@@ -150,6 +169,25 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G, con
     y.off_ngraph = take(sizeof(int32_t) * (G > 0 ? n + 1 : 1));
     y.off_gedge = take(sizeof(int64_t) * (G + 1));
     y.off_pacc = take(sizeof(uint64_t) * (size_t)pa_layout(L).gstart[9]);
+    if (y.blk_groups > 0) {
+        const size_t kg = (size_t)y.blk_groups;
+        y.off_blk_list_a = take(sizeof(uint2) * kg);
+        y.off_blk_list_b = take(sizeof(uint2) * kg);
+        y.off_blk_meta = take(sizeof(uint32_t) * (3 * (kg + 1) + 8 * (kg / 8 + 1)));
+        // items of distinct groups: at most one per adjacency slot, plus a
+        // total per group
+        y.off_blk_ipre = take(sizeof(uint32_t) * ((size_t)nnz + kg + 1));
+        y.off_blk_bcount = take(sizeof(int64_t) * (size_t)(y.blk_nbk + 1));
+        y.off_blk_bstart = take(sizeof(int64_t) * (size_t)(y.blk_nbk + 1));
+        y.off_blk_pcur = take(sizeof(uint32_t) * (size_t)(y.blk_nbk + 1));
+        y.off_blk_bgroup = take(sizeof(uint32_t) * (size_t)(y.blk_nbk + 1));
+        // padded for the count kernel's 16-byte loads past the last record
+        y.off_blk_rec = take(sizeof(uint16_t) * (size_t)y.blk_records + 16);
+        y.off_blk_cand_a = take(sizeof(uint2) * (size_t)(n + 1));
+        y.off_blk_cand_b = take(sizeof(uint2) * (size_t)(n + 1));
+        y.off_blk_flag = take(2 * (size_t)(n + 8));
+        y.off_blk_hist = take(sizeof(uint64_t) * 2 * 2 * BLK_BINS);
+    }
     y.total = off;
     return TG_OK;
 }
@@ -451,10 +489,26 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
 
     // ---- 4-cycles from degree-ordered wedges
     HIPCHK(launch_fill_u64(NC, 0, words32 ? (m * LL + 1) / 2 : m * LL, st));
+    // blocked path: counts of a blocked group's targets never exceed their
+    // degree, held in 16-bit fields
+    const bool blk_on = y.blk_groups > 0 && !batch && words32 && L <= 16;
+    BlkSelect bsel;
+    bsel.cand_a = blk_on ? at<uint2>(ws, y.off_blk_cand_a) : nullptr;
+    bsel.cand_b = blk_on ? at<uint2>(ws, y.off_blk_cand_b) : nullptr;
+    bsel.hist_a = blk_on ? at<uint64_t>(ws, y.off_blk_hist) : nullptr;
+    bsel.hist_b = blk_on ? bsel.hist_a + 2 * BLK_BINS : nullptr;
+    bsel.min_wedges_a = (uint64_t)g_tune[TG_TUNE_BLK_WEDGES];
+    bsel.min_wedges_b = (uint64_t)g_tune[TG_TUNE_BLK_WEDGES_B];
+    uint8_t *blk_flag = blk_on ? at<uint8_t>(ws, y.off_blk_flag) : nullptr;
+    if (blk_on) {
+        // flags of both passes and the histograms start at zero
+        HIPCHK(launch_fill_u64(at<uint64_t>(ws, y.off_blk_flag), 0, (2 * (n + 8) + 7) / 8, st));
+        HIPCHK(launch_fill_u64(bsel.hist_a, 0, 4 * BLK_BINS, st));
+    }
     HIPCHK(launch_cyc_work(nrp, ncol, neid, eslot, nlow, n, la_l, la_h, lb_l, lb_h, counters,
                            (uint64_t)g_tune[TG_TUNE_TASK_WEDGES], L,
                            (uint64_t)g_tune[TG_TUNE_RANGE_BYTES],
-                           (uint64_t)g_tune[TG_TUNE_LIGHT_WEDGES], status, st));
+                           (uint64_t)g_tune[TG_TUNE_LIGHT_WEDGES], bsel, status, st));
     timing_mark("cyc_work");
     CycleArgs ca;
     ca.tasks = nullptr;
@@ -471,6 +525,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
         ca.light_log2 = lg;
     }
     ca.deg_sorted = batch ? 0 : 1;
+    ca.blk_flag = nullptr;
     ca.max_deg = max_deg;
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
@@ -485,6 +540,36 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
         ca.next_idx = 0;
         HIPCHK(launch_cycles(pass, false, ca, light_grid, st));
         timing_mark(pass == 0 ? "cycA_light" : "cycB_light");
+        if (blk_on) {
+            BlkArgs bk;
+            bk.list = at<uint2>(ws, pass == 0 ? y.off_blk_list_a : y.off_blk_list_b);
+            bk.c_count = pass == 0 ? C_BLK_A : C_BLK_B;
+            bk.max_groups = y.blk_groups;
+            bk.cand = pass == 0 ? bsel.cand_a : bsel.cand_b;
+            bk.c_cand = pass == 0 ? C_BLK_CAND_A : C_BLK_CAND_B;
+            bk.hist = pass == 0 ? bsel.hist_a : bsel.hist_b;
+            bk.flag = blk_flag + (pass == 0 ? 0 : (size_t)(n + 8));
+            bk.max_wedges = (uint64_t)y.blk_records;
+            bk.maps_words = (uint64_t)y.heavy_slots * (uint64_t)n * (uint64_t)L;
+            bk.task = (uint32_t)g_tune[TG_TUNE_BLK_TASK];
+            uint32_t *meta = at<uint32_t>(ws, y.off_blk_meta);
+            bk.ioff = meta;
+            bk.tstart = meta + (y.blk_groups + 1);
+            bk.boff = meta + 2 * (size_t)(y.blk_groups + 1);
+            bk.xstart = meta + 3 * (size_t)(y.blk_groups + 1);
+            bk.ipre = at<uint32_t>(ws, y.off_blk_ipre);
+            bk.bcount = at<int64_t>(ws, y.off_blk_bcount);
+            bk.bstart = at<int64_t>(ws, y.off_blk_bstart);
+            bk.pcur = at<uint32_t>(ws, y.off_blk_pcur);
+            bk.bgroup = at<uint32_t>(ws, y.off_blk_bgroup);
+            bk.rec = at<uint16_t>(ws, y.off_blk_rec);
+            bk.nb_max = y.blk_nb;
+            bk.nbk = y.blk_nbk;
+            bk.emit_chunk = blk_emit_chunk(L);
+            HIPCHK(launch_blk(pass, ca, bk, stmp64, st));
+            timing_mark(pass == 0 ? "cycA_blk" : "cycB_blk");
+        }
+        ca.blk_flag = blk_on ? blk_flag + (pass == 0 ? 0 : (size_t)(n + 8)) : nullptr;
         ca.tasks = pass == 0 ? la_h : lb_h;
         ca.count_idx = pass == 0 ? C_A_HEAVY : C_B_HEAVY;
         ca.next_idx = pass == 0 ? C_A_NEXT : C_B_NEXT;
@@ -598,6 +683,14 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     g_timing.stats[7] = (int64_t)cnt_host[C_TRI_SUM];
     g_timing.stats[8] = (int64_t)sh_cand;
     g_timing.stats[9] = (int64_t)S;
+    {
+        const uint64_t kg = (uint64_t)y.blk_groups;
+        const uint64_t ka = cnt_host[C_BLK_A] < kg ? cnt_host[C_BLK_A] : kg;
+        const uint64_t kb = cnt_host[C_BLK_B] < kg ? cnt_host[C_BLK_B] : kg;
+        g_timing.stats[11] = blk_on ? (int64_t)(ka + kb) : 0;
+        g_timing.stats[12] = (int64_t)cnt_host[C_BLK_A_DONE];
+        g_timing.stats[13] = (int64_t)cnt_host[C_BLK_B_DONE];
+    }
     g_timing.stats[10] = (int64_t)H;
     if (end_bits) return status_from_bits(end_bits) == TG_OK ? TG_E_INTERNAL
                                                               : status_from_bits(end_bits);
@@ -1059,6 +1152,17 @@ tg_status tg_set_tuning(int32_t knob, int64_t value) {
         // at least the hub-core degree, so that super-hubs stay inside the core
         if (value < tg::HUB_DMIN || value > INT32_MAX) return TG_E_INVALID_ARG;
         break;
+    case TG_TUNE_BLK_WEDGES:
+    case TG_TUNE_BLK_WEDGES_B:
+        if (value < 1) return TG_E_INVALID_ARG;
+        break;
+    case TG_TUNE_BLK_TASK:
+        if (value < 1024 || value > tg::BLK_TASK) return TG_E_INVALID_ARG;
+        break;
+    case TG_TUNE_BLK_BYTES:
+        // record positions are 32-bit: at most 2^32 records
+        if (value < 0 || value > (int64_t(1) << 33)) return TG_E_INVALID_ARG;
+        break;
     default:
         return TG_E_INVALID_ARG;
     }
@@ -1067,7 +1171,7 @@ tg_status tg_set_tuning(int32_t knob, int64_t value) {
 }
 
 int64_t tg_get_tuning(int32_t knob) {
-    if (knob < 0 || knob > TG_TUNE_SH_DEG) return -1;
+    if (knob < 0 || knob >= TG_NUM_TUNE) return -1;
     return tg::g_tune[knob];
 }
 

@@ -51,6 +51,22 @@ constexpr int HUB_MAX = 8192;         // largest hub core (bit-matrix HUB_MAX^2 
 constexpr int SH_DMIN = 1024;         // default smallest degree of a super-hub (full-row bitmap)
 constexpr int SH_MAX = 2048;          // most super-hubs (the default cap)
 constexpr size_t SH_BUDGET = size_t(512) << 20;  // bytes of super-hub bitmaps and prefixes
+// Blocked heavy 4-cycle groups: the wedges of a group are partitioned by
+// target block (BLK_IDS ids) into 16-bit records (offset in the block, centre
+// type in the top 4 bits, so L <= 16), counted block by block in LDS into one
+// map per group, then walked again in tasks of BLK_TASK wedges that read it.
+constexpr int BLK_SHIFT = 12;
+constexpr int BLK_IDS = 1 << BLK_SHIFT;
+constexpr uint32_t BLK_TASK = 1u << 16;      // default and largest wedges per walk task
+                                             // (32-bit tallies stay exact)
+constexpr int BLK_MAX_GROUPS = 4096;         // blocked groups per pass (each owns one map)
+constexpr int BLK_BINS = 128;                // group-size histogram: 4 bins per octave
+constexpr int64_t BLK_MAX_NODES = int64_t(BLK_IDS) * 8192;  // at most 8192 blocks per group
+constexpr int64_t BLK_MIN_WEDGES = 1 << 16;  // default smallest blocked group (pass A)
+// pass B's groups (many, and small) run faster on the task kernel: off by
+// default (no group reaches 2^31 wedges on this path)
+constexpr int64_t BLK_MIN_WEDGES_B = int64_t(1) << 31;
+constexpr size_t BLK_BUDGET = size_t(4) << 30;  // default bytes of records
 
 // Device-side layout of everything the library keeps in the caller's
 // workspace.  All offsets are byte offsets from the workspace base.
@@ -72,6 +88,14 @@ struct Layout {
     size_t off_node_graph, off_ngraph, off_gedge;   // batched graphs only
     size_t off_SB, off_SP;                          // super-hub bitmaps
     size_t off_pacc;                                // position-aware global accumulators
+    // blocked heavy 4-cycle groups (single graphs; blk_groups = 0: none)
+    int blk_groups;                                 // most blocked groups per pass
+    int blk_nb;                                     // blocks of the widest target range
+    int64_t blk_records;                            // record capacity
+    int64_t blk_nbk;                                // bucket capacity
+    size_t off_blk_list_a, off_blk_list_b, off_blk_meta, off_blk_ipre;
+    size_t off_blk_cand_a, off_blk_cand_b, off_blk_flag, off_blk_hist;
+    size_t off_blk_bcount, off_blk_bstart, off_blk_pcur, off_blk_rec, off_blk_bgroup;
     int sh_max;
     int64_t G;
     size_t total;
@@ -83,7 +107,13 @@ enum Counter {
     C_A_NEXT, C_B_NEXT, C_EDGE_NEXT, C_WEDGES_A, C_WEDGES_B,
     C_WEDGES_A_HEAVY, C_WEDGES_B_HEAVY, C_TRI_SUM, C_HUB_CAND, C_SH_CAND,
     C_TASK_EXTRA, C_HEAVY_GROUPS, C_MAX_GSIZE,
-    C_NUM
+    // blocked groups: list lengths and wedges per pass, then the current
+    // pass's group count, walk tasks, buckets and queue positions
+    C_BLK_A, C_BLK_CAND_A, C_BLK_B, C_BLK_CAND_B, C_BLK_GROUPS, C_BLK_TASKS, C_BLK_BUCKETS,
+    C_BLK_NEXT_H, C_BLK_NEXT_P, C_BLK_NEXT_C, C_BLK_A_DONE, C_BLK_B_DONE, C_BLK_STRIDE,
+    C_BLK_NEXT_E,                           // eight emit queues, one per XCD
+    C_BLK_NEXT_E_END = C_BLK_NEXT_E + 8,
+    C_NUM = C_BLK_NEXT_E_END
 };
 
 // Workspace budgets of the per-workgroup scratch regions: the heavy 4-cycle
@@ -97,6 +127,7 @@ struct Budget {
     int64_t sh_max;
     size_t sh_bytes;
     size_t xyk_bytes;
+    size_t blk_bytes;     // records of the blocked 4-cycle groups (0: no blocked path)
 };
 
 // The budgets the scheduling knobs of the calling thread give.
@@ -143,6 +174,35 @@ struct CycleArgs {
     int light_log2;            // log2 of the light kernel's hash slots (> light bucket)
     int deg_sorted;            // node ids ranked by degree (not the graph-major batch order)
     int64_t max_deg;           // largest degree (or a bound)
+    const uint8_t *blk_flag;   // groups counted by the blocked path (skipped by the tasks), or null
+};
+
+// Blocked heavy 4-cycle groups of one pass (see BLK_SHIFT).
+struct BlkArgs {
+    uint2 *list;            // (group, wedges) of the pass's blocked groups
+    int c_count;            // counter holding the list length
+    int max_groups;
+    const uint2 *cand;      // candidate groups (heavy, at least the smallest blocked size)
+    int c_cand;             // counter holding the candidate count
+    const uint64_t *hist;   // [BLK_BINS][2] candidates and their wedges per size bin
+    uint8_t *flag;          // per node: 1 if its group is blocked
+    uint64_t max_wedges;    // record capacity
+    uint64_t maps_words;    // words of the map region
+    uint32_t task;          // wedges per walk task (at most BLK_TASK)
+    uint32_t *ioff;         // [max_groups + 1] first item prefix of each group
+    uint32_t *tstart;       // [max_groups + 1] first walk task of each group
+    uint32_t *boff;         // [max_groups + 1] first bucket of each group
+    uint32_t *xstart;       // [8][max_groups / 8 + 1] first walk task of group x + 8 i
+                            // within the emit queue of XCD x
+    uint32_t *ipre;         // per group: exclusive wedge prefix of its items, then the total
+    int64_t *bcount;        // [nbk + 1] records per bucket (group, block)
+    int64_t *bstart;        // [nbk + 1] exclusive prefix of bcount
+    uint32_t *pcur;         // [nbk + 1] records placed per bucket
+    uint32_t *bgroup;       // [nbk + 1] group of each bucket
+    uint16_t *rec;          // records grouped by bucket
+    int nb_max;             // blocks of the widest target range
+    int64_t nbk;            // bucket capacity
+    int emit_chunk;         // items per staging round of the emit walk
 };
 
 // Arguments of the per-edge clique / derivation kernels.
@@ -288,11 +348,26 @@ hipError_t launch_node_aggr(const int64_t *nrp, const int32_t *ncol, const uint8
                             const uint32_t *tri_slot, const uint32_t *tdeg,
                             int64_t n, int L, uint64_t *A, uint64_t *D, bool ad_u32,
                             const uint32_t *status, hipStream_t st);
+// Blocked-group candidates of the wedge-count kernel: heavy groups of at
+// least min_wedges wedges (and below 2^31) are appended to cand_a / cand_b
+// and counted in a size histogram (all heavy groups still get their tasks);
+// null lists turn the blocked path off.
+struct BlkSelect {
+    uint2 *cand_a, *cand_b;
+    uint64_t *hist_a, *hist_b;
+    uint64_t min_wedges_a, min_wedges_b;
+};
 hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32_t *neid,
                            const uint32_t *eslot, const uint32_t *nlow, int64_t n, uint32_t *la_l,
                            uint4 *la_h, uint32_t *lb_l, uint4 *lb_h, uint64_t *counters,
                            uint64_t task_wedges, int L, uint64_t range_bytes,
-                           uint64_t light_max, const uint32_t *status, hipStream_t st);
+                           uint64_t light_max, const BlkSelect &blk, const uint32_t *status,
+                           hipStream_t st);
+// The blocked groups of one pass: selection bookkeeping, item prefixes,
+// record partition, block counts into the group maps and the emit walk.
+hipError_t launch_blk(int pass, const CycleArgs &args, const BlkArgs &blk, int64_t *scan_tmp,
+                      hipStream_t st);
+int blk_emit_chunk(int L);
 int heavy_chunk_for(int L, int threads);
 hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned grid, hipStream_t st);
 hipError_t launch_edges(bool heavy, const EdgeArgs &args, unsigned grid, hipStream_t st);

@@ -792,10 +792,14 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
                 // longest tasks do not form the tail
                 uint4 tk = a.tasks[count - 1 - idx];
                 int32_t g = (int32_t)tk.x;
+                if (a.blk_flag && a.blk_flag[g]) tk.z = 0;   // counted by the blocked path
                 int32_t rb = PASS == 0 ? 0 : g + 1;
                 int32_t re = PASS == 0 ? g : (int32_t)a.n;
                 int32_t lo = rb, hi = re;
-                if (tk.z > 1) {
+                if (tk.z == 0) {
+                    hi = lo;
+                    tk.z = 1;
+                } else if (tk.z > 1) {
                     lo = range_cut(a.nrp, rb, re, tk.y, tk.z);
                     hi = range_cut(a.nrp, rb, re, tk.y + 1, tk.z);
                 }
@@ -923,6 +927,674 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
     }
 }
 
+// ------------------------------------------------ blocked heavy 4-cycle groups
+//
+// A large heavy group is counted without a private map per workgroup and
+// without global atomics in its count:
+//   select  the largest candidate groups whose maps and records fit (the
+//           task kernel skips their tasks);
+//   setup   per group: items, walk tasks of a fixed wedge count, target
+//           blocks (exclusive prefixes over the pass's blocked groups);
+//   items   per group: exclusive wedge prefix over its items, so a walk task
+//           (a wedge range) finds its first item by binary search;
+//   hist    per walk task: wedges per target block (LDS), added to the
+//           bucket (group, block) counts;
+//   part    per walk task: the same histogram reserves a run of each
+//           bucket, then every wedge writes a 16-bit record (target offset
+//           in the block, centre type) into its run;
+//   count   per bucket: the records counted in LDS per (target, centre
+//           type), written as the group map's entries of that block (the
+//           degree-class layout of the task maps; only reached targets are
+//           written, and only reached targets are read);
+//   emit    per walk task: every wedge reads its target's entry from the
+//           group's map (read-only now, shared by all tasks of the group)
+//           and adds the counts to the item's LDS tallies, flushed to NC.
+// Every wedge of a blocked group is thus walked four times with streaming
+// reads and written once as a record; the only random accesses are the
+// LDS counts and the emit reads of one map per group.
+
+constexpr int BLK_UNROLL = 4;   // wedges per thread and step of the walks
+constexpr int BLK_HOLD = 2;     // 16-byte record loads a count thread keeps for its second pass
+
+// Largest k < K with start[k] <= t (start[0] = 0 <= t).
+__device__ __forceinline__ int blk_find(const uint32_t *start, int K, uint32_t t) {
+    int lo = 0, hi = K;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= t) lo = mid + 1; else hi = mid;
+    }
+    return lo - 1;
+}
+
+// Size bin of a group of w >= 1 wedges: 4 bins per octave (the octave and
+// the two bits below its leading one), nondecreasing in w.
+__device__ __forceinline__ int blk_bin(uint64_t w) {
+    const int e = 63 - __clzll((long long)w);
+    const int frac = e >= 2 ? (int)((w >> (e - 2)) & 3u) : (e == 1 ? (int)((w & 1u) << 1) : 0);
+    return 4 * e + frac;
+}
+
+// Selection of the pass's blocked groups (one workgroup): the packed map
+// stride of the degree-class layout sets how many group maps fit the map
+// region; the largest size bins are taken from the top while the groups
+// fit those slots and their wedges the records; the chosen candidates are
+// listed and flagged (the task kernel skips their tasks).
+template <int PASS>
+__global__ void __launch_bounds__(1024) k_blk_select(CycleArgs a, BlkArgs b) {
+    __shared__ int s_bin;
+    __shared__ uint32_t s_cnt;
+    if (input_failed(a.status)) return;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        const MapClasses mc = map_classes(a);
+        uint64_t stride = map_word(mc, (int32_t)a.n, map_class(mc, (int32_t)a.n), a.L);
+        if (stride < 1) stride = 1;
+        uint64_t slots = b.maps_words / stride;
+        if (slots > (uint64_t)b.max_groups) slots = (uint64_t)b.max_groups;
+        uint64_t cnt = 0, wsum = 0;
+        int bin = BLK_BINS;
+        for (int q = BLK_BINS - 1; q >= 0; --q) {
+            const uint64_t c = b.hist[2 * q], ws = b.hist[2 * q + 1];
+            if (!c) continue;
+            if (cnt + c > slots || wsum + ws > b.max_wedges) break;
+            cnt += c;
+            wsum += ws;
+            bin = q;
+        }
+        s_bin = bin;
+        s_cnt = 0;
+        a.counters[C_BLK_STRIDE] = stride;
+    }
+    __syncthreads();
+    const int bin = s_bin;
+    const uint64_t ncand = a.counters[b.c_cand];
+    for (uint64_t i = tid; i < ncand; i += 1024) {
+        const uint2 e = b.cand[i];
+        if (blk_bin(e.y) >= bin) {
+            const uint32_t k = atomicAdd(&s_cnt, 1u);
+            b.list[k] = e;
+            b.flag[e.x] = 1;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) a.counters[b.c_count] = s_cnt;
+}
+
+// One walk task: the wedges [f0, f1) of blocked group k (group node g).
+struct BlkWalk {
+    int32_t g;
+    int k;
+    uint32_t f0, f1;
+    uint32_t first;        // item holding wedge f0
+    uint32_t ni;           // items of the group
+    int64_t ib;            // slot of the first item in g's row
+};
+
+// Takes the next walk task from the queue at counters[next]; g < 0 when
+// the queue is empty.  Called by one thread.
+template <int PASS>
+__device__ BlkWalk blk_take(const CycleArgs &a, const BlkArgs &b, int next) {
+    BlkWalk w;
+    w.g = -1;
+    const uint32_t total = (uint32_t)a.counters[C_BLK_TASKS];
+    const uint32_t t = (uint32_t)atomicAdd((unsigned long long *)&a.counters[next], 1ull);
+    if (t >= total) return w;
+    const int K = (int)a.counters[C_BLK_GROUPS];
+    const int k = blk_find(b.tstart, K, t);
+    const uint2 e = b.list[k];
+    w.g = (int32_t)e.x;
+    w.k = k;
+    w.f0 = (t - b.tstart[k]) * b.task;
+    w.f1 = e.y - w.f0 < b.task ? e.y : w.f0 + b.task;
+    w.ni = b.ioff[k + 1] - b.ioff[k] - 1;
+    int64_t ie;
+    item_range<PASS>(a, w.g, w.ib, ie);
+    // last item whose prefix is at most f0 (items without wedges skipped)
+    const uint32_t *pre = b.ipre + b.ioff[k];
+    uint32_t lo = 0, hi = w.ni;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= w.f0) lo = mid + 1; else hi = mid;
+    }
+    w.first = lo - 1;
+    return w;
+}
+
+// Takes the next emit task: from the queue of XCD x + q (mod 8), moving q
+// on when that queue is empty (q = 8: every queue is empty).  Called by one
+// thread; q lives across calls.
+template <int PASS>
+__device__ BlkWalk blk_take_emit(const CycleArgs &a, const BlkArgs &b, int x, int &q) {
+    BlkWalk w;
+    w.g = -1;
+    const int K = (int)a.counters[C_BLK_GROUPS];
+    const int pitch = b.max_groups / 8 + 1;
+    while (q < 8) {
+        const int xx = (x + q) & 7;
+        const int nx = K > xx ? (K - xx + 7) / 8 : 0;
+        const uint32_t *xs = b.xstart + (size_t)xx * pitch;
+        const uint32_t total = xs[nx];
+        const uint32_t p = total ? (uint32_t)atomicAdd(
+                                       (unsigned long long *)&a.counters[C_BLK_NEXT_E + xx], 1ull)
+                                 : 0u;
+        if (p >= total) {
+            ++q;
+            continue;
+        }
+        const int i = blk_find(xs, nx, p);
+        const int k = xx + 8 * i;
+        const uint2 e = b.list[k];
+        w.g = (int32_t)e.x;
+        w.k = k;
+        w.f0 = (p - xs[i]) * b.task;
+        w.f1 = e.y - w.f0 < b.task ? e.y : w.f0 + b.task;
+        w.ni = b.ioff[k + 1] - b.ioff[k] - 1;
+        int64_t ie;
+        item_range<PASS>(a, w.g, w.ib, ie);
+        const uint32_t *pre = b.ipre + b.ioff[k];
+        uint32_t lo = 0, hi = w.ni;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (pre[mid] <= w.f0) lo = mid + 1; else hi = mid;
+        }
+        w.first = lo - 1;
+        return w;
+    }
+    return w;
+}
+
+// Stages the items first + [0, CH) of a walk task that have wedges before
+// f1: per item its first target slot inside the task, its type, edge and
+// orientation flip, and the inclusive scan of its target counts inside the
+// task in scan[].  Returns how many were staged (the same in every thread).
+template <int PASS, int NT>
+__device__ int blk_stage(const CycleArgs &a, const BlkArgs &b, const BlkWalk &w, uint32_t first,
+                         int CH, int64_t *it_tb, uint32_t *it_scan, int32_t *it_tx,
+                         uint32_t *it_eid, int *it_flip, uint32_t *wave_tot) {
+    const int tid = threadIdx.x;
+    const uint32_t *pre = b.ipre + b.ioff[w.k];
+    const uint32_t i = first + (uint32_t)tid;
+    const bool ok = tid < CH && i < w.ni && pre[i] < w.f1;
+    uint32_t len = 0;
+    if (ok) {
+        const uint32_t p0 = pre[i], p1 = pre[i + 1];
+        const uint32_t lo = p0 > w.f0 ? p0 : w.f0;
+        const uint32_t hi = p1 < w.f1 ? p1 : w.f1;
+        len = hi > lo ? hi - lo : 0u;
+        const int64_t s = w.ib + i;
+        const int32_t x = a.ncol[s];
+        const uint32_t e = a.neid[s];
+        int64_t tb, te;
+        target_range<PASS>(a, w.g, x, e, tb, te);
+        it_tb[tid] = tb + (lo - p0);
+        it_tx[tid] = a.ntype[x];
+        it_eid[tid] = e;
+        it_flip[tid] = orient_flip<PASS>(a, w.g, x, e);
+    }
+    const int cnt = __syncthreads_count(ok);
+    block_scan_chunk<NT>(len, it_scan, wave_tot);
+    return cnt;
+}
+
+// Per group: items, walk tasks and blocks, with exclusive prefixes over the
+// pass's blocked groups; resets the queues.  One workgroup.
+template <int PASS>
+__global__ void __launch_bounds__(1024) k_blk_setup(CycleArgs a, BlkArgs b) {
+    constexpr int NT = 1024;
+    __shared__ uint32_t wt[3][NT / WAVE];
+    __shared__ uint32_t carry[3];
+    if (input_failed(a.status)) return;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+    const uint64_t listed = a.counters[b.c_count];
+    const int K = (int)(listed < (uint64_t)b.max_groups ? listed : (uint64_t)b.max_groups);
+    if (tid < 3) carry[tid] = 0;
+    __syncthreads();
+    uint32_t *out[3] = {b.ioff, b.tstart, b.boff};
+    for (int c0 = 0; c0 < K; c0 += NT) {
+        const int k = c0 + tid;
+        uint32_t v[3] = {0u, 0u, 0u};
+        if (k < K) {
+            const uint2 e = b.list[k];
+            const int32_t g = (int32_t)e.x;
+            int64_t ib, ie;
+            item_range<PASS>(a, g, ib, ie);
+            const int64_t span = PASS == 0 ? (int64_t)g : a.n - 1 - g;
+            v[0] = (uint32_t)(ie - ib) + 1u;
+            v[1] = (e.y + b.task - 1) / b.task;
+            v[2] = (uint32_t)((span + BLK_IDS - 1) >> BLK_SHIFT);
+        }
+        uint32_t incl[3];
+        for (int q = 0; q < 3; ++q) {
+            incl[q] = wave_incl_scan(v[q]);
+            if (lane == WAVE - 1) wt[q][wv] = incl[q];
+        }
+        __syncthreads();
+        uint32_t add[3];
+        for (int q = 0; q < 3; ++q) {
+            add[q] = carry[q];
+            for (int r = 0; r < wv; ++r) add[q] += wt[q][r];
+            if (k < K) out[q][k] = add[q] + incl[q] - v[q];
+        }
+        __syncthreads();
+        if (tid == NT - 1)
+            for (int q = 0; q < 3; ++q) carry[q] = add[q] + incl[q];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        for (int q = 0; q < 3; ++q) out[q][K] = carry[q];
+        a.counters[C_BLK_GROUPS] = (uint64_t)K;
+        a.counters[C_BLK_TASKS] = carry[1];
+        a.counters[C_BLK_BUCKETS] = carry[2];
+        a.counters[C_BLK_NEXT_H] = 0;
+        a.counters[C_BLK_NEXT_P] = 0;
+        a.counters[C_BLK_NEXT_C] = 0;
+    }
+    // emit queues: XCD x walks the tasks of groups x, x + 8, x + 16, ...
+    // (their maps then stay in that XCD's L2); thread x scans them
+    __syncthreads();
+    if (tid < 8) {
+        const int x = tid;
+        const int pitch = b.max_groups / 8 + 1;
+        uint32_t *xs = b.xstart + (size_t)x * pitch;
+        uint32_t acc = 0;
+        int i = 0;
+        for (int k = x; k < K; k += 8, ++i) {
+            xs[i] = acc;
+            acc += b.tstart[k + 1] - b.tstart[k];
+        }
+        xs[i] = acc;
+        a.counters[C_BLK_NEXT_E + x] = 0;
+    }
+}
+
+// Per group: exclusive wedge prefix of its items (their target counts), the
+// total checked against the wedge count of the selection; clears the
+// group's bucket counts.
+template <int PASS>
+__global__ void __launch_bounds__(256) k_blk_items(CycleArgs a, BlkArgs b) {
+    constexpr int NT = 256;
+    __shared__ uint32_t wt[NT / WAVE];
+    __shared__ uint32_t s_carry;
+    if (input_failed(a.status)) return;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+    const int K = (int)a.counters[C_BLK_GROUPS];
+    for (int k = blockIdx.x; k < K; k += gridDim.x) {
+        const uint2 e = b.list[k];
+        const int32_t g = (int32_t)e.x;
+        int64_t ib, ie;
+        item_range<PASS>(a, g, ib, ie);
+        const uint32_t ni = (uint32_t)(ie - ib);
+        uint32_t *pre = b.ipre + b.ioff[k];
+        if (tid == 0) s_carry = 0;
+        __syncthreads();
+        for (uint32_t c0 = 0; c0 < ni; c0 += NT) {
+            const uint32_t i = c0 + (uint32_t)tid;
+            uint32_t len = 0;
+            if (i < ni) {
+                const int64_t s = ib + i;
+                int64_t tb, te;
+                target_range<PASS>(a, g, a.ncol[s], a.neid[s], tb, te);
+                len = te > tb ? (uint32_t)(te - tb) : 0u;
+            }
+            const uint32_t incl = wave_incl_scan(len);
+            if (lane == WAVE - 1) wt[wv] = incl;
+            __syncthreads();
+            uint32_t add = s_carry;
+            for (int r = 0; r < wv; ++r) add += wt[r];
+            if (i < ni) pre[i] = add + incl - len;
+            __syncthreads();
+            if (tid == NT - 1) s_carry = add + incl;
+            __syncthreads();
+        }
+        if (tid == 0) {
+            pre[ni] = s_carry;
+            if (s_carry != e.y) atomicOr(a.status, ST_INTERNAL);
+            atomicAdd((unsigned long long *)&a.counters[PASS == 0 ? C_BLK_A_DONE : C_BLK_B_DONE],
+                      (unsigned long long)e.y);
+        }
+        for (uint32_t j = b.boff[k] + tid; j < b.boff[k + 1]; j += NT) {
+            b.bcount[j] = 0;
+            b.pcur[j] = 0u;
+            b.bgroup[j] = (uint32_t)k;
+        }
+        __syncthreads();
+    }
+}
+
+// Adds the task's wedges per target block to hist[] (LDS); with RECORDS,
+// writes each wedge's record at the position hist[] holds for its block
+// instead (and advances it).
+template <int PASS, int NT, bool RECORDS>
+__device__ void blk_walk_blocks(const CycleArgs &a, const BlkArgs &b, const BlkWalk &w,
+                                uint32_t *hist, int64_t *it_tb, uint32_t *it_scan, int32_t *it_tx,
+                                uint32_t *it_eid, int *it_flip, uint32_t *wave_tot) {
+    constexpr int CH = NT / 2;
+    const int tid = threadIdx.x;
+    const int32_t rbase = PASS == 0 ? 0 : w.g + 1;
+    for (uint32_t first = w.first;; first += CH) {
+        const int cnt = blk_stage<PASS, NT>(a, b, w, first, CH, it_tb, it_scan, it_tx, it_eid,
+                                            it_flip, wave_tot);
+        if (cnt == 0) break;
+        const uint32_t total = it_scan[cnt - 1];
+        int o = 0;
+        // BLK_UNROLL wedges per thread and step: their target loads are
+        // issued together
+        for (uint32_t f0 = tid; f0 < total; f0 += NT * BLK_UNROLL) {
+            int32_t y[BLK_UNROLL];
+            int ow[BLK_UNROLL];
+#pragma unroll
+            for (int u = 0; u < BLK_UNROLL; ++u) {
+                const uint32_t f = f0 + (uint32_t)u * NT;
+                ow[u] = -1;
+                if (f < total) {
+                    o = owner_next(it_scan, cnt, f, o);
+                    const uint32_t excl = o ? it_scan[o - 1] : 0u;
+                    ow[u] = o;
+                    y[u] = a.ncol[it_tb[o] + (f - excl)];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < BLK_UNROLL; ++u) {
+                if (ow[u] < 0) continue;
+                const uint32_t rel = (uint32_t)(y[u] - rbase);
+                if (RECORDS) {
+                    const uint32_t pos = atomicAdd(&hist[rel >> BLK_SHIFT], 1u);
+                    b.rec[pos] = (uint16_t)((rel & (BLK_IDS - 1)) |
+                                            ((uint32_t)it_tx[ow[u]] << BLK_SHIFT));
+                } else {
+                    atomicAdd(&hist[rel >> BLK_SHIFT], 1u);
+                }
+            }
+        }
+        __syncthreads();
+        if (cnt < CH) break;
+    }
+}
+
+// Bucket counts: one walk task at a time, wedges per block in LDS, then
+// added to the group's bucket counts.
+template <int PASS, int NT>
+__global__ void __launch_bounds__(NT) k_blk_hist(CycleArgs a, BlkArgs b) {
+    extern __shared__ uint32_t sm_hist[];  // nb_max counts
+    constexpr int CH = NT / 2;
+    __shared__ int64_t it_tb[CH];
+    __shared__ uint32_t it_scan[CH];
+    __shared__ int32_t it_tx[CH];
+    __shared__ uint32_t it_eid[CH];
+    __shared__ int it_flip[CH];
+    __shared__ uint32_t wave_tot[NT / WAVE];
+    __shared__ BlkWalk s_w;
+    if (input_failed(a.status)) return;
+    const int tid = threadIdx.x;
+    while (true) {
+        if (tid == 0) s_w = blk_take<PASS>(a, b, C_BLK_NEXT_H);
+        __syncthreads();
+        const BlkWalk w = s_w;
+        if (w.g < 0) break;
+        const uint32_t b0 = b.boff[w.k], nb = b.boff[w.k + 1] - b0;
+        for (uint32_t j = tid; j < nb; j += NT) sm_hist[j] = 0u;
+        __syncthreads();
+        blk_walk_blocks<PASS, NT, false>(a, b, w, sm_hist, it_tb, it_scan, it_tx, it_eid, it_flip,
+                                         wave_tot);
+        for (uint32_t j = tid; j < nb; j += NT)
+            if (sm_hist[j])
+                atomicAdd((unsigned long long *)&b.bcount[b0 + j], (unsigned long long)sm_hist[j]);
+        __syncthreads();
+    }
+}
+
+// Record partition: one walk task at a time; its wedges per block reserve
+// a run of each bucket, then every wedge writes its record into the run.
+template <int PASS, int NT>
+__global__ void __launch_bounds__(NT) k_blk_part(CycleArgs a, BlkArgs b) {
+    extern __shared__ uint32_t sm_hist[];  // nb_max counts, then record positions
+    constexpr int CH = NT / 2;
+    __shared__ int64_t it_tb[CH];
+    __shared__ uint32_t it_scan[CH];
+    __shared__ int32_t it_tx[CH];
+    __shared__ uint32_t it_eid[CH];
+    __shared__ int it_flip[CH];
+    __shared__ uint32_t wave_tot[NT / WAVE];
+    __shared__ BlkWalk s_w;
+    if (input_failed(a.status)) return;
+    const int tid = threadIdx.x;
+    while (true) {
+        if (tid == 0) s_w = blk_take<PASS>(a, b, C_BLK_NEXT_P);
+        __syncthreads();
+        const BlkWalk w = s_w;
+        if (w.g < 0) break;
+        const uint32_t b0 = b.boff[w.k], nb = b.boff[w.k + 1] - b0;
+        for (uint32_t j = tid; j < nb; j += NT) sm_hist[j] = 0u;
+        __syncthreads();
+        blk_walk_blocks<PASS, NT, false>(a, b, w, sm_hist, it_tb, it_scan, it_tx, it_eid, it_flip,
+                                         wave_tot);
+        for (uint32_t j = tid; j < nb; j += NT) {
+            const uint32_t c = sm_hist[j];
+            if (c)
+                sm_hist[j] = (uint32_t)b.bstart[b0 + j] + atomicAdd(&b.pcur[b0 + j], c);
+        }
+        __syncthreads();
+        blk_walk_blocks<PASS, NT, true>(a, b, w, sm_hist, it_tb, it_scan, it_tx, it_eid, it_flip,
+                                        wave_tot);
+    }
+}
+
+// Block counts: one bucket (group, block) at a time; its records counted in
+// LDS as 16-bit fields per (target, centre type) (a count never exceeds the
+// target's degree, below 2^16 on this path); then a second pass over the
+// records lets the first record of each target (a claim bit) write the
+// target's entry to the group's map in the degree-class layout and clear
+// its fields, so the counts are zero again for the next bucket.  Only
+// reached targets are written, and only reached targets are read.
+template <int PASS>
+__global__ void __launch_bounds__(256) k_blk_count(CycleArgs a, BlkArgs b) {
+    constexpr int NT = 256;
+    extern __shared__ uint32_t sm_cnt[];  // BLK_IDS * L 16-bit fields, then BLK_IDS claim bits
+    __shared__ int s_k;
+    __shared__ uint32_t s_j;
+    __shared__ MapClasses s_mc;
+    if (input_failed(a.status)) return;
+    const int tid = threadIdx.x;
+    const int L = a.L;
+    const uint32_t total = (uint32_t)a.counters[C_BLK_BUCKETS];
+    const size_t stride = (size_t)a.counters[C_BLK_STRIDE];
+    const int words = (BLK_IDS * L + 1) / 2;
+    uint32_t *claim = sm_cnt + words;
+    for (int q = tid; q < words + BLK_IDS / 32; q += NT) sm_cnt[q] = 0u;
+    if (tid == 0) s_mc = map_classes(a);
+    __syncthreads();
+    const MapClasses mc = s_mc;
+    while (true) {
+        if (tid == 0) {
+            const uint32_t j = (uint32_t)atomicAdd((unsigned long long *)&a.counters[C_BLK_NEXT_C], 1ull);
+            s_j = j;
+            s_k = j < total ? (int)b.bgroup[j] : -1;
+        }
+        __syncthreads();
+        const uint32_t j = s_j;
+        const int k = s_k;
+        if (k < 0) break;
+        const int64_t r0 = b.bstart[j], r1 = b.bstart[j + 1];
+        // records 8 at a time (16-byte loads of the 16-byte aligned runs
+        // covering [r0, r1); the record region is padded to 256 bytes); a
+        // bucket of at most NT * 8 * BLK_HOLD records stays in registers
+        // for the second pass
+        const int64_t v0 = r0 >> 3, v1 = (r1 + 7) >> 3;
+        const uint4 *rv = reinterpret_cast<const uint4 *>(b.rec);
+        const bool hold = v1 - v0 <= (int64_t)NT * BLK_HOLD;
+        uint4 held[BLK_HOLD];
+#pragma unroll
+        for (int h = 0; h < BLK_HOLD; ++h) held[h] = make_uint4(0u, 0u, 0u, 0u);
+        for (int64_t v = v0 + tid, h = 0; v < v1; v += NT, ++h) {
+            const uint4 q = rv[v];
+            if (hold) {
+#pragma unroll
+                for (int hh = 0; hh < BLK_HOLD; ++hh)
+                    if (hh == h) held[hh] = q;
+            }
+            const uint32_t wv[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int64_t r = v * 8 + e;
+                if (r < r0 || r >= r1) continue;
+                const uint32_t rc = (wv[e >> 1] >> ((e & 1) * 16)) & 0xffffu;
+                const uint32_t idx = (rc & (BLK_IDS - 1)) * (uint32_t)L + (rc >> BLK_SHIFT);
+                atomicAdd(&sm_cnt[idx >> 1], 1u << ((idx & 1u) * 16u));
+            }
+        }
+        __syncthreads();
+        const int32_t g = (int32_t)b.list[k].x;
+        const int64_t rbase = PASS == 0 ? 0 : (int64_t)g + 1;
+        const int64_t id0 = rbase + (int64_t)(j - b.boff[k]) * BLK_IDS;
+        uint32_t *map = a.maps + (size_t)k * stride;
+        for (int64_t v = v0 + tid, h = 0; v < v1; v += NT, ++h) {
+          uint4 q;
+          if (hold) {
+              q = held[0];
+#pragma unroll
+              for (int hh = 1; hh < BLK_HOLD; ++hh)
+                  if (hh == h) q = held[hh];
+          } else {
+              q = rv[v];
+          }
+          const uint32_t wv[4] = {q.x, q.y, q.z, q.w};
+          for (int e = 0; e < 8; ++e) {
+            const int64_t r = v * 8 + e;
+            if (r < r0 || r >= r1) continue;
+            const uint32_t off = ((wv[e >> 1] >> ((e & 1) * 16)) & 0xffffu) & (BLK_IDS - 1);
+            const uint32_t bit = 1u << (off & 31u);
+            if (atomicOr(&claim[off >> 5], bit) & bit) continue;
+            const int32_t wid = (int32_t)(id0 + off);
+            const uint32_t base = off * (uint32_t)L;
+            const int cls = map_class(mc, wid);
+            const int bits = class_bits(cls);
+            const int F = 32 / bits;
+            uint32_t *my = map + map_word(mc, wid, cls, L);
+            for (int q = 0; q * F < L; ++q) {
+                uint32_t word = 0;
+                for (int t = q * F; t < L && t < (q + 1) * F; ++t) {
+                    const uint32_t idx = base + t;
+                    const uint32_t sh = (idx & 1u) * 16u;
+                    const uint32_t c = (sm_cnt[idx >> 1] >> sh) & 0xffffu;
+                    word |= c << ((t - q * F) * bits);
+                    // this target's fields belong to this thread now
+                    atomicAnd(&sm_cnt[idx >> 1], ~(0xffffu << sh));
+                }
+                my[q] = word;
+            }
+          }
+        }
+        __syncthreads();
+        for (int q = tid; q < BLK_IDS / 32; q += NT) claim[q] = 0u;
+        __syncthreads();
+    }
+}
+
+// Emit walk: one walk task at a time; each wedge reads its target's entry
+// from the group's map and adds count - [same type as the centre] to the
+// item's 32-bit tallies in LDS (a task has at most BLK_TASK wedges of
+// counts below 2^16), flushed to NC after each staging round.
+template <int PASS, int NT>
+__global__ void __launch_bounds__(NT) k_blk_emit(CycleArgs a, BlkArgs b) {
+    extern __shared__ uint32_t sm_acc[];  // emit_chunk * L * L tallies
+    constexpr int CHMAX = NT / 2;
+    __shared__ int64_t it_tb[CHMAX];
+    __shared__ uint32_t it_scan[CHMAX];
+    __shared__ int32_t it_tx[CHMAX];
+    __shared__ uint32_t it_eid[CHMAX];
+    __shared__ int it_flip[CHMAX];
+    __shared__ uint32_t wave_tot[NT / WAVE];
+    __shared__ BlkWalk s_w;
+    __shared__ MapClasses s_mc;
+    if (input_failed(a.status)) return;
+    const int tid = threadIdx.x;
+    const int L = a.L, LL = L * L;
+    const int CH = b.emit_chunk;
+    const size_t stride = (size_t)a.counters[C_BLK_STRIDE];
+    // workgroups are dispatched to the eight XCDs in turn
+    const int xcd = (int)(blockIdx.x & 7u);
+    int q = 0;   // thread 0's queue position
+    if (tid == 0) s_mc = map_classes(a);
+    __syncthreads();
+    const MapClasses mc = s_mc;
+    while (true) {
+        if (tid == 0) s_w = blk_take_emit<PASS>(a, b, xcd, q);
+        __syncthreads();
+        const BlkWalk w = s_w;
+        if (w.g < 0) break;
+        const uint32_t *map = a.maps + (size_t)w.k * stride;
+        for (uint32_t first = w.first;; first += CH) {
+            const int cnt = blk_stage<PASS, NT>(a, b, w, first, CH, it_tb, it_scan, it_tx, it_eid,
+                                                it_flip, wave_tot);
+            if (cnt == 0) break;
+            for (int q = tid; q < cnt * LL; q += NT) sm_acc[q] = 0u;
+            __syncthreads();
+            const uint32_t total = it_scan[cnt - 1];
+            int o = 0;
+            // BLK_UNROLL wedges per thread and step: target loads issued
+            // together, then the first map word of each target together
+            for (uint32_t f0 = tid; f0 < total; f0 += NT * BLK_UNROLL) {
+                int ow[BLK_UNROLL], ty[BLK_UNROLL], cl[BLK_UNROLL];
+                int32_t y[BLK_UNROLL];
+                uint32_t w0[BLK_UNROLL];
+                const uint32_t *my[BLK_UNROLL];
+#pragma unroll
+                for (int u = 0; u < BLK_UNROLL; ++u) {
+                    const uint32_t f = f0 + (uint32_t)u * NT;
+                    ow[u] = -1;
+                    if (f < total) {
+                        o = owner_next(it_scan, cnt, f, o);
+                        const uint32_t excl = o ? it_scan[o - 1] : 0u;
+                        ow[u] = o;
+                        const int64_t ys = it_tb[o] + (f - excl);
+                        y[u] = a.ncol[ys];
+                        ty[u] = a.ctype[ys];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < BLK_UNROLL; ++u) {
+                    if (ow[u] < 0) continue;
+                    cl[u] = map_class(mc, y[u]);
+                    my[u] = map + map_word(mc, y[u], cl[u], L);
+                    w0[u] = my[u][0];
+                }
+#pragma unroll
+                for (int u = 0; u < BLK_UNROLL; ++u) {
+                    if (ow[u] < 0) continue;
+                    const int tx = it_tx[ow[u]];
+                    const int bits = class_bits(cl[u]);
+                    const int F = 32 / bits;
+                    const uint32_t mask = bits == 32 ? 0xffffffffu : (1u << bits) - 1u;
+                    uint32_t *ac = sm_acc + ow[u] * LL;
+                    int wq = 0;
+                    uint32_t word = w0[u];
+                    for (int t = 0; t < L; ++t) {
+                        if (t / F != wq) {
+                            wq = t / F;
+                            word = my[u][wq];
+                        }
+                        const uint32_t c = (word >> ((t % F) * bits)) & mask;
+                        const uint32_t val = c - (t == tx ? 1u : 0u);
+                        if (val) atomicAdd(&ac[pass_entry<PASS>(t, ty[u], L)], val);
+                    }
+                }
+            }
+            __syncthreads();
+            for (int q = tid; q < cnt * LL; q += NT) {
+                const uint32_t v = sm_acc[q];
+                if (!v) continue;
+                const int oo = q / LL;
+                const int pq = q - oo * LL;
+                const int p = pq / L, r = pq - p * L;
+                const int canon = it_flip[oo] ? r * L + p : pq;
+                nc_add(a, (size_t)it_eid[oo] * LL + canon, v);
+            }
+            __syncthreads();
+            if (cnt < CH) break;
+        }
+    }
+}
+
 // Bytes of one target's map entry assumed by the id-range splits (the
 // 16-bit class; targets of smaller degree take less, of degree >= 2^16 more).
 __device__ __forceinline__ uint64_t map_bytes_per_id(int L) { return (uint64_t)((L + 1) / 2) * 4; }
@@ -936,11 +1608,21 @@ __device__ __forceinline__ uint64_t map_bytes_per_id(int L) { return (uint64_t)(
 __device__ void push_groups(int32_t v, uint64_t w, uint32_t *light, uint4 *heavy,
                             uint64_t *counters, int c_light, int c_heavy, int c_wedges,
                             int c_wedges_heavy, uint64_t task_wedges, int64_t range_ids,
-                            uint64_t map_bytes_per_id, uint64_t range_bytes, uint64_t light_max) {
+                            uint64_t map_bytes_per_id, uint64_t range_bytes, uint64_t light_max,
+                            uint2 *cand, uint64_t *chist, int c_cand, uint64_t cand_min) {
     const int lane = lane_id();
     const uint64_t below = (1ull << lane) - 1ull;
     const bool is_light = w && w <= light_max;
     const bool is_heavy = w > light_max;
+    // candidates of the blocked path (a node is one group per pass, so the
+    // list holds at most n entries); the selection takes the largest later
+    if (cand && is_heavy && w >= cand_min && w < (1ull << 31)) {
+        const uint64_t k = atomicAdd((unsigned long long *)&counters[c_cand], 1ull);
+        cand[k] = make_uint2((uint32_t)v, (uint32_t)w);
+        const int bin = blk_bin(w);
+        atomicAdd((unsigned long long *)&chist[2 * bin], 1ull);
+        atomicAdd((unsigned long long *)&chist[2 * bin + 1], (unsigned long long)w);
+    }
     uint64_t bl = __ballot(is_light);
     if (bl) {
         uint64_t base = 0;
@@ -1021,7 +1703,8 @@ __global__ void __launch_bounds__(256) k_cyc_work(
     const uint32_t *__restrict__ nlow, int64_t n, uint32_t *__restrict__ listA_light,
     uint4 *__restrict__ listA_heavy, uint32_t *__restrict__ listB_light,
     uint4 *__restrict__ listB_heavy, uint64_t *__restrict__ counters, uint64_t task_wedges,
-    int L, uint64_t range_bytes, uint64_t light_max, const uint32_t *__restrict__ status) {
+    int L, uint64_t range_bytes, uint64_t light_max, BlkSelect bs,
+    const uint32_t *__restrict__ status) {
     if (input_failed(status)) return;
     __shared__ int64_t s_thr;
     if (threadIdx.x == 0) {
@@ -1046,10 +1729,12 @@ __global__ void __launch_bounds__(256) k_cyc_work(
                 node_wedges(nrp, ncol, neid, eslot, nlow, (int32_t)v, s, wa, wb);
         push_groups((int32_t)v, wa, listA_light, listA_heavy, counters, C_A_LIGHT, C_A_HEAVY,
                     C_WEDGES_A, C_WEDGES_A_HEAVY, task_wedges, v,
-                    map_bytes_per_id(L), range_bytes, light_max);
+                    map_bytes_per_id(L), range_bytes, light_max, bs.cand_a, bs.hist_a, C_BLK_CAND_A,
+                    bs.min_wedges_a);
         push_groups((int32_t)v, wb, listB_light, listB_heavy, counters, C_B_LIGHT, C_B_HEAVY,
                     C_WEDGES_B, C_WEDGES_B_HEAVY, task_wedges, n - 1 - v,
-                    map_bytes_per_id(L), range_bytes, light_max);
+                    map_bytes_per_id(L), range_bytes, light_max, bs.cand_b, bs.hist_b, C_BLK_CAND_B,
+                    bs.min_wedges_b);
     }
     for (int64_t v = thr + wid; v < n; v += nwaves) {
         uint64_t wa = 0, wb = 0;
@@ -1059,10 +1744,12 @@ __global__ void __launch_bounds__(256) k_cyc_work(
         wb = wave_sum_u64(wb);
         push_groups((int32_t)v, lane == 0 ? wa : 0ull, listA_light, listA_heavy, counters,
                     C_A_LIGHT, C_A_HEAVY, C_WEDGES_A, C_WEDGES_A_HEAVY, task_wedges, v,
-                    map_bytes_per_id(L), range_bytes, light_max);
+                    map_bytes_per_id(L), range_bytes, light_max, bs.cand_a, bs.hist_a, C_BLK_CAND_A,
+                    bs.min_wedges_a);
         push_groups((int32_t)v, lane == 0 ? wb : 0ull, listB_light, listB_heavy, counters,
                     C_B_LIGHT, C_B_HEAVY, C_WEDGES_B, C_WEDGES_B_HEAVY, task_wedges, n - 1 - v,
-                    map_bytes_per_id(L), range_bytes, light_max);
+                    map_bytes_per_id(L), range_bytes, light_max, bs.cand_b, bs.hist_b, C_BLK_CAND_B,
+                    bs.min_wedges_b);
     }
 }
 
@@ -1236,7 +1923,8 @@ hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32
                            const uint32_t *eslot, const uint32_t *nlow, int64_t n, uint32_t *la_l,
                            uint4 *la_h, uint32_t *lb_l, uint4 *lb_h, uint64_t *counters,
                            uint64_t task_wedges, int L, uint64_t range_bytes,
-                           uint64_t light_max, const uint32_t *status, hipStream_t st) {
+                           uint64_t light_max, const BlkSelect &blk, const uint32_t *status,
+                           hipStream_t st) {
     if (n <= 0) return hipSuccess;
     int dev = 0, cus = 0;
     hipError_t err = hipGetDevice(&dev);
@@ -1247,7 +1935,7 @@ hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32
     int64_t cap = (int64_t)(cus > 0 ? cus : 256) * 16;
     unsigned grid = (unsigned)(want < cap ? want : cap);
     k_cyc_work<<<grid, 256, 0, st>>>(nrp, ncol, neid, eslot, nlow, n, la_l, la_h, lb_l, lb_h,
-                                     counters, task_wedges, L, range_bytes, light_max, status);
+                                     counters, task_wedges, L, range_bytes, light_max, blk, status);
     LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1278,6 +1966,60 @@ hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned g
     }
     LAUNCH_CHECK();
     return hipSuccess;
+}
+
+// Threads of the blocked walk kernels (hist, part, emit).
+constexpr int BLK_WALK_THREADS = 512;
+
+// Items per emit staging round: at most a quarter of the threads, with
+// 32-bit tallies of L^2 words per item within 64 KB of LDS.
+int blk_emit_chunk(int L) {
+    int ch = 65536 / (L * L * (int)sizeof(uint32_t));
+    // at most 128 items: three emit workgroups fit a CU's LDS
+    if (ch > BLK_WALK_THREADS / 4) ch = BLK_WALK_THREADS / 4;
+    if (ch < 1) ch = 1;
+    return ch;
+}
+
+template <int PASS>
+static hipError_t launch_blk_pass(const CycleArgs &a, const BlkArgs &b, int64_t *scan_tmp,
+                                  unsigned wide, hipStream_t st) {
+    constexpr int NT = BLK_WALK_THREADS;
+    const size_t sh_hist = (size_t)b.nb_max * sizeof(uint32_t);
+    const size_t sh_cnt = (size_t)((BLK_IDS * a.L + 1) / 2 + BLK_IDS / 32) * sizeof(uint32_t);
+    const size_t sh_acc = (size_t)b.emit_chunk * a.L * a.L * sizeof(uint32_t);
+    k_blk_select<PASS><<<1, 1024, 0, st>>>(a, b);
+    LAUNCH_CHECK();
+    k_blk_setup<PASS><<<1, 1024, 0, st>>>(a, b);
+    LAUNCH_CHECK();
+    k_blk_items<PASS><<<(unsigned)b.max_groups, 256, 0, st>>>(a, b);
+    LAUNCH_CHECK();
+    k_blk_hist<PASS, NT><<<wide, NT, sh_hist, st>>>(a, b);
+    LAUNCH_CHECK();
+    hipError_t err = launch_excl_scan(b.bcount, b.bstart, b.nbk + 1, scan_tmp, a.status, st);
+    if (err != hipSuccess) return err;
+    k_blk_part<PASS, NT><<<wide, NT, sh_hist, st>>>(a, b);
+    LAUNCH_CHECK();
+    k_blk_count<PASS><<<wide, 256, sh_cnt, st>>>(a, b);
+    LAUNCH_CHECK();
+    k_blk_emit<PASS, NT><<<wide, NT, sh_acc, st>>>(a, b);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_blk(int pass, const CycleArgs &a, const BlkArgs &b, int64_t *scan_tmp,
+                      hipStream_t st) {
+    if (b.max_groups <= 0 || a.L > 16 || b.emit_chunk < 1 || b.emit_chunk > BLK_WALK_THREADS / 2 ||
+        b.task < 1 || b.task > BLK_TASK)
+        return hipErrorInvalidValue;
+    int dev = 0, cus = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return err;
+    err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (err != hipSuccess) return err;
+    const unsigned wide = (unsigned)(cus > 0 ? cus : 256) * 4;
+    return pass == 0 ? launch_blk_pass<0>(a, b, scan_tmp, wide, st)
+                     : launch_blk_pass<1>(a, b, scan_tmp, wide, st);
 }
 
 hipError_t launch_global_finalize(const uint64_t *gacc, int L, int gw, uint64_t *out, uint32_t *status,

@@ -148,7 +148,7 @@ struct Server {
     int workers = 0;
     int64_t single_edges = 0, max_batch_edges = 0;
     int device = 0;
-    int64_t knobs[TG_TUNE_SH_DEG + 1];
+    int64_t knobs[TG_NUM_TUNE];
     Arena pool;                       // request blocks: the arena after the worker regions
     size_t pool_base = 0;
     std::mutex mu;
@@ -363,11 +363,13 @@ void Server::worker_main(int w) {
     }
     // the creating thread's scheduling knobs, with the per-workgroup
     // scratch budgets kept within this worker's region
-    for (int k = 0; k <= TG_TUNE_SH_DEG; ++k) tg_set_tuning(k, knobs[k]);
+    for (int k = 0; k < TG_NUM_TUNE; ++k) tg_set_tuning(k, knobs[k]);
     if ((size_t)knobs[TG_TUNE_MAP_BYTES] > worker_bytes / 4)
         tg_set_tuning(TG_TUNE_MAP_BYTES, (int64_t)(worker_bytes / 4 > 0 ? worker_bytes / 4 : 1));
     if ((size_t)knobs[TG_TUNE_TBUF_BYTES] > worker_bytes / 8)
         tg_set_tuning(TG_TUNE_TBUF_BYTES, (int64_t)(worker_bytes / 8 > 0 ? worker_bytes / 8 : 1));
+    if ((size_t)knobs[TG_TUNE_BLK_BYTES] > worker_bytes / 16)
+        tg_set_tuning(TG_TUNE_BLK_BYTES, (int64_t)(worker_bytes / 16));
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
         std::lock_guard<std::mutex> lk(mu);
@@ -442,7 +444,7 @@ tg_status tg_server_create(void *arena, size_t arena_bytes, int32_t workers, siz
         delete h;
         return TG_E_DEVICE;
     }
-    for (int k = 0; k <= TG_TUNE_SH_DEG; ++k) s.knobs[k] = tg_get_tuning(k);
+    for (int k = 0; k < TG_NUM_TUNE; ++k) s.knobs[k] = tg_get_tuning(k);
     s.pool_base = (size_t)workers * worker_bytes;
     s.pool.reset(arena_bytes - s.pool_base);
     for (int w = 0; w < workers; ++w) s.threads.emplace_back([&s, w] { s.worker_main(w); });

@@ -102,6 +102,16 @@ def test_tuning_knobs():
     for bad in ({"light_wedges": 0}, {"light_wedges": 513}, {"edge_deg": 0}, {"edge_deg": 1025}):
         with pytest.raises(P.TGError):
             P.set_tuning(**bad)
+    # blocked 4-cycle path: its record space is workspace, 0 turns it off
+    assert base["blk_wedges"] == 1 << 16 and base["blk_bytes"] == 4 << 30
+    assert base["blk_task"] == 1 << 16 and base["blk_wedges_b"] == 1 << 31
+    with_blk = P.workspace_bytes(1000, 8000, 5)
+    P.set_tuning(blk_bytes=0)
+    assert 0 < P.workspace_bytes(1000, 8000, 5) < with_blk - (4 << 30) + (1 << 20)
+    for bad in ({"blk_wedges": 0}, {"blk_bytes": -1}, {"blk_bytes": (8 << 30) + 1},
+                {"blk_task": 1023}, {"blk_task": (1 << 16) + 1}, {"blk_wedges_b": 0}):
+        with pytest.raises(P.TGError):
+            P.set_tuning(**bad)
     P.set_tuning(**base)
     assert P.get_tuning() == base
 

@@ -246,6 +246,50 @@ def test_split_heavy_tasks(oracle_mod, knobs):
         P.set_tuning(**old)
 
 
+@pytest.mark.parametrize("knobs", [dict(blk_wedges=1, blk_wedges_b=1),
+                                   dict(blk_wedges=4000, blk_wedges_b=4000),
+                                   dict(blk_wedges=1, blk_wedges_b=1, blk_bytes="half"),
+                                   dict(blk_wedges=1, blk_wedges_b=1, light_wedges=1),
+                                   dict(blk_wedges=1, blk_wedges_b=1, blk_task=1024)],
+                         ids=["heavy_blocked", "large_blocked", "record_space_cut",
+                              "every_group", "small_tasks"])
+def test_blocked_groups(oracle_mod, knobs):
+    """Heavy 4-cycle groups counted by the blocked path (records per target
+    block, LDS block counts into one map per group, emit walk over wedge
+    ranges): every heavy group, only the large ones, a record space that
+    sends most groups back to the task kernel, every group of two or more
+    wedges (more candidates than list slots), and walk tasks of 1024 wedges
+    (items spread over several tasks).  Counts must not change; L = 16
+    fills the record's four type bits."""
+    import paper_2010_14058_amd as P
+
+    g = G.chung_lu_typed(20000, 16.0, 2.1, 3000.0, 5, type_probs=G.zipf_probs(5, 1.2),
+                         homophily=0.6, seed=5, name="cl_20k_blocked")
+    knobs = dict(knobs)
+    if knobs.get("blk_bytes") == "half":
+        # records for about half of pass A's heavy wedges: the selection
+        # must stop inside the size bins
+        old = P.set_tuning(blk_bytes=0)
+        run_gpu(g, per_edge=False)
+        P.set_tuning(**old)
+        knobs["blk_bytes"] = P.last_stats()["heavy_wedges_pass_a"]
+    old = P.set_tuning(**knobs)
+    try:
+        check(oracle_mod, g)
+        st = P.last_stats()
+        assert st["blocked_groups"] >= 1
+        assert st["blocked_wedges_pass_a"] > 0 and st["blocked_wedges_pass_b"] > 0
+        assert st["blocked_wedges_pass_a"] <= st["heavy_wedges_pass_a"]
+        if "blk_bytes" in knobs:
+            assert st["blocked_wedges_pass_a"] <= knobs["blk_bytes"] // 2
+            assert st["blocked_wedges_pass_a"] < st["heavy_wedges_pass_a"]
+        check(oracle_mod, G.config_graph(2, scale=0.01))
+        check(oracle_mod, G.chung_lu_typed(3000, 12.0, 2.1, 800.0, 16, seed=3, name="cl_3k_L16"))
+        assert P.last_stats()["blocked_groups"] >= 1
+    finally:
+        P.set_tuning(**old)
+
+
 @pytest.mark.parametrize("derive_edges", [1, 2, 3, 4])
 def test_derive_batching(oracle_mod, derive_edges):
     """The light kernel derives several edges' rows in one wave; every batch
