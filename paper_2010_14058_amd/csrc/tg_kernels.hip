@@ -954,6 +954,7 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
 // LDS counts and the emit reads of one map per group.
 
 constexpr int BLK_UNROLL = 4;   // wedges per thread and step of the walks
+constexpr int BLK_COPIES = 1;   // copies of each item's emit tallies (more copies measured no faster)
 constexpr int BLK_HOLD = 2;     // 16-byte record loads a count thread keeps for its second pass
 
 // Largest k < K with start[k] <= t (start[0] = 0 <= t).
@@ -1270,6 +1271,7 @@ __device__ void blk_walk_blocks(const CycleArgs &a, const BlkArgs &b, const BlkW
                                 uint32_t *it_eid, int *it_flip, uint32_t *wave_tot) {
     constexpr int CH = NT / 2;
     const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
     const int32_t rbase = PASS == 0 ? 0 : w.g + 1;
     for (uint32_t first = w.first;; first += CH) {
         const int cnt = blk_stage<PASS, NT>(a, b, w, first, CH, it_tb, it_scan, it_tx, it_eid,
@@ -1295,14 +1297,30 @@ __device__ void blk_walk_blocks(const CycleArgs &a, const BlkArgs &b, const BlkW
             }
 #pragma unroll
             for (int u = 0; u < BLK_UNROLL; ++u) {
-                if (ow[u] < 0) continue;
-                const uint32_t rel = (uint32_t)(y[u] - rbase);
+                // the lanes of a wave hold consecutive wedges, mostly of one
+                // item with ascending targets: runs of lanes share a block,
+                // and the first lane of each run counts the whole run (one
+                // LDS atomic per run instead of one per wedge)
+                const bool act = ow[u] >= 0;
+                const uint32_t rel = act ? (uint32_t)(y[u] - rbase) : 0u;
+                const int key = act ? (int)(rel >> BLK_SHIFT) : -1;
+                const int prev = __shfl_up(key, 1, WAVE);
+                const bool lead = act && (lane == 0 || prev != key);
+                const uint64_t leads = __ballot(lead);
+                const uint64_t acts = __ballot(act);
+                const int nact = __popcll(acts);   // active lanes are a prefix
+                const uint64_t above = lane == WAVE - 1 ? 0ull : leads >> (lane + 1);
+                const int run = above ? __ffsll((long long)above) : nact - lane;
+                const int head = WAVE - 1 - __clzll((long long)(leads & ((2ull << lane) - 1ull)));
                 if (RECORDS) {
-                    const uint32_t pos = atomicAdd(&hist[rel >> BLK_SHIFT], 1u);
-                    b.rec[pos] = (uint16_t)((rel & (BLK_IDS - 1)) |
-                                            ((uint32_t)it_tx[ow[u]] << BLK_SHIFT));
-                } else {
-                    atomicAdd(&hist[rel >> BLK_SHIFT], 1u);
+                    uint32_t pos = 0;
+                    if (lead) pos = atomicAdd(&hist[key], (uint32_t)run);
+                    pos = (uint32_t)__shfl((int)pos, act ? head : lane, WAVE) + (uint32_t)(lane - head);
+                    if (act)
+                        b.rec[pos] = (uint16_t)((rel & (BLK_IDS - 1)) |
+                                                ((uint32_t)it_tx[ow[u]] << BLK_SHIFT));
+                } else if (lead) {
+                    atomicAdd(&hist[key], (uint32_t)run);
                 }
             }
         }
@@ -1392,6 +1410,7 @@ __global__ void __launch_bounds__(256) k_blk_count(CycleArgs a, BlkArgs b) {
     extern __shared__ uint32_t sm_cnt[];  // BLK_IDS * L 16-bit fields, then BLK_IDS claim bits
     __shared__ int s_k;
     __shared__ uint32_t s_j;
+    __shared__ int64_t s_r[2];
     __shared__ MapClasses s_mc;
     if (input_failed(a.status)) return;
     const int tid = threadIdx.x;
@@ -1404,17 +1423,33 @@ __global__ void __launch_bounds__(256) k_blk_count(CycleArgs a, BlkArgs b) {
     if (tid == 0) s_mc = map_classes(a);
     __syncthreads();
     const MapClasses mc = s_mc;
+    // thread 0 takes the next bucket while the workgroup counts the current
+    // one (the queue position is only read at the next step)
+    uint32_t next = 0;
+    if (tid == 0) next = (uint32_t)atomicAdd((unsigned long long *)&a.counters[C_BLK_NEXT_C], 1ull);
     while (true) {
         if (tid == 0) {
-            const uint32_t j = (uint32_t)atomicAdd((unsigned long long *)&a.counters[C_BLK_NEXT_C], 1ull);
+            // empty buckets are passed over here, without a barrier
+            uint32_t j = next;
+            int64_t r0 = 0, r1 = 0;
+            while (j < total) {
+                r0 = b.bstart[j];
+                r1 = b.bstart[j + 1];
+                if (r1 != r0) break;
+                j = (uint32_t)atomicAdd((unsigned long long *)&a.counters[C_BLK_NEXT_C], 1ull);
+            }
             s_j = j;
             s_k = j < total ? (int)b.bgroup[j] : -1;
+            s_r[0] = r0;
+            s_r[1] = r1;
+            if (j < total)
+                next = (uint32_t)atomicAdd((unsigned long long *)&a.counters[C_BLK_NEXT_C], 1ull);
         }
         __syncthreads();
         const uint32_t j = s_j;
         const int k = s_k;
         if (k < 0) break;
-        const int64_t r0 = b.bstart[j], r1 = b.bstart[j + 1];
+        const int64_t r0 = s_r[0], r1 = s_r[1];
         // records 8 at a time (16-byte loads of the 16-byte aligned runs
         // covering [r0, r1); the record region is padded to 256 bytes); a
         // bucket of at most NT * 8 * BLK_HOLD records stays in registers
@@ -1462,8 +1497,10 @@ __global__ void __launch_bounds__(256) k_blk_count(CycleArgs a, BlkArgs b) {
             const int64_t r = v * 8 + e;
             if (r < r0 || r >= r1) continue;
             const uint32_t off = ((wv[e >> 1] >> ((e & 1) * 16)) & 0xffffu) & (BLK_IDS - 1);
-            const uint32_t bit = 1u << (off & 31u);
-            if (atomicOr(&claim[off >> 5], bit) & bit) continue;
+            // claim bit of target off: word off % 128, bit off / 128, so
+            // that consecutive targets (dense hub blocks) use different banks
+            const uint32_t bit = 1u << (off >> 7);
+            if (atomicOr(&claim[off & (BLK_IDS / 32 - 1)], bit) & bit) continue;
             const int32_t wid = (int32_t)(id0 + off);
             const uint32_t base = off * (uint32_t)L;
             const int cls = map_class(mc, wid);
@@ -1527,17 +1564,16 @@ __global__ void __launch_bounds__(NT) k_blk_emit(CycleArgs a, BlkArgs b) {
             const int cnt = blk_stage<PASS, NT>(a, b, w, first, CH, it_tb, it_scan, it_tx, it_eid,
                                                 it_flip, wave_tot);
             if (cnt == 0) break;
-            for (int q = tid; q < cnt * LL; q += NT) sm_acc[q] = 0u;
+            for (int q = tid; q < cnt * LL * BLK_COPIES; q += NT) sm_acc[q] = 0u;
             __syncthreads();
             const uint32_t total = it_scan[cnt - 1];
             int o = 0;
             // BLK_UNROLL wedges per thread and step: target loads issued
             // together, then the first map word of each target together
             for (uint32_t f0 = tid; f0 < total; f0 += NT * BLK_UNROLL) {
-                int ow[BLK_UNROLL], ty[BLK_UNROLL], cl[BLK_UNROLL];
+                int ow[BLK_UNROLL], ty[BLK_UNROLL];
                 int32_t y[BLK_UNROLL];
                 uint32_t w0[BLK_UNROLL];
-                const uint32_t *my[BLK_UNROLL];
 #pragma unroll
                 for (int u = 0; u < BLK_UNROLL; ++u) {
                     const uint32_t f = f0 + (uint32_t)u * NT;
@@ -1554,34 +1590,37 @@ __global__ void __launch_bounds__(NT) k_blk_emit(CycleArgs a, BlkArgs b) {
 #pragma unroll
                 for (int u = 0; u < BLK_UNROLL; ++u) {
                     if (ow[u] < 0) continue;
-                    cl[u] = map_class(mc, y[u]);
-                    my[u] = map + map_word(mc, y[u], cl[u], L);
-                    w0[u] = my[u][0];
+                    w0[u] = map[map_word(mc, y[u], map_class(mc, y[u]), L)];
                 }
 #pragma unroll
                 for (int u = 0; u < BLK_UNROLL; ++u) {
                     if (ow[u] < 0) continue;
                     const int tx = it_tx[ow[u]];
-                    const int bits = class_bits(cl[u]);
+                    const int cls = map_class(mc, y[u]);
+                    const int bits = class_bits(cls);
                     const int F = 32 / bits;
                     const uint32_t mask = bits == 32 ? 0xffffffffu : (1u << bits) - 1u;
-                    uint32_t *ac = sm_acc + ow[u] * LL;
+                    // BLK_COPIES interleaved copies of each item's tallies:
+                    // lanes of one item and target type spread over banks
+                    uint32_t *ac = sm_acc + (size_t)ow[u] * LL * BLK_COPIES + (tid & (BLK_COPIES - 1));
                     int wq = 0;
                     uint32_t word = w0[u];
                     for (int t = 0; t < L; ++t) {
                         if (t / F != wq) {
                             wq = t / F;
-                            word = my[u][wq];
+                            word = map[map_word(mc, y[u], cls, L) + wq];
                         }
                         const uint32_t c = (word >> ((t % F) * bits)) & mask;
                         const uint32_t val = c - (t == tx ? 1u : 0u);
-                        if (val) atomicAdd(&ac[pass_entry<PASS>(t, ty[u], L)], val);
+                        if (val) atomicAdd(&ac[pass_entry<PASS>(t, ty[u], L) * BLK_COPIES], val);
                     }
                 }
             }
             __syncthreads();
             for (int q = tid; q < cnt * LL; q += NT) {
-                const uint32_t v = sm_acc[q];
+                uint32_t v = 0;
+#pragma unroll
+                for (int r = 0; r < BLK_COPIES; ++r) v += sm_acc[q * BLK_COPIES + r];
                 if (!v) continue;
                 const int oo = q / LL;
                 const int pq = q - oo * LL;
@@ -1970,13 +2009,14 @@ hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned g
 
 // Threads of the blocked walk kernels (hist, part, emit).
 constexpr int BLK_WALK_THREADS = 512;
+constexpr int BLK_EMIT_THREADS = 512;
 
-// Items per emit staging round: at most a quarter of the threads, with
-// 32-bit tallies of L^2 words per item within 64 KB of LDS.
+// Items per emit staging round: at most a quarter of the emit threads,
+// with BLK_COPIES copies of 32-bit tallies of L^2 words per item within
+// 64 KB of LDS.
 int blk_emit_chunk(int L) {
-    int ch = 65536 / (L * L * (int)sizeof(uint32_t));
-    // at most 128 items: three emit workgroups fit a CU's LDS
-    if (ch > BLK_WALK_THREADS / 4) ch = BLK_WALK_THREADS / 4;
+    int ch = 65536 / (L * L * (int)sizeof(uint32_t) * BLK_COPIES);
+    if (ch > BLK_EMIT_THREADS / 4) ch = BLK_EMIT_THREADS / 4;
     if (ch < 1) ch = 1;
     return ch;
 }
@@ -1987,7 +2027,7 @@ static hipError_t launch_blk_pass(const CycleArgs &a, const BlkArgs &b, int64_t 
     constexpr int NT = BLK_WALK_THREADS;
     const size_t sh_hist = (size_t)b.nb_max * sizeof(uint32_t);
     const size_t sh_cnt = (size_t)((BLK_IDS * a.L + 1) / 2 + BLK_IDS / 32) * sizeof(uint32_t);
-    const size_t sh_acc = (size_t)b.emit_chunk * a.L * a.L * sizeof(uint32_t);
+    const size_t sh_acc = (size_t)b.emit_chunk * a.L * a.L * sizeof(uint32_t) * BLK_COPIES;
     k_blk_select<PASS><<<1, 1024, 0, st>>>(a, b);
     LAUNCH_CHECK();
     k_blk_setup<PASS><<<1, 1024, 0, st>>>(a, b);
@@ -2002,14 +2042,14 @@ static hipError_t launch_blk_pass(const CycleArgs &a, const BlkArgs &b, int64_t 
     LAUNCH_CHECK();
     k_blk_count<PASS><<<wide, 256, sh_cnt, st>>>(a, b);
     LAUNCH_CHECK();
-    k_blk_emit<PASS, NT><<<wide, NT, sh_acc, st>>>(a, b);
+    k_blk_emit<PASS, BLK_EMIT_THREADS><<<wide, BLK_EMIT_THREADS, sh_acc, st>>>(a, b);
     LAUNCH_CHECK();
     return hipSuccess;
 }
 
 hipError_t launch_blk(int pass, const CycleArgs &a, const BlkArgs &b, int64_t *scan_tmp,
                       hipStream_t st) {
-    if (b.max_groups <= 0 || a.L > 16 || b.emit_chunk < 1 || b.emit_chunk > BLK_WALK_THREADS / 2 ||
+    if (b.max_groups <= 0 || a.L > 16 || b.emit_chunk < 1 || b.emit_chunk > BLK_EMIT_THREADS / 2 ||
         b.task < 1 || b.task > BLK_TASK)
         return hipErrorInvalidValue;
     int dev = 0, cus = 0;
