@@ -526,6 +526,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     }
     ca.deg_sorted = batch ? 0 : 1;
     ca.blk_flag = nullptr;
+    ca.hub_ids = 0;
     ca.max_deg = max_deg;
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
@@ -573,7 +574,12 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
         ca.tasks = pass == 0 ? la_h : lb_h;
         ca.count_idx = pass == 0 ? C_A_HEAVY : C_B_HEAVY;
         ca.next_idx = pass == 0 ? C_A_NEXT : C_B_NEXT;
-        ca.chunk = heavy_chunk_for(L, pass == 0 ? HEAVY_THREADS_A : HEAVY_THREADS_B);
+        // pass B's targets lie above both ends of the wedge and concentrate
+        // on the top-ranked nodes (single graphs: ids ranked by degree):
+        // those are counted in LDS (16-bit fields, so only when every degree
+        // is below 2^16)
+        ca.hub_ids = pass == 1 && !batch && words32 && L <= 16 ? heavy_hub_ids(L, n) : 0;
+        ca.chunk = heavy_chunk_for(L, pass == 0 ? HEAVY_THREADS_A : HEAVY_THREADS_B, ca.hub_ids);
         HIPCHK(launch_cycles(pass, true, ca, (unsigned)y.heavy_slots, st));
         timing_mark(pass == 0 ? "cycA_heavy" : "cycB_heavy");
     }

@@ -175,6 +175,7 @@ struct CycleArgs {
     int deg_sorted;            // node ids ranked by degree (not the graph-major batch order)
     int64_t max_deg;           // largest degree (or a bound)
     const uint8_t *blk_flag;   // groups counted by the blocked path (skipped by the tasks), or null
+    int hub_ids;               // task kernel: targets among the top hub_ids ids counted in LDS (0: none)
 };
 
 // Blocked heavy 4-cycle groups of one pass (see BLK_SHIFT).
@@ -368,7 +369,8 @@ hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32
 hipError_t launch_blk(int pass, const CycleArgs &args, const BlkArgs &blk, int64_t *scan_tmp,
                       hipStream_t st);
 int blk_emit_chunk(int L);
-int heavy_chunk_for(int L, int threads);
+int heavy_chunk_for(int L, int threads, int hub_ids = 0);
+int heavy_hub_ids(int L, int64_t n);
 hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned grid, hipStream_t st);
 hipError_t launch_edges(bool heavy, const EdgeArgs &args, unsigned grid, hipStream_t st);
 hipError_t launch_derive(const EdgeArgs &args, unsigned grid, hipStream_t st);

@@ -768,6 +768,11 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
     const int LL = L * L;
     const int CH = a.chunk;
     uint64_t *acc = sm_heavy;  // CH * L * L
+    // hub targets (the top hub_ids ids) are counted in LDS as 16-bit fields
+    // per (target, centre type) after the tallies; the rest in the map
+    uint32_t *hub = reinterpret_cast<uint32_t *>(acc + (size_t)CH * LL);
+    const int32_t hub_lo = a.hub_ids > 0 ? (int32_t)(a.n - a.hub_ids) : (int32_t)a.n;
+    const int hub_words = (a.hub_ids * L + 1) / 2;
     __shared__ int32_t it_tx[HEAVY_CHUNK];  // type of each staged item (the centre)
     __shared__ int64_t it_tb[HEAVY_CHUNK];
     __shared__ uint32_t it_scan[HEAVY_CHUNK];
@@ -804,8 +809,10 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
                     hi = range_cut(a.nrp, rb, re, tk.y + 1, tk.z);
                 }
                 const MapClasses mc = s_mc;
+                // hub targets live in LDS: only [lo, min(hi, hub_lo)) of the map is used
+                const int32_t mhi = hi < hub_lo ? hi : (lo > hub_lo ? lo : hub_lo);
                 const uint64_t w0 = map_word(mc, lo, map_class(mc, lo), L);
-                const uint64_t w1 = map_word(mc, hi, map_class(mc, hi), L);
+                const uint64_t w1 = map_word(mc, mhi, map_class(mc, mhi), L);
                 uint64_t wt = tk.w / tk.z;
                 s_task[0] = g;
                 s_task[1] = lo;
@@ -824,10 +831,15 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
         item_range<PASS>(a, g, ib, ie);
         const MapClasses mc = s_mc;
         if (hi <= lo) continue;
+        if (hub_words > 0 && hi > hub_lo) {
+            for (int q = tid; q < hub_words; q += HEAVY_THREADS) hub[q] = 0u;
+            __syncthreads();
+        }
         if (streamed) {
+            const int32_t mhi = hi < hub_lo ? hi : (lo > hub_lo ? lo : hub_lo);
             const uint64_t w0 = map_word(mc, lo, map_class(mc, lo), L);
             uint32_t *p0 = map + w0;
-            size_t cnt = (size_t)(map_word(mc, hi, map_class(mc, hi), L) - w0);
+            size_t cnt = (size_t)(map_word(mc, mhi, map_class(mc, mhi), L) - w0);
             size_t head = ((16 - ((uintptr_t)p0 & 15)) & 15) / 4;
             if (head > cnt) head = cnt;
             if ((size_t)tid < head) p0[tid] = 0u;
@@ -872,6 +884,27 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
                     const int tx = it_tx[o];
                     const int64_t ys = it_tb[o] + (f - excl);
                     const int32_t y = a.ncol[ys];
+                    if (y >= hub_lo) {
+                        // a count never exceeds the target's degree (below
+                        // 2^16 whenever hub targets are on)
+                        const uint32_t base = (uint32_t)(y - hub_lo) * (uint32_t)L;
+                        if (phase == 1) {
+                            const uint32_t idx = base + (uint32_t)tx;
+                            atomicAdd(&hub[idx >> 1], 1u << ((idx & 1u) * 16u));
+                        } else if (phase == 2) {
+                            const int ty = a.ctype[ys];
+                            uint64_t *ac = acc + (size_t)o * LL;
+                            for (int t = 0; t < L; ++t) {
+                                const uint32_t idx = base + (uint32_t)t;
+                                const uint32_t c = (hub[idx >> 1] >> ((idx & 1u) * 16u)) & 0xffffu;
+                                const uint32_t val = c - (t == tx ? 1u : 0u);
+                                if (val)
+                                    atomicAdd((unsigned long long *)&ac[pass_entry<PASS>(t, ty, L)],
+                                              (unsigned long long)val);
+                            }
+                        }
+                        continue;
+                    }
                     const int cls = map_class(mc, y);
                     const int bits = class_bits(cls);
                     const int F = 32 / bits;
@@ -1982,14 +2015,24 @@ hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32
 // Items per staging round: at most threads / 2, with LDS accumulators of
 // L^2 words per item within 32 KB (256 threads) or 50 KB (512 or more), so
 // a workgroup stays under 64 KB of LDS for every L.
-int heavy_chunk_for(int L, int threads) {
+int heavy_chunk_for(int L, int threads, int hub_ids) {
     // LDS for the per-item tallies: a 1024-thread workgroup runs alone on
-    // its CU (registers), so it may take twice the budget of smaller ones
-    const int budget = threads >= 1024 ? 102400 : threads >= 512 ? 51200 : 32768;
+    // its CU (registers), so it may take twice the budget of smaller ones;
+    // with hub targets in LDS the tallies and the hub fields share it
+    int budget = threads >= 1024 ? 102400 : threads >= 512 ? 51200 : 32768;
+    if (hub_ids > 0) budget = 36864 - ((hub_ids * L + 1) / 2) * 4;   // four workgroups per CU
     int ch = budget / (L * L * 8);
     if (ch > threads / 2) ch = threads / 2;
     if (ch < 1) ch = 1;
     return ch;
+}
+
+// Hub targets of the pass-B task kernel: the top ids whose 16-bit fields
+// (L per target) fit 20 KB of LDS, a power of two, at most n.
+int heavy_hub_ids(int L, int64_t n) {
+    int h = 1;
+    while ((int64_t)(2 * h) * L * 2 <= 20480) h *= 2;
+    return (int64_t)h > n ? (int)n : h;
 }
 
 hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned grid, hipStream_t st) {
@@ -1999,7 +2042,8 @@ hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned g
         if (pass == 0) k_cyc_light<0><<<grid, 64, sh, st>>>(args);
         else k_cyc_light<1><<<grid, 64, sh, st>>>(args);
     } else {
-        size_t sh = (size_t)args.chunk * args.L * args.L * sizeof(uint64_t);
+        size_t sh = (size_t)args.chunk * args.L * args.L * sizeof(uint64_t) +
+                    (size_t)((args.hub_ids * args.L + 1) / 2) * sizeof(uint32_t);
         if (pass == 0) k_cyc_heavy<0, HEAVY_THREADS_A><<<grid, HEAVY_THREADS_A, sh, st>>>(args);
         else k_cyc_heavy<1, HEAVY_THREADS_B><<<grid, HEAVY_THREADS_B, sh, st>>>(args);
     }
