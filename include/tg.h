@@ -572,6 +572,11 @@ const char *tg_last_error(void);
  *   TG_TUNE_BLK_WEDGES_B (default 2^31 = off, >= 1): the same bound for
  *       pass-B groups (grouped by the vertex opposite the top), which are
  *       many and small on power-law graphs.
+ *   TG_TUNE_HUB_LDS      (default 20480, 0..65536): LDS bytes of the pass-B
+ *       task kernel for 16-bit counts of targets among the top-ranked ids
+ *       (single graphs with every degree below 2^16; pass-B targets lie
+ *       above both ends of their wedge, so they concentrate there); 0 keeps
+ *       every target in the workgroup's map.
  *   TG_TUNE_BLK_BYTES    (default 4 GiB, 0..2^33): workspace bytes for the
  *       blocked path's records (two bytes per wedge of the blocked groups of
  *       one pass); 0 turns the blocked path off.
@@ -596,9 +601,10 @@ typedef enum {
     TG_TUNE_BLK_WEDGES = 12,
     TG_TUNE_BLK_BYTES = 13,
     TG_TUNE_BLK_TASK = 14,
-    TG_TUNE_BLK_WEDGES_B = 15
+    TG_TUNE_BLK_WEDGES_B = 15,
+    TG_TUNE_HUB_LDS = 16
 } tg_tune;
-#define TG_NUM_TUNE 16
+#define TG_NUM_TUNE 17
 tg_status tg_set_tuning(int32_t knob, int64_t value);
 int64_t tg_get_tuning(int32_t knob);
 

@@ -217,7 +217,8 @@ def kernel_sums() -> dict:
 TUNE_KNOBS = {"task_wedges": 0, "clear_bytes": 1, "cycle_slots": 2, "map_bytes": 3,
               "edge_slots": 4, "tbuf_bytes": 5, "range_bytes": 6, "derive_edges": 7,
               "light_wedges": 8, "edge_deg": 9, "sh_max": 10, "sh_deg": 11,
-              "blk_wedges": 12, "blk_bytes": 13, "blk_task": 14, "blk_wedges_b": 15}
+              "blk_wedges": 12, "blk_bytes": 13, "blk_task": 14, "blk_wedges_b": 15,
+              "hub_lds": 16}
 
 
 def set_tuning(**knobs) -> dict:

@@ -42,7 +42,7 @@ static const size_t XYK_BUDGET = size_t(16) << 30;
 thread_local int64_t g_tune[TG_NUM_TUNE] = {
     TASK_WEDGES, SEQ_CLEAR_BYTES, MAX_CYCLE_SLOTS, (int64_t)MAP_BUDGET, MAX_HEAVY_SLOTS,
     (int64_t)TBUF_BUDGET, TASK_RANGE_BYTES, 0, LIGHT_MAXW, TCAP, SH_MAX, SH_DMIN,
-    BLK_MIN_WEDGES, (int64_t)BLK_BUDGET, BLK_TASK, BLK_MIN_WEDGES_B};
+    BLK_MIN_WEDGES, (int64_t)BLK_BUDGET, BLK_TASK, BLK_MIN_WEDGES_B, HUB_LDS_BYTES};
 
 // Temporary storage of the preparation's sorts and prefix sums.
 static size_t sort_tmp_bytes(int64_t n, int64_t nnz) {
@@ -578,7 +578,8 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
         // on the top-ranked nodes (single graphs: ids ranked by degree):
         // those are counted in LDS (16-bit fields, so only when every degree
         // is below 2^16)
-        ca.hub_ids = pass == 1 && !batch && words32 && L <= 16 ? heavy_hub_ids(L, n) : 0;
+        ca.hub_ids = pass == 1 && !batch && words32 && L <= 16
+                         ? heavy_hub_ids(L, n, g_tune[TG_TUNE_HUB_LDS]) : 0;
         ca.chunk = heavy_chunk_for(L, pass == 0 ? HEAVY_THREADS_A : HEAVY_THREADS_B, ca.hub_ids);
         HIPCHK(launch_cycles(pass, true, ca, (unsigned)y.heavy_slots, st));
         timing_mark(pass == 0 ? "cycA_heavy" : "cycB_heavy");
@@ -1161,6 +1162,9 @@ tg_status tg_set_tuning(int32_t knob, int64_t value) {
     case TG_TUNE_BLK_WEDGES:
     case TG_TUNE_BLK_WEDGES_B:
         if (value < 1) return TG_E_INVALID_ARG;
+        break;
+    case TG_TUNE_HUB_LDS:
+        if (value < 0 || value > 65536) return TG_E_INVALID_ARG;
         break;
     case TG_TUNE_BLK_TASK:
         if (value < 1024 || value > tg::BLK_TASK) return TG_E_INVALID_ARG;

@@ -66,6 +66,7 @@ constexpr int64_t BLK_MIN_WEDGES = 1 << 16;  // default smallest blocked group (
 // pass B's groups (many, and small) run faster on the task kernel: off by
 // default (no group reaches 2^31 wedges on this path)
 constexpr int64_t BLK_MIN_WEDGES_B = int64_t(1) << 31;
+constexpr int64_t HUB_LDS_BYTES = 20480;   // default LDS for the pass-B kernel's hub targets
 constexpr size_t BLK_BUDGET = size_t(4) << 30;  // default bytes of records
 
 // Device-side layout of everything the library keeps in the caller's
@@ -370,7 +371,7 @@ hipError_t launch_blk(int pass, const CycleArgs &args, const BlkArgs &blk, int64
                       hipStream_t st);
 int blk_emit_chunk(int L);
 int heavy_chunk_for(int L, int threads, int hub_ids = 0);
-int heavy_hub_ids(int L, int64_t n);
+int heavy_hub_ids(int L, int64_t n, int64_t bytes);
 hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned grid, hipStream_t st);
 hipError_t launch_edges(bool heavy, const EdgeArgs &args, unsigned grid, hipStream_t st);
 hipError_t launch_derive(const EdgeArgs &args, unsigned grid, hipStream_t st);

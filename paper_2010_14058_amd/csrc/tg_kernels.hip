@@ -2020,7 +2020,12 @@ int heavy_chunk_for(int L, int threads, int hub_ids) {
     // its CU (registers), so it may take twice the budget of smaller ones;
     // with hub targets in LDS the tallies and the hub fields share it
     int budget = threads >= 1024 ? 102400 : threads >= 512 ? 51200 : 32768;
-    if (hub_ids > 0) budget = 36864 - ((hub_ids * L + 1) / 2) * 4;   // four workgroups per CU
+    if (hub_ids > 0) {
+        // four workgroups per CU while the hub fields leave room, else the
+        // tallies keep 8 KB
+        budget = 36864 - ((hub_ids * L + 1) / 2) * 4;
+        if (budget < 8192) budget = 8192;
+    }
     int ch = budget / (L * L * 8);
     if (ch > threads / 2) ch = threads / 2;
     if (ch < 1) ch = 1;
@@ -2028,10 +2033,11 @@ int heavy_chunk_for(int L, int threads, int hub_ids) {
 }
 
 // Hub targets of the pass-B task kernel: the top ids whose 16-bit fields
-// (L per target) fit 20 KB of LDS, a power of two, at most n.
-int heavy_hub_ids(int L, int64_t n) {
+// (L per target) fit `bytes` of LDS, a power of two, at most n (0: none).
+int heavy_hub_ids(int L, int64_t n, int64_t bytes) {
+    if ((int64_t)L * 2 > bytes) return 0;
     int h = 1;
-    while ((int64_t)(2 * h) * L * 2 <= 20480) h *= 2;
+    while ((int64_t)(2 * h) * L * 2 <= bytes) h *= 2;
     return (int64_t)h > n ? (int)n : h;
 }
 

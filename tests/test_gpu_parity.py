@@ -290,6 +290,23 @@ def test_blocked_groups(oracle_mod, knobs):
         P.set_tuning(**old)
 
 
+@pytest.mark.parametrize("hub_lds", [0, 64, 65536])
+def test_pass_b_hub_targets(oracle_mod, hub_lds):
+    """Pass-B targets among the top-ranked ids counted in LDS: off, a hub set
+    of a few ids (the boundary inside most target lists) and the largest LDS
+    share; counts must not change (L = 5 and L = 16)."""
+    import paper_2010_14058_amd as P
+
+    old = P.set_tuning(hub_lds=hub_lds)
+    try:
+        g = G.chung_lu_typed(20000, 16.0, 2.1, 3000.0, 5, type_probs=G.zipf_probs(5, 1.2),
+                             homophily=0.6, seed=5, name="cl_20k_hub")
+        check(oracle_mod, g)
+        check(oracle_mod, G.chung_lu_typed(3000, 12.0, 2.1, 800.0, 16, seed=3, name="cl_3k_L16"))
+    finally:
+        P.set_tuning(**old)
+
+
 @pytest.mark.parametrize("derive_edges", [1, 2, 3, 4])
 def test_derive_batching(oracle_mod, derive_edges):
     """The light kernel derives several edges' rows in one wave; every batch
