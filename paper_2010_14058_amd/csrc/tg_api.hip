@@ -94,6 +94,10 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G, con
         y.blk_nb = (int)((n + BLK_IDS - 1) / BLK_IDS);
         int64_t rec = (int64_t)(bud.blk_bytes / sizeof(uint16_t));
         if (rec > (int64_t)0xffffffffll) rec = (int64_t)0xffffffffll;
+        // a pass has at most sum over nodes of d^2 <= nnz^2 / 2 wedges
+        // (nnz < 2^32): small graphs need no more records than that
+        const double cap = 0.5 * (double)nnz * (double)nnz + 8.0;
+        if ((double)rec > cap) rec = (int64_t)cap;
         y.blk_records = rec;
         y.blk_nbk = (int64_t)y.blk_groups * y.blk_nb;
     }
@@ -492,15 +496,21 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
     // blocked path: counts of a blocked group's targets never exceed their
     // degree, held in 16-bit fields
     const bool blk_on = y.blk_groups > 0 && !batch && words32 && L <= 16;
+    // a group has at most min(d_max^2, nnz) wedges: a pass whose smallest
+    // blocked group cannot occur launches nothing of the blocked path
+    const uint64_t wedge_cap = (uint64_t)(max_deg * max_deg < nnz ? max_deg * max_deg : nnz);
+    const bool blk_pass[2] = {blk_on && wedge_cap >= (uint64_t)g_tune[TG_TUNE_BLK_WEDGES],
+                              blk_on && wedge_cap >= (uint64_t)g_tune[TG_TUNE_BLK_WEDGES_B] &&
+                                  g_tune[TG_TUNE_BLK_WEDGES_B] < (int64_t(1) << 31)};
     BlkSelect bsel;
-    bsel.cand_a = blk_on ? at<uint2>(ws, y.off_blk_cand_a) : nullptr;
-    bsel.cand_b = blk_on ? at<uint2>(ws, y.off_blk_cand_b) : nullptr;
+    bsel.cand_a = blk_pass[0] ? at<uint2>(ws, y.off_blk_cand_a) : nullptr;
+    bsel.cand_b = blk_pass[1] ? at<uint2>(ws, y.off_blk_cand_b) : nullptr;
     bsel.hist_a = blk_on ? at<uint64_t>(ws, y.off_blk_hist) : nullptr;
     bsel.hist_b = blk_on ? bsel.hist_a + 2 * BLK_BINS : nullptr;
     bsel.min_wedges_a = (uint64_t)g_tune[TG_TUNE_BLK_WEDGES];
     bsel.min_wedges_b = (uint64_t)g_tune[TG_TUNE_BLK_WEDGES_B];
     uint8_t *blk_flag = blk_on ? at<uint8_t>(ws, y.off_blk_flag) : nullptr;
-    if (blk_on) {
+    if (blk_pass[0] || blk_pass[1]) {
         // flags of both passes and the histograms start at zero
         HIPCHK(launch_fill_u64(at<uint64_t>(ws, y.off_blk_flag), 0, (2 * (n + 8) + 7) / 8, st));
         HIPCHK(launch_fill_u64(bsel.hist_a, 0, 4 * BLK_BINS, st));
@@ -541,7 +551,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
         ca.next_idx = 0;
         HIPCHK(launch_cycles(pass, false, ca, light_grid, st));
         timing_mark(pass == 0 ? "cycA_light" : "cycB_light");
-        if (blk_on) {
+        if (blk_pass[pass]) {
             BlkArgs bk;
             bk.list = at<uint2>(ws, pass == 0 ? y.off_blk_list_a : y.off_blk_list_b);
             bk.c_count = pass == 0 ? C_BLK_A : C_BLK_B;
@@ -570,7 +580,7 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
             HIPCHK(launch_blk(pass, ca, bk, stmp64, st));
             timing_mark(pass == 0 ? "cycA_blk" : "cycB_blk");
         }
-        ca.blk_flag = blk_on ? blk_flag + (pass == 0 ? 0 : (size_t)(n + 8)) : nullptr;
+        ca.blk_flag = blk_pass[pass] ? blk_flag + (pass == 0 ? 0 : (size_t)(n + 8)) : nullptr;
         ca.tasks = pass == 0 ? la_h : lb_h;
         ca.count_idx = pass == 0 ? C_A_HEAVY : C_B_HEAVY;
         ca.next_idx = pass == 0 ? C_A_NEXT : C_B_NEXT;

@@ -106,9 +106,14 @@ def test_tuning_knobs():
     assert base["blk_wedges"] == 1 << 16 and base["blk_bytes"] == 4 << 30
     assert base["blk_task"] == 1 << 16 and base["blk_wedges_b"] == 1 << 31
     assert base["hub_lds"] == 20480
-    with_blk = P.workspace_bytes(1000, 8000, 5)
+    # (a graph of 8e5 adjacency slots may need the whole 4 GiB of records;
+    # a small one gets at most nnz^2 / 2 records)
+    with_blk = P.workspace_bytes(100000, 800000, 5)
+    small_blk = P.workspace_bytes(1000, 8000, 5)
     P.set_tuning(blk_bytes=0)
-    assert 0 < P.workspace_bytes(1000, 8000, 5) < with_blk - (4 << 30) + (1 << 20)
+    assert 0 < P.workspace_bytes(100000, 800000, 5) < with_blk - (4 << 30) + (1 << 20)
+    assert 0 < P.workspace_bytes(1000, 8000, 5) < small_blk <= \
+        P.workspace_bytes(1000, 8000, 5) + 8000 * 8000 + (4 << 20)
     for bad in ({"blk_wedges": 0}, {"blk_bytes": -1}, {"blk_bytes": (8 << 30) + 1},
                 {"blk_task": 1023}, {"blk_task": (1 << 16) + 1}, {"blk_wedges_b": 0},
                 {"hub_lds": -1}, {"hub_lds": 65537}):
