@@ -768,6 +768,11 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
     const int LL = L * L;
     const int CH = a.chunk;
     uint64_t *acc = sm_heavy;  // CH * L * L
+    // every degree below 2^16: a round's tally of one item (its targets in
+    // the task, each count below 2^16) stays below 2^32, so the tallies are
+    // 32-bit words in two interleaved copies (same LDS, fewer conflicts)
+    uint32_t *acc32 = reinterpret_cast<uint32_t *>(sm_heavy);
+    const bool t32 = a.nc_u32 != 0;
     // hub targets (the top hub_ids ids) are counted in LDS as 16-bit fields
     // per (target, centre type) after the tallies; the rest in the map
     uint32_t *hub = reinterpret_cast<uint32_t *>(acc + (size_t)CH * LL);
@@ -894,11 +899,15 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
                         } else if (phase == 2) {
                             const int ty = a.ctype[ys];
                             uint64_t *ac = acc + (size_t)o * LL;
+                            uint32_t *ac32 = acc32 + (size_t)o * LL * 2 + (tid & 1);
                             for (int t = 0; t < L; ++t) {
                                 const uint32_t idx = base + (uint32_t)t;
                                 const uint32_t c = (hub[idx >> 1] >> ((idx & 1u) * 16u)) & 0xffffu;
                                 const uint32_t val = c - (t == tx ? 1u : 0u);
-                                if (val)
+                                if (!val) continue;
+                                if (t32)
+                                    atomicAdd(&ac32[pass_entry<PASS>(t, ty, L) * 2], val);
+                                else
                                     atomicAdd((unsigned long long *)&ac[pass_entry<PASS>(t, ty, L)],
                                               (unsigned long long)val);
                             }
@@ -920,6 +929,7 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
                     } else {
                         int ty = a.ctype[ys];
                         uint64_t *ac = acc + (size_t)o * LL;
+                        uint32_t *ac32 = acc32 + (size_t)o * LL * 2 + (tid & 1);
                         // one load per map word (atomic loads are not merged by
                         // the compiler), the counts of its types extracted
                         const uint32_t mask = bits == 32 ? 0xffffffffu : (1u << bits) - 1u;
@@ -933,7 +943,10 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
                             }
                             const uint32_t c = (word >> ((t % F) * bits)) & mask;
                             const uint32_t val = c - (t == tx ? 1u : 0u);
-                            if (val)
+                            if (!val) continue;
+                            if (t32)
+                                atomicAdd(&ac32[pass_entry<PASS>(t, ty, L) * 2], val);
+                            else
                                 atomicAdd((unsigned long long *)&ac[pass_entry<PASS>(t, ty, L)],
                                           (unsigned long long)val);
                         }
@@ -942,7 +955,7 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
                 __syncthreads();
                 if (phase == 2) {
                     for (int q = tid; q < nitems * LL; q += HEAVY_THREADS) {
-                        uint64_t v = acc[q];
+                        uint64_t v = t32 ? (uint64_t)acc32[2 * q] + acc32[2 * q + 1] : acc[q];
                         if (!v) continue;
                         int o = q / LL;
                         int pq = q - o * LL;
