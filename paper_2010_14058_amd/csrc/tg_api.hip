@@ -59,6 +59,7 @@ Budget budget_from_tuning() {
     b.sh_bytes = SH_BUDGET;
     b.xyk_bytes = XYK_BUDGET;
     b.blk_bytes = (size_t)g_tune[TG_TUNE_BLK_BYTES];
+    b.blk_task = g_tune[TG_TUNE_BLK_TASK];
     return b;
 }
 
@@ -100,6 +101,11 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G, con
         if ((double)rec > cap) rec = (int64_t)cap;
         y.blk_records = rec;
         y.blk_nbk = (int64_t)y.blk_groups * y.blk_nb;
+        // histogram matrix: one row of block counts per walk task, at most
+        // (records / task + groups) tasks of blk_nb blocks; kept within 1 GiB
+        const int64_t task = bud.blk_task > 0 ? bud.blk_task : BLK_TASK;
+        const int64_t mat = (rec / task + y.blk_groups + 1) * (int64_t)y.blk_nb;
+        y.blk_mat = mat * (int64_t)sizeof(uint32_t) <= (int64_t(1) << 30) ? mat : 0;
     }
     {
         int64_t scan_len = nnz > y.blk_nbk ? nnz : y.blk_nbk;
@@ -177,7 +183,8 @@ tg_status plan_layout(int64_t n, int64_t nnz, int L, Layout *lay, int64_t G, con
         const size_t kg = (size_t)y.blk_groups;
         y.off_blk_list_a = take(sizeof(uint2) * kg);
         y.off_blk_list_b = take(sizeof(uint2) * kg);
-        y.off_blk_meta = take(sizeof(uint32_t) * (3 * (kg + 1) + 8 * (kg / 8 + 1)));
+        y.off_blk_meta = take(sizeof(uint32_t) * (4 * (kg + 1) + 8 * (kg / 8 + 1)));
+        y.off_blk_mat = take(sizeof(uint32_t) * (size_t)(y.blk_mat > 0 ? y.blk_mat : 1));
         // items of distinct groups: at most one per adjacency slot, plus a
         // total per group
         y.off_blk_ipre = take(sizeof(uint32_t) * ((size_t)nnz + kg + 1));
@@ -567,7 +574,10 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
             bk.ioff = meta;
             bk.tstart = meta + (y.blk_groups + 1);
             bk.boff = meta + 2 * (size_t)(y.blk_groups + 1);
-            bk.xstart = meta + 3 * (size_t)(y.blk_groups + 1);
+            bk.moff = meta + 3 * (size_t)(y.blk_groups + 1);
+            bk.xstart = meta + 4 * (size_t)(y.blk_groups + 1);
+            bk.mat = at<uint32_t>(ws, y.off_blk_mat);
+            bk.mat_cap = y.blk_mat;
             bk.ipre = at<uint32_t>(ws, y.off_blk_ipre);
             bk.bcount = at<int64_t>(ws, y.off_blk_bcount);
             bk.bstart = at<int64_t>(ws, y.off_blk_bstart);

@@ -96,7 +96,8 @@ struct Layout {
     int64_t blk_nbk;                                // bucket capacity
     size_t off_blk_list_a, off_blk_list_b, off_blk_meta, off_blk_ipre;
     size_t off_blk_cand_a, off_blk_cand_b, off_blk_flag, off_blk_hist;
-    size_t off_blk_bcount, off_blk_bstart, off_blk_pcur, off_blk_rec, off_blk_bgroup;
+    size_t off_blk_bcount, off_blk_bstart, off_blk_pcur, off_blk_rec, off_blk_bgroup, off_blk_mat;
+    int64_t blk_mat;                                // histogram matrix capacity (0: none)
     int sh_max;
     int64_t G;
     size_t total;
@@ -112,6 +113,7 @@ enum Counter {
     // pass's group count, walk tasks, buckets and queue positions
     C_BLK_A, C_BLK_CAND_A, C_BLK_B, C_BLK_CAND_B, C_BLK_GROUPS, C_BLK_TASKS, C_BLK_BUCKETS,
     C_BLK_NEXT_H, C_BLK_NEXT_P, C_BLK_NEXT_C, C_BLK_A_DONE, C_BLK_B_DONE, C_BLK_STRIDE,
+    C_BLK_MAT,                              // 1: this pass's histogram rows are in the matrix
     C_BLK_NEXT_E,                           // eight emit queues, one per XCD
     C_BLK_NEXT_E_END = C_BLK_NEXT_E + 8,
     C_NUM = C_BLK_NEXT_E_END
@@ -129,6 +131,7 @@ struct Budget {
     size_t sh_bytes;
     size_t xyk_bytes;
     size_t blk_bytes;     // records of the blocked 4-cycle groups (0: no blocked path)
+    int64_t blk_task;     // wedges per blocked walk task (sizes the histogram matrix)
 };
 
 // The budgets the scheduling knobs of the calling thread give.
@@ -194,6 +197,9 @@ struct BlkArgs {
     uint32_t *ioff;         // [max_groups + 1] first item prefix of each group
     uint32_t *tstart;       // [max_groups + 1] first walk task of each group
     uint32_t *boff;         // [max_groups + 1] first bucket of each group
+    uint32_t *moff;         // [max_groups + 1] first histogram-matrix entry of each group
+    uint32_t *mat;          // per walk task its wedges per block (rows of the group's block count)
+    int64_t mat_cap;        // matrix capacity (0: the partition walks its task twice)
     uint32_t *xstart;       // [8][max_groups / 8 + 1] first walk task of group x + 8 i
                             // within the emit queue of XCD x
     uint32_t *ipre;         // per group: exclusive wedge prefix of its items, then the total

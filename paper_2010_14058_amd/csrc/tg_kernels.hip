@@ -1071,6 +1071,7 @@ __global__ void __launch_bounds__(1024) k_blk_select(CycleArgs a, BlkArgs b) {
 struct BlkWalk {
     int32_t g;
     int k;
+    uint32_t t;            // walk task index
     uint32_t f0, f1;
     uint32_t first;        // item holding wedge f0
     uint32_t ni;           // items of the group
@@ -1091,6 +1092,7 @@ __device__ BlkWalk blk_take(const CycleArgs &a, const BlkArgs &b, int next) {
     const uint2 e = b.list[k];
     w.g = (int32_t)e.x;
     w.k = k;
+    w.t = t;
     w.f0 = (t - b.tstart[k]) * b.task;
     w.f1 = e.y - w.f0 < b.task ? e.y : w.f0 + b.task;
     w.ni = b.ioff[k + 1] - b.ioff[k] - 1;
@@ -1188,18 +1190,20 @@ __device__ int blk_stage(const CycleArgs &a, const BlkArgs &b, const BlkWalk &w,
 template <int PASS>
 __global__ void __launch_bounds__(1024) k_blk_setup(CycleArgs a, BlkArgs b) {
     constexpr int NT = 1024;
-    __shared__ uint32_t wt[3][NT / WAVE];
-    __shared__ uint32_t carry[3];
+    __shared__ uint32_t wt[4][NT / WAVE];
+    __shared__ uint32_t carry[4];
+    __shared__ unsigned long long s_mtot;
     if (input_failed(a.status)) return;
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
     const uint64_t listed = a.counters[b.c_count];
     const int K = (int)(listed < (uint64_t)b.max_groups ? listed : (uint64_t)b.max_groups);
-    if (tid < 3) carry[tid] = 0;
+    if (tid < 4) carry[tid] = 0;
+    if (tid == 0) s_mtot = 0;
     __syncthreads();
-    uint32_t *out[3] = {b.ioff, b.tstart, b.boff};
+    uint32_t *out[4] = {b.ioff, b.tstart, b.boff, b.moff};
     for (int c0 = 0; c0 < K; c0 += NT) {
         const int k = c0 + tid;
-        uint32_t v[3] = {0u, 0u, 0u};
+        uint32_t v[4] = {0u, 0u, 0u, 0u};
         if (k < K) {
             const uint2 e = b.list[k];
             const int32_t g = (int32_t)e.x;
@@ -1209,26 +1213,32 @@ __global__ void __launch_bounds__(1024) k_blk_setup(CycleArgs a, BlkArgs b) {
             v[0] = (uint32_t)(ie - ib) + 1u;
             v[1] = (e.y + b.task - 1) / b.task;
             v[2] = (uint32_t)((span + BLK_IDS - 1) >> BLK_SHIFT);
+            // histogram-matrix rows: tasks x blocks (saturated; a total
+            // beyond the capacity turns the matrix off for the pass)
+            const uint64_t mw = (uint64_t)v[1] * v[2];
+            v[3] = mw > 0xffffffffull ? 0xffffffffu : (uint32_t)mw;
+            atomicAdd(&s_mtot, (unsigned long long)v[3]);
         }
-        uint32_t incl[3];
-        for (int q = 0; q < 3; ++q) {
+        uint32_t incl[4];
+        for (int q = 0; q < 4; ++q) {
             incl[q] = wave_incl_scan(v[q]);
             if (lane == WAVE - 1) wt[q][wv] = incl[q];
         }
         __syncthreads();
-        uint32_t add[3];
-        for (int q = 0; q < 3; ++q) {
+        uint32_t add[4];
+        for (int q = 0; q < 4; ++q) {
             add[q] = carry[q];
             for (int r = 0; r < wv; ++r) add[q] += wt[q][r];
             if (k < K) out[q][k] = add[q] + incl[q] - v[q];
         }
         __syncthreads();
         if (tid == NT - 1)
-            for (int q = 0; q < 3; ++q) carry[q] = add[q] + incl[q];
+            for (int q = 0; q < 4; ++q) carry[q] = add[q] + incl[q];
         __syncthreads();
     }
     if (tid == 0) {
-        for (int q = 0; q < 3; ++q) out[q][K] = carry[q];
+        for (int q = 0; q < 4; ++q) out[q][K] = carry[q];
+        a.counters[C_BLK_MAT] = b.mat_cap > 0 && s_mtot <= (unsigned long long)b.mat_cap ? 1u : 0u;
         a.counters[C_BLK_GROUPS] = (uint64_t)K;
         a.counters[C_BLK_TASKS] = carry[1];
         a.counters[C_BLK_BUCKETS] = carry[2];
@@ -1390,6 +1400,7 @@ __global__ void __launch_bounds__(NT) k_blk_hist(CycleArgs a, BlkArgs b) {
     __shared__ BlkWalk s_w;
     if (input_failed(a.status)) return;
     const int tid = threadIdx.x;
+    const bool mat_on = a.counters[C_BLK_MAT] != 0;
     while (true) {
         if (tid == 0) s_w = blk_take<PASS>(a, b, C_BLK_NEXT_H);
         __syncthreads();
@@ -1400,9 +1411,12 @@ __global__ void __launch_bounds__(NT) k_blk_hist(CycleArgs a, BlkArgs b) {
         __syncthreads();
         blk_walk_blocks<PASS, NT, false>(a, b, w, sm_hist, it_tb, it_scan, it_tx, it_eid, it_flip,
                                          wave_tot);
-        for (uint32_t j = tid; j < nb; j += NT)
-            if (sm_hist[j])
-                atomicAdd((unsigned long long *)&b.bcount[b0 + j], (unsigned long long)sm_hist[j]);
+        uint32_t *row = mat_on ? b.mat + b.moff[w.k] + (size_t)(w.t - b.tstart[w.k]) * nb : nullptr;
+        for (uint32_t j = tid; j < nb; j += NT) {
+            const uint32_t c = sm_hist[j];
+            if (row) row[j] = c;
+            if (c) atomicAdd((unsigned long long *)&b.bcount[b0 + j], (unsigned long long)c);
+        }
         __syncthreads();
     }
 }
@@ -1422,16 +1436,24 @@ __global__ void __launch_bounds__(NT) k_blk_part(CycleArgs a, BlkArgs b) {
     __shared__ BlkWalk s_w;
     if (input_failed(a.status)) return;
     const int tid = threadIdx.x;
+    const bool mat_on = a.counters[C_BLK_MAT] != 0;
     while (true) {
         if (tid == 0) s_w = blk_take<PASS>(a, b, C_BLK_NEXT_P);
         __syncthreads();
         const BlkWalk w = s_w;
         if (w.g < 0) break;
         const uint32_t b0 = b.boff[w.k], nb = b.boff[w.k + 1] - b0;
-        for (uint32_t j = tid; j < nb; j += NT) sm_hist[j] = 0u;
-        __syncthreads();
-        blk_walk_blocks<PASS, NT, false>(a, b, w, sm_hist, it_tb, it_scan, it_tx, it_eid, it_flip,
-                                         wave_tot);
+        if (mat_on) {
+            // the histogram kernel left this task's row of block counts
+            const uint32_t *row = b.mat + b.moff[w.k] + (size_t)(w.t - b.tstart[w.k]) * nb;
+            for (uint32_t j = tid; j < nb; j += NT) sm_hist[j] = row[j];
+            __syncthreads();
+        } else {
+            for (uint32_t j = tid; j < nb; j += NT) sm_hist[j] = 0u;
+            __syncthreads();
+            blk_walk_blocks<PASS, NT, false>(a, b, w, sm_hist, it_tb, it_scan, it_tx, it_eid,
+                                             it_flip, wave_tot);
+        }
         for (uint32_t j = tid; j < nb; j += NT) {
             const uint32_t c = sm_hist[j];
             if (c)
