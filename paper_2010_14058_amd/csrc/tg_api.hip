@@ -600,7 +600,8 @@ static tg_status run(const int64_t *row_ptr, const int32_t *col, const uint8_t *
         // is below 2^16)
         ca.hub_ids = pass == 1 && !batch && words32 && L <= 16
                          ? heavy_hub_ids(L, n, g_tune[TG_TUNE_HUB_LDS]) : 0;
-        ca.chunk = heavy_chunk_for(L, pass == 0 ? HEAVY_THREADS_A : HEAVY_THREADS_B, ca.hub_ids);
+        ca.chunk = heavy_chunk_for(L, pass == 0 ? HEAVY_THREADS_A : HEAVY_THREADS_B, ca.hub_ids,
+                                   words32);
         HIPCHK(launch_cycles(pass, true, ca, (unsigned)y.heavy_slots, st));
         timing_mark(pass == 0 ? "cycA_heavy" : "cycB_heavy");
     }

@@ -376,7 +376,7 @@ hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32
 hipError_t launch_blk(int pass, const CycleArgs &args, const BlkArgs &blk, int64_t *scan_tmp,
                       hipStream_t st);
 int blk_emit_chunk(int L);
-int heavy_chunk_for(int L, int threads, int hub_ids = 0);
+int heavy_chunk_for(int L, int threads, int hub_ids = 0, bool t32 = false);
 int heavy_hub_ids(int L, int64_t n, int64_t bytes);
 hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned grid, hipStream_t st);
 hipError_t launch_edges(bool heavy, const EdgeArgs &args, unsigned grid, hipStream_t st);

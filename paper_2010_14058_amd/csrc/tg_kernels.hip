@@ -678,6 +678,9 @@ __device__ __forceinline__ int32_t range_cut(const int64_t *nrp, int32_t rb, int
     return lo;
 }
 
+// Copies of the task kernel's 32-bit tallies (every degree below 2^16).
+constexpr int TALLY_COPIES = 2;   // (4 measured slower)
+
 // Map entries by target degree class.  The count of centres of one type at
 // target w never exceeds w's degree, so targets of degree < 16 keep 4-bit
 // counts, < 64 6-bit, < 256 8-bit, < 1024 10-bit, < 65536 16-bit and the
@@ -770,12 +773,13 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
     uint64_t *acc = sm_heavy;  // CH * L * L
     // every degree below 2^16: a round's tally of one item (its targets in
     // the task, each count below 2^16) stays below 2^32, so the tallies are
-    // 32-bit words in two interleaved copies (same LDS, fewer conflicts)
+    // 32-bit words in TALLY_COPIES interleaved copies (fewer conflicts)
     uint32_t *acc32 = reinterpret_cast<uint32_t *>(sm_heavy);
     const bool t32 = a.nc_u32 != 0;
+    uint32_t *hub_after = reinterpret_cast<uint32_t *>(acc + (size_t)CH * LL * (t32 ? TALLY_COPIES / 2 : 1));
     // hub targets (the top hub_ids ids) are counted in LDS as 16-bit fields
     // per (target, centre type) after the tallies; the rest in the map
-    uint32_t *hub = reinterpret_cast<uint32_t *>(acc + (size_t)CH * LL);
+    uint32_t *hub = hub_after;
     const int32_t hub_lo = a.hub_ids > 0 ? (int32_t)(a.n - a.hub_ids) : (int32_t)a.n;
     const int hub_words = (a.hub_ids * L + 1) / 2;
     __shared__ int32_t it_tx[HEAVY_CHUNK];  // type of each staged item (the centre)
@@ -879,7 +883,8 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
                 block_scan_chunk<NT>(len, it_scan, wave_tot);
                 uint32_t total = it_scan[nitems - 1];
                 if (phase == 2) {
-                    for (int q = tid; q < nitems * LL; q += HEAVY_THREADS) acc[q] = 0;
+                    const int words = t32 ? nitems * LL * TALLY_COPIES / 2 : nitems * LL;
+                    for (int q = tid; q < words; q += HEAVY_THREADS) acc[q] = 0;
                     __syncthreads();
                 }
                 int o = 0;
@@ -899,14 +904,14 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
                         } else if (phase == 2) {
                             const int ty = a.ctype[ys];
                             uint64_t *ac = acc + (size_t)o * LL;
-                            uint32_t *ac32 = acc32 + (size_t)o * LL * 2 + (tid & 1);
+                            uint32_t *ac32 = acc32 + (size_t)o * LL * TALLY_COPIES + (tid & (TALLY_COPIES - 1));
                             for (int t = 0; t < L; ++t) {
                                 const uint32_t idx = base + (uint32_t)t;
                                 const uint32_t c = (hub[idx >> 1] >> ((idx & 1u) * 16u)) & 0xffffu;
                                 const uint32_t val = c - (t == tx ? 1u : 0u);
                                 if (!val) continue;
                                 if (t32)
-                                    atomicAdd(&ac32[pass_entry<PASS>(t, ty, L) * 2], val);
+                                    atomicAdd(&ac32[pass_entry<PASS>(t, ty, L) * TALLY_COPIES], val);
                                 else
                                     atomicAdd((unsigned long long *)&ac[pass_entry<PASS>(t, ty, L)],
                                               (unsigned long long)val);
@@ -929,7 +934,7 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
                     } else {
                         int ty = a.ctype[ys];
                         uint64_t *ac = acc + (size_t)o * LL;
-                        uint32_t *ac32 = acc32 + (size_t)o * LL * 2 + (tid & 1);
+                        uint32_t *ac32 = acc32 + (size_t)o * LL * TALLY_COPIES + (tid & (TALLY_COPIES - 1));
                         // one load per map word (atomic loads are not merged by
                         // the compiler), the counts of its types extracted
                         const uint32_t mask = bits == 32 ? 0xffffffffu : (1u << bits) - 1u;
@@ -945,7 +950,7 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
                             const uint32_t val = c - (t == tx ? 1u : 0u);
                             if (!val) continue;
                             if (t32)
-                                atomicAdd(&ac32[pass_entry<PASS>(t, ty, L) * 2], val);
+                                atomicAdd(&ac32[pass_entry<PASS>(t, ty, L) * TALLY_COPIES], val);
                             else
                                 atomicAdd((unsigned long long *)&ac[pass_entry<PASS>(t, ty, L)],
                                           (unsigned long long)val);
@@ -955,7 +960,13 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
                 __syncthreads();
                 if (phase == 2) {
                     for (int q = tid; q < nitems * LL; q += HEAVY_THREADS) {
-                        uint64_t v = t32 ? (uint64_t)acc32[2 * q] + acc32[2 * q + 1] : acc[q];
+                        uint64_t v = 0;
+                        if (t32) {
+#pragma unroll
+                            for (int r = 0; r < TALLY_COPIES; ++r) v += acc32[TALLY_COPIES * q + r];
+                        } else {
+                            v = acc[q];
+                        }
                         if (!v) continue;
                         int o = q / LL;
                         int pq = q - o * LL;
@@ -1000,6 +1011,7 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
 // LDS counts and the emit reads of one map per group.
 
 constexpr int BLK_UNROLL = 4;   // wedges per thread and step of the walks
+constexpr int BLK_COUNT_THREADS = 512;   // threads of the block-count kernel
 constexpr int BLK_COPIES = 1;   // copies of each item's emit tallies (more copies measured no faster)
 constexpr int BLK_HOLD = 2;     // 16-byte record loads a count thread keeps for its second pass
 
@@ -1473,8 +1485,8 @@ __global__ void __launch_bounds__(NT) k_blk_part(CycleArgs a, BlkArgs b) {
 // its fields, so the counts are zero again for the next bucket.  Only
 // reached targets are written, and only reached targets are read.
 template <int PASS>
-__global__ void __launch_bounds__(256) k_blk_count(CycleArgs a, BlkArgs b) {
-    constexpr int NT = 256;
+__global__ void __launch_bounds__(BLK_COUNT_THREADS) k_blk_count(CycleArgs a, BlkArgs b) {
+    constexpr int NT = BLK_COUNT_THREADS;
     extern __shared__ uint32_t sm_cnt[];  // BLK_IDS * L 16-bit fields, then BLK_IDS claim bits
     __shared__ int s_k;
     __shared__ uint32_t s_j;
@@ -2050,7 +2062,7 @@ hipError_t launch_cyc_work(const int64_t *nrp, const int32_t *ncol, const uint32
 // Items per staging round: at most threads / 2, with LDS accumulators of
 // L^2 words per item within 32 KB (256 threads) or 50 KB (512 or more), so
 // a workgroup stays under 64 KB of LDS for every L.
-int heavy_chunk_for(int L, int threads, int hub_ids) {
+int heavy_chunk_for(int L, int threads, int hub_ids, bool t32) {
     // LDS for the per-item tallies: a 1024-thread workgroup runs alone on
     // its CU (registers), so it may take twice the budget of smaller ones;
     // with hub targets in LDS the tallies and the hub fields share it
@@ -2061,7 +2073,7 @@ int heavy_chunk_for(int L, int threads, int hub_ids) {
         budget = 36864 - ((hub_ids * L + 1) / 2) * 4;
         if (budget < 8192) budget = 8192;
     }
-    int ch = budget / (L * L * 8);
+    int ch = budget / (L * L * (t32 ? 4 * TALLY_COPIES : 8));
     if (ch > threads / 2) ch = threads / 2;
     if (ch < 1) ch = 1;
     return ch;
@@ -2083,7 +2095,8 @@ hipError_t launch_cycles(int pass, bool heavy, const CycleArgs &args, unsigned g
         if (pass == 0) k_cyc_light<0><<<grid, 64, sh, st>>>(args);
         else k_cyc_light<1><<<grid, 64, sh, st>>>(args);
     } else {
-        size_t sh = (size_t)args.chunk * args.L * args.L * sizeof(uint64_t) +
+        size_t sh = (size_t)args.chunk * args.L * args.L *
+                        (args.nc_u32 ? sizeof(uint32_t) * TALLY_COPIES : sizeof(uint64_t)) +
                     (size_t)((args.hub_ids * args.L + 1) / 2) * sizeof(uint32_t);
         if (pass == 0) k_cyc_heavy<0, HEAVY_THREADS_A><<<grid, HEAVY_THREADS_A, sh, st>>>(args);
         else k_cyc_heavy<1, HEAVY_THREADS_B><<<grid, HEAVY_THREADS_B, sh, st>>>(args);
@@ -2125,7 +2138,7 @@ static hipError_t launch_blk_pass(const CycleArgs &a, const BlkArgs &b, int64_t 
     if (err != hipSuccess) return err;
     k_blk_part<PASS, NT><<<wide, NT, sh_hist, st>>>(a, b);
     LAUNCH_CHECK();
-    k_blk_count<PASS><<<wide, 256, sh_cnt, st>>>(a, b);
+    k_blk_count<PASS><<<wide, BLK_COUNT_THREADS, sh_cnt, st>>>(a, b);
     LAUNCH_CHECK();
     k_blk_emit<PASS, BLK_EMIT_THREADS><<<wide, BLK_EMIT_THREADS, sh_acc, st>>>(a, b);
     LAUNCH_CHECK();
