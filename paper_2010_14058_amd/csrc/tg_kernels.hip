@@ -1011,7 +1011,8 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
 // LDS counts and the emit reads of one map per group.
 
 constexpr int BLK_UNROLL = 4;   // wedges per thread and step of the walks
-constexpr int BLK_COUNT_THREADS = 512;   // threads of the block-count kernel
+constexpr int BLK_COUNT_THREADS = 512;   // threads of the block-count kernel (256: 9.3 ms, 1024: 14.8 ms, 512: 7.6 ms)
+constexpr int BLK_EMIT_UNROLL = 4;       // wedges per thread and step of the emit walk
 constexpr int BLK_COPIES = 1;   // copies of each item's emit tallies (more copies measured no faster)
 constexpr int BLK_HOLD = 2;     // 16-byte record loads a count thread keeps for its second pass
 
@@ -1648,14 +1649,14 @@ __global__ void __launch_bounds__(NT) k_blk_emit(CycleArgs a, BlkArgs b) {
             __syncthreads();
             const uint32_t total = it_scan[cnt - 1];
             int o = 0;
-            // BLK_UNROLL wedges per thread and step: target loads issued
+            // BLK_EMIT_UNROLL wedges per thread and step: target loads issued
             // together, then the first map word of each target together
-            for (uint32_t f0 = tid; f0 < total; f0 += NT * BLK_UNROLL) {
-                int ow[BLK_UNROLL], ty[BLK_UNROLL];
-                int32_t y[BLK_UNROLL];
-                uint32_t w0[BLK_UNROLL];
+            for (uint32_t f0 = tid; f0 < total; f0 += NT * BLK_EMIT_UNROLL) {
+                int ow[BLK_EMIT_UNROLL], ty[BLK_EMIT_UNROLL];
+                int32_t y[BLK_EMIT_UNROLL];
+                uint32_t w0[BLK_EMIT_UNROLL];
 #pragma unroll
-                for (int u = 0; u < BLK_UNROLL; ++u) {
+                for (int u = 0; u < BLK_EMIT_UNROLL; ++u) {
                     const uint32_t f = f0 + (uint32_t)u * NT;
                     ow[u] = -1;
                     if (f < total) {
@@ -1668,12 +1669,12 @@ __global__ void __launch_bounds__(NT) k_blk_emit(CycleArgs a, BlkArgs b) {
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < BLK_UNROLL; ++u) {
+                for (int u = 0; u < BLK_EMIT_UNROLL; ++u) {
                     if (ow[u] < 0) continue;
                     w0[u] = map[map_word(mc, y[u], map_class(mc, y[u]), L)];
                 }
 #pragma unroll
-                for (int u = 0; u < BLK_UNROLL; ++u) {
+                for (int u = 0; u < BLK_EMIT_UNROLL; ++u) {
                     if (ow[u] < 0) continue;
                     const int tx = it_tx[ow[u]];
                     const int cls = map_class(mc, y[u]);
