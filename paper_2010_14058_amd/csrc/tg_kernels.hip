@@ -995,10 +995,12 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
 //   items   per group: exclusive wedge prefix over its items, so a walk task
 //           (a wedge range) finds its first item by binary search;
 //   hist    per walk task: wedges per target block (LDS), added to the
-//           bucket (group, block) counts;
-//   part    per walk task: the same histogram reserves a run of each
-//           bucket, then every wedge writes a 16-bit record (target offset
-//           in the block, centre type) into its run;
+//           bucket (group, block) counts and kept as the task's row of a
+//           histogram matrix;
+//   part    per walk task: that row reserves a run of each bucket, then
+//           every wedge writes a 16-bit record (target offset in the
+//           block, centre type) into its run (without the matrix the task
+//           is walked once more for the row);
 //   count   per bucket: the records counted in LDS per (target, centre
 //           type), written as the group map's entries of that block (the
 //           degree-class layout of the task maps; only reached targets are
@@ -1006,12 +1008,12 @@ __global__ void __launch_bounds__(NT) k_cyc_heavy(CycleArgs a) {
 //   emit    per walk task: every wedge reads its target's entry from the
 //           group's map (read-only now, shared by all tasks of the group)
 //           and adds the counts to the item's LDS tallies, flushed to NC.
-// Every wedge of a blocked group is thus walked four times with streaming
-// reads and written once as a record; the only random accesses are the
-// LDS counts and the emit reads of one map per group.
+// Every wedge of a blocked group is thus read three times as a target id
+// (streaming) and written and read once as a record; the only random
+// accesses are the LDS counts and the emit reads of one map per group.
 
 constexpr int BLK_UNROLL = 4;   // wedges per thread and step of the walks
-constexpr int BLK_COUNT_THREADS = 512;   // threads of the block-count kernel (256: 9.3 ms, 1024: 14.8 ms, 512: 7.6 ms)
+constexpr int BLK_COUNT_THREADS = 512;   // threads of the block-count kernel (measured best of 256, 512, 1024)
 constexpr int BLK_EMIT_UNROLL = 4;       // wedges per thread and step of the emit walk
 constexpr int BLK_COPIES = 1;   // copies of each item's emit tallies (more copies measured no faster)
 constexpr int BLK_HOLD = 2;     // 16-byte record loads a count thread keeps for its second pass
