@@ -167,6 +167,39 @@ __device__ __forceinline__ void gather_member(const EdgeArgs &a, int32_t k, int 
     }
 }
 
+// Copies of the workgroup kernel's 32-bit gather sums per wave: lanes of a
+// wave gathering members of one type add into different copies.
+constexpr int GATHER_COPIES = 4;
+
+// gather_member into 32-bit copies (every degree below 2^16: a sum over the
+// members of an edge's triangle set, each below 2^16, stays below 2^32);
+// entry e of lane copy c is word e * GATHER_COPIES + c.
+__device__ __forceinline__ void gather_member32(const EdgeArgs &a, int32_t k, int t, int64_t s_i,
+                                                int64_t s_j, uint32_t *Xi) {
+    const int L = a.L;
+    uint32_t *Xj = Xi + L * L * GATHER_COPIES;
+    uint32_t *Y = Xi + 2 * L * L * GATHER_COPIES;
+    const int LP = tri_pitch(L);
+    const uint4 *ri = reinterpret_cast<const uint4 *>(a.tri_slot + (size_t)s_i * LP);
+    const uint4 *rj = reinterpret_cast<const uint4 *>(a.tri_slot + (size_t)s_j * LP);
+    const uint4 *ry = reinterpret_cast<const uint4 *>(a.tdeg + (size_t)k * LP);
+    for (int c = 0; c < LP; c += 4) {
+        const uint4 vi = ri[c >> 2], vj = rj[c >> 2], vy = ry[c >> 2];
+        const uint32_t wi[4] = {vi.x, vi.y, vi.z, vi.w};
+        const uint32_t wj[4] = {vj.x, vj.y, vj.z, vj.w};
+        const uint32_t wy[4] = {vy.x, vy.y, vy.z, vy.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int t2 = c + q;
+            if (t2 >= L) break;
+            const int e = (t * L + t2) * GATHER_COPIES;
+            if (wi[q]) atomicAdd(&Xi[e], wi[q]);
+            if (wj[q]) atomicAdd(&Xj[e], wj[q]);
+            if (wy[q]) atomicAdd(&Y[e], wy[q]);
+        }
+    }
+}
+
 // Ordered append of flagged items across the NT threads; returns each
 // flagged thread's position (order = thread order) and advances *count.
 template <int NT>
@@ -246,20 +279,30 @@ __device__ __forceinline__ uint32_t group_incl_scan(uint32_t v, uint32_t *wave_c
 }
 
 // Build T (hub mask/list and sorted low list) and the gathers X_i, X_j, Y.
-template <int NT>
+// With G32 (every degree below 2^16, workgroup kernel) the per-wave gather
+// copies are GATHER_COPIES 32-bit lane copies.
+template <int NT, bool G32 = false>
 __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeShared &S, int tid) {
     const int L = a.L, LL = L * L;
     const int Hw = a.Hw;
     const int32_t base = a.hub_base;
     for (int q = tid; q < 4 * LL; q += NT) S.Xi[q] = 0;
-    if (S.Gw)
-        for (int q = tid; q < (NT / WAVE) * 3 * LL; q += NT) S.Gw[q] = 0;
+    if (S.Gw) {
+        const int gwords = (NT / WAVE) * 3 * LL * (G32 ? GATHER_COPIES / 2 : 1);
+        for (int q = tid; q < gwords; q += NT) S.Gw[q] = 0;
+    }
     for (int q = tid; q < Hw; q += NT) S.Tm[q] = 0;
     // gathers go to this wave's private copy when there is one (fewer
     // conflicting LDS atomics), summed into Xi, Xj, Y at the end
     uint64_t *gXi = S.Gw ? S.Gw + (size_t)(tid / WAVE) * 3 * LL : S.Xi;
     uint64_t *gXj = S.Gw ? gXi + LL : S.Xj;
     uint64_t *gY = S.Gw ? gXi + 2 * LL : S.Y;
+    // 32-bit lane copies: wave w's block of 3 L^2 entries x GATHER_COPIES
+    uint32_t *hXi = G32 ? reinterpret_cast<uint32_t *>(S.Gw) +
+                              (size_t)(tid / WAVE) * 3 * LL * GATHER_COPIES +
+                              (lane_id() & (GATHER_COPIES - 1))
+                        : nullptr;
+
     if (tid == 0) {
         S.meta[0] = 0;
         S.meta[1] = 0;
@@ -327,7 +370,10 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
             }
             if (found) {
                 S.Tl[pos] = (uint32_t)x;
-                gather_member(a, x, a.ctype[p], i_small ? p : q, i_small ? q : p, gXi, gXj, gY);
+                if constexpr (G32)
+                    gather_member32(a, x, a.ctype[p], i_small ? p : q, i_small ? q : p, hXi);
+                else
+                    gather_member(a, x, a.ctype[p], i_small ? p : q, i_small ? q : p, gXi, gXj, gY);
             }
         }
         if (tid == 0 && !unordered) S.meta[0] = count;
@@ -366,8 +412,12 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
         for (uint32_t f = tid; f < nh; f += NT) {
             const int hk = th_get<NT>(S, f);
             const int32_t k = base + hk;
-            gather_member(a, k, a.ntype[k], hub_slot(a, i, hx_i, hk), hub_slot(a, j, hx_j, hk), gXi,
-                          gXj, gY);
+            if constexpr (G32)
+                gather_member32(a, k, a.ntype[k], hub_slot(a, i, hx_i, hk), hub_slot(a, j, hx_j, hk),
+                                hXi);
+            else
+                gather_member(a, k, a.ntype[k], hub_slot(a, i, hx_i, hk), hub_slot(a, j, hx_j, hk),
+                              gXi, gXj, gY);
         }
     } else {
         // scan the shorter hub suffix; test the other endpoint by its bit row
@@ -395,14 +445,25 @@ __device__ void edge_build(const EdgeArgs &a, int32_t i, int32_t j, const EdgeSh
             atomicMax(&S.meta[3], (uint32_t)(hk >> 6));
             uint32_t pos = atomicAdd(&S.meta[1], 1u);
             th_put<NT>(S, pos, hk);
-            gather_member(a, x, a.ctype[p], i_small ? p : q, i_small ? q : p, gXi, gXj, gY);
+            if constexpr (G32)
+                gather_member32(a, x, a.ctype[p], i_small ? p : q, i_small ? q : p, hXi);
+            else
+                gather_member(a, x, a.ctype[p], i_small ? p : q, i_small ? q : p, gXi, gXj, gY);
         }
     }
     group_sync<NT>();
     if (S.Gw) {
+        const uint32_t *gw32 = reinterpret_cast<const uint32_t *>(S.Gw);
         for (int q = tid; q < 3 * LL; q += NT) {
             uint64_t v = 0;
-            for (int w = 0; w < NT / WAVE; ++w) v += S.Gw[(size_t)w * 3 * LL + q];
+            if constexpr (G32) {
+                for (int w = 0; w < NT / WAVE; ++w)
+#pragma unroll
+                    for (int c = 0; c < GATHER_COPIES; ++c)
+                        v += gw32[((size_t)w * 3 * LL + q) * GATHER_COPIES + c];
+            } else {
+                for (int w = 0; w < NT / WAVE; ++w) v += S.Gw[(size_t)w * 3 * LL + q];
+            }
             S.Xi[q] = v;  // Xi, Xj, Y are consecutive
         }
         group_sync<NT>();
@@ -949,7 +1010,8 @@ __global__ void __launch_bounds__(64) k_edges_light_fused(EdgeArgs a) {
 // Heavy edges: one 256-thread workgroup per edge, pulled from a queue; the
 // low list lives in a global buffer of n entries private to the workgroup,
 // the hub list (at most H entries) in LDS.  MODE 0 stores each edge's Xi,
-// Xj, Y, K for the separate derivation; 1 and 2 derive in place with 32-bit
+// Xj, Y, K for the separate derivation (MODE 3 the same with 32-bit gather
+// copies, every degree below 2^16); 1 and 2 derive in place with 32-bit
 // and 64-bit A, D and NC (one instance each, so that the deferred one holds
 // no derivation state).
 // The deferred instance runs under a register budget for five waves per SIMD
@@ -957,7 +1019,7 @@ __global__ void __launch_bounds__(64) k_edges_light_fused(EdgeArgs a) {
 // CU's LDS.
 template <int MODE>
 __global__ void __launch_bounds__(EDGE_THREADS_HEAVY)
-__attribute__((amdgpu_waves_per_eu(MODE == 0 ? 5 : 1))) k_edges_heavy(EdgeArgs a) {
+__attribute__((amdgpu_waves_per_eu(MODE == 0 || MODE == 3 ? 5 : 1))) k_edges_heavy(EdgeArgs a) {
     extern __shared__ uint64_t sm_edgeh[];
     __shared__ uint32_t meta[4];
     __shared__ uint32_t wave_cnt[EDGE_THREADS_HEAVY / WAVE];
@@ -976,7 +1038,7 @@ __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 5 : 1))) k_edges_heavy(EdgeArgs a
         reinterpret_cast<uint64_t *>((reinterpret_cast<uintptr_t>(after) + 15) & ~uintptr_t(15));
     const int TMw = tm_pitch(a.L) * a.Hw;
     uint64_t *Gw = TMs + TMw;                     // per-wave gather copies
-    uint32_t *Th = (uint32_t *)(Gw + (size_t)(NT / WAVE) * 3 * LL);
+    uint32_t *Th = (uint32_t *)(Gw + (size_t)(NT / WAVE) * 3 * LL * (GATHER_COPIES / 2));
     uint32_t *Tl = a.tbuf + (size_t)blockIdx.x * (size_t)a.n;
     EdgeShared S = carve(a, sm_edgeh, meta, wave_cnt, &hist, Th, 1, Tl);
     S.Gw = Gw;
@@ -995,11 +1057,11 @@ __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 5 : 1))) k_edges_heavy(EdgeArgs a
         if (idx >= count) break;
         int64_t e = a.heavy_list[idx];
         int32_t i = a.ei[e], j = a.ej[e];
-        edge_build<NT>(a, i, j, S, tid);
+        edge_build<NT, MODE == 3>(a, i, j, S, tid);
         __threadfence_block();
         __syncthreads();
         edge_cliques<NT>(a, i, j, S, TMs, F, tid);
-        if constexpr (MODE == 0) {
+        if constexpr (MODE == 0 || MODE == 3) {
             store_xyk(a, e, S.Xi, tid, NT);
         } else {
             if (tid == 0) {
@@ -1098,7 +1160,7 @@ size_t edge_lds_bytes(const EdgeArgs &args, bool heavy) {
     size_t sh = (size_t)(4 * LL * args.derive_batch + hw + args.Hw) * sizeof(uint64_t);
     if (!heavy) sh += (size_t)args.tcap * sizeof(uint32_t);
     else sh += (size_t)(tm_pitch(args.L) * args.Hw + 1) * sizeof(uint64_t) +
-               (size_t)(EDGE_THREADS_HEAVY / WAVE) * 3 * LL * sizeof(uint64_t) +
+               (size_t)(EDGE_THREADS_HEAVY / WAVE) * 3 * LL * sizeof(uint64_t) * (GATHER_COPIES / 2) +
                (size_t)(args.hub_base < args.n ? (args.n - args.hub_base) : 0) * sizeof(uint16_t);
     return sh;
 }
@@ -1107,7 +1169,8 @@ hipError_t launch_edges(bool heavy, const EdgeArgs &args, unsigned grid, hipStre
     if (grid == 0) return hipSuccess;
     size_t sh = edge_lds_bytes(args, heavy);
     if (heavy) {
-        if (args.xyk) k_edges_heavy<0><<<grid, EDGE_THREADS_HEAVY, sh, st>>>(args);
+        if (args.xyk && args.agg_u32) k_edges_heavy<3><<<grid, EDGE_THREADS_HEAVY, sh, st>>>(args);
+        else if (args.xyk) k_edges_heavy<0><<<grid, EDGE_THREADS_HEAVY, sh, st>>>(args);
         else if (args.agg_u32) k_edges_heavy<1><<<grid, EDGE_THREADS_HEAVY, sh, st>>>(args);
         else k_edges_heavy<2><<<grid, EDGE_THREADS_HEAVY, sh, st>>>(args);
     } else if (args.xyk) {
